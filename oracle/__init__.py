@@ -1,0 +1,202 @@
+"""TEST INFRASTRUCTURE ONLY: the plain FP64 CPU oracle of the hard-sphere
+lattice Boltzmann step, and a plain FP64 reference of the learned force
+surrogate's network.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` import this package.  The GPU library neither links nor calls it and
+shares no source with it.
+
+``hsref.c`` holds the lattice Boltzmann oracle (see its header for the equations
+and readings it follows); this module loads it through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hsref.c")
+_LIB = os.path.join(_HERE, "libhsref.so")
+
+FORCE_EXACT = 0
+FORCE_OFF = 2
+G2_PAPER = 0
+G2_CS = 1
+
+
+def build(verbose: bool = False) -> str:
+    """Compile ``hsref.c`` into ``libhsref.so`` (plain IEEE FP64, OpenMP)."""
+    tmp = _LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fopenmp", "-fPIC", "-shared",
+           "-ffp-contract=off", "-o", tmp, _SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("wall_lo", ctypes.c_int32), ("wall_hi", ctypes.c_int32),
+        ("sigma", ctypes.c_int32),
+        ("tau", ctypes.c_double),
+        ("accel", ctypes.c_double * 3),
+        ("g2_model", ctypes.c_int32), ("wall_reg", ctypes.c_int32),
+        ("force_mode", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.POINTER
+    d = P(ctypes.c_double)
+    lib.hsref_create.restype = ctypes.c_void_p
+    lib.hsref_create.argtypes = [P(_Params)]
+    lib.hsref_destroy.argtypes = [ctypes.c_void_p]
+    for name in ("hsref_init", "hsref_moments", "hsref_profiles"):
+        getattr(lib, name).argtypes = [ctypes.c_void_p, d, d]
+        getattr(lib, name).restype = ctypes.c_int
+    for name in ("hsref_force", "hsref_eta_bar", "hsref_get_populations", "hsref_set_populations"):
+        getattr(lib, name).argtypes = [ctypes.c_void_p, d]
+        getattr(lib, name).restype = ctypes.c_int
+    lib.hsref_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+    lib.hsref_step.restype = ctypes.c_int
+    lib.hsref_g2.argtypes = [ctypes.c_int, ctypes.c_double]
+    lib.hsref_g2.restype = ctypes.c_double
+    lib.hsref_shell_table.argtypes = [ctypes.c_int, d, d, P(ctypes.c_int), P(ctypes.c_int), d]
+    lib.hsref_ball_count.argtypes = [ctypes.c_int]
+    lib.hsref_lattice.argtypes = [P(ctypes.c_int), d]
+    lib.hsref_set_threads.argtypes = [ctypes.c_int]
+    lib.hsref_max_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def set_threads(n: int) -> None:
+    _load().hsref_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(_load().hsref_max_threads())
+
+
+def g2(eta: float, model: int = G2_PAPER) -> float:
+    return float(_load().hsref_g2(int(model), float(eta)))
+
+
+def shell_table(sigma: int):
+    """Return (W[18], s[18,3], ncorner[18], d[18,4,3], alpha[18,4])."""
+    lib = _load()
+    W = np.zeros(18)
+    s = np.zeros((18, 3))
+    nc = np.zeros(18, dtype=np.int32)
+    d = np.zeros((18, 4, 3), dtype=np.int32)
+    al = np.zeros((18, 4))
+    rc = lib.hsref_shell_table(int(sigma), _dptr(W), _dptr(s),
+                               nc.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                               d.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dptr(al))
+    assert rc == 0
+    return W, s, nc, d, al
+
+
+def ball_count(sigma: int) -> int:
+    return int(_load().hsref_ball_count(int(sigma)))
+
+
+def lattice():
+    """Return (c[19,3], w[19]) of the D3Q19 lattice."""
+    c = np.zeros((19, 3), dtype=np.int32)
+    w = np.zeros(19)
+    _load().hsref_lattice(c.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dptr(w))
+    return c, w
+
+
+class Oracle:
+    """One lattice on the CPU.  Fields use the node order x fastest, then y, then
+    z: arrays are shaped (nz, ny, nx) and vectors (3, nz, ny, nx)."""
+
+    def __init__(self, nx, ny, nz, sigma, tau, accel=(0.0, 0.0, 0.0), wall_lo=0, wall_hi=0,
+                 g2_model=G2_PAPER, wall_reg=1, force_mode=FORCE_EXACT):
+        self._lib = _load()
+        p = _Params()
+        p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
+        p.wall_lo, p.wall_hi = int(wall_lo), int(wall_hi)
+        p.sigma = int(sigma)
+        p.tau = float(tau)
+        p.accel = (ctypes.c_double * 3)(*[float(a) for a in accel])
+        p.g2_model, p.wall_reg, p.force_mode = int(g2_model), int(wall_reg), int(force_mode)
+        self.params = p
+        self.shape = (int(nz), int(ny), int(nx))
+        self.N = int(nx) * int(ny) * int(nz)
+        self._ctx = self._lib.hsref_create(ctypes.byref(p))
+        if not self._ctx:
+            raise ValueError("oracle rejected the parameters")
+
+    def __del__(self):
+        ctx = getattr(self, "_ctx", None)
+        if ctx:
+            self._lib.hsref_destroy(ctx)
+            self._ctx = None
+
+    def _chk(self, rc, what):
+        if rc != 0:
+            raise ValueError(f"oracle {what} failed ({rc})")
+
+    def init(self, n, u=None):
+        n = np.ascontiguousarray(n, dtype=np.float64).reshape(self.N)
+        if u is None:
+            u = np.zeros(3 * self.N)
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(3 * self.N)
+        self._chk(self._lib.hsref_init(self._ctx, _dptr(n), _dptr(u)), "init")
+
+    def step(self, nsteps=1):
+        self._chk(self._lib.hsref_step(self._ctx, int(nsteps)), "step")
+
+    def moments(self):
+        n = np.zeros(self.N)
+        u = np.zeros(3 * self.N)
+        self._chk(self._lib.hsref_moments(self._ctx, _dptr(n), _dptr(u)), "moments")
+        return n.reshape(self.shape), u.reshape((3,) + self.shape)
+
+    def profiles(self):
+        nz = self.shape[0]
+        pn = np.zeros(nz)
+        pu = np.zeros(3 * nz)
+        self._chk(self._lib.hsref_profiles(self._ctx, _dptr(pn), _dptr(pu)), "profiles")
+        return pn, pu.reshape(3, nz)
+
+    def force(self):
+        F = np.zeros(3 * self.N)
+        self._chk(self._lib.hsref_force(self._ctx, _dptr(F)), "force")
+        return F.reshape((3,) + self.shape)
+
+    def eta_bar(self):
+        e = np.zeros(self.N)
+        self._chk(self._lib.hsref_eta_bar(self._ctx, _dptr(e)), "eta_bar")
+        return e.reshape(self.shape)
+
+    def get_populations(self):
+        f = np.zeros(19 * self.N)
+        self._chk(self._lib.hsref_get_populations(self._ctx, _dptr(f)), "get_populations")
+        return f.reshape((19,) + self.shape)
+
+    def set_populations(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(19 * self.N)
+        self._chk(self._lib.hsref_set_populations(self._ctx, _dptr(f)), "set_populations")

@@ -1,0 +1,637 @@
+/*
+ * hsref.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, FP64 CPU oracle for the time step of the lattice Boltzmann
+ * method for inhomogeneous hard-sphere fluids of Melchionna and Marini Bettolo
+ * Marconi ("Lattice Boltzmann method for inhomogeneous fluids", EPL).
+ *
+ * Only the test suite, the package smoke check and the benchmark's CPU-baseline
+ * leg load this library.  The GPU library never includes, links or calls it, and
+ * it shares no source with it.
+ *
+ * Equation numbers are the paper's printed ones:
+ *   (3)  Dufty-Santos-Brey kinetic equation: BGK relaxation plus the Hermite
+ *        sources C^(1) (momentum transfer) and C^(2) (energy transfer);
+ *   (8)  hydrodynamic moments as lattice sums over the populations;
+ *   (10) first-order forward-Euler propagation with the Hermite source;
+ *   (11) second-order (low-Mach) local equilibrium;
+ *   (12) C^(1) as a surface integral over the sphere of radius sigma with the
+ *        density-current coupling term.
+ * Section "Methods and Results" also fixes: the isothermal restriction (T const,
+ * so C^(2) and all temperature differences drop out), the coarse-grained density
+ * (uniform smearing over a ball of radius sigma/2, packing fraction
+ * eta = pi sigma^3 n / 6), the contact-value closure for g2 evaluated at the pair
+ * midpoint, the 18-point spherical quadrature with 6 on-lattice and 12
+ * interpolated points, and the wall factor (1 - exp(-|r - r_w|/sigma)) on the
+ * density-current term.  Subsection "Numerical validation" fixes the halfway
+ * bounce-back walls and the uniform driving field parallel to the walls.
+ *
+ * Readings where the paper is silent or garbled (all listed in the design notes):
+ *   - m = 1, v_T^2 = k_B T = 1/3 and the standard D3Q19 weights 1/3, 1/18, 1/36;
+ *   - the surface integral is sigma^2 * 4 pi * sum_q W_q (...), with the 18-point
+ *     rule W = 1/30 on the 6 axis points and 1/15 on the 12 face diagonals;
+ *   - the "linear interpolation" of an off-lattice point interpolates the pair
+ *     elements (g2 * n * [...] of each lattice pair) bilinearly over the four
+ *     in-plane lattice corners around the point;
+ *   - g2 is evaluated at the midpoint of each actual lattice pair; at a
+ *     half-integer midpoint the coarse-grained packing fraction is the mean over
+ *     the 2^h lattice nodes nearest to it (h = number of half-integer coordinates);
+ *   - the closure is the printed one, (1 - eta/2 + eta^2/4)/(1 - eta)^3, with the
+ *     Carnahan-Starling contact value (1 - eta/2)/(1 - eta)^3 as a switch;
+ *   - the velocity in the equilibrium and in the current term is u = j/n, with
+ *     the force added as the first-order source 3 w_i c_i . F;
+ *   - the external field is a force per particle g, so its momentum source is n g;
+ *   - solid nodes and points beyond the array carry n = j = 0;
+ *   - the wall factor multiplies only the current term, is evaluated at the
+ *     receiving node, and uses the distance to the nearest halfway wall plane.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define NQ 19
+#define NSHELL 18
+
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t wall_lo, wall_hi; /* solid layers at each z end; both 0 -> z periodic */
+    int32_t sigma;            /* hard-sphere diameter in lattice units (>= 2) */
+    double tau;               /* BGK relaxation time */
+    double accel[3];          /* external force per particle (m = 1) */
+    int32_t g2_model;         /* 0: printed closure, 1: Carnahan-Starling */
+    int32_t wall_reg;         /* 1: wall factor on the current term */
+    int32_t force_mode;       /* 0: hard-sphere term on, 2: off */
+} hsref_params;
+
+/* D3Q19 velocities, the discrete set of section "Methods and Results". */
+static const int CV[NQ][3] = {
+    {0, 0, 0},
+    {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+    {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+    {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
+static double weight_of(int i)
+{
+    int s = abs(CV[i][0]) + abs(CV[i][1]) + abs(CV[i][2]);
+    if (s == 0) return 1.0 / 3.0;
+    if (s == 1) return 1.0 / 18.0;
+    return 1.0 / 36.0;
+}
+
+static int opposite_of(int i)
+{
+    for (int k = 0; k < NQ; ++k)
+        if (CV[k][0] == -CV[i][0] && CV[k][1] == -CV[i][1] && CV[k][2] == -CV[i][2]) return k;
+    return -1;
+}
+
+/* One of the 18 quadrature directions on the sphere of radius sigma. */
+typedef struct {
+    double W;         /* quadrature weight (sums to 1 over the 18 points) */
+    double s[3];      /* unit vector s_hat */
+    int ncorner;      /* 1 for an on-lattice point, 4 for an interpolated one */
+    int d[4][3];      /* lattice offsets of the corners */
+    double alpha[4];  /* interpolation weights of the corners */
+} shell_dir;
+
+struct hsref_ctx {
+    hsref_params p;
+    int64_t N;
+    int zperiodic;
+    double w[NQ];
+    int opp[NQ];
+    shell_dir shell[NSHELL];
+    int nball;
+    int (*ball)[3];
+    double *chi;     /* [nz] wall factor of the receiving layer */
+    double *f;       /* [19][N] populations after streaming */
+    double *fs;      /* [19][N] scratch for the streamed populations */
+    double *n;       /* [N] */
+    double *j;       /* [3][N] */
+    double *u;       /* [3][N] */
+    double *eb;      /* [N] coarse-grained packing fraction */
+    double *F;       /* [3][N] total force */
+};
+
+typedef struct hsref_ctx hsref_ctx;
+
+/* ---------------------------------------------------------------- tables */
+
+/* The 18-point rule: the 6 axis points +-sigma e_a lie on the lattice; each of
+ * the 12 face-diagonal points sigma (s_a e_a + s_b e_b)/sqrt(2) is replaced by
+ * the 4 lattice corners of its in-plane cell with bilinear weights. */
+static void build_shell(int sigma, shell_dir *sh)
+{
+    int q = 0;
+    for (int a = 0; a < 3; ++a) {
+        for (int sgn = 1; sgn >= -1; sgn -= 2) {
+            shell_dir *e = &sh[q++];
+            memset(e, 0, sizeof(*e));
+            e->W = 1.0 / 30.0;
+            e->s[a] = (double)sgn;
+            e->ncorner = 1;
+            e->d[0][a] = sgn * sigma;
+            e->alpha[0] = 1.0;
+        }
+    }
+    const double A = (double)sigma / sqrt(2.0);
+    const int l = (int)floor(A);
+    const double th = A - (double)l;
+    const int planes[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    for (int pl = 0; pl < 3; ++pl) {
+        int a = planes[pl][0], b = planes[pl][1];
+        const int sab[2][2] = {{1, 1}, {1, -1}};
+        for (int v = 0; v < 2; ++v) {
+            /* the direction and its negation, as a pair */
+            for (int neg = 0; neg < 2; ++neg) {
+                int sa = neg ? -sab[v][0] : sab[v][0];
+                int sb = neg ? -sab[v][1] : sab[v][1];
+                shell_dir *e = &sh[q++];
+                memset(e, 0, sizeof(*e));
+                e->W = 1.0 / 15.0;
+                e->s[a] = sa / sqrt(2.0);
+                e->s[b] = sb / sqrt(2.0);
+                e->ncorner = 4;
+                int k = 0;
+                for (int ia = 0; ia < 2; ++ia) {
+                    for (int ib = 0; ib < 2; ++ib) {
+                        e->d[k][a] = sa * (l + ia);
+                        e->d[k][b] = sb * (l + ib);
+                        double wa = ia ? th : 1.0 - th;
+                        double wb = ib ? th : 1.0 - th;
+                        e->alpha[k] = wa * wb;
+                        ++k;
+                    }
+                }
+            }
+        }
+    }
+}
+
+/* All integer offsets inside the closed ball of radius sigma/2. */
+static int build_ball(int sigma, int (*out)[3])
+{
+    int r = sigma / 2 + 1, cnt = 0;
+    for (int z = -r; z <= r; ++z)
+        for (int y = -r; y <= r; ++y)
+            for (int x = -r; x <= r; ++x)
+                if (4 * (x * x + y * y + z * z) <= sigma * sigma) {
+                    if (out) {
+                        out[cnt][0] = x;
+                        out[cnt][1] = y;
+                        out[cnt][2] = z;
+                    }
+                    ++cnt;
+                }
+    return cnt;
+}
+
+/* Contact value of the pair correlation as a function of the coarse-grained
+ * packing fraction (section "Methods and Results", Fischer-Methfessel
+ * prescription). */
+double hsref_g2(int model, double eta)
+{
+    double om = 1.0 - eta;
+    if (model == 1) return (1.0 - 0.5 * eta) / (om * om * om);
+    return (1.0 - 0.5 * eta + 0.25 * eta * eta) / (om * om * om);
+}
+
+/* ---------------------------------------------------------------- helpers */
+
+static int wrapi(int v, int n)
+{
+    int m = v % n;
+    return m < 0 ? m + n : m;
+}
+
+static int is_solid_z(const hsref_ctx *c, int z)
+{
+    return z < c->p.wall_lo || z >= c->p.nz - c->p.wall_hi;
+}
+
+/* Lattice node at (x,y,z) after periodic wrapping; -1 when the point lies
+ * beyond a non-periodic end of the array. */
+static int64_t node_at(const hsref_ctx *c, int x, int y, int z)
+{
+    x = wrapi(x, c->p.nx);
+    y = wrapi(y, c->p.ny);
+    if (c->zperiodic)
+        z = wrapi(z, c->p.nz);
+    else if (z < 0 || z >= c->p.nz)
+        return -1;
+    return (int64_t)x + (int64_t)c->p.nx * ((int64_t)y + (int64_t)c->p.ny * z);
+}
+
+static int fluid_node(const hsref_ctx *c, int64_t id)
+{
+    if (id < 0) return 0;
+    int z = (int)(id / ((int64_t)c->p.nx * c->p.ny));
+    return !is_solid_z(c, z);
+}
+
+/* ---------------------------------------------------------------- create */
+
+void hsref_set_threads(int nt)
+{
+#ifdef _OPENMP
+    if (nt > 0) omp_set_num_threads(nt);
+#else
+    (void)nt;
+#endif
+}
+
+int hsref_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+hsref_ctx *hsref_create(const hsref_params *p)
+{
+    if (!p) return NULL;
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return NULL;
+    if (p->wall_lo < 0 || p->wall_hi < 0) return NULL;
+    if ((p->wall_lo == 0) != (p->wall_hi == 0)) return NULL;
+    if (p->wall_lo + p->wall_hi >= p->nz) return NULL;
+    if (p->force_mode != 2 && p->sigma < 2) return NULL;
+    if (!(p->tau > 0.5)) return NULL;
+    hsref_ctx *c = (hsref_ctx *)calloc(1, sizeof(hsref_ctx));
+    if (!c) return NULL;
+    c->p = *p;
+    c->N = (int64_t)p->nx * p->ny * p->nz;
+    c->zperiodic = (p->wall_lo == 0 && p->wall_hi == 0);
+    for (int i = 0; i < NQ; ++i) {
+        c->w[i] = weight_of(i);
+        c->opp[i] = opposite_of(i);
+    }
+    int sig = p->sigma >= 2 ? p->sigma : 2;
+    build_shell(sig, c->shell);
+    c->nball = build_ball(sig, NULL);
+    c->ball = malloc(sizeof(int[3]) * (size_t)c->nball);
+    build_ball(sig, c->ball);
+    c->chi = malloc(sizeof(double) * (size_t)p->nz);
+    for (int z = 0; z < p->nz; ++z) {
+        double chi = 1.0;
+        if (!c->zperiodic && p->wall_reg) {
+            double za = p->wall_lo - 0.5, zb = p->nz - p->wall_hi - 0.5;
+            double dw = fmin((double)z - za, zb - (double)z);
+            chi = 1.0 - exp(-dw / (double)sig);
+        }
+        c->chi[z] = chi;
+    }
+    size_t N = (size_t)c->N;
+    c->f = calloc((size_t)NQ * N, sizeof(double));
+    c->fs = calloc((size_t)NQ * N, sizeof(double));
+    c->n = calloc(N, sizeof(double));
+    c->j = calloc(3 * N, sizeof(double));
+    c->u = calloc(3 * N, sizeof(double));
+    c->eb = calloc(N, sizeof(double));
+    c->F = calloc(3 * N, sizeof(double));
+    if (!c->ball || !c->chi || !c->f || !c->fs || !c->n || !c->j || !c->u || !c->eb || !c->F) {
+        free(c->ball); free(c->chi); free(c->f); free(c->fs); free(c->n); free(c->j);
+        free(c->u); free(c->eb); free(c->F); free(c);
+        return NULL;
+    }
+    return c;
+}
+
+void hsref_destroy(hsref_ctx *c)
+{
+    if (!c) return;
+    free(c->ball); free(c->chi); free(c->f); free(c->fs); free(c->n); free(c->j);
+    free(c->u); free(c->eb); free(c->F);
+    free(c);
+}
+
+/* ---------------------------------------------------------------- phases */
+
+/* Equation (8): n = sum_i f_i, n u = sum_i c_i f_i.  Solid nodes carry nothing. */
+static void phase_moments(hsref_ctx *c)
+{
+    const int64_t N = c->N;
+    const int64_t plane = (int64_t)c->p.nx * c->p.ny;
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < c->p.nz; ++z) {
+        for (int64_t id = z * plane; id < (z + 1) * plane; ++id) {
+            double n = 0.0, j[3] = {0.0, 0.0, 0.0};
+            if (!is_solid_z(c, z)) {
+                for (int i = 0; i < NQ; ++i) {
+                    double fi = c->f[(int64_t)i * N + id];
+                    n += fi;
+                    j[0] += CV[i][0] * fi;
+                    j[1] += CV[i][1] * fi;
+                    j[2] += CV[i][2] * fi;
+                }
+            }
+            c->n[id] = n;
+            for (int a = 0; a < 3; ++a) {
+                c->j[a * N + id] = j[a];
+                c->u[a * N + id] = n != 0.0 ? j[a] / n : 0.0;
+            }
+        }
+    }
+}
+
+/* Coarse-grained packing fraction: the density averaged over the lattice nodes
+ * of the ball of radius sigma/2, times pi sigma^3 / 6. */
+static void phase_eta_bar(hsref_ctx *c)
+{
+    const int64_t plane = (int64_t)c->p.nx * c->p.ny;
+    const double sig = (double)c->p.sigma;
+    const double pref = M_PI * sig * sig * sig / 6.0 / (double)c->nball;
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < c->p.nz; ++z) {
+        for (int y = 0; y < c->p.ny; ++y) {
+            for (int x = 0; x < c->p.nx; ++x) {
+                double s = 0.0;
+                for (int b = 0; b < c->nball; ++b) {
+                    int64_t id = node_at(c, x + c->ball[b][0], y + c->ball[b][1], z + c->ball[b][2]);
+                    if (id >= 0) s += c->n[id];
+                }
+                c->eb[z * plane + (int64_t)y * c->p.nx + x] = pref * s;
+            }
+        }
+    }
+}
+
+/* Coarse-grained packing fraction at the midpoint of the pair (r, r+d): the mean
+ * over the 2^h lattice nodes nearest to r + d/2.  Returns 0 when one of them lies
+ * beyond the array (such pairs carry no density and are never used). */
+static int eta_mid(const hsref_ctx *c, int x, int y, int z, const int d[3], double *out)
+{
+    int lo[3], hi[3];
+    const int r[3] = {x, y, z};
+    for (int a = 0; a < 3; ++a) {
+        /* floor(d/2) and ceil(d/2) for either sign */
+        int fl = (d[a] >= 0) ? d[a] / 2 : -((-d[a] + 1) / 2);
+        lo[a] = r[a] + fl;
+        hi[a] = r[a] + d[a] - fl;
+    }
+    double s = 0.0;
+    int cnt = 0;
+    for (int zz = lo[2]; zz <= hi[2]; ++zz)
+        for (int yy = lo[1]; yy <= hi[1]; ++yy)
+            for (int xx = lo[0]; xx <= hi[0]; ++xx) {
+                int64_t id = node_at(c, xx, yy, zz);
+                if (id < 0) return 0;
+                s += c->eb[id];
+                ++cnt;
+            }
+    *out = s / (double)cnt;
+    return 1;
+}
+
+/* Equation (12) with the isothermal restriction, plus the external field:
+ *   C1(r) = -v_T^2 sigma^2 4pi n(r) sum_q W_q s_q sum_k alpha_qk G_qk
+ *           [ n(r+d) - chi(r) kappa s_q . (j(r+d) - n(r+d) u(r)) ],
+ *   kappa = 2/(v_T sqrt(pi)),  G_qk = g2(eta_bar at the pair midpoint),
+ *   F = C1 + n(r) g.
+ * Directions are summed as (q, -q) pairs, pairs in table order. */
+static void phase_force(hsref_ctx *c)
+{
+    const int64_t N = c->N;
+    const int64_t plane = (int64_t)c->p.nx * c->p.ny;
+    const double vt2 = 1.0 / 3.0;
+    const double kappa = 2.0 / (sqrt(vt2) * sqrt(M_PI));
+    const double sig = (double)c->p.sigma;
+    const double pref = -vt2 * sig * sig * 4.0 * M_PI;
+    const int hs_on = (c->p.force_mode != 2);
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < c->p.nz; ++z) {
+        for (int y = 0; y < c->p.ny; ++y) {
+            for (int x = 0; x < c->p.nx; ++x) {
+                int64_t id = z * plane + (int64_t)y * c->p.nx + x;
+                double Fv[3] = {0.0, 0.0, 0.0};
+                if (!is_solid_z(c, z)) {
+                    double nr = c->n[id];
+                    double ur[3] = {c->u[id], c->u[N + id], c->u[2 * N + id]};
+                    double S[3] = {0.0, 0.0, 0.0};
+                    if (hs_on) {
+                        for (int pr = 0; pr < NSHELL / 2; ++pr) {
+                            double Sp[3] = {0.0, 0.0, 0.0};
+                            for (int m = 0; m < 2; ++m) {
+                                const shell_dir *e = &c->shell[2 * pr + m];
+                                double acc = 0.0;
+                                for (int k = 0; k < e->ncorner; ++k) {
+                                    int64_t id2 = node_at(c, x + e->d[k][0], y + e->d[k][1], z + e->d[k][2]);
+                                    if (!fluid_node(c, id2)) continue; /* n = j = 0 there */
+                                    double etam;
+                                    if (!eta_mid(c, x, y, z, e->d[k], &etam)) continue;
+                                    double G = hsref_g2(c->p.g2_model, etam);
+                                    double n2 = c->n[id2];
+                                    double cur = 0.0;
+                                    for (int a = 0; a < 3; ++a)
+                                        cur += e->s[a] * (c->j[a * N + id2] - n2 * ur[a]);
+                                    acc += e->alpha[k] * G * (n2 - c->chi[z] * kappa * cur);
+                                }
+                                for (int a = 0; a < 3; ++a) Sp[a] += e->W * e->s[a] * acc;
+                            }
+                            for (int a = 0; a < 3; ++a) S[a] += Sp[a];
+                        }
+                    }
+                    for (int a = 0; a < 3; ++a) Fv[a] = pref * nr * S[a] + nr * c->p.accel[a];
+                }
+                for (int a = 0; a < 3; ++a) c->F[a * N + id] = Fv[a];
+            }
+        }
+    }
+}
+
+/* Equations (10) and (11): BGK relaxation toward the second-order equilibrium
+ * with the first-order source 3 w_i c_i . F, then propagation to r + c_i, with
+ * halfway bounce-back (the population returns reversed to r) when r + c_i is
+ * solid. */
+static void phase_collide_stream(hsref_ctx *c)
+{
+    const int64_t N = c->N;
+    const int64_t plane = (int64_t)c->p.nx * c->p.ny;
+    const double tau = c->p.tau;
+    memset(c->fs, 0, sizeof(double) * (size_t)NQ * (size_t)N);
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < c->p.nz; ++z) {
+        if (is_solid_z(c, z)) continue;
+        for (int y = 0; y < c->p.ny; ++y) {
+            for (int x = 0; x < c->p.nx; ++x) {
+                int64_t id = z * plane + (int64_t)y * c->p.nx + x;
+                double n = c->n[id];
+                double u[3] = {c->u[id], c->u[N + id], c->u[2 * N + id]};
+                double F[3] = {c->F[id], c->F[N + id], c->F[2 * N + id]};
+                double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+                for (int i = 0; i < NQ; ++i) {
+                    double cu = CV[i][0] * u[0] + CV[i][1] * u[1] + CV[i][2] * u[2];
+                    double cF = CV[i][0] * F[0] + CV[i][1] * F[1] + CV[i][2] * F[2];
+                    double feq = c->w[i] * n * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+                    double fi = c->f[(int64_t)i * N + id];
+                    double fpost = fi - (fi - feq) / tau + 3.0 * c->w[i] * cF;
+                    int64_t id2 = node_at(c, x + CV[i][0], y + CV[i][1], z + CV[i][2]);
+                    if (fluid_node(c, id2))
+                        c->fs[(int64_t)i * N + id2] = fpost;
+                    else
+                        c->fs[(int64_t)c->opp[i] * N + id] = fpost;
+                }
+            }
+        }
+    }
+    double *t = c->f;
+    c->f = c->fs;
+    c->fs = t;
+}
+
+/* ---------------------------------------------------------------- API */
+
+static int check_fields(const hsref_ctx *c, const double *n, const double *u)
+{
+    const int64_t N = c->N;
+    for (int64_t id = 0; id < N; ++id) {
+        if (!fluid_node(c, id)) continue;
+        if (!isfinite(n[id]) || n[id] < 0.0) return -1;
+        if (u)
+            for (int a = 0; a < 3; ++a)
+                if (!isfinite(u[a * N + id])) return -1;
+    }
+    return 0;
+}
+
+/* Initial populations: the local equilibrium (11) of the given fields. */
+int hsref_init(hsref_ctx *c, const double *n, const double *u)
+{
+    if (!c || !n) return -1;
+    if (check_fields(c, n, u)) return -1;
+    const int64_t N = c->N;
+    memset(c->f, 0, sizeof(double) * (size_t)NQ * (size_t)N);
+    for (int64_t id = 0; id < N; ++id) {
+        if (!fluid_node(c, id)) continue;
+        double uu[3] = {0.0, 0.0, 0.0};
+        if (u)
+            for (int a = 0; a < 3; ++a) uu[a] = u[a * N + id];
+        double u2 = uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2];
+        for (int i = 0; i < NQ; ++i) {
+            double cu = CV[i][0] * uu[0] + CV[i][1] * uu[1] + CV[i][2] * uu[2];
+            c->f[(int64_t)i * N + id] = c->w[i] * n[id] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * u2);
+        }
+    }
+    phase_moments(c);
+    return 0;
+}
+
+int hsref_step(hsref_ctx *c, int64_t nsteps)
+{
+    if (!c || nsteps < 0) return -1;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        phase_moments(c);
+        if (c->p.force_mode != 2) phase_eta_bar(c);
+        phase_force(c);
+        phase_collide_stream(c);
+    }
+    phase_moments(c);
+    return 0;
+}
+
+int hsref_moments(hsref_ctx *c, double *n, double *u)
+{
+    if (!c) return -1;
+    phase_moments(c);
+    const size_t N = (size_t)c->N;
+    if (n) memcpy(n, c->n, sizeof(double) * N);
+    if (u) memcpy(u, c->u, sizeof(double) * 3 * N);
+    return 0;
+}
+
+/* Layer profiles: n(z) is the layer mean of n, u(z) = sum j / sum n. */
+int hsref_profiles(hsref_ctx *c, double *nz_out, double *uz_out)
+{
+    if (!c) return -1;
+    phase_moments(c);
+    const int64_t N = c->N, plane = (int64_t)c->p.nx * c->p.ny;
+    for (int z = 0; z < c->p.nz; ++z) {
+        double sn = 0.0, sj[3] = {0.0, 0.0, 0.0};
+        for (int64_t id = z * plane; id < (z + 1) * plane; ++id) {
+            sn += c->n[id];
+            for (int a = 0; a < 3; ++a) sj[a] += c->j[a * N + id];
+        }
+        if (nz_out) nz_out[z] = sn / (double)plane;
+        if (uz_out)
+            for (int a = 0; a < 3; ++a) uz_out[a * c->p.nz + z] = sn != 0.0 ? sj[a] / sn : 0.0;
+    }
+    return 0;
+}
+
+/* Total force F = C1 + n g at the current state, [3][N]. */
+int hsref_force(hsref_ctx *c, double *F)
+{
+    if (!c || !F) return -1;
+    phase_moments(c);
+    if (c->p.force_mode != 2) phase_eta_bar(c);
+    phase_force(c);
+    memcpy(F, c->F, sizeof(double) * 3 * (size_t)c->N);
+    return 0;
+}
+
+int hsref_eta_bar(hsref_ctx *c, double *eb)
+{
+    if (!c || !eb) return -1;
+    phase_moments(c);
+    phase_eta_bar(c);
+    memcpy(eb, c->eb, sizeof(double) * (size_t)c->N);
+    return 0;
+}
+
+int hsref_get_populations(hsref_ctx *c, double *f)
+{
+    if (!c || !f) return -1;
+    memcpy(f, c->f, sizeof(double) * NQ * (size_t)c->N);
+    return 0;
+}
+
+int hsref_set_populations(hsref_ctx *c, const double *f)
+{
+    if (!c || !f) return -1;
+    memcpy(c->f, f, sizeof(double) * NQ * (size_t)c->N);
+    for (int64_t id = 0; id < c->N; ++id)
+        if (!fluid_node(c, id))
+            for (int i = 0; i < NQ; ++i) c->f[(int64_t)i * c->N + id] = 0.0;
+    phase_moments(c);
+    return 0;
+}
+
+/* The 18-direction table for sigma: W[18], s[18][3], ncorner[18], d[18][4][3],
+ * alpha[18][4] (unused corners are zero). */
+int hsref_shell_table(int sigma, double *W, double *s, int *ncorner, int *d, double *alpha)
+{
+    if (sigma < 1) return -1;
+    shell_dir sh[NSHELL];
+    build_shell(sigma, sh);
+    for (int q = 0; q < NSHELL; ++q) {
+        if (W) W[q] = sh[q].W;
+        for (int a = 0; a < 3; ++a)
+            if (s) s[3 * q + a] = sh[q].s[a];
+        if (ncorner) ncorner[q] = sh[q].ncorner;
+        for (int k = 0; k < 4; ++k) {
+            if (alpha) alpha[4 * q + k] = k < sh[q].ncorner ? sh[q].alpha[k] : 0.0;
+            for (int a = 0; a < 3; ++a)
+                if (d) d[12 * q + 3 * k + a] = k < sh[q].ncorner ? sh[q].d[k][a] : 0;
+        }
+    }
+    return 0;
+}
+
+int hsref_ball_count(int sigma) { return build_ball(sigma, NULL); }
+
+/* D3Q19 velocities [19][3] and weights [19]. */
+int hsref_lattice(int *c, double *w)
+{
+    for (int i = 0; i < NQ; ++i) {
+        if (w) w[i] = weight_of(i);
+        for (int a = 0; a < 3; ++a)
+            if (c) c[3 * i + a] = CV[i][a];
+    }
+    return 0;
+}

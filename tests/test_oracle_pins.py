@@ -1,0 +1,425 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics fix,
+independently of the oracle's own code: lattice and quadrature identities,
+closed forms (Poiseuille flow with halfway bounce-back, the equations of state
+implied by each closure, the collisional shear viscosity), conservation laws,
+hand-evaluated special cases of equation (12), and a brute-force evaluator.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_0712_2247_amd import workloads
+from tests import _bruteforce as bf
+
+VT2 = 1.0 / 3.0
+KAPPA = 2.0 / math.sqrt(VT2 * math.pi)
+
+
+# --------------------------------------------------------------- lattice / rule
+
+
+def test_d3q19_isotropy():
+    """Gauss-Hermite conditions of the D3Q19 set with v_T^2 = 1/3 (section
+    "Methods and Results"): weights sum to 1, odd moments vanish, the second
+    moment is v_T^2 I and the fourth v_T^4 (dd + dd + dd)."""
+    c, w = oracle.lattice()
+    c = c.astype(float)
+    assert abs(w.sum() - 1.0) < 1e-15
+    assert np.abs((w[:, None] * c).sum(0)).max() < 1e-15
+    m2 = np.einsum("i,ia,ib->ab", w, c, c)
+    assert np.abs(m2 - np.eye(3) / 3.0).max() < 1e-15
+    m4 = np.einsum("i,ia,ib,ic,id->abcd", w, c, c, c, c)
+    d = np.eye(3)
+    ref = (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d)
+           + np.einsum("ad,bc->abcd", d, d)) / 9.0
+    assert np.abs(m4 - ref).max() < 1e-15
+    assert np.abs(np.einsum("i,ia,ib,ic->abc", w, c, c, c)).max() < 1e-15
+    # every velocity has its opposite
+    for i in range(19):
+        assert any((c[k] == -c[i]).all() for k in range(19))
+
+
+def _sphere_mean(px, py, pz):
+    """Mean of x^px y^py z^pz over the unit sphere (closed form with double
+    factorials); zero when any power is odd."""
+    if px % 2 or py % 2 or pz % 2:
+        return 0.0
+
+    def df(k):  # (k-1)!! for even k
+        r = 1
+        for t in range(k - 1, 0, -2):
+            r *= t
+        return r
+    tot = px + py + pz
+    den = 1
+    for t in range(tot + 1, 1, -2):
+        den *= t
+    return df(px) * df(py) * df(pz) / den
+
+
+@pytest.mark.parametrize("sigma", [2, 3, 4, 5, 6, 7, 8])
+def test_shell_rule_exact_to_degree_5(sigma):
+    """The 18-point rule integrates every monomial of degree <= 5 exactly and
+    misses x^6 (2/15 instead of 1/7); the corner weights of each interpolated
+    point sum to one and reproduce the point itself (bilinear interpolation is
+    exact on linear functions)."""
+    W, s, nc, d, al = oracle.shell_table(sigma)
+    assert abs(W.sum() - 1.0) < 1e-15
+    for px in range(6):
+        for py in range(6 - px):
+            for pz in range(6 - px - py):
+                val = np.sum(W * s[:, 0] ** px * s[:, 1] ** py * s[:, 2] ** pz)
+                assert abs(val - _sphere_mean(px, py, pz)) < 1e-15, (px, py, pz)
+    x6 = np.sum(W * s[:, 0] ** 6)
+    assert abs(x6 - 2.0 / 15.0) < 1e-15 and abs(x6 - 1.0 / 7.0) > 1e-3
+    for q in range(18):
+        a = al[q, : nc[q]]
+        assert abs(a.sum() - 1.0) < 1e-15
+        assert (a >= 0).all()
+        pos = (a[:, None] * d[q, : nc[q]]).sum(0)
+        assert np.abs(pos - sigma * s[q]).max() < 1e-13
+        # corners are the lattice nodes of the cell around the point
+        for k in range(nc[q]):
+            assert np.abs(d[q, k] - sigma * s[q]).max() < 1.0
+    # the table comes in (q, -q) pairs
+    for p in range(9):
+        assert np.array_equal(s[2 * p], -s[2 * p + 1])
+        assert np.array_equal(d[2 * p], -d[2 * p + 1])
+        assert np.array_equal(al[2 * p], al[2 * p + 1])
+
+
+def test_ball_counts():
+    """Lattice points in the closed ball of radius sigma/2: for integer radius
+    the cubic-lattice ball counts 7, 33, 123, 257 (radii 1, 2, 3, 4); for radius
+    1.5 and 2.5 the shells of norm 0..2 and 0..6 give 1+6+12 = 19 and
+    1+6+12+8+6+24+24 = 81; radius 3.5 adds the norms 7..12
+    (0, 12, 30, 24, 24, 8 points) to those 81, giving 179."""
+    assert [oracle.ball_count(s) for s in (2, 3, 4, 5, 6, 8)] == [7, 19, 33, 81, 123, 257]
+    assert oracle.ball_count(7) == 179
+
+
+def test_g2_closures_and_equations_of_state():
+    """Contact values: the printed closure gives the compressibility factor
+    1 + 4 eta g2 = (1 + eta + eta^2)/(1 - eta)^3 (Percus-Yevick compressibility
+    route); the Carnahan-Starling contact value gives
+    (1 + eta + eta^2 - eta^3)/(1 - eta)^3.  Both reduce to 1 at eta = 0."""
+    for eta in (0.0, 0.05, 0.1, 0.2, 0.3, 0.35, 0.4):
+        zp = 1.0 + 4.0 * eta * oracle.g2(eta, oracle.G2_PAPER)
+        zc = 1.0 + 4.0 * eta * oracle.g2(eta, oracle.G2_CS)
+        assert abs(zp - (1 + eta + eta ** 2) / (1 - eta) ** 3) < 1e-14
+        assert abs(zc - (1 + eta + eta ** 2 - eta ** 3) / (1 - eta) ** 3) < 1e-14
+    assert oracle.g2(0.0) == 1.0
+    assert abs(oracle.g2(0.30) - 2.543731778425656) < 1e-12
+    assert abs(oracle.g2(0.30, oracle.G2_CS) - 2.478134110787172) < 1e-12
+
+
+# --------------------------------------------------------------- special cases
+
+
+def _two_node(sigma, r1off, a, b, jb=(0.0, 0.0, 0.0), L=16, wall=0):
+    nz = L + 2 * wall
+    n = np.zeros((nz, L, L))
+    j = np.zeros((3, nz, L, L))
+    r0 = (5, 5, wall)
+    r1 = tuple(r0[k] + r1off[k] for k in range(3))
+    n[r0[2], r0[1], r0[0]] = a
+    n[r1[2], r1[1], r1[0]] = b
+    u = np.zeros_like(j)
+    for k in range(3):
+        u[k, r1[2], r1[1], r1[0]] = jb[k] / b
+    o = oracle.Oracle(L, L, nz, sigma=sigma, tau=1.0, wall_lo=wall, wall_hi=wall)
+    o.init(n, u)
+    F = o.force()
+    return F[:, r0[2], r0[1], r0[0]], F[:, r1[2], r1[1], r1[0]], F
+
+
+def test_two_node_axis_pair():
+    """Two occupied nodes sigma apart along x (sigma = 4): each sees the other
+    through one axis point (W = 1/30, alpha = 1); the midpoint is a lattice node
+    at distance sigma/2 from both, so its coarse-grained packing fraction is
+    (pi sigma^3/6)(a + b)/33.  A current at the far node that moves it away
+    lowers the repulsion by the factor (1 - kappa u)."""
+    a, b, jx = 2e-3, 3e-3, 4e-6
+    F0, F1, F = _two_node(4, (4, 0, 0), a, b, jb=(jx, 0, 0))
+    P = VT2 * 16 * 4 * math.pi
+    G = bf.g2(math.pi * 64 / 6 * (a + b) / 33)
+    e0 = -P * a * (1 / 30) * G * (b - KAPPA * jx)
+    u1 = jx / b
+    e1 = P * b * (1 / 30) * G * (a - KAPPA * a * u1)
+    assert abs(F0[0] - e0) < 1e-15 * abs(e0) * 10 and F0[1] == 0 and F0[2] == 0
+    assert abs(F1[0] - e1) < 1e-15 * abs(e1) * 10
+    assert e0 < 0 < e1  # repulsive
+    assert abs(F.sum(axis=(1, 2, 3))).max() < 1e-18
+    # only the two nodes feel a force
+    assert np.count_nonzero(np.abs(F).sum(0)) == 2
+
+
+def test_two_node_diagonal_corners():
+    """Pairs at the corners of the interpolated point sigma(e_x + e_y)/sqrt(2),
+    sigma = 4, l = 2, theta = 2 sqrt(2) - 2: the corner (2,2) carries
+    alpha = (1-theta)^2 with an on-lattice midpoint; the corner (3,2) carries
+    theta (1 - theta) with a half-integer midpoint whose packing fraction is the
+    mean of two lattice values, each seeing only one of the pair."""
+    th = 2 * math.sqrt(2) - 2
+    a, b = 1.5e-3, 2.5e-3
+    P = VT2 * 16 * 4 * math.pi
+    pref = math.pi * 64 / 6
+    F0, _, _ = _two_node(4, (2, 2, 0), a, b)
+    G = bf.g2(pref * (a + b) / 33)
+    e = -P * a * (1 / 15) * (1 - th) ** 2 * G * b / math.sqrt(2)
+    assert abs(F0[0] - e) < 1e-14 * abs(e) and abs(F0[1] - e) < 1e-14 * abs(e) and F0[2] == 0
+    F0, _, _ = _two_node(4, (3, 2, 0), a, b)
+    G = bf.g2(pref * (a + b) / 66)
+    e = -P * a * (1 / 15) * th * (1 - th) * G * b / math.sqrt(2)
+    assert abs(F0[0] - e) < 1e-14 * abs(e) and abs(F0[1] - e) < 1e-14 * abs(e)
+
+
+def test_two_node_odd_sigma_axis():
+    """sigma = 3: the axis midpoint r + (1.5, 0, 0) is half-integer; the mean of
+    the packing fraction at its two lattice neighbours sees each node once
+    (19-point ball of radius 1.5)."""
+    a, b = 1e-2, 2e-2
+    F0, _, _ = _two_node(3, (3, 0, 0), a, b)
+    P = VT2 * 9 * 4 * math.pi
+    G = bf.g2(math.pi * 27 / 6 * (a + b) / 38)
+    e = -P * a * (1 / 30) * G * b
+    assert abs(F0[0] - e) < 1e-14 * abs(e)
+
+
+def test_wall_factor_on_current_term():
+    """The wall factor multiplies only the density-current term, evaluated at
+    the receiving node: in the first fluid layer, half a lattice spacing from
+    the halfway wall plane, it is 1 - exp(-1/(2 sigma))."""
+    a, b, jx = 2e-3, 3e-3, 5e-6
+    F0, _, _ = _two_node(4, (4, 0, 0), a, b, jb=(jx, 0, 0), wall=2)
+    P = VT2 * 16 * 4 * math.pi
+    G = bf.g2(math.pi * 64 / 6 * (a + b) / 33)
+    chi = 1 - math.exp(-0.5 / 4)
+    e = -P * a * (1 / 30) * G * (b - chi * KAPPA * jx)
+    assert abs(F0[0] - e) < 1e-14 * abs(e)
+
+
+# --------------------------------------------------------------- brute force
+
+
+@pytest.mark.parametrize("sigma,walls", [(2, 0), (3, 0), (4, 0), (5, 0), (3, 2), (4, 2), (5, 3)])
+def test_force_matches_brute_force(sigma, walls):
+    shape = (8 + 2 * walls, 7, 6)
+    nb = workloads.number_density(0.25, sigma)
+    n, u = workloads.random_state(shape, nb, 0.05, 2e-3, seed=100 + sigma, solid_lo=walls,
+                                  solid_hi=walls)
+    o = oracle.Oracle(6, 7, shape[0], sigma=sigma, tau=1.0, wall_lo=walls, wall_hi=walls,
+                      accel=(1e-5, -2e-6, 0.0))
+    o.init(n, u)
+    F = o.force()
+    nn, uu = o.moments()
+    ref = bf.Grid(nn, nn[None] * uu, sigma, walls, walls).force(accel=(1e-5, -2e-6, 0.0))
+    scale = np.abs(ref).max()
+    assert scale > 0
+    assert np.abs(F - ref).max() <= 1e-13 * scale
+
+
+# --------------------------------------------------------------- uniform fluid
+
+
+@pytest.mark.parametrize("sigma,eta", [(2, 0.1), (3, 0.2), (4, 0.3), (6, 0.25), (8, 0.35)])
+@pytest.mark.parametrize("model", [oracle.G2_PAPER, oracle.G2_CS])
+def test_uniform_fluid(sigma, eta, model):
+    """Uniform periodic fluid: the coarse-grained packing fraction is eta, the
+    hard-sphere force vanishes exactly at rest and to rounding with a uniform
+    flow."""
+    L = max(12, 2 * sigma + 2)
+    nb = workloads.number_density(eta, sigma)
+    o = oracle.Oracle(L, L, L, sigma=sigma, tau=1.0, g2_model=model)
+    o.init(np.full((L, L, L), nb))
+    assert np.abs(o.eta_bar() - eta).max() < 1e-14
+    assert np.abs(o.force()).max() == 0.0
+    u = np.zeros((3, L, L, L))
+    u[0], u[1], u[2] = 1e-3, -2e-3, 5e-4
+    o.init(np.full((L, L, L), nb), u)
+    ref = VT2 * sigma ** 2 * 4 * math.pi * nb * nb * oracle.g2(eta, model)
+    assert np.abs(o.force()).max() <= 1e-15 * ref
+
+
+def test_eos_linear_response():
+    """A long-wave density modulation on a uniform fluid: the z force per unit
+    volume tends to -dP^c/dn dn/dz with the collisional pressure
+    P^c = k_B T (2 pi/3) sigma^3 n^2 g2 of the paper's bulk equation of state,
+    with the error falling as (sigma/L)^2.  Richardson extrapolation of L = 128
+    and 256 removes that term."""
+    for model in (oracle.G2_PAPER, oracle.G2_CS):
+        for sigma, eta in ((4, 0.30), (6, 0.25)):
+            ratios = []
+            for L in (128, 256):
+                nb = workloads.number_density(eta, sigma)
+                eps = 1e-7
+                z = np.arange(L)
+                n = (nb * (1 + eps * np.sin(2 * np.pi * z / L))).reshape(L, 1, 1)
+                o = oracle.Oracle(1, 1, L, sigma=sigma, tau=1.0, g2_model=model)
+                o.init(n)
+                Fz = o.force()[2, :, 0, 0]
+                h = 1e-5
+                dg = (bf.g2(eta + h, model) - bf.g2(eta - h, model)) / (2 * h)
+                g = bf.g2(eta, model)
+                dPdn = VT2 * 2 * np.pi / 3 * sigma ** 3 * (
+                    2 * nb * g + nb ** 2 * dg * np.pi * sigma ** 3 / 6)
+                pred = -dPdn * eps * nb * 2 * np.pi / L * np.cos(2 * np.pi * z / L)
+                ratios.append(np.dot(Fz, pred) / np.dot(pred, pred))
+            assert abs(ratios[1] - 1) < 3e-3
+            extrap = (4 * ratios[1] - ratios[0]) / 3
+            assert abs(extrap - 1) < 2e-5, (model, sigma, ratios, extrap)
+
+
+# --------------------------------------------------------------- dynamics
+
+
+def _poiseuille_exact(g, tau, nz, wall):
+    """Steady channel flow of D3Q19 BGK with halfway bounce-back, first-order
+    forcing and u = j/n: the parabola between the halfway planes plus a
+    constant slip term (16 tau^2 - 20 tau + 3)/12."""
+    nu = (tau - 0.5) / 3
+    za, zb = wall - 0.5, nz - wall - 0.5
+    z = np.arange(wall, nz - wall)
+    return g / (2 * nu) * ((z - za) * (zb - z) + (16 * tau ** 2 - 20 * tau + 3) / 12)
+
+
+@pytest.mark.parametrize("tau", [0.6, 0.8, 1.0, 1.5])
+@pytest.mark.parametrize("H", [10, 20])
+def test_poiseuille_closed_form(tau, H):
+    g = 1e-6
+    nz = H + 2
+    o = oracle.Oracle(1, 1, nz, sigma=4, tau=tau, accel=(g, 0, 0), wall_lo=1, wall_hi=1,
+                      force_mode=oracle.FORCE_OFF)
+    n = np.zeros((nz, 1, 1))
+    n[1:-1] = 1.0
+    o.init(n)
+    steps = int(40 * H * H / ((tau - 0.5) / 3)) + 2000
+    o.step(steps)
+    _, pu = o.profiles()
+    ex = _poiseuille_exact(g, tau, nz, 1)
+    assert np.abs(pu[0, 1:-1] - ex).max() <= 1e-9 * ex.max()
+    assert np.abs(pu[1:]).max() <= 1e-9 * ex.max()
+
+
+def test_poiseuille_low_packing_limit():
+    """With the hard-sphere term on, the slit velocity profile approaches the
+    plain BGK profile linearly in the packing fraction."""
+    sigma, H, tau, g = 4, 20, 1.0, 1e-6
+    w = workloads.wall_layers(sigma)
+    nz = H + 2 * w
+
+    def run(eta, fm):
+        o = oracle.Oracle(1, 1, nz, sigma=sigma, tau=tau, accel=(g, 0, 0), wall_lo=w,
+                          wall_hi=w, force_mode=fm)
+        n = np.zeros((nz, 1, 1))
+        n[w:-w] = workloads.number_density(eta, sigma)
+        o.init(n)
+        o.step(30000)
+        return o.profiles()[1][0, w:-w]
+
+    u0 = run(1e-3, oracle.FORCE_OFF)
+    errs = []
+    for eta in (1e-2, 1e-3, 1e-4):
+        errs.append(np.linalg.norm(run(eta, oracle.FORCE_EXACT) - u0) / np.linalg.norm(u0))
+    assert errs[0] < 0.1
+    for k in range(2):
+        assert 7.0 < errs[k] / errs[k + 1] < 13.0, errs
+
+
+def test_shear_wave_collisional_viscosity():
+    """Decay of a transverse wave u_x ~ sin(k z) on a uniform periodic fluid.
+    Switching the hard-sphere term on multiplies the per-step amplitude by
+    1 - nu_c(k) k^2 with nu_c(k) the lattice symbol of the density-current
+    term; nu_c(k) tends to the continuum value (4/15) sqrt(pi) v_T n sigma^4 g2
+    up to the discretisation of the shell."""
+    for sigma, eta, L in ((4, 0.30, 128), (6, 0.25, 128), (8, 0.35, 256)):
+        nb = workloads.number_density(eta, sigma)
+        k = 2 * np.pi / L
+        z = np.arange(L)
+        basis = np.sin(k * z)
+
+        def rate(fm):
+            u = np.zeros((3, L, 1, 1))
+            u[0, :, 0, 0] = 1e-6 * basis
+            o = oracle.Oracle(1, 1, L, sigma=sigma, tau=1.0, force_mode=fm)
+            o.init(np.full((L, 1, 1), nb), u)
+            amps = []
+            for t in range(300):
+                n, uu = o.moments()
+                amps.append(np.dot(n[:, 0, 0] * uu[0, :, 0, 0], basis))
+                o.step(1)
+            t = np.arange(300)
+            return -np.polyfit(t[150:], np.log(amps[150:]), 1)[0]
+
+        G = bf.g2(eta)
+        acc = 0.0
+        for W, s in bf.quadrature_points():
+            for d, al in bf.corners(sigma, s):
+                acc += W * al * s[0] ** 2 * (1 - math.cos(k * d[2]))
+        nuc_k = VT2 * sigma ** 2 * 4 * math.pi * nb * G * KAPPA * acc / k ** 2
+        lam = rate(oracle.FORCE_EXACT) - rate(oracle.FORCE_OFF)
+        assert abs(lam / -math.log(1 - nuc_k * k * k) - 1) < 2e-5
+        cont = 4 / 15 * math.sqrt(math.pi) * math.sqrt(VT2) * nb * sigma ** 4 * G
+        assert abs(nuc_k / cont - 1) < 0.03
+
+
+def test_momentum_conservation_periodic():
+    """Periodic box with random density and current, no external field: the
+    total momentum stays constant (each lattice pair exchanges equal and
+    opposite momentum)."""
+    L, sigma = 8, 3
+    nb = workloads.number_density(0.2, sigma)
+    n, u = workloads.random_state((L, L, L), nb, 0.05, 1e-3, seed=7)
+    u[0] += 2e-3
+    o = oracle.Oracle(L, L, L, sigma=sigma, tau=0.9)
+    o.init(n, u)
+    F = o.force()
+    assert np.abs(F.sum(axis=(1, 2, 3))).max() <= 1e-15 * np.abs(F).sum()
+    n0, u0 = o.moments()
+    p0 = (n0[None] * u0).sum(axis=(1, 2, 3))
+    m0 = n0.sum()
+    o.step(2000)
+    n1, u1 = o.moments()
+    p1 = (n1[None] * u1).sum(axis=(1, 2, 3))
+    assert abs(n1.sum() - m0) <= 1e-12 * m0
+    assert np.abs(p1 - p0).max() <= 1e-12 * np.abs(p0).max()
+
+
+def test_mass_conservation_slit():
+    """Slit 8x8x24, sigma 4, eta 0.30, driven for 2000 steps: no mass source
+    (C^(0) = 0) and the bounce-back walls lose nothing."""
+    wl = workloads.slit_small_f64()
+    n, u = wl.fields()
+    o = oracle.Oracle(**wl.params())
+    o.init(n, u)
+    m0 = o.moments()[0].sum()
+    o.step(wl.steps)
+    nn, uu = o.moments()
+    assert np.isfinite(nn).all()
+    assert abs(nn.sum() - m0) <= 1e-12 * m0
+    assert (nn[: wl.wall_lo] == 0).all() and (nn[wl.nz - wl.wall_hi:] == 0).all()
+    pn, pu = o.profiles()
+    # a steady slit flow in +x, symmetric about the mid plane
+    assert (pu[0, wl.wall_lo: wl.nz - wl.wall_hi] > 0).all()
+    assert np.abs(pn - pn[::-1]).max() < 1e-6 * pn.max()
+
+
+def test_init_equilibrium_and_determinism():
+    wl = workloads.slit_small_f64()
+    n, u = wl.fields()
+    u[0, wl.wall_lo: wl.nz - wl.wall_hi] = 1e-3
+    u[2, wl.wall_lo: wl.nz - wl.wall_hi] = -5e-4
+    o = oracle.Oracle(**wl.params())
+    o.init(n, u)
+    nn, uu = o.moments()
+    assert np.abs(nn - n).max() <= 4e-15 * n.max()
+    assert np.abs(uu - u).max() <= 1e-13 * 1e-3
+    f = o.get_populations()
+    o.step(50)
+    a = o.get_populations()
+    o.set_populations(f)
+    o.step(50)
+    b = o.get_populations()
+    assert np.array_equal(a, b)
