@@ -1,0 +1,178 @@
+/*
+ * hslb.h -- C ABI of libhslb.so: the time step of the lattice Boltzmann method
+ * for inhomogeneous hard-sphere fluids (Melchionna and Marini Bettolo Marconi,
+ * "Lattice Boltzmann method for inhomogeneous fluids") on one AMD Instinct MI355X
+ * (gfx950) GPU.
+ *
+ * The problem the calls state is the paper's: a D3Q19 lattice (section
+ * "Methods and Results") carrying a hard-sphere fluid between two flat walls
+ * normal to z with halfway bounce-back (subsection "Numerical validation"),
+ * periodic in x and y (and in z when there are no walls), driven by a uniform
+ * external field parallel to the walls, evolved by the forward-Euler
+ * propagation of equation (10) with the second-order equilibrium (11) and the
+ * isothermal hard-sphere momentum-transfer term C^(1) of equation (12).
+ *
+ * Conventions shared by every call:
+ *  - Node order: node = x + nx*(y + ny*z).  Scalar fields are [N] arrays,
+ *    vector fields [3][N] (component-major), populations [19][N], where
+ *    N = nx*ny*nz counts solid wall layers too.
+ *  - Host arrays are caller-owned, FP64, and copied during the call; the
+ *    library never keeps a host pointer.  The library owns all device memory.
+ *  - Units: lattice units, particle mass m = 1, k_B T = v_T^2 = 1/3.
+ *  - Every call returns int: HSLB_OK (0) or a negative HSLB_E* code; no call
+ *    aborts or throws.  hslb_last_error() gives a message for the last failure.
+ *  - A context is used by one host thread at a time.  Work is queued on the
+ *    context's HIP stream; calls that return host data synchronise it.
+ *
+ * D3Q19 velocity order (index i: c_i):
+ *   0:(0,0,0) 1:(1,0,0) 2:(-1,0,0) 3:(0,1,0) 4:(0,-1,0) 5:(0,0,1) 6:(0,0,-1)
+ *   7:(1,1,0) 8:(-1,-1,0) 9:(1,-1,0) 10:(-1,1,0) 11:(1,0,1) 12:(-1,0,-1)
+ *   13:(1,0,-1) 14:(-1,0,1) 15:(0,1,1) 16:(0,-1,-1) 17:(0,1,-1) 18:(0,-1,1)
+ */
+#ifndef HSLB_H
+#define HSLB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    HSLB_OK = 0,
+    HSLB_EINVAL = -1,    /* bad parameters or fields */
+    HSLB_ENOMEM = -2,    /* device or host allocation failed */
+    HSLB_EDEVICE = -3,   /* HIP runtime error */
+    HSLB_EUNSTABLE = -4, /* watchdog: non-finite state or mass drift */
+    HSLB_ESTATE = -5,    /* call out of order (e.g. step before init) */
+    HSLB_ENOSURR = -6    /* surrogate force requested without weights */
+};
+
+enum { HSLB_FP64 = 0, HSLB_FP32 = 1 }; /* population storage precision */
+
+/* Contact value of the pair correlation as a function of the coarse-grained
+ * packing fraction eta (section "Methods and Results", Fischer-Methfessel
+ * prescription): HSLB_G2_PAPER is the printed closure
+ * (1 - eta/2 + eta^2/4)/(1 - eta)^3, HSLB_G2_CS the Carnahan-Starling contact
+ * value (1 - eta/2)/(1 - eta)^3. */
+enum { HSLB_G2_PAPER = 0, HSLB_G2_CS = 1 };
+
+/* Interaction force: the exact shell sum of equation (12), the learned
+ * surrogate (with the exact sum as periodic judge), or none. */
+enum { HSLB_FORCE_EXACT = 0, HSLB_FORCE_SURROGATE = 1, HSLB_FORCE_OFF = 2 };
+
+typedef struct {
+    int32_t nx, ny, nz;       /* full grid, solid wall layers included */
+    int32_t wall_lo, wall_hi; /* solid layers at the z ends; both 0: z periodic.
+                                 Walls sit halfway between the last solid and the
+                                 first fluid layer. */
+    int32_t sigma;            /* hard-sphere diameter in lattice units, 2..8;
+                                 nx, ny >= sigma + 2 */
+    double tau;               /* BGK relaxation time, > 1/2 */
+    double accel[3];          /* external force per particle g; the momentum
+                                 source is n g (equation (1)'s field term) */
+    int32_t g2_model;         /* HSLB_G2_* */
+    int32_t wall_reg;         /* 1: wall factor 1 - exp(-d_w/sigma) on the
+                                 density-current term (section "Methods and
+                                 Results"); 0: off */
+    int32_t precision;        /* HSLB_FP64 or HSLB_FP32 */
+    int32_t force_mode;       /* HSLB_FORCE_* */
+    int32_t surr_check_every; /* surrogate mode: exact judge every K steps */
+    double surr_tol;          /* surrogate mode: residual threshold */
+} hslb_params;
+
+typedef struct hslb_ctx hslb_ctx;
+
+/* Validate *p and allocate a context on the current HIP device.
+ * Errors: HSLB_EINVAL (bad parameters; *out untouched), HSLB_ENOMEM,
+ * HSLB_EDEVICE.  Release with hslb_destroy. */
+int hslb_create(const hslb_params *p, hslb_ctx **out);
+
+/* Free every device and host resource of the context.  NULL is ignored. */
+void hslb_destroy(hslb_ctx *ctx);
+
+/* Message of the last failing call on ctx (library-owned, valid until the next
+ * call on ctx); a static message when ctx is NULL. */
+const char *hslb_last_error(const hslb_ctx *ctx);
+
+/* Queue all later work on the given hipStream_t (NULL: the context's own
+ * stream).  The caller keeps ownership of the stream. */
+int hslb_set_stream(hslb_ctx *ctx, void *hip_stream);
+
+/* Initial state: populations set to the local equilibrium (11) of the density
+ * n[N] and velocity u[3][N] (u may be NULL for rest).  Values on solid layers
+ * are ignored and treated as 0.  Errors: HSLB_EINVAL if a fluid n is negative
+ * or non-finite or a fluid u non-finite. */
+int hslb_init(hslb_ctx *ctx, const double *n, const double *u);
+
+/* Advance nsteps time steps of equation (10): moments, coarse-grained density,
+ * midpoint contact values, hard-sphere force (12) plus n g, BGK collision with
+ * the first-order source, streaming with halfway bounce-back.  Asynchronous;
+ * launch errors are returned here, a failing watchdog (see
+ * hslb_set_watchdog) returns HSLB_EUNSTABLE.  Errors: HSLB_ESTATE before init,
+ * HSLB_EINVAL for nsteps < 0. */
+int hslb_step(hslb_ctx *ctx, int64_t nsteps);
+
+/* Wait for all queued work of the context. */
+int hslb_sync(hslb_ctx *ctx);
+
+/* Number of steps taken since init (or since the last set_populations). */
+int hslb_step_count(const hslb_ctx *ctx, int64_t *steps);
+
+/* Moments of the current populations (equation (8)): n[N] and u[3][N] with
+ * u = j/n (0 where n = 0, and on solid nodes).  Either pointer may be NULL. */
+int hslb_moments(hslb_ctx *ctx, double *n, double *u);
+
+/* Layer profiles accumulated in FP64 on the GPU: n_z[nz] = mean of n over the
+ * layer, u_z[3][nz] = (sum of j over the layer)/(sum of n) (0 on empty layers).
+ * Either pointer may be NULL. */
+int hslb_profiles(hslb_ctx *ctx, double *n_z, double *u_z);
+
+/* Total force F[3][N] = C^(1) + n g at the current state (0 on solid nodes),
+ * as the next step would apply it. */
+int hslb_force(hslb_ctx *ctx, double *F);
+
+/* Coarse-grained packing fraction eta_bar[N] = (pi sigma^3/6) times the mean
+ * density over the lattice nodes of the closed ball of radius sigma/2, at the
+ * current state. */
+int hslb_eta_bar(hslb_ctx *ctx, double *eta_bar);
+
+/* Populations f[19][N] of the current state (checkpoint), and their
+ * replacement (resume).  set_populations zeroes solid nodes and resets the
+ * step counter.  In HSLB_FP32 contexts the values pass through FP32 storage. */
+int hslb_get_populations(hslb_ctx *ctx, double *f);
+int hslb_set_populations(hslb_ctx *ctx, const double *f);
+
+/* Watchdog: every `every` steps (0: off) check that the state is finite and
+ * that the total mass drifts by at most tol (relative) from its value at init;
+ * hslb_step returns HSLB_EUNSTABLE at the first failing check, with the step
+ * count at that check available from hslb_step_count. */
+int hslb_set_watchdog(hslb_ctx *ctx, int64_t every, double tol);
+
+/* Replay steps from a captured HIP graph (1, default) or launch kernels one by
+ * one (0).  Both give bitwise identical results. */
+int hslb_set_graph(hslb_ctx *ctx, int32_t enable);
+
+/* Per-kernel timing with HIP events on the context's stream.  When enabled
+ * (and graphs off), hslb_step brackets every kernel launch with events;
+ * hslb_kernel_times fills names/total milliseconds/launch counts for up to
+ * `cap` kernels and sets *count. */
+int hslb_set_kernel_timing(hslb_ctx *ctx, int32_t enable);
+int hslb_kernel_times(hslb_ctx *ctx, int32_t cap, char (*names)[32], double *total_ms,
+                      int64_t *launches, int32_t *count);
+
+/* Wall-clock milliseconds per step and fluid-node updates per second / 1e6
+ * over the last hslb_step call (measured with HIP events around the call). */
+int hslb_get_timings(hslb_ctx *ctx, double *ms_per_step, double *mlups);
+
+/* Device-to-device copy of `bytes` bytes, repeated `iters` times on a private
+ * stream: *gbps = 2 * bytes * iters / elapsed (read + write).  The reference
+ * for the achievable HBM bandwidth and the calibration kernel ("k_copy") of the
+ * traffic counters.  Allocates and frees its own two buffers. */
+int hslb_copy_bandwidth(int64_t bytes, int32_t iters, double *gbps);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSLB_H */

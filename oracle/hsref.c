@@ -54,6 +54,9 @@
 #endif
 
 #define NQ 19
+/* grids below this size run on one thread: the fork/join of four phases per
+ * step would cost more than the work */
+#define PAR_MIN_NODES 32768
 #define NSHELL 18
 
 typedef struct {
@@ -318,7 +321,7 @@ static void phase_moments(hsref_ctx *c)
 {
     const int64_t N = c->N;
     const int64_t plane = (int64_t)c->p.nx * c->p.ny;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (c->N >= PAR_MIN_NODES)
     for (int z = 0; z < c->p.nz; ++z) {
         for (int64_t id = z * plane; id < (z + 1) * plane; ++id) {
             double n = 0.0, j[3] = {0.0, 0.0, 0.0};
@@ -347,7 +350,7 @@ static void phase_eta_bar(hsref_ctx *c)
     const int64_t plane = (int64_t)c->p.nx * c->p.ny;
     const double sig = (double)c->p.sigma;
     const double pref = M_PI * sig * sig * sig / 6.0 / (double)c->nball;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (c->N >= PAR_MIN_NODES)
     for (int z = 0; z < c->p.nz; ++z) {
         for (int y = 0; y < c->p.ny; ++y) {
             for (int x = 0; x < c->p.nx; ++x) {
@@ -404,7 +407,7 @@ static void phase_force(hsref_ctx *c)
     const double sig = (double)c->p.sigma;
     const double pref = -vt2 * sig * sig * 4.0 * M_PI;
     const int hs_on = (c->p.force_mode != 2);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (c->N >= PAR_MIN_NODES)
     for (int z = 0; z < c->p.nz; ++z) {
         for (int y = 0; y < c->p.ny; ++y) {
             for (int x = 0; x < c->p.nx; ++x) {
@@ -455,7 +458,7 @@ static void phase_collide_stream(hsref_ctx *c)
     const int64_t plane = (int64_t)c->p.nx * c->p.ny;
     const double tau = c->p.tau;
     memset(c->fs, 0, sizeof(double) * (size_t)NQ * (size_t)N);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (c->N >= PAR_MIN_NODES)
     for (int z = 0; z < c->p.nz; ++z) {
         if (is_solid_z(c, z)) continue;
         for (int y = 0; y < c->p.ny; ++y) {

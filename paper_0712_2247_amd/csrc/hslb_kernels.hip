@@ -1,0 +1,680 @@
+// HIP kernels of the hard-sphere lattice Boltzmann step for gfx950.
+//
+// One step (equation (10) of the paper) runs as four kernels on the stream:
+//   k_moments  populations -> n, j                      (equation (8))
+//   k_smooth   n -> coarse-grained packing fraction     (ball of radius sigma/2)
+//   k_gfield   eta_bar -> contact values g2 on the 7 sub-lattices of pair
+//              midpoints (lattice nodes, edge, face centres)
+//   k_collide  shell-sum force C^(1) of equation (12) + n g, BGK collision with
+//              the second-order equilibrium (11) and first-order source, push
+//              streaming with halfway bounce-back
+//
+// Storage: populations SoA [19][pop_stride] in TF (float or double), shifted by
+// the constant w_i n_ref so that FP32 storage keeps the small deviations from a
+// uniform state; every sum, the equilibrium subtraction and the force are FP64
+// in registers.  Moment fields (n, j, eta_bar, G) are TM, padded with hz layers
+// in z that hold zeros beyond walls or periodic ghost copies.
+#include "hslb_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace hslb {
+
+namespace {
+
+constexpr int CX[NQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int CY[NQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int CZ[NQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+constexpr int OPP[NQ] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+
+__device__ __forceinline__ constexpr double wq(int i)
+{
+    return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+// floor(sigma / sqrt(2)): the largest l with 2 l^2 <= sigma^2.
+__host__ __device__ constexpr int ell_of(int sigma)
+{
+    int l = 0;
+    while (2 * (l + 1) * (l + 1) <= sigma * sigma) ++l;
+    return l;
+}
+
+__host__ __device__ constexpr int floordiv2(int d) { return (d - (d & 1)) / 2; }
+
+template <int D>
+__device__ __forceinline__ int wrapc(int v, int n)
+{
+    int w = v + D;
+    if constexpr (D > 0) w = (w >= n) ? w - n : w;
+    if constexpr (D < 0) w = (w < 0) ? w + n : w;
+    return w;
+}
+
+__device__ __forceinline__ int wrapr(int w, int n)
+{
+    w = (w < 0) ? w + n : w;
+    return (w >= n) ? w - n : w;
+}
+
+__device__ __forceinline__ double g2_of(double eta, int model)
+{
+    const double om = 1.0 - eta;
+    const double num = model ? (1.0 - 0.5 * eta) : (1.0 - 0.5 * eta + 0.25 * eta * eta);
+    return num / (om * om * om);
+}
+
+// Store v at padded z = z + hz and, for a periodic z axis, at every ghost layer
+// congruent to it modulo nz.
+template <typename TM>
+__device__ __forceinline__ void store_padded(const LatticeDev &L, TM *dst, int rem, int z, TM v)
+{
+    if (!L.zper) {
+        dst[rem + L.plane * (z + L.hz)] = v;
+        return;
+    }
+    int p = z + L.hz;
+    while (p - L.nz >= 0) p -= L.nz;
+    for (; p < L.nz + 2 * L.hz; p += L.nz) dst[rem + L.plane * p] = v;
+}
+
+__device__ __forceinline__ bool is_fluid_z(const LatticeDev &L, int z)
+{
+    return L.zper || (z >= L.wall_lo && z < L.nz - L.wall_hi);
+}
+
+// --------------------------------------------------------------------- init
+
+template <typename TF>
+__global__ __launch_bounds__(256) void k_init(LatticeDev L, double n_ref, const double *__restrict__ n,
+                                              const double *__restrict__ u, TF *__restrict__ f)
+{
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= L.N) return;
+    const int z = id / L.plane;
+    const bool fl = is_fluid_z(L, z);
+    const double nn = fl ? n[id] : 0.0;
+    const double ux = fl ? u[id] : 0.0, uy = fl ? u[L.N + id] : 0.0, uz = fl ? u[2 * L.N + id] : 0.0;
+    const double uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+        const double feq = wq(i) * nn * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        f[(size_t)i * L.pop_stride + id] = fl ? (TF)(feq - wq(i) * n_ref) : (TF)0;
+    }
+}
+
+// ------------------------------------------------------------------ moments
+
+template <typename TF, typename TM>
+__global__ __launch_bounds__(256) void k_moments(LatticeDev L, double n_ref, const TF *__restrict__ f,
+                                                 Fields<TM> fld)
+{
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= L.N) return;
+    const int z = id / L.plane;
+    const int rem = id - z * L.plane;
+    double n = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    if (is_fluid_z(L, z)) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            const double fi = (double)f[(size_t)i * L.pop_stride + id];
+            s += fi;
+            if (CX[i] > 0) jx += fi;
+            if (CX[i] < 0) jx -= fi;
+            if (CY[i] > 0) jy += fi;
+            if (CY[i] < 0) jy -= fi;
+            if (CZ[i] > 0) jz += fi;
+            if (CZ[i] < 0) jz -= fi;
+        }
+        n = s + n_ref;
+    }
+    store_padded(L, fld.n, rem, z, (TM)n);
+    store_padded(L, fld.j, rem, z, (TM)jx);
+    store_padded(L, fld.j + L.fld_stride, rem, z, (TM)jy);
+    store_padded(L, fld.j + 2 * L.fld_stride, rem, z, (TM)jz);
+}
+
+// ------------------------------------------------- coarse-grained density
+
+template <int SIG, typename TM>
+__global__ __launch_bounds__(256) void k_smooth(LatticeDev L, double eta_pref, Fields<TM> fld)
+{
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= L.N) return;
+    const int z = id / L.plane;
+    const int rem = id - z * L.plane;
+    const int y = rem / L.nx;
+    const int x = rem - y * L.nx;
+    constexpr int R = SIG / 2;
+    double s = 0.0;
+#pragma unroll
+    for (int oz = -R; oz <= R; ++oz) {
+#pragma unroll
+        for (int oy = -R; oy <= R; ++oy) {
+            const int yy = wrapr(y + oy, L.ny);
+            const TM *row = fld.n + L.nx * (yy + L.ny * (z + L.hz + oz));
+#pragma unroll
+            for (int ox = -R; ox <= R; ++ox) {
+                if (4 * (ox * ox + oy * oy + oz * oz) <= SIG * SIG) s += (double)row[wrapr(x + ox, L.nx)];
+            }
+        }
+    }
+    store_padded(L, fld.eb, rem, z, (TM)(eta_pref * s));
+}
+
+// ------------------------------------------ contact values at pair midpoints
+
+// G slot b (bits x=1, y=2, z=4) at node r: g2 of the mean eta_bar over the
+// nodes r + {0,1}^b, i.e. at the midpoint r + b/2 of every lattice pair whose
+// offset has odd components exactly on the axes of b.
+template <typename TM>
+__global__ __launch_bounds__(256) void k_gfield(LatticeDev L, int model, Fields<TM> fld)
+{
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= L.N) return;
+    const int z = id / L.plane;
+    const int rem = id - z * L.plane;
+    const int y = rem / L.nx;
+    const int x = rem - y * L.nx;
+    const int x1 = wrapc<1>(x, L.nx), y1 = wrapc<1>(y, L.ny);
+    const int zp = z + L.hz;
+    auto e = [&](int xx, int yy, int zz) -> double {
+        return (double)fld.eb[xx + L.nx * (yy + L.ny * zz)];
+    };
+    const double e000 = e(x, y, zp), e100 = e(x1, y, zp), e010 = e(x, y1, zp), e001 = e(x, y, zp + 1);
+    const double e110 = e(x1, y1, zp), e101 = e(x1, y, zp + 1), e011 = e(x, y1, zp + 1);
+    const size_t fs = L.fld_stride;
+    store_padded(L, fld.G + 0 * fs, rem, z, (TM)g2_of(e000, model));
+    store_padded(L, fld.G + 1 * fs, rem, z, (TM)g2_of(0.5 * (e000 + e100), model));
+    store_padded(L, fld.G + 2 * fs, rem, z, (TM)g2_of(0.5 * (e000 + e010), model));
+    store_padded(L, fld.G + 3 * fs, rem, z, (TM)g2_of(0.25 * ((e000 + e100) + (e010 + e110)), model));
+    store_padded(L, fld.G + 4 * fs, rem, z, (TM)g2_of(0.5 * (e000 + e001), model));
+    store_padded(L, fld.G + 5 * fs, rem, z, (TM)g2_of(0.25 * ((e000 + e100) + (e001 + e101)), model));
+    store_padded(L, fld.G + 6 * fs, rem, z, (TM)g2_of(0.25 * ((e000 + e010) + (e001 + e011)), model));
+}
+
+// ------------------------------------------------------------ shell force
+
+struct NodeCtx {
+    int x, y, zp;
+    double u[3];
+    double ckap;  // chi(z) * kappa
+};
+
+// One pair element: the contact value at the midpoint of (r, r+d) times
+// [n(r+d) - chi kappa s.(j(r+d) - n(r+d) u(r))], for s = (SX,SY,SZ) (scaled by
+// 1/sqrt(2) on the face diagonals).
+template <int DX, int DY, int DZ, int SX, int SY, int SZ, bool DIAG, typename TM>
+__device__ __forceinline__ double element(const Fields<TM> &F, const LatticeDev &L, const NodeCtx &c)
+{
+    const int xx = wrapc<DX>(c.x, L.nx), yy = wrapc<DY>(c.y, L.ny);
+    const int idx = xx + L.nx * (yy + L.ny * (c.zp + DZ));
+    constexpr int BX = floordiv2(DX), BY = floordiv2(DY), BZ = floordiv2(DZ);
+    constexpr int SLOT = (DX & 1) | ((DY & 1) << 1) | ((DZ & 1) << 2);
+    const int bx = wrapc<BX>(c.x, L.nx), by = wrapc<BY>(c.y, L.ny);
+    const int bidx = bx + L.nx * (by + L.ny * (c.zp + BZ));
+    const double G = (double)F.G[(size_t)SLOT * L.fld_stride + bidx];
+    const double ne = (double)F.n[idx];
+    double cur = 0.0;
+    if constexpr (SX != 0) cur += SX * ((double)F.j[idx] - ne * c.u[0]);
+    if constexpr (SY != 0) cur += SY * ((double)F.j[L.fld_stride + idx] - ne * c.u[1]);
+    if constexpr (SZ != 0) cur += SZ * ((double)F.j[2 * (size_t)L.fld_stride + idx] - ne * c.u[2]);
+    if constexpr (DIAG) cur *= 0.70710678118654752440;
+    return G * (ne - c.ckap * cur);
+}
+
+// Offsets of corner (IA, IB) of the face diagonal with signs (SA, SB) in plane
+// PL (0: xy, 1: xz, 2: yz), lengths l + IA and l + IB.
+template <int PL, int SA, int SB, int LA, int LB>
+struct Diag {
+    static constexpr int a = SA * LA, b = SB * LB;
+    static constexpr int DX = (PL == 2) ? 0 : a;
+    static constexpr int DY = (PL == 0) ? b : ((PL == 2) ? a : 0);
+    static constexpr int DZ = (PL == 0) ? 0 : b;
+    static constexpr int SX = (PL == 2) ? 0 : SA;
+    static constexpr int SY = (PL == 0) ? SB : ((PL == 2) ? SA : 0);
+    static constexpr int SZ = (PL == 0) ? 0 : SB;
+};
+
+template <int PL, int SA, int SB, int LA, int LB, typename TM>
+__device__ __forceinline__ double diag_elem(const Fields<TM> &F, const LatticeDev &L, const NodeCtx &c)
+{
+    using D = Diag<PL, SA, SB, LA, LB>;
+    return element<D::DX, D::DY, D::DZ, D::SX, D::SY, D::SZ, true>(F, L, c);
+}
+
+// Sum over the four bilinear corners of one interpolated quadrature point.
+template <int PL, int SA, int SB, int LL, typename TM>
+__device__ __forceinline__ double diag_point(const Fields<TM> &F, const LatticeDev &L, const NodeCtx &c,
+                                             const double *alpha)
+{
+    double acc = alpha[0] * diag_elem<PL, SA, SB, LL, LL>(F, L, c);
+    acc += alpha[1] * diag_elem<PL, SA, SB, LL, LL + 1>(F, L, c);
+    acc += alpha[2] * diag_elem<PL, SA, SB, LL + 1, LL>(F, L, c);
+    acc += alpha[3] * diag_elem<PL, SA, SB, LL + 1, LL + 1>(F, L, c);
+    return acc;
+}
+
+template <int PL, int SA, int SB, int LL, typename TM>
+__device__ __forceinline__ void diag_pair(const Fields<TM> &F, const LatticeDev &L, const NodeCtx &c,
+                                          const double *alpha, double S[3])
+{
+    const double d = diag_point<PL, SA, SB, LL>(F, L, c, alpha) - diag_point<PL, -SA, -SB, LL>(F, L, c, alpha);
+    constexpr int A = (PL == 2) ? 1 : 0;
+    constexpr int B = (PL == 0) ? 1 : 2;
+    const double w = (1.0 / 15.0) * 0.70710678118654752440 * d;
+    S[A] += SA * w;
+    S[B] += SB * w;
+}
+
+// S = sum_q W_q s_q sum_k alpha_qk G_qk [ ... ] over the 18-point rule, with
+// directions taken in (q, -q) pairs so that a uniform fluid gives exactly 0.
+template <int SIG, typename TM>
+__device__ __forceinline__ void shell_sum(const Fields<TM> &F, const LatticeDev &L, const NodeCtx &c,
+                                          const double *alpha, double S[3])
+{
+    constexpr int LL = ell_of(SIG);
+    S[0] = (1.0 / 30.0) * (element<SIG, 0, 0, 1, 0, 0, false>(F, L, c) - element<-SIG, 0, 0, -1, 0, 0, false>(F, L, c));
+    S[1] = (1.0 / 30.0) * (element<0, SIG, 0, 0, 1, 0, false>(F, L, c) - element<0, -SIG, 0, 0, -1, 0, false>(F, L, c));
+    S[2] = (1.0 / 30.0) * (element<0, 0, SIG, 0, 0, 1, false>(F, L, c) - element<0, 0, -SIG, 0, 0, -1, false>(F, L, c));
+    diag_pair<0, 1, 1, LL>(F, L, c, alpha, S);
+    diag_pair<0, 1, -1, LL>(F, L, c, alpha, S);
+    diag_pair<1, 1, 1, LL>(F, L, c, alpha, S);
+    diag_pair<1, 1, -1, LL>(F, L, c, alpha, S);
+    diag_pair<2, 1, 1, LL>(F, L, c, alpha, S);
+    diag_pair<2, 1, -1, LL>(F, L, c, alpha, S);
+}
+
+// Total force C^(1) + n g at a fluid node with local moments (n, u).
+template <int SIG, typename TM>
+__device__ __forceinline__ void node_force(const Fields<TM> &F, const LatticeDev &L, const StepConst &sc,
+                                           const double *__restrict__ chi, int x, int y, int z, double n,
+                                           const double u[3], double Fo[3])
+{
+    double S[3] = {0.0, 0.0, 0.0};
+    if (sc.hs_on) {
+        NodeCtx c;
+        c.x = x;
+        c.y = y;
+        c.zp = z + L.hz;
+        c.u[0] = u[0];
+        c.u[1] = u[1];
+        c.u[2] = u[2];
+        c.ckap = chi[z] * sc.kappa;
+        shell_sum<SIG>(F, L, c, sc.alpha, S);
+    }
+    const double pn = sc.pref * n;
+    Fo[0] = pn * S[0] + n * sc.g[0];
+    Fo[1] = pn * S[1] + n * sc.g[1];
+    Fo[2] = pn * S[2] + n * sc.g[2];
+}
+
+// ------------------------------------------------- collide and stream
+
+template <int SIG, typename TF, typename TM>
+__global__ __launch_bounds__(256) void k_collide(LatticeDev L, StepConst sc, const double *__restrict__ chi,
+                                                 const TF *__restrict__ fin, TF *__restrict__ fout,
+                                                 Fields<TM> fld)
+{
+    const int first = L.zper ? 0 : L.wall_lo * L.plane;
+    const int last = L.zper ? L.N : (L.nz - L.wall_hi) * L.plane;
+    const int id = first + blockIdx.x * 256 + threadIdx.x;
+    if (id >= last) return;
+    const int z = id / L.plane;
+    const int rem = id - z * L.plane;
+    const int y = rem / L.nx;
+    const int x = rem - y * L.nx;
+
+    double f[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) f[i] = (double)fin[(size_t)i * L.pop_stride + id] + wq(i) * sc.n_ref;
+    double n = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        n += f[i];
+        if (CX[i] > 0) jx += f[i];
+        if (CX[i] < 0) jx -= f[i];
+        if (CY[i] > 0) jy += f[i];
+        if (CY[i] < 0) jy -= f[i];
+        if (CZ[i] > 0) jz += f[i];
+        if (CZ[i] < 0) jz -= f[i];
+    }
+    const double inv_n = (n != 0.0) ? 1.0 / n : 0.0;
+    const double u[3] = {jx * inv_n, jy * inv_n, jz * inv_n};
+    double Fv[3];
+    node_force<SIG>(fld, L, sc, chi, x, y, z, n, u, Fv);
+
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double omega = 1.0 / sc.tau;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const double cu = CX[i] * u[0] + CY[i] * u[1] + CZ[i] * u[2];
+        const double cF = CX[i] * Fv[0] + CY[i] * Fv[1] + CZ[i] * Fv[2];
+        const double feq = wq(i) * n * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        const double fp = f[i] - omega * (f[i] - feq) + 3.0 * wq(i) * cF;
+        const TF val = (TF)(fp - wq(i) * sc.n_ref);
+        const int xt = wrapr(x + CX[i], L.nx);
+        const int yt = wrapr(y + CY[i], L.ny);
+        int zt = z + CZ[i];
+        bool bounce = false;
+        if (L.zper) {
+            zt = (zt < 0) ? zt + L.nz : ((zt >= L.nz) ? zt - L.nz : zt);
+        } else {
+            bounce = (zt < L.wall_lo) || (zt >= L.nz - L.wall_hi);
+        }
+        if (bounce)
+            fout[(size_t)OPP[i] * L.pop_stride + id] = val;
+        else
+            fout[(size_t)i * L.pop_stride + xt + L.nx * (yt + L.ny * zt)] = val;
+    }
+}
+
+template <int SIG, typename TF, typename TM>
+__global__ __launch_bounds__(256) void k_force(LatticeDev L, StepConst sc, const double *__restrict__ chi,
+                                               const TF *__restrict__ fin, Fields<TM> fld, double *__restrict__ Fout)
+{
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= L.N) return;
+    const int z = id / L.plane;
+    const int rem = id - z * L.plane;
+    const int y = rem / L.nx;
+    const int x = rem - y * L.nx;
+    double Fv[3] = {0.0, 0.0, 0.0};
+    if (is_fluid_z(L, z)) {
+        double n = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            const double fi = (double)fin[(size_t)i * L.pop_stride + id] + wq(i) * sc.n_ref;
+            n += fi;
+            jx += CX[i] * fi;
+            jy += CY[i] * fi;
+            jz += CZ[i] * fi;
+        }
+        const double inv_n = (n != 0.0) ? 1.0 / n : 0.0;
+        const double u[3] = {jx * inv_n, jy * inv_n, jz * inv_n};
+        node_force<SIG>(fld, L, sc, chi, x, y, z, n, u, Fv);
+    }
+    Fout[id] = Fv[0];
+    Fout[L.N + id] = Fv[1];
+    Fout[2 * (size_t)L.N + id] = Fv[2];
+}
+
+// -------------------------------------------------------------- reductions
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Layer profiles from FP64 sums taken straight from the populations:
+// out[0][z] = mean n over the layer, out[1+a][z] = (sum j_a)/(sum n),
+// out[4][z] = sum n.  One block per layer, fixed summation order.
+template <typename TF>
+__global__ __launch_bounds__(256) void k_profiles(LatticeDev L, double n_ref, const TF *__restrict__ f,
+                                                  double *__restrict__ out)
+{
+    const int z = blockIdx.x;
+    __shared__ double red[4][4];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    if (is_fluid_z(L, z)) {
+        for (int r = threadIdx.x; r < L.plane; r += 256) {
+            const int id = z * L.plane + r;
+            double n = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) {
+                const double fi = (double)f[(size_t)i * L.pop_stride + id];
+                n += fi;
+                jx += CX[i] * fi;
+                jy += CY[i] * fi;
+                jz += CZ[i] * fi;
+            }
+            s[0] += n + n_ref;
+            s[1] += jx;
+            s[2] += jy;
+            s[3] += jz;
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double t = wave_sum(s[k]);
+        if (lane == 0) red[wv][k] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) t[k] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+        out[z] = t[0] / (double)L.plane;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) out[(1 + a) * L.nz + z] = (t[0] != 0.0) ? t[1 + a] / t[0] : 0.0;
+        out[4 * L.nz + z] = t[0];
+    }
+}
+
+template <typename TM>
+__global__ __launch_bounds__(256) void k_unpad(LatticeDev L, const TM *__restrict__ src, double *__restrict__ dst)
+{
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= L.N) return;
+    const int z = id / L.plane;
+    const int rem = id - z * L.plane;
+    dst[id] = (double)src[rem + L.plane * (z + L.hz)];
+}
+
+// Moments for export: n and u = j/n in FP64 from the populations.
+template <typename TF>
+__global__ __launch_bounds__(256) void k_export_moments(LatticeDev L, double n_ref, const TF *__restrict__ f,
+                                                        double *__restrict__ n_out, double *__restrict__ u_out)
+{
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= L.N) return;
+    double n = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    if (is_fluid_z(L, id / L.plane)) {
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            const double fi = (double)f[(size_t)i * L.pop_stride + id];
+            n += fi;
+            jx += CX[i] * fi;
+            jy += CY[i] * fi;
+            jz += CZ[i] * fi;
+        }
+        n += n_ref;
+    }
+    const double inv = (n != 0.0) ? 1.0 / n : 0.0;
+    n_out[id] = n;
+    u_out[id] = jx * inv;
+    u_out[L.N + id] = jy * inv;
+    u_out[2 * (size_t)L.N + id] = jz * inv;
+}
+
+template <typename TF>
+__global__ __launch_bounds__(256) void k_get_pop(LatticeDev L, double n_ref, const TF *__restrict__ f,
+                                                 double *__restrict__ out)
+{
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= L.N) return;
+    const bool fl = is_fluid_z(L, id / L.plane);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i)
+        out[(size_t)i * L.N + id] = fl ? (double)f[(size_t)i * L.pop_stride + id] + wq(i) * n_ref : 0.0;
+}
+
+template <typename TF>
+__global__ __launch_bounds__(256) void k_set_pop(LatticeDev L, double n_ref, const double *__restrict__ in,
+                                                 TF *__restrict__ f)
+{
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= L.N) return;
+    const bool fl = is_fluid_z(L, id / L.plane);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i)
+        f[(size_t)i * L.pop_stride + id] = fl ? (TF)(in[(size_t)i * L.N + id] - wq(i) * n_ref) : (TF)0;
+}
+
+// Plain device-to-device copy (16-byte lanes, grid-stride): the achievable
+// HBM bandwidth reference and the calibration kernel of the traffic counters.
+__global__ __launch_bounds__(256) void k_copy(const float4 *__restrict__ a, float4 *__restrict__ b, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) b[i] = a[i];
+}
+
+inline unsigned blocks_for(int n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+hipError_t launch_copy(hipStream_t s, const void *src, void *dst, size_t bytes)
+{
+    const size_t n = bytes / 16;
+    const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 256 * 64);
+    hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, s, (const float4 *)src, (float4 *)dst, n);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <typename TF>
+hipError_t launch_init(hipStream_t s, const LatticeDev &L, double n_ref, const double *n, const double *u, TF *f)
+{
+    hipLaunchKernelGGL(k_init<TF>, dim3(blocks_for(L.N)), dim3(256), 0, s, L, n_ref, n, u, f);
+    return hipGetLastError();
+}
+
+template <typename TF, typename TM>
+hipError_t launch_moments(hipStream_t s, const LatticeDev &L, double n_ref, const TF *f, Fields<TM> fld)
+{
+    hipLaunchKernelGGL((k_moments<TF, TM>), dim3(blocks_for(L.N)), dim3(256), 0, s, L, n_ref, f, fld);
+    return hipGetLastError();
+}
+
+template <typename TM>
+hipError_t launch_smooth(hipStream_t s, const LatticeDev &L, int sigma, double eta_pref, Fields<TM> fld)
+{
+    const dim3 g(blocks_for(L.N)), b(256);
+    switch (sigma) {
+    case 2: hipLaunchKernelGGL((k_smooth<2, TM>), g, b, 0, s, L, eta_pref, fld); break;
+    case 3: hipLaunchKernelGGL((k_smooth<3, TM>), g, b, 0, s, L, eta_pref, fld); break;
+    case 4: hipLaunchKernelGGL((k_smooth<4, TM>), g, b, 0, s, L, eta_pref, fld); break;
+    case 5: hipLaunchKernelGGL((k_smooth<5, TM>), g, b, 0, s, L, eta_pref, fld); break;
+    case 6: hipLaunchKernelGGL((k_smooth<6, TM>), g, b, 0, s, L, eta_pref, fld); break;
+    case 7: hipLaunchKernelGGL((k_smooth<7, TM>), g, b, 0, s, L, eta_pref, fld); break;
+    case 8: hipLaunchKernelGGL((k_smooth<8, TM>), g, b, 0, s, L, eta_pref, fld); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename TM>
+hipError_t launch_gfield(hipStream_t s, const LatticeDev &L, int g2_model, Fields<TM> fld)
+{
+    hipLaunchKernelGGL(k_gfield<TM>, dim3(blocks_for(L.N)), dim3(256), 0, s, L, g2_model, fld);
+    return hipGetLastError();
+}
+
+template <typename TF, typename TM>
+hipError_t launch_collide(hipStream_t s, const LatticeDev &L, int sigma, const StepConst &c, const double *chi,
+                          const TF *fin, TF *fout, Fields<TM> fld)
+{
+    const int nfl = L.zper ? L.N : (L.nz - L.wall_lo - L.wall_hi) * L.plane;
+    const dim3 g(blocks_for(nfl)), b(256);
+    switch (sigma) {
+    case 2: hipLaunchKernelGGL((k_collide<2, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld); break;
+    case 3: hipLaunchKernelGGL((k_collide<3, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld); break;
+    case 4: hipLaunchKernelGGL((k_collide<4, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld); break;
+    case 5: hipLaunchKernelGGL((k_collide<5, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld); break;
+    case 6: hipLaunchKernelGGL((k_collide<6, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld); break;
+    case 7: hipLaunchKernelGGL((k_collide<7, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld); break;
+    case 8: hipLaunchKernelGGL((k_collide<8, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename TF, typename TM>
+hipError_t launch_force(hipStream_t s, const LatticeDev &L, int sigma, const StepConst &c, const double *chi,
+                        const TF *f, Fields<TM> fld, double *F)
+{
+    const dim3 g(blocks_for(L.N)), b(256);
+    switch (sigma) {
+    case 2: hipLaunchKernelGGL((k_force<2, TF, TM>), g, b, 0, s, L, c, chi, f, fld, F); break;
+    case 3: hipLaunchKernelGGL((k_force<3, TF, TM>), g, b, 0, s, L, c, chi, f, fld, F); break;
+    case 4: hipLaunchKernelGGL((k_force<4, TF, TM>), g, b, 0, s, L, c, chi, f, fld, F); break;
+    case 5: hipLaunchKernelGGL((k_force<5, TF, TM>), g, b, 0, s, L, c, chi, f, fld, F); break;
+    case 6: hipLaunchKernelGGL((k_force<6, TF, TM>), g, b, 0, s, L, c, chi, f, fld, F); break;
+    case 7: hipLaunchKernelGGL((k_force<7, TF, TM>), g, b, 0, s, L, c, chi, f, fld, F); break;
+    case 8: hipLaunchKernelGGL((k_force<8, TF, TM>), g, b, 0, s, L, c, chi, f, fld, F); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename TF>
+hipError_t launch_profiles_pop(hipStream_t s, const LatticeDev &L, double n_ref, const TF *f, double *out)
+{
+    hipLaunchKernelGGL(k_profiles<TF>, dim3(L.nz), dim3(256), 0, s, L, n_ref, f, out);
+    return hipGetLastError();
+}
+
+template <typename TM>
+hipError_t launch_unpad(hipStream_t s, const LatticeDev &L, const TM *src, double *dst)
+{
+    hipLaunchKernelGGL(k_unpad<TM>, dim3(blocks_for(L.N)), dim3(256), 0, s, L, src, dst);
+    return hipGetLastError();
+}
+
+template <typename TF>
+hipError_t launch_export_moments(hipStream_t s, const LatticeDev &L, double n_ref, const TF *f, double *n,
+                                 double *u)
+{
+    hipLaunchKernelGGL(k_export_moments<TF>, dim3(blocks_for(L.N)), dim3(256), 0, s, L, n_ref, f, n, u);
+    return hipGetLastError();
+}
+
+template <typename TF>
+hipError_t launch_get_pop(hipStream_t s, const LatticeDev &L, double n_ref, const TF *f, double *out)
+{
+    hipLaunchKernelGGL(k_get_pop<TF>, dim3(blocks_for(L.N)), dim3(256), 0, s, L, n_ref, f, out);
+    return hipGetLastError();
+}
+
+template <typename TF>
+hipError_t launch_set_pop(hipStream_t s, const LatticeDev &L, double n_ref, const double *in, TF *f)
+{
+    hipLaunchKernelGGL(k_set_pop<TF>, dim3(blocks_for(L.N)), dim3(256), 0, s, L, n_ref, in, f);
+    return hipGetLastError();
+}
+
+#define HSLB_INST_TF(TF)                                                                                  \
+    template hipError_t launch_init<TF>(hipStream_t, const LatticeDev &, double, const double *,         \
+                                        const double *, TF *);                                            \
+    template hipError_t launch_profiles_pop<TF>(hipStream_t, const LatticeDev &, double, const TF *,     \
+                                                double *);                                                \
+    template hipError_t launch_get_pop<TF>(hipStream_t, const LatticeDev &, double, const TF *, double *); \
+    template hipError_t launch_export_moments<TF>(hipStream_t, const LatticeDev &, double, const TF *,    \
+                                                  double *, double *);                                    \
+    template hipError_t launch_set_pop<TF>(hipStream_t, const LatticeDev &, double, const double *, TF *);
+#define HSLB_INST_TM(TM)                                                                              \
+    template hipError_t launch_smooth<TM>(hipStream_t, const LatticeDev &, int, double, Fields<TM>); \
+    template hipError_t launch_gfield<TM>(hipStream_t, const LatticeDev &, int, Fields<TM>);         \
+    template hipError_t launch_unpad<TM>(hipStream_t, const LatticeDev &, const TM *, double *);
+#define HSLB_INST_TFTM(TF, TM)                                                                              \
+    template hipError_t launch_moments<TF, TM>(hipStream_t, const LatticeDev &, double, const TF *,        \
+                                               Fields<TM>);                                                 \
+    template hipError_t launch_collide<TF, TM>(hipStream_t, const LatticeDev &, int, const StepConst &,    \
+                                               const double *, const TF *, TF *, Fields<TM>);               \
+    template hipError_t launch_force<TF, TM>(hipStream_t, const LatticeDev &, int, const StepConst &,      \
+                                             const double *, const TF *, Fields<TM>, double *);
+
+HSLB_INST_TF(float)
+HSLB_INST_TF(double)
+HSLB_INST_TM(float)
+HSLB_INST_TM(double)
+HSLB_INST_TFTM(float, float)
+HSLB_INST_TFTM(double, double)
+
+}  // namespace hslb

@@ -1,0 +1,320 @@
+"""Python binding of libhslb.so: the C ABI of include/hslb.h under the same
+names, plus a small ``Sim`` wrapper that owns one context.  Argument
+marshalling only: every step of the method runs in the library's HIP kernels.
+
+Importing works without a GPU; loading the library needs the built
+``libhslb.so`` (``python -m paper_0712_2247_amd.build``) and fails loudly
+without it -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhslb.so")
+
+HSLB_OK = 0
+HSLB_EINVAL = -1
+HSLB_ENOMEM = -2
+HSLB_EDEVICE = -3
+HSLB_EUNSTABLE = -4
+HSLB_ESTATE = -5
+HSLB_ENOSURR = -6
+
+HSLB_FP64 = 0
+HSLB_FP32 = 1
+HSLB_G2_PAPER = 0
+HSLB_G2_CS = 1
+HSLB_FORCE_EXACT = 0
+HSLB_FORCE_SURROGATE = 1
+HSLB_FORCE_OFF = 2
+
+# Every exported entry point of include/hslb.h.
+EXPORTS = (
+    "hslb_create", "hslb_destroy", "hslb_last_error", "hslb_set_stream", "hslb_init",
+    "hslb_step", "hslb_sync", "hslb_step_count", "hslb_moments", "hslb_profiles",
+    "hslb_force", "hslb_eta_bar", "hslb_get_populations", "hslb_set_populations",
+    "hslb_set_watchdog", "hslb_set_graph", "hslb_set_kernel_timing", "hslb_kernel_times",
+    "hslb_get_timings", "hslb_copy_bandwidth",
+)
+
+
+class hslb_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("wall_lo", ctypes.c_int32), ("wall_hi", ctypes.c_int32),
+        ("sigma", ctypes.c_int32),
+        ("tau", ctypes.c_double),
+        ("accel", ctypes.c_double * 3),
+        ("g2_model", ctypes.c_int32), ("wall_reg", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("force_mode", ctypes.c_int32),
+        ("surr_check_every", ctypes.c_int32),
+        ("surr_tol", ctypes.c_double),
+    ]
+
+
+class HslbError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"hslb error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+_P = ctypes.POINTER
+_dp = _P(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+def load(path: Optional[str] = None):
+    """Load libhslb.so once and declare every signature."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_0712_2247_amd.build` "
+                          "(there is no non-GPU fallback)")
+    lib = ctypes.CDLL(path)
+    sig = {
+        "hslb_create": (ctypes.c_int, [_P(hslb_params), _P(_vp)]),
+        "hslb_destroy": (None, [_vp]),
+        "hslb_last_error": (ctypes.c_char_p, [_vp]),
+        "hslb_set_stream": (ctypes.c_int, [_vp, _vp]),
+        "hslb_init": (ctypes.c_int, [_vp, _dp, _dp]),
+        "hslb_step": (ctypes.c_int, [_vp, ctypes.c_int64]),
+        "hslb_sync": (ctypes.c_int, [_vp]),
+        "hslb_step_count": (ctypes.c_int, [_vp, _P(ctypes.c_int64)]),
+        "hslb_moments": (ctypes.c_int, [_vp, _dp, _dp]),
+        "hslb_profiles": (ctypes.c_int, [_vp, _dp, _dp]),
+        "hslb_force": (ctypes.c_int, [_vp, _dp]),
+        "hslb_eta_bar": (ctypes.c_int, [_vp, _dp]),
+        "hslb_get_populations": (ctypes.c_int, [_vp, _dp]),
+        "hslb_set_populations": (ctypes.c_int, [_vp, _dp]),
+        "hslb_set_watchdog": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_double]),
+        "hslb_set_graph": (ctypes.c_int, [_vp, ctypes.c_int32]),
+        "hslb_set_kernel_timing": (ctypes.c_int, [_vp, ctypes.c_int32]),
+        "hslb_kernel_times": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_void_p, _dp,
+                                             _P(ctypes.c_int64), _P(ctypes.c_int32)]),
+        "hslb_get_timings": (ctypes.c_int, [_vp, _dp, _dp]),
+        "hslb_copy_bandwidth": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, _dp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _d(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def _chk(ctx, rc: int):
+    if rc != HSLB_OK:
+        raise HslbError(rc, load().hslb_last_error(ctx).decode())
+
+
+# ----------------------------------------------------------- C-ABI mirror
+
+
+def hslb_create(params: hslb_params):
+    lib = load()
+    ctx = _vp()
+    rc = lib.hslb_create(ctypes.byref(params), ctypes.byref(ctx))
+    if rc != HSLB_OK:
+        raise HslbError(rc, lib.hslb_last_error(None).decode())
+    return ctx
+
+
+def hslb_destroy(ctx):
+    load().hslb_destroy(ctx)
+
+
+def hslb_last_error(ctx) -> str:
+    return load().hslb_last_error(ctx).decode()
+
+
+def hslb_set_stream(ctx, stream_handle: int):
+    _chk(ctx, load().hslb_set_stream(ctx, _vp(stream_handle)))
+
+
+def hslb_init(ctx, n: np.ndarray, u: Optional[np.ndarray]):
+    _chk(ctx, load().hslb_init(ctx, _d(n), _d(u)))
+
+
+def hslb_step(ctx, nsteps: int):
+    _chk(ctx, load().hslb_step(ctx, int(nsteps)))
+
+
+def hslb_sync(ctx):
+    _chk(ctx, load().hslb_sync(ctx))
+
+
+def hslb_step_count(ctx) -> int:
+    v = ctypes.c_int64()
+    _chk(ctx, load().hslb_step_count(ctx, ctypes.byref(v)))
+    return v.value
+
+
+def hslb_moments(ctx, n: Optional[np.ndarray], u: Optional[np.ndarray]):
+    _chk(ctx, load().hslb_moments(ctx, _d(n), _d(u)))
+
+
+def hslb_profiles(ctx, n_z: Optional[np.ndarray], u_z: Optional[np.ndarray]):
+    _chk(ctx, load().hslb_profiles(ctx, _d(n_z), _d(u_z)))
+
+
+def hslb_force(ctx, F: np.ndarray):
+    _chk(ctx, load().hslb_force(ctx, _d(F)))
+
+
+def hslb_eta_bar(ctx, eb: np.ndarray):
+    _chk(ctx, load().hslb_eta_bar(ctx, _d(eb)))
+
+
+def hslb_get_populations(ctx, f: np.ndarray):
+    _chk(ctx, load().hslb_get_populations(ctx, _d(f)))
+
+
+def hslb_set_populations(ctx, f: np.ndarray):
+    _chk(ctx, load().hslb_set_populations(ctx, _d(f)))
+
+
+def hslb_set_watchdog(ctx, every: int, tol: float):
+    _chk(ctx, load().hslb_set_watchdog(ctx, int(every), float(tol)))
+
+
+def hslb_set_graph(ctx, enable: bool):
+    _chk(ctx, load().hslb_set_graph(ctx, int(bool(enable))))
+
+
+def hslb_set_kernel_timing(ctx, enable: bool):
+    _chk(ctx, load().hslb_set_kernel_timing(ctx, int(bool(enable))))
+
+
+def hslb_kernel_times(ctx, cap: int = 32):
+    names = (ctypes.c_char * 32 * cap)()
+    ms = np.zeros(cap)
+    cnt = np.zeros(cap, dtype=np.int64)
+    count = ctypes.c_int32()
+    _chk(ctx, load().hslb_kernel_times(ctx, cap, ctypes.cast(names, ctypes.c_void_p), _d(ms),
+                                       cnt.ctypes.data_as(_P(ctypes.c_int64)),
+                                       ctypes.byref(count)))
+    out = {}
+    for k in range(min(count.value, cap)):
+        out[bytes(names[k]).split(b"\0", 1)[0].decode()] = (float(ms[k]), int(cnt[k]))
+    return out
+
+
+def hslb_get_timings(ctx):
+    ms = ctypes.c_double()
+    ml = ctypes.c_double()
+    _chk(ctx, load().hslb_get_timings(ctx, ctypes.byref(ms), ctypes.byref(ml)))
+    return ms.value, ml.value
+
+
+def hslb_copy_bandwidth(nbytes: int, iters: int) -> float:
+    v = ctypes.c_double()
+    rc = load().hslb_copy_bandwidth(int(nbytes), int(iters), ctypes.byref(v))
+    if rc != HSLB_OK:
+        raise HslbError(rc, load().hslb_last_error(None).decode())
+    return v.value
+
+
+# ----------------------------------------------------------- convenience
+
+
+def make_params(nx, ny, nz, sigma, tau, accel=(0.0, 0.0, 0.0), wall_lo=0, wall_hi=0,
+                g2_model=HSLB_G2_PAPER, wall_reg=1, precision=HSLB_FP64,
+                force_mode=HSLB_FORCE_EXACT, surr_check_every=50, surr_tol=1e-3) -> hslb_params:
+    p = hslb_params()
+    p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
+    p.wall_lo, p.wall_hi = int(wall_lo), int(wall_hi)
+    p.sigma = int(sigma)
+    p.tau = float(tau)
+    p.accel = (ctypes.c_double * 3)(*[float(a) for a in accel])
+    p.g2_model, p.wall_reg = int(g2_model), int(wall_reg)
+    p.precision, p.force_mode = int(precision), int(force_mode)
+    p.surr_check_every, p.surr_tol = int(surr_check_every), float(surr_tol)
+    return p
+
+
+class Sim:
+    """One lattice on the GPU.  Fields are float64 arrays shaped (nz, ny, nx),
+    vectors (3, nz, ny, nx), populations (19, nz, ny, nx)."""
+
+    def __init__(self, nx, ny, nz, sigma, tau, accel=(0.0, 0.0, 0.0), wall_lo=0, wall_hi=0,
+                 precision="f64", g2_model=HSLB_G2_PAPER, wall_reg=1,
+                 force_mode=HSLB_FORCE_EXACT):
+        prec = {"f64": HSLB_FP64, "f32": HSLB_FP32}[precision] if isinstance(precision, str) \
+            else int(precision)
+        self.params = make_params(nx, ny, nz, sigma, tau, accel, wall_lo, wall_hi, g2_model,
+                                  wall_reg, prec, force_mode)
+        self.shape = (int(nz), int(ny), int(nx))
+        self.N = int(nx) * int(ny) * int(nz)
+        self.ctx = hslb_create(self.params)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            hslb_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        self.close()
+
+    def init(self, n, u=None):
+        n = np.ascontiguousarray(n, dtype=np.float64).reshape(self.N)
+        if u is not None:
+            u = np.ascontiguousarray(u, dtype=np.float64).reshape(3 * self.N)
+        hslb_init(self.ctx, n, u)
+
+    def step(self, nsteps=1):
+        hslb_step(self.ctx, nsteps)
+
+    def sync(self):
+        hslb_sync(self.ctx)
+
+    def moments(self):
+        n = np.zeros(self.N)
+        u = np.zeros(3 * self.N)
+        hslb_moments(self.ctx, n, u)
+        return n.reshape(self.shape), u.reshape((3,) + self.shape)
+
+    def profiles(self):
+        nz = self.shape[0]
+        pn = np.zeros(nz)
+        pu = np.zeros(3 * nz)
+        hslb_profiles(self.ctx, pn, pu)
+        return pn, pu.reshape(3, nz)
+
+    def force(self):
+        F = np.zeros(3 * self.N)
+        hslb_force(self.ctx, F)
+        return F.reshape((3,) + self.shape)
+
+    def eta_bar(self):
+        e = np.zeros(self.N)
+        hslb_eta_bar(self.ctx, e)
+        return e.reshape(self.shape)
+
+    def get_populations(self):
+        f = np.zeros(19 * self.N)
+        hslb_get_populations(self.ctx, f)
+        return f.reshape((19,) + self.shape)
+
+    def set_populations(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(19 * self.N)
+        hslb_set_populations(self.ctx, f)
+
+    def timings(self):
+        return hslb_get_timings(self.ctx)
+
+    @classmethod
+    def from_workload(cls, wl, precision: Optional[str] = None, **kw):
+        return cls(wl.nx, wl.ny, wl.nz, wl.sigma, wl.tau, accel=wl.accel, wall_lo=wl.wall_lo,
+                   wall_hi=wl.wall_hi, precision=precision or wl.precision, **kw)

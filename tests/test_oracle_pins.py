@@ -423,3 +423,22 @@ def test_init_equilibrium_and_determinism():
     o.step(50)
     b = o.get_populations()
     assert np.array_equal(a, b)
+
+
+def test_stability_verdicts_sigma8_slit():
+    """The 128-layer slit with sigma 8, tau 0.8 and +-0.5% noise, run as a
+    laterally uniform column: at eta 0.35 the scheme diverges within a few
+    hundred steps of the uniform start; at eta 0.30 it stays finite."""
+    def finite_after(eta, steps):
+        wl = workloads.slit("col", 1, 1, 128, 8, eta, 0.8, 2e-6, steps, "f64", 1002, 0.005)
+        n, u = wl.fields()
+        o = oracle.Oracle(**wl.params())
+        o.init(n, u)
+        for _ in range(steps // 100):
+            o.step(100)
+            if not np.isfinite(o.moments()[0]).all():
+                return False
+        return True
+
+    assert not finite_after(0.35, 1000)
+    assert finite_after(0.30, 1000)
