@@ -20,12 +20,12 @@ HIPFLAGS = [
 ]
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
-    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+def build(verbose: bool = False, jobs: int = 4, out: str = LIB, defines=()) -> str:
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC, *[f"-D{d}" for d in defines]]
     objs = []
     procs = []
     for src in SOURCES:
-        obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
+        obj = out + "." + os.path.splitext(src)[0] + ".o"
         cmd = ["hipcc", *HIPFLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -34,15 +34,15 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     bad = [p.wait() for p in procs]
     if any(bad):
         raise RuntimeError("hipcc failed")
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     for o in objs:
         os.remove(o)
-    return LIB
+    return out
 
 
 if __name__ == "__main__":

@@ -58,6 +58,7 @@ hipError_t launch_smooth(hipStream_t s, const LatticeDev &L, int sigma, double e
                          Fields<TM> fld);
 template <typename TM>
 hipError_t launch_gfield(hipStream_t s, const LatticeDev &L, int g2_model, Fields<TM> fld);
+
 template <typename TF, typename TM>
 hipError_t launch_collide(hipStream_t s, const LatticeDev &L, int sigma, const StepConst &c,
                           const double *chi, const TF *fin, TF *fout, Fields<TM> fld);

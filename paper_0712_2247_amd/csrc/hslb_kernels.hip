@@ -11,13 +11,19 @@
 //
 // Storage: populations SoA [19][pop_stride] in TF (float or double), shifted by
 // the constant w_i n_ref so that FP32 storage keeps the small deviations from a
-// uniform state; every sum, the equilibrium subtraction and the force are FP64
-// in registers.  Moment fields (n, j, eta_bar, G) are TM, padded with hz layers
+// uniform state; every sum, the equilibrium subtraction and the shell sum are
+// FP64 in registers.  Moment fields (n, j, eta_bar, G) are TM, padded with hz layers
 // in z that hold zeros beyond walls or periodic ghost copies.
 #include "hslb_internal.hpp"
 
 #include <algorithm>
 #include <cmath>
+
+// Tuning switch (compile-time): 1 evaluates the shell sum in FP64 whatever the
+// storage precision (measured faster on gfx950 than FP32 with conversions).
+#ifndef HSLB_FORCE_FP64
+#define HSLB_FORCE_FP64 1
+#endif
 
 namespace hslb {
 
@@ -198,36 +204,60 @@ __global__ __launch_bounds__(256) void k_gfield(LatticeDev L, int model, Fields<
 
 // ------------------------------------------------------------ shell force
 
+template <typename TC>
 struct NodeCtx {
     int x, y, zp;
-    double u[3];
-    double ckap;  // chi(z) * kappa
+    TC u[3];
+    TC ckap;  // chi(z) * kappa
 };
 
-// One pair element: the contact value at the midpoint of (r, r+d) times
-// [n(r+d) - chi kappa s.(j(r+d) - n(r+d) u(r))], for s = (SX,SY,SZ) (scaled by
-// 1/sqrt(2) on the face diagonals).
-template <int DX, int DY, int DZ, int SX, int SY, int SZ, bool DIAG, typename TM>
-__device__ __forceinline__ double element(const Fields<TM> &F, const LatticeDev &L, const NodeCtx &c)
+// Difference of the two elements of one mirrored lattice pair, the corner d of
+// direction q and the corner -d of direction -q:
+//   e+ - e- = G+ [n+ - chi kappa s.(j+ - n+ u)] - G- [n- + chi kappa s.(j- - n- u)]
+// with G+- the contact value at the midpoint of (r, r+-d).  The density part is
+// written as ((G+ + G-)(n+ - n-) + (G+ - G-)(n+ + n-))/2, whose differences are
+// exact in floating point for neighbouring values, so that the result keeps
+// full relative precision even in FP32 although the two elements nearly
+// cancel.  `su` is s.u(r) (s scaled by 1/sqrt(2) on the face diagonals).
+template <int DX, int DY, int DZ, int SX, int SY, int SZ, bool DIAG, typename TM, typename TC>
+__device__ __forceinline__ TC pair_element(const Fields<TM> &F, const LatticeDev &L, const NodeCtx<TC> &c,
+                                           TC su)
 {
-    const int xx = wrapc<DX>(c.x, L.nx), yy = wrapc<DY>(c.y, L.ny);
-    const int idx = xx + L.nx * (yy + L.ny * (c.zp + DZ));
-    constexpr int BX = floordiv2(DX), BY = floordiv2(DY), BZ = floordiv2(DZ);
+    const size_t fs = L.fld_stride;
+    const int ip = wrapc<DX>(c.x, L.nx) + L.nx * (wrapc<DY>(c.y, L.ny) + L.ny * (c.zp + DZ));
+    const int im = wrapc<-DX>(c.x, L.nx) + L.nx * (wrapc<-DY>(c.y, L.ny) + L.ny * (c.zp - DZ));
     constexpr int SLOT = (DX & 1) | ((DY & 1) << 1) | ((DZ & 1) << 2);
-    const int bx = wrapc<BX>(c.x, L.nx), by = wrapc<BY>(c.y, L.ny);
-    const int bidx = bx + L.nx * (by + L.ny * (c.zp + BZ));
-    const double G = (double)F.G[(size_t)SLOT * L.fld_stride + bidx];
-    const double ne = (double)F.n[idx];
-    double cur = 0.0;
-    if constexpr (SX != 0) cur += SX * ((double)F.j[idx] - ne * c.u[0]);
-    if constexpr (SY != 0) cur += SY * ((double)F.j[L.fld_stride + idx] - ne * c.u[1]);
-    if constexpr (SZ != 0) cur += SZ * ((double)F.j[2 * (size_t)L.fld_stride + idx] - ne * c.u[2]);
-    if constexpr (DIAG) cur *= 0.70710678118654752440;
-    return G * (ne - c.ckap * cur);
+    constexpr int BXP = floordiv2(DX), BYP = floordiv2(DY), BZP = floordiv2(DZ);
+    constexpr int BXM = floordiv2(-DX), BYM = floordiv2(-DY), BZM = floordiv2(-DZ);
+    const int gp = wrapc<BXP>(c.x, L.nx) + L.nx * (wrapc<BYP>(c.y, L.ny) + L.ny * (c.zp + BZP));
+    const int gm = wrapc<BXM>(c.x, L.nx) + L.nx * (wrapc<BYM>(c.y, L.ny) + L.ny * (c.zp + BZM));
+    const TC Gp = (TC)F.G[SLOT * fs + gp], Gm = (TC)F.G[SLOT * fs + gm];
+    const TC np = (TC)F.n[ip], nm = (TC)F.n[im];
+    TC sjp = TC(0), sjm = TC(0);
+    if constexpr (SX != 0) {
+        sjp += TC(SX) * (TC)F.j[ip];
+        sjm += TC(SX) * (TC)F.j[im];
+    }
+    if constexpr (SY != 0) {
+        sjp += TC(SY) * (TC)F.j[fs + ip];
+        sjm += TC(SY) * (TC)F.j[fs + im];
+    }
+    if constexpr (SZ != 0) {
+        sjp += TC(SZ) * (TC)F.j[2 * fs + ip];
+        sjm += TC(SZ) * (TC)F.j[2 * fs + im];
+    }
+    if constexpr (DIAG) {
+        sjp *= TC(0.70710678118654752440);
+        sjm *= TC(0.70710678118654752440);
+    }
+    const TC cp = sjp - np * su;
+    const TC cm = sjm - nm * su;
+    const TC dens = TC(0.5) * ((Gp + Gm) * (np - nm) + (Gp - Gm) * (np + nm));
+    return dens - c.ckap * (Gp * cp + Gm * cm);
 }
 
-// Offsets of corner (IA, IB) of the face diagonal with signs (SA, SB) in plane
-// PL (0: xy, 1: xz, 2: yz), lengths l + IA and l + IB.
+// Offsets of corner (LA, LB) of the face diagonal with signs (SA, SB) in plane
+// PL (0: xy, 1: xz, 2: yz).
 template <int PL, int SA, int SB, int LA, int LB>
 struct Diag {
     static constexpr int a = SA * LA, b = SB * LB;
@@ -239,47 +269,43 @@ struct Diag {
     static constexpr int SZ = (PL == 0) ? 0 : SB;
 };
 
-template <int PL, int SA, int SB, int LA, int LB, typename TM>
-__device__ __forceinline__ double diag_elem(const Fields<TM> &F, const LatticeDev &L, const NodeCtx &c)
+template <int PL, int SA, int SB, int LA, int LB, typename TM, typename TC>
+__device__ __forceinline__ TC diag_pair_element(const Fields<TM> &F, const LatticeDev &L, const NodeCtx<TC> &c,
+                                                TC su)
 {
     using D = Diag<PL, SA, SB, LA, LB>;
-    return element<D::DX, D::DY, D::DZ, D::SX, D::SY, D::SZ, true>(F, L, c);
+    return pair_element<D::DX, D::DY, D::DZ, D::SX, D::SY, D::SZ, true>(F, L, c, su);
 }
 
-// Sum over the four bilinear corners of one interpolated quadrature point.
-template <int PL, int SA, int SB, int LL, typename TM>
-__device__ __forceinline__ double diag_point(const Fields<TM> &F, const LatticeDev &L, const NodeCtx &c,
-                                             const double *alpha)
+// The interpolated quadrature point q = (SA, SB) in plane PL and its mirror -q:
+// W s_q sum_k alpha_k (e+_k - e-_k), k over the four bilinear corners.
+template <int PL, int SA, int SB, int LL, typename TM, typename TC>
+__device__ __forceinline__ void diag_pair(const Fields<TM> &F, const LatticeDev &L, const NodeCtx<TC> &c,
+                                          const TC *alpha, TC S[3])
 {
-    double acc = alpha[0] * diag_elem<PL, SA, SB, LL, LL>(F, L, c);
-    acc += alpha[1] * diag_elem<PL, SA, SB, LL, LL + 1>(F, L, c);
-    acc += alpha[2] * diag_elem<PL, SA, SB, LL + 1, LL>(F, L, c);
-    acc += alpha[3] * diag_elem<PL, SA, SB, LL + 1, LL + 1>(F, L, c);
-    return acc;
-}
-
-template <int PL, int SA, int SB, int LL, typename TM>
-__device__ __forceinline__ void diag_pair(const Fields<TM> &F, const LatticeDev &L, const NodeCtx &c,
-                                          const double *alpha, double S[3])
-{
-    const double d = diag_point<PL, SA, SB, LL>(F, L, c, alpha) - diag_point<PL, -SA, -SB, LL>(F, L, c, alpha);
     constexpr int A = (PL == 2) ? 1 : 0;
     constexpr int B = (PL == 0) ? 1 : 2;
-    const double w = (1.0 / 15.0) * 0.70710678118654752440 * d;
-    S[A] += SA * w;
-    S[B] += SB * w;
+    const TC su = TC(0.70710678118654752440) * (TC(SA) * c.u[A] + TC(SB) * c.u[B]);
+    TC d = alpha[0] * diag_pair_element<PL, SA, SB, LL, LL>(F, L, c, su);
+    d += alpha[1] * diag_pair_element<PL, SA, SB, LL, LL + 1>(F, L, c, su);
+    d += alpha[2] * diag_pair_element<PL, SA, SB, LL + 1, LL>(F, L, c, su);
+    d += alpha[3] * diag_pair_element<PL, SA, SB, LL + 1, LL + 1>(F, L, c, su);
+    const TC w = TC((1.0 / 15.0) * 0.70710678118654752440) * d;
+    S[A] += TC(SA) * w;
+    S[B] += TC(SB) * w;
 }
 
 // S = sum_q W_q s_q sum_k alpha_qk G_qk [ ... ] over the 18-point rule, with
-// directions taken in (q, -q) pairs so that a uniform fluid gives exactly 0.
-template <int SIG, typename TM>
-__device__ __forceinline__ void shell_sum(const Fields<TM> &F, const LatticeDev &L, const NodeCtx &c,
-                                          const double *alpha, double S[3])
+// directions taken in (q, -q) pairs (a uniform fluid at rest gives exactly 0).
+template <int SIG, typename TM, typename TC>
+__device__ __forceinline__ void shell_sum(const Fields<TM> &F, const LatticeDev &L, const NodeCtx<TC> &c,
+                                          const TC *alpha, TC S[3])
 {
     constexpr int LL = ell_of(SIG);
-    S[0] = (1.0 / 30.0) * (element<SIG, 0, 0, 1, 0, 0, false>(F, L, c) - element<-SIG, 0, 0, -1, 0, 0, false>(F, L, c));
-    S[1] = (1.0 / 30.0) * (element<0, SIG, 0, 0, 1, 0, false>(F, L, c) - element<0, -SIG, 0, 0, -1, 0, false>(F, L, c));
-    S[2] = (1.0 / 30.0) * (element<0, 0, SIG, 0, 0, 1, false>(F, L, c) - element<0, 0, -SIG, 0, 0, -1, false>(F, L, c));
+    const TC w30 = TC(1.0 / 30.0);
+    S[0] = w30 * pair_element<SIG, 0, 0, 1, 0, 0, false>(F, L, c, c.u[0]);
+    S[1] = w30 * pair_element<0, SIG, 0, 0, 1, 0, false>(F, L, c, c.u[1]);
+    S[2] = w30 * pair_element<0, 0, SIG, 0, 0, 1, false>(F, L, c, c.u[2]);
     diag_pair<0, 1, 1, LL>(F, L, c, alpha, S);
     diag_pair<0, 1, -1, LL>(F, L, c, alpha, S);
     diag_pair<1, 1, 1, LL>(F, L, c, alpha, S);
@@ -294,22 +320,28 @@ __device__ __forceinline__ void node_force(const Fields<TM> &F, const LatticeDev
                                            const double *__restrict__ chi, int x, int y, int z, double n,
                                            const double u[3], double Fo[3])
 {
-    double S[3] = {0.0, 0.0, 0.0};
+#if HSLB_FORCE_FP64
+    using TC = double;
+#else
+    using TC = TM;
+#endif
+    TC S[3] = {TC(0), TC(0), TC(0)};
     if (sc.hs_on) {
-        NodeCtx c;
+        NodeCtx<TC> c;
         c.x = x;
         c.y = y;
         c.zp = z + L.hz;
-        c.u[0] = u[0];
-        c.u[1] = u[1];
-        c.u[2] = u[2];
-        c.ckap = chi[z] * sc.kappa;
-        shell_sum<SIG>(F, L, c, sc.alpha, S);
+        c.u[0] = (TC)u[0];
+        c.u[1] = (TC)u[1];
+        c.u[2] = (TC)u[2];
+        c.ckap = (TC)(chi[z] * sc.kappa);
+        const TC alpha[4] = {(TC)sc.alpha[0], (TC)sc.alpha[1], (TC)sc.alpha[2], (TC)sc.alpha[3]};
+        shell_sum<SIG>(F, L, c, alpha, S);
     }
     const double pn = sc.pref * n;
-    Fo[0] = pn * S[0] + n * sc.g[0];
-    Fo[1] = pn * S[1] + n * sc.g[1];
-    Fo[2] = pn * S[2] + n * sc.g[2];
+    Fo[0] = pn * (double)S[0] + n * sc.g[0];
+    Fo[1] = pn * (double)S[1] + n * sc.g[1];
+    Fo[2] = pn * (double)S[2] + n * sc.g[2];
 }
 
 // ------------------------------------------------- collide and stream
