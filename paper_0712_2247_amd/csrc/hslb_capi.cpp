@@ -155,7 +155,8 @@ public:
         const size_t popb = sizeof(TF) * (size_t)NQ * L_.pop_stride;
         if (hipMalloc(&f_[0], popb) != hipSuccess || hipMalloc(&f_[1], popb) != hipSuccess)
             return fail(err, HSLB_ENOMEM, "population buffers (%zu bytes each) do not fit", popb);
-        const size_t nfld = (size_t)(1 + 3 + 1 + NGSLOT) * L_.fld_stride;
+        // n, j, eta_bar, the 7 contact-value slots and sigma/2 + 1 row-sum fields
+        const size_t nfld = (size_t)(1 + 3 + 1 + NGSLOT + sig / 2 + 1) * L_.fld_stride;
         if (hipMalloc(&fld_mem_, sizeof(TM) * nfld) != hipSuccess)
             return fail(err, HSLB_ENOMEM, "moment fields do not fit");
         HIP_TRY(hipMemset(fld_mem_, 0, sizeof(TM) * nfld));
@@ -165,6 +166,7 @@ public:
         fld_.j = fld_mem_ + L_.fld_stride;
         fld_.eb = fld_mem_ + 4 * (size_t)L_.fld_stride;
         fld_.G = fld_mem_ + 5 * (size_t)L_.fld_stride;
+        rs_ = fld_mem_ + (size_t)(5 + NGSLOT) * L_.fld_stride;
 
         std::vector<double> chi(p_.nz, 1.0);
         if (!L_.zper && p_.wall_reg) {
@@ -265,7 +267,7 @@ public:
     // Coarse-grained density and contact values of the current moments.
     int fields_hs()
     {
-        int rc = launch("smooth", [&] { return launch_smooth<TM>(st(), L_, sigma_, sc_.eta_pref, fld_); });
+        int rc = launch("smooth", [&] { return launch_smooth2<TM>(st(), L_, sigma_, sc_.eta_pref, fld_, rs_); });
         if (rc) return rc;
         return launch("gfield", [&] { return launch_gfield<TM>(st(), L_, sc_.g2_model, fld_); });
     }
@@ -454,7 +456,7 @@ public:
         int rc = io(sizeof(double) * (size_t)L_.N, &d);
         if (rc) return rc;
         HIP_TRY(launch_moments<TF, TM>(st(), L_, sc_.n_ref, f_[cur_], fld_));
-        HIP_TRY(launch_smooth<TM>(st(), L_, sigma_, sc_.eta_pref, fld_));
+        HIP_TRY(launch_smooth2<TM>(st(), L_, sigma_, sc_.eta_pref, fld_, rs_));
         HIP_TRY(launch_unpad<TM>(st(), L_, fld_.eb, d));
         HIP_TRY(hipMemcpyAsync(eb, d, sizeof(double) * L_.N, hipMemcpyDeviceToHost, st()));
         HIP_TRY(hipStreamSynchronize(st()));
@@ -502,6 +504,7 @@ private:
     TF *f_[2] = {nullptr, nullptr};
     int cur_ = 0;
     TM *fld_mem_ = nullptr;
+    TM *rs_ = nullptr;
     Fields<TM> fld_{};
     double *chi_d_ = nullptr, *prof_d_ = nullptr, *prof_h_ = nullptr;
     double *io_d_ = nullptr;

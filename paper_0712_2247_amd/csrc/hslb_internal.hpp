@@ -58,6 +58,10 @@ hipError_t launch_smooth(hipStream_t s, const LatticeDev &L, int sigma, double e
                          Fields<TM> fld);
 template <typename TM>
 hipError_t launch_gfield(hipStream_t s, const LatticeDev &L, int g2_model, Fields<TM> fld);
+// Two-pass ball sum; rs holds (sigma/2 + 1) padded fields of row sums.
+template <typename TM>
+hipError_t launch_smooth2(hipStream_t s, const LatticeDev &L, int sigma, double eta_pref, Fields<TM> fld,
+                          TM *rs);
 
 template <typename TF, typename TM>
 hipError_t launch_collide(hipStream_t s, const LatticeDev &L, int sigma, const StepConst &c,

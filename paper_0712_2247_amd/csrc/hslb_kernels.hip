@@ -1,8 +1,9 @@
 // HIP kernels of the hard-sphere lattice Boltzmann step for gfx950.
 //
-// One step (equation (10) of the paper) runs as four kernels on the stream:
+// One step (equation (10) of the paper) runs as five kernels on the stream:
 //   k_moments  populations -> n, j                      (equation (8))
-//   k_smooth   n -> coarse-grained packing fraction     (ball of radius sigma/2)
+//   k_rowsum,  n -> coarse-grained packing fraction      (ball of radius sigma/2,
+//   k_ballsum     as row-segment sums: two passes)
 //   k_gfield   eta_bar -> contact values g2 on the 7 sub-lattices of pair
 //              midpoints (lattice nodes, edge, face centres)
 //   k_collide  shell-sum force C^(1) of equation (12) + n g, BGK collision with
@@ -165,6 +166,69 @@ __global__ __launch_bounds__(256) void k_smooth(LatticeDev L, double eta_pref, F
 #pragma unroll
             for (int ox = -R; ox <= R; ++ox) {
                 if (4 * (ox * ox + oy * oy + oz * oz) <= SIG * SIG) s += (double)row[wrapr(x + ox, L.nx)];
+            }
+        }
+    }
+    store_padded(L, fld.eb, rem, z, (TM)(eta_pref * s));
+}
+
+// The ball sum in two passes.  Pass 1 (k_rowsum): for every node of the
+// padded z range the ball needs, the sums of n over the centred x segments of
+// half-width w = 0..R, rs[w] (at most 2R+1 reads per node).  Pass 2
+// (k_ballsum): eta_bar as the sum over the (oy, oz) rows of the ball of
+// rs[w(oy, oz)], one read per row (49 for sigma = 8 instead of 257).
+__host__ __device__ constexpr int isqrt_floor(int v)
+{
+    int r = 0;
+    while ((r + 1) * (r + 1) <= v) ++r;
+    return r;
+}
+
+template <int SIG, typename TM>
+__global__ __launch_bounds__(256) void k_rowsum(LatticeDev L, Fields<TM> fld, TM *__restrict__ rs)
+{
+    constexpr int R = SIG / 2;
+    const int nrows = L.plane * (L.nz + 2 * R);
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= nrows) return;
+    const int zl = t / L.plane;           // 0 .. nz + 2R - 1
+    const int rem = t - zl * L.plane;
+    const int y = rem / L.nx;
+    const int x = rem - y * L.nx;
+    const int p = rem + L.plane * (zl - R + L.hz);
+    const TM *row = fld.n + (p - x);
+    TM acc = row[x];
+    rs[p] = acc;
+#pragma unroll
+    for (int w = 1; w <= R; ++w) {
+        acc += row[wrapr(x - w, L.nx)] + row[wrapr(x + w, L.nx)];
+        rs[(size_t)w * L.fld_stride + p] = acc;
+    }
+}
+
+template <int SIG, typename TM>
+__global__ __launch_bounds__(256) void k_ballsum(LatticeDev L, double eta_pref, Fields<TM> fld,
+                                                 const TM *__restrict__ rs)
+{
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= L.N) return;
+    const int z = id / L.plane;
+    const int rem = id - z * L.plane;
+    const int y = rem / L.nx;
+    const int x = rem - y * L.nx;
+    constexpr int R = SIG / 2;
+    double s = 0.0;
+#pragma unroll
+    for (int oy = -R; oy <= R; ++oy) {
+        const int yy = wrapr(y + oy, L.ny);
+        const TM *col = rs + x + L.nx * (yy + L.ny * (z + L.hz));
+#pragma unroll
+        for (int oz = -R; oz <= R; ++oz) {
+            constexpr int S2 = SIG * SIG;
+            const int rem2 = S2 - 4 * (oy * oy + oz * oz);
+            if (rem2 >= 0) {
+                const int w = isqrt_floor(rem2 / 4);
+                s += (double)col[(size_t)w * L.fld_stride + L.plane * oz];
             }
         }
     }
@@ -602,6 +666,32 @@ hipError_t launch_smooth(hipStream_t s, const LatticeDev &L, int sigma, double e
 }
 
 template <typename TM>
+hipError_t launch_smooth2(hipStream_t s, const LatticeDev &L, int sigma, double eta_pref, Fields<TM> fld,
+                          TM *rs)
+{
+    const dim3 b(256);
+    const int R = sigma / 2;
+    const dim3 g1(blocks_for(L.plane * (L.nz + 2 * R))), g2(blocks_for(L.N));
+#define HSLB_S2(SG)                                                                                \
+    case SG:                                                                                       \
+        hipLaunchKernelGGL((k_rowsum<SG, TM>), g1, b, 0, s, L, fld, rs);                           \
+        hipLaunchKernelGGL((k_ballsum<SG, TM>), g2, b, 0, s, L, eta_pref, fld, (const TM *)rs);    \
+        break;
+    switch (sigma) {
+        HSLB_S2(2)
+        HSLB_S2(3)
+        HSLB_S2(4)
+        HSLB_S2(5)
+        HSLB_S2(6)
+        HSLB_S2(7)
+        HSLB_S2(8)
+    default: return hipErrorInvalidValue;
+    }
+#undef HSLB_S2
+    return hipGetLastError();
+}
+
+template <typename TM>
 hipError_t launch_gfield(hipStream_t s, const LatticeDev &L, int g2_model, Fields<TM> fld)
 {
     hipLaunchKernelGGL(k_gfield<TM>, dim3(blocks_for(L.N)), dim3(256), 0, s, L, g2_model, fld);
@@ -693,6 +783,7 @@ hipError_t launch_set_pop(hipStream_t s, const LatticeDev &L, double n_ref, cons
 #define HSLB_INST_TM(TM)                                                                              \
     template hipError_t launch_smooth<TM>(hipStream_t, const LatticeDev &, int, double, Fields<TM>); \
     template hipError_t launch_gfield<TM>(hipStream_t, const LatticeDev &, int, Fields<TM>);         \
+    template hipError_t launch_smooth2<TM>(hipStream_t, const LatticeDev &, int, double, Fields<TM>, TM *); \
     template hipError_t launch_unpad<TM>(hipStream_t, const LatticeDev &, const TM *, double *);
 #define HSLB_INST_TFTM(TF, TM)                                                                              \
     template hipError_t launch_moments<TF, TM>(hipStream_t, const LatticeDev &, double, const TF *,        \
