@@ -137,17 +137,36 @@ int hslb_force(hslb_ctx *ctx, double *F);
  * current state. */
 int hslb_eta_bar(hslb_ctx *ctx, double *eta_bar);
 
-/* Populations f[19][N] of the current state (checkpoint), and their
- * replacement (resume).  set_populations zeroes solid nodes and resets the
- * step counter.  In HSLB_FP32 contexts the values pass through FP32 storage. */
+/* Populations f[19][N] of the current state, and their replacement.
+ * set_populations zeroes solid nodes, resets the step counter and rebuilds the
+ * storage reference from the given populations; in HSLB_FP32 contexts the
+ * values pass through FP32 storage (for a bitwise resume use the raw
+ * checkpoint below). */
 int hslb_get_populations(hslb_ctx *ctx, double *f);
 int hslb_set_populations(hslb_ctx *ctx, const double *f);
+
+/* Raw checkpoint of a single lattice: the populations in storage precision,
+ * the per-layer reference table and the step counters, so that a run resumed
+ * from it continues bit for bit.  hslb_checkpoint_size gives the byte count of
+ * the caller-owned buffer; hslb_checkpoint_load needs an initialised context
+ * of the same grid and precision (HSLB_EINVAL otherwise). */
+int hslb_checkpoint_size(hslb_ctx *ctx, int64_t *bytes);
+int hslb_checkpoint_save(hslb_ctx *ctx, void *buf);
+int hslb_checkpoint_load(hslb_ctx *ctx, const void *buf);
 
 /* Watchdog: every `every` steps (0: off) check that the state is finite and
  * that the total mass drifts by at most tol (relative) from its value at init;
  * hslb_step returns HSLB_EUNSTABLE at the first failing check, with the step
  * count at that check available from hslb_step_count. */
 int hslb_set_watchdog(hslb_ctx *ctx, int64_t every, double tol);
+
+/* Storage of the populations: f_i is kept as f_i - w_i nref(z), with nref the
+ * mean density of the layer the population was streamed from, so that FP32
+ * storage resolves the deviations from the layered state rather than the
+ * layered state itself.  Every `every` steps (FP32 default 50, FP64 default
+ * 0 = never) one step moves nref to the current layer means.  The values of
+ * the populations are the same either way up to storage rounding. */
+int hslb_set_shift_period(hslb_ctx *ctx, int64_t every);
 
 /* Replay steps from a captured HIP graph (1, default) or launch kernels one by
  * one (0).  Both give bitwise identical results. */
@@ -164,6 +183,36 @@ int hslb_kernel_times(hslb_ctx *ctx, int32_t cap, char (*names)[32], double *tot
 /* Wall-clock milliseconds per step and fluid-node updates per second / 1e6
  * over the last hslb_step call (measured with HIP events around the call). */
 int hslb_get_timings(hslb_ctx *ctx, double *ms_per_step, double *mlups);
+
+/* ---- Batched ensembles ------------------------------------------------------
+ * Many independent slits (each its own grid, walls, sigma, tau, field, packing)
+ * advanced together: every phase of the step is one persistent launch whose
+ * grid walks a work list spanning all slits, and steps replay K at a time from
+ * one captured HIP graph.  The slits' problems are the single-lattice one of
+ * this header; a batch context accepts hslb_step, hslb_sync, hslb_get_timings,
+ * hslb_set_graph, hslb_set_kernel_timing, hslb_set_stream and hslb_destroy.
+ *
+ * hslb_batch_create: slits[nslits] validated as for hslb_create, all with the
+ *   same precision and no surrogate force.  Errors as hslb_create (the message
+ *   names the failing slit).
+ * hslb_batch_init: initial state of one slit, arrays of that slit's size (see
+ *   hslb_init).  Every slit must be initialised before the first step.
+ * hslb_batch_profiles: layer profiles of one slit (see hslb_profiles).
+ * hslb_batch_finite: flags[nslits] = 1 where the slit's state is finite
+ *   (unstable slits diverge independently of the others).
+ * hslb_batch_set_config: persistent grid of grid_per_cu blocks per compute
+ *   unit; work in slit order (order 0) or grouped by sigma (order 1).
+ * hslb_batch_autotune: times the 12 (grid, order) candidates -- grids of
+ *   1, 2, 4, 8, 16, 32 blocks per CU, slit order then sigma order -- over
+ *   `steps` steps each, keeps the fastest (*choice = its index), writes the
+ *   microseconds per step of up to `cap` candidates; the state is restored. */
+int hslb_batch_create(const hslb_params *slits, int32_t nslits, hslb_ctx **out);
+int hslb_batch_init(hslb_ctx *ctx, int32_t slit, const double *n, const double *u);
+int hslb_batch_profiles(hslb_ctx *ctx, int32_t slit, double *n_z, double *u_z);
+int hslb_batch_finite(hslb_ctx *ctx, int32_t *flags);
+int hslb_batch_set_config(hslb_ctx *ctx, int32_t grid_per_cu, int32_t order);
+int hslb_batch_autotune(hslb_ctx *ctx, int32_t steps, int32_t *choice, double *us_per_step,
+                        int32_t cap);
 
 /* Device-to-device copy of `bytes` bytes, repeated `iters` times on a private
  * stream: *gbps = 2 * bytes * iters / elapsed (read + write).  The reference

@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <memory>
 #include <string>
@@ -58,12 +59,59 @@ public:
     virtual int sync() = 0;
     virtual int timings(double *ms, double *mlups) = 0;
     virtual void set_stream(hipStream_t s) = 0;
+    // batched ensembles only
+    virtual int batch_init(int slit, const double *n, const double *u)
+    {
+        (void)slit, (void)n, (void)u;
+        return fail_state("not a batch context");
+    }
+    virtual int batch_profiles(int slit, double *nz, double *uz)
+    {
+        (void)slit, (void)nz, (void)uz;
+        return fail_state("not a batch context");
+    }
+    virtual int batch_finite(int32_t *flags)
+    {
+        (void)flags;
+        return fail_state("not a batch context");
+    }
+    virtual int batch_autotune(int32_t steps, int32_t *choice, double *us_per_step, int32_t cap)
+    {
+        (void)steps, (void)choice, (void)us_per_step, (void)cap;
+        return fail_state("not a batch context");
+    }
+    virtual int batch_set_config(int32_t grid_per_cu, int32_t order)
+    {
+        (void)grid_per_cu, (void)order;
+        return fail_state("not a batch context");
+    }
+    virtual int checkpoint_bytes(int64_t *bytes)
+    {
+        (void)bytes;
+        return fail_state("checkpoints are per lattice");
+    }
+    virtual int checkpoint_save(void *buf)
+    {
+        (void)buf;
+        return fail_state("checkpoints are per lattice");
+    }
+    virtual int checkpoint_load(const void *buf)
+    {
+        (void)buf;
+        return fail_state("checkpoints are per lattice");
+    }
+    int fail_state(const char *msg)
+    {
+        err = msg;
+        return HSLB_ESTATE;
+    }
     std::string err;
     int64_t steps = 0;
     bool inited = false;
     int64_t watch_every = 0;
     double watch_tol = 0.0;
     bool use_graph = true;
+    int64_t shift_every = 0;  // refresh period of the layer reference densities (0: never)
     KernelTimer kt;
 };
 
@@ -111,6 +159,7 @@ public:
         (void)hipFree(fld_mem_);
         (void)hipFree(chi_d_);
         (void)hipFree(prof_d_);
+        (void)hipFree(nref_d_);
         (void)hipHostFree(prof_h_);
         (void)hipFree(io_d_);
         if (own_stream_ && stream_) (void)hipStreamDestroy(stream_);
@@ -134,7 +183,6 @@ public:
 
         sc_.tau = p_.tau;
         for (int a = 0; a < 3; ++a) sc_.g[a] = p_.accel[a];
-        sc_.n_ref = 0.0;
         const double vt2 = 1.0 / 3.0;
         sc_.pref = -vt2 * (double)sig * (double)sig * 4.0 * M_PI;
         sc_.kappa = 2.0 / (std::sqrt(vt2) * std::sqrt(M_PI));
@@ -179,6 +227,11 @@ public:
         HIP_TRY(hipMalloc(&chi_d_, sizeof(double) * p_.nz));
         HIP_TRY(hipMemcpy(chi_d_, chi.data(), sizeof(double) * p_.nz, hipMemcpyHostToDevice));
         HIP_TRY(hipMalloc(&prof_d_, sizeof(double) * 5 * p_.nz));
+        HIP_TRY(hipMalloc(&nref_d_, sizeof(double) * 2 * NQ * p_.nz));
+        HIP_TRY(hipMemset(nref_d_, 0, sizeof(double) * 2 * NQ * p_.nz));
+        sc_.nref_r = nref_d_;
+        sc_.nref_w = nref_d_ + NQ * p_.nz;
+        shift_every = (sizeof(TF) == 4) ? 50 : 0;
         HIP_TRY(hipHostMalloc((void **)&prof_h_, sizeof(double) * 5 * p_.nz, hipHostMallocDefault));
         return HSLB_OK;
     }
@@ -211,6 +264,17 @@ public:
             }
     }
 
+    // Store full FP64 populations [19][N] (device): the reference tables
+    // become their layer means, then the populations are stored relative to them.
+    int store_populations(const double *stage)
+    {
+        HIP_TRY(launch_layer_means<double>(st(), L_, stage, L_.N, nullptr, nref_d_));
+        HIP_TRY(hipMemcpyAsync(nref_d_ + NQ * L_.nz, nref_d_, sizeof(double) * NQ * L_.nz, hipMemcpyDeviceToDevice,
+                               st()));
+        HIP_TRY(launch_set_pop<TF>(st(), L_, nref_d_, stage, f_[cur_]));
+        return HSLB_OK;
+    }
+
     int init(const double *n, const double *u) override
     {
         const int N = L_.N;
@@ -227,21 +291,24 @@ public:
             msum += n[id];
             ++nfl;
         }
-        sc_.n_ref = nfl ? msum / (double)nfl : 0.0;
         mass0_ = msum;
         double *d;
-        int rc = io(sizeof(double) * 4 * (size_t)N, &d);
+        int rc = io(sizeof(double) * (4 + NQ) * (size_t)N, &d);
         if (rc) return rc;
+        double *stage = d + 4 * (size_t)N;
         HIP_TRY(hipMemcpyAsync(d, n, sizeof(double) * N, hipMemcpyHostToDevice, st()));
         if (u)
             HIP_TRY(hipMemcpyAsync(d + N, u, sizeof(double) * 3 * (size_t)N, hipMemcpyHostToDevice, st()));
         else
             HIP_TRY(hipMemsetAsync(d + N, 0, sizeof(double) * 3 * (size_t)N, st()));
         cur_ = 0;
-        HIP_TRY(launch_init<TF>(st(), L_, sc_.n_ref, d, d + N, f_[0]));
+        HIP_TRY(launch_feq(st(), L_, d, d + N, stage));
+        rc = store_populations(stage);
+        if (rc) return rc;
         HIP_TRY(hipStreamSynchronize(st()));
         drop_graphs();
         steps = 0;
+        refreshed_at_ = -1;
         inited = true;
         return HSLB_OK;
     }
@@ -274,7 +341,7 @@ public:
 
     int one_step()
     {
-        int rc = launch("moments", [&] { return launch_moments<TF, TM>(st(), L_, sc_.n_ref, f_[cur_], fld_); });
+        int rc = launch("moments", [&] { return launch_moments<TF, TM>(st(), L_, nref_d_, f_[cur_], fld_); });
         if (rc) return rc;
         if (sc_.hs_on && (rc = fields_hs())) return rc;
         rc = launch("collide", [&] {
@@ -310,11 +377,32 @@ public:
         return HSLB_OK;
     }
 
+    // One step that moves the reference tables to the current layer means of
+    // the populations: the step reads with the old table, writes with the new.
+    int refresh_step()
+    {
+        HIP_TRY(launch_layer_means<TF>(st(), L_, f_[cur_], L_.pop_stride, nref_d_, nref_d_ + NQ * L_.nz));
+        int rc = one_step();
+        if (rc) return rc;
+        HIP_TRY(hipMemcpyAsync(nref_d_, nref_d_ + NQ * L_.nz, sizeof(double) * NQ * L_.nz, hipMemcpyDeviceToDevice,
+                               st()));
+        return HSLB_OK;
+    }
+
     int advance(int64_t n)
     {
         const bool graph = use_graph && !kt.enabled;
         while (n > 0) {
-            if (graph && n >= 2) {
+            if (shift_every > 0 && steps > 0 && steps % shift_every == 0 && refreshed_at_ != steps) {
+                int rc = refresh_step();
+                if (rc) return rc;
+                refreshed_at_ = steps;
+                n -= 1;
+                steps += 1;
+                continue;
+            }
+            const int64_t room = shift_every > 0 ? shift_every - steps % shift_every : n;
+            if (graph && n >= 2 && room >= 2) {
                 if (!gexec_[cur_]) {
                     int rc = capture(cur_);
                     if (rc) return rc;
@@ -350,7 +438,7 @@ public:
 
     int watchdog_check()
     {
-        HIP_TRY(launch_profiles_pop<TF>(st(), L_, sc_.n_ref, f_[cur_], prof_d_));
+        HIP_TRY(launch_profiles_pop<TF>(st(), L_, nref_d_, f_[cur_], prof_d_));
         HIP_TRY(hipMemcpyAsync(prof_h_, prof_d_, sizeof(double) * 5 * L_.nz, hipMemcpyDeviceToHost, st()));
         HIP_TRY(hipStreamSynchronize(st()));
         double m = 0.0;
@@ -416,7 +504,7 @@ public:
         const size_t N = L_.N;
         int rc = io(sizeof(double) * 4 * N, &d);
         if (rc) return rc;
-        HIP_TRY(launch_export_moments<TF>(st(), L_, sc_.n_ref, f_[cur_], d, d + N));
+        HIP_TRY(launch_export_moments<TF>(st(), L_, nref_d_, f_[cur_], d, d + N));
         if (n) HIP_TRY(hipMemcpyAsync(n, d, sizeof(double) * N, hipMemcpyDeviceToHost, st()));
         if (u) HIP_TRY(hipMemcpyAsync(u, d + N, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, st()));
         HIP_TRY(hipStreamSynchronize(st()));
@@ -426,7 +514,7 @@ public:
     int profiles(double *nz, double *uz) override
     {
         if (!inited) return fail(err, HSLB_ESTATE, "profiles before init");
-        HIP_TRY(launch_profiles_pop<TF>(st(), L_, sc_.n_ref, f_[cur_], prof_d_));
+        HIP_TRY(launch_profiles_pop<TF>(st(), L_, nref_d_, f_[cur_], prof_d_));
         HIP_TRY(hipMemcpyAsync(prof_h_, prof_d_, sizeof(double) * 5 * L_.nz, hipMemcpyDeviceToHost, st()));
         HIP_TRY(hipStreamSynchronize(st()));
         if (nz) std::memcpy(nz, prof_h_, sizeof(double) * L_.nz);
@@ -441,7 +529,7 @@ public:
         const size_t N = L_.N;
         int rc = io(sizeof(double) * 3 * N, &d);
         if (rc) return rc;
-        HIP_TRY(launch_moments<TF, TM>(st(), L_, sc_.n_ref, f_[cur_], fld_));
+        HIP_TRY(launch_moments<TF, TM>(st(), L_, nref_d_, f_[cur_], fld_));
         if (sc_.hs_on && (rc = fields_hs())) return rc;
         HIP_TRY(launch_force<TF, TM>(st(), L_, sigma_, sc_, chi_d_, f_[cur_], fld_, d));
         HIP_TRY(hipMemcpyAsync(F, d, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, st()));
@@ -455,7 +543,7 @@ public:
         double *d;
         int rc = io(sizeof(double) * (size_t)L_.N, &d);
         if (rc) return rc;
-        HIP_TRY(launch_moments<TF, TM>(st(), L_, sc_.n_ref, f_[cur_], fld_));
+        HIP_TRY(launch_moments<TF, TM>(st(), L_, nref_d_, f_[cur_], fld_));
         HIP_TRY(launch_smooth2<TM>(st(), L_, sigma_, sc_.eta_pref, fld_, rs_));
         HIP_TRY(launch_unpad<TM>(st(), L_, fld_.eb, d));
         HIP_TRY(hipMemcpyAsync(eb, d, sizeof(double) * L_.N, hipMemcpyDeviceToHost, st()));
@@ -470,7 +558,7 @@ public:
         const size_t tot = (size_t)NQ * L_.N;
         int rc = io(sizeof(double) * tot, &d);
         if (rc) return rc;
-        HIP_TRY(launch_get_pop<TF>(st(), L_, sc_.n_ref, f_[cur_], d));
+        HIP_TRY(launch_get_pop<TF>(st(), L_, nref_d_, f_[cur_], d));
         HIP_TRY(hipMemcpyAsync(f, d, sizeof(double) * tot, hipMemcpyDeviceToHost, st()));
         HIP_TRY(hipStreamSynchronize(st()));
         return HSLB_OK;
@@ -487,9 +575,63 @@ public:
         int rc = io(sizeof(double) * tot, &d);
         if (rc) return rc;
         HIP_TRY(hipMemcpyAsync(d, f, sizeof(double) * tot, hipMemcpyHostToDevice, st()));
-        HIP_TRY(launch_set_pop<TF>(st(), L_, sc_.n_ref, d, f_[cur_]));
+        rc = store_populations(d);
+        if (rc) return rc;
         HIP_TRY(hipStreamSynchronize(st()));
         steps = 0;
+        refreshed_at_ = -1;
+        return HSLB_OK;
+    }
+
+    // Raw checkpoint: header, populations in storage precision [19][N], the
+    // reference table [nz][19].
+    struct CkHeader {
+        int64_t magic, tf_bytes, nx, ny, nz, steps, refreshed_at;
+    };
+    static constexpr int64_t kMagic = 0x48534c4243503031;  // "HSLBCP01"
+
+    int checkpoint_bytes(int64_t *bytes) override
+    {
+        *bytes = (int64_t)sizeof(CkHeader) + (int64_t)sizeof(TF) * NQ * L_.N + (int64_t)sizeof(double) * NQ * L_.nz;
+        return HSLB_OK;
+    }
+
+    int checkpoint_save(void *buf) override
+    {
+        if (!inited) return fail(err, HSLB_ESTATE, "checkpoint before init");
+        CkHeader h{kMagic, (int64_t)sizeof(TF), L_.nx, L_.ny, L_.nz, steps, refreshed_at_};
+        char *p = (char *)buf;
+        std::memcpy(p, &h, sizeof(h));
+        p += sizeof(h);
+        for (int i = 0; i < NQ; ++i) {
+            HIP_TRY(hipMemcpyAsync(p, f_[cur_] + (size_t)i * L_.pop_stride, sizeof(TF) * L_.N, hipMemcpyDeviceToHost,
+                                   st()));
+            p += sizeof(TF) * L_.N;
+        }
+        HIP_TRY(hipMemcpyAsync(p, nref_d_, sizeof(double) * NQ * L_.nz, hipMemcpyDeviceToHost, st()));
+        HIP_TRY(hipStreamSynchronize(st()));
+        return HSLB_OK;
+    }
+
+    int checkpoint_load(const void *buf) override
+    {
+        if (!inited) return fail(err, HSLB_ESTATE, "initialise before loading a checkpoint");
+        CkHeader h;
+        std::memcpy(&h, buf, sizeof(h));
+        if (h.magic != kMagic || h.tf_bytes != (int64_t)sizeof(TF) || h.nx != L_.nx || h.ny != L_.ny ||
+            h.nz != L_.nz)
+            return fail(err, HSLB_EINVAL, "checkpoint does not match this context");
+        const char *p = (const char *)buf + sizeof(h);
+        for (int i = 0; i < NQ; ++i) {
+            HIP_TRY(hipMemcpyAsync(f_[cur_] + (size_t)i * L_.pop_stride, p, sizeof(TF) * L_.N, hipMemcpyHostToDevice,
+                                   st()));
+            p += sizeof(TF) * L_.N;
+        }
+        HIP_TRY(hipMemcpyAsync(nref_d_, p, sizeof(double) * NQ * L_.nz, hipMemcpyHostToDevice, st()));
+        HIP_TRY(hipMemcpyAsync(nref_d_ + NQ * L_.nz, p, sizeof(double) * NQ * L_.nz, hipMemcpyHostToDevice, st()));
+        HIP_TRY(hipStreamSynchronize(st()));
+        steps = h.steps;
+        refreshed_at_ = h.refreshed_at;
         return HSLB_OK;
     }
 
@@ -507,12 +649,536 @@ private:
     TM *rs_ = nullptr;
     Fields<TM> fld_{};
     double *chi_d_ = nullptr, *prof_d_ = nullptr, *prof_h_ = nullptr;
+    double *nref_d_ = nullptr;  // [2][nz][19]: read table, write table
     double *io_d_ = nullptr;
     size_t io_bytes_ = 0;
     double mass0_ = 0.0;
     int64_t last_steps_ = 0;
     hipGraphExec_t gexec_[2] = {nullptr, nullptr};
     bool capturing_ = false;
+    int64_t refreshed_at_ = -1;
+};
+
+// ------------------------------------------------------------------ batch
+
+// Per-slit constants, built on the host exactly as for a single lattice.
+void slit_consts(const hslb_params &p, LatticeDev &L, StepConst &sc, std::vector<double> &chi)
+{
+    const int sig = p.sigma >= 2 ? p.sigma : 2;
+    L.nx = p.nx;
+    L.ny = p.ny;
+    L.nz = p.nz;
+    L.wall_lo = p.wall_lo;
+    L.wall_hi = p.wall_hi;
+    L.zper = (p.wall_lo == 0 && p.wall_hi == 0) ? 1 : 0;
+    L.hz = sig;
+    L.plane = p.nx * p.ny;
+    L.N = L.plane * p.nz;
+    sc.tau = p.tau;
+    for (int a = 0; a < 3; ++a) sc.g[a] = p.accel[a];
+    const double vt2 = 1.0 / 3.0;
+    sc.pref = -vt2 * (double)sig * (double)sig * 4.0 * M_PI;
+    sc.kappa = 2.0 / (std::sqrt(vt2) * std::sqrt(M_PI));
+    sc.eta_pref = M_PI * (double)sig * sig * sig / 6.0 / (double)ball_count(sig);
+    const double A = (double)sig / std::sqrt(2.0);
+    const double th = A - std::floor(A);
+    sc.alpha[0] = (1.0 - th) * (1.0 - th);
+    sc.alpha[1] = (1.0 - th) * th;
+    sc.alpha[2] = th * (1.0 - th);
+    sc.alpha[3] = th * th;
+    sc.g2_model = p.g2_model;
+    sc.hs_on = (p.force_mode == HSLB_FORCE_OFF) ? 0 : 1;
+    chi.assign(p.nz, 1.0);
+    if (!L.zper && p.wall_reg) {
+        const double za = p.wall_lo - 0.5, zb = p.nz - p.wall_hi - 0.5;
+        for (int z = 0; z < p.nz; ++z) chi[z] = 1.0 - std::exp(-std::fmin((double)z - za, zb - (double)z) / (double)sig);
+    }
+}
+
+// A ragged ensemble of independent slits advanced together: five persistent
+// launches per step (moments, row sums, ball sums, contact values, collide)
+// over work lists that span every slit, K steps per captured HIP graph.
+template <typename TF, typename TM>
+class BatchT final : public Engine {
+public:
+    explicit BatchT(std::vector<hslb_params> p) : p_(std::move(p)) {}
+
+    ~BatchT() override
+    {
+        drop_graphs();
+        if (ev0_) (void)hipEventDestroy(ev0_);
+        if (ev1_) (void)hipEventDestroy(ev1_);
+        (void)hipFree(f_[0]);
+        (void)hipFree(f_[1]);
+        (void)hipFree(fld_mem_);
+        (void)hipFree(aux_);
+        (void)hipHostFree(prof_h_);
+        (void)hipFree(io_d_);
+        if (stream_) (void)hipStreamDestroy(stream_);
+    }
+
+    int setup()
+    {
+        const int ns = (int)p_.size();
+        desc_.resize(ns);
+        std::vector<double> chi_all;
+        int64_t pop = 0, fld = 0, prof = 0;
+        int maxR = 0;
+        for (int k = 0; k < ns; ++k) {
+            SlitDesc &d = desc_[k];
+            std::vector<double> chi;
+            slit_consts(p_[k], d.L, d.sc, chi);
+            d.sigma = p_[k].sigma >= 2 ? p_[k].sigma : 2;
+            maxR = std::max(maxR, d.sigma / 2);
+            d.pop_off = (int)pop;
+            d.fld_off = (int)fld;
+            d.chi_off = (int)chi_all.size();
+            chi_all.insert(chi_all.end(), chi.begin(), chi.end());
+            pop += (d.L.N + 63) / 64 * 64;
+            fld += ((int64_t)d.L.plane * (d.L.nz + 2 * d.L.hz) + 63) / 64 * 64;
+            prof_off_.push_back((int)prof);
+            prof += 5 * (int64_t)d.L.nz;
+            nfluid_ += (int64_t)d.L.plane * (d.L.nz - d.L.wall_lo - d.L.wall_hi);
+        }
+        if (pop * NQ >= ((int64_t)1 << 31) || fld * 8 >= ((int64_t)1 << 31))
+            return fail(err, HSLB_EINVAL, "ensemble too large for 32-bit indices");
+        pop_stride_ = (int)pop;
+        fld_stride_ = (int)((fld + 63) / 64 * 64);
+        for (auto &d : desc_) {
+            d.L.pop_stride = pop_stride_;
+            d.L.fld_stride = fld_stride_;
+        }
+        nprof_ = (int)prof;
+        // work lists: all nodes, row-sum rows, fluid nodes; profile items (slit, z)
+        for (int k = 0; k < ns; ++k) {
+            const LatticeDev &L = desc_[k].L;
+            const int R = desc_[k].sigma / 2;
+            const int nfl = L.zper ? L.N : (L.nz - L.wall_lo - L.wall_hi) * L.plane;
+            for (int b = 0; b < (L.N + 255) / 256; ++b) wl_nodes_.push_back({k, b});
+            for (int b = 0; b < (L.plane * (L.nz + 2 * R) + 255) / 256; ++b) wl_rows_.push_back({k, b});
+            for (int b = 0; b < (nfl + 255) / 256; ++b) wl_fluid_.push_back({k, b});
+            for (int z = 0; z < L.nz; ++z) wl_prof_.push_back({k, z});
+        }
+        HIP_TRY(hipStreamCreate(&stream_));
+        HIP_TRY(hipEventCreate(&ev0_));
+        HIP_TRY(hipEventCreate(&ev1_));
+        const size_t popb = sizeof(TF) * (size_t)NQ * pop_stride_;
+        if (hipMalloc(&f_[0], popb) != hipSuccess || hipMalloc(&f_[1], popb) != hipSuccess)
+            return fail(err, HSLB_ENOMEM, "population buffers (%zu bytes each) do not fit", popb);
+        HIP_TRY(hipMemset(f_[0], 0, popb));
+        HIP_TRY(hipMemset(f_[1], 0, popb));
+        const size_t nf = (size_t)(1 + 3 + 1 + NGSLOT + maxR + 1) * fld_stride_;
+        if (hipMalloc(&fld_mem_, sizeof(TM) * nf) != hipSuccess) return fail(err, HSLB_ENOMEM, "moment fields");
+        HIP_TRY(hipMemset(fld_mem_, 0, sizeof(TM) * nf));
+        fld_.n = fld_mem_;
+        fld_.j = fld_mem_ + fld_stride_;
+        fld_.eb = fld_mem_ + 4 * (size_t)fld_stride_;
+        fld_.G = fld_mem_ + 5 * (size_t)fld_stride_;
+        rs_ = fld_mem_ + (size_t)(5 + NGSLOT) * fld_stride_;
+        // descriptors, work lists, chi, profile offsets and profiles in one block
+        const size_t bdesc = sizeof(SlitDesc) * ns;
+        const size_t bw = sizeof(WorkItem) * (wl_nodes_.size() + wl_rows_.size() + wl_fluid_.size() + wl_prof_.size());
+        const size_t bchi = sizeof(double) * chi_all.size();
+        const size_t bpo = sizeof(int) * ns;
+        const size_t bprof = sizeof(double) * nprof_;
+        const size_t bref = sizeof(double) * 2 * NQ * chi_all.size();
+        auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+        HIP_TRY(hipMalloc(&aux_, al(bdesc) + al(bw) + al(bchi) + al(bpo) + al(bprof) + al(bref)));
+        char *a = (char *)aux_;
+        desc_d_ = (SlitDesc *)a;
+        a += al(bdesc);
+        work_d_ = (WorkItem *)a;
+        a += al(bw);
+        chi_d_ = (double *)a;
+        a += al(bchi);
+        prof_off_d_ = (int *)a;
+        a += al(bpo);
+        prof_d_ = (double *)a;
+        a += al(bprof);
+        nref_d_ = (double *)a;
+        ztot_ = (int)chi_all.size();
+        HIP_TRY(hipMemset(nref_d_, 0, bref));
+        for (auto &d : desc_) {
+            d.sc.nref_r = nref_d_ + (size_t)NQ * d.chi_off;
+            d.sc.nref_w = nref_d_ + (size_t)NQ * (ztot_ + d.chi_off);
+        }
+        shift_every = (sizeof(TF) == 4) ? 50 : 0;
+        HIP_TRY(hipMemcpy(desc_d_, desc_.data(), bdesc, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(chi_d_, chi_all.data(), bchi, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(prof_off_d_, prof_off_.data(), bpo, hipMemcpyHostToDevice));
+        HIP_TRY(upload_work(0));
+        HIP_TRY(hipHostMalloc((void **)&prof_h_, bprof, hipHostMallocDefault));
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        HIP_TRY(hipDeviceGetAttribute(&ncu_, hipDeviceAttributeMultiprocessorCount, dev));
+        inited_.assign(ns, 0);
+        return HSLB_OK;
+    }
+
+    // Order 0: slit order; 1: grouped by sigma (largest stencils first).
+    hipError_t upload_work(int order)
+    {
+        auto sorted = [&](std::vector<WorkItem> v) {
+            if (order == 1)
+                std::stable_sort(v.begin(), v.end(), [&](const WorkItem &a, const WorkItem &b) {
+                    return desc_[a.slit].sigma > desc_[b.slit].sigma;
+                });
+            return v;
+        };
+        std::vector<WorkItem> all;
+        for (auto *wl : {&wl_nodes_, &wl_rows_, &wl_fluid_}) {
+            auto v = sorted(*wl);
+            all.insert(all.end(), v.begin(), v.end());
+        }
+        all.insert(all.end(), wl_prof_.begin(), wl_prof_.end());
+        order_ = order;
+        return hipMemcpy(work_d_, all.data(), sizeof(WorkItem) * all.size(), hipMemcpyHostToDevice);
+    }
+
+    void set_stream(hipStream_t s) override { ext_stream_ = s; }
+    hipStream_t st() const { return ext_stream_ ? ext_stream_ : stream_; }
+
+    void drop_graphs()
+    {
+        for (auto &g : gexec_)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+    }
+
+    int io(size_t bytes, double **out)
+    {
+        if (bytes > io_bytes_) {
+            (void)hipFree(io_d_);
+            io_d_ = nullptr;
+            io_bytes_ = 0;
+            if (hipMalloc(&io_d_, bytes) != hipSuccess) return fail(err, HSLB_ENOMEM, "staging buffer");
+            io_bytes_ = bytes;
+        }
+        *out = io_d_;
+        return HSLB_OK;
+    }
+
+    int batch_init(int slit, const double *n, const double *u) override
+    {
+        if (slit < 0 || slit >= (int)p_.size()) return fail(err, HSLB_EINVAL, "slit %d out of range", slit);
+        SlitDesc &d = desc_[slit];
+        const int N = d.L.N;
+        double msum = 0.0;
+        int64_t nfl = 0;
+        for (int id = 0; id < N; ++id) {
+            const int z = id / d.L.plane;
+            if (!(d.L.zper || (z >= d.L.wall_lo && z < d.L.nz - d.L.wall_hi))) continue;
+            if (!std::isfinite(n[id]) || n[id] < 0.0)
+                return fail(err, HSLB_EINVAL, "slit %d: density at node %d is negative or not finite", slit, id);
+            if (u)
+                for (int a = 0; a < 3; ++a)
+                    if (!std::isfinite(u[(size_t)a * N + id]))
+                        return fail(err, HSLB_EINVAL, "slit %d: velocity at node %d is not finite", slit, id);
+            msum += n[id];
+            ++nfl;
+        }
+        double *dd;
+        int rc = io(sizeof(double) * (4 + NQ) * (size_t)N, &dd);
+        if (rc) return rc;
+        double *stage = dd + 4 * (size_t)N;
+        HIP_TRY(hipMemcpyAsync(dd, n, sizeof(double) * N, hipMemcpyHostToDevice, st()));
+        if (u)
+            HIP_TRY(hipMemcpyAsync(dd + N, u, sizeof(double) * 3 * (size_t)N, hipMemcpyHostToDevice, st()));
+        else
+            HIP_TRY(hipMemsetAsync(dd + N, 0, sizeof(double) * 3 * (size_t)N, st()));
+        HIP_TRY(launch_feq(st(), d.L, dd, dd + N, stage));
+        double *R = nref_d_ + (size_t)NQ * d.chi_off, *W = nref_d_ + (size_t)NQ * (ztot_ + d.chi_off);
+        HIP_TRY(launch_layer_means<double>(st(), d.L, stage, N, nullptr, R));
+        HIP_TRY(hipMemcpyAsync(W, R, sizeof(double) * NQ * d.L.nz, hipMemcpyDeviceToDevice, st()));
+        HIP_TRY(launch_set_pop<TF>(st(), d.L, R, stage, f_[cur_] + d.pop_off));
+        HIP_TRY(hipStreamSynchronize(st()));
+        inited_[slit] = 1;
+        steps = 0;
+        refreshed_at_ = -1;
+        inited = std::all_of(inited_.begin(), inited_.end(), [](char c) { return c != 0; });
+        return HSLB_OK;
+    }
+
+    int init(const double *, const double *) override { return fail_state("use hslb_batch_init on a batch"); }
+
+    int phase(const char *name, int ph, const WorkItem *w, int nw)
+    {
+        hipEvent_t a = nullptr, b = nullptr;
+        if (kt.enabled && !capturing_) {
+            HIP_TRY(kt.ev(&a));
+            HIP_TRY(kt.ev(&b));
+            HIP_TRY(hipEventRecord(a, st()));
+        }
+        const unsigned grid = (unsigned)std::max(1, std::min(nw, ncu_ * grid_per_cu_));
+        HIP_TRY(launch_batch_phase<TF, TM>(st(), ph, grid, desc_d_, w, nw, f_[cur_], f_[1 - cur_], fld_, rs_, chi_d_));
+        if (a) {
+            HIP_TRY(hipEventRecord(b, st()));
+            kt.pending.push_back({name, {(int)kt.used - 2, (int)kt.used - 1}});
+        }
+        return HSLB_OK;
+    }
+
+    int one_step()
+    {
+        const WorkItem *wn = work_d_, *wr = wn + wl_nodes_.size(), *wf = wr + wl_rows_.size();
+        int rc;
+        if ((rc = phase("b_moments", 0, wn, (int)wl_nodes_.size()))) return rc;
+        if ((rc = phase("b_rowsum", 1, wr, (int)wl_rows_.size()))) return rc;
+        if ((rc = phase("b_ballsum", 2, wn, (int)wl_nodes_.size()))) return rc;
+        if ((rc = phase("b_gfield", 3, wn, (int)wl_nodes_.size()))) return rc;
+        if ((rc = phase("b_collide", 4, wf, (int)wl_fluid_.size()))) return rc;
+        cur_ = 1 - cur_;
+        return HSLB_OK;
+    }
+
+    int capture(int parity)
+    {
+        const int save = cur_;
+        cur_ = parity;
+        capturing_ = true;
+        HIP_TRY(hipStreamBeginCapture(st(), hipStreamCaptureModeThreadLocal));
+        int rc = HSLB_OK;
+        for (int k = 0; k < graph_steps_ && !rc; ++k) rc = one_step();
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(st(), &g);
+        capturing_ = false;
+        cur_ = save;
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(err, HSLB_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&gexec_[parity], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(err, HSLB_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+        return HSLB_OK;
+    }
+
+    int refresh_step()
+    {
+        const WorkItem *wp = work_d_ + wl_nodes_.size() + wl_rows_.size() + wl_fluid_.size();
+        HIP_TRY(launch_batch_layer_means<TF>(st(), desc_d_, wp, (int)wl_prof_.size(), f_[cur_]));
+        int rc = one_step();
+        if (rc) return rc;
+        HIP_TRY(hipMemcpyAsync(nref_d_, nref_d_ + (size_t)NQ * ztot_, sizeof(double) * NQ * ztot_,
+                               hipMemcpyDeviceToDevice, st()));
+        return HSLB_OK;
+    }
+
+    int advance(int64_t n)
+    {
+        const bool graph = use_graph && !kt.enabled;
+        while (n > 0) {
+            if (shift_every > 0 && steps > 0 && steps % shift_every == 0 && refreshed_at_ != steps) {
+                int rc = refresh_step();
+                if (rc) return rc;
+                refreshed_at_ = steps;
+                n -= 1;
+                steps += 1;
+                continue;
+            }
+            const int64_t room = shift_every > 0 ? shift_every - steps % shift_every : n;
+            if (graph && n >= graph_steps_ && room >= graph_steps_) {
+                if (!gexec_[cur_]) {
+                    int rc = capture(cur_);
+                    if (rc) return rc;
+                }
+                HIP_TRY(hipGraphLaunch(gexec_[cur_], st()));
+                n -= graph_steps_;
+                steps += graph_steps_;
+                if (graph_steps_ % 2) cur_ = 1 - cur_;
+            } else {
+                int rc = one_step();
+                if (rc) return rc;
+                n -= 1;
+                steps += 1;
+            }
+        }
+        return HSLB_OK;
+    }
+
+    int step(int64_t nsteps) override
+    {
+        if (!inited) return fail(err, HSLB_ESTATE, "step before every slit is initialised");
+        if (nsteps < 0) return fail(err, HSLB_EINVAL, "negative step count");
+        HIP_TRY(hipEventRecord(ev0_, st()));
+        int rc = advance(nsteps);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(ev1_, st()));
+        last_steps_ = nsteps;
+        prof_valid_ = false;
+        if (kt.enabled && !kt.pending.empty()) {
+            HIP_TRY(hipStreamSynchronize(st()));
+            for (auto &pr : kt.pending) {
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, kt.pool[pr.second.first], kt.pool[pr.second.second]));
+                auto &t = kt.totals[pr.first];
+                t.first += ms;
+                t.second += 1;
+            }
+            kt.pending.clear();
+            kt.used = 0;
+        }
+        return HSLB_OK;
+    }
+
+    int sync() override
+    {
+        HIP_TRY(hipStreamSynchronize(st()));
+        return HSLB_OK;
+    }
+
+    int timings(double *ms, double *mlups) override
+    {
+        HIP_TRY(hipEventSynchronize(ev1_));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, ev0_, ev1_));
+        const double per = last_steps_ > 0 ? (double)t / (double)last_steps_ : 0.0;
+        if (ms) *ms = per;
+        if (mlups) *mlups = per > 0 ? (double)nfluid_ / (per * 1e-3) / 1e6 : 0.0;
+        return HSLB_OK;
+    }
+
+    int refresh_profiles()
+    {
+        if (prof_valid_) return HSLB_OK;
+        const WorkItem *wp = work_d_ + wl_nodes_.size() + wl_rows_.size() + wl_fluid_.size();
+        HIP_TRY(launch_batch_profiles<TF>(st(), desc_d_, wp, (int)wl_prof_.size(), prof_off_d_, f_[cur_], prof_d_));
+        HIP_TRY(hipMemcpyAsync(prof_h_, prof_d_, sizeof(double) * nprof_, hipMemcpyDeviceToHost, st()));
+        HIP_TRY(hipStreamSynchronize(st()));
+        prof_valid_ = true;
+        return HSLB_OK;
+    }
+
+    int batch_profiles(int slit, double *nz, double *uz) override
+    {
+        if (slit < 0 || slit >= (int)p_.size()) return fail(err, HSLB_EINVAL, "slit %d out of range", slit);
+        if (!inited) return fail(err, HSLB_ESTATE, "profiles before init");
+        int rc = refresh_profiles();
+        if (rc) return rc;
+        const int n = desc_[slit].L.nz;
+        const double *o = prof_h_ + prof_off_[slit];
+        if (nz) std::memcpy(nz, o, sizeof(double) * n);
+        if (uz) std::memcpy(uz, o + n, sizeof(double) * 3 * n);
+        return HSLB_OK;
+    }
+
+    int batch_finite(int32_t *flags) override
+    {
+        if (!inited) return fail(err, HSLB_ESTATE, "finite check before init");
+        int rc = refresh_profiles();
+        if (rc) return rc;
+        for (size_t k = 0; k < p_.size(); ++k) {
+            const double *o = prof_h_ + prof_off_[k];
+            bool ok = true;
+            for (int i = 0; i < 5 * desc_[k].L.nz; ++i) ok = ok && std::isfinite(o[i]);
+            flags[k] = ok ? 1 : 0;
+        }
+        return HSLB_OK;
+    }
+
+    int batch_set_config(int32_t grid_per_cu, int32_t order) override
+    {
+        if (grid_per_cu < 1 || grid_per_cu > 1024 || order < 0 || order > 1)
+            return fail(err, HSLB_EINVAL, "batch configuration");
+        grid_per_cu_ = grid_per_cu;
+        if (order != order_) HIP_TRY(upload_work(order));
+        drop_graphs();
+        return HSLB_OK;
+    }
+
+    // Time every (grid size, work order) candidate over `nsteps` launched steps
+    // and keep the fastest.  The state is saved before and restored after.
+    int batch_autotune(int32_t nsteps, int32_t *choice, double *us, int32_t cap) override
+    {
+        if (!inited) return fail(err, HSLB_ESTATE, "autotune before init");
+        const int grids[] = {1, 2, 4, 8, 16, 32};
+        const size_t popb = sizeof(TF) * (size_t)NQ * pop_stride_;
+        TF *save = nullptr;
+        if (hipMalloc(&save, popb) != hipSuccess) return fail(err, HSLB_ENOMEM, "autotune snapshot");
+        HIP_TRY(hipMemcpyAsync(save, f_[cur_], popb, hipMemcpyDeviceToDevice, st()));
+        std::vector<double> save_ref(2 * (size_t)NQ * ztot_);
+        HIP_TRY(hipMemcpyAsync(save_ref.data(), nref_d_, sizeof(double) * save_ref.size(), hipMemcpyDeviceToHost,
+                               st()));
+        HIP_TRY(hipStreamSynchronize(st()));
+        const int save_cur = cur_;
+        const int64_t save_steps = steps, save_refreshed = refreshed_at_;
+        double best = 1e300;
+        int best_k = 0, k = 0;
+        for (int order = 0; order < 2; ++order)
+            for (int g : grids) {
+                int rc = batch_set_config(g, order);
+                if (!rc) rc = advance(2);  // warm
+                if (!rc && hipEventRecord(ev0_, st()) != hipSuccess) rc = HSLB_EDEVICE;
+                if (!rc) rc = advance(nsteps);
+                float ms = 0.f;
+                if (!rc && (hipEventRecord(ev1_, st()) != hipSuccess || hipEventSynchronize(ev1_) != hipSuccess ||
+                            hipEventElapsedTime(&ms, ev0_, ev1_) != hipSuccess))
+                    rc = fail(err, HSLB_EDEVICE, "autotune timing");
+                if (rc) {
+                    (void)hipFree(save);
+                    return rc;
+                }
+                const double per = 1e3 * ms / nsteps;
+                if (us && k < cap) us[k] = per;
+                if (per < best) {
+                    best = per;
+                    best_k = k;
+                }
+                ++k;
+            }
+        cur_ = save_cur;
+        HIP_TRY(hipMemcpyAsync(f_[cur_], save, popb, hipMemcpyDeviceToDevice, st()));
+        HIP_TRY(hipMemcpyAsync(nref_d_, save_ref.data(), sizeof(double) * save_ref.size(), hipMemcpyHostToDevice,
+                               st()));
+        HIP_TRY(hipStreamSynchronize(st()));
+        (void)hipFree(save);
+        steps = save_steps;
+        refreshed_at_ = save_refreshed;
+        prof_valid_ = false;
+        int rc = batch_set_config(grids[best_k % 6], best_k / 6);
+        if (rc) return rc;
+        if (choice) *choice = best_k;
+        return HSLB_OK;
+    }
+
+    int moments(double *, double *) override { return fail_state("use hslb_batch_profiles on a batch"); }
+    int profiles(double *, double *) override { return fail_state("use hslb_batch_profiles on a batch"); }
+    int force(double *) override { return fail_state("not available on a batch"); }
+    int eta_bar(double *) override { return fail_state("not available on a batch"); }
+    int get_pop(double *) override { return fail_state("not available on a batch"); }
+    int set_pop(const double *) override { return fail_state("not available on a batch"); }
+
+    int graph_steps_ = 10;
+
+private:
+    std::vector<hslb_params> p_;
+    std::vector<SlitDesc> desc_;
+    std::vector<WorkItem> wl_nodes_, wl_rows_, wl_fluid_, wl_prof_;
+    std::vector<int> prof_off_;
+    std::vector<char> inited_;
+    int pop_stride_ = 0, fld_stride_ = 0, nprof_ = 0, ncu_ = 256, grid_per_cu_ = 8, order_ = 0;
+    int64_t nfluid_ = 0;
+    hipStream_t stream_ = nullptr, ext_stream_ = nullptr;
+    hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
+    TF *f_[2] = {nullptr, nullptr};
+    int cur_ = 0;
+    TM *fld_mem_ = nullptr, *rs_ = nullptr;
+    Fields<TM> fld_{};
+    void *aux_ = nullptr;
+    SlitDesc *desc_d_ = nullptr;
+    WorkItem *work_d_ = nullptr;
+    double *chi_d_ = nullptr, *prof_d_ = nullptr, *prof_h_ = nullptr, *io_d_ = nullptr;
+    int *prof_off_d_ = nullptr;
+    size_t io_bytes_ = 0;
+    int64_t last_steps_ = 0;
+    bool prof_valid_ = false, capturing_ = false;
+    hipGraphExec_t gexec_[2] = {nullptr, nullptr};
+    double *nref_d_ = nullptr;  // [2][sum nz][19]: read tables, write tables
+    int ztot_ = 0;
+    int64_t refreshed_at_ = -1;
 };
 
 const char *g_static_err = "invalid context";
@@ -679,6 +1345,35 @@ int hslb_set_watchdog(hslb_ctx *ctx, int64_t every, double tol)
     return HSLB_OK;
 }
 
+int hslb_checkpoint_size(hslb_ctx *ctx, int64_t *bytes)
+{
+    CTX_CHECK(ctx);
+    if (!bytes) return fail(ctx->eng->err, HSLB_EINVAL, "null output");
+    return ctx->eng->checkpoint_bytes(bytes);
+}
+
+int hslb_checkpoint_save(hslb_ctx *ctx, void *buf)
+{
+    CTX_CHECK(ctx);
+    if (!buf) return fail(ctx->eng->err, HSLB_EINVAL, "null buffer");
+    return ctx->eng->checkpoint_save(buf);
+}
+
+int hslb_checkpoint_load(hslb_ctx *ctx, const void *buf)
+{
+    CTX_CHECK(ctx);
+    if (!buf) return fail(ctx->eng->err, HSLB_EINVAL, "null buffer");
+    return ctx->eng->checkpoint_load(buf);
+}
+
+int hslb_set_shift_period(hslb_ctx *ctx, int64_t every)
+{
+    CTX_CHECK(ctx);
+    if (every < 0) return fail(ctx->eng->err, HSLB_EINVAL, "negative period");
+    ctx->eng->shift_every = every;
+    return HSLB_OK;
+}
+
 int hslb_set_graph(hslb_ctx *ctx, int32_t enable)
 {
     CTX_CHECK(ctx);
@@ -718,6 +1413,75 @@ int hslb_get_timings(hslb_ctx *ctx, double *ms_per_step, double *mlups)
 {
     CTX_CHECK(ctx);
     return ctx->eng->timings(ms_per_step, mlups);
+}
+
+int hslb_batch_create(const hslb_params *slits, int32_t nslits, hslb_ctx **out)
+{
+    std::string &err = g_create_err;
+    err.clear();
+    if (!out || !slits || nslits < 1) return fail(err, HSLB_EINVAL, "batch arguments");
+    for (int k = 0; k < nslits; ++k) {
+        int rc = validate(&slits[k], err);
+        if (rc) {
+            err = "slit " + std::to_string(k) + ": " + err;
+            return rc;
+        }
+        if (slits[k].precision != slits[0].precision) return fail(err, HSLB_EINVAL, "mixed precisions in a batch");
+        if (slits[k].force_mode == HSLB_FORCE_SURROGATE) return fail(err, HSLB_EINVAL, "surrogate in a batch");
+    }
+    std::unique_ptr<hslb_ctx> c(new (std::nothrow) hslb_ctx());
+    if (!c) return fail(err, HSLB_ENOMEM, "context allocation");
+    c->p = slits[0];
+    std::vector<hslb_params> v(slits, slits + nslits);
+    int rc;
+    if (slits[0].precision == HSLB_FP32) {
+        auto e = std::make_unique<BatchT<float, float>>(v);
+        rc = e->setup();
+        c->eng = std::move(e);
+    } else {
+        auto e = std::make_unique<BatchT<double, double>>(v);
+        rc = e->setup();
+        c->eng = std::move(e);
+    }
+    if (rc) {
+        err = c->eng->err;
+        return rc;
+    }
+    *out = c.release();
+    return HSLB_OK;
+}
+
+int hslb_batch_init(hslb_ctx *ctx, int32_t slit, const double *n, const double *u)
+{
+    CTX_CHECK(ctx);
+    if (!n) return fail(ctx->eng->err, HSLB_EINVAL, "null density");
+    return ctx->eng->batch_init(slit, n, u);
+}
+
+int hslb_batch_profiles(hslb_ctx *ctx, int32_t slit, double *n_z, double *u_z)
+{
+    CTX_CHECK(ctx);
+    return ctx->eng->batch_profiles(slit, n_z, u_z);
+}
+
+int hslb_batch_finite(hslb_ctx *ctx, int32_t *flags)
+{
+    CTX_CHECK(ctx);
+    if (!flags) return fail(ctx->eng->err, HSLB_EINVAL, "null output");
+    return ctx->eng->batch_finite(flags);
+}
+
+int hslb_batch_set_config(hslb_ctx *ctx, int32_t grid_per_cu, int32_t order)
+{
+    CTX_CHECK(ctx);
+    return ctx->eng->batch_set_config(grid_per_cu, order);
+}
+
+int hslb_batch_autotune(hslb_ctx *ctx, int32_t steps, int32_t *choice, double *us_per_step, int32_t cap)
+{
+    CTX_CHECK(ctx);
+    if (steps < 1) return fail(ctx->eng->err, HSLB_EINVAL, "autotune steps");
+    return ctx->eng->batch_autotune(steps, choice, us_per_step, cap);
 }
 
 int hslb_copy_bandwidth(int64_t bytes, int32_t iters, double *gbps)

@@ -29,7 +29,11 @@ struct LatticeDev {
 struct StepConst {
     double tau;
     double g[3];        // external force per particle
-    double n_ref;       // populations are stored as f_i - w_i n_ref
+    // Populations are stored as f_i - ref[z][i], ref[z] the layer means of the
+    // 19 populations ([nz][19] doubles); the collide kernel reads with nref_r
+    // and writes with nref_w (equal except on a refresh step).
+    const double *nref_r;
+    const double *nref_w;
     double pref;        // -v_T^2 sigma^2 4 pi
     double kappa;       // 2 / (v_T sqrt(pi))
     double eta_pref;    // (pi sigma^3 / 6) / N_ball
@@ -46,12 +50,33 @@ struct Fields {
     TM *G;          // [7][fld_stride]
 };
 
+// One slit of a batched ensemble.  Its populations start at pop_off in arrays
+// of stride L.pop_stride shared by all slits, its padded fields at fld_off in
+// arrays of stride L.fld_stride, its wall-factor table at chi_off.
+struct SlitDesc {
+    LatticeDev L;
+    StepConst sc;
+    int sigma;
+    int pop_off;
+    int fld_off;
+    int chi_off;
+};
+
+// Work item of a persistent batch kernel: (slit, block of 256 indices).
+struct WorkItem {
+    int slit;
+    int block;
+};
+
 // Host-side launchers (hslb_kernels.hip).  All are asynchronous on `s`.
+// Local equilibrium of (n, u) as full FP64 populations [19][N].
+hipError_t launch_feq(hipStream_t s, const LatticeDev &L, const double *n, const double *u, double *out);
+// Layer means [nz][19] of populations with stride `stride`, plus ref (if any).
 template <typename TF>
-hipError_t launch_init(hipStream_t s, const LatticeDev &L, double n_ref, const double *n,
-                       const double *u, TF *f);
+hipError_t launch_layer_means(hipStream_t s, const LatticeDev &L, const TF *f, int stride, const double *ref,
+                              double *out);
 template <typename TF, typename TM>
-hipError_t launch_moments(hipStream_t s, const LatticeDev &L, double n_ref, const TF *f,
+hipError_t launch_moments(hipStream_t s, const LatticeDev &L, const double *nref, const TF *f,
                           Fields<TM> fld);
 template <typename TM>
 hipError_t launch_smooth(hipStream_t s, const LatticeDev &L, int sigma, double eta_pref,
@@ -70,20 +95,36 @@ template <typename TF, typename TM>
 hipError_t launch_force(hipStream_t s, const LatticeDev &L, int sigma, const StepConst &c,
                         const double *chi, const TF *f, Fields<TM> fld, double *F);
 template <typename TF>
-hipError_t launch_profiles_pop(hipStream_t s, const LatticeDev &L, double n_ref, const TF *f,
+hipError_t launch_profiles_pop(hipStream_t s, const LatticeDev &L, const double *nref, const TF *f,
                                double *out);
 template <typename TM>
 hipError_t launch_unpad(hipStream_t s, const LatticeDev &L, const TM *src, double *dst);
 template <typename TF>
-hipError_t launch_export_moments(hipStream_t s, const LatticeDev &L, double n_ref, const TF *f,
+hipError_t launch_export_moments(hipStream_t s, const LatticeDev &L, const double *nref, const TF *f,
                                  double *n, double *u);
 template <typename TF>
-hipError_t launch_get_pop(hipStream_t s, const LatticeDev &L, double n_ref, const TF *f,
+hipError_t launch_get_pop(hipStream_t s, const LatticeDev &L, const double *nref, const TF *f,
                           double *out);
 template <typename TF>
-hipError_t launch_set_pop(hipStream_t s, const LatticeDev &L, double n_ref, const double *in,
+hipError_t launch_set_pop(hipStream_t s, const LatticeDev &L, const double *nref, const double *in,
                           TF *f);
 
 hipError_t launch_copy(hipStream_t s, const void *src, void *dst, size_t bytes);
+
+// Batched ensemble: one persistent launch per phase over a work list.
+// phase 0 moments, 1 row sums, 2 ball sums, 3 contact values, 4 collide.
+template <typename TF, typename TM>
+hipError_t launch_batch_phase(hipStream_t s, int phase, unsigned grid, const SlitDesc *desc,
+                              const WorkItem *work, int nwork, const TF *fin, TF *fout, Fields<TM> fld,
+                              TM *rs, const double *chi);
+// Layer profiles of every slit: items (slit, z); out holds 5 rows per slit
+// layer at prof_off[slit] (n_z, u_z[3], sum n).
+template <typename TF>
+hipError_t launch_batch_profiles(hipStream_t s, const SlitDesc *desc, const WorkItem *items, int nitems,
+                                 const int *prof_off, const TF *f, double *out);
+// Layer means of every slit's stored populations into its write table.
+template <typename TF>
+hipError_t launch_batch_layer_means(hipStream_t s, const SlitDesc *desc, const WorkItem *items, int nitems,
+                                    const TF *f);
 
 }  // namespace hslb

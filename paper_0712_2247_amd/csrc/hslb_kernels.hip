@@ -10,9 +10,10 @@
 //              the second-order equilibrium (11) and first-order source, push
 //              streaming with halfway bounce-back
 //
-// Storage: populations SoA [19][pop_stride] in TF (float or double), shifted by
-// the constant w_i n_ref so that FP32 storage keeps the small deviations from a
-// uniform state; every sum, the equilibrium subtraction and the shell sum are
+// Storage: populations SoA [19][pop_stride] in TF (float or double), kept
+// relative to the layer means of each population (a per-layer reference table,
+// refreshed now and then) so that FP32 storage keeps the small lateral
+// deviations rather than the layered state itself; every sum, the equilibrium subtraction and the shell sum are
 // FP64 in registers.  Moment fields (n, j, eta_bar, G) are TM, padded with hz layers
 // in z that hold zeros beyond walls or periodic ghost copies.
 #include "hslb_internal.hpp"
@@ -91,11 +92,18 @@ __device__ __forceinline__ bool is_fluid_z(const LatticeDev &L, int z)
     return L.zper || (z >= L.wall_lo && z < L.nz - L.wall_hi);
 }
 
+// Populations are stored relative to a per-layer reference: the value kept
+// for direction i at a node of layer z is f_i - ref[z][i], where ref[z] holds
+// the layer means of the 19 populations (refreshed now and then).  ref tables
+// are [nz][19] doubles.
+__device__ __forceinline__ const double *layer_ref(const double *__restrict__ ref, int z) { return ref + 19 * z; }
+
 // --------------------------------------------------------------------- init
 
-template <typename TF>
-__global__ __launch_bounds__(256) void k_init(LatticeDev L, double n_ref, const double *__restrict__ n,
-                                              const double *__restrict__ u, TF *__restrict__ f)
+// Local equilibrium (11) of (n, u) as full FP64 populations [19][N] (0 on
+// solid nodes): the staging form from which initial populations are stored.
+__global__ __launch_bounds__(256) void k_feq(LatticeDev L, const double *__restrict__ n,
+                                             const double *__restrict__ u, double *__restrict__ out)
 {
     const int id = blockIdx.x * 256 + threadIdx.x;
     if (id >= L.N) return;
@@ -107,28 +115,74 @@ __global__ __launch_bounds__(256) void k_init(LatticeDev L, double n_ref, const 
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
         const double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
-        const double feq = wq(i) * nn * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-        f[(size_t)i * L.pop_stride + id] = fl ? (TF)(feq - wq(i) * n_ref) : (TF)0;
+        out[(size_t)i * L.N + id] = fl ? wq(i) * nn * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu) : 0.0;
     }
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Layer means of the 19 populations of layer z (0 on solid layers), summed in
+// FP64 in a fixed order: from full FP64 populations [19][N] (ref == nullptr)
+// or from stored ones plus the current reference.
+template <typename TF>
+__device__ __forceinline__ void d_layer_means(const LatticeDev &L, const TF *__restrict__ f, int stride,
+                                              const double *__restrict__ ref, double *__restrict__ out, int z)
+{
+    __shared__ double red[4][NQ];
+    double s[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) s[i] = 0.0;
+    const bool fl = is_fluid_z(L, z);
+    if (fl) {
+        for (int r = threadIdx.x; r < L.plane; r += 256) {
+            const int id = z * L.plane + r;
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) s[i] += (double)f[(size_t)i * stride + id];
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const double t = wave_sum(s[i]);
+        if (lane == 0) red[wv][i] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < NQ) {
+        const int i = threadIdx.x;
+        const double t = (red[0][i] + red[1][i]) + (red[2][i] + red[3][i]);
+        const double base = ref ? layer_ref(ref, z)[i] : 0.0;
+        out[19 * z + i] = fl ? base + t / (double)L.plane : 0.0;
+    }
+}
+
+template <typename TF>
+__global__ __launch_bounds__(256) void k_layer_means(LatticeDev L, const TF *__restrict__ f, int stride,
+                                                     const double *__restrict__ ref, double *__restrict__ out)
+{
+    d_layer_means(L, f, stride, ref, out, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ moments
 
 template <typename TF, typename TM>
-__global__ __launch_bounds__(256) void k_moments(LatticeDev L, double n_ref, const TF *__restrict__ f,
-                                                 Fields<TM> fld)
+__device__ __forceinline__ void d_moments(const LatticeDev &L, const double *__restrict__ nref,
+                                          const TF *__restrict__ f, const Fields<TM> &fld, int id)
 {
-    const int id = blockIdx.x * 256 + threadIdx.x;
     if (id >= L.N) return;
     const int z = id / L.plane;
     const int rem = id - z * L.plane;
     double n = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
     if (is_fluid_z(L, z)) {
-        double s = 0.0;
+        const double *r = layer_ref(nref, z);
 #pragma unroll
         for (int i = 0; i < NQ; ++i) {
-            const double fi = (double)f[(size_t)i * L.pop_stride + id];
-            s += fi;
+            const double fi = (double)f[(size_t)i * L.pop_stride + id] + r[i];
+            n += fi;
             if (CX[i] > 0) jx += fi;
             if (CX[i] < 0) jx -= fi;
             if (CY[i] > 0) jy += fi;
@@ -136,12 +190,18 @@ __global__ __launch_bounds__(256) void k_moments(LatticeDev L, double n_ref, con
             if (CZ[i] > 0) jz += fi;
             if (CZ[i] < 0) jz -= fi;
         }
-        n = s + n_ref;
     }
     store_padded(L, fld.n, rem, z, (TM)n);
     store_padded(L, fld.j, rem, z, (TM)jx);
     store_padded(L, fld.j + L.fld_stride, rem, z, (TM)jy);
     store_padded(L, fld.j + 2 * L.fld_stride, rem, z, (TM)jz);
+}
+
+template <typename TF, typename TM>
+__global__ __launch_bounds__(256) void k_moments(LatticeDev L, const double *__restrict__ nref,
+                                                 const TF *__restrict__ f, Fields<TM> fld)
+{
+    d_moments(L, nref, f, fld, blockIdx.x * 256 + threadIdx.x);
 }
 
 // ------------------------------------------------- coarse-grained density
@@ -185,11 +245,10 @@ __host__ __device__ constexpr int isqrt_floor(int v)
 }
 
 template <int SIG, typename TM>
-__global__ __launch_bounds__(256) void k_rowsum(LatticeDev L, Fields<TM> fld, TM *__restrict__ rs)
+__device__ __forceinline__ void d_rowsum(const LatticeDev &L, const Fields<TM> &fld, TM *__restrict__ rs, int t)
 {
     constexpr int R = SIG / 2;
     const int nrows = L.plane * (L.nz + 2 * R);
-    const int t = blockIdx.x * 256 + threadIdx.x;
     if (t >= nrows) return;
     const int zl = t / L.plane;           // 0 .. nz + 2R - 1
     const int rem = t - zl * L.plane;
@@ -207,10 +266,15 @@ __global__ __launch_bounds__(256) void k_rowsum(LatticeDev L, Fields<TM> fld, TM
 }
 
 template <int SIG, typename TM>
-__global__ __launch_bounds__(256) void k_ballsum(LatticeDev L, double eta_pref, Fields<TM> fld,
-                                                 const TM *__restrict__ rs)
+__global__ __launch_bounds__(256) void k_rowsum(LatticeDev L, Fields<TM> fld, TM *__restrict__ rs)
 {
-    const int id = blockIdx.x * 256 + threadIdx.x;
+    d_rowsum<SIG>(L, fld, rs, blockIdx.x * 256 + threadIdx.x);
+}
+
+template <int SIG, typename TM>
+__device__ __forceinline__ void d_ballsum(const LatticeDev &L, double eta_pref, const Fields<TM> &fld,
+                                          const TM *__restrict__ rs, int id)
+{
     if (id >= L.N) return;
     const int z = id / L.plane;
     const int rem = id - z * L.plane;
@@ -235,15 +299,21 @@ __global__ __launch_bounds__(256) void k_ballsum(LatticeDev L, double eta_pref, 
     store_padded(L, fld.eb, rem, z, (TM)(eta_pref * s));
 }
 
+template <int SIG, typename TM>
+__global__ __launch_bounds__(256) void k_ballsum(LatticeDev L, double eta_pref, Fields<TM> fld,
+                                                 const TM *__restrict__ rs)
+{
+    d_ballsum<SIG>(L, eta_pref, fld, rs, blockIdx.x * 256 + threadIdx.x);
+}
+
 // ------------------------------------------ contact values at pair midpoints
 
 // G slot b (bits x=1, y=2, z=4) at node r: g2 of the mean eta_bar over the
 // nodes r + {0,1}^b, i.e. at the midpoint r + b/2 of every lattice pair whose
 // offset has odd components exactly on the axes of b.
 template <typename TM>
-__global__ __launch_bounds__(256) void k_gfield(LatticeDev L, int model, Fields<TM> fld)
+__device__ __forceinline__ void d_gfield(const LatticeDev &L, int model, const Fields<TM> &fld, int id)
 {
-    const int id = blockIdx.x * 256 + threadIdx.x;
     if (id >= L.N) return;
     const int z = id / L.plane;
     const int rem = id - z * L.plane;
@@ -264,6 +334,12 @@ __global__ __launch_bounds__(256) void k_gfield(LatticeDev L, int model, Fields<
     store_padded(L, fld.G + 4 * fs, rem, z, (TM)g2_of(0.5 * (e000 + e001), model));
     store_padded(L, fld.G + 5 * fs, rem, z, (TM)g2_of(0.25 * ((e000 + e100) + (e001 + e101)), model));
     store_padded(L, fld.G + 6 * fs, rem, z, (TM)g2_of(0.25 * ((e000 + e010) + (e001 + e011)), model));
+}
+
+template <typename TM>
+__global__ __launch_bounds__(256) void k_gfield(LatticeDev L, int model, Fields<TM> fld)
+{
+    d_gfield(L, model, fld, blockIdx.x * 256 + threadIdx.x);
 }
 
 // ------------------------------------------------------------ shell force
@@ -410,14 +486,15 @@ __device__ __forceinline__ void node_force(const Fields<TM> &F, const LatticeDev
 
 // ------------------------------------------------- collide and stream
 
+// k indexes the fluid nodes (all nodes with a periodic z axis).
 template <int SIG, typename TF, typename TM>
-__global__ __launch_bounds__(256) void k_collide(LatticeDev L, StepConst sc, const double *__restrict__ chi,
-                                                 const TF *__restrict__ fin, TF *__restrict__ fout,
-                                                 Fields<TM> fld)
+__device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &sc, const double *__restrict__ chi,
+                                          const TF *__restrict__ fin, TF *__restrict__ fout, const Fields<TM> &fld,
+                                          int k)
 {
     const int first = L.zper ? 0 : L.wall_lo * L.plane;
     const int last = L.zper ? L.N : (L.nz - L.wall_hi) * L.plane;
-    const int id = first + blockIdx.x * 256 + threadIdx.x;
+    const int id = first + k;
     if (id >= last) return;
     const int z = id / L.plane;
     const int rem = id - z * L.plane;
@@ -425,8 +502,9 @@ __global__ __launch_bounds__(256) void k_collide(LatticeDev L, StepConst sc, con
     const int x = rem - y * L.nx;
 
     double f[NQ];
+    const double *rr = layer_ref(sc.nref_r, z);
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) f[i] = (double)fin[(size_t)i * L.pop_stride + id] + wq(i) * sc.n_ref;
+    for (int i = 0; i < NQ; ++i) f[i] = (double)fin[(size_t)i * L.pop_stride + id] + rr[i];
     double n = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
@@ -451,7 +529,6 @@ __global__ __launch_bounds__(256) void k_collide(LatticeDev L, StepConst sc, con
         const double cF = CX[i] * Fv[0] + CY[i] * Fv[1] + CZ[i] * Fv[2];
         const double feq = wq(i) * n * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
         const double fp = f[i] - omega * (f[i] - feq) + 3.0 * wq(i) * cF;
-        const TF val = (TF)(fp - wq(i) * sc.n_ref);
         const int xt = wrapr(x + CX[i], L.nx);
         const int yt = wrapr(y + CY[i], L.ny);
         int zt = z + CZ[i];
@@ -461,11 +538,20 @@ __global__ __launch_bounds__(256) void k_collide(LatticeDev L, StepConst sc, con
         } else {
             bounce = (zt < L.wall_lo) || (zt >= L.nz - L.wall_hi);
         }
+        // stored relative to the reference of the layer it lands in
         if (bounce)
-            fout[(size_t)OPP[i] * L.pop_stride + id] = val;
+            fout[(size_t)OPP[i] * L.pop_stride + id] = (TF)(fp - layer_ref(sc.nref_w, z)[OPP[i]]);
         else
-            fout[(size_t)i * L.pop_stride + xt + L.nx * (yt + L.ny * zt)] = val;
+            fout[(size_t)i * L.pop_stride + xt + L.nx * (yt + L.ny * zt)] = (TF)(fp - layer_ref(sc.nref_w, zt)[i]);
     }
+}
+
+template <int SIG, typename TF, typename TM>
+__global__ __launch_bounds__(256) void k_collide(LatticeDev L, StepConst sc, const double *__restrict__ chi,
+                                                 const TF *__restrict__ fin, TF *__restrict__ fout,
+                                                 Fields<TM> fld)
+{
+    d_collide<SIG>(L, sc, chi, fin, fout, fld, blockIdx.x * 256 + threadIdx.x);
 }
 
 template <int SIG, typename TF, typename TM>
@@ -481,9 +567,10 @@ __global__ __launch_bounds__(256) void k_force(LatticeDev L, StepConst sc, const
     double Fv[3] = {0.0, 0.0, 0.0};
     if (is_fluid_z(L, z)) {
         double n = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+        const double *rr = layer_ref(sc.nref_r, z);
 #pragma unroll
         for (int i = 0; i < NQ; ++i) {
-            const double fi = (double)fin[(size_t)i * L.pop_stride + id] + wq(i) * sc.n_ref;
+            const double fi = (double)fin[(size_t)i * L.pop_stride + id] + rr[i];
             n += fi;
             jx += CX[i] * fi;
             jy += CY[i] * fi;
@@ -500,36 +587,30 @@ __global__ __launch_bounds__(256) void k_force(LatticeDev L, StepConst sc, const
 
 // -------------------------------------------------------------- reductions
 
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
-}
-
 // Layer profiles from FP64 sums taken straight from the populations:
 // out[0][z] = mean n over the layer, out[1+a][z] = (sum j_a)/(sum n),
 // out[4][z] = sum n.  One block per layer, fixed summation order.
 template <typename TF>
-__global__ __launch_bounds__(256) void k_profiles(LatticeDev L, double n_ref, const TF *__restrict__ f,
-                                                  double *__restrict__ out)
+__global__ __launch_bounds__(256) void k_profiles(LatticeDev L, const double *__restrict__ nref,
+                                                  const TF *__restrict__ f, double *__restrict__ out)
 {
     const int z = blockIdx.x;
     __shared__ double red[4][4];
     double s[4] = {0.0, 0.0, 0.0, 0.0};
     if (is_fluid_z(L, z)) {
+        const double *rr = layer_ref(nref, z);
         for (int r = threadIdx.x; r < L.plane; r += 256) {
             const int id = z * L.plane + r;
             double n = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
             for (int i = 0; i < NQ; ++i) {
-                const double fi = (double)f[(size_t)i * L.pop_stride + id];
+                const double fi = (double)f[(size_t)i * L.pop_stride + id] + rr[i];
                 n += fi;
                 jx += CX[i] * fi;
                 jy += CY[i] * fi;
                 jz += CZ[i] * fi;
             }
-            s[0] += n + n_ref;
+            s[0] += n;
             s[1] += jx;
             s[2] += jy;
             s[3] += jz;
@@ -565,22 +646,23 @@ __global__ __launch_bounds__(256) void k_unpad(LatticeDev L, const TM *__restric
 
 // Moments for export: n and u = j/n in FP64 from the populations.
 template <typename TF>
-__global__ __launch_bounds__(256) void k_export_moments(LatticeDev L, double n_ref, const TF *__restrict__ f,
-                                                        double *__restrict__ n_out, double *__restrict__ u_out)
+__global__ __launch_bounds__(256) void k_export_moments(LatticeDev L, const double *__restrict__ nref,
+                                                        const TF *__restrict__ f, double *__restrict__ n_out,
+                                                        double *__restrict__ u_out)
 {
     const int id = blockIdx.x * 256 + threadIdx.x;
     if (id >= L.N) return;
     double n = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
     if (is_fluid_z(L, id / L.plane)) {
+        const double *rr = layer_ref(nref, id / L.plane);
 #pragma unroll
         for (int i = 0; i < NQ; ++i) {
-            const double fi = (double)f[(size_t)i * L.pop_stride + id];
+            const double fi = (double)f[(size_t)i * L.pop_stride + id] + rr[i];
             n += fi;
             jx += CX[i] * fi;
             jy += CY[i] * fi;
             jz += CZ[i] * fi;
         }
-        n += n_ref;
     }
     const double inv = (n != 0.0) ? 1.0 / n : 0.0;
     n_out[id] = n;
@@ -590,27 +672,149 @@ __global__ __launch_bounds__(256) void k_export_moments(LatticeDev L, double n_r
 }
 
 template <typename TF>
-__global__ __launch_bounds__(256) void k_get_pop(LatticeDev L, double n_ref, const TF *__restrict__ f,
-                                                 double *__restrict__ out)
+__global__ __launch_bounds__(256) void k_get_pop(LatticeDev L, const double *__restrict__ nref,
+                                                 const TF *__restrict__ f, double *__restrict__ out)
 {
     const int id = blockIdx.x * 256 + threadIdx.x;
     if (id >= L.N) return;
-    const bool fl = is_fluid_z(L, id / L.plane);
+    const int z = id / L.plane;
+    const bool fl = is_fluid_z(L, z);
+    const double *r = layer_ref(nref, z);
 #pragma unroll
     for (int i = 0; i < NQ; ++i)
-        out[(size_t)i * L.N + id] = fl ? (double)f[(size_t)i * L.pop_stride + id] + wq(i) * n_ref : 0.0;
+        out[(size_t)i * L.N + id] = fl ? (double)f[(size_t)i * L.pop_stride + id] + r[i] : 0.0;
 }
 
 template <typename TF>
-__global__ __launch_bounds__(256) void k_set_pop(LatticeDev L, double n_ref, const double *__restrict__ in,
-                                                 TF *__restrict__ f)
+__global__ __launch_bounds__(256) void k_set_pop(LatticeDev L, const double *__restrict__ nref,
+                                                 const double *__restrict__ in, TF *__restrict__ f)
 {
     const int id = blockIdx.x * 256 + threadIdx.x;
     if (id >= L.N) return;
-    const bool fl = is_fluid_z(L, id / L.plane);
+    const int z = id / L.plane;
+    const bool fl = is_fluid_z(L, z);
+    const double *r = layer_ref(nref, z);
 #pragma unroll
     for (int i = 0; i < NQ; ++i)
-        f[(size_t)i * L.pop_stride + id] = fl ? (TF)(in[(size_t)i * L.N + id] - wq(i) * n_ref) : (TF)0;
+        f[(size_t)i * L.pop_stride + id] = fl ? (TF)(in[(size_t)i * L.N + id] - r[i]) : (TF)0;
+}
+
+
+// ------------------------------------------------------- batched ensemble
+
+template <typename TM>
+__device__ __forceinline__ Fields<TM> shift_fields(const Fields<TM> &F, int off)
+{
+    Fields<TM> g;
+    g.n = F.n + off;
+    g.j = F.j + off;
+    g.eb = F.eb + off;
+    g.G = F.G + off;
+    return g;
+}
+
+// Persistent kernel of one phase of the step for every slit: the grid walks
+// the work list; each item is one block of 256 indices of one slit, whose
+// descriptor (and sigma, hence the shell stencil) is uniform over the block.
+template <typename TF, typename TM>
+__global__ __launch_bounds__(256) void kb_phase(int phase, const SlitDesc *__restrict__ desc,
+                                                const WorkItem *__restrict__ work, int nwork,
+                                                const TF *__restrict__ fin, TF *__restrict__ fout, Fields<TM> fld,
+                                                TM *__restrict__ rs, const double *__restrict__ chi)
+{
+    for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+        const WorkItem it = work[w];
+        const SlitDesc &d = desc[it.slit];
+        const int idx = it.block * 256 + threadIdx.x;
+        const Fields<TM> F = shift_fields(fld, d.fld_off);
+        TM *r = rs + d.fld_off;
+        const TF *fi = fin + d.pop_off;
+        TF *fo = fout + d.pop_off;
+        const double *ch = chi + d.chi_off;
+        switch (phase) {
+        case 0: d_moments(d.L, d.sc.nref_r, fi, F, idx); break;
+        case 3: d_gfield(d.L, d.sc.g2_model, F, idx); break;
+        default:
+#define HSLB_BPH(SG)                                                                     \
+    case SG:                                                                             \
+        if (phase == 1) d_rowsum<SG>(d.L, F, r, idx);                                    \
+        else if (phase == 2) d_ballsum<SG>(d.L, d.sc.eta_pref, F, r, idx);              \
+        else d_collide<SG>(d.L, d.sc, ch, fi, fo, F, idx);                               \
+        break;
+            switch (d.sigma) {
+                HSLB_BPH(2)
+                HSLB_BPH(3)
+                HSLB_BPH(4)
+                HSLB_BPH(5)
+                HSLB_BPH(6)
+                HSLB_BPH(7)
+                HSLB_BPH(8)
+            default: break;
+            }
+#undef HSLB_BPH
+        }
+    }
+}
+
+template <typename TF>
+__global__ __launch_bounds__(256) void kb_profiles(const SlitDesc *__restrict__ desc, const WorkItem *__restrict__ items,
+                                                   const int *__restrict__ prof_off, const TF *__restrict__ f,
+                                                   double *__restrict__ out)
+{
+    const WorkItem it = items[blockIdx.x];
+    const SlitDesc &d = desc[it.slit];
+    const LatticeDev &L = d.L;
+    const int z = it.block;
+    const TF *fs = f + d.pop_off;
+    __shared__ double red[4][4];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    if (is_fluid_z(L, z)) {
+        const double *rr = layer_ref(d.sc.nref_r, z);
+        for (int r = threadIdx.x; r < L.plane; r += 256) {
+            const int id = z * L.plane + r;
+            double n = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) {
+                const double fi = (double)fs[(size_t)i * L.pop_stride + id] + rr[i];
+                n += fi;
+                jx += CX[i] * fi;
+                jy += CY[i] * fi;
+                jz += CZ[i] * fi;
+            }
+            s[0] += n;
+            s[1] += jx;
+            s[2] += jy;
+            s[3] += jz;
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double t = wave_sum(s[k]);
+        if (lane == 0) red[wv][k] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) t[k] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+        double *o = out + prof_off[it.slit];
+        o[z] = t[0] / (double)L.plane;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) o[(1 + a) * L.nz + z] = (t[0] != 0.0) ? t[1 + a] / t[0] : 0.0;
+        o[4 * L.nz + z] = t[0];
+    }
+}
+
+// Layer means of the stored populations of every slit: items (slit, z); the
+// new reference goes to the write table.
+template <typename TF>
+__global__ __launch_bounds__(256) void kb_layer_means(const SlitDesc *__restrict__ desc,
+                                                      const WorkItem *__restrict__ items, const TF *__restrict__ f)
+{
+    const WorkItem it = items[blockIdx.x];
+    const SlitDesc &d = desc[it.slit];
+    d_layer_means(d.L, f + d.pop_off, d.L.pop_stride, d.sc.nref_r, const_cast<double *>(d.sc.nref_w), it.block);
 }
 
 // Plain device-to-device copy (16-byte lanes, grid-stride): the achievable
@@ -634,17 +838,24 @@ hipError_t launch_copy(hipStream_t s, const void *src, void *dst, size_t bytes)
 
 // ------------------------------------------------------------------ launchers
 
-template <typename TF>
-hipError_t launch_init(hipStream_t s, const LatticeDev &L, double n_ref, const double *n, const double *u, TF *f)
+hipError_t launch_feq(hipStream_t s, const LatticeDev &L, const double *n, const double *u, double *out)
 {
-    hipLaunchKernelGGL(k_init<TF>, dim3(blocks_for(L.N)), dim3(256), 0, s, L, n_ref, n, u, f);
+    hipLaunchKernelGGL(k_feq, dim3(blocks_for(L.N)), dim3(256), 0, s, L, n, u, out);
+    return hipGetLastError();
+}
+
+template <typename TF>
+hipError_t launch_layer_means(hipStream_t s, const LatticeDev &L, const TF *f, int stride, const double *ref,
+                              double *out)
+{
+    hipLaunchKernelGGL(k_layer_means<TF>, dim3(L.nz), dim3(256), 0, s, L, f, stride, ref, out);
     return hipGetLastError();
 }
 
 template <typename TF, typename TM>
-hipError_t launch_moments(hipStream_t s, const LatticeDev &L, double n_ref, const TF *f, Fields<TM> fld)
+hipError_t launch_moments(hipStream_t s, const LatticeDev &L, const double *nref, const TF *f, Fields<TM> fld)
 {
-    hipLaunchKernelGGL((k_moments<TF, TM>), dim3(blocks_for(L.N)), dim3(256), 0, s, L, n_ref, f, fld);
+    hipLaunchKernelGGL((k_moments<TF, TM>), dim3(blocks_for(L.N)), dim3(256), 0, s, L, nref, f, fld);
     return hipGetLastError();
 }
 
@@ -736,9 +947,9 @@ hipError_t launch_force(hipStream_t s, const LatticeDev &L, int sigma, const Ste
 }
 
 template <typename TF>
-hipError_t launch_profiles_pop(hipStream_t s, const LatticeDev &L, double n_ref, const TF *f, double *out)
+hipError_t launch_profiles_pop(hipStream_t s, const LatticeDev &L, const double *nref, const TF *f, double *out)
 {
-    hipLaunchKernelGGL(k_profiles<TF>, dim3(L.nz), dim3(256), 0, s, L, n_ref, f, out);
+    hipLaunchKernelGGL(k_profiles<TF>, dim3(L.nz), dim3(256), 0, s, L, nref, f, out);
     return hipGetLastError();
 }
 
@@ -750,48 +961,85 @@ hipError_t launch_unpad(hipStream_t s, const LatticeDev &L, const TM *src, doubl
 }
 
 template <typename TF>
-hipError_t launch_export_moments(hipStream_t s, const LatticeDev &L, double n_ref, const TF *f, double *n,
+hipError_t launch_export_moments(hipStream_t s, const LatticeDev &L, const double *nref, const TF *f, double *n,
                                  double *u)
 {
-    hipLaunchKernelGGL(k_export_moments<TF>, dim3(blocks_for(L.N)), dim3(256), 0, s, L, n_ref, f, n, u);
+    hipLaunchKernelGGL(k_export_moments<TF>, dim3(blocks_for(L.N)), dim3(256), 0, s, L, nref, f, n, u);
     return hipGetLastError();
 }
 
 template <typename TF>
-hipError_t launch_get_pop(hipStream_t s, const LatticeDev &L, double n_ref, const TF *f, double *out)
+hipError_t launch_get_pop(hipStream_t s, const LatticeDev &L, const double *nref, const TF *f, double *out)
 {
-    hipLaunchKernelGGL(k_get_pop<TF>, dim3(blocks_for(L.N)), dim3(256), 0, s, L, n_ref, f, out);
+    hipLaunchKernelGGL(k_get_pop<TF>, dim3(blocks_for(L.N)), dim3(256), 0, s, L, nref, f, out);
     return hipGetLastError();
 }
 
 template <typename TF>
-hipError_t launch_set_pop(hipStream_t s, const LatticeDev &L, double n_ref, const double *in, TF *f)
+hipError_t launch_set_pop(hipStream_t s, const LatticeDev &L, const double *nref, const double *in, TF *f)
 {
-    hipLaunchKernelGGL(k_set_pop<TF>, dim3(blocks_for(L.N)), dim3(256), 0, s, L, n_ref, in, f);
+    hipLaunchKernelGGL(k_set_pop<TF>, dim3(blocks_for(L.N)), dim3(256), 0, s, L, nref, in, f);
+    return hipGetLastError();
+}
+
+template <typename TF>
+hipError_t launch_batch_layer_means(hipStream_t s, const SlitDesc *desc, const WorkItem *items, int nitems,
+                                    const TF *f)
+{
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_layer_means<TF>, dim3(nitems), dim3(256), 0, s, desc, items, f);
+    return hipGetLastError();
+}
+
+template <typename TF, typename TM>
+hipError_t launch_batch_phase(hipStream_t s, int phase, unsigned grid, const SlitDesc *desc, const WorkItem *work,
+                              int nwork, const TF *fin, TF *fout, Fields<TM> fld, TM *rs, const double *chi)
+{
+    if (nwork <= 0) return hipSuccess;
+    hipLaunchKernelGGL((kb_phase<TF, TM>), dim3(grid), dim3(256), 0, s, phase, desc, work, nwork, fin, fout, fld,
+                       rs, chi);
+    return hipGetLastError();
+}
+
+template <typename TF>
+hipError_t launch_batch_profiles(hipStream_t s, const SlitDesc *desc, const WorkItem *items, int nitems,
+                                 const int *prof_off, const TF *f, double *out)
+{
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_profiles<TF>, dim3(nitems), dim3(256), 0, s, desc, items, prof_off, f, out);
     return hipGetLastError();
 }
 
 #define HSLB_INST_TF(TF)                                                                                  \
-    template hipError_t launch_init<TF>(hipStream_t, const LatticeDev &, double, const double *,         \
-                                        const double *, TF *);                                            \
-    template hipError_t launch_profiles_pop<TF>(hipStream_t, const LatticeDev &, double, const TF *,     \
-                                                double *);                                                \
-    template hipError_t launch_get_pop<TF>(hipStream_t, const LatticeDev &, double, const TF *, double *); \
-    template hipError_t launch_export_moments<TF>(hipStream_t, const LatticeDev &, double, const TF *,    \
-                                                  double *, double *);                                    \
-    template hipError_t launch_set_pop<TF>(hipStream_t, const LatticeDev &, double, const double *, TF *);
+    template hipError_t launch_layer_means<TF>(hipStream_t, const LatticeDev &, const TF *, int,          \
+                                               const double *, double *);                                 \
+    template hipError_t launch_batch_layer_means<TF>(hipStream_t, const SlitDesc *, const WorkItem *, int, \
+                                                     const TF *);                                         \
+    template hipError_t launch_profiles_pop<TF>(hipStream_t, const LatticeDev &, const double *,          \
+                                                const TF *, double *);                                    \
+    template hipError_t launch_get_pop<TF>(hipStream_t, const LatticeDev &, const double *, const TF *,   \
+                                           double *);                                                     \
+    template hipError_t launch_export_moments<TF>(hipStream_t, const LatticeDev &, const double *,        \
+                                                  const TF *, double *, double *);                        \
+    template hipError_t launch_set_pop<TF>(hipStream_t, const LatticeDev &, const double *,               \
+                                           const double *, TF *);                                         \
+    template hipError_t launch_batch_profiles<TF>(hipStream_t, const SlitDesc *, const WorkItem *, int,     \
+                                                  const int *, const TF *, double *);
 #define HSLB_INST_TM(TM)                                                                              \
     template hipError_t launch_smooth<TM>(hipStream_t, const LatticeDev &, int, double, Fields<TM>); \
     template hipError_t launch_gfield<TM>(hipStream_t, const LatticeDev &, int, Fields<TM>);         \
     template hipError_t launch_smooth2<TM>(hipStream_t, const LatticeDev &, int, double, Fields<TM>, TM *); \
     template hipError_t launch_unpad<TM>(hipStream_t, const LatticeDev &, const TM *, double *);
 #define HSLB_INST_TFTM(TF, TM)                                                                              \
-    template hipError_t launch_moments<TF, TM>(hipStream_t, const LatticeDev &, double, const TF *,        \
+    template hipError_t launch_moments<TF, TM>(hipStream_t, const LatticeDev &, const double *, const TF *, \
                                                Fields<TM>);                                                 \
     template hipError_t launch_collide<TF, TM>(hipStream_t, const LatticeDev &, int, const StepConst &,    \
                                                const double *, const TF *, TF *, Fields<TM>);               \
     template hipError_t launch_force<TF, TM>(hipStream_t, const LatticeDev &, int, const StepConst &,      \
-                                             const double *, const TF *, Fields<TM>, double *);
+                                             const double *, const TF *, Fields<TM>, double *);              \
+    template hipError_t launch_batch_phase<TF, TM>(hipStream_t, int, unsigned, const SlitDesc *,            \
+                                                   const WorkItem *, int, const TF *, TF *, Fields<TM>, TM *, \
+                                                   const double *);
 
 HSLB_INST_TF(float)
 HSLB_INST_TF(double)

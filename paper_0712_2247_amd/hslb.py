@@ -38,8 +38,11 @@ EXPORTS = (
     "hslb_create", "hslb_destroy", "hslb_last_error", "hslb_set_stream", "hslb_init",
     "hslb_step", "hslb_sync", "hslb_step_count", "hslb_moments", "hslb_profiles",
     "hslb_force", "hslb_eta_bar", "hslb_get_populations", "hslb_set_populations",
-    "hslb_set_watchdog", "hslb_set_graph", "hslb_set_kernel_timing", "hslb_kernel_times",
+    "hslb_set_watchdog", "hslb_set_shift_period", "hslb_set_graph",
+    "hslb_checkpoint_size", "hslb_checkpoint_save", "hslb_checkpoint_load", "hslb_set_kernel_timing", "hslb_kernel_times",
     "hslb_get_timings", "hslb_copy_bandwidth",
+    "hslb_batch_create", "hslb_batch_init", "hslb_batch_profiles", "hslb_batch_finite",
+    "hslb_batch_set_config", "hslb_batch_autotune",
 )
 
 
@@ -95,12 +98,23 @@ def load(path: Optional[str] = None):
         "hslb_get_populations": (ctypes.c_int, [_vp, _dp]),
         "hslb_set_populations": (ctypes.c_int, [_vp, _dp]),
         "hslb_set_watchdog": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_double]),
+        "hslb_set_shift_period": (ctypes.c_int, [_vp, ctypes.c_int64]),
+        "hslb_checkpoint_size": (ctypes.c_int, [_vp, _P(ctypes.c_int64)]),
+        "hslb_checkpoint_save": (ctypes.c_int, [_vp, ctypes.c_void_p]),
+        "hslb_checkpoint_load": (ctypes.c_int, [_vp, ctypes.c_void_p]),
         "hslb_set_graph": (ctypes.c_int, [_vp, ctypes.c_int32]),
         "hslb_set_kernel_timing": (ctypes.c_int, [_vp, ctypes.c_int32]),
         "hslb_kernel_times": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_void_p, _dp,
                                              _P(ctypes.c_int64), _P(ctypes.c_int32)]),
         "hslb_get_timings": (ctypes.c_int, [_vp, _dp, _dp]),
         "hslb_copy_bandwidth": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, _dp]),
+        "hslb_batch_create": (ctypes.c_int, [_P(hslb_params), ctypes.c_int32, _P(_vp)]),
+        "hslb_batch_init": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, _dp]),
+        "hslb_batch_profiles": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, _dp]),
+        "hslb_batch_finite": (ctypes.c_int, [_vp, _P(ctypes.c_int32)]),
+        "hslb_batch_set_config": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
+        "hslb_batch_autotune": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_int32), _dp,
+                                               ctypes.c_int32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -189,6 +203,23 @@ def hslb_set_watchdog(ctx, every: int, tol: float):
     _chk(ctx, load().hslb_set_watchdog(ctx, int(every), float(tol)))
 
 
+def hslb_checkpoint_save(ctx) -> bytes:
+    n = ctypes.c_int64()
+    _chk(ctx, load().hslb_checkpoint_size(ctx, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value)
+    _chk(ctx, load().hslb_checkpoint_save(ctx, buf))
+    return buf.raw
+
+
+def hslb_checkpoint_load(ctx, data: bytes):
+    buf = ctypes.create_string_buffer(data, len(data))
+    _chk(ctx, load().hslb_checkpoint_load(ctx, buf))
+
+
+def hslb_set_shift_period(ctx, every: int):
+    _chk(ctx, load().hslb_set_shift_period(ctx, int(every)))
+
+
 def hslb_set_graph(ctx, enable: bool):
     _chk(ctx, load().hslb_set_graph(ctx, int(bool(enable))))
 
@@ -224,6 +255,44 @@ def hslb_copy_bandwidth(nbytes: int, iters: int) -> float:
     if rc != HSLB_OK:
         raise HslbError(rc, load().hslb_last_error(None).decode())
     return v.value
+
+
+def hslb_batch_create(slits) -> ctypes.c_void_p:
+    lib = load()
+    arr = (hslb_params * len(slits))(*slits)
+    ctx = _vp()
+    rc = lib.hslb_batch_create(arr, len(slits), ctypes.byref(ctx))
+    if rc != HSLB_OK:
+        raise HslbError(rc, lib.hslb_last_error(None).decode())
+    return ctx
+
+
+def hslb_batch_init(ctx, slit: int, n: np.ndarray, u: Optional[np.ndarray]):
+    _chk(ctx, load().hslb_batch_init(ctx, int(slit), _d(n), _d(u)))
+
+
+def hslb_batch_profiles(ctx, slit: int, n_z: Optional[np.ndarray], u_z: Optional[np.ndarray]):
+    _chk(ctx, load().hslb_batch_profiles(ctx, int(slit), _d(n_z), _d(u_z)))
+
+
+def hslb_batch_finite(ctx, nslits: int) -> np.ndarray:
+    flags = np.zeros(nslits, dtype=np.int32)
+    _chk(ctx, load().hslb_batch_finite(ctx, flags.ctypes.data_as(_P(ctypes.c_int32))))
+    return flags
+
+
+def hslb_batch_set_config(ctx, grid_per_cu: int, order: int):
+    _chk(ctx, load().hslb_batch_set_config(ctx, int(grid_per_cu), int(order)))
+
+
+def hslb_batch_autotune(ctx, steps: int):
+    """Returns (choice, us_per_step[12]): candidates are grid sizes of
+    (1, 2, 4, 8, 16, 32) blocks per compute unit with work in slit order, then
+    the same with work grouped by sigma."""
+    choice = ctypes.c_int32()
+    us = np.zeros(12)
+    _chk(ctx, load().hslb_batch_autotune(ctx, int(steps), ctypes.byref(choice), _d(us), 12))
+    return choice.value, us
 
 
 # ----------------------------------------------------------- convenience
@@ -315,6 +384,62 @@ class Sim:
         return hslb_get_timings(self.ctx)
 
     @classmethod
-    def from_workload(cls, wl, precision: Optional[str] = None, **kw):
+    def from_workload(cls, wl, precision: Optional[str] = None, **kw):  # noqa: D102
         return cls(wl.nx, wl.ny, wl.nz, wl.sigma, wl.tau, accel=wl.accel, wall_lo=wl.wall_lo,
                    wall_hi=wl.wall_hi, precision=precision or wl.precision, **kw)
+
+
+class Batch:
+    """A ragged ensemble of slits advanced together on the GPU (one persistent
+    launch per phase, K steps per HIP graph)."""
+
+    def __init__(self, workloads_, precision="f32", **kw):
+        prec = {"f64": HSLB_FP64, "f32": HSLB_FP32}[precision]
+        self.wls = list(workloads_)
+        self.params = [make_params(w.nx, w.ny, w.nz, w.sigma, w.tau, w.accel, w.wall_lo, w.wall_hi,
+                                   precision=prec, **kw) for w in self.wls]
+        self.ctx = hslb_batch_create(self.params)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            hslb_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        self.close()
+
+    def init(self, slit, n, u=None):
+        w = self.wls[slit]
+        N = w.nx * w.ny * w.nz
+        n = np.ascontiguousarray(n, dtype=np.float64).reshape(N)
+        if u is not None:
+            u = np.ascontiguousarray(u, dtype=np.float64).reshape(3 * N)
+        hslb_batch_init(self.ctx, slit, n, u)
+
+    def init_all(self):
+        for k, w in enumerate(self.wls):
+            n, u = w.fields()
+            self.init(k, n, u)
+
+    def step(self, nsteps=1):
+        hslb_step(self.ctx, nsteps)
+
+    def sync(self):
+        hslb_sync(self.ctx)
+
+    def profiles(self, slit):
+        nz = self.wls[slit].nz
+        pn = np.zeros(nz)
+        pu = np.zeros(3 * nz)
+        hslb_batch_profiles(self.ctx, slit, pn, pu)
+        return pn, pu.reshape(3, nz)
+
+    def finite(self):
+        return hslb_batch_finite(self.ctx, len(self.wls)).astype(bool)
+
+    def autotune(self, steps=20):
+        return hslb_batch_autotune(self.ctx, steps)
+
+    @property
+    def fluid_nodes(self):
+        return sum(w.fluid_nodes for w in self.wls)

@@ -1,0 +1,165 @@
+"""Batched ensemble of slits on the GPU: the persistent, graph-replayed batch
+path against the single-lattice path and against the FP64 oracle, slit by
+slit.
+
+The ensemble starts from laterally uniform density and rest, so every slit
+stays uniform in x and y: the oracle runs it as a 1 x 1 x nz column, which by
+the definitions (periodic wrapping of every lateral offset) computes exactly
+the same profiles as the 16 x 16 x nz slit.
+"""
+import multiprocessing as mp
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_0712_2247_amd import hslb, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    b = np.asarray(b)
+    return float(np.linalg.norm(np.asarray(a) - b) / np.linalg.norm(b))
+
+
+def _column(args):
+    """Oracle profiles of one ensemble slit run as a laterally uniform column;
+    with `eps`, from a start whose density is perturbed by eps sin(z).  Also
+    returns the step by which the run diverged (None if it stayed finite)."""
+    k, steps, eps = args
+    w = workloads.ensemble()[k]
+    o = oracle.Oracle(1, 1, w.nz, sigma=w.sigma, tau=w.tau, accel=w.accel, wall_lo=w.wall_lo,
+                      wall_hi=w.wall_hi)
+    n, u = w.fields()
+    n = n[:, :1, :1] * (1.0 + eps * np.sin(np.arange(w.nz))[:, None, None])
+    o.init(n, u[:, :, :1, :1])
+    div = None
+    chunk = 500
+    for done in range(0, steps, chunk):
+        o.step(min(chunk, steps - done))
+        if div is None and not np.isfinite(o.moments()[0]).all():
+            div = done + chunk
+            break
+    pn, pu = o.profiles()
+    return k, pn, pu, div
+
+
+def _oracle_columns(indices, steps, eps=0.0):
+    procs = min(16, len(os.sched_getaffinity(0)))
+    with mp.get_context("fork").Pool(procs) as pool:
+        return {k: (pn, pu, div) for k, pn, pu, div in
+                pool.map(_column, [(k, steps, eps) for k in indices])}
+
+
+SMALL = [0, 1, 2, 3, 5, 8, 13, 21, 34, 55, 89, 144]
+
+
+def test_batch_matches_single_lattice_and_oracle():
+    steps = 1000
+    wls = [workloads.ensemble()[k].with_size(steps=steps) for k in SMALL]
+    print("sigmas", [w.sigma for w in wls], "nz", [w.nz for w in wls], flush=True)
+    b = hslb.Batch(wls)
+    b.init_all()
+    b.step(steps)
+    fin = b.finite()
+    ref = _oracle_columns(SMALL, steps)
+    for i, k in enumerate(SMALL):
+        pn, pu = b.profiles(i)
+        on, ou, _ = ref[k]
+        o_fin = bool(np.isfinite(on).all() and np.isfinite(ou).all())
+        assert bool(fin[i]) == o_fin, (k, fin[i], o_fin)
+        if o_fin:
+            assert rel(pn, on) <= 1e-5 and rel(pu[0], ou[0]) <= 1e-5, k
+    # the same slits one by one through the single-lattice path
+    for i in (0, 3, 7):
+        w = wls[i]
+        g = hslb.Sim.from_workload(w)
+        n, u = w.fields()
+        g.init(n, u)
+        g.step(steps)
+        sn, su = g.profiles()
+        pn, pu = b.profiles(i)
+        if fin[i]:
+            assert rel(pn, sn) <= 1e-12 and rel(pu[0], su[0]) <= 1e-12
+
+
+def test_batch_graph_and_eager_agree_and_autotune_restores_state():
+    wls = [workloads.ensemble()[k].with_size(steps=60) for k in SMALL[:6]]
+    a = hslb.Batch(wls)
+    a.init_all()
+    a.step(40)
+    before = [a.profiles(i) for i in range(len(wls))]
+    choice, us = a.autotune(steps=10)
+    assert 0 <= choice < 12 and (us > 0).all()
+    after = [a.profiles(i) for i in range(len(wls))]
+    for (p0, u0), (p1, u1) in zip(before, after):
+        assert np.array_equal(p0, p1) and np.array_equal(u0, u1)
+    b = hslb.Batch(wls)
+    hslb.hslb_set_graph(b.ctx, False)
+    b.init_all()
+    for _ in range(40):
+        b.step(1)
+    for i in range(len(wls)):
+        assert np.array_equal(a.profiles(i)[0], b.profiles(i)[0])
+
+
+# Both sides start from the ensemble's uniform density times 1 + EPS sin(z):
+# the paired shell sum of the GPU path is exactly antisymmetric under the
+# mirror z -> nz-1-z, so without a common seed an unstable mirror-antisymmetric
+# mode would grow on the oracle (whose summation order breaks the symmetry at
+# the level of rounding) but never on the GPU.
+EPS = 1e-9
+
+
+def test_ensemble_512_slits_against_oracle():
+    """The full ensemble: 512 slits, 16x16 cross section, H in 10..60,
+    sigma in {3,4,5,6,8}, packing in [0.10, 0.40], 10000 steps in one batch.
+
+    A slit the oracle sees diverge within 5000 steps (from the seeded start and
+    from one seeded twice as strongly) diverges on the GPU too.  Slower divergence grows
+    from rounding noise, so its timing -- and the verdict at 10000 steps --
+    depends on the noise and is only reported.  A slit that stays finite and
+    whose final state is unique (doubling the seed moves the oracle's
+    profiles by at most 1e-6) agrees with the oracle to 1e-5.  Beyond the bulk
+    stability limit of the closure some finite slits settle into layered
+    states that the noise selects (the second oracle run lands elsewhere);
+    those are reported, not compared."""
+    wls = workloads.ensemble()
+    b = hslb.Batch(wls)
+    for k, w in enumerate(wls):
+        n, u = w.fields()
+        b.init(k, n * (1.0 + EPS * np.sin(np.arange(w.nz)))[:, None, None], u)
+    choice, us = b.autotune(steps=10)
+    print(f"autotune choice {choice}: {np.round(us, 1)} us/step", flush=True)
+    b.step(10000)
+    fin = b.finite()
+    print(f"{fin.sum()} of {len(wls)} slits finite", flush=True)
+    ref = _oracle_columns(range(len(wls)), 10000, eps=EPS)
+    pert = _oracle_columns(range(len(wls)), 10000, eps=2 * EPS)
+    worst, compared, selected, marginal, diverged = 0.0, 0, [], [], 0
+    for k, w in enumerate(wls):
+        on, ou, div = ref[k]
+        pn2, pu2, div2 = pert[k]
+        if div is not None and div2 is not None and max(div, div2) <= 5000:
+            # a fast instability: it must show on the GPU as well
+            assert not fin[k], (k, w.sigma, w.eta, div)
+            diverged += 1
+            continue
+        if div is not None or div2 is not None:
+            marginal.append(k)  # slow growth from noise: the verdict depends on it
+            continue
+        assert fin[k], (k, w.sigma, w.eta)
+        if max(rel(pn2, on), rel(pu2[0], ou[0])) > 1e-6:
+            selected.append(k)
+            continue
+        pn, pu = b.profiles(k)
+        e = max(rel(pn, on), rel(pu[0], ou[0]))
+        worst = max(worst, e)
+        compared += 1
+        assert e <= 1e-5, (k, w.sigma, w.eta, e)
+    print(f"{compared} slits compared to 1e-5 (worst {worst:.2e}); {diverged} diverge fast in both; "
+          f"{len(selected)} finite slits with noise-selected states: {selected}; "
+          f"{len(marginal)} diverging slowly from noise: {marginal}", flush=True)
+    assert compared >= 300

@@ -218,25 +218,46 @@ def test_slit_64_full_run_against_golden():
     assert checked >= 1
 
 
-def test_checkpoint_resume_bitwise():
-    """FP32 storage: N + N steps equal N steps, get_populations, a fresh
-    context, set_populations, N steps -- bit for bit."""
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_checkpoint_resume_bitwise(precision):
+    """N + N steps equal N steps, raw checkpoint, a fresh context, load, N
+    steps -- bit for bit, across a refresh of the storage reference (FP32
+    refreshes every 50 steps)."""
+    wl = workloads.slit_small_f64()
+    n, u = wl.fields()
+    a = hslb.Sim.from_workload(wl, precision=precision)
+    a.init(n, u)
+    a.step(120)
+    ref = a.get_populations()
+    assert np.isfinite(ref).all()
+    b = hslb.Sim.from_workload(wl, precision=precision)
+    b.init(n, u)
+    b.step(70)
+    blob = hslb.hslb_checkpoint_save(b.ctx)
+    c = hslb.Sim.from_workload(wl, precision=precision)
+    c.init(n, u)
+    hslb.hslb_checkpoint_load(c.ctx, blob)
+    assert hslb.hslb_step_count(c.ctx) == 70
+    c.step(50)
+    assert np.array_equal(c.get_populations(), ref)
+
+
+def test_set_populations_round_trip():
+    """FP64 populations out and back in: the state is reproduced to FP32
+    storage rounding and the run continues within 1e-6 of the original."""
     wl = workloads.slit_small_f64()
     n, u = wl.fields()
     a = hslb.Sim.from_workload(wl, precision="f32")
     a.init(n, u)
-    a.step(40)
-    ref = a.get_populations()
-    assert np.isfinite(ref).all()
-    b = hslb.Sim.from_workload(wl, precision="f32")
-    b.init(n, u)
-    b.step(20)
-    f = b.get_populations()
+    a.step(30)
+    f = a.get_populations()
     c = hslb.Sim.from_workload(wl, precision="f32")
     c.init(n, u)
     c.set_populations(f)
-    c.step(20)
-    assert np.array_equal(c.get_populations(), ref)
+    assert rel(c.get_populations(), f) <= 1e-7
+    a.step(30)
+    c.step(30)
+    assert rel(c.get_populations(), a.get_populations()) <= 1e-6
 
 
 def test_graph_replay_matches_eager():
