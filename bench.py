@@ -47,18 +47,47 @@ def _kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_collide_slit64x64x136_s8.txt")
+
+
 def _traffic(workload: str):
-    """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, if it was taken on the current
-    kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic_collide_slit64.json")
+    """HBM bytes per launch of the dominant kernel, from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary (key = value lines), if it was
+    taken on the current kernel source and workload; else None."""
     try:
-        rec = json.load(open(path))
-    except (OSError, ValueError):
+        rec = {}
+        for line in open(TRAFFIC_FILE):
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                rec[k.strip()] = v.strip()
+    except OSError:
         return None
     if rec.get("kernel_source_hash") != _kernel_source_hash() or rec.get("workload") != workload:
         return None
-    return rec.get("bytes_per_launch")
+    return float(rec["bytes_per_launch"])
+
+
+def ensemble_throughput(hslb, workloads, steps: int):
+    """The 512-slit ragged ensemble advanced by the batched persistent path
+    (autotuned launch shape, graph replay): MLUPS over `steps` steps."""
+    wls = workloads.ensemble()
+    b = hslb.Batch(wls)
+    b.init_all()
+    choice, us = b.autotune(steps=10)
+    b.step(20)
+    b.sync()
+    t0 = time.perf_counter()
+    b.step(steps)
+    b.sync()
+    dt = time.perf_counter() - t0
+    fin = int(b.finite().sum())
+    out = {"workload": f"{len(wls)} slits 16x16x(H+walls), H 10..60, sigma 3..8, packing 0.10..0.40",
+           "fluid_nodes": b.fluid_nodes, "steps": steps,
+           "value": round(b.fluid_nodes * steps / dt / 1e6, 1), "unit": "MLUPS",
+           "ms_per_step": round(dt / steps * 1e3, 5),
+           "autotune_choice": int(choice), "finite_slits": fin}
+    b.close()
+    return out
 
 
 def cpu_baseline(wl, n, u, budget_s: float):
@@ -88,6 +117,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-pass", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
@@ -161,6 +191,15 @@ def main():
 
     gn, gu = sim.moments()
     assert np.isfinite(gn).all(), "non-finite state"
+    sim.close()
+
+    copy_gbps = hslb.hslb_copy_bandwidth(1 << 30, 20)
+    print(f"bench: device copy {copy_gbps:.0f} GB/s", file=sys.stderr, flush=True)
+
+    ens = None
+    if not args.no_ensemble:
+        print("bench: ensemble", file=sys.stderr, flush=True)
+        ens = ensemble_throughput(hslb, workloads, min(args.steps, 500))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -186,7 +225,10 @@ def main():
                    "force": "exact shell sum", "parallelism": "single GPU"},
         "step_algorithmic_GBps": round(mlups * 1e6 * STEP_BYTES / 1e9, 1),
         "step_hbm_frac": round(mlups * 1e6 * STEP_BYTES / 1e9 / PEAK_HBM_GBPS, 4),
+        "copy_GBps": round(copy_gbps, 1),
+        "step_copy_frac": round(mlups * 1e6 * STEP_BYTES / 1e9 / copy_gbps, 4),
         "as_specified": as_specified,
+        "ensemble": ens,
         "roofline": roof,
         "kernels_us": kernels,
         "cpu_baseline": cpu,

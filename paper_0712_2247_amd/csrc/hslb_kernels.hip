@@ -169,19 +169,19 @@ __global__ __launch_bounds__(256) void k_layer_means(LatticeDev L, const TF *__r
 
 // ------------------------------------------------------------------ moments
 
+// Node r of layer z (0 <= r < plane).  Called with a block-uniform z from the
+// layer-indexed grid, so the reference row is read through scalar loads.
 template <typename TF, typename TM>
 __device__ __forceinline__ void d_moments(const LatticeDev &L, const double *__restrict__ nref,
-                                          const TF *__restrict__ f, const Fields<TM> &fld, int id)
+                                          const TF *__restrict__ f, const Fields<TM> &fld, int z, int r)
 {
-    if (id >= L.N) return;
-    const int z = id / L.plane;
-    const int rem = id - z * L.plane;
+    const int id = z * L.plane + r;
     double n = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
     if (is_fluid_z(L, z)) {
-        const double *r = layer_ref(nref, z);
+        const double *rf = layer_ref(nref, z);
 #pragma unroll
         for (int i = 0; i < NQ; ++i) {
-            const double fi = (double)f[(size_t)i * L.pop_stride + id] + r[i];
+            const double fi = (double)f[(size_t)i * L.pop_stride + id] + rf[i];
             n += fi;
             if (CX[i] > 0) jx += fi;
             if (CX[i] < 0) jx -= fi;
@@ -191,17 +191,19 @@ __device__ __forceinline__ void d_moments(const LatticeDev &L, const double *__r
             if (CZ[i] < 0) jz -= fi;
         }
     }
-    store_padded(L, fld.n, rem, z, (TM)n);
-    store_padded(L, fld.j, rem, z, (TM)jx);
-    store_padded(L, fld.j + L.fld_stride, rem, z, (TM)jy);
-    store_padded(L, fld.j + 2 * L.fld_stride, rem, z, (TM)jz);
+    store_padded(L, fld.n, r, z, (TM)n);
+    store_padded(L, fld.j, r, z, (TM)jx);
+    store_padded(L, fld.j + L.fld_stride, r, z, (TM)jy);
+    store_padded(L, fld.j + 2 * L.fld_stride, r, z, (TM)jz);
 }
 
+// grid (ceil(plane / 256), nz): x = chunk of the layer, y = layer
 template <typename TF, typename TM>
 __global__ __launch_bounds__(256) void k_moments(LatticeDev L, const double *__restrict__ nref,
                                                  const TF *__restrict__ f, Fields<TM> fld)
 {
-    d_moments(L, nref, f, fld, blockIdx.x * 256 + threadIdx.x);
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r < L.plane) d_moments(L, nref, f, fld, (int)blockIdx.y, r);
 }
 
 // ------------------------------------------------- coarse-grained density
@@ -486,20 +488,15 @@ __device__ __forceinline__ void node_force(const Fields<TM> &F, const LatticeDev
 
 // ------------------------------------------------- collide and stream
 
-// k indexes the fluid nodes (all nodes with a periodic z axis).
+// Node r (0 <= r < plane) of fluid layer z.
 template <int SIG, typename TF, typename TM>
 __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &sc, const double *__restrict__ chi,
                                           const TF *__restrict__ fin, TF *__restrict__ fout, const Fields<TM> &fld,
-                                          int k)
+                                          int z, int r)
 {
-    const int first = L.zper ? 0 : L.wall_lo * L.plane;
-    const int last = L.zper ? L.N : (L.nz - L.wall_hi) * L.plane;
-    const int id = first + k;
-    if (id >= last) return;
-    const int z = id / L.plane;
-    const int rem = id - z * L.plane;
-    const int y = rem / L.nx;
-    const int x = rem - y * L.nx;
+    const int id = z * L.plane + r;
+    const int y = r / L.nx;
+    const int x = r - y * L.nx;
 
     double f[NQ];
     const double *rr = layer_ref(sc.nref_r, z);
@@ -546,12 +543,16 @@ __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &
     }
 }
 
+// grid (ceil(plane / 256), fluid layers): z is uniform over a block, so the
+// rows of the storage reference tables come in through scalar loads.
 template <int SIG, typename TF, typename TM>
 __global__ __launch_bounds__(256) void k_collide(LatticeDev L, StepConst sc, const double *__restrict__ chi,
                                                  const TF *__restrict__ fin, TF *__restrict__ fout,
                                                  Fields<TM> fld)
 {
-    d_collide<SIG>(L, sc, chi, fin, fout, fld, blockIdx.x * 256 + threadIdx.x);
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    const int z = (L.zper ? 0 : L.wall_lo) + (int)blockIdx.y;
+    if (r < L.plane) d_collide<SIG>(L, sc, chi, fin, fout, fld, z, r);
 }
 
 template <int SIG, typename TF, typename TM>
@@ -713,6 +714,21 @@ __device__ __forceinline__ Fields<TM> shift_fields(const Fields<TM> &F, int off)
     return g;
 }
 
+// Collision at fluid index k of a slit (fluid nodes counted from the first
+// fluid layer); the layer is computed per lane (see kb_phase).
+template <int SIG, typename TF, typename TM>
+__device__ __forceinline__ void batch_collide(const LatticeDev &L, const StepConst &sc, const double *__restrict__ chi,
+                                              const TF *__restrict__ fin, TF *__restrict__ fout,
+                                              const Fields<TM> &fld, int k)
+{
+    const int first = L.zper ? 0 : L.wall_lo * L.plane;
+    const int last = L.zper ? L.N : (L.nz - L.wall_hi) * L.plane;
+    const int id = first + k;
+    if (id >= last) return;
+    const int z = id / L.plane;
+    d_collide<SIG>(L, sc, chi, fin, fout, fld, z, id - z * L.plane);
+}
+
 // Persistent kernel of one phase of the step for every slit: the grid walks
 // the work list; each item is one block of 256 indices of one slit, whose
 // descriptor (and sigma, hence the shell stencil) is uniform over the block.
@@ -727,19 +743,23 @@ __global__ __launch_bounds__(256) void kb_phase(int phase, const SlitDesc *__res
         const SlitDesc &d = desc[it.slit];
         const int idx = it.block * 256 + threadIdx.x;
         const Fields<TM> F = shift_fields(fld, d.fld_off);
-        TM *r = rs + d.fld_off;
+        TM *rsl = rs + d.fld_off;
         const TF *fi = fin + d.pop_off;
         TF *fo = fout + d.pop_off;
         const double *ch = chi + d.chi_off;
         switch (phase) {
-        case 0: d_moments(d.L, d.sc.nref_r, fi, F, idx); break;
+        case 0:
+            // the layer is computed per lane: in this kernel scalar reads of
+            // the reference rows would spill scalar registers
+            if (idx < d.L.N) d_moments(d.L, d.sc.nref_r, fi, F, idx / d.L.plane, idx % d.L.plane);
+            break;
         case 3: d_gfield(d.L, d.sc.g2_model, F, idx); break;
         default:
 #define HSLB_BPH(SG)                                                                     \
     case SG:                                                                             \
-        if (phase == 1) d_rowsum<SG>(d.L, F, r, idx);                                    \
-        else if (phase == 2) d_ballsum<SG>(d.L, d.sc.eta_pref, F, r, idx);              \
-        else d_collide<SG>(d.L, d.sc, ch, fi, fo, F, idx);                               \
+        if (phase == 1) d_rowsum<SG>(d.L, F, rsl, idx);                                  \
+        else if (phase == 2) d_ballsum<SG>(d.L, d.sc.eta_pref, F, rsl, idx);            \
+        else batch_collide<SG>(d.L, d.sc, ch, fi, fo, F, idx);                           \
         break;
             switch (d.sigma) {
                 HSLB_BPH(2)
@@ -855,7 +875,7 @@ hipError_t launch_layer_means(hipStream_t s, const LatticeDev &L, const TF *f, i
 template <typename TF, typename TM>
 hipError_t launch_moments(hipStream_t s, const LatticeDev &L, const double *nref, const TF *f, Fields<TM> fld)
 {
-    hipLaunchKernelGGL((k_moments<TF, TM>), dim3(blocks_for(L.N)), dim3(256), 0, s, L, nref, f, fld);
+    hipLaunchKernelGGL((k_moments<TF, TM>), dim3(blocks_for(L.plane), L.nz), dim3(256), 0, s, L, nref, f, fld);
     return hipGetLastError();
 }
 
@@ -913,8 +933,8 @@ template <typename TF, typename TM>
 hipError_t launch_collide(hipStream_t s, const LatticeDev &L, int sigma, const StepConst &c, const double *chi,
                           const TF *fin, TF *fout, Fields<TM> fld)
 {
-    const int nfl = L.zper ? L.N : (L.nz - L.wall_lo - L.wall_hi) * L.plane;
-    const dim3 g(blocks_for(nfl)), b(256);
+    const int layers = L.zper ? L.nz : L.nz - L.wall_lo - L.wall_hi;
+    const dim3 g(blocks_for(L.plane), layers), b(256);
     switch (sigma) {
     case 2: hipLaunchKernelGGL((k_collide<2, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld); break;
     case 3: hipLaunchKernelGGL((k_collide<3, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld); break;

@@ -85,6 +85,28 @@ def test_batch_matches_single_lattice_and_oracle():
             assert rel(pn, sn) <= 1e-12 and rel(pu[0], su[0]) <= 1e-12
 
 
+def test_batch_ragged_planes_match_single_lattice():
+    """Cross sections whose planes are not multiples of 256 nodes (10x12:
+    one partial chunk per layer; 24x20: one full and one partial) and lateral
+    noise: the batch reproduces the single-lattice path node for node."""
+    base = [workloads.ensemble()[k] for k in (1, 2, 5)]
+    wls = [base[0].with_size(nx=10, ny=12, noise=0.01, steps=50),
+           base[1].with_size(nx=24, ny=20, noise=0.01, steps=50),
+           base[2].with_size(nx=16, ny=16, noise=0.01, steps=50)]
+    b = hslb.Batch(wls)
+    b.init_all()
+    b.step(50)
+    for i, w in enumerate(wls):
+        g = hslb.Sim.from_workload(w)
+        n, u = w.fields()
+        g.init(n, u)
+        g.step(50)
+        sn, su = g.profiles()
+        pn, pu = b.profiles(i)
+        assert np.isfinite(sn).all()
+        assert rel(pn, sn) <= 1e-12 and rel(pu[0], su[0]) <= 1e-12, (i, rel(pn, sn), rel(pu[0], su[0]))
+
+
 def test_batch_graph_and_eager_agree_and_autotune_restores_state():
     wls = [workloads.ensemble()[k].with_size(steps=60) for k in SMALL[:6]]
     a = hslb.Batch(wls)
