@@ -543,15 +543,29 @@ __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &
     }
 }
 
-// grid (ceil(plane / 256), fluid layers): z is uniform over a block, so the
-// rows of the storage reference tables come in through scalar loads.
+// Workgroups are handed to the 8 XCDs round-robin by linear block index.  This
+// bijection gives XCD x a contiguous run of logical blocks (hence of layers),
+// so the moment-field planes a layer's shell sum reads stay in that XCD's L2
+// instead of being fetched by all eight.
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    const int q = nb >> 3, rm = nb & 7;
+    const int x = b & 7, slot = b >> 3;
+    return x * q + (x < rm ? x : rm) + slot;
+}
+
+// 1-D grid over (layer, chunk of 256 nodes of the layer): z is uniform over a
+// block, so the rows of the storage reference tables come in through scalar
+// loads.
 template <int SIG, typename TF, typename TM>
 __global__ __launch_bounds__(256) void k_collide(LatticeDev L, StepConst sc, const double *__restrict__ chi,
                                                  const TF *__restrict__ fin, TF *__restrict__ fout,
-                                                 Fields<TM> fld)
+                                                 Fields<TM> fld, int cpp)
 {
-    const int r = blockIdx.x * 256 + threadIdx.x;
-    const int z = (L.zper ? 0 : L.wall_lo) + (int)blockIdx.y;
+    const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int zl = lb / cpp;
+    const int r = (lb - zl * cpp) * 256 + threadIdx.x;
+    const int z = (L.zper ? 0 : L.wall_lo) + zl;
     if (r < L.plane) d_collide<SIG>(L, sc, chi, fin, fout, fld, z, r);
 }
 
@@ -934,15 +948,16 @@ hipError_t launch_collide(hipStream_t s, const LatticeDev &L, int sigma, const S
                           const TF *fin, TF *fout, Fields<TM> fld)
 {
     const int layers = L.zper ? L.nz : L.nz - L.wall_lo - L.wall_hi;
-    const dim3 g(blocks_for(L.plane), layers), b(256);
+    const int cpp = (int)blocks_for(L.plane);
+    const dim3 g(cpp * layers), b(256);
     switch (sigma) {
-    case 2: hipLaunchKernelGGL((k_collide<2, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld); break;
-    case 3: hipLaunchKernelGGL((k_collide<3, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld); break;
-    case 4: hipLaunchKernelGGL((k_collide<4, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld); break;
-    case 5: hipLaunchKernelGGL((k_collide<5, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld); break;
-    case 6: hipLaunchKernelGGL((k_collide<6, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld); break;
-    case 7: hipLaunchKernelGGL((k_collide<7, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld); break;
-    case 8: hipLaunchKernelGGL((k_collide<8, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld); break;
+    case 2: hipLaunchKernelGGL((k_collide<2, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
+    case 3: hipLaunchKernelGGL((k_collide<3, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
+    case 4: hipLaunchKernelGGL((k_collide<4, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
+    case 5: hipLaunchKernelGGL((k_collide<5, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
+    case 6: hipLaunchKernelGGL((k_collide<6, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
+    case 7: hipLaunchKernelGGL((k_collide<7, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
+    case 8: hipLaunchKernelGGL((k_collide<8, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
