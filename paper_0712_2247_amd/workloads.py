@@ -174,6 +174,34 @@ def surrogate_training_runs(nruns: int = 40, seed: int = 1006) -> List[Workload]
     return out
 
 
+# Learned force: canonical weight vector W1[32][1][125], b1[32], W2[32][32][125],
+# b2[32], W3[3][32][125], b3[3] (tap t = (dz+2)*25 + (dy+2)*5 + (dx+2)).
+CNN_SHAPES = [(32, 1, 125), (32,), (32, 32, 125), (32,), (3, 32, 125), (3,)]
+CNN_NWEIGHTS = sum(int(np.prod(s)) for s in CNN_SHAPES)
+
+
+def cnn_init_weights(seed: int = 1007) -> np.ndarray:
+    """Initial weights of the learned force, FP32 values: W ~ N(0, 2/fan_in)
+    for the two GELU layers, N(0, 1/fan_in) for the output layer, zero
+    biases (fan_in = 125 x input channels)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shp, gain in zip(CNN_SHAPES, (2.0, None, 2.0, None, 1.0, None)):
+        if gain is None:
+            parts.append(np.zeros(shp))
+        else:
+            parts.append(rng.standard_normal(shp) * math.sqrt(gain / (shp[1] * shp[2])))
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+
+
+def bf16_grid_values(shape, scale: float, seed: int) -> np.ndarray:
+    """Seeded random values that are exactly representable in bfloat16
+    (FP32 draws with the low 16 bits cleared), as float32."""
+    rng = np.random.default_rng(seed)
+    a = (scale * rng.standard_normal(size=shape)).astype(np.float32)
+    return (a.view(np.uint32) & np.uint32(0xFFFF0000)).view(np.float32)
+
+
 WORKLOADS = {
     "slit_small_f64": slit_small_f64,
     "slit_64_f32": slit_64_f32,
