@@ -214,6 +214,92 @@ int hslb_batch_set_config(hslb_ctx *ctx, int32_t grid_per_cu, int32_t order);
 int hslb_batch_autotune(hslb_ctx *ctx, int32_t steps, int32_t *choice, double *us_per_step,
                         int32_t cap);
 
+/* ---- Learned force ---------------------------------------------------------
+ * Not in the paper: a 3-D convolutional network replaces the exact interaction
+ * force C1 of eq. (12) between periodic exact checks.  Network: three 5x5x5
+ * convolutions with bias, 1 -> 32 -> 32 -> 3 channels, exact GELU after the
+ * first two; input the packing-fraction field pi sigma^3 n / 6; output F_hat
+ * with C1 ~= F_hat v_T^2 (6/pi)^2 4 pi / sigma^4.  x and y wrap, z wraps
+ * without walls and reads zero beyond walled arrays.  The input, weights and
+ * hidden activations are rounded to bfloat16 for the BF16 matrix cores, with
+ * FP32 accumulation, biases and activations.
+ *
+ * Weights: HSLB_CNN_NWEIGHTS FP32 values, canonical order W1[32][1][125],
+ * b1[32], W2[32][32][125], b2[32], W3[3][32][125], b3[3]; tap
+ * t = (dz+2)*25 + (dy+2)*5 + (dx+2), conv(x)[co][r] = sum W[co][ci][t] x[ci][r + d_t].
+ *
+ * A context created with force_mode HSLB_FORCE_SURROGATE (nx % 32 == 0,
+ * ny % 4 == 0, surr_check_every >= 1, surr_tol > 0, else HSLB_EINVAL) steps
+ * as follows once weights are loaded (hslb_step before that: HSLB_ENOSURR):
+ *   - every surr_check_every steps (step index % K == 0) an exact step that
+ *     also evaluates the network and its residual
+ *     r = |fs F_hat - C1|_2 / |C1|_2 over the fluid nodes, and keeps the
+ *     correction delta = C1 - fs F_hat;
+ *   - otherwise, if the last check had r <= surr_tol, a step with
+ *     C1 = fs F_hat(n_t) + delta (HSLB_SURR_CORRECTED), fs F_hat(n_t)
+ *     (HSLB_SURR_PLAIN) or the frozen exact force delta of the last check
+ *     without the network (HSLB_SURR_FROZEN, the no-network ablation);
+ *     if r > surr_tol, exact steps until the next check.
+ * hslb_surrogate_stats: checks done, exact fallback steps, last and largest
+ * residual.  hslb_surrogate_force: fs F_hat [3][N] of the current state
+ * (host, caller-owned).  Weight arrays are caller-owned and copied. */
+#define HSLB_CNN_NWEIGHTS 144067
+enum { HSLB_SURR_CORRECTED = 0, HSLB_SURR_PLAIN = 1, HSLB_SURR_FROZEN = 2 };
+int hslb_surrogate_set_weights(hslb_ctx *ctx, const float *w, int64_t nw);
+int hslb_surrogate_get_weights(hslb_ctx *ctx, float *w, int64_t nw);
+int hslb_surrogate_set_mode(hslb_ctx *ctx, int32_t mode);
+int hslb_surrogate_stats(hslb_ctx *ctx, int64_t *checks, int64_t *fallback_steps, double *last_residual,
+                         double *max_residual);
+int hslb_surrogate_force(hslb_ctx *ctx, double *F);
+
+/* Training of the learned force on the GPU.  A trainer holds up to
+ * capacity_nodes nodes of snapshots (14 bytes per node of device memory), each
+ * of at most max_snapshot_nodes nodes: the network input of a lattice state
+ * and its target C1 / fs (exact force without the external field).
+ *   hslb_trainer_add_snapshot: from a context's current state (FP32 or FP64,
+ *     exact or surrogate force mode; nx % 32 == 0, ny % 4 == 0);
+ *   hslb_trainer_add_snapshot_host: from host arrays eta[N] (network input
+ *     before rounding) and target[3][N]; walls as in hslb_params;
+ *   hslb_trainer_set_weights: FP32 master weights (resets Adam);
+ *   hslb_trainer_eval / _grad: loss = mean over fluid nodes and the 3
+ *     components of (F_hat - target)^2, the raw output F_hat [3][N] and the
+ *     gradient [HSLB_CNN_NWEIGHTS] (each output nullable);
+ *   hslb_trainer_step: one Adam step (beta 0.9, 0.999, eps 1e-8) on snapshot k.
+ * Gradients: bfloat16 operands (activations, activation gradients), FP32
+ * accumulation.  Errors: HSLB_EINVAL, HSLB_ENOMEM (store full), HSLB_ENOSURR
+ * (no weights), HSLB_EDEVICE; the message is in hslb_trainer_last_error. */
+typedef struct hslb_trainer hslb_trainer;
+int hslb_trainer_create(int64_t capacity_nodes, int64_t max_snapshot_nodes, hslb_trainer **out);
+void hslb_trainer_destroy(hslb_trainer *tr);
+const char *hslb_trainer_last_error(const hslb_trainer *tr);
+int hslb_trainer_add_snapshot(hslb_trainer *tr, hslb_ctx *ctx, int32_t *index);
+int hslb_trainer_add_snapshot_host(hslb_trainer *tr, int32_t nx, int32_t ny, int32_t nz, int32_t wall_lo,
+                                   int32_t wall_hi, const double *eta, const double *target, int32_t *index);
+int hslb_trainer_count(hslb_trainer *tr, int32_t *count);
+int hslb_trainer_set_weights(hslb_trainer *tr, const float *w, int64_t nw);
+int hslb_trainer_get_weights(hslb_trainer *tr, float *w, int64_t nw);
+int hslb_trainer_eval(hslb_trainer *tr, int32_t snapshot, double *loss, float *out);
+int hslb_trainer_grad(hslb_trainer *tr, int32_t snapshot, double *loss, float *grad);
+int hslb_trainer_step(hslb_trainer *tr, int32_t snapshot, double lr, double *loss);
+
+/* One network operation on host data (nx % 32 == 0, ny % 4 == 0, zper: z
+ * periodic).  All host arrays are FP32, channel-major [c][N]; values that feed
+ * a convolution are rounded to bfloat16 first; w in canonical order.
+ *   FWD1: in x[N]          -> out z1[32][N], a1[32][N]    (a = bf16(GELU(z)))
+ *   FWD2: in a1[32][N]     -> out z2[32][N], a2[32][N]
+ *   FWD3: in a2[32][N]     -> out F_hat[3][N]
+ *   DX3:  in g[3][N], aux z2[32][N]   -> out da2[32][N], dz2 = bf16(da2 GELU'(z2))
+ *   DX2:  in dz2[32][N], aux z1[32][N] -> out da1[32][N], dz1
+ *   DW1:  in x[N], aux dz1[32][N]     -> out dW1[32*125], db1[32]
+ *   DW2:  in a1[32][N], aux dz2[32][N] -> out dW2[32*32*125], db2[32]
+ *   DW3:  in a2[32][N], aux g[3][N]    -> out dW3[3*32*125], db3[3]
+ * (da = transposed convolution of the gradient; dW, db as the weight and bias
+ * gradients of the layer.)  Message in hslb_trainer_last_error(NULL). */
+enum { HSLB_CNN_FWD1 = 0, HSLB_CNN_FWD2, HSLB_CNN_FWD3, HSLB_CNN_DX3, HSLB_CNN_DX2, HSLB_CNN_DW1, HSLB_CNN_DW2,
+       HSLB_CNN_DW3 };
+int hslb_cnn_op(int32_t op, int32_t nx, int32_t ny, int32_t nz, int32_t zper, const float *w, const float *in,
+                const float *aux, float *out);
+
 /* Device-to-device copy of `bytes` bytes, repeated `iters` times on a private
  * stream: *gbps = 2 * bytes * iters / elapsed (read + write).  The reference
  * for the achievable HBM bandwidth and the calibration kernel ("k_copy") of the

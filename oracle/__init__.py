@@ -69,7 +69,8 @@ def _load():
     for name in ("hsref_init", "hsref_moments", "hsref_profiles"):
         getattr(lib, name).argtypes = [ctypes.c_void_p, d, d]
         getattr(lib, name).restype = ctypes.c_int
-    for name in ("hsref_force", "hsref_eta_bar", "hsref_get_populations", "hsref_set_populations"):
+    for name in ("hsref_force", "hsref_eta_bar", "hsref_get_populations", "hsref_set_populations",
+                 "hsref_step_with_force"):
         getattr(lib, name).argtypes = [ctypes.c_void_p, d]
         getattr(lib, name).restype = ctypes.c_int
     lib.hsref_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
@@ -186,6 +187,12 @@ class Oracle:
         F = np.zeros(3 * self.N)
         self._chk(self._lib.hsref_force(self._ctx, _dptr(F)), "force")
         return F.reshape((3,) + self.shape)
+
+    def step_with_force(self, C1):
+        """One step with the interaction force C1 [3, nz, ny, nx] given (plus
+        the external field n g) instead of the shell sum."""
+        C1 = np.ascontiguousarray(C1, dtype=np.float64).reshape(3 * self.N)
+        self._chk(self._lib.hsref_step_with_force(self._ctx, _dptr(C1)), "step_with_force")
 
     def eta_bar(self):
         e = np.zeros(self.N)

@@ -21,7 +21,7 @@ Network, all convolutions 5x5x5 with bias:
     z2 = conv(a1, W2) + b2     (32 -> 32)           a2 = GELU(z2)
     F  = conv(a2, W3) + b3     (32 -> 3)
 
-GELU(z) = z Phi(z) = z (1 + erf(z / sqrt 2)) / 2, the exact form.
+GELU(z) = z Phi(z) with Phi the standard normal distribution function (the exact form).
 
 conv(x, W)[co, z, y, x] = sum_ci sum_t W[co, ci, t] x[ci, z + dz_t, y + dy_t, x + dx_t],
 with taps t = (dz+2)*25 + (dy+2)*5 + (dx+2) and dz, dy, dx in -2..2.  x and y
@@ -45,7 +45,7 @@ from __future__ import annotations
 import math
 
 import numpy as np
-from scipy.special import erf
+from scipy.special import erf, erfc
 
 NT = 125
 C1 = 32
@@ -95,13 +95,19 @@ def bf16(a):
     return np.ldexp(np.rint(m * 256.0) / 256.0, e)
 
 
+def norm_cdf(z):
+    """Phi(z) = erfc(-z / sqrt 2) / 2, the same as (1 + erf(z / sqrt 2)) / 2 but
+    without its cancellation for z << 0."""
+    return 0.5 * erfc(-np.asarray(z, dtype=np.float64) / math.sqrt(2.0))
+
+
 def gelu(z):
-    return 0.5 * z * (1.0 + erf(z / math.sqrt(2.0)))
+    return z * norm_cdf(z)
 
 
 def gelu_grad(z):
     """d GELU / dz = Phi(z) + z phi(z)."""
-    return 0.5 * (1.0 + erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
+    return norm_cdf(z) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
 
 
 def shift(x, dz, dy, dx, zper: bool):

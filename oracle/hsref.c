@@ -568,6 +568,24 @@ int hsref_profiles(hsref_ctx *c, double *nz_out, double *uz_out)
 }
 
 /* Total force F = C1 + n g at the current state, [3][N]. */
+/* One step whose interaction force is given per node instead of computed:
+ * F = C1 + n g at fluid nodes, then the collision (10)-(11) and propagation as
+ * in hsref_step.  C1 is [3][N]; its solid-node values are ignored.  (The
+ * learned force replaces C1 this way between exact steps.) */
+int hsref_step_with_force(hsref_ctx *c, const double *C1)
+{
+    if (!c || !C1) return -1;
+    const int64_t N = c->N;
+    phase_moments(c);
+    for (int64_t id = 0; id < N; ++id) {
+        const int fl = fluid_node(c, id);
+        for (int a = 0; a < 3; ++a) c->F[a * N + id] = fl ? C1[a * N + id] + c->n[id] * c->p.accel[a] : 0.0;
+    }
+    phase_collide_stream(c);
+    phase_moments(c);
+    return 0;
+}
+
 int hsref_force(hsref_ctx *c, double *F)
 {
     if (!c || !F) return -1;

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhslb.so")
 
-SOURCES = ["hslb_kernels.hip", "hslb_capi.cpp"]
+SOURCES = ["hslb_kernels.hip", "hslb_cnn.hip", "hslb_capi.cpp", "hslb_train.cpp"]
 
 HIPFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

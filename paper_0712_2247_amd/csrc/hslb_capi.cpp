@@ -5,6 +5,7 @@
 // HIP stream, replays pairs of steps from captured HIP graphs, and copies
 // results out on request.
 #include "hslb.h"
+#include "hslb_cnn.hpp"
 #include "hslb_internal.hpp"
 
 #include <cmath>
@@ -100,6 +101,22 @@ public:
         (void)buf;
         return fail_state("checkpoints are per lattice");
     }
+    // learned force (single lattices only)
+    virtual int surr_set_weights(const float *w) { (void)w; return fail_state("learned force needs a single lattice"); }
+    virtual int surr_get_weights(float *w) { (void)w; return fail_state("learned force needs a single lattice"); }
+    virtual int surr_set_mode(int mode) { (void)mode; return fail_state("learned force needs a single lattice"); }
+    virtual int surr_stats(int64_t *checks, int64_t *fallback, double *last_r, double *max_r)
+    {
+        (void)checks, (void)fallback, (void)last_r, (void)max_r;
+        return fail_state("learned force needs a single lattice");
+    }
+    virtual int surr_force(double *F) { (void)F; return fail_state("learned force needs a single lattice"); }
+    // network input x = bf16(eta) and target C1 / force scale of the current state
+    virtual int training_pair(uint16_t *x, float *target, cnn::Geo *g, int *wall_lo, int *wall_hi, int *sigma)
+    {
+        (void)x, (void)target, (void)g, (void)wall_lo, (void)wall_hi, (void)sigma;
+        return fail_state("training pairs come from single lattices");
+    }
     int fail_state(const char *msg)
     {
         err = msg;
@@ -162,6 +179,8 @@ public:
         (void)hipFree(nref_d_);
         (void)hipHostFree(prof_h_);
         (void)hipFree(io_d_);
+        (void)hipFree(surr_mem_);
+        (void)hipHostFree(jpart_h_);
         if (own_stream_ && stream_) (void)hipStreamDestroy(stream_);
     }
 
@@ -391,6 +410,7 @@ public:
 
     int advance(int64_t n)
     {
+        if (p_.force_mode == HSLB_FORCE_SURROGATE) return advance_surrogate(n);
         const bool graph = use_graph && !kt.enabled;
         while (n > 0) {
             if (shift_every > 0 && steps > 0 && steps % shift_every == 0 && refreshed_at_ != steps) {
@@ -635,7 +655,273 @@ public:
         return HSLB_OK;
     }
 
+    // ------------------------------------------------ learned force
+
+    cnn::Geo cnn_geo() const { return cnn::Geo{L_.nx, L_.ny, L_.nz, L_.zper, L_.N}; }
+
+    // Network buffers, allocated with the first weights.
+    int surr_alloc()
+    {
+        if (surr_mem_) return HSLB_OK;
+        const size_t N = L_.N;
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            const size_t o = off;
+            off += (bytes + 255) / 256 * 256;
+            return o;
+        };
+        const size_t o_w = take(sizeof(float) * cnn::NW);
+        size_t o_pk[3];
+        for (int k = 0; k < 3; ++k) o_pk[k] = take(sizeof(uint16_t) * cnn::pack_elems(k));
+        const size_t o_x = take(sizeof(uint16_t) * N);
+        const size_t o_a1 = take(sizeof(uint16_t) * 32 * N);
+        const size_t o_a2 = take(sizeof(uint16_t) * 32 * N);
+        const size_t o_fh = take(sizeof(float) * 3 * N);
+        const size_t o_dl = take(sizeof(float) * 3 * N);
+        const size_t o_c1 = take(sizeof(double) * 3 * N);
+        const size_t o_jp = take(sizeof(double) * 2 * cnn::judge_blocks(cnn_geo()));
+        if (hipMalloc(&surr_mem_, off) != hipSuccess) return fail(err, HSLB_ENOMEM, "learned-force buffers (%zu bytes)", off);
+        char *b = (char *)surr_mem_;
+        cw_ = (float *)(b + o_w);
+        for (int k = 0; k < 3; ++k) cpk_[k] = (uint16_t *)(b + o_pk[k]);
+        cx_ = (uint16_t *)(b + o_x);
+        ca1_ = (uint16_t *)(b + o_a1);
+        ca2_ = (uint16_t *)(b + o_a2);
+        fhat_ = (float *)(b + o_fh);
+        delta_ = (float *)(b + o_dl);
+        c1_ = (double *)(b + o_c1);
+        jpart_ = (double *)(b + o_jp);
+        HIP_TRY(hipMemset(delta_, 0, sizeof(float) * 3 * N));
+        HIP_TRY(hipHostMalloc((void **)&jpart_h_, sizeof(double) * 2 * cnn::judge_blocks(cnn_geo()), hipHostMallocDefault));
+        fscale_ = (1.0 / 3.0) * (6.0 / M_PI) * (6.0 / M_PI) * 4.0 * M_PI / std::pow((double)sigma_, 4);
+        return HSLB_OK;
+    }
+
+    int surr_set_weights(const float *w) override
+    {
+        if (p_.force_mode != HSLB_FORCE_SURROGATE) return fail(err, HSLB_ESTATE, "context is not in surrogate mode");
+        for (int i = 0; i < cnn::NW; ++i)
+            if (!std::isfinite(w[i])) return fail(err, HSLB_EINVAL, "weight %d is not finite", i);
+        int rc = surr_alloc();
+        if (rc) return rc;
+        HIP_TRY(hipMemcpyAsync(cw_, w, sizeof(float) * cnn::NW, hipMemcpyHostToDevice, st()));
+        for (int k = 0; k < 3; ++k) HIP_TRY(cnn::launch_pack(st(), k, cw_, cpk_[k]));
+        HIP_TRY(hipStreamSynchronize(st()));
+        have_w_ = true;
+        surr_ok_ = false;
+        surr_checks_ = surr_fallback_ = 0;
+        surr_last_r_ = -1.0;
+        surr_max_r_ = 0.0;
+        return HSLB_OK;
+    }
+
+    int surr_get_weights(float *w) override
+    {
+        if (!have_w_) return fail(err, HSLB_ENOSURR, "no weights loaded");
+        HIP_TRY(hipMemcpyAsync(w, cw_, sizeof(float) * cnn::NW, hipMemcpyDeviceToHost, st()));
+        HIP_TRY(hipStreamSynchronize(st()));
+        return HSLB_OK;
+    }
+
+    int surr_set_mode(int mode) override
+    {
+        if (p_.force_mode != HSLB_FORCE_SURROGATE) return fail(err, HSLB_ESTATE, "context is not in surrogate mode");
+        if (mode < HSLB_SURR_CORRECTED || mode > HSLB_SURR_FROZEN) return fail(err, HSLB_EINVAL, "surrogate mode");
+        surr_mode_ = mode;
+        surr_ok_ = false;
+        return HSLB_OK;
+    }
+
+    int surr_stats(int64_t *checks, int64_t *fallback, double *last_r, double *max_r) override
+    {
+        if (checks) *checks = surr_checks_;
+        if (fallback) *fallback = surr_fallback_;
+        if (last_r) *last_r = surr_last_r_;
+        if (max_r) *max_r = surr_max_r_;
+        return HSLB_OK;
+    }
+
+    // F_hat of the current moments (in fld_.n) into fhat_.
+    int cnn_forward()
+    {
+        const cnn::Geo g = cnn_geo();
+        const double eta_in = M_PI * std::pow((double)sigma_, 3) / 6.0;
+        int rc = launch("cnn_input", [&] { return cnn::launch_eta_input<TM>(st(), g, L_.hz, eta_in, fld_.n, cx_); });
+        if (rc) return rc;
+        cnn::FwdArgs a{};
+        a.g = g;
+        a.in = cx_;
+        a.wp = cpk_[0];
+        a.bias = cw_ + cnn::OB1;
+        a.out_cl = ca1_;
+        if ((rc = launch("cnn_l1", [&] { return cnn::launch_conv_fwd(st(), 1, 32, cnn::EPI_GELU, a); }))) return rc;
+        a.in = ca1_;
+        a.wp = cpk_[1];
+        a.bias = cw_ + cnn::OB2;
+        a.out_cl = ca2_;
+        if ((rc = launch("cnn_l2", [&] { return cnn::launch_conv_fwd(st(), 32, 32, cnn::EPI_GELU, a); }))) return rc;
+        a.in = ca2_;
+        a.wp = cpk_[2];
+        a.bias = cw_ + cnn::OB3;
+        a.out_cl = nullptr;
+        a.out_f32 = fhat_;
+        return launch("cnn_l3", [&] { return cnn::launch_conv_fwd(st(), 32, 3, cnn::EPI_OUT, a); });
+    }
+
+    // A step with the learned force (plus the frozen correction).
+    int step_surrogate()
+    {
+        int rc = launch("moments", [&] { return launch_moments<TF, TM>(st(), L_, nref_d_, f_[cur_], fld_); });
+        if (rc) return rc;
+        if (surr_mode_ != HSLB_SURR_FROZEN && (rc = cnn_forward())) return rc;
+        StepConst sc = sc_;
+        sc.fext = surr_mode_ != HSLB_SURR_FROZEN ? fhat_ : nullptr;
+        sc.fdelta = surr_mode_ != HSLB_SURR_PLAIN ? delta_ : nullptr;
+        sc.fscale = fscale_;
+        rc = launch("collide_ext", [&] {
+            return launch_collide<TF, TM>(st(), L_, 0, sc, chi_d_, f_[cur_], f_[1 - cur_], fld_);
+        });
+        if (rc) return rc;
+        cur_ = 1 - cur_;
+        return HSLB_OK;
+    }
+
+    // Exact step that also judges the learned force: residual
+    // |fs F_hat - C1| / |C1| over fluid nodes, correction C1 - fs F_hat.
+    int step_check()
+    {
+        int rc = launch("moments", [&] { return launch_moments<TF, TM>(st(), L_, nref_d_, f_[cur_], fld_); });
+        if (rc) return rc;
+        if ((rc = fields_hs())) return rc;
+        StepConst s0 = sc_;
+        s0.g[0] = s0.g[1] = s0.g[2] = 0.0;
+        if ((rc = launch("exact_c1", [&] {
+                 return launch_force<TF, TM>(st(), L_, sigma_, s0, chi_d_, f_[cur_], fld_, c1_);
+             })))
+            return rc;
+        const bool net = surr_mode_ != HSLB_SURR_FROZEN;
+        if (net && (rc = cnn_forward())) return rc;
+        const cnn::Geo g = cnn_geo();
+        const unsigned nb = cnn::judge_blocks(g);
+        if ((rc = launch("judge", [&] {
+                 return cnn::launch_judge(st(), g, L_.zper ? 0 : L_.wall_lo, L_.zper ? 0 : L_.wall_hi, net ? fscale_ : 0.0,
+                                          net ? fhat_ : nullptr, c1_, delta_, jpart_);
+             })))
+            return rc;
+        HIP_TRY(hipMemcpyAsync(jpart_h_, jpart_, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, st()));
+        rc = launch("collide", [&] {
+            return launch_collide<TF, TM>(st(), L_, sigma_, sc_, chi_d_, f_[cur_], f_[1 - cur_], fld_);
+        });
+        if (rc) return rc;
+        cur_ = 1 - cur_;
+        HIP_TRY(hipStreamSynchronize(st()));
+        double a = 0.0, b = 0.0;
+        for (unsigned k = 0; k < nb; ++k) {
+            a += jpart_h_[2 * k];
+            b += jpart_h_[2 * k + 1];
+        }
+        const double r = b > 0.0 ? std::sqrt(a / b) : (a > 0.0 ? INFINITY : 0.0);
+        surr_last_r_ = r;
+        surr_max_r_ = std::max(surr_max_r_, r);
+        surr_checks_ += 1;
+        surr_ok_ = surr_mode_ == HSLB_SURR_FROZEN || r <= p_.surr_tol;
+        return HSLB_OK;
+    }
+
+    int advance_surrogate(int64_t n)
+    {
+        if (!have_w_) return fail(err, HSLB_ENOSURR, "no surrogate weights loaded");
+        const int64_t K = p_.surr_check_every;
+        while (n > 0) {
+            const bool refresh =
+                shift_every > 0 && steps > 0 && steps % shift_every == 0 && refreshed_at_ != steps;
+            if (refresh)
+                HIP_TRY(launch_layer_means<TF>(st(), L_, f_[cur_], L_.pop_stride, nref_d_, nref_d_ + NQ * L_.nz));
+            int rc;
+            if (steps % K == 0 || !surr_ok_) {
+                if (steps % K == 0) {
+                    rc = step_check();
+                } else {
+                    surr_fallback_ += 1;
+                    rc = one_step();
+                }
+            } else {
+                rc = step_surrogate();
+            }
+            if (rc) return rc;
+            if (refresh) {
+                HIP_TRY(hipMemcpyAsync(nref_d_, nref_d_ + NQ * L_.nz, sizeof(double) * NQ * L_.nz,
+                                       hipMemcpyDeviceToDevice, st()));
+                refreshed_at_ = steps;
+            }
+            n -= 1;
+            steps += 1;
+        }
+        return HSLB_OK;
+    }
+
+    int surr_force(double *F) override
+    {
+        if (!inited) return fail(err, HSLB_ESTATE, "force before init");
+        if (!have_w_) return fail(err, HSLB_ENOSURR, "no surrogate weights loaded");
+        double *d;
+        const size_t N = L_.N;
+        int rc = io(sizeof(double) * 3 * N, &d);
+        if (rc) return rc;
+        HIP_TRY(launch_moments<TF, TM>(st(), L_, nref_d_, f_[cur_], fld_));
+        if ((rc = cnn_forward())) return rc;
+        HIP_TRY(cnn::launch_scale_f32_to_f64(st(), fhat_, fscale_, 3 * N, d));
+        HIP_TRY(hipMemcpyAsync(F, d, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, st()));
+        HIP_TRY(hipStreamSynchronize(st()));
+        return HSLB_OK;
+    }
+
+    int training_pair(uint16_t *x, float *target, cnn::Geo *g, int *wall_lo, int *wall_hi, int *sigma) override
+    {
+        if (!inited) return fail(err, HSLB_ESTATE, "snapshot before init");
+        if (p_.force_mode == HSLB_FORCE_OFF) return fail(err, HSLB_ESTATE, "hard-sphere term is off");
+        if (L_.nx % 32 || L_.ny % 4) return fail(err, HSLB_EINVAL, "training snapshots need nx %% 32 == 0 and ny %% 4 == 0");
+        if (!x || !target) {  // geometry only
+            *g = cnn_geo();
+            *wall_lo = L_.zper ? 0 : L_.wall_lo;
+            *wall_hi = L_.zper ? 0 : L_.wall_hi;
+            *sigma = sigma_;
+            return HSLB_OK;
+        }
+        double *d;
+        const size_t N = L_.N;
+        int rc = io(sizeof(double) * 3 * N, &d);
+        if (rc) return rc;
+        const double fs = (1.0 / 3.0) * (6.0 / M_PI) * (6.0 / M_PI) * 4.0 * M_PI / std::pow((double)sigma_, 4);
+        HIP_TRY(launch_moments<TF, TM>(st(), L_, nref_d_, f_[cur_], fld_));
+        if ((rc = fields_hs())) return rc;
+        StepConst s0 = sc_;
+        s0.g[0] = s0.g[1] = s0.g[2] = 0.0;
+        HIP_TRY(launch_force<TF, TM>(st(), L_, sigma_, s0, chi_d_, f_[cur_], fld_, d));
+        HIP_TRY(cnn::launch_scale_f64_to_f32(st(), d, 1.0 / fs, 3 * N, target));
+        HIP_TRY(cnn::launch_eta_input<TM>(st(), cnn_geo(), L_.hz, M_PI * std::pow((double)sigma_, 3) / 6.0, fld_.n, x));
+        HIP_TRY(hipStreamSynchronize(st()));
+        *g = cnn_geo();
+        *wall_lo = L_.zper ? 0 : L_.wall_lo;
+        *wall_hi = L_.zper ? 0 : L_.wall_hi;
+        *sigma = sigma_;
+        return HSLB_OK;
+    }
+
 private:
+    // learned force
+    void *surr_mem_ = nullptr;
+    float *cw_ = nullptr;
+    uint16_t *cpk_[3] = {nullptr, nullptr, nullptr};
+    uint16_t *cx_ = nullptr, *ca1_ = nullptr, *ca2_ = nullptr;
+    float *fhat_ = nullptr, *delta_ = nullptr;
+    double *c1_ = nullptr, *jpart_ = nullptr, *jpart_h_ = nullptr;
+    double fscale_ = 0.0;
+    bool have_w_ = false, surr_ok_ = false;
+    int surr_mode_ = HSLB_SURR_CORRECTED;
+    int64_t surr_checks_ = 0, surr_fallback_ = 0;
+    double surr_last_r_ = -1.0, surr_max_r_ = 0.0;
+
     hslb_params p_;
     LatticeDev L_{};
     StepConst sc_{};
@@ -1212,11 +1498,21 @@ static int validate(const hslb_params *p, std::string &err)
     } else if (p->nx < 2 || p->ny < 2) {
         return fail(err, HSLB_EINVAL, "nx and ny must be >= 2");
     }
-    if (p->force_mode == HSLB_FORCE_SURROGATE) return fail(err, HSLB_ENOSURR, "no surrogate weights loaded");
+    if (p->force_mode == HSLB_FORCE_SURROGATE) {
+        if (p->nx % 32 || p->ny % 4)
+            return fail(err, HSLB_EINVAL, "the learned force needs nx %% 32 == 0 and ny %% 4 == 0");
+        if (p->surr_check_every < 1) return fail(err, HSLB_EINVAL, "surr_check_every must be >= 1");
+        if (!(p->surr_tol > 0.0)) return fail(err, HSLB_EINVAL, "surr_tol must be > 0");
+    }
     const int sig = p->sigma >= 2 ? p->sigma : 2;
     const double fld = (double)p->nx * p->ny * (p->nz + 2.0 * sig);
     if (fld + 64 >= 2147483647.0) return fail(err, HSLB_EINVAL, "grid too large for 32-bit node indices");
     return HSLB_OK;
+}
+
+namespace hslb {
+int context_training_pair(hslb_ctx *ctx, uint16_t *x, float *target, cnn::Geo *g, int *wall_lo, int *wall_hi,
+                          int *sigma, std::string *msg);
 }
 
 extern "C" {
@@ -1364,6 +1660,42 @@ int hslb_checkpoint_load(hslb_ctx *ctx, const void *buf)
     CTX_CHECK(ctx);
     if (!buf) return fail(ctx->eng->err, HSLB_EINVAL, "null buffer");
     return ctx->eng->checkpoint_load(buf);
+}
+
+int hslb_surrogate_set_weights(hslb_ctx *ctx, const float *w, int64_t nw)
+{
+    CTX_CHECK(ctx);
+    if (!w) return fail(ctx->eng->err, HSLB_EINVAL, "null weights");
+    if (nw != cnn::NW) return fail(ctx->eng->err, HSLB_EINVAL, "expected %d weights, got %lld", cnn::NW, (long long)nw);
+    return ctx->eng->surr_set_weights(w);
+}
+
+int hslb_surrogate_get_weights(hslb_ctx *ctx, float *w, int64_t nw)
+{
+    CTX_CHECK(ctx);
+    if (!w) return fail(ctx->eng->err, HSLB_EINVAL, "null weights");
+    if (nw != cnn::NW) return fail(ctx->eng->err, HSLB_EINVAL, "expected %d weights, got %lld", cnn::NW, (long long)nw);
+    return ctx->eng->surr_get_weights(w);
+}
+
+int hslb_surrogate_set_mode(hslb_ctx *ctx, int32_t mode)
+{
+    CTX_CHECK(ctx);
+    return ctx->eng->surr_set_mode(mode);
+}
+
+int hslb_surrogate_stats(hslb_ctx *ctx, int64_t *checks, int64_t *fallback_steps, double *last_residual,
+                         double *max_residual)
+{
+    CTX_CHECK(ctx);
+    return ctx->eng->surr_stats(checks, fallback_steps, last_residual, max_residual);
+}
+
+int hslb_surrogate_force(hslb_ctx *ctx, double *F)
+{
+    CTX_CHECK(ctx);
+    if (!F) return fail(ctx->eng->err, HSLB_EINVAL, "null output");
+    return ctx->eng->surr_force(F);
 }
 
 int hslb_set_shift_period(hslb_ctx *ctx, int64_t every)
@@ -1517,3 +1849,14 @@ int hslb_copy_bandwidth(int64_t bytes, int32_t iters, double *gbps)
 }
 
 }  // extern "C"
+
+namespace hslb {
+int context_training_pair(hslb_ctx *ctx, uint16_t *x, float *target, cnn::Geo *g, int *wall_lo, int *wall_hi,
+                          int *sigma, std::string *msg)
+{
+    if (!ctx || !ctx->eng) return HSLB_EINVAL;
+    const int rc = ctx->eng->training_pair(x, target, g, wall_lo, wall_hi, sigma);
+    if (rc && msg) *msg = ctx->eng->err;
+    return rc;
+}
+}  // namespace hslb

@@ -1,0 +1,715 @@
+// Learned-force network on gfx950: 5x5x5 convolutions as implicit GEMMs on
+// the BF16 matrix cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation).
+//
+// MFMA operand layout (16x16x32): lane l holds A[m = l%16][k = 8(l/16) .. +8),
+// B[k = 8(l/16) .. +8][n = l%16], and accumulates D[m = 4(l/16) + j][n = l%16],
+// j = 0..3.  The 8 K-values of a lane are contiguous in K.
+//
+//  - Forward and input-gradient convolutions: M = 16 consecutive x-nodes of a
+//    row, N = output channels, K = (tap, input channel).  The 8 K-values of a
+//    lane are 8 channels of one node, a 16-byte load from channel-last bf16
+//    activations.  A wave computes 4 rows (y) x 16 nodes against both 16-column
+//    output halves; B comes pre-packed in lane order.
+//  - Weight gradients: K = nodes, so a lane's 8 K-values are 8 consecutive
+//    x-nodes of one channel (channel-major copies).  The x-shift of a tap is
+//    taken from aligned 16-byte chunks with 16-bit funnel shifts, wrapping at
+//    row ends (nx % 8 == 0 makes the chunks row-aligned).  Per-wave partial
+//    sums go to scratch and a second kernel reduces them in a fixed order.
+#include "hslb_cnn.hpp"
+#include "hslb_internal.hpp"
+
+#include <cmath>
+
+namespace hslb {
+namespace cnn {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((__vector_size__(16)));
+typedef float f32x4 __attribute__((__vector_size__(16)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// FP32 -> bf16, round to nearest, ties to even (finite inputs).
+__device__ __forceinline__ uint32_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+// FP64 -> bf16 directly: keep 8 significant bits of m in d = m 2^e, ties to even.
+__device__ __forceinline__ uint32_t d2bf(double d)
+{
+    int e;
+    const double m = frexp(d, &e);
+    const double r = rint(m * 256.0) * (1.0 / 256.0);
+    return __float_as_uint((float)ldexp(r, e)) >> 16;
+}
+
+__device__ __forceinline__ float bf2f(uint32_t h) { return __uint_as_float(h << 16); }
+
+// Phi(z) = erfc(-z / sqrt 2) / 2: accurate in relative terms also for z << 0,
+// where 1 + erf(z / sqrt 2) would cancel.
+__device__ __forceinline__ float phi_cdf(float z) { return 0.5f * erfcf(-z * 0.70710678118654752f); }
+
+__device__ __forceinline__ float gelu(float z) { return z * phi_cdf(z); }
+
+__device__ __forceinline__ float gelu_grad(float z)
+{
+    return phi_cdf(z) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+__device__ __forceinline__ bf16x8 as_bf(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+__device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// z of a tap read: -1 when it falls beyond a walled array.
+__device__ __forceinline__ int zsrc(const Geo &g, int z)
+{
+    if (g.zper) return wrapi(z, g.nz);
+    return (z < 0 || z >= g.nz) ? -1 : z;
+}
+
+// ------------------------------------------------------------- forward
+
+// A operand of K-step s for the node (xl, y, z) of this lane.
+template <int CIN>
+__device__ __forceinline__ u32x4 load_a(const Geo &g, const uint16_t *__restrict__ in, int s, int xl, int y, int z,
+                                        int lg)
+{
+    u32x4 v = {0u, 0u, 0u, 0u};
+    if constexpr (CIN == 32) {
+        const int dz = s / 25 - 2, dy = (s / 5) % 5 - 2, dx = s % 5 - 2;
+        const int zs = zsrc(g, z + dz);
+        if (zs >= 0) {
+            const int node = wrapi(xl + dx, g.nx) + g.nx * (wrapi(y + dy, g.ny) + g.ny * zs);
+            v = *(const u32x4 *)(in + (size_t)node * 32 + 8 * lg);
+        }
+    } else if constexpr (CIN == 4) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int t = 8 * s + 2 * lg + q;
+            if (t < NT) {
+                const int dz = t / 25 - 2, dy = (t / 5) % 5 - 2, dx = t % 5 - 2;
+                const int zs = zsrc(g, z + dz);
+                if (zs >= 0) {
+                    const int node = wrapi(xl + dx, g.nx) + g.nx * (wrapi(y + dy, g.ny) + g.ny * zs);
+                    const u32x2 w = *(const u32x2 *)(in + (size_t)node * 4);
+                    v[2 * q] = w[0];
+                    v[2 * q + 1] = w[1];
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int t = 32 * s + 8 * lg + e;
+            uint32_t h = 0;
+            if (t < NT) {
+                const int dz = t / 25 - 2, dy = (t / 5) % 5 - 2, dx = t % 5 - 2;
+                const int zs = zsrc(g, z + dz);
+                if (zs >= 0) h = in[wrapi(xl + dx, g.nx) + g.nx * (wrapi(y + dy, g.ny) + g.ny * zs)];
+            }
+            v[e >> 1] |= h << (16 * (e & 1));
+        }
+    }
+    return v;
+}
+
+constexpr int ROWS = 4;
+
+template <int CIN, int NH, int EPI>
+__global__ __launch_bounds__(256) void k_conv_fwd(FwdArgs a)
+{
+    constexpr int KS = CIN == 32 ? NT : (CIN == 4 ? 16 : 4);
+    const Geo g = a.g;
+    const int lane = threadIdx.x & 63;
+    const int wave = xcd_block((int)blockIdx.x, (int)gridDim.x) * 4 + (int)(threadIdx.x >> 6);
+    const int nxc = g.nx >> 4, nyq = g.ny >> 2;
+    if (wave >= nxc * nyq * g.nz) return;  // whole waves only: no barriers below
+    const int z = wave / (nxc * nyq);
+    const int rem = wave - z * nxc * nyq;
+    const int yq = rem / nxc;
+    const int x0 = (rem - yq * nxc) * 16, y0 = yq * ROWS;
+    const int li = lane & 15, lg = lane >> 4;
+
+    f32x4 acc[ROWS][NH];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+        for (int h = 0; h < NH; ++h) acc[r][h] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+    for (int s = 0; s < KS; ++s) {
+        bf16x8 b[NH];
+#pragma unroll
+        for (int h = 0; h < NH; ++h) b[h] = as_bf(*(const u32x4 *)(a.wp + ((size_t)(s * NH + h) * 64 + lane) * 8));
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const bf16x8 av = as_bf(load_a<CIN>(g, a.in, s, x0 + li, y0 + r, z, lg));
+#pragma unroll
+            for (int h = 0; h < NH; ++h) acc[r][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b[h], acc[r][h], 0, 0, 0);
+        }
+    }
+
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int rowbase = g.nx * ((y0 + r) + g.ny * z);
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            const int c = 16 * h + li;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int node = rowbase + x0 + 4 * lg + j;
+                const float v = acc[r][h][j];
+                if constexpr (EPI == EPI_GELU) {
+                    const float zz = v + a.bias[c];
+                    const uint32_t bits = f2bf(gelu(zz));
+                    if (a.out_cl) a.out_cl[(size_t)node * 32 + c] = (uint16_t)bits;
+                    if (a.out_cm) a.out_cm[(size_t)c * g.N + node] = (uint16_t)bits;
+                    if (a.out_f32) a.out_f32[(size_t)node * 32 + c] = zz;
+                } else if constexpr (EPI == EPI_OUT) {
+                    if (c < CO) a.out_f32[(size_t)c * g.N + node] = v + a.bias[c];
+                } else {
+                    const uint32_t bits = f2bf(v * gelu_grad(a.zsave[(size_t)node * 32 + c]));
+                    if (a.out_f32) a.out_f32[(size_t)node * 32 + c] = v;
+                    if (a.out_cl) a.out_cl[(size_t)node * 32 + c] = (uint16_t)bits;
+                    if (a.out_cm) a.out_cm[(size_t)c * g.N + node] = (uint16_t)bits;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------- weight gradients
+
+// 8 consecutive elements starting at element `sh` (in -2..2) of the chunk
+// `cur`, continuing into `prv` / `nxt`.
+__device__ __forceinline__ u32x4 shifted(const u32x4 &prv, const u32x4 &cur, const u32x4 &nxt, int sh)
+{
+    u32x4 o;
+    if (sh == 0) return cur;
+    if (sh == 2) {
+        o[0] = cur[1];
+        o[1] = cur[2];
+        o[2] = cur[3];
+        o[3] = nxt[0];
+    } else if (sh == -2) {
+        o[0] = prv[3];
+        o[1] = cur[0];
+        o[2] = cur[1];
+        o[3] = cur[2];
+    } else if (sh == 1) {
+        o[0] = (cur[0] >> 16) | (cur[1] << 16);
+        o[1] = (cur[1] >> 16) | (cur[2] << 16);
+        o[2] = (cur[2] >> 16) | (cur[3] << 16);
+        o[3] = (cur[3] >> 16) | (nxt[0] << 16);
+    } else {
+        o[0] = (prv[3] >> 16) | (cur[0] << 16);
+        o[1] = (cur[0] >> 16) | (cur[1] << 16);
+        o[2] = (cur[1] >> 16) | (cur[2] << 16);
+        o[3] = (cur[2] >> 16) | (cur[3] << 16);
+    }
+    return o;
+}
+
+// rows (y, z) of the lattice split into chunks of rpw rows
+struct RowSplit {
+    int rows, rpw, chunks;
+};
+
+__host__ __device__ inline RowSplit row_split(const Geo &g, int max_chunks)
+{
+    RowSplit r;
+    r.rows = g.ny * g.nz;
+    const int c = r.rows < max_chunks ? r.rows : max_chunks;
+    r.rpw = (r.rows + c - 1) / c;
+    r.chunks = (r.rows + r.rpw - 1) / r.rpw;
+    return r;
+}
+
+constexpr int WG_CHUNKS_CH = 64;    // layers 2, 3: waves = 25 tap rows x chunks
+constexpr int WG_CHUNKS_TAP = 1024; // layer 1: waves = chunks
+
+// Layers 2 and 3: M = input channel (2 x 16), N = output channel (NB x 16),
+// K = nodes.  Wave = (tap row (dz, dy), chunk of lattice rows); the 5 dx taps
+// share the three chunks loaded per channel.
+// partial[wave][5][32][16 NB]
+template <int NB>
+__global__ __launch_bounds__(256) void k_wgrad_ch(Geo g, RowSplit rs, int cout, const uint16_t *__restrict__ actT,
+                                                  const uint16_t *__restrict__ gT, float *__restrict__ partial)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (wave >= 25 * rs.chunks) return;
+    const int gq = wave % 25, chunk = wave / 25;
+    const int dz = gq / 5 - 2, dy = gq % 5 - 2;
+    const int li = lane & 15, lg = lane >> 4;
+    f32x4 acc[5][2][NB];
+#pragma unroll
+    for (int d = 0; d < 5; ++d)
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[d][mi][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+    const int r0 = chunk * rs.rpw, r1 = min(rs.rows, r0 + rs.rpw);
+    for (int row = r0; row < r1; ++row) {
+        const int y = row % g.ny, z = row / g.ny;
+        const int zs = zsrc(g, z + dz);
+        if (zs < 0) continue;  // the tap reads beyond the walls: zero
+        const size_t srow = (size_t)g.nx * (wrapi(y + dy, g.ny) + g.ny * zs);
+        const size_t orow = (size_t)g.nx * (y + g.ny * z);
+        for (int x0 = 0; x0 < g.nx; x0 += 32) {
+            const int xc = x0 + 8 * lg;
+            bf16x8 bv[NB];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int co = 16 * nb + li;
+                u32x4 w = {0u, 0u, 0u, 0u};
+                if (co < cout) w = *(const u32x4 *)(gT + (size_t)co * g.N + orow + xc);
+                bv[nb] = as_bf(w);
+            }
+            const int xp = xc == 0 ? g.nx - 8 : xc - 8, xn = xc + 8 == g.nx ? 0 : xc + 8;
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi) {
+                const uint16_t *base = actT + (size_t)(16 * mi + li) * g.N + srow;
+                const u32x4 prv = *(const u32x4 *)(base + xp);
+                const u32x4 cur = *(const u32x4 *)(base + xc);
+                const u32x4 nxt = *(const u32x4 *)(base + xn);
+#pragma unroll
+                for (int d = 0; d < 5; ++d) {
+                    const bf16x8 av = as_bf(shifted(prv, cur, nxt, d - 2));
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+                        acc[d][mi][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nb], acc[d][mi][nb], 0, 0, 0);
+                }
+            }
+        }
+    }
+    float *out = partial + (size_t)wave * 5 * 32 * 16 * NB;
+#pragma unroll
+    for (int d = 0; d < 5; ++d)
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int ci = 16 * mi + 4 * lg + j, co = 16 * nb + li;
+                    out[((size_t)d * 32 + ci) * 16 * NB + co] = acc[d][mi][nb][j];
+                }
+}
+
+// dW[co][ci][t] = sum over chunks, t = gq * 5 + d
+__global__ __launch_bounds__(256) void k_wgrad_ch_reduce(int chunks, int nb16, int cout, const float *__restrict__ partial,
+                                                         float *__restrict__ dW)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= cout * 32 * NT) return;
+    const int t = i % NT, ci = (i / NT) % 32, co = i / (NT * 32);
+    const int gq = t / 5, d = t % 5;
+    double s = 0.0;
+    for (int c = 0; c < chunks; ++c)
+        s += partial[(((size_t)(c * 25 + gq) * 5 + d) * 32 + ci) * nb16 + co];
+    dW[i] = (float)s;
+}
+
+// Layer 1: M = tap (8 x 16, taps >= 125 zero), N = output channel (2 x 16),
+// K = nodes.  Each lane's tap has its own shift.  partial[wave][128][32]
+__global__ __launch_bounds__(256) void k_wgrad_tap(Geo g, RowSplit rs, const uint16_t *__restrict__ x,
+                                                   const uint16_t *__restrict__ gT, float *__restrict__ partial)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (wave >= rs.chunks) return;
+    const int li = lane & 15, lg = lane >> 4;
+    f32x4 acc[8][2];
+#pragma unroll
+    for (int mi = 0; mi < 8; ++mi)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) acc[mi][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+    const int r0 = wave * rs.rpw, r1 = min(rs.rows, r0 + rs.rpw);
+    for (int row = r0; row < r1; ++row) {
+        const int y = row % g.ny, z = row / g.ny;
+        const size_t orow = (size_t)g.nx * (y + g.ny * z);
+        for (int x0 = 0; x0 < g.nx; x0 += 32) {
+            const int xc = x0 + 8 * lg;
+            bf16x8 bv[2];
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) bv[nb] = as_bf(*(const u32x4 *)(gT + (size_t)(16 * nb + li) * g.N + orow + xc));
+            const int xp = xc == 0 ? g.nx - 8 : xc - 8, xn = xc + 8 == g.nx ? 0 : xc + 8;
+#pragma unroll
+            for (int mi = 0; mi < 8; ++mi) {
+                const int t = 16 * mi + li;
+                u32x4 v = {0u, 0u, 0u, 0u};
+                if (t < NT) {
+                    const int dz = t / 25 - 2, dy = (t / 5) % 5 - 2, dx = t % 5 - 2;
+                    const int zs = zsrc(g, z + dz);
+                    if (zs >= 0) {
+                        const uint16_t *base = x + (size_t)g.nx * (wrapi(y + dy, g.ny) + g.ny * zs);
+                        const u32x4 cur = *(const u32x4 *)(base + xc);
+                        const u32x4 prv = dx < 0 ? *(const u32x4 *)(base + xp) : cur;
+                        const u32x4 nxt = dx > 0 ? *(const u32x4 *)(base + xn) : cur;
+                        v = shifted(prv, cur, nxt, dx);
+                    }
+                }
+                const bf16x8 av = as_bf(v);
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb)
+                    acc[mi][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nb], acc[mi][nb], 0, 0, 0);
+            }
+        }
+    }
+    float *out = partial + (size_t)wave * 128 * 32;
+#pragma unroll
+    for (int mi = 0; mi < 8; ++mi)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) out[(16 * mi + 4 * lg + j) * 32 + 16 * nb + li] = acc[mi][nb][j];
+}
+
+// dW1[co][0][t]
+__global__ __launch_bounds__(256) void k_wgrad_tap_reduce(int chunks, const float *__restrict__ partial,
+                                                          float *__restrict__ dW)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= 32 * NT) return;
+    const int t = i % NT, co = i / NT;
+    double s = 0.0;
+    for (int c = 0; c < chunks; ++c) s += partial[((size_t)c * 128 + t) * 32 + co];
+    dW[i] = (float)s;
+}
+
+// --------------------------------------------------------- reductions
+
+__device__ __forceinline__ double block_sum(double v, double *red)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const double t = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return t;
+}
+
+constexpr int COLSUM_CHUNKS = 64;
+
+// partial[c][chunk]
+__global__ __launch_bounds__(256) void k_colsum(Geo g, const uint16_t *__restrict__ gT, float *__restrict__ partial)
+{
+    __shared__ double red[4];
+    const int c = blockIdx.y, chunk = blockIdx.x;
+    const int per = (g.N + COLSUM_CHUNKS - 1) / COLSUM_CHUNKS;
+    const int n0 = chunk * per, n1 = min(g.N, n0 + per);
+    double s = 0.0;
+    for (int n = n0 + (int)threadIdx.x; n < n1; n += 256) s += (double)bf2f(gT[(size_t)c * g.N + n]);
+    const double t = block_sum(s, red);
+    if (threadIdx.x == 0) partial[c * COLSUM_CHUNKS + chunk] = (float)t;
+}
+
+__global__ void k_colsum_reduce(int nch, const float *__restrict__ partial, float *__restrict__ db)
+{
+    const int c = threadIdx.x;
+    if (c >= nch) return;
+    double s = 0.0;
+    for (int k = 0; k < COLSUM_CHUNKS; ++k) s += (double)partial[c * COLSUM_CHUNKS + k];
+    db[c] = (float)s;
+}
+
+// ------------------------------------------------------------ packing
+
+__global__ __launch_bounds__(256) void k_pack(int kind, const float *__restrict__ w, uint16_t *__restrict__ out, int total)
+{
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    const int e = idx & 7, lane = (idx >> 3) & 63, rest = idx >> 9;
+    const int li = lane & 15, lg = lane >> 4;
+    const int H = kind == PK_F3 ? 1 : 2;
+    const int h = rest % H, s = rest / H;
+    const int col = 16 * h + li;
+    float v = 0.f;
+    if (kind == PK_F1) {
+        const int t = 32 * s + 8 * lg + e;
+        if (t < NT) v = w[OW1 + col * NT + t];
+    } else if (kind == PK_F2) {
+        v = w[OW2 + (col * CH + 8 * lg + e) * NT + s];
+    } else if (kind == PK_F3) {
+        if (li < CO) v = w[OW3 + (li * CH + 8 * lg + e) * NT + s];
+    } else if (kind == PK_D2) {
+        v = w[OW2 + ((8 * lg + e) * CH + col) * NT + (NT - 1 - s)];
+    } else {
+        const int t = 8 * s + 2 * lg + (e >> 2), cf = e & 3;
+        if (t < NT && cf < CO) v = w[OW3 + (cf * CH + col) * NT + (NT - 1 - t)];
+    }
+    out[idx] = (uint16_t)f2bf(v);
+}
+
+// --------------------------------------------------------------- misc
+
+template <typename TM>
+__global__ __launch_bounds__(256) void k_eta_input(Geo g, int hz, double eta_pref, const TM *__restrict__ n,
+                                                   uint16_t *__restrict__ x)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= g.N) return;
+    const int plane = g.nx * g.ny;
+    x[i] = (uint16_t)d2bf(eta_pref * (double)n[i + hz * plane]);
+}
+
+__global__ __launch_bounds__(256) void k_to_bf16(const double *__restrict__ v, size_t count, uint16_t *__restrict__ out)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < count) out[i] = (uint16_t)d2bf(v[i]);
+}
+
+__global__ __launch_bounds__(256) void k_loss(Geo g, int wall_lo, int wall_hi, float scale, const float *__restrict__ out,
+                                              const float *__restrict__ target, uint16_t *__restrict__ d_cl,
+                                              uint16_t *__restrict__ d_cm, double *__restrict__ sq_partial)
+{
+    __shared__ double red[4];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    double sq = 0.0;
+    if (i < g.N) {
+        const int z = i / (g.nx * g.ny);
+        const bool fl = z >= wall_lo && z < g.nz - wall_hi;
+#pragma unroll
+        for (int c = 0; c < CO; ++c) {
+            const float d = fl ? out[(size_t)c * g.N + i] - target[(size_t)c * g.N + i] : 0.f;
+            sq += (double)d * (double)d;
+            const uint16_t b = (uint16_t)f2bf(d * scale);
+            d_cl[(size_t)i * 4 + c] = b;
+            d_cm[(size_t)c * g.N + i] = b;
+        }
+        d_cl[(size_t)i * 4 + 3] = 0;
+    }
+    const double t = block_sum(sq, red);
+    if (threadIdx.x == 0) sq_partial[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void k_adam(int n, float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                                              const float *__restrict__ g, float c1, float c2, float lr)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = 0.9f * m[i] + 0.1f * gi;
+    const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + 1e-8f);
+}
+
+__global__ __launch_bounds__(256) void k_judge(Geo g, int wall_lo, int wall_hi, double fs, const float *__restrict__ fhat,
+                                               const double *__restrict__ c1, float *__restrict__ delta,
+                                               double *__restrict__ partial)
+{
+    __shared__ double red[4];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    double a = 0.0, b = 0.0;
+    if (i < g.N) {
+        const int z = i / (g.nx * g.ny);
+        const bool fl = z >= wall_lo && z < g.nz - wall_hi;
+#pragma unroll
+        for (int c = 0; c < CO; ++c) {
+            const double e = c1[(size_t)c * g.N + i];
+            const double f = fhat ? fs * (double)fhat[(size_t)c * g.N + i] : 0.0;
+            const double d = fl ? e - f : 0.0;
+            if (fl) {
+                a += d * d;
+                b += e * e;
+            }
+            if (delta) delta[(size_t)c * g.N + i] = (float)d;
+        }
+    }
+    const double ta = block_sum(a, red);
+    const double tb = block_sum(b, red);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = ta;
+        partial[2 * blockIdx.x + 1] = tb;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_f32_to_f64(const float *__restrict__ in, double s, size_t count,
+                                                    double *__restrict__ out)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < count) out[i] = s * (double)in[i];
+}
+
+__global__ __launch_bounds__(256) void k_f64_to_f32(const double *__restrict__ in, double s, size_t count,
+                                                    float *__restrict__ out)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < count) out[i] = (float)(s * in[i]);
+}
+
+__global__ __launch_bounds__(256) void k_cm_to_bf16(const float *__restrict__ in, int c, int cp, int N,
+                                                    uint16_t *__restrict__ out_cl, uint16_t *__restrict__ out_cm)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (size_t)cp * N) return;
+    const int n = (int)(i / cp), k = (int)(i % cp);
+    const uint16_t b = k < c ? (uint16_t)f2bf(in[(size_t)k * N + n]) : (uint16_t)0;
+    if (out_cl) out_cl[i] = b;
+    if (out_cm && k < c) out_cm[(size_t)k * N + n] = b;
+}
+
+__global__ __launch_bounds__(256) void k_cl_bf16_to_cm(const uint16_t *__restrict__ in, int c, int N, float *__restrict__ out)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (size_t)c * N) return;
+    const int k = (int)(i / N), n = (int)(i % N);
+    out[i] = bf2f(in[(size_t)n * c + k]);
+}
+
+__global__ __launch_bounds__(256) void k_cl_f32_to_cm(const float *__restrict__ in, int c, int N, float *__restrict__ out)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (size_t)c * N) return;
+    const int k = (int)(i / N), n = (int)(i % N);
+    out[i] = in[(size_t)n * c + k];
+}
+
+inline unsigned nblocks(size_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+hipError_t launch_conv_fwd(hipStream_t s, int cin, int cout, int epi, const FwdArgs &a)
+{
+    const int waves = (a.g.nx / 16) * (a.g.ny / ROWS) * a.g.nz;
+    const dim3 grid((waves + 3) / 4), blk(256);
+    const int nh = cout == 32 ? 2 : 1;
+#define HSLB_CONV(CI, NH_, EP) \
+    if (cin == CI && nh == NH_ && epi == EP) { hipLaunchKernelGGL((k_conv_fwd<CI, NH_, EP>), grid, blk, 0, s, a); return hipGetLastError(); }
+    HSLB_CONV(1, 2, EPI_GELU)
+    HSLB_CONV(32, 2, EPI_GELU)
+    HSLB_CONV(32, 1, EPI_OUT)
+    HSLB_CONV(32, 2, EPI_DGELU)
+    HSLB_CONV(4, 2, EPI_DGELU)
+#undef HSLB_CONV
+    return hipErrorInvalidValue;
+}
+
+size_t wgrad_partial_floats(const Geo &g, int layer)
+{
+    if (layer == 1) return (size_t)row_split(g, WG_CHUNKS_TAP).chunks * 128 * 32;
+    const int nb = layer == 2 ? 2 : 1;
+    return (size_t)25 * row_split(g, WG_CHUNKS_CH).chunks * 5 * 32 * 16 * nb;
+}
+
+hipError_t launch_wgrad(hipStream_t s, int layer, const Geo &g, const uint16_t *src, const uint16_t *gT,
+                        float *partial, float *dW)
+{
+    if (layer == 1) {
+        const RowSplit rs = row_split(g, WG_CHUNKS_TAP);
+        hipLaunchKernelGGL(k_wgrad_tap, dim3((rs.chunks + 3) / 4), dim3(256), 0, s, g, rs, src, gT, partial);
+        hipLaunchKernelGGL(k_wgrad_tap_reduce, dim3(nblocks(32 * NT)), dim3(256), 0, s, rs.chunks, partial, dW);
+        return hipGetLastError();
+    }
+    const RowSplit rs = row_split(g, WG_CHUNKS_CH);
+    const unsigned grid = (unsigned)((25 * rs.chunks + 3) / 4);
+    if (layer == 2) {
+        hipLaunchKernelGGL(k_wgrad_ch<2>, dim3(grid), dim3(256), 0, s, g, rs, CH, src, gT, partial);
+        hipLaunchKernelGGL(k_wgrad_ch_reduce, dim3(nblocks(CH * 32 * NT)), dim3(256), 0, s, rs.chunks, 32, CH, partial, dW);
+    } else {
+        hipLaunchKernelGGL(k_wgrad_ch<1>, dim3(grid), dim3(256), 0, s, g, rs, CO, src, gT, partial);
+        hipLaunchKernelGGL(k_wgrad_ch_reduce, dim3(nblocks(CO * 32 * NT)), dim3(256), 0, s, rs.chunks, 16, CO, partial, dW);
+    }
+    return hipGetLastError();
+}
+
+size_t colsum_partial_floats(const Geo &, int nch) { return (size_t)nch * COLSUM_CHUNKS; }
+
+hipError_t launch_colsum(hipStream_t s, const Geo &g, int nch, const uint16_t *gT, float *partial, float *db)
+{
+    hipLaunchKernelGGL(k_colsum, dim3(COLSUM_CHUNKS, nch), dim3(256), 0, s, g, gT, partial);
+    hipLaunchKernelGGL(k_colsum_reduce, dim3(1), dim3(64), 0, s, nch, partial, db);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(hipStream_t s, int kind, const float *w, uint16_t *out)
+{
+    const int total = pack_elems(kind);
+    hipLaunchKernelGGL(k_pack, dim3(nblocks(total)), dim3(256), 0, s, kind, w, out, total);
+    return hipGetLastError();
+}
+
+template <typename TM>
+hipError_t launch_eta_input(hipStream_t s, const Geo &g, int hz, double eta_pref, const TM *n, uint16_t *x)
+{
+    hipLaunchKernelGGL(k_eta_input<TM>, dim3(nblocks(g.N)), dim3(256), 0, s, g, hz, eta_pref, n, x);
+    return hipGetLastError();
+}
+template hipError_t launch_eta_input<float>(hipStream_t, const Geo &, int, double, const float *, uint16_t *);
+template hipError_t launch_eta_input<double>(hipStream_t, const Geo &, int, double, const double *, uint16_t *);
+
+hipError_t launch_to_bf16(hipStream_t s, const double *v, size_t count, uint16_t *out)
+{
+    hipLaunchKernelGGL(k_to_bf16, dim3(nblocks(count)), dim3(256), 0, s, v, count, out);
+    return hipGetLastError();
+}
+
+unsigned loss_blocks(const Geo &g) { return nblocks(g.N); }
+
+hipError_t launch_loss(hipStream_t s, const Geo &g, int wall_lo, int wall_hi, const float *out, const float *target,
+                       uint16_t *d_cl, uint16_t *d_cm, double *sq_partial)
+{
+    const long nf = (long)g.nx * g.ny * (g.nz - wall_lo - wall_hi);
+    const float scale = (float)(2.0 / (3.0 * (double)nf));
+    hipLaunchKernelGGL(k_loss, dim3(loss_blocks(g)), dim3(256), 0, s, g, wall_lo, wall_hi, scale, out, target, d_cl, d_cm,
+                       sq_partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(hipStream_t s, int n, float *w, float *m, float *v, const float *g, int t, float lr)
+{
+    const float c1 = (float)(1.0 / (1.0 - std::pow(0.9, t)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow(0.999, t)));
+    hipLaunchKernelGGL(k_adam, dim3(nblocks(n)), dim3(256), 0, s, n, w, m, v, g, c1, c2, lr);
+    return hipGetLastError();
+}
+
+unsigned judge_blocks(const Geo &g) { return nblocks(g.N); }
+
+hipError_t launch_cm_to_bf16(hipStream_t s, const float *in, int c, int cp, int N, uint16_t *out_cl, uint16_t *out_cm)
+{
+    hipLaunchKernelGGL(k_cm_to_bf16, dim3(nblocks((size_t)cp * N)), dim3(256), 0, s, in, c, cp, N, out_cl, out_cm);
+    return hipGetLastError();
+}
+
+hipError_t launch_cl_bf16_to_cm(hipStream_t s, const uint16_t *in, int c, int N, float *out)
+{
+    hipLaunchKernelGGL(k_cl_bf16_to_cm, dim3(nblocks((size_t)c * N)), dim3(256), 0, s, in, c, N, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_cl_f32_to_cm(hipStream_t s, const float *in, int c, int N, float *out)
+{
+    hipLaunchKernelGGL(k_cl_f32_to_cm, dim3(nblocks((size_t)c * N)), dim3(256), 0, s, in, c, N, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_f32_to_f64(hipStream_t st, const float *in, double s, size_t count, double *out)
+{
+    hipLaunchKernelGGL(k_f32_to_f64, dim3(nblocks(count)), dim3(256), 0, st, in, s, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_f64_to_f32(hipStream_t st, const double *in, double s, size_t count, float *out)
+{
+    hipLaunchKernelGGL(k_f64_to_f32, dim3(nblocks(count)), dim3(256), 0, st, in, s, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_judge(hipStream_t s, const Geo &g, int wall_lo, int wall_hi, double fs, const float *fhat,
+                        const double *c1, float *delta, double *partial)
+{
+    hipLaunchKernelGGL(k_judge, dim3(judge_blocks(g)), dim3(256), 0, s, g, wall_lo, wall_hi, fs, fhat, c1, delta, partial);
+    return hipGetLastError();
+}
+
+}  // namespace cnn
+}  // namespace hslb

@@ -10,6 +10,17 @@ namespace hslb {
 constexpr int NQ = 19;
 constexpr int NGSLOT = 7;  // contact-value sub-lattices: bits x=1, y=2, z=4 (0..6)
 
+// Workgroups are handed to the 8 XCDs round-robin by linear block index.  This
+// bijection of [0, nb) gives XCD x a contiguous run of logical blocks, so that
+// a stencil's neighbouring planes stay in that XCD's L2 instead of being
+// fetched by all eight.
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    const int q = nb >> 3, rm = nb & 7;
+    const int x = b & 7, slot = b >> 3;
+    return x * q + (x < rm ? x : rm) + slot;
+}
+
 // Geometry of one lattice as the kernels see it.
 //  - populations: [19][pop_stride], node = x + nx*(y + ny*z), z in [0, nz)
 //  - padded fields (n, j, eta_bar, G): [.. ][fld_stride] with hz ghost/zero
@@ -40,6 +51,11 @@ struct StepConst {
     double alpha[4];    // bilinear corner weights: (l,l), (l,l+1), (l+1,l), (l+1,l+1)
     int g2_model;
     int hs_on;          // hard-sphere term on
+    // External interaction force (collide without the shell sum):
+    // C1 = fscale * fext + fdelta, both [3][N] FP32, either may be null.
+    const float *fext;
+    const float *fdelta;
+    double fscale;
 };
 
 template <typename TM>

@@ -467,6 +467,18 @@ __device__ __forceinline__ void node_force(const Fields<TM> &F, const LatticeDev
 #else
     using TC = TM;
 #endif
+    if constexpr (SIG == 0) {
+        // interaction force supplied per node (learned force and its correction)
+        const int id = x + L.nx * (y + L.ny * z);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double c1 = 0.0;
+            if (sc.fext) c1 += sc.fscale * (double)sc.fext[(size_t)a * L.N + id];
+            if (sc.fdelta) c1 += (double)sc.fdelta[(size_t)a * L.N + id];
+            Fo[a] = c1 + n * sc.g[a];
+        }
+        return;
+    } else {
     TC S[3] = {TC(0), TC(0), TC(0)};
     if (sc.hs_on) {
         NodeCtx<TC> c;
@@ -484,6 +496,7 @@ __device__ __forceinline__ void node_force(const Fields<TM> &F, const LatticeDev
     Fo[0] = pn * (double)S[0] + n * sc.g[0];
     Fo[1] = pn * (double)S[1] + n * sc.g[1];
     Fo[2] = pn * (double)S[2] + n * sc.g[2];
+    }
 }
 
 // ------------------------------------------------- collide and stream
@@ -541,17 +554,6 @@ __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &
         else
             fout[(size_t)i * L.pop_stride + xt + L.nx * (yt + L.ny * zt)] = (TF)(fp - layer_ref(sc.nref_w, zt)[i]);
     }
-}
-
-// Workgroups are handed to the 8 XCDs round-robin by linear block index.  This
-// bijection gives XCD x a contiguous run of logical blocks (hence of layers),
-// so the moment-field planes a layer's shell sum reads stay in that XCD's L2
-// instead of being fetched by all eight.
-__device__ __forceinline__ int xcd_block(int b, int nb)
-{
-    const int q = nb >> 3, rm = nb & 7;
-    const int x = b & 7, slot = b >> 3;
-    return x * q + (x < rm ? x : rm) + slot;
 }
 
 // 1-D grid over (layer, chunk of 256 nodes of the layer): z is uniform over a
@@ -951,6 +953,7 @@ hipError_t launch_collide(hipStream_t s, const LatticeDev &L, int sigma, const S
     const int cpp = (int)blocks_for(L.plane);
     const dim3 g(cpp * layers), b(256);
     switch (sigma) {
+    case 0: hipLaunchKernelGGL((k_collide<0, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
     case 2: hipLaunchKernelGGL((k_collide<2, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
     case 3: hipLaunchKernelGGL((k_collide<3, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
     case 4: hipLaunchKernelGGL((k_collide<4, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;

@@ -32,6 +32,12 @@ HSLB_G2_CS = 1
 HSLB_FORCE_EXACT = 0
 HSLB_FORCE_SURROGATE = 1
 HSLB_FORCE_OFF = 2
+HSLB_SURR_CORRECTED = 0
+HSLB_SURR_PLAIN = 1
+HSLB_SURR_FROZEN = 2
+HSLB_CNN_NWEIGHTS = 144067
+(HSLB_CNN_FWD1, HSLB_CNN_FWD2, HSLB_CNN_FWD3, HSLB_CNN_DX3, HSLB_CNN_DX2, HSLB_CNN_DW1,
+ HSLB_CNN_DW2, HSLB_CNN_DW3) = range(8)
 
 # Every exported entry point of include/hslb.h.
 EXPORTS = (
@@ -43,6 +49,12 @@ EXPORTS = (
     "hslb_get_timings", "hslb_copy_bandwidth",
     "hslb_batch_create", "hslb_batch_init", "hslb_batch_profiles", "hslb_batch_finite",
     "hslb_batch_set_config", "hslb_batch_autotune",
+    "hslb_surrogate_set_weights", "hslb_surrogate_get_weights", "hslb_surrogate_set_mode",
+    "hslb_surrogate_stats", "hslb_surrogate_force",
+    "hslb_trainer_create", "hslb_trainer_destroy", "hslb_trainer_last_error",
+    "hslb_trainer_add_snapshot", "hslb_trainer_add_snapshot_host", "hslb_trainer_count",
+    "hslb_trainer_set_weights", "hslb_trainer_get_weights", "hslb_trainer_eval",
+    "hslb_trainer_grad", "hslb_trainer_step", "hslb_cnn_op",
 )
 
 
@@ -69,6 +81,7 @@ class HslbError(RuntimeError):
 _lib = None
 _P = ctypes.POINTER
 _dp = _P(ctypes.c_double)
+_fp = _P(ctypes.c_float)
 _vp = ctypes.c_void_p
 
 
@@ -115,6 +128,24 @@ def load(path: Optional[str] = None):
         "hslb_batch_set_config": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
         "hslb_batch_autotune": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_int32), _dp,
                                                ctypes.c_int32]),
+        "hslb_surrogate_set_weights": (ctypes.c_int, [_vp, _fp, ctypes.c_int64]),
+        "hslb_surrogate_get_weights": (ctypes.c_int, [_vp, _fp, ctypes.c_int64]),
+        "hslb_surrogate_set_mode": (ctypes.c_int, [_vp, ctypes.c_int32]),
+        "hslb_surrogate_stats": (ctypes.c_int, [_vp, _P(ctypes.c_int64), _P(ctypes.c_int64), _dp, _dp]),
+        "hslb_surrogate_force": (ctypes.c_int, [_vp, _dp]),
+        "hslb_trainer_create": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, _P(_vp)]),
+        "hslb_trainer_destroy": (None, [_vp]),
+        "hslb_trainer_last_error": (ctypes.c_char_p, [_vp]),
+        "hslb_trainer_add_snapshot": (ctypes.c_int, [_vp, _vp, _P(ctypes.c_int32)]),
+        "hslb_trainer_add_snapshot_host": (ctypes.c_int, [_vp] + [ctypes.c_int32] * 5 +
+                                           [_dp, _dp, _P(ctypes.c_int32)]),
+        "hslb_trainer_count": (ctypes.c_int, [_vp, _P(ctypes.c_int32)]),
+        "hslb_trainer_set_weights": (ctypes.c_int, [_vp, _fp, ctypes.c_int64]),
+        "hslb_trainer_get_weights": (ctypes.c_int, [_vp, _fp, ctypes.c_int64]),
+        "hslb_trainer_eval": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, _fp]),
+        "hslb_trainer_grad": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, _fp]),
+        "hslb_trainer_step": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_double, _dp]),
+        "hslb_cnn_op": (ctypes.c_int, [ctypes.c_int32] * 5 + [_fp, _fp, _fp, _fp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -126,6 +157,14 @@ def load(path: Optional[str] = None):
 
 def _d(a: Optional[np.ndarray]):
     return None if a is None else a.ctypes.data_as(_dp)
+
+
+def _f(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(_fp)
+
+
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float32)
 
 
 def _chk(ctx, rc: int):
@@ -295,6 +334,119 @@ def hslb_batch_autotune(ctx, steps: int):
     return choice.value, us
 
 
+def hslb_surrogate_set_weights(ctx, w: np.ndarray):
+    w = _f32(w).ravel()
+    _chk(ctx, load().hslb_surrogate_set_weights(ctx, _f(w), w.size))
+
+
+def hslb_surrogate_get_weights(ctx) -> np.ndarray:
+    w = np.zeros(HSLB_CNN_NWEIGHTS, dtype=np.float32)
+    _chk(ctx, load().hslb_surrogate_get_weights(ctx, _f(w), w.size))
+    return w
+
+
+def hslb_surrogate_set_mode(ctx, mode: int):
+    _chk(ctx, load().hslb_surrogate_set_mode(ctx, int(mode)))
+
+
+def hslb_surrogate_stats(ctx):
+    """(checks, exact fallback steps, last residual, largest residual)."""
+    c, f = ctypes.c_int64(), ctypes.c_int64()
+    r, m = ctypes.c_double(), ctypes.c_double()
+    _chk(ctx, load().hslb_surrogate_stats(ctx, ctypes.byref(c), ctypes.byref(f), ctypes.byref(r),
+                                          ctypes.byref(m)))
+    return c.value, f.value, r.value, m.value
+
+
+def hslb_surrogate_force(ctx, F: np.ndarray):
+    _chk(ctx, load().hslb_surrogate_force(ctx, _d(F)))
+
+
+def _tchk(tr, rc: int):
+    if rc != HSLB_OK:
+        raise HslbError(rc, load().hslb_trainer_last_error(tr).decode())
+
+
+def hslb_trainer_create(capacity_nodes: int, max_snapshot_nodes: int):
+    tr = _vp()
+    _tchk(None, load().hslb_trainer_create(int(capacity_nodes), int(max_snapshot_nodes), ctypes.byref(tr)))
+    return tr
+
+
+def hslb_trainer_destroy(tr):
+    load().hslb_trainer_destroy(tr)
+
+
+def hslb_trainer_last_error(tr) -> str:
+    return load().hslb_trainer_last_error(tr).decode()
+
+
+def hslb_trainer_add_snapshot(tr, ctx) -> int:
+    k = ctypes.c_int32()
+    rc = load().hslb_trainer_add_snapshot(tr, ctx, ctypes.byref(k))
+    _tchk(tr, rc)
+    return k.value
+
+
+def hslb_trainer_add_snapshot_host(tr, nx, ny, nz, wall_lo, wall_hi, eta, target) -> int:
+    eta = np.ascontiguousarray(eta, dtype=np.float64).ravel()
+    target = np.ascontiguousarray(target, dtype=np.float64).ravel()
+    k = ctypes.c_int32()
+    _tchk(tr, load().hslb_trainer_add_snapshot_host(tr, nx, ny, nz, wall_lo, wall_hi, _d(eta), _d(target),
+                                                    ctypes.byref(k)))
+    return k.value
+
+
+def hslb_trainer_count(tr) -> int:
+    k = ctypes.c_int32()
+    _tchk(tr, load().hslb_trainer_count(tr, ctypes.byref(k)))
+    return k.value
+
+
+def hslb_trainer_set_weights(tr, w):
+    w = _f32(w).ravel()
+    _tchk(tr, load().hslb_trainer_set_weights(tr, _f(w), w.size))
+
+
+def hslb_trainer_get_weights(tr) -> np.ndarray:
+    w = np.zeros(HSLB_CNN_NWEIGHTS, dtype=np.float32)
+    _tchk(tr, load().hslb_trainer_get_weights(tr, _f(w), w.size))
+    return w
+
+
+def hslb_trainer_eval(tr, k: int, out: Optional[np.ndarray] = None) -> float:
+    L = ctypes.c_double()
+    _tchk(tr, load().hslb_trainer_eval(tr, int(k), ctypes.byref(L), _f(out)))
+    return L.value
+
+
+def hslb_trainer_grad(tr, k: int, grad: Optional[np.ndarray] = None) -> float:
+    L = ctypes.c_double()
+    _tchk(tr, load().hslb_trainer_grad(tr, int(k), ctypes.byref(L), _f(grad)))
+    return L.value
+
+
+def hslb_trainer_step(tr, k: int, lr: float) -> float:
+    L = ctypes.c_double()
+    _tchk(tr, load().hslb_trainer_step(tr, int(k), float(lr), ctypes.byref(L)))
+    return L.value
+
+
+_CNN_OUT = {HSLB_CNN_FWD1: 64, HSLB_CNN_FWD2: 64, HSLB_CNN_FWD3: 3, HSLB_CNN_DX3: 64, HSLB_CNN_DX2: 64}
+_CNN_WOUT = {HSLB_CNN_DW1: 32 * 125 + 32, HSLB_CNN_DW2: 32 * 32 * 125 + 32, HSLB_CNN_DW3: 3 * 32 * 125 + 3}
+
+
+def hslb_cnn_op(op: int, nx: int, ny: int, nz: int, zper: bool, w, inp, aux=None) -> np.ndarray:
+    """One network operation on host data (see include/hslb.h)."""
+    N = nx * ny * nz
+    out = np.zeros(_CNN_OUT[op] * N if op in _CNN_OUT else _CNN_WOUT[op], dtype=np.float32)
+    w = _f32(w).ravel()
+    inp = _f32(inp).ravel()
+    aux = None if aux is None else _f32(aux).ravel()
+    _tchk(None, load().hslb_cnn_op(int(op), nx, ny, nz, int(bool(zper)), _f(w), _f(inp), _f(aux), _f(out)))
+    return out
+
+
 # ----------------------------------------------------------- convenience
 
 
@@ -319,11 +471,11 @@ class Sim:
 
     def __init__(self, nx, ny, nz, sigma, tau, accel=(0.0, 0.0, 0.0), wall_lo=0, wall_hi=0,
                  precision="f64", g2_model=HSLB_G2_PAPER, wall_reg=1,
-                 force_mode=HSLB_FORCE_EXACT):
+                 force_mode=HSLB_FORCE_EXACT, surr_check_every=50, surr_tol=1e-3):
         prec = {"f64": HSLB_FP64, "f32": HSLB_FP32}[precision] if isinstance(precision, str) \
             else int(precision)
         self.params = make_params(nx, ny, nz, sigma, tau, accel, wall_lo, wall_hi, g2_model,
-                                  wall_reg, prec, force_mode)
+                                  wall_reg, prec, force_mode, surr_check_every, surr_tol)
         self.shape = (int(nz), int(ny), int(nx))
         self.N = int(nx) * int(ny) * int(nz)
         self.ctx = hslb_create(self.params)
@@ -382,6 +534,11 @@ class Sim:
 
     def timings(self):
         return hslb_get_timings(self.ctx)
+
+    def surrogate_force(self):
+        F = np.zeros(3 * self.N)
+        hslb_surrogate_force(self.ctx, F)
+        return F.reshape((3,) + self.shape)
 
     @classmethod
     def from_workload(cls, wl, precision: Optional[str] = None, **kw):  # noqa: D102
@@ -443,3 +600,52 @@ class Batch:
     @property
     def fluid_nodes(self):
         return sum(w.fluid_nodes for w in self.wls)
+
+
+class Trainer:
+    """Snapshot store, weights and Adam state of the learned force on the GPU."""
+
+    def __init__(self, capacity_nodes: int, max_snapshot_nodes: int):
+        self.tr = hslb_trainer_create(capacity_nodes, max_snapshot_nodes)
+        self.sizes = []
+
+    def close(self):
+        if getattr(self, "tr", None):
+            hslb_trainer_destroy(self.tr)
+            self.tr = None
+
+    def __del__(self):
+        self.close()
+
+    def add(self, sim: Sim) -> int:
+        k = hslb_trainer_add_snapshot(self.tr, sim.ctx)
+        self.sizes.append(sim.shape)
+        return k
+
+    def add_host(self, eta, target, wall_lo=0, wall_hi=0) -> int:
+        nz, ny, nx = np.shape(eta)
+        k = hslb_trainer_add_snapshot_host(self.tr, nx, ny, nz, wall_lo, wall_hi, eta, target)
+        self.sizes.append((nz, ny, nx))
+        return k
+
+    def __len__(self):
+        return hslb_trainer_count(self.tr)
+
+    def set_weights(self, w):
+        hslb_trainer_set_weights(self.tr, w)
+
+    def weights(self) -> np.ndarray:
+        return hslb_trainer_get_weights(self.tr)
+
+    def eval(self, k: int, want_out: bool = False):
+        out = np.zeros((3,) + tuple(self.sizes[k]), dtype=np.float32) if want_out else None
+        L = hslb_trainer_eval(self.tr, k, out)
+        return (L, out) if want_out else L
+
+    def grad(self, k: int):
+        g = np.zeros(HSLB_CNN_NWEIGHTS, dtype=np.float32)
+        L = hslb_trainer_grad(self.tr, k, g)
+        return L, g
+
+    def step(self, k: int, lr: float) -> float:
+        return hslb_trainer_step(self.tr, k, lr)

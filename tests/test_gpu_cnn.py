@@ -1,0 +1,340 @@
+"""The learned force on the GPU against the FP64 oracle (oracle/cnn.py):
+each convolution kernel on seeded bf16-exact inputs, the trainer's loss and
+gradient, Adam, and the surrogate step schedule (exact checks, network force
+plus frozen correction, fallback)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import cnn
+from paper_0712_2247_amd import hslb, workloads
+
+pytestmark = pytest.mark.gpu
+
+NX, NY, NZ = 32, 8, 6
+
+
+def rel(a, b):
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(np.asarray(a, dtype=np.float64) - b) / np.linalg.norm(b))
+
+
+def weights(seed, bias_scale=0.1, out_scale=1.0):
+    w = workloads.cnn_init_weights(seed).astype(np.float64)
+    rng = np.random.default_rng(seed + 1)
+    p = cnn.unflatten(w)
+    p = {k: v.copy() for k, v in p.items()}
+    for b in ("b1", "b2", "b3"):
+        p[b] = bias_scale * rng.standard_normal(p[b].shape)
+    p["W3"] *= out_scale
+    p["b3"] *= out_scale
+    return cnn.flatten(p).astype(np.float32)
+
+
+def check_bf16(gpu, exact, bound):
+    """gpu = bf16 rounding of `exact` evaluated in FP32 arithmetic: equal,
+    except where `exact` lies within `bound` (an FP32 error bound per element)
+    of the midpoint between the two neighbouring bf16 values, where the two
+    evaluations may round to different sides."""
+    gpu = np.asarray(gpu, dtype=np.float64).ravel()
+    exact = np.asarray(exact, dtype=np.float64).ravel()
+    bound = np.asarray(bound, dtype=np.float64).ravel()
+    if bound.size == 1:
+        bound = np.full(exact.shape, bound[0])
+    want = cnn.bf16(exact)
+    bad = np.nonzero(gpu != want)[0]
+    for i in bad:
+        mid = 0.5 * (gpu[i] + want[i])
+        assert abs(exact[i] - mid) <= bound[i], (i, gpu[i], want[i], exact[i], bound[i])
+    assert len(bad) <= max(3, exact.size // 1000), len(bad)
+
+
+# FP32 accumulation of up to 4000 products (MFMA, FP32 sums): a generous
+# bound on its error is EPS_ACC times the sum of the absolute terms.
+EPS_ACC = 1e-5
+EPS_F32 = 1e-6   # a few ulp of the FP32 GELU evaluation
+
+
+def phi(z):
+    return cnn.norm_cdf(z)
+
+
+def gelu_bound(z, zabs):
+    """FP32 error bound of GELU(z) when z carries EPS_ACC * zabs."""
+    return np.abs(cnn.gelu_grad(z)) * EPS_ACC * zabs + EPS_F32 * np.abs(cnn.gelu(z))
+
+
+def dgelu_bound(da, daabs, z):
+    """FP32 error bound of da * GELU'(z)."""
+    dphi = np.abs(phi(z)) + np.abs(z) * np.exp(-0.5 * z * z) / math.sqrt(2 * math.pi)
+    return np.abs(cnn.gelu_grad(z)) * EPS_ACC * daabs + EPS_F32 * np.abs(da) * dphi
+
+
+@pytest.mark.parametrize("zper", [True, False])
+def test_forward_layers(zper):
+    shape = (NZ, NY, NX)
+    N = NX * NY * NZ
+    w = weights(21)
+    p = cnn.unflatten(w.astype(np.float64))
+    # layer 1 on an eta-like field
+    x = workloads.bf16_grid_values(shape, 0.1, 31) + np.float32(0.25)
+    x = cnn.bf16(x).astype(np.float32)
+    out = hslb.hslb_cnn_op(hslb.HSLB_CNN_FWD1, NX, NY, NZ, zper, w, x).reshape(2, 32, N)
+    z1 = cnn.conv(x.astype(np.float64)[None], cnn.bf16(p["W1"]), p["b1"], zper)
+    z1abs = cnn.conv(np.abs(x.astype(np.float64))[None], np.abs(cnn.bf16(p["W1"])), np.abs(p["b1"]), zper)
+    assert rel(out[0], z1.reshape(32, N)) <= 1e-5
+    check_bf16(out[1], cnn.gelu(z1), gelu_bound(z1, z1abs))
+    # layer 2 on bf16 activations
+    a1 = np.abs(workloads.bf16_grid_values((32,) + shape, 0.5, 32))
+    out = hslb.hslb_cnn_op(hslb.HSLB_CNN_FWD2, NX, NY, NZ, zper, w, a1).reshape(2, 32, N)
+    z2 = cnn.conv(a1.astype(np.float64), cnn.bf16(p["W2"]), p["b2"], zper)
+    z2abs = cnn.conv(np.abs(a1.astype(np.float64)), np.abs(cnn.bf16(p["W2"])), np.abs(p["b2"]), zper)
+    assert rel(out[0], z2.reshape(32, N)) <= 1e-5
+    check_bf16(out[1], cnn.gelu(z2), gelu_bound(z2, z2abs))
+    # layer 3
+    out = hslb.hslb_cnn_op(hslb.HSLB_CNN_FWD3, NX, NY, NZ, zper, w, a1).reshape(3, N)
+    F = cnn.conv(a1.astype(np.float64), cnn.bf16(p["W3"]), p["b3"], zper)
+    assert rel(out, F.reshape(3, N)) <= 1e-5
+
+
+@pytest.mark.parametrize("zper", [True, False])
+def test_input_gradient_layers(zper):
+    shape = (NZ, NY, NX)
+    N = NX * NY * NZ
+    w = weights(22)
+    p = cnn.unflatten(w.astype(np.float64))
+    g3 = workloads.bf16_grid_values((3,) + shape, 1e-3, 33)
+    z2 = (workloads.bf16_grid_values((32,) + shape, 1.0, 34)).astype(np.float32)
+    out = hslb.hslb_cnn_op(hslb.HSLB_CNN_DX3, NX, NY, NZ, zper, w, g3, z2).reshape(2, 32, N)
+    da2 = cnn.conv_transpose(g3.astype(np.float64), cnn.bf16(p["W3"]), zper)
+    da2abs = cnn.conv_transpose(np.abs(g3.astype(np.float64)), np.abs(cnn.bf16(p["W3"])), zper)
+    assert rel(out[0], da2.reshape(32, N)) <= 1e-5
+    z2d = z2.astype(np.float64)
+    check_bf16(out[1], (da2 * cnn.gelu_grad(z2d)).reshape(32, N), dgelu_bound(da2, da2abs, z2d).reshape(32, N))
+    dz2 = workloads.bf16_grid_values((32,) + shape, 1e-3, 35)
+    z1 = (workloads.bf16_grid_values((32,) + shape, 1.0, 36)).astype(np.float32)
+    out = hslb.hslb_cnn_op(hslb.HSLB_CNN_DX2, NX, NY, NZ, zper, w, dz2, z1).reshape(2, 32, N)
+    da1 = cnn.conv_transpose(dz2.astype(np.float64), cnn.bf16(p["W2"]), zper)
+    da1abs = cnn.conv_transpose(np.abs(dz2.astype(np.float64)), np.abs(cnn.bf16(p["W2"])), zper)
+    assert rel(out[0], da1.reshape(32, N)) <= 1e-5
+    z1d = z1.astype(np.float64)
+    check_bf16(out[1], (da1 * cnn.gelu_grad(z1d)).reshape(32, N), dgelu_bound(da1, da1abs, z1d).reshape(32, N))
+
+
+@pytest.mark.parametrize("zper", [True, False])
+def test_weight_gradients(zper):
+    shape = (NZ, NY, NX)
+    w = weights(23)
+    x = workloads.bf16_grid_values(shape, 0.3, 37)
+    a = workloads.bf16_grid_values((32,) + shape, 0.5, 38)
+    d32 = workloads.bf16_grid_values((32,) + shape, 1e-3, 39)
+    d3 = workloads.bf16_grid_values((3,) + shape, 1e-3, 40)
+    for op, src, g, shp in ((hslb.HSLB_CNN_DW1, x[None], d32, (32, 1, 125)),
+                            (hslb.HSLB_CNN_DW2, a, d32, (32, 32, 125)),
+                            (hslb.HSLB_CNN_DW3, a, d3, (3, 32, 125))):
+        out = hslb.hslb_cnn_op(op, NX, NY, NZ, zper, w, src, g)
+        nw = int(np.prod(shp))
+        dW = cnn.conv_weight_grad(src.astype(np.float64), g.astype(np.float64), zper)
+        assert rel(out[:nw], dW.ravel()) <= 1e-5, op
+        db = g.astype(np.float64).reshape(shp[0], -1).sum(axis=1)
+        assert rel(out[nw:], db) <= 1e-5, op
+
+
+def snapshot_fields(seed, walls=2, shape=(12, 8, 32)):
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    eta = 0.25 * (1.0 + 0.2 * rng.uniform(-1, 1, shape))
+    if walls:
+        eta[:walls] = 0.0
+        eta[nz - walls:] = 0.0
+    target = (0.02 * rng.standard_normal((3,) + shape)).astype(np.float32).astype(np.float64)
+    return eta, target
+
+
+def test_trainer_loss_and_gradient():
+    """Loss and gradient of one snapshot against the oracle's forward (same
+    bf16 roundings) and analytic backward (FP64 gradients).
+
+    Output: an FP32 evaluation lands on the other side of a bf16 rounding tie
+    than the FP64 one for a fraction ~1e-6 / 2^-8 of the hidden activations
+    (a few dozen of 2 x 98k here), each changing by 2^-8; the output moves by
+    about 1e-4 relative, bounded by 1e-3.  Gradients: the GPU also rounds the
+    backward activation gradients to bf16 (2^-9 relative each), which moves
+    each weight-gradient block by well under 1e-2."""
+    walls = 2
+    eta, target = snapshot_fields(41, walls)
+    nz, ny, nx = eta.shape
+    w = weights(24)
+    tr = hslb.Trainer(20000, 5000)
+    k = tr.add_host(eta, target, walls, walls)
+    tr.set_weights(w)
+    L_gpu, out = tr.eval(k, want_out=True)
+    c = cnn.forward(w.astype(np.float64), eta, zper=False)
+    mask = cnn.fluid_mask(nz, ny, nx, walls, walls)
+    L_or, gout = cnn.loss_and_grad_out(c["out"], target, mask)
+    print(f"trainer: output {rel(out, c['out']):.2e}, loss {abs(L_gpu - L_or) / L_or:.2e}", flush=True)
+    assert rel(out, c["out"]) <= 1e-3
+    assert abs(L_gpu - L_or) <= 1e-3 * L_or
+    L2, g = tr.grad(k)
+    assert L2 == L_gpu
+    g_or, _ = cnn.backward(w.astype(np.float64), c, gout)
+    o = 0
+    for name, shp in cnn.SHAPES:
+        m = int(np.prod(shp))
+        e = rel(g[o:o + m], g_or[o:o + m])
+        print(f"trainer: gradient {name} {e:.2e}", flush=True)
+        assert e <= 1e-2, (name, e)
+        o += m
+
+
+def test_trainer_adam_steps_reduce_the_loss():
+    tr = hslb.Trainer(40000, 5000)
+    ks = [tr.add_host(*snapshot_fields(50 + i), 2, 2) for i in range(3)]
+    w0 = weights(25)
+    tr.set_weights(w0)
+    L0 = [tr.eval(k) for k in ks]
+    lr = 1e-3
+    tr.step(ks[0], lr)
+    w1 = tr.weights()
+    dw = w1.astype(np.float64) - w0
+    assert np.abs(dw).max() <= lr * 1.0001          # |first Adam step| <= lr
+    # where the gradient is well resolved, the step goes against it
+    c = cnn.forward(w0.astype(np.float64), snapshot_fields(50)[0], zper=False)
+    mask = cnn.fluid_mask(12, 8, 32, 2, 2)
+    _, gout = cnn.loss_and_grad_out(c["out"], snapshot_fields(50)[1], mask)
+    g_or, _ = cnn.backward(w0.astype(np.float64), c, gout)
+    big = np.abs(g_or) > 0.05 * np.abs(g_or).max()
+    assert big.sum() > 100 and np.all(np.sign(dw[big]) == -np.sign(g_or[big]))
+    for it in range(300):
+        tr.step(ks[it % 3], lr)
+    L1 = [tr.eval(k) for k in ks]
+    assert all(b < 0.5 * a for a, b in zip(L0, L1)), (L0, L1)
+
+
+# ------------------------------------------------- the learned force in the step
+
+def small_slit(precision="f64"):
+    """32x8x20 slit (16 fluid layers), sigma 4, packing 0.2, tau 1, g 1e-5,
+    +-1% noise: small enough for the oracle's network at every step."""
+    return workloads.slit("surr-32x8x20", 32, 8, 16, 4, 0.2, 1.0, 1e-5, 100, precision, 1010, 0.01)
+
+
+def surr_sim(wl, K, tol, precision="f64", mode=hslb.HSLB_SURR_CORRECTED, w=None):
+    s = hslb.Sim.from_workload(wl, precision=precision, force_mode=hslb.HSLB_FORCE_SURROGATE,
+                               surr_check_every=K, surr_tol=tol)
+    if w is not None:
+        hslb.hslb_surrogate_set_weights(s.ctx, w)
+    hslb.hslb_surrogate_set_mode(s.ctx, mode)
+    n, u = wl.fields()
+    s.init(n, u)
+    return s
+
+
+def oracle_fhat(w, n, sigma, zper=False):
+    """fs * F_hat of the oracle's network on the density n."""
+    return cnn.force_scale(sigma) * cnn.forward(w.astype(np.float64), cnn.eta_field(n, sigma), zper)["out"]
+
+
+def test_surrogate_force_matches_oracle():
+    wl = small_slit()
+    w = weights(26, out_scale=1e-3)
+    s = surr_sim(wl, 50, 1.0, w=w)
+    F = s.surrogate_force()
+    n, _ = wl.fields()
+    ref = oracle_fhat(w, n, wl.sigma)
+    assert rel(F, ref) <= 1e-4
+
+
+def test_step_before_weights_is_reported():
+    s = surr_sim(small_slit(), 10, 1e-3)
+    with pytest.raises(hslb.HslbError) as ei:
+        s.step(1)
+    assert ei.value.code == hslb.HSLB_ENOSURR
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_failing_network_falls_back_to_the_exact_step(precision):
+    """A network that predicts zero force fails every check (residual 1), so
+    every step is exact: the run is the plain run, bit for bit."""
+    wl = small_slit()
+    w = np.zeros(hslb.HSLB_CNN_NWEIGHTS, dtype=np.float32)
+    s = surr_sim(wl, 10, 1e-3, precision, w=w)
+    s.step(35)
+    g = hslb.Sim.from_workload(wl, precision=precision)
+    n, u = wl.fields()
+    g.init(n, u)
+    hslb.hslb_set_graph(g.ctx, False)
+    g.step(35)
+    assert np.array_equal(s.get_populations(), g.get_populations())
+    checks, fallback, last_r, max_r = hslb.hslb_surrogate_stats(s.ctx)
+    assert checks == 4 and fallback == 31 and last_r == 1.0 and max_r == 1.0
+
+
+def test_frozen_exact_force_between_checks():
+    """The no-network ablation: between checks the interaction force is the
+    exact one of the last check.  Against the oracle driven by the same
+    schedule (exact step at every K-th step, else the frozen C1); the GPU keeps
+    the frozen force in FP32."""
+    wl = small_slit()
+    K, steps = 5, 23
+    s = surr_sim(wl, K, 1e-3, mode=hslb.HSLB_SURR_FROZEN, w=weights(27))
+    s.step(steps)
+    o = oracle.Oracle(**wl.params())
+    n, u = wl.fields()
+    o.init(n, u)
+    g = np.array(wl.accel)[:, None, None, None]
+    frozen = None
+    for t in range(steps):
+        if t % K == 0:
+            m, _ = o.moments()
+            frozen = o.force() - m[None] * g
+            o.step(1)
+        else:
+            o.step_with_force(frozen)
+    # the frozen force is stored in FP32 (relative rounding 2^-24 per value),
+    # re-applied at every step between checks and fed back through the flow:
+    # bound the populations' deviation from rest by 1e-6 relative
+    f_o = o.get_populations()
+    rest = workloads.number_density(wl.eta, wl.sigma) * oracle.lattice()[1][:, None, None, None]
+    fl = slice(wl.wall_lo, wl.nz - wl.wall_hi)
+    e = rel((s.get_populations() - rest)[:, fl], (f_o - rest)[:, fl])
+    print(f"frozen schedule: populations {e:.2e}", flush=True)
+    assert e <= 1e-6
+
+
+def test_corrected_network_schedule_matches_oracle():
+    """Network force plus the frozen correction between checks, against the
+    oracle's network driven by the same schedule.  The residual threshold is
+    set high so the network is used after every check."""
+    wl = small_slit()
+    K, steps = 4, 10
+    w = weights(28, out_scale=1e-3)
+    s = surr_sim(wl, K, 1e9, w=w)
+    s.step(steps)
+    o = oracle.Oracle(**wl.params())
+    n, u = wl.fields()
+    o.init(n, u)
+    g = np.array(wl.accel)[:, None, None, None]
+    mask = cnn.fluid_mask(wl.nz, wl.ny, wl.nx, wl.wall_lo, wl.wall_hi)[None]
+    delta = None
+    for t in range(steps):
+        m, _ = o.moments()
+        fh = oracle_fhat(w, m, wl.sigma)
+        if t % K == 0:
+            delta = (o.force() - m[None] * g - fh) * mask
+            o.step(1)
+        else:
+            o.step_with_force(fh + delta)
+    # The GPU network evaluates in FP32 with bf16 activations whose rounding
+    # can fall on the other side of a tie than the oracle's FP64 evaluation
+    # (a handful of nodes, 2^-8 relative each): the force differs by about
+    # 1e-5 relative, the profiles much less.
+    pn, pu = s.profiles()
+    on, ou = o.profiles()
+    en, eu = rel(pn, on), rel(pu[0], ou[0])
+    print(f"corrected schedule: n_z {en:.2e} u_z {eu:.2e}", flush=True)
+    assert en <= 1e-6 and eu <= 1e-4
+    checks, fallback, _, _ = hslb.hslb_surrogate_stats(s.ctx)
+    assert checks == 3 and fallback == 0

@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -53,9 +54,26 @@ def test_create_rejects_bad_parameters(lib, bad):
     assert lib.hslb_last_error(None)
 
 
-def test_surrogate_without_weights_is_reported(lib):
-    p = lib.make_params(12, 12, 20, 4, 1.0, wall_lo=2, wall_hi=2,
-                        force_mode=lib.HSLB_FORCE_SURROGATE)
+@pytest.mark.parametrize("nx,ny,K,tol", [(48, 32, 50, 1e-3), (32, 30, 50, 1e-3), (32, 32, 0, 1e-3),
+                                         (32, 32, 50, 0.0)])
+def test_surrogate_geometry_and_judge_settings_are_validated(lib, nx, ny, K, tol):
+    """The learned force needs nx % 32 == 0, ny % 4 == 0, K >= 1, tol > 0;
+    rejected before any device work."""
+    p = lib.make_params(nx, ny, 20, 4, 1.0, wall_lo=2, wall_hi=2, force_mode=lib.HSLB_FORCE_SURROGATE,
+                        surr_check_every=K, surr_tol=tol)
     with pytest.raises(lib.HslbError) as ei:
         lib.hslb_create(p)
-    assert ei.value.code == lib.HSLB_ENOSURR
+    assert ei.value.code == lib.HSLB_EINVAL
+
+
+def test_trainer_and_network_op_arguments_are_validated(lib):
+    with pytest.raises(lib.HslbError) as ei:
+        lib.hslb_trainer_create(100, 1000)          # per-snapshot maximum above the capacity
+    assert ei.value.code == lib.HSLB_EINVAL
+    w = np.zeros(lib.HSLB_CNN_NWEIGHTS, dtype=np.float32)
+    with pytest.raises(lib.HslbError) as ei:
+        lib.hslb_cnn_op(lib.HSLB_CNN_FWD1, 30, 4, 4, True, w, np.zeros(480))   # nx % 32 != 0
+    assert ei.value.code == lib.HSLB_EINVAL
+    with pytest.raises(lib.HslbError) as ei:
+        lib.hslb_cnn_op(lib.HSLB_CNN_DW2, 32, 4, 4, True, w, np.zeros(32 * 512))  # aux missing
+    assert ei.value.code == lib.HSLB_EINVAL

@@ -45,6 +45,8 @@ def test_gelu_values_and_derivative():
     h = 1e-5
     fd = (cnn.gelu(z + h) - cnn.gelu(z - h)) / (2 * h)
     assert np.abs(fd - cnn.gelu_grad(z)).max() < 1e-9
+    # far left tail: Phi(-10) = 7.619853024160527e-24 (normal tables)
+    assert abs(cnn.gelu(np.array(-10.0)) / (-10.0 * 7.619853024160527e-24) - 1.0) < 1e-12
 
 
 @pytest.mark.parametrize("zper", [True, False])

@@ -442,3 +442,21 @@ def test_stability_verdicts_sigma8_slit():
 
     assert not finite_after(0.35, 1000)
     assert finite_after(0.30, 1000)
+
+
+def test_step_with_given_exact_force_is_the_step():
+    """A step driven by a supplied interaction force equals the plain step
+    when the supplied force is the exact C1 (the external field is added in
+    both), bit for bit."""
+    wl = workloads.slit_small_f64()
+    n, u = wl.fields()
+    a = oracle.Oracle(**wl.params())
+    a.init(n, u)
+    b = oracle.Oracle(**wl.params())
+    b.init(n, u)
+    g = np.array(wl.accel)[:, None, None, None]
+    for _ in range(5):
+        m, _ = a.moments()
+        a.step_with_force(a.force() - m[None] * g)
+        b.step(1)
+    assert np.array_equal(a.get_populations(), b.get_populations())
