@@ -90,6 +90,53 @@ def ensemble_throughput(hslb, workloads, steps: int):
     return out
 
 
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def surrogate_leg(hslb, workloads, wl, steps: int, epochs: int):
+    """The learned force on the benchmark slit: snapshots of the 40 training
+    slits (64x64xnz, sigma 4..8, stable runs only), Adam on the GPU, then the
+    surrogate path (exact judge every 50 steps, residual threshold 1e-3) with
+    the network plus frozen correction and without the network (frozen exact
+    force: the ablation), each against the exact path's profiles."""
+    from paper_0712_2247_amd import surrogate
+    runs = workloads.surrogate_training_runs()
+    tr = hslb.Trainer(sum(w.nodes for w in runs) * 100 + 1, max(w.nodes for w in runs))
+    t0 = time.perf_counter()
+    recs = surrogate.collect(tr, runs, 20, 2000)
+    snaps = [k for r in recs for k in r["snapshots"]]
+    t_collect = time.perf_counter() - t0
+    res = surrogate.train(tr, workloads.cnn_init_weights(), snaps, epochs, 1e-3)
+    w = res["weights"]
+    tr.close()
+    ref = surrogate.exact_profiles(wl, steps)
+    out = {"training": {"runs": len(runs), "stable_runs": sum(r["stable"] for r in recs),
+                        "snapshots": len(snaps), "epochs": epochs, "adam_steps": res["steps"],
+                        "mean_loss_per_epoch": [float(v) for v in res["losses"]],
+                        "collect_s": round(t_collect, 1), "train_s": round(res["seconds"], 1)}}
+    for mode in (hslb.HSLB_SURR_CORRECTED, hslb.HSLB_SURR_FROZEN):
+        r = surrogate.evaluate(wl, w, steps, 50, 1e-3, mode, reference=ref)
+        out[r["mode"]] = r
+        print(f"bench: surrogate {r['mode']}: {r}", file=sys.stderr, flush=True)
+    # network kernel times on the benchmark slit (eager, HIP events)
+    s = hslb.Sim.from_workload(wl, force_mode=hslb.HSLB_FORCE_SURROGATE, surr_check_every=50, surr_tol=1e-3)
+    hslb.hslb_surrogate_set_weights(s.ctx, w)
+    n, u = wl.fields()
+    s.init(n, u)
+    hslb.hslb_set_kernel_timing(s.ctx, True)
+    s.step(100)
+    s.sync()
+    kt = {k: v[0] / v[1] * 1e3 for k, v in hslb.hslb_kernel_times(s.ctx).items()}
+    s.close()
+    out["kernels_us"] = {k: round(v, 2) for k, v in kt.items()}
+    flops = 2.0 * 125 * 32 * 32 * wl.nodes   # layer 2: 32 -> 32 channels, 5^3 taps, every node
+    ach = flops / (kt["cnn_l2"] * 1e-6) / 1e12
+    out["roofline_cnn_l2"] = {"bound": "mfma", "achieved": round(ach, 1), "peak": PEAK_BF16_TFLOPS,
+                              "unit": "TFLOP/s", "frac": round(ach / PEAK_BF16_TFLOPS, 4),
+                              "algorithmic_flop_per_launch": flops}
+    return out
+
+
 def cpu_baseline(wl, n, u, budget_s: float):
     import oracle
     o = oracle.Oracle(**wl.params())
@@ -118,6 +165,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-pass", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-epochs", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
@@ -201,6 +250,11 @@ def main():
         print("bench: ensemble", file=sys.stderr, flush=True)
         ens = ensemble_throughput(hslb, workloads, min(args.steps, 500))
 
+    surr = None
+    if not args.no_surrogate:
+        print("bench: surrogate", file=sys.stderr, flush=True)
+        surr = surrogate_leg(hslb, workloads, wl, args.steps, args.surrogate_epochs)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
@@ -229,6 +283,7 @@ def main():
         "step_copy_frac": round(mlups * 1e6 * STEP_BYTES / 1e9 / copy_gbps, 4),
         "as_specified": as_specified,
         "ensemble": ens,
+        "surrogate": surr,
         "roofline": roof,
         "kernels_us": kernels,
         "cpu_baseline": cpu,

@@ -232,14 +232,18 @@ int hslb_batch_autotune(hslb_ctx *ctx, int32_t steps, int32_t *choice, double *u
  * ny % 4 == 0, surr_check_every >= 1, surr_tol > 0, else HSLB_EINVAL) steps
  * as follows once weights are loaded (hslb_step before that: HSLB_ENOSURR):
  *   - every surr_check_every steps (step index % K == 0) an exact step that
- *     also evaluates the network and its residual
- *     r = |fs F_hat - C1|_2 / |C1|_2 over the fluid nodes, and keeps the
- *     correction delta = C1 - fs F_hat;
+ *     also judges the force the surrogate path would apply at that state,
+ *     pred = fs F_hat(n) + delta_prev (HSLB_SURR_CORRECTED), fs F_hat(n)
+ *     (HSLB_SURR_PLAIN) or delta_prev (HSLB_SURR_FROZEN; delta_prev is 0
+ *     at the first check after init or a mode change), by its residual
+ *     r = |pred - C1|_2 / |C1|_2 over the fluid nodes, and then keeps the
+ *     correction delta = C1 - fs F_hat (C1 itself without the network);
  *   - otherwise, if the last check had r <= surr_tol, a step with
- *     C1 = fs F_hat(n_t) + delta (HSLB_SURR_CORRECTED), fs F_hat(n_t)
- *     (HSLB_SURR_PLAIN) or the frozen exact force delta of the last check
- *     without the network (HSLB_SURR_FROZEN, the no-network ablation);
- *     if r > surr_tol, exact steps until the next check.
+ *     C1 = fs F_hat(n_t) + delta (corrected), fs F_hat(n_t) (plain) or the
+ *     frozen exact force delta of the last check without the network (frozen,
+ *     the no-network ablation); if r > surr_tol, exact steps until the next
+ *     check.  The first check after init, hslb_set_populations, a checkpoint
+ *     load or new weights has no previous correction.
  * hslb_surrogate_stats: checks done, exact fallback steps, last and largest
  * residual.  hslb_surrogate_force: fs F_hat [3][N] of the current state
  * (host, caller-owned).  Weight arrays are caller-owned and copied. */
@@ -281,6 +285,10 @@ int hslb_trainer_get_weights(hslb_trainer *tr, float *w, int64_t nw);
 int hslb_trainer_eval(hslb_trainer *tr, int32_t snapshot, double *loss, float *out);
 int hslb_trainer_grad(hslb_trainer *tr, int32_t snapshot, double *loss, float *grad);
 int hslb_trainer_step(hslb_trainer *tr, int32_t snapshot, double lr, double *loss);
+/* n Adam steps on the snapshots order[0..n) in turn; *mean_loss = the mean
+ * of their losses (each taken before its step).  HSLB_EUNSTABLE if a loss is
+ * not finite. */
+int hslb_trainer_train(hslb_trainer *tr, const int32_t *order, int32_t n, double lr, double *mean_loss);
 
 /* One network operation on host data (nx % 32 == 0, ny % 4 == 0, zper: z
  * periodic).  All host arrays are FP32, channel-major [c][N]; values that feed

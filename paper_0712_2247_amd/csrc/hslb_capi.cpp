@@ -329,6 +329,8 @@ public:
         steps = 0;
         refreshed_at_ = -1;
         inited = true;
+        surr_ok_ = false;
+        have_delta_ = false;
         return HSLB_OK;
     }
 
@@ -600,6 +602,8 @@ public:
         HIP_TRY(hipStreamSynchronize(st()));
         steps = 0;
         refreshed_at_ = -1;
+        surr_ok_ = false;
+        have_delta_ = false;
         return HSLB_OK;
     }
 
@@ -652,6 +656,8 @@ public:
         HIP_TRY(hipStreamSynchronize(st()));
         steps = h.steps;
         refreshed_at_ = h.refreshed_at;
+        surr_ok_ = false;
+        have_delta_ = false;
         return HSLB_OK;
     }
 
@@ -709,6 +715,7 @@ public:
         HIP_TRY(hipStreamSynchronize(st()));
         have_w_ = true;
         surr_ok_ = false;
+        have_delta_ = false;
         surr_checks_ = surr_fallback_ = 0;
         surr_last_r_ = -1.0;
         surr_max_r_ = 0.0;
@@ -729,6 +736,7 @@ public:
         if (mode < HSLB_SURR_CORRECTED || mode > HSLB_SURR_FROZEN) return fail(err, HSLB_EINVAL, "surrogate mode");
         surr_mode_ = mode;
         surr_ok_ = false;
+        have_delta_ = false;
         return HSLB_OK;
     }
 
@@ -801,11 +809,14 @@ public:
             return rc;
         const bool net = surr_mode_ != HSLB_SURR_FROZEN;
         if (net && (rc = cnn_forward())) return rc;
+        // judge the force the path would apply now: with the correction of the
+        // previous check (corrected and frozen modes), the bare network (plain)
+        const int use_prev = have_delta_ && surr_mode_ != HSLB_SURR_PLAIN ? 1 : 0;
         const cnn::Geo g = cnn_geo();
         const unsigned nb = cnn::judge_blocks(g);
         if ((rc = launch("judge", [&] {
                  return cnn::launch_judge(st(), g, L_.zper ? 0 : L_.wall_lo, L_.zper ? 0 : L_.wall_hi, net ? fscale_ : 0.0,
-                                          net ? fhat_ : nullptr, c1_, delta_, jpart_);
+                                          net ? fhat_ : nullptr, c1_, use_prev, delta_, jpart_);
              })))
             return rc;
         HIP_TRY(hipMemcpyAsync(jpart_h_, jpart_, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, st()));
@@ -820,11 +831,16 @@ public:
             a += jpart_h_[2 * k];
             b += jpart_h_[2 * k + 1];
         }
-        const double r = b > 0.0 ? std::sqrt(a / b) : (a > 0.0 ? INFINITY : 0.0);
+        // a non-finite state or force fails the check
+        const double r = !(std::isfinite(a) && std::isfinite(b)) ? INFINITY
+                         : b > 0.0                                ? std::sqrt(a / b)
+                         : a > 0.0                                ? INFINITY
+                                                                  : 0.0;
         surr_last_r_ = r;
         surr_max_r_ = std::max(surr_max_r_, r);
         surr_checks_ += 1;
-        surr_ok_ = surr_mode_ == HSLB_SURR_FROZEN || r <= p_.surr_tol;
+        have_delta_ = true;
+        surr_ok_ = r <= p_.surr_tol;
         return HSLB_OK;
     }
 
@@ -917,7 +933,7 @@ private:
     float *fhat_ = nullptr, *delta_ = nullptr;
     double *c1_ = nullptr, *jpart_ = nullptr, *jpart_h_ = nullptr;
     double fscale_ = 0.0;
-    bool have_w_ = false, surr_ok_ = false;
+    bool have_w_ = false, surr_ok_ = false, have_delta_ = false;
     int surr_mode_ = HSLB_SURR_CORRECTED;
     int64_t surr_checks_ = 0, surr_fallback_ = 0;
     double surr_last_r_ = -1.0, surr_max_r_ = 0.0;

@@ -502,8 +502,11 @@ __global__ __launch_bounds__(256) void k_adam(int n, float *__restrict__ w, floa
     w[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + 1e-8f);
 }
 
+// Residual of the force the surrogate path applies, fs F_hat + delta_old
+// (delta_old only with use_prev), against the exact C1 over fluid nodes; then
+// delta = C1 - fs F_hat (in place: each node reads its old value first).
 __global__ __launch_bounds__(256) void k_judge(Geo g, int wall_lo, int wall_hi, double fs, const float *__restrict__ fhat,
-                                               const double *__restrict__ c1, float *__restrict__ delta,
+                                               const double *__restrict__ c1, int use_prev, float *__restrict__ delta,
                                                double *__restrict__ partial)
 {
     __shared__ double red[4];
@@ -514,14 +517,15 @@ __global__ __launch_bounds__(256) void k_judge(Geo g, int wall_lo, int wall_hi, 
         const bool fl = z >= wall_lo && z < g.nz - wall_hi;
 #pragma unroll
         for (int c = 0; c < CO; ++c) {
-            const double e = c1[(size_t)c * g.N + i];
-            const double f = fhat ? fs * (double)fhat[(size_t)c * g.N + i] : 0.0;
-            const double d = fl ? e - f : 0.0;
+            const size_t k = (size_t)c * g.N + i;
+            const double e = c1[k];
+            const double f = fhat ? fs * (double)fhat[k] : 0.0;
             if (fl) {
-                a += d * d;
+                const double pred = f + (use_prev ? (double)delta[k] : 0.0);
+                a += (e - pred) * (e - pred);
                 b += e * e;
             }
-            if (delta) delta[(size_t)c * g.N + i] = (float)d;
+            delta[k] = fl ? (float)(e - f) : 0.f;
         }
     }
     const double ta = block_sum(a, red);
@@ -705,9 +709,10 @@ hipError_t launch_scale_f64_to_f32(hipStream_t st, const double *in, double s, s
 }
 
 hipError_t launch_judge(hipStream_t s, const Geo &g, int wall_lo, int wall_hi, double fs, const float *fhat,
-                        const double *c1, float *delta, double *partial)
+                        const double *c1, int use_prev, float *delta, double *partial)
 {
-    hipLaunchKernelGGL(k_judge, dim3(judge_blocks(g)), dim3(256), 0, s, g, wall_lo, wall_hi, fs, fhat, c1, delta, partial);
+    hipLaunchKernelGGL(k_judge, dim3(judge_blocks(g)), dim3(256), 0, s, g, wall_lo, wall_hi, fs, fhat, c1, use_prev,
+                       delta, partial);
     return hipGetLastError();
 }
 

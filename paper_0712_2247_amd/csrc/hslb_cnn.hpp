@@ -94,12 +94,13 @@ hipError_t launch_loss(hipStream_t s, const Geo &g, int wall_lo, int wall_hi, co
 // Adam on the canonical FP32 weights (step t >= 1).
 hipError_t launch_adam(hipStream_t s, int n, float *w, float *m, float *v, const float *g, int t, float lr);
 
-// Residual of the learned force against the exact one over fluid nodes:
-// partial sums [blocks][2] of |fs*F_hat - C1|^2 and |C1|^2, and (if delta is
-// not null) delta = C1 - fs*F_hat (0 off the fluid).  fhat may be null (0).
+// Residual of the force the surrogate path applies against the exact one
+// over fluid nodes: partial sums [blocks][2] of |C1 - pred|^2 and |C1|^2 with
+// pred = fs*F_hat + (use_prev ? delta : 0); then delta = C1 - fs*F_hat (0 off
+// the fluid).  fhat may be null (0).
 unsigned judge_blocks(const Geo &g);
 hipError_t launch_judge(hipStream_t s, const Geo &g, int wall_lo, int wall_hi, double fs, const float *fhat,
-                        const double *c1, float *delta, double *partial);
+                        const double *c1, int use_prev, float *delta, double *partial);
 
 // Layout conversions for host-staged test data (FP32 values, channel-major
 // [c][N] on the host side): to bf16 channel-last [N][cp] (channels c..cp-1

@@ -443,6 +443,31 @@ int hslb_trainer_step(hslb_trainer *tr, int32_t k, double lr, double *loss)
     return HSLB_OK;
 }
 
+int hslb_trainer_train(hslb_trainer *tr, const int32_t *order, int32_t n, double lr, double *mean_loss)
+{
+    if (!tr || (!order && n > 0) || n < 0) return HSLB_EINVAL;
+    std::string &err = tr->err;
+    if (!tr->have_w) return tfail(err, HSLB_ENOSURR, "no weights set");
+    if (!(lr > 0.0) || !std::isfinite(lr)) return tfail(err, HSLB_EINVAL, "learning rate must be > 0");
+    for (int32_t i = 0; i < n; ++i)
+        if (order[i] < 0 || order[i] >= (int32_t)tr->snaps.size())
+            return tfail(err, HSLB_EINVAL, "order[%d] = %d is not a snapshot", (int)i, (int)order[i]);
+    double sum = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        double L = 0.0;
+        int rc = tr->run(order[i], true, &L);
+        if (rc) return rc;
+        if (!std::isfinite(L)) return tfail(err, HSLB_EUNSTABLE, "loss is not finite at step %d", (int)i);
+        sum += L;
+        tr->t += 1;
+        T_TRY(launch_adam(tr->stream, NW, tr->w, tr->m, tr->v, tr->grad, tr->t, (float)lr));
+        T_TRY(tr->pk.build(tr->stream, tr->w));
+    }
+    T_TRY(hipStreamSynchronize(tr->stream));
+    if (mean_loss) *mean_loss = n > 0 ? sum / n : 0.0;
+    return HSLB_OK;
+}
+
 int hslb_cnn_op(int32_t op, int32_t nx, int32_t ny, int32_t nz, int32_t zper, const float *w, const float *in,
                 const float *aux, float *out)
 {

@@ -54,7 +54,7 @@ EXPORTS = (
     "hslb_trainer_create", "hslb_trainer_destroy", "hslb_trainer_last_error",
     "hslb_trainer_add_snapshot", "hslb_trainer_add_snapshot_host", "hslb_trainer_count",
     "hslb_trainer_set_weights", "hslb_trainer_get_weights", "hslb_trainer_eval",
-    "hslb_trainer_grad", "hslb_trainer_step", "hslb_cnn_op",
+    "hslb_trainer_grad", "hslb_trainer_step", "hslb_trainer_train", "hslb_cnn_op",
 )
 
 
@@ -145,6 +145,7 @@ def load(path: Optional[str] = None):
         "hslb_trainer_eval": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, _fp]),
         "hslb_trainer_grad": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, _fp]),
         "hslb_trainer_step": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_double, _dp]),
+        "hslb_trainer_train": (ctypes.c_int, [_vp, _P(ctypes.c_int32), ctypes.c_int32, ctypes.c_double, _dp]),
         "hslb_cnn_op": (ctypes.c_int, [ctypes.c_int32] * 5 + [_fp, _fp, _fp, _fp]),
     }
     for name, (res, args) in sig.items():
@@ -432,6 +433,14 @@ def hslb_trainer_step(tr, k: int, lr: float) -> float:
     return L.value
 
 
+def hslb_trainer_train(tr, order, lr: float) -> float:
+    order = np.ascontiguousarray(order, dtype=np.int32)
+    L = ctypes.c_double()
+    _tchk(tr, load().hslb_trainer_train(tr, order.ctypes.data_as(_P(ctypes.c_int32)), order.size, float(lr),
+                                        ctypes.byref(L)))
+    return L.value
+
+
 _CNN_OUT = {HSLB_CNN_FWD1: 64, HSLB_CNN_FWD2: 64, HSLB_CNN_FWD3: 3, HSLB_CNN_DX3: 64, HSLB_CNN_DX2: 64}
 _CNN_WOUT = {HSLB_CNN_DW1: 32 * 125 + 32, HSLB_CNN_DW2: 32 * 32 * 125 + 32, HSLB_CNN_DW3: 3 * 32 * 125 + 3}
 
@@ -649,3 +658,6 @@ class Trainer:
 
     def step(self, k: int, lr: float) -> float:
         return hslb_trainer_step(self.tr, k, lr)
+
+    def train(self, order, lr: float) -> float:
+        return hslb_trainer_train(self.tr, order, lr)
