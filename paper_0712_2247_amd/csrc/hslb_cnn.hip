@@ -72,67 +72,92 @@ __device__ __forceinline__ int zsrc(const Geo &g, int z)
 
 // ------------------------------------------------------------- forward
 
-// A operand of K-step s for the node (xl, y, z) of this lane.
+// A block of 4 waves computes a 16 (x) x 4 (y) x 4 (z) tile of output nodes:
+// wave w takes y0 + w, its 4 rows the layers z0 .. z0 + 3.  The input nodes
+// the tile reads, 20 x 8 x 8 with the halo of 2, are staged in LDS once (x
+// and y wrapped, z wrapped or zero beyond walls); every tap's A operand then
+// comes from LDS.  cin = 32: 64 B per node (80 KB); cin = 4: 8 B; cin = 1: 2 B.
+constexpr int TX = 16, TY = 4, TZ = 4;
+constexpr int HX = TX + 4, HY = TY + 4, HZ = TZ + 4, HNODES = HX * HY * HZ;
+constexpr int ROWS = TZ;
+
+__device__ __forceinline__ int lnode(int hx, int hy, int hz) { return (hz * HY + hy) * HX + hx; }
+
+__device__ __forceinline__ int mod_pos(int v, int n) { return ((v % n) + n) % n; }
+
 template <int CIN>
-__device__ __forceinline__ u32x4 load_a(const Geo &g, const uint16_t *__restrict__ in, int s, int xl, int y, int z,
-                                        int lg)
+__device__ __forceinline__ void stage_tile(const Geo &g, const uint16_t *__restrict__ in, uint16_t *tile, int x0,
+                                           int y0, int z0)
+{
+    constexpr int PARTS = CIN == 32 ? 4 : 1;  // 16-byte parts per node (cin 32)
+    for (int c = threadIdx.x; c < HNODES * PARTS; c += 256) {
+        const int node = c / PARTS, part = c % PARTS;
+        const int hx = node % HX, hy = (node / HX) % HY, hz = node / (HX * HY);
+        const int zr = z0 - 2 + hz;
+        const int zs = g.zper ? mod_pos(zr, g.nz) : ((zr < 0 || zr >= g.nz) ? -1 : zr);
+        size_t src = 0;
+        if (zs >= 0) src = (size_t)wrapi(x0 - 2 + hx, g.nx) + (size_t)g.nx * (mod_pos(y0 - 2 + hy, g.ny) + (size_t)g.ny * zs);
+        if constexpr (CIN == 32) {
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (zs >= 0) v = ((const u32x4 *)(in + src * 32))[part];
+            ((u32x4 *)tile)[c] = v;
+        } else if constexpr (CIN == 4) {
+            u32x2 v = {0u, 0u};
+            if (zs >= 0) v = *(const u32x2 *)(in + src * 4);
+            ((u32x2 *)tile)[node] = v;
+        } else {
+            tile[node] = zs >= 0 ? in[src] : (uint16_t)0;
+        }
+    }
+}
+
+// A operand of K-step s for row r of wave w (node x0 + li of the tile).
+template <int CIN>
+__device__ __forceinline__ u32x4 lds_a(const uint16_t *tile, int s, int li, int w, int r, int lg)
 {
     u32x4 v = {0u, 0u, 0u, 0u};
     if constexpr (CIN == 32) {
-        const int dz = s / 25 - 2, dy = (s / 5) % 5 - 2, dx = s % 5 - 2;
-        const int zs = zsrc(g, z + dz);
-        if (zs >= 0) {
-            const int node = wrapi(xl + dx, g.nx) + g.nx * (wrapi(y + dy, g.ny) + g.ny * zs);
-            v = *(const u32x4 *)(in + (size_t)node * 32 + 8 * lg);
-        }
+        const int dz = s / 25, dy = (s / 5) % 5, dx = s % 5;  // offsets + 2
+        v = ((const u32x4 *)tile)[lnode(li + dx, w + dy, r + dz) * 4 + lg];
     } else if constexpr (CIN == 4) {
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int t = 8 * s + 2 * lg + q;
             if (t < NT) {
-                const int dz = t / 25 - 2, dy = (t / 5) % 5 - 2, dx = t % 5 - 2;
-                const int zs = zsrc(g, z + dz);
-                if (zs >= 0) {
-                    const int node = wrapi(xl + dx, g.nx) + g.nx * (wrapi(y + dy, g.ny) + g.ny * zs);
-                    const u32x2 w = *(const u32x2 *)(in + (size_t)node * 4);
-                    v[2 * q] = w[0];
-                    v[2 * q + 1] = w[1];
-                }
+                const u32x2 w2 = ((const u32x2 *)tile)[lnode(li + t % 5, w + (t / 5) % 5, r + t / 25)];
+                v[2 * q] = w2[0];
+                v[2 * q + 1] = w2[1];
             }
         }
     } else {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int t = 32 * s + 8 * lg + e;
-            uint32_t h = 0;
-            if (t < NT) {
-                const int dz = t / 25 - 2, dy = (t / 5) % 5 - 2, dx = t % 5 - 2;
-                const int zs = zsrc(g, z + dz);
-                if (zs >= 0) h = in[wrapi(xl + dx, g.nx) + g.nx * (wrapi(y + dy, g.ny) + g.ny * zs)];
-            }
+            const uint32_t h = t < NT ? tile[lnode(li + t % 5, w + (t / 5) % 5, r + t / 25)] : 0u;
             v[e >> 1] |= h << (16 * (e & 1));
         }
     }
     return v;
 }
 
-constexpr int ROWS = 4;
-
 template <int CIN, int NH, int EPI>
 __global__ __launch_bounds__(256) void k_conv_fwd(FwdArgs a)
 {
     constexpr int KS = CIN == 32 ? NT : (CIN == 4 ? 16 : 4);
+    __shared__ __attribute__((aligned(16))) uint16_t tile[HNODES * CIN];
     const Geo g = a.g;
-    const int lane = threadIdx.x & 63;
-    const int wave = xcd_block((int)blockIdx.x, (int)gridDim.x) * 4 + (int)(threadIdx.x >> 6);
-    const int nxc = g.nx >> 4, nyq = g.ny >> 2;
-    if (wave >= nxc * nyq * g.nz) return;  // whole waves only: no barriers below
-    const int z = wave / (nxc * nyq);
-    const int rem = wave - z * nxc * nyq;
-    const int yq = rem / nxc;
-    const int x0 = (rem - yq * nxc) * 16, y0 = yq * ROWS;
-    const int li = lane & 15, lg = lane >> 4;
+    const int nxb = g.nx / TX, nyb = g.ny / TY;
+    const int b = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int zb = b / (nxb * nyb);
+    const int rem = b - zb * nxb * nyb;
+    const int yb = rem / nxb;
+    const int x0 = (rem - yb * nxb) * TX, y0 = yb * TY, z0 = zb * TZ;
+    stage_tile<CIN>(g, a.in, tile, x0, y0, z0);
+    __syncthreads();
 
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int rows = min(ROWS, g.nz - z0);  // the last z tile may be partial
     f32x4 acc[ROWS][NH];
 #pragma unroll
     for (int r = 0; r < ROWS; ++r)
@@ -140,20 +165,24 @@ __global__ __launch_bounds__(256) void k_conv_fwd(FwdArgs a)
         for (int h = 0; h < NH; ++h) acc[r][h] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
     for (int s = 0; s < KS; ++s) {
-        bf16x8 b[NH];
+        bf16x8 bw[NH];
 #pragma unroll
-        for (int h = 0; h < NH; ++h) b[h] = as_bf(*(const u32x4 *)(a.wp + ((size_t)(s * NH + h) * 64 + lane) * 8));
+        for (int h = 0; h < NH; ++h) bw[h] = as_bf(*(const u32x4 *)(a.wp + ((size_t)(s * NH + h) * 64 + lane) * 8));
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
-            const bf16x8 av = as_bf(load_a<CIN>(g, a.in, s, x0 + li, y0 + r, z, lg));
+            if (r < rows) {
+                const bf16x8 av = as_bf(lds_a<CIN>(tile, s, li, w, r, lg));
 #pragma unroll
-            for (int h = 0; h < NH; ++h) acc[r][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b[h], acc[r][h], 0, 0, 0);
+                for (int h = 0; h < NH; ++h)
+                    acc[r][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[h], acc[r][h], 0, 0, 0);
+            }
         }
     }
 
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
-        const int rowbase = g.nx * ((y0 + r) + g.ny * z);
+        if (r >= rows) continue;
+        const int rowbase = g.nx * ((y0 + w) + g.ny * (z0 + r));
 #pragma unroll
         for (int h = 0; h < NH; ++h) {
             const int c = 16 * h + li;
@@ -583,8 +612,8 @@ inline unsigned nblocks(size_t n) { return (unsigned)((n + 255) / 256); }
 
 hipError_t launch_conv_fwd(hipStream_t s, int cin, int cout, int epi, const FwdArgs &a)
 {
-    const int waves = (a.g.nx / 16) * (a.g.ny / ROWS) * a.g.nz;
-    const dim3 grid((waves + 3) / 4), blk(256);
+    const int blocks = (a.g.nx / TX) * (a.g.ny / TY) * ((a.g.nz + TZ - 1) / TZ);
+    const dim3 grid(blocks), blk(256);
     const int nh = cout == 32 ? 2 : 1;
 #define HSLB_CONV(CI, NH_, EP) \
     if (cin == CI && nh == NH_ && epi == EP) { hipLaunchKernelGGL((k_conv_fwd<CI, NH_, EP>), grid, blk, 0, s, a); return hipGetLastError(); }
