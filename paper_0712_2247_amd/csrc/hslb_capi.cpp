@@ -223,17 +223,17 @@ public:
         if (hipMalloc(&f_[0], popb) != hipSuccess || hipMalloc(&f_[1], popb) != hipSuccess)
             return fail(err, HSLB_ENOMEM, "population buffers (%zu bytes each) do not fit", popb);
         // n, j, eta_bar, the 7 contact-value slots and sigma/2 + 1 row-sum fields
-        const size_t nfld = (size_t)(1 + 3 + 1 + NGSLOT + sig / 2 + 1) * L_.fld_stride;
+        const size_t nfld = (size_t)(1 + 4 + 1 + NGSLOT + sig / 2 + 1) * L_.fld_stride;
         if (hipMalloc(&fld_mem_, sizeof(TM) * nfld) != hipSuccess)
             return fail(err, HSLB_ENOMEM, "moment fields do not fit");
         HIP_TRY(hipMemset(fld_mem_, 0, sizeof(TM) * nfld));
         HIP_TRY(hipMemset(f_[0], 0, popb));
         HIP_TRY(hipMemset(f_[1], 0, popb));
         fld_.n = fld_mem_;
-        fld_.j = fld_mem_ + L_.fld_stride;
-        fld_.eb = fld_mem_ + 4 * (size_t)L_.fld_stride;
-        fld_.G = fld_mem_ + 5 * (size_t)L_.fld_stride;
-        rs_ = fld_mem_ + (size_t)(5 + NGSLOT) * L_.fld_stride;
+        fld_.nj = fld_mem_ + L_.fld_stride;
+        fld_.eb = fld_mem_ + 5 * (size_t)L_.fld_stride;
+        fld_.G = fld_mem_ + 6 * (size_t)L_.fld_stride;
+        rs_ = fld_mem_ + (size_t)(6 + NGSLOT) * L_.fld_stride;
 
         std::vector<double> chi(p_.nz, 1.0);
         if (!L_.zper && p_.wall_reg) {
@@ -1069,14 +1069,14 @@ public:
             return fail(err, HSLB_ENOMEM, "population buffers (%zu bytes each) do not fit", popb);
         HIP_TRY(hipMemset(f_[0], 0, popb));
         HIP_TRY(hipMemset(f_[1], 0, popb));
-        const size_t nf = (size_t)(1 + 3 + 1 + NGSLOT + maxR + 1) * fld_stride_;
+        const size_t nf = (size_t)(1 + 4 + 1 + NGSLOT + maxR + 1) * fld_stride_;
         if (hipMalloc(&fld_mem_, sizeof(TM) * nf) != hipSuccess) return fail(err, HSLB_ENOMEM, "moment fields");
         HIP_TRY(hipMemset(fld_mem_, 0, sizeof(TM) * nf));
         fld_.n = fld_mem_;
-        fld_.j = fld_mem_ + fld_stride_;
-        fld_.eb = fld_mem_ + 4 * (size_t)fld_stride_;
-        fld_.G = fld_mem_ + 5 * (size_t)fld_stride_;
-        rs_ = fld_mem_ + (size_t)(5 + NGSLOT) * fld_stride_;
+        fld_.nj = fld_mem_ + fld_stride_;
+        fld_.eb = fld_mem_ + 5 * (size_t)fld_stride_;
+        fld_.G = fld_mem_ + 6 * (size_t)fld_stride_;
+        rs_ = fld_mem_ + (size_t)(6 + NGSLOT) * fld_stride_;
         // descriptors, work lists, chi, profile offsets and profiles in one block
         const size_t bdesc = sizeof(SlitDesc) * ns;
         const size_t bw = sizeof(WorkItem) * (wl_nodes_.size() + wl_rows_.size() + wl_fluid_.size() + wl_prof_.size());

@@ -61,7 +61,7 @@ struct StepConst {
 template <typename TM>
 struct Fields {
     TM *n;          // [fld_stride]
-    TM *j;          // [3][fld_stride]
+    TM *nj;         // [fld_stride][4]: (n, jx, jy, jz) interleaved, one load per shell read
     TM *eb;         // [fld_stride]
     TM *G;          // [7][fld_stride]
 };

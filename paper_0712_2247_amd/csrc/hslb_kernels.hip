@@ -73,6 +73,25 @@ __device__ __forceinline__ double g2_of(double eta, int model)
     return num / (om * om * om);
 }
 
+// One vector access to the interleaved (n, jx, jy, jz) of a node.
+typedef float f32v4 __attribute__((ext_vector_type(4)));
+typedef double f64v4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void load4(const float *p, float q[4])
+{
+    const f32v4 v = *(const f32v4 *)p;
+    q[0] = v[0], q[1] = v[1], q[2] = v[2], q[3] = v[3];
+}
+__device__ __forceinline__ void load4(const double *p, double q[4])
+{
+    const f64v4 v = *(const f64v4 *)p;
+    q[0] = v[0], q[1] = v[1], q[2] = v[2], q[3] = v[3];
+}
+__device__ __forceinline__ void store4(float *p, float a, float b, float c, float d) { *(f32v4 *)p = (f32v4){a, b, c, d}; }
+__device__ __forceinline__ void store4(double *p, double a, double b, double c, double d)
+{
+    *(f64v4 *)p = (f64v4){a, b, c, d};
+}
+
 // Store v at padded z = z + hz and, for a periodic z axis, at every ghost layer
 // congruent to it modulo nz.
 template <typename TM>
@@ -85,6 +104,20 @@ __device__ __forceinline__ void store_padded(const LatticeDev &L, TM *dst, int r
     int p = z + L.hz;
     while (p - L.nz >= 0) p -= L.nz;
     for (; p < L.nz + 2 * L.hz; p += L.nz) dst[rem + L.plane * p] = v;
+}
+
+// The interleaved (n, j) of a node into the padded field [..][4], with the
+// periodic images in the ghost layers as store_padded.
+template <typename TM>
+__device__ __forceinline__ void store_padded4(const LatticeDev &L, TM *dst, int rem, int z, TM a, TM b, TM c, TM d)
+{
+    if (!L.zper) {
+        store4(dst + 4 * ((size_t)rem + (size_t)L.plane * (z + L.hz)), a, b, c, d);
+        return;
+    }
+    int p = z + L.hz;
+    while (p - L.nz >= 0) p -= L.nz;
+    for (; p < L.nz + 2 * L.hz; p += L.nz) store4(dst + 4 * ((size_t)rem + (size_t)L.plane * p), a, b, c, d);
 }
 
 __device__ __forceinline__ bool is_fluid_z(const LatticeDev &L, int z)
@@ -192,9 +225,7 @@ __device__ __forceinline__ void d_moments(const LatticeDev &L, const double *__r
         }
     }
     store_padded(L, fld.n, r, z, (TM)n);
-    store_padded(L, fld.j, r, z, (TM)jx);
-    store_padded(L, fld.j + L.fld_stride, r, z, (TM)jy);
-    store_padded(L, fld.j + 2 * L.fld_stride, r, z, (TM)jz);
+    store_padded4(L, fld.nj, r, z, (TM)n, (TM)jx, (TM)jy, (TM)jz);
 }
 
 // grid (ceil(plane / 256), nz): x = chunk of the layer, y = layer
@@ -374,19 +405,22 @@ __device__ __forceinline__ TC pair_element(const Fields<TM> &F, const LatticeDev
     const int gp = wrapc<BXP>(c.x, L.nx) + L.nx * (wrapc<BYP>(c.y, L.ny) + L.ny * (c.zp + BZP));
     const int gm = wrapc<BXM>(c.x, L.nx) + L.nx * (wrapc<BYM>(c.y, L.ny) + L.ny * (c.zp + BZM));
     const TC Gp = (TC)F.G[SLOT * fs + gp], Gm = (TC)F.G[SLOT * fs + gm];
-    const TC np = (TC)F.n[ip], nm = (TC)F.n[im];
+    TM qp[4], qm[4];
+    load4(F.nj + 4 * (size_t)ip, qp);
+    load4(F.nj + 4 * (size_t)im, qm);
+    const TC np = (TC)qp[0], nm = (TC)qm[0];
     TC sjp = TC(0), sjm = TC(0);
     if constexpr (SX != 0) {
-        sjp += TC(SX) * (TC)F.j[ip];
-        sjm += TC(SX) * (TC)F.j[im];
+        sjp += TC(SX) * (TC)qp[1];
+        sjm += TC(SX) * (TC)qm[1];
     }
     if constexpr (SY != 0) {
-        sjp += TC(SY) * (TC)F.j[fs + ip];
-        sjm += TC(SY) * (TC)F.j[fs + im];
+        sjp += TC(SY) * (TC)qp[2];
+        sjm += TC(SY) * (TC)qm[2];
     }
     if constexpr (SZ != 0) {
-        sjp += TC(SZ) * (TC)F.j[2 * fs + ip];
-        sjm += TC(SZ) * (TC)F.j[2 * fs + im];
+        sjp += TC(SZ) * (TC)qp[3];
+        sjm += TC(SZ) * (TC)qm[3];
     }
     if constexpr (DIAG) {
         sjp *= TC(0.70710678118654752440);
@@ -560,7 +594,13 @@ __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &
 // block, so the rows of the storage reference tables come in through scalar
 // loads.
 template <int SIG, typename TF, typename TM>
-__global__ __launch_bounds__(256) void k_collide(LatticeDev L, StepConst sc, const double *__restrict__ chi,
+// Waves per SIMD the collide kernel is compiled for (register budget
+// 512 / waves).  3 leaves the compiler its natural 131 VGPRs; 4 (114 VGPRs)
+// and more measured slower: fewer shell loads stay in flight.
+#ifndef HSLB_COLLIDE_WAVES
+#define HSLB_COLLIDE_WAVES 3
+#endif
+__global__ __launch_bounds__(256, HSLB_COLLIDE_WAVES) void k_collide(LatticeDev L, StepConst sc, const double *__restrict__ chi,
                                                  const TF *__restrict__ fin, TF *__restrict__ fout,
                                                  Fields<TM> fld, int cpp)
 {
@@ -724,7 +764,7 @@ __device__ __forceinline__ Fields<TM> shift_fields(const Fields<TM> &F, int off)
 {
     Fields<TM> g;
     g.n = F.n + off;
-    g.j = F.j + off;
+    g.nj = F.nj + 4 * (size_t)off;
     g.eb = F.eb + off;
     g.G = F.G + off;
     return g;
