@@ -277,17 +277,14 @@ __host__ __device__ constexpr int isqrt_floor(int v)
     return r;
 }
 
+// Row sums of node r (0 <= r < plane) of padded layer zl (0 .. nz + 2R - 1).
 template <int SIG, typename TM>
-__device__ __forceinline__ void d_rowsum(const LatticeDev &L, const Fields<TM> &fld, TM *__restrict__ rs, int t)
+__device__ __forceinline__ void d_rowsum(const LatticeDev &L, const Fields<TM> &fld, TM *__restrict__ rs, int zl, int r)
 {
     constexpr int R = SIG / 2;
-    const int nrows = L.plane * (L.nz + 2 * R);
-    if (t >= nrows) return;
-    const int zl = t / L.plane;           // 0 .. nz + 2R - 1
-    const int rem = t - zl * L.plane;
-    const int y = rem / L.nx;
-    const int x = rem - y * L.nx;
-    const int p = rem + L.plane * (zl - R + L.hz);
+    const int y = r / L.nx;
+    const int x = r - y * L.nx;
+    const int p = r + L.plane * (zl - R + L.hz);
     const TM *row = fld.n + (p - x);
     TM acc = row[x];
     rs[p] = acc;
@@ -298,21 +295,21 @@ __device__ __forceinline__ void d_rowsum(const LatticeDev &L, const Fields<TM> &
     }
 }
 
+// grid (ceil(plane / 256), nz + 2R)
 template <int SIG, typename TM>
 __global__ __launch_bounds__(256) void k_rowsum(LatticeDev L, Fields<TM> fld, TM *__restrict__ rs)
 {
-    d_rowsum<SIG>(L, fld, rs, blockIdx.x * 256 + threadIdx.x);
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r < L.plane) d_rowsum<SIG>(L, fld, rs, (int)blockIdx.y, r);
 }
 
+// eta_bar of node r (0 <= r < plane) of layer z.
 template <int SIG, typename TM>
 __device__ __forceinline__ void d_ballsum(const LatticeDev &L, double eta_pref, const Fields<TM> &fld,
-                                          const TM *__restrict__ rs, int id)
+                                          const TM *__restrict__ rs, int z, int r)
 {
-    if (id >= L.N) return;
-    const int z = id / L.plane;
-    const int rem = id - z * L.plane;
-    const int y = rem / L.nx;
-    const int x = rem - y * L.nx;
+    const int y = r / L.nx;
+    const int x = r - y * L.nx;
     constexpr int R = SIG / 2;
     double s = 0.0;
 #pragma unroll
@@ -329,14 +326,16 @@ __device__ __forceinline__ void d_ballsum(const LatticeDev &L, double eta_pref, 
             }
         }
     }
-    store_padded(L, fld.eb, rem, z, (TM)(eta_pref * s));
+    store_padded(L, fld.eb, r, z, (TM)(eta_pref * s));
 }
 
+// grid (ceil(plane / 256), nz)
 template <int SIG, typename TM>
 __global__ __launch_bounds__(256) void k_ballsum(LatticeDev L, double eta_pref, Fields<TM> fld,
                                                  const TM *__restrict__ rs)
 {
-    d_ballsum<SIG>(L, eta_pref, fld, rs, blockIdx.x * 256 + threadIdx.x);
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r < L.plane) d_ballsum<SIG>(L, eta_pref, fld, rs, (int)blockIdx.y, r);
 }
 
 // ------------------------------------------ contact values at pair midpoints
@@ -344,35 +343,53 @@ __global__ __launch_bounds__(256) void k_ballsum(LatticeDev L, double eta_pref, 
 // G slot b (bits x=1, y=2, z=4) at node r: g2 of the mean eta_bar over the
 // nodes r + {0,1}^b, i.e. at the midpoint r + b/2 of every lattice pair whose
 // offset has odd components exactly on the axes of b.
-template <typename TM>
-__device__ __forceinline__ void d_gfield(const LatticeDev &L, int model, const Fields<TM> &fld, int id)
+// The closure in FP64.  FP64 fields divide exactly; FP32 fields (which store
+// the result rounded to FP32) take 1/(1-eta)^3 from a single-precision
+// reciprocal refined by two Newton steps in FP64 (24 -> 48 -> full bits).
+template <typename T>
+__device__ __forceinline__ T g2_t(double eta, int model)
 {
-    if (id >= L.N) return;
-    const int z = id / L.plane;
-    const int rem = id - z * L.plane;
-    const int y = rem / L.nx;
-    const int x = rem - y * L.nx;
+    const double om = 1.0 - eta;
+    const double num = model ? (1.0 - 0.5 * eta) : (1.0 - 0.5 * eta + 0.25 * eta * eta);
+    const double d = om * om * om;
+    if constexpr (sizeof(T) == 8) {
+        return num / d;
+    } else {
+        double r = (double)__builtin_amdgcn_rcpf((float)d);
+        r = r * (2.0 - d * r);
+        r = r * (2.0 - d * r);
+        return (T)(num * r);
+    }
+}
+
+// Node r (0 <= r < plane) of layer z.
+template <typename TM>
+__device__ __forceinline__ void d_gfield(const LatticeDev &L, int model, const Fields<TM> &fld, int z, int r)
+{
+    const int y = r / L.nx;
+    const int x = r - y * L.nx;
     const int x1 = wrapc<1>(x, L.nx), y1 = wrapc<1>(y, L.ny);
     const int zp = z + L.hz;
-    auto e = [&](int xx, int yy, int zz) -> double {
-        return (double)fld.eb[xx + L.nx * (yy + L.ny * zz)];
-    };
+    auto e = [&](int xx, int yy, int zz) -> double { return (double)fld.eb[xx + L.nx * (yy + L.ny * zz)]; };
     const double e000 = e(x, y, zp), e100 = e(x1, y, zp), e010 = e(x, y1, zp), e001 = e(x, y, zp + 1);
     const double e110 = e(x1, y1, zp), e101 = e(x1, y, zp + 1), e011 = e(x, y1, zp + 1);
     const size_t fs = L.fld_stride;
-    store_padded(L, fld.G + 0 * fs, rem, z, (TM)g2_of(e000, model));
-    store_padded(L, fld.G + 1 * fs, rem, z, (TM)g2_of(0.5 * (e000 + e100), model));
-    store_padded(L, fld.G + 2 * fs, rem, z, (TM)g2_of(0.5 * (e000 + e010), model));
-    store_padded(L, fld.G + 3 * fs, rem, z, (TM)g2_of(0.25 * ((e000 + e100) + (e010 + e110)), model));
-    store_padded(L, fld.G + 4 * fs, rem, z, (TM)g2_of(0.5 * (e000 + e001), model));
-    store_padded(L, fld.G + 5 * fs, rem, z, (TM)g2_of(0.25 * ((e000 + e100) + (e001 + e101)), model));
-    store_padded(L, fld.G + 6 * fs, rem, z, (TM)g2_of(0.25 * ((e000 + e010) + (e001 + e011)), model));
+    const double h = 0.5, q = 0.25;
+    store_padded(L, fld.G + 0 * fs, r, z, g2_t<TM>(e000, model));
+    store_padded(L, fld.G + 1 * fs, r, z, g2_t<TM>(h * (e000 + e100), model));
+    store_padded(L, fld.G + 2 * fs, r, z, g2_t<TM>(h * (e000 + e010), model));
+    store_padded(L, fld.G + 3 * fs, r, z, g2_t<TM>(q * ((e000 + e100) + (e010 + e110)), model));
+    store_padded(L, fld.G + 4 * fs, r, z, g2_t<TM>(h * (e000 + e001), model));
+    store_padded(L, fld.G + 5 * fs, r, z, g2_t<TM>(q * ((e000 + e100) + (e001 + e101)), model));
+    store_padded(L, fld.G + 6 * fs, r, z, g2_t<TM>(q * ((e000 + e010) + (e001 + e011)), model));
 }
 
+// grid (ceil(plane / 256), nz)
 template <typename TM>
 __global__ __launch_bounds__(256) void k_gfield(LatticeDev L, int model, Fields<TM> fld)
 {
-    d_gfield(L, model, fld, blockIdx.x * 256 + threadIdx.x);
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r < L.plane) d_gfield(L, model, fld, (int)blockIdx.y, r);
 }
 
 // ------------------------------------------------------------ shell force
@@ -809,12 +826,18 @@ __global__ __launch_bounds__(256) void kb_phase(int phase, const SlitDesc *__res
             // the reference rows would spill scalar registers
             if (idx < d.L.N) d_moments(d.L, d.sc.nref_r, fi, F, idx / d.L.plane, idx % d.L.plane);
             break;
-        case 3: d_gfield(d.L, d.sc.g2_model, F, idx); break;
+        case 3:
+            if (idx < d.L.N) d_gfield(d.L, d.sc.g2_model, F, idx / d.L.plane, idx % d.L.plane);
+            break;
         default:
 #define HSLB_BPH(SG)                                                                     \
     case SG:                                                                             \
-        if (phase == 1) d_rowsum<SG>(d.L, F, rsl, idx);                                  \
-        else if (phase == 2) d_ballsum<SG>(d.L, d.sc.eta_pref, F, rsl, idx);            \
+        if (phase == 1) {                                                                \
+            if (idx < d.L.plane * (d.L.nz + 2 * (SG / 2)))                               \
+                d_rowsum<SG>(d.L, F, rsl, idx / d.L.plane, idx % d.L.plane);             \
+        } else if (phase == 2) {                                                         \
+            if (idx < d.L.N) d_ballsum<SG>(d.L, d.sc.eta_pref, F, rsl, idx / d.L.plane, idx % d.L.plane); \
+        }                                                                                \
         else batch_collide<SG>(d.L, d.sc, ch, fi, fo, F, idx);                           \
         break;
             switch (d.sigma) {
@@ -958,7 +981,7 @@ hipError_t launch_smooth2(hipStream_t s, const LatticeDev &L, int sigma, double 
 {
     const dim3 b(256);
     const int R = sigma / 2;
-    const dim3 g1(blocks_for(L.plane * (L.nz + 2 * R))), g2(blocks_for(L.N));
+    const dim3 g1(blocks_for(L.plane), L.nz + 2 * R), g2(blocks_for(L.plane), L.nz);
 #define HSLB_S2(SG)                                                                                \
     case SG:                                                                                       \
         hipLaunchKernelGGL((k_rowsum<SG, TM>), g1, b, 0, s, L, fld, rs);                           \
@@ -981,7 +1004,7 @@ hipError_t launch_smooth2(hipStream_t s, const LatticeDev &L, int sigma, double 
 template <typename TM>
 hipError_t launch_gfield(hipStream_t s, const LatticeDev &L, int g2_model, Fields<TM> fld)
 {
-    hipLaunchKernelGGL(k_gfield<TM>, dim3(blocks_for(L.N)), dim3(256), 0, s, L, g2_model, fld);
+    hipLaunchKernelGGL(k_gfield<TM>, dim3(blocks_for(L.plane), L.nz), dim3(256), 0, s, L, g2_model, fld);
     return hipGetLastError();
 }
 
