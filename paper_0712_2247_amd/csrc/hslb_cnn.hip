@@ -77,7 +77,10 @@ __device__ __forceinline__ int zsrc(const Geo &g, int z)
 // the tile reads, 20 x 8 x 8 with the halo of 2, are staged in LDS once (x
 // and y wrapped, z wrapped or zero beyond walls); every tap's A operand then
 // comes from LDS.  cin = 32: 64 B per node (80 KB); cin = 4: 8 B; cin = 1: 2 B.
-constexpr int TX = 16, TY = 4, TZ = 4;
+#ifndef HSLB_CNN_TZ
+#define HSLB_CNN_TZ 4
+#endif
+constexpr int TX = 16, TY = 4, TZ = HSLB_CNN_TZ;
 constexpr int HX = TX + 4, HY = TY + 4, HZ = TZ + 4, HNODES = HX * HY * HZ;
 constexpr int ROWS = TZ;
 

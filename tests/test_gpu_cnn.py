@@ -72,8 +72,11 @@ def dgelu_bound(da, daabs, z):
     return np.abs(cnn.gelu_grad(z)) * EPS_ACC * daabs + EPS_F32 * np.abs(da) * dphi
 
 
-@pytest.mark.parametrize("zper", [True, False])
-def test_forward_layers(zper):
+@pytest.mark.parametrize("zper,nz", [(True, NZ), (False, NZ), (False, 9)])
+def test_forward_layers(zper, nz):
+    """Every layer of the forward pass; nz = 6 and 9 leave a partial last
+    z tile of the 16 x 4 x 4 output blocks."""
+    NZ = nz
     shape = (NZ, NY, NX)
     N = NX * NY * NZ
     w = weights(21)
@@ -355,3 +358,36 @@ def test_corrected_network_schedule_matches_oracle():
     assert en <= 1e-6 and eu <= 1e-4
     checks, fallback, _, _ = hslb.hslb_surrogate_stats(s.ctx)
     assert checks == 3 and fallback == 0
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_snapshot_from_a_lattice_against_oracle(precision):
+    """A snapshot captured from a lattice state holds the network input
+    bf16(pi sigma^3 n / 6) and the target C1 / fs (exact force without the
+    external field): with zero weights the loss is the mean square of the
+    target, with random weights the output is the oracle network on the same
+    state."""
+    wl = workloads.slit("snap-32x8x28", 32, 8, 24, 4, 0.22, 1.0, 1e-5, 10, "f64", 1030, 0.02)
+    s = hslb.Sim.from_workload(wl, precision=precision)
+    n, u = wl.fields()
+    s.init(n, u)
+    s.step(7)
+    o = oracle.Oracle(**wl.params())
+    o.init(n, u)
+    o.step(7)
+    m, _ = o.moments()
+    g = np.array(wl.accel)[:, None, None, None]
+    mask = cnn.fluid_mask(wl.nz, wl.ny, wl.nx, wl.wall_lo, wl.wall_hi)
+    target = (o.force() - m[None] * g) / cnn.force_scale(wl.sigma)
+    tol = 1e-9 if precision == "f64" else 1e-5
+    tr = hslb.Trainer(20000, 10000)
+    k = tr.add(s)
+    tr.set_weights(np.zeros(hslb.HSLB_CNN_NWEIGHTS, dtype=np.float32))
+    L = tr.eval(k)
+    L_or = float(((target * mask[None]) ** 2).sum() / (3 * mask.sum()))
+    assert L == pytest.approx(L_or, rel=max(tol, 1e-6))
+    w = weights(29, out_scale=1e-2)
+    tr.set_weights(w)
+    _, out = tr.eval(k, want_out=True)
+    ref = cnn.forward(w.astype(np.float64), cnn.eta_field(m, wl.sigma), zper=False)["out"]
+    assert rel(out, ref) <= 1e-3   # bf16 near-tie flips, as in the trainer test

@@ -300,3 +300,44 @@ def test_uniform_fluid_zero_force_gpu():
         g = hslb.Sim(16, 16, 16, 6, 1.0, precision=precision)
         g.init(np.full((16, 16, 16), nb))
         assert np.abs(g.force()).max() <= 1e-15 * scale, precision
+
+
+def test_zero_steps_is_a_no_op():
+    wl = workloads.slit_small_f64()
+    n, u = wl.fields()
+    g = hslb.Sim.from_workload(wl)
+    g.init(n, u)
+    g.step(3)
+    f = g.get_populations()
+    g.step(0)
+    assert hslb.hslb_step_count(g.ctx) == 3 and np.array_equal(g.get_populations(), f)
+
+
+@pytest.mark.parametrize("sigma", [2, 3])
+def test_single_fluid_layer_slit(sigma):
+    """The thinnest slit: one fluid layer between walls of ceil(sigma/2)
+    layers (every shell and ball read beyond the layer is a wall read)."""
+    w = workloads.wall_layers(sigma)
+    nx, ny, nz = 10, 9, 2 * w + 1
+    nb = workloads.number_density(0.2, sigma)
+    n, u = workloads.random_state((nz, ny, nx), nb, 0.02, 1e-3, seed=61, solid_lo=w, solid_hi=w)
+    g, o = pair(nx, ny, nz, sigma, 0.9, accel=(1e-5, 0, 0), walls=w)
+    g.init(n, u)
+    o.init(n, u)
+    g.step(20)
+    o.step(20)
+    assert rel(g.get_populations(), o.get_populations()) <= 1e-12
+
+
+def test_batch_of_one_slit_is_the_single_lattice():
+    wl = workloads.ensemble()[7].with_size(nx=16, ny=16, noise=0.01)
+    b = hslb.Batch([wl], precision="f64")
+    b.init_all()
+    b.step(30)
+    g = hslb.Sim.from_workload(wl, precision="f64")
+    n, u = wl.fields()
+    g.init(n, u)
+    g.step(30)
+    pn, pu = b.profiles(0)
+    gn, gu = g.profiles()
+    assert rel(pn, gn) <= 1e-12 and rel(pu[0], gu[0]) <= 1e-12
