@@ -332,18 +332,19 @@ __global__ __launch_bounds__(256) void k_wgrad_ch(Geo g, RowSplit rs, int cout, 
                 }
 }
 
-// dW[co][ci][t] = sum over chunks, t = gq * 5 + d
+// dW[co][ci][t] = sum over chunks, t = gq * 5 + d; threads run over co
+// fastest, then ci, so that neighbouring threads read neighbouring partials
 __global__ __launch_bounds__(256) void k_wgrad_ch_reduce(int chunks, int nb16, int cout, const float *__restrict__ partial,
                                                          float *__restrict__ dW)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= cout * 32 * NT) return;
-    const int t = i % NT, ci = (i / NT) % 32, co = i / (NT * 32);
+    const int co = i % cout, ci = (i / cout) % 32, t = i / (cout * 32);
     const int gq = t / 5, d = t % 5;
     double s = 0.0;
     for (int c = 0; c < chunks; ++c)
         s += partial[(((size_t)(c * 25 + gq) * 5 + d) * 32 + ci) * nb16 + co];
-    dW[i] = (float)s;
+    dW[(co * 32 + ci) * NT + t] = (float)s;
 }
 
 // Layer 1: M = tap (8 x 16, taps >= 125 zero), N = output channel (2 x 16),
@@ -402,16 +403,16 @@ __global__ __launch_bounds__(256) void k_wgrad_tap(Geo g, RowSplit rs, const uin
             for (int j = 0; j < 4; ++j) out[(16 * mi + 4 * lg + j) * 32 + 16 * nb + li] = acc[mi][nb][j];
 }
 
-// dW1[co][0][t]
+// dW1[co][0][t]; threads run over co fastest (neighbouring partials)
 __global__ __launch_bounds__(256) void k_wgrad_tap_reduce(int chunks, const float *__restrict__ partial,
                                                           float *__restrict__ dW)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= 32 * NT) return;
-    const int t = i % NT, co = i / NT;
+    const int co = i % 32, t = i / 32;
     double s = 0.0;
     for (int c = 0; c < chunks; ++c) s += partial[((size_t)c * 128 + t) * 32 + co];
-    dW[i] = (float)s;
+    dW[co * NT + t] = (float)s;
 }
 
 // --------------------------------------------------------- reductions
