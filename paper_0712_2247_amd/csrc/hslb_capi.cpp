@@ -360,11 +360,26 @@ public:
         return launch("gfield", [&] { return launch_gfield<TM>(st(), L_, sc_.g2_model, fld_); });
     }
 
+    // whole x-rows per 256-thread block: moments and row sums in one launch
+    bool fused_rows() const { return 256 % L_.nx == 0 && L_.plane % 256 == 0; }
+
     int one_step()
     {
-        int rc = launch("moments", [&] { return launch_moments<TF, TM>(st(), L_, nref_d_, f_[cur_], fld_); });
-        if (rc) return rc;
-        if (sc_.hs_on && (rc = fields_hs())) return rc;
+        int rc;
+        if (sc_.hs_on && fused_rows()) {
+            rc = launch("moments", [&] {
+                return launch_moments_rs<TF, TM>(st(), L_, sigma_, nref_d_, f_[cur_], fld_, rs_);
+            });
+            if (rc) return rc;
+            rc = launch("smooth", [&] { return launch_ballsum<TM>(st(), L_, sigma_, sc_.eta_pref, fld_, rs_); });
+            if (rc) return rc;
+            rc = launch("gfield", [&] { return launch_gfield<TM>(st(), L_, sc_.g2_model, fld_); });
+            if (rc) return rc;
+        } else {
+            rc = launch("moments", [&] { return launch_moments<TF, TM>(st(), L_, nref_d_, f_[cur_], fld_); });
+            if (rc) return rc;
+            if (sc_.hs_on && (rc = fields_hs())) return rc;
+        }
         rc = launch("collide", [&] {
             return launch_collide<TF, TM>(st(), L_, sigma_, sc_, chi_d_, f_[cur_], f_[1 - cur_], fld_);
         });

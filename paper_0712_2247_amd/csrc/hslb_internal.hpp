@@ -99,6 +99,15 @@ hipError_t launch_smooth(hipStream_t s, const LatticeDev &L, int sigma, double e
                          Fields<TM> fld);
 template <typename TM>
 hipError_t launch_gfield(hipStream_t s, const LatticeDev &L, int g2_model, Fields<TM> fld);
+// Moments plus the row sums of the two-pass ball sum in one launch; returns
+// hipErrorInvalidValue (launching nothing) unless nx divides 256 and the plane
+// is a multiple of 256.  Then launch_ballsum completes eta_bar.
+template <typename TF, typename TM>
+hipError_t launch_moments_rs(hipStream_t s, const LatticeDev &L, int sigma, const double *nref, const TF *f,
+                             Fields<TM> fld, TM *rs);
+template <typename TM>
+hipError_t launch_ballsum(hipStream_t s, const LatticeDev &L, int sigma, double eta_pref, Fields<TM> fld,
+                          const TM *rs);
 // Two-pass ball sum; rs holds (sigma/2 + 1) padded fields of row sums.
 template <typename TM>
 hipError_t launch_smooth2(hipStream_t s, const LatticeDev &L, int sigma, double eta_pref, Fields<TM> fld,

@@ -205,8 +205,8 @@ __global__ __launch_bounds__(256) void k_layer_means(LatticeDev L, const TF *__r
 // Node r of layer z (0 <= r < plane).  Called with a block-uniform z from the
 // layer-indexed grid, so the reference row is read through scalar loads.
 template <typename TF, typename TM>
-__device__ __forceinline__ void d_moments(const LatticeDev &L, const double *__restrict__ nref,
-                                          const TF *__restrict__ f, const Fields<TM> &fld, int z, int r)
+__device__ __forceinline__ TM d_moments(const LatticeDev &L, const double *__restrict__ nref,
+                                        const TF *__restrict__ f, const Fields<TM> &fld, int z, int r)
 {
     const int id = z * L.plane + r;
     double n = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
@@ -226,6 +226,7 @@ __device__ __forceinline__ void d_moments(const LatticeDev &L, const double *__r
     }
     store_padded(L, fld.n, r, z, (TM)n);
     store_padded4(L, fld.nj, r, z, (TM)n, (TM)jx, (TM)jy, (TM)jz);
+    return (TM)n;
 }
 
 // grid (ceil(plane / 256), nz): x = chunk of the layer, y = layer
@@ -235,6 +236,39 @@ __global__ __launch_bounds__(256) void k_moments(LatticeDev L, const double *__r
 {
     const int r = blockIdx.x * 256 + threadIdx.x;
     if (r < L.plane) d_moments(L, nref, f, fld, (int)blockIdx.y, r);
+}
+
+// Moments fused with the row sums of the two-pass ball sum: the block holds
+// whole x-rows of layer z (nx divides 256, plane a multiple of 256), so each
+// node's row sums rs[w], w = 0..R, come from the block's densities in LDS.
+// They are written at the padded layer of z and, for a periodic z axis, at
+// its images within the padded range the ball sum reads, [hz - R, nz + hz + R).
+template <int SIG, typename TF, typename TM>
+__global__ __launch_bounds__(256) void k_moments_rs(LatticeDev L, const double *__restrict__ nref,
+                                                    const TF *__restrict__ f, Fields<TM> fld, TM *__restrict__ rs)
+{
+    constexpr int R = SIG / 2;
+    __shared__ TM sn[256];
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    const int z = (int)blockIdx.y;
+    sn[threadIdx.x] = d_moments(L, nref, f, fld, z, r);
+    __syncthreads();
+    const int x = (int)threadIdx.x % L.nx;
+    const int row = (int)threadIdx.x - x;
+    TM acc[R + 1];
+    acc[0] = sn[threadIdx.x];
+#pragma unroll
+    for (int w = 1; w <= R; ++w) acc[w] = acc[w - 1] + (sn[row + wrapr(x - w, L.nx)] + sn[row + wrapr(x + w, L.nx)]);
+    int p0 = z + L.hz, p1 = p0;
+    if (L.zper) {
+        while (p0 - L.nz >= L.hz - R) p0 -= L.nz;
+        p1 = L.nz + L.hz + R - 1;
+    }
+    for (int p = p0; p <= p1; p += L.nz) {
+        const size_t q = (size_t)r + (size_t)L.plane * p;
+#pragma unroll
+        for (int w = 0; w <= R; ++w) rs[(size_t)w * L.fld_stride + q] = acc[w];
+    }
 }
 
 // ------------------------------------------------- coarse-grained density
@@ -617,13 +651,15 @@ template <int SIG, typename TF, typename TM>
 #ifndef HSLB_COLLIDE_WAVES
 #define HSLB_COLLIDE_WAVES 3
 #endif
+
 __global__ __launch_bounds__(256, HSLB_COLLIDE_WAVES) void k_collide(LatticeDev L, StepConst sc, const double *__restrict__ chi,
                                                  const TF *__restrict__ fin, TF *__restrict__ fout,
                                                  Fields<TM> fld, int cpp)
 {
     const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int zl = lb / cpp;
-    const int r = (lb - zl * cpp) * 256 + threadIdx.x;
+    const int c = lb - zl * cpp;
+    const int r = c * 256 + threadIdx.x;
     const int z = (L.zper ? 0 : L.wall_lo) + zl;
     if (r < L.plane) d_collide<SIG>(L, sc, chi, fin, fout, fld, z, r);
 }
@@ -1001,6 +1037,42 @@ hipError_t launch_smooth2(hipStream_t s, const LatticeDev &L, int sigma, double 
     return hipGetLastError();
 }
 
+template <typename TF, typename TM>
+hipError_t launch_moments_rs(hipStream_t s, const LatticeDev &L, int sigma, const double *nref, const TF *f,
+                             Fields<TM> fld, TM *rs)
+{
+    if (256 % L.nx != 0 || L.plane % 256 != 0) return hipErrorInvalidValue;
+    const dim3 g(L.plane / 256, L.nz), b(256);
+    switch (sigma) {
+    case 2: hipLaunchKernelGGL((k_moments_rs<2, TF, TM>), g, b, 0, s, L, nref, f, fld, rs); break;
+    case 3: hipLaunchKernelGGL((k_moments_rs<3, TF, TM>), g, b, 0, s, L, nref, f, fld, rs); break;
+    case 4: hipLaunchKernelGGL((k_moments_rs<4, TF, TM>), g, b, 0, s, L, nref, f, fld, rs); break;
+    case 5: hipLaunchKernelGGL((k_moments_rs<5, TF, TM>), g, b, 0, s, L, nref, f, fld, rs); break;
+    case 6: hipLaunchKernelGGL((k_moments_rs<6, TF, TM>), g, b, 0, s, L, nref, f, fld, rs); break;
+    case 7: hipLaunchKernelGGL((k_moments_rs<7, TF, TM>), g, b, 0, s, L, nref, f, fld, rs); break;
+    case 8: hipLaunchKernelGGL((k_moments_rs<8, TF, TM>), g, b, 0, s, L, nref, f, fld, rs); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename TM>
+hipError_t launch_ballsum(hipStream_t s, const LatticeDev &L, int sigma, double eta_pref, Fields<TM> fld, const TM *rs)
+{
+    const dim3 g(blocks_for(L.plane), L.nz), b(256);
+    switch (sigma) {
+    case 2: hipLaunchKernelGGL((k_ballsum<2, TM>), g, b, 0, s, L, eta_pref, fld, rs); break;
+    case 3: hipLaunchKernelGGL((k_ballsum<3, TM>), g, b, 0, s, L, eta_pref, fld, rs); break;
+    case 4: hipLaunchKernelGGL((k_ballsum<4, TM>), g, b, 0, s, L, eta_pref, fld, rs); break;
+    case 5: hipLaunchKernelGGL((k_ballsum<5, TM>), g, b, 0, s, L, eta_pref, fld, rs); break;
+    case 6: hipLaunchKernelGGL((k_ballsum<6, TM>), g, b, 0, s, L, eta_pref, fld, rs); break;
+    case 7: hipLaunchKernelGGL((k_ballsum<7, TM>), g, b, 0, s, L, eta_pref, fld, rs); break;
+    case 8: hipLaunchKernelGGL((k_ballsum<8, TM>), g, b, 0, s, L, eta_pref, fld, rs); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename TM>
 hipError_t launch_gfield(hipStream_t s, const LatticeDev &L, int g2_model, Fields<TM> fld)
 {
@@ -1130,10 +1202,13 @@ hipError_t launch_batch_profiles(hipStream_t s, const SlitDesc *desc, const Work
     template hipError_t launch_smooth<TM>(hipStream_t, const LatticeDev &, int, double, Fields<TM>); \
     template hipError_t launch_gfield<TM>(hipStream_t, const LatticeDev &, int, Fields<TM>);         \
     template hipError_t launch_smooth2<TM>(hipStream_t, const LatticeDev &, int, double, Fields<TM>, TM *); \
+    template hipError_t launch_ballsum<TM>(hipStream_t, const LatticeDev &, int, double, Fields<TM>, const TM *); \
     template hipError_t launch_unpad<TM>(hipStream_t, const LatticeDev &, const TM *, double *);
 #define HSLB_INST_TFTM(TF, TM)                                                                              \
     template hipError_t launch_moments<TF, TM>(hipStream_t, const LatticeDev &, const double *, const TF *, \
                                                Fields<TM>);                                                 \
+    template hipError_t launch_moments_rs<TF, TM>(hipStream_t, const LatticeDev &, int, const double *,      \
+                                                  const TF *, Fields<TM>, TM *);                            \
     template hipError_t launch_collide<TF, TM>(hipStream_t, const LatticeDev &, int, const StepConst &,    \
                                                const double *, const TF *, TF *, Fields<TM>);               \
     template hipError_t launch_force<TF, TM>(hipStream_t, const LatticeDev &, int, const StepConst &,      \
