@@ -95,9 +95,6 @@ template <typename TF, typename TM>
 hipError_t launch_moments(hipStream_t s, const LatticeDev &L, const double *nref, const TF *f,
                           Fields<TM> fld);
 template <typename TM>
-hipError_t launch_smooth(hipStream_t s, const LatticeDev &L, int sigma, double eta_pref,
-                         Fields<TM> fld);
-template <typename TM>
 hipError_t launch_gfield(hipStream_t s, const LatticeDev &L, int g2_model, Fields<TM> fld);
 // Moments plus the row sums of the two-pass ball sum in one launch; returns
 // hipErrorInvalidValue (launching nothing) unless nx divides 256 and the plane

@@ -273,32 +273,6 @@ __global__ __launch_bounds__(256) void k_moments_rs(LatticeDev L, const double *
 
 // ------------------------------------------------- coarse-grained density
 
-template <int SIG, typename TM>
-__global__ __launch_bounds__(256) void k_smooth(LatticeDev L, double eta_pref, Fields<TM> fld)
-{
-    const int id = blockIdx.x * 256 + threadIdx.x;
-    if (id >= L.N) return;
-    const int z = id / L.plane;
-    const int rem = id - z * L.plane;
-    const int y = rem / L.nx;
-    const int x = rem - y * L.nx;
-    constexpr int R = SIG / 2;
-    double s = 0.0;
-#pragma unroll
-    for (int oz = -R; oz <= R; ++oz) {
-#pragma unroll
-        for (int oy = -R; oy <= R; ++oy) {
-            const int yy = wrapr(y + oy, L.ny);
-            const TM *row = fld.n + L.nx * (yy + L.ny * (z + L.hz + oz));
-#pragma unroll
-            for (int ox = -R; ox <= R; ++ox) {
-                if (4 * (ox * ox + oy * oy + oz * oz) <= SIG * SIG) s += (double)row[wrapr(x + ox, L.nx)];
-            }
-        }
-    }
-    store_padded(L, fld.eb, rem, z, (TM)(eta_pref * s));
-}
-
 // The ball sum in two passes.  Pass 1 (k_rowsum): for every node of the
 // padded z range the ball needs, the sums of n over the centred x segments of
 // half-width w = 0..R, rs[w] (at most 2R+1 reads per node).  Pass 2
@@ -995,23 +969,6 @@ hipError_t launch_moments(hipStream_t s, const LatticeDev &L, const double *nref
 }
 
 template <typename TM>
-hipError_t launch_smooth(hipStream_t s, const LatticeDev &L, int sigma, double eta_pref, Fields<TM> fld)
-{
-    const dim3 g(blocks_for(L.N)), b(256);
-    switch (sigma) {
-    case 2: hipLaunchKernelGGL((k_smooth<2, TM>), g, b, 0, s, L, eta_pref, fld); break;
-    case 3: hipLaunchKernelGGL((k_smooth<3, TM>), g, b, 0, s, L, eta_pref, fld); break;
-    case 4: hipLaunchKernelGGL((k_smooth<4, TM>), g, b, 0, s, L, eta_pref, fld); break;
-    case 5: hipLaunchKernelGGL((k_smooth<5, TM>), g, b, 0, s, L, eta_pref, fld); break;
-    case 6: hipLaunchKernelGGL((k_smooth<6, TM>), g, b, 0, s, L, eta_pref, fld); break;
-    case 7: hipLaunchKernelGGL((k_smooth<7, TM>), g, b, 0, s, L, eta_pref, fld); break;
-    case 8: hipLaunchKernelGGL((k_smooth<8, TM>), g, b, 0, s, L, eta_pref, fld); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template <typename TM>
 hipError_t launch_smooth2(hipStream_t s, const LatticeDev &L, int sigma, double eta_pref, Fields<TM> fld,
                           TM *rs)
 {
@@ -1199,7 +1156,6 @@ hipError_t launch_batch_profiles(hipStream_t s, const SlitDesc *desc, const Work
     template hipError_t launch_batch_profiles<TF>(hipStream_t, const SlitDesc *, const WorkItem *, int,     \
                                                   const int *, const TF *, double *);
 #define HSLB_INST_TM(TM)                                                                              \
-    template hipError_t launch_smooth<TM>(hipStream_t, const LatticeDev &, int, double, Fields<TM>); \
     template hipError_t launch_gfield<TM>(hipStream_t, const LatticeDev &, int, Fields<TM>);         \
     template hipError_t launch_smooth2<TM>(hipStream_t, const LatticeDev &, int, double, Fields<TM>, TM *); \
     template hipError_t launch_ballsum<TM>(hipStream_t, const LatticeDev &, int, double, Fields<TM>, const TM *); \
