@@ -1,0 +1,270 @@
+"""Reruns of the paper's numerical validation (section "Numerical validation",
+Figs. 1-4) on the engine.
+
+Host orchestration only: every step runs in libhslb.so through ``hslb.Sim``;
+this module sets up the runs, decides when a run has converged and reduces
+the layer profiles the engine returns to the quantities the figures plot.
+The closed forms the paper compares against (the Longuet-Higgins-Pople and
+Enskog viscosities of the Fig. 1 caption, the Navier-Stokes parabola of
+Fig. 4) are evaluated here for the report.
+
+Units: lattice spacing, time step and particle mass 1, k_B T = v_T^2 = 1/3;
+the sphere diameter sigma is an integer number of lattice spacings.  The
+figures' reduced density is n* = n sigma^3; a slit of width L holds L fluid
+layers between halfway bounce-back walls; the driving field is a force
+per particle along x.  Every state is laterally uniform (no noise): a
+16 x 16 lateral grid then carries the same layer profiles as an infinite one.
+
+    python -m paper_0712_2247_amd.experiments --out results.json [--sigma 8]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+from typing import Dict, Sequence
+
+import numpy as np
+
+from . import hslb, workloads
+
+VT2 = 1.0 / 3.0
+LATERAL = 16
+
+
+def g2_paper(eta: float) -> float:
+    """Contact value of the pair correlation as the paper prints it
+    (section "Methods and Results"); only the reference curves use it."""
+    return (1.0 - eta / 2.0 + eta * eta / 4.0) / (1.0 - eta) ** 3
+
+
+def eta_of(n_star: float) -> float:
+    return math.pi * n_star / 6.0
+
+
+def viscosity_closed_forms(n_star: float) -> Dict[str, float]:
+    """Collisional shear viscosity in units of sqrt(m k_B T) / sigma^2:
+    the Longuet-Higgins-Pople form as the Fig. 1 caption prints it, the same
+    form with the sqrt(pi) that the current coupling 2/(v_T sqrt(pi)) of
+    eq. (12) implies, and the collisional part of Enskog's viscosity from
+    the same caption."""
+    g = g2_paper(eta_of(n_star))
+    lhp = 4.0 / 15.0 * g * n_star ** 2
+    b = 2.0 * math.pi / 3.0 * n_star
+    enskog = 5.0 / 16.0 / math.sqrt(math.pi) * (0.8 * b + 0.7737 * g * b * b)
+    return {"lhp_printed": lhp, "lhp_sqrt_pi": math.sqrt(math.pi) * lhp, "enskog": enskog}
+
+
+def _slit_sim(sigma: int, H: int, n_star: float, tau: float, g: float, precision: str):
+    wl = workloads.slit(f"slit-H{H}-s{sigma}-n{n_star}", LATERAL, LATERAL, H, sigma, eta_of(n_star),
+                        tau, g, 0, precision, 0, 0.0)
+    s = hslb.Sim.from_workload(wl, precision=precision)
+    n, u = wl.fields()
+    s.init(n, u)
+    return wl, s
+
+
+def _run_to_steady(s, wl, key: str, block: int, max_steps: int, tol: float):
+    """Steps in blocks until the largest change of the fluid layers' profile
+    `key` ('n' or 'ux') over a block is below tol times its largest value."""
+    fl = slice(wl.wall_lo, wl.nz - wl.wall_hi)
+    prev = None
+    done = 0
+    change = math.inf
+    while done < max_steps:
+        s.step(block)
+        done += block
+        pn, pu = s.profiles()
+        cur = (pn if key == "n" else pu[0])[fl].copy()
+        if not np.isfinite(cur).all():
+            raise RuntimeError(f"{wl.name}: non-finite profile after {done} steps")
+        if prev is not None:
+            change = float(np.abs(cur - prev).max() / np.abs(cur).max())
+            if change < tol:
+                break
+        prev = cur
+    return done, change
+
+
+def _layer_velocity_midstep(s, wl) -> np.ndarray:
+    """u_x of each fluid layer with half the step's force added to the current,
+    (sum of j_x + F_x / 2) / (sum of n): the velocity of the second-order
+    reading of the forcing, reported beside the unshifted one."""
+    n, u = s.moments()
+    F = s.force()
+    fl = slice(wl.wall_lo, wl.nz - wl.wall_hi)
+    jx = (n * u[0] + 0.5 * F[0])[fl].sum(axis=(1, 2))
+    return jx / n[fl].sum(axis=(1, 2))
+
+
+def near_wall_drop(u: np.ndarray) -> float:
+    """Largest fall of u met when walking from a wall to the centre, in units
+    of max u (0 for a profile rising monotonically from both walls)."""
+    h = (u.size + 1) // 2
+    best = 0.0
+    for half in (u[:h], u[::-1][:h]):
+        run = np.maximum.accumulate(half)
+        best = max(best, float((run - half).max()))
+    return best / float(np.abs(u).max())
+
+
+def viscosity_sweep(n_stars: Sequence[float], sigma: int = 8, tau: float = 1.0, L: int = 256,
+                    amp: float = 1e-4, precision: str = "f64", log=None) -> Dict:
+    """Fig. 1: the collisional shear viscosity from the decay of a transverse
+    wave u_x = amp sin(2 pi z / L) in a periodic box (16 x 16 x L).  The
+    layer-averaged shear amplitude is read at t1 and t2 (the wave decays by
+    about e between them) and nu = -ln(a2/a1) / ((t2 - t1) k^2); the BGK part
+    (tau - 1/2)/3 is subtracted and the rest converted to the reduced
+    viscosity eta* = n* nu_c / (sigma v_T)."""
+    k = 2.0 * math.pi / L
+    z = np.arange(L)
+    ph = np.exp(-1j * k * z)
+    rows = []
+    for ns in n_stars:
+        eta = eta_of(ns)
+        nb = workloads.number_density(eta, sigma)
+        ref = viscosity_closed_forms(ns)
+        nu_guess = (tau - 0.5) / 3.0 + ref["lhp_sqrt_pi"] * sigma * math.sqrt(VT2) / ns
+        t1 = max(20, int(0.1 / (nu_guess * k * k)))
+        t2 = t1 + max(50, int(1.0 / (nu_guess * k * k)))
+        s = hslb.Sim(LATERAL, LATERAL, L, sigma, tau, precision=precision)
+        n0 = np.full((L, LATERAL, LATERAL), nb)
+        u0 = np.zeros((3,) + n0.shape)
+        u0[0] = (amp * np.sin(k * z))[:, None, None]
+        s.init(n0, u0)
+        amps = []
+        done = 0
+        for t in (t1, t2):
+            s.step(t - done)
+            done = t
+            pn, pu = s.profiles()
+            amps.append(abs(((pn * pu[0]) * ph).sum()) / L)
+        s.close()
+        nu = -math.log(amps[1] / amps[0]) / ((t2 - t1) * k * k)
+        nu_c = nu - (tau - 0.5) / 3.0
+        row = {"n_star": ns, "eta": eta, "t1": t1, "t2": t2, "nu": nu, "nu_c": nu_c,
+               "eta_star": ns * nu_c / (sigma * math.sqrt(VT2)), **ref}
+        rows.append(row)
+        if log:
+            log(f"fig1 n* {ns:.3f}: nu {nu:.5f}, eta* {row['eta_star']:.5f} (LHP x sqrt(pi) "
+                f"{ref['lhp_sqrt_pi']:.5f}, printed LHP {ref['lhp_printed']:.5f}, Enskog {ref['enskog']:.5f})")
+    return {"sigma": sigma, "tau": tau, "L": L, "amp": amp, "rows": rows}
+
+
+def statics(n_stars: Sequence[float], L_over_sigma: int = 5, sigma: int = 8, tau: float = 1.0,
+            precision: str = "f64", max_steps: int = 40000, log=None) -> Dict:
+    """Fig. 2 (the lattice Boltzmann side): equilibrium density profiles of
+    a slit of width L = 5 sigma without driving, from the uniform state at
+    n* (the initial mean density).  Reports n(z)/n_b over the fluid layers,
+    the contact value, and the largest deviation from the centre density
+    near the walls (first quarter) and in the central half."""
+    H = L_over_sigma * sigma
+    rows = []
+    for ns in n_stars:
+        wl, s = _slit_sim(sigma, H, ns, tau, 0.0, precision)
+        steps, change = _run_to_steady(s, wl, "n", 500, max_steps, 1e-11)
+        pn, _ = s.profiles()
+        s.close()
+        fl = slice(wl.wall_lo, wl.nz - wl.wall_hi)
+        r = pn[fl] / wl.n_bulk
+        c = slice(H // 4, H - H // 4)
+        nc = float(r[c].mean())
+        q = H // 4
+        dev_wall = float(max(np.abs(r[:q] - nc).max(), np.abs(r[-q:] - nc).max()))
+        row = {"n_star": ns, "steps": steps, "last_change": change, "n_over_nb": r.tolist(),
+               "contact": float(0.5 * (r[0] + r[-1])), "centre": nc, "dev_wall": dev_wall,
+               "dev_centre": float(np.abs(r[c] - nc).max()), "std": float(r.std())}
+        rows.append(row)
+        if log:
+            log(f"fig2 n* {ns:.3f}: {steps} steps, contact {row['contact']:.3f}, centre {nc:.3f}, "
+                f"deviation near walls {dev_wall:.3f}, in the centre {row['dev_centre']:.3f}")
+    return {"sigma": sigma, "tau": tau, "L_over_sigma": L_over_sigma, "rows": rows}
+
+
+def _poiseuille_row(sigma, H, ns, tau, g, precision, max_steps):
+    wl, s = _slit_sim(sigma, H, ns, tau, g, precision)
+    steps, change = _run_to_steady(s, wl, "ux", 1000, max_steps, 1e-8)
+    pn, pu = s.profiles()
+    um = _layer_velocity_midstep(s, wl)
+    s.close()
+    fl = slice(wl.wall_lo, wl.nz - wl.wall_hi)
+    n, u = pn[fl], pu[0][fl]
+    zc = np.arange(H) + 0.5          # distance of each layer from the lower wall plane
+    c = slice(H // 4, H - H // 4)
+    p = np.polyfit(zc[c], u[c], 2)
+    n_centre = float(n[H // 2 - 1:H // 2 + 1].mean())
+    nsc = n_centre * sigma ** 3
+    nu_ns = (tau - 0.5) / 3.0 + viscosity_closed_forms(nsc)["lhp_sqrt_pi"] * sigma * math.sqrt(VT2) / nsc
+    u_ns = g / (2.0 * nu_ns) * zc * (H - zc)
+    return {"n_star": ns, "H": H, "steps": steps, "last_change": change,
+            "n_over_nb": (n / wl.n_bulk).tolist(), "ux": u.tolist(), "ux_midstep": um.tolist(),
+            "u_mean": float((n * u).sum() / n.sum()), "u_max": float(u.max()),
+            "near_wall_drop": near_wall_drop(u),
+            "central_fit_resid": float(np.abs(u[c] - np.polyval(p, zc[c])).max() / u.max()),
+            "nu_fit": float(-g / (2.0 * p[0])), "n_star_centre": nsc, "nu_ns": nu_ns,
+            "u_ns": u_ns.tolist(),
+            "ns_centre_offset": float((u[H // 2] - u_ns[H // 2]) / u_ns[H // 2])}
+
+
+def poiseuille_density(n_stars: Sequence[float], L_over_sigma: int = 10, sigma: int = 8,
+                       tau: float = 1.0, g: float = 2.4e-6, precision: str = "f64",
+                       max_steps: int = 60000, log=None) -> Dict:
+    """Fig. 3: steady streaming profiles u_x(z) of a slit of width L = 10
+    sigma driven by a force g per particle along x, at several densities."""
+    rows = []
+    for ns in n_stars:
+        row = _poiseuille_row(sigma, L_over_sigma * sigma, ns, tau, g, precision, max_steps)
+        rows.append(row)
+        if log:
+            log(f"fig3 n* {ns:.3f}: {row['steps']} steps, mean u {row['u_mean']:.4e}, max u "
+                f"{row['u_max']:.4e}, near-wall drop {row['near_wall_drop']:.3f}")
+    return {"sigma": sigma, "tau": tau, "g": g, "L_over_sigma": L_over_sigma, "rows": rows}
+
+
+def poiseuille_width(widths: Sequence[int], n_star: float = 0.512, sigma: int = 8, tau: float = 1.0,
+                     g: float = 2.4e-6, precision: str = "f64", max_steps: int = 60000, log=None) -> Dict:
+    """Fig. 4: steady streaming profiles at n* = 0.512 for slit widths
+    L = widths x sigma, with the Navier-Stokes parabola g z (L - z) / (2 nu)
+    (nu: the BGK part plus the collisional viscosity of eq. (12) at the
+    centre density) and a quadratic fitted to the central half."""
+    rows = []
+    for w in widths:
+        row = _poiseuille_row(sigma, w * sigma, n_star, tau, g, precision, max_steps)
+        rows.append(row)
+        if log:
+            log(f"fig4 L {w} sigma: {row['steps']} steps, max u {row['u_max']:.4e}, near-wall drop "
+                f"{row['near_wall_drop']:.3f}, central fit residual {row['central_fit_resid']:.2e}, "
+                f"nu fit {row['nu_fit']:.4f} vs Navier-Stokes {row['nu_ns']:.4f}")
+    return {"sigma": sigma, "tau": tau, "g": g, "n_star": n_star, "rows": rows}
+
+
+FIG1_NSTARS = (0.064, 0.128, 0.192, 0.256, 0.32, 0.384, 0.448, 0.512, 0.576, 0.609)
+FIG2_NSTARS = (0.256, 0.512, 0.609)
+FIG3_NSTARS = (0.064, 0.128, 0.256, 0.384, 0.512)
+FIG4_WIDTHS = (5, 10, 15, 20)
+
+
+def run_all(sigma: int = 8, log=print) -> Dict:
+    t0 = time.perf_counter()
+    out = {"fig1": viscosity_sweep(FIG1_NSTARS, sigma=sigma, log=log),
+           "fig2": statics(FIG2_NSTARS, sigma=sigma, log=log),
+           "fig3": poiseuille_density(FIG3_NSTARS, sigma=sigma, log=log),
+           "fig4": poiseuille_width(FIG4_WIDTHS, sigma=sigma, log=log)}
+    out["seconds"] = time.perf_counter() - t0
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--sigma", type=int, default=8)
+    a = ap.parse_args(argv)
+    res = run_all(a.sigma, log=lambda m: print(m, flush=True))
+    with open(a.out, "w") as fh:
+        json.dump(res, fh)
+    print(f"wrote {a.out} ({res['seconds']:.1f} s)", flush=True)
+
+
+if __name__ == "__main__":
+    main()
