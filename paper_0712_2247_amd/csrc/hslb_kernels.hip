@@ -409,6 +409,41 @@ struct NodeCtx {
     TC ckap;  // chi(z) * kappa
 };
 
+// Byte offset, inside its layer, of the node at x + D (xb) or of the row at
+// y + D (yb), periodic in x and y, for elements of ES bytes.  Offsets inside a
+// layer fit 32 bits; the layer and field-slot parts are added to the base
+// pointer, so that a block with uniform z keeps them in scalar registers and a
+// shell read costs one vector add.
+template <int D, int ES>
+__device__ __forceinline__ uint32_t xb(int x, int nx)
+{
+    return (uint32_t)wrapc<D>(x, nx) * (uint32_t)ES;
+}
+template <int D, int ES>
+__device__ __forceinline__ uint32_t yb(int y, int ny, int nx)
+{
+    return __umul24((uint32_t)wrapc<D>(y, ny), (uint32_t)nx * (uint32_t)ES);
+}
+
+// s.j of a loaded (n, jx, jy, jz) for the unit direction with components
+// (SX, SY, SZ) in {-1, 0, 1} (not yet scaled by 1/sqrt(2) on a diagonal).
+template <int SX, int SY, int SZ, typename TM, typename TC>
+__device__ __forceinline__ TC s_dot_j(const TM q[4])
+{
+    if constexpr (SX != 0) {
+        TC s = TC(SX) * (TC)q[1];
+        if constexpr (SY != 0) s += TC(SY) * (TC)q[2];
+        if constexpr (SZ != 0) s += TC(SZ) * (TC)q[3];
+        return s;
+    } else if constexpr (SY != 0) {
+        TC s = TC(SY) * (TC)q[2];
+        if constexpr (SZ != 0) s += TC(SZ) * (TC)q[3];
+        return s;
+    } else {
+        return TC(SZ) * (TC)q[3];
+    }
+}
+
 // Difference of the two elements of one mirrored lattice pair, the corner d of
 // direction q and the corner -d of direction -q:
 //   e+ - e- = G+ [n+ - chi kappa s.(j+ - n+ u)] - G- [n- + chi kappa s.(j- - n- u)]
@@ -417,36 +452,46 @@ struct NodeCtx {
 // exact in floating point for neighbouring values, so that the result keeps
 // full relative precision even in FP32 although the two elements nearly
 // cancel.  `su` is s.u(r) (s scaled by 1/sqrt(2) on the face diagonals).
-template <int DX, int DY, int DZ, int SX, int SY, int SZ, bool DIAG, typename TM, typename TC>
+//
+// LZ: z is uniform over the block (layer-indexed grids); the layer parts of
+// the addresses then stay scalar.  Grids with a per-lane z (batch, k_force)
+// form one 32-bit node index per read instead, which needs fewer registers.
+template <int DX, int DY, int DZ, int SX, int SY, int SZ, bool DIAG, bool LZ, typename TM, typename TC>
 __device__ __forceinline__ TC pair_element(const Fields<TM> &F, const LatticeDev &L, const NodeCtx<TC> &c,
                                            TC su)
 {
-    const size_t fs = L.fld_stride;
-    const int ip = wrapc<DX>(c.x, L.nx) + L.nx * (wrapc<DY>(c.y, L.ny) + L.ny * (c.zp + DZ));
-    const int im = wrapc<-DX>(c.x, L.nx) + L.nx * (wrapc<-DY>(c.y, L.ny) + L.ny * (c.zp - DZ));
     constexpr int SLOT = (DX & 1) | ((DY & 1) << 1) | ((DZ & 1) << 2);
     constexpr int BXP = floordiv2(DX), BYP = floordiv2(DY), BZP = floordiv2(DZ);
     constexpr int BXM = floordiv2(-DX), BYM = floordiv2(-DY), BZM = floordiv2(-DZ);
-    const int gp = wrapc<BXP>(c.x, L.nx) + L.nx * (wrapc<BYP>(c.y, L.ny) + L.ny * (c.zp + BZP));
-    const int gm = wrapc<BXM>(c.x, L.nx) + L.nx * (wrapc<BYM>(c.y, L.ny) + L.ny * (c.zp + BZM));
-    const TC Gp = (TC)F.G[SLOT * fs + gp], Gm = (TC)F.G[SLOT * fs + gm];
+    TC Gp, Gm;
     TM qp[4], qm[4];
-    load4(F.nj + 4 * (size_t)ip, qp);
-    load4(F.nj + 4 * (size_t)im, qm);
+    if constexpr (LZ) {
+        constexpr int NJB = 4 * (int)sizeof(TM);  // bytes of one (n, j) entry
+        constexpr int GB = (int)sizeof(TM);
+        const size_t lay = (size_t)L.plane;
+        const char *njp = (const char *)F.nj + NJB * lay * (size_t)(c.zp + DZ);
+        const char *njm = (const char *)F.nj + NJB * lay * (size_t)(c.zp - DZ);
+        const char *gs = (const char *)F.G + GB * (size_t)SLOT * L.fld_stride;
+        const char *gzp = gs + GB * lay * (size_t)(c.zp + BZP);
+        const char *gzm = gs + GB * lay * (size_t)(c.zp + BZM);
+        Gp = (TC) * (const TM *)(gzp + (xb<BXP, GB>(c.x, L.nx) + yb<BYP, GB>(c.y, L.ny, L.nx)));
+        Gm = (TC) * (const TM *)(gzm + (xb<BXM, GB>(c.x, L.nx) + yb<BYM, GB>(c.y, L.ny, L.nx)));
+        load4((const TM *)(njp + (xb<DX, NJB>(c.x, L.nx) + yb<DY, NJB>(c.y, L.ny, L.nx))), qp);
+        load4((const TM *)(njm + (xb<-DX, NJB>(c.x, L.nx) + yb<-DY, NJB>(c.y, L.ny, L.nx))), qm);
+    } else {
+        const size_t fs = L.fld_stride;
+        const int ip = wrapc<DX>(c.x, L.nx) + L.nx * (wrapc<DY>(c.y, L.ny) + L.ny * (c.zp + DZ));
+        const int im = wrapc<-DX>(c.x, L.nx) + L.nx * (wrapc<-DY>(c.y, L.ny) + L.ny * (c.zp - DZ));
+        const int gp = wrapc<BXP>(c.x, L.nx) + L.nx * (wrapc<BYP>(c.y, L.ny) + L.ny * (c.zp + BZP));
+        const int gm = wrapc<BXM>(c.x, L.nx) + L.nx * (wrapc<BYM>(c.y, L.ny) + L.ny * (c.zp + BZM));
+        Gp = (TC)F.G[SLOT * fs + gp];
+        Gm = (TC)F.G[SLOT * fs + gm];
+        load4(F.nj + 4 * (size_t)ip, qp);
+        load4(F.nj + 4 * (size_t)im, qm);
+    }
     const TC np = (TC)qp[0], nm = (TC)qm[0];
-    TC sjp = TC(0), sjm = TC(0);
-    if constexpr (SX != 0) {
-        sjp += TC(SX) * (TC)qp[1];
-        sjm += TC(SX) * (TC)qm[1];
-    }
-    if constexpr (SY != 0) {
-        sjp += TC(SY) * (TC)qp[2];
-        sjm += TC(SY) * (TC)qm[2];
-    }
-    if constexpr (SZ != 0) {
-        sjp += TC(SZ) * (TC)qp[3];
-        sjm += TC(SZ) * (TC)qm[3];
-    }
+    TC sjp = s_dot_j<SX, SY, SZ, TM, TC>(qp);
+    TC sjm = s_dot_j<SX, SY, SZ, TM, TC>(qm);
     if constexpr (DIAG) {
         sjp *= TC(0.70710678118654752440);
         sjm *= TC(0.70710678118654752440);
@@ -470,27 +515,27 @@ struct Diag {
     static constexpr int SZ = (PL == 0) ? 0 : SB;
 };
 
-template <int PL, int SA, int SB, int LA, int LB, typename TM, typename TC>
+template <int PL, int SA, int SB, int LA, int LB, bool LZ, typename TM, typename TC>
 __device__ __forceinline__ TC diag_pair_element(const Fields<TM> &F, const LatticeDev &L, const NodeCtx<TC> &c,
                                                 TC su)
 {
     using D = Diag<PL, SA, SB, LA, LB>;
-    return pair_element<D::DX, D::DY, D::DZ, D::SX, D::SY, D::SZ, true>(F, L, c, su);
+    return pair_element<D::DX, D::DY, D::DZ, D::SX, D::SY, D::SZ, true, LZ>(F, L, c, su);
 }
 
 // The interpolated quadrature point q = (SA, SB) in plane PL and its mirror -q:
 // W s_q sum_k alpha_k (e+_k - e-_k), k over the four bilinear corners.
-template <int PL, int SA, int SB, int LL, typename TM, typename TC>
+template <int PL, int SA, int SB, int LL, bool LZ, typename TM, typename TC>
 __device__ __forceinline__ void diag_pair(const Fields<TM> &F, const LatticeDev &L, const NodeCtx<TC> &c,
                                           const TC *alpha, TC S[3])
 {
     constexpr int A = (PL == 2) ? 1 : 0;
     constexpr int B = (PL == 0) ? 1 : 2;
     const TC su = TC(0.70710678118654752440) * (TC(SA) * c.u[A] + TC(SB) * c.u[B]);
-    TC d = alpha[0] * diag_pair_element<PL, SA, SB, LL, LL>(F, L, c, su);
-    d += alpha[1] * diag_pair_element<PL, SA, SB, LL, LL + 1>(F, L, c, su);
-    d += alpha[2] * diag_pair_element<PL, SA, SB, LL + 1, LL>(F, L, c, su);
-    d += alpha[3] * diag_pair_element<PL, SA, SB, LL + 1, LL + 1>(F, L, c, su);
+    TC d = alpha[0] * diag_pair_element<PL, SA, SB, LL, LL, LZ>(F, L, c, su);
+    d += alpha[1] * diag_pair_element<PL, SA, SB, LL, LL + 1, LZ>(F, L, c, su);
+    d += alpha[2] * diag_pair_element<PL, SA, SB, LL + 1, LL, LZ>(F, L, c, su);
+    d += alpha[3] * diag_pair_element<PL, SA, SB, LL + 1, LL + 1, LZ>(F, L, c, su);
     const TC w = TC((1.0 / 15.0) * 0.70710678118654752440) * d;
     S[A] += TC(SA) * w;
     S[B] += TC(SB) * w;
@@ -498,25 +543,25 @@ __device__ __forceinline__ void diag_pair(const Fields<TM> &F, const LatticeDev 
 
 // S = sum_q W_q s_q sum_k alpha_qk G_qk [ ... ] over the 18-point rule, with
 // directions taken in (q, -q) pairs (a uniform fluid at rest gives exactly 0).
-template <int SIG, typename TM, typename TC>
+template <int SIG, bool LZ, typename TM, typename TC>
 __device__ __forceinline__ void shell_sum(const Fields<TM> &F, const LatticeDev &L, const NodeCtx<TC> &c,
                                           const TC *alpha, TC S[3])
 {
     constexpr int LL = ell_of(SIG);
     const TC w30 = TC(1.0 / 30.0);
-    S[0] = w30 * pair_element<SIG, 0, 0, 1, 0, 0, false>(F, L, c, c.u[0]);
-    S[1] = w30 * pair_element<0, SIG, 0, 0, 1, 0, false>(F, L, c, c.u[1]);
-    S[2] = w30 * pair_element<0, 0, SIG, 0, 0, 1, false>(F, L, c, c.u[2]);
-    diag_pair<0, 1, 1, LL>(F, L, c, alpha, S);
-    diag_pair<0, 1, -1, LL>(F, L, c, alpha, S);
-    diag_pair<1, 1, 1, LL>(F, L, c, alpha, S);
-    diag_pair<1, 1, -1, LL>(F, L, c, alpha, S);
-    diag_pair<2, 1, 1, LL>(F, L, c, alpha, S);
-    diag_pair<2, 1, -1, LL>(F, L, c, alpha, S);
+    S[0] = w30 * pair_element<SIG, 0, 0, 1, 0, 0, false, LZ>(F, L, c, c.u[0]);
+    S[1] = w30 * pair_element<0, SIG, 0, 0, 1, 0, false, LZ>(F, L, c, c.u[1]);
+    S[2] = w30 * pair_element<0, 0, SIG, 0, 0, 1, false, LZ>(F, L, c, c.u[2]);
+    diag_pair<0, 1, 1, LL, LZ>(F, L, c, alpha, S);
+    diag_pair<0, 1, -1, LL, LZ>(F, L, c, alpha, S);
+    diag_pair<1, 1, 1, LL, LZ>(F, L, c, alpha, S);
+    diag_pair<1, 1, -1, LL, LZ>(F, L, c, alpha, S);
+    diag_pair<2, 1, 1, LL, LZ>(F, L, c, alpha, S);
+    diag_pair<2, 1, -1, LL, LZ>(F, L, c, alpha, S);
 }
 
 // Total force C^(1) + n g at a fluid node with local moments (n, u).
-template <int SIG, typename TM>
+template <int SIG, bool LZ, typename TM>
 __device__ __forceinline__ void node_force(const Fields<TM> &F, const LatticeDev &L, const StepConst &sc,
                                            const double *__restrict__ chi, int x, int y, int z, double n,
                                            const double u[3], double Fo[3])
@@ -549,7 +594,7 @@ __device__ __forceinline__ void node_force(const Fields<TM> &F, const LatticeDev
         c.u[2] = (TC)u[2];
         c.ckap = (TC)(chi[z] * sc.kappa);
         const TC alpha[4] = {(TC)sc.alpha[0], (TC)sc.alpha[1], (TC)sc.alpha[2], (TC)sc.alpha[3]};
-        shell_sum<SIG>(F, L, c, alpha, S);
+        shell_sum<SIG, LZ>(F, L, c, alpha, S);
     }
     const double pn = sc.pref * n;
     Fo[0] = pn * (double)S[0] + n * sc.g[0];
@@ -561,19 +606,32 @@ __device__ __forceinline__ void node_force(const Fields<TM> &F, const LatticeDev
 // ------------------------------------------------- collide and stream
 
 // Node r (0 <= r < plane) of fluid layer z.
-template <int SIG, typename TF, typename TM>
+template <int SIG, bool LZ, typename TF, typename TM>
 __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &sc, const double *__restrict__ chi,
                                           const TF *__restrict__ fin, TF *__restrict__ fout, const Fields<TM> &fld,
                                           int z, int r)
 {
-    const int id = z * L.plane + r;
     const int y = r / L.nx;
     const int x = r - y * L.nx;
 
+    // LZ: byte offsets with the direction and layer parts on the base
+    // pointers and the node's place in its layer as a 32-bit lane offset;
+    // otherwise node indices
+    constexpr uint32_t EB = sizeof(TF);
+    const size_t dstride = EB * (size_t)L.pop_stride;
+    const size_t lstride = EB * (size_t)L.plane;
+    const uint32_t rb = (uint32_t)r * EB;
+    const int id = z * L.plane + r;
     double f[NQ];
     const double *rr = layer_ref(sc.nref_r, z);
+    if constexpr (LZ) {
+        const char *fz = (const char *)fin + lstride * (size_t)z;
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) f[i] = (double)fin[(size_t)i * L.pop_stride + id] + rr[i];
+        for (int i = 0; i < NQ; ++i) f[i] = (double)*(const TF *)(fz + dstride * i + rb) + rr[i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) f[i] = (double)fin[(size_t)i * L.pop_stride + id] + rr[i];
+    }
     double n = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
@@ -588,7 +646,7 @@ __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &
     const double inv_n = (n != 0.0) ? 1.0 / n : 0.0;
     const double u[3] = {jx * inv_n, jy * inv_n, jz * inv_n};
     double Fv[3];
-    node_force<SIG>(fld, L, sc, chi, x, y, z, n, u, Fv);
+    node_force<SIG, LZ>(fld, L, sc, chi, x, y, z, n, u, Fv);
 
     const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     const double omega = 1.0 / sc.tau;
@@ -608,10 +666,20 @@ __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &
             bounce = (zt < L.wall_lo) || (zt >= L.nz - L.wall_hi);
         }
         // stored relative to the reference of the layer it lands in
-        if (bounce)
-            fout[(size_t)OPP[i] * L.pop_stride + id] = (TF)(fp - layer_ref(sc.nref_w, z)[OPP[i]]);
-        else
-            fout[(size_t)i * L.pop_stride + xt + L.nx * (yt + L.ny * zt)] = (TF)(fp - layer_ref(sc.nref_w, zt)[i]);
+        if constexpr (LZ) {
+            char *fo = (char *)fout;
+            if (bounce)
+                *(TF *)(fo + dstride * OPP[i] + lstride * (size_t)z + rb) = (TF)(fp - layer_ref(sc.nref_w, z)[OPP[i]]);
+            else
+                *(TF *)(fo + dstride * i + lstride * (size_t)zt +
+                        ((uint32_t)xt * EB + __umul24((uint32_t)yt, (uint32_t)L.nx * EB))) =
+                    (TF)(fp - layer_ref(sc.nref_w, zt)[i]);
+        } else {
+            if (bounce)
+                fout[(size_t)OPP[i] * L.pop_stride + id] = (TF)(fp - layer_ref(sc.nref_w, z)[OPP[i]]);
+            else
+                fout[(size_t)i * L.pop_stride + xt + L.nx * (yt + L.ny * zt)] = (TF)(fp - layer_ref(sc.nref_w, zt)[i]);
+        }
     }
 }
 
@@ -620,8 +688,9 @@ __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &
 // loads.
 template <int SIG, typename TF, typename TM>
 // Waves per SIMD the collide kernel is compiled for (register budget
-// 512 / waves).  3 leaves the compiler its natural 131 VGPRs; 4 (114 VGPRs)
-// and more measured slower: fewer shell loads stay in flight.
+// 512 / waves).  3 leaves the compiler its natural ~130 VGPRs; 4 and 5
+// (104 and 96 VGPRs, no spills) measured 25 % slower: the shell reads of more
+// resident waves overflow the L1.
 #ifndef HSLB_COLLIDE_WAVES
 #define HSLB_COLLIDE_WAVES 3
 #endif
@@ -635,7 +704,7 @@ __global__ __launch_bounds__(256, HSLB_COLLIDE_WAVES) void k_collide(LatticeDev 
     const int c = lb - zl * cpp;
     const int r = c * 256 + threadIdx.x;
     const int z = (L.zper ? 0 : L.wall_lo) + zl;
-    if (r < L.plane) d_collide<SIG>(L, sc, chi, fin, fout, fld, z, r);
+    if (r < L.plane) d_collide<SIG, true>(L, sc, chi, fin, fout, fld, z, r);
 }
 
 template <int SIG, typename TF, typename TM>
@@ -662,7 +731,7 @@ __global__ __launch_bounds__(256) void k_force(LatticeDev L, StepConst sc, const
         }
         const double inv_n = (n != 0.0) ? 1.0 / n : 0.0;
         const double u[3] = {jx * inv_n, jy * inv_n, jz * inv_n};
-        node_force<SIG>(fld, L, sc, chi, x, y, z, n, u, Fv);
+        node_force<SIG, false>(fld, L, sc, chi, x, y, z, n, u, Fv);
     }
     Fout[id] = Fv[0];
     Fout[L.N + id] = Fv[1];
@@ -809,7 +878,7 @@ __device__ __forceinline__ void batch_collide(const LatticeDev &L, const StepCon
     const int id = first + k;
     if (id >= last) return;
     const int z = id / L.plane;
-    d_collide<SIG>(L, sc, chi, fin, fout, fld, z, id - z * L.plane);
+    d_collide<SIG, false>(L, sc, chi, fin, fout, fld, z, id - z * L.plane);
 }
 
 // Persistent kernel of one phase of the step for every slit: the grid walks

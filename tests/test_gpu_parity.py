@@ -35,6 +35,13 @@ CASES = [  # (nx, ny, nz, sigma, walls)
     (12, 11, 14, 2, 0), (13, 12, 20, 3, 2), (12, 12, 22, 4, 2), (14, 13, 17, 5, 0),
     (16, 15, 26, 6, 3), (17, 16, 30, 7, 4), (20, 18, 28, 8, 4), (10, 12, 9, 8, 0),
 ]
+# Grids whose 256-node chunks are whole x-rows (nx divides 256 and the plane),
+# as the benchmarked slit: one block of the moments kernel then also forms the
+# row sums of the ball sum.
+ROW_CASES = [
+    (16, 16, 12, 2, 0), (32, 8, 14, 3, 2), (16, 32, 16, 4, 2), (32, 16, 12, 5, 0),
+    (32, 16, 20, 6, 3), (16, 16, 22, 7, 4), (32, 32, 24, 8, 4), (64, 12, 14, 8, 0),
+]
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c)))
@@ -67,7 +74,7 @@ def test_force_fp32_storage(case):
     assert np.abs(F_g - F_o).max() <= 2e-6 * np.abs(F_o).max()
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c)))
+@pytest.mark.parametrize("case", CASES + ROW_CASES, ids=lambda c: "x".join(map(str, c)))
 def test_steps_fp64(case):
     nx, ny, nz, sigma, walls = case
     nb = workloads.number_density(0.25, sigma)
@@ -126,11 +133,12 @@ def test_poiseuille_closed_form_gpu(precision, tol):
     assert np.abs(pu[0, 1:-1] - ex).max() <= tol * ex.max()
 
 
-def test_fp32_slit_against_oracle():
-    """FP32 populations on a 24x24x40 slit (sigma 8, eta 0.25, tau 0.8, noisy
-    start), 600 steps: profiles and velocity field within 1e-5 of the FP64
-    oracle."""
-    wl = workloads.slit_64_f32_stable().with_size(nx=24, ny=24, nz=40, steps=600)
+@pytest.mark.parametrize("lateral", [24, 32])
+def test_fp32_slit_against_oracle(lateral):
+    """FP32 populations on a 24x24x40 and a 32x32x40 slit (sigma 8, eta 0.25,
+    tau 0.8, noisy start; the second has whole x-rows per block), 600 steps:
+    profiles and velocity field within 1e-5 of the FP64 oracle."""
+    wl = workloads.slit_64_f32_stable().with_size(nx=lateral, ny=lateral, nz=40, steps=600)
     n, u = wl.fields()
     g = hslb.Sim.from_workload(wl)
     g.init(n, u)
