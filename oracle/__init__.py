@@ -48,6 +48,7 @@ class _Params(ctypes.Structure):
         ("accel", ctypes.c_double * 3),
         ("g2_model", ctypes.c_int32), ("wall_reg", ctypes.c_int32),
         ("force_mode", ctypes.c_int32),
+        ("att_eps", ctypes.c_double), ("att_range", ctypes.c_double),
     ]
 
 
@@ -70,7 +71,7 @@ def _load():
         getattr(lib, name).argtypes = [ctypes.c_void_p, d, d]
         getattr(lib, name).restype = ctypes.c_int
     for name in ("hsref_force", "hsref_eta_bar", "hsref_get_populations", "hsref_set_populations",
-                 "hsref_step_with_force"):
+                 "hsref_step_with_force", "hsref_attraction_potential"):
         getattr(lib, name).argtypes = [ctypes.c_void_p, d]
         getattr(lib, name).restype = ctypes.c_int
     lib.hsref_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
@@ -134,7 +135,7 @@ class Oracle:
     z: arrays are shaped (nz, ny, nx) and vectors (3, nz, ny, nx)."""
 
     def __init__(self, nx, ny, nz, sigma, tau, accel=(0.0, 0.0, 0.0), wall_lo=0, wall_hi=0,
-                 g2_model=G2_PAPER, wall_reg=1, force_mode=FORCE_EXACT):
+                 g2_model=G2_PAPER, wall_reg=1, force_mode=FORCE_EXACT, att_eps=0.0, att_range=0.0):
         self._lib = _load()
         p = _Params()
         p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
@@ -143,6 +144,7 @@ class Oracle:
         p.tau = float(tau)
         p.accel = (ctypes.c_double * 3)(*[float(a) for a in accel])
         p.g2_model, p.wall_reg, p.force_mode = int(g2_model), int(wall_reg), int(force_mode)
+        p.att_eps, p.att_range = float(att_eps), float(att_range)
         self.params = p
         self.shape = (int(nz), int(ny), int(nx))
         self.N = int(nx) * int(ny) * int(nz)
@@ -193,6 +195,12 @@ class Oracle:
         the external field n g) instead of the shell sum."""
         C1 = np.ascontiguousarray(C1, dtype=np.float64).reshape(3 * self.N)
         self._chk(self._lib.hsref_step_with_force(self._ctx, _dptr(C1)), "step_with_force")
+
+    def attraction_potential(self):
+        """Mean-field attraction potential Phi [nz, ny, nx] of the current state."""
+        phi = np.zeros(self.N)
+        self._chk(self._lib.hsref_attraction_potential(self._ctx, _dptr(phi)), "attraction_potential")
+        return phi.reshape(self.shape)
 
     def eta_bar(self):
         e = np.zeros(self.N)

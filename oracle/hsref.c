@@ -44,6 +44,17 @@
  *   - solid nodes and points beyond the array carry n = j = 0;
  *   - the wall factor multiplies only the current term, is evaluated at the
  *     receiving node, and uses the distance to the nearest halfway wall plane.
+ *
+ * Optional mean-field attraction (the generalisation to attractive forces the
+ * paper's conclusions name; off unless att_eps != 0).  In equilibrium the
+ * paper ties C^(1) to density functional theory, C^(1) = -n grad dF_exc/dn
+ * (m = 1); a mean-field attractive functional (1/2) sum sum n n' phi adds
+ * dF/dn = (phi * n), so the attraction enters the force as
+ *   Phi(r)    = -att_eps sum_{o: |o_x|,|o_y|,|o_z| <= R} exp(-|o|^2/att_range^2) n(r+o),
+ *   C1_att(r) = -n(r) [Phi(r + e_a) - Phi(r - e_a)] / 2   (each axis a),
+ * with R = ceil(3 att_range), the same n = 0 on solid nodes and beyond the
+ * array, and periodic images along periodic axes.  Written here as the plain
+ * triple sum.
  */
 #include <math.h>
 #include <stdint.h>
@@ -68,6 +79,8 @@ typedef struct {
     int32_t g2_model;         /* 0: printed closure, 1: Carnahan-Starling */
     int32_t wall_reg;         /* 1: wall factor on the current term */
     int32_t force_mode;       /* 0: hard-sphere term on, 2: off */
+    double att_eps;           /* depth of the Gaussian attraction (0: off) */
+    double att_range;         /* its range in lattice units */
 } hsref_params;
 
 /* D3Q19 velocities, the discrete set of section "Methods and Results". */
@@ -119,6 +132,8 @@ struct hsref_ctx {
     double *u;       /* [3][N] */
     double *eb;      /* [N] coarse-grained packing fraction */
     double *F;       /* [3][N] total force */
+    double *phi;     /* [N] mean-field attraction potential (att_eps != 0) */
+    int att_R;       /* its cube half-width, ceil(3 att_range) */
 };
 
 typedef struct hsref_ctx hsref_ctx;
@@ -266,6 +281,8 @@ hsref_ctx *hsref_create(const hsref_params *p)
     if (p->wall_lo + p->wall_hi >= p->nz) return NULL;
     if (p->force_mode != 2 && p->sigma < 2) return NULL;
     if (!(p->tau > 0.5)) return NULL;
+    if (!isfinite(p->att_eps) || (p->att_eps != 0.0 && !(p->att_range > 0.0 && p->att_range <= 10.0)))
+        return NULL;
     hsref_ctx *c = (hsref_ctx *)calloc(1, sizeof(hsref_ctx));
     if (!c) return NULL;
     c->p = *p;
@@ -298,9 +315,11 @@ hsref_ctx *hsref_create(const hsref_params *p)
     c->u = calloc(3 * N, sizeof(double));
     c->eb = calloc(N, sizeof(double));
     c->F = calloc(3 * N, sizeof(double));
-    if (!c->ball || !c->chi || !c->f || !c->fs || !c->n || !c->j || !c->u || !c->eb || !c->F) {
+    c->phi = calloc(N, sizeof(double));
+    c->att_R = p->att_eps != 0.0 ? (int)ceil(3.0 * p->att_range) : 0;
+    if (!c->ball || !c->chi || !c->f || !c->fs || !c->n || !c->j || !c->u || !c->eb || !c->F || !c->phi) {
         free(c->ball); free(c->chi); free(c->f); free(c->fs); free(c->n); free(c->j);
-        free(c->u); free(c->eb); free(c->F); free(c);
+        free(c->u); free(c->eb); free(c->F); free(c->phi); free(c);
         return NULL;
     }
     return c;
@@ -310,7 +329,7 @@ void hsref_destroy(hsref_ctx *c)
 {
     if (!c) return;
     free(c->ball); free(c->chi); free(c->f); free(c->fs); free(c->n); free(c->j);
-    free(c->u); free(c->eb); free(c->F);
+    free(c->u); free(c->eb); free(c->F); free(c->phi);
     free(c);
 }
 
@@ -392,6 +411,32 @@ static int eta_mid(const hsref_ctx *c, int x, int y, int z, const int d[3], doub
     return 1;
 }
 
+/* Mean-field attraction potential at every node (see the header):
+ *   Phi(r) = -att_eps sum_o exp(-|o|^2 / att_range^2) n(r + o),
+ * o over the cube |o_a| <= R, as a plain triple sum. */
+static void phase_attraction(hsref_ctx *c)
+{
+    const int64_t plane = (int64_t)c->p.nx * c->p.ny;
+    const int R = c->att_R;
+    const double l2 = c->p.att_range * c->p.att_range;
+#pragma omp parallel for schedule(static) if (c->N >= PAR_MIN_NODES)
+    for (int z = 0; z < c->p.nz; ++z) {
+        for (int y = 0; y < c->p.ny; ++y) {
+            for (int x = 0; x < c->p.nx; ++x) {
+                double s = 0.0;
+                for (int oz = -R; oz <= R; ++oz)
+                    for (int oy = -R; oy <= R; ++oy)
+                        for (int ox = -R; ox <= R; ++ox) {
+                            int64_t id = node_at(c, x + ox, y + oy, z + oz);
+                            if (id < 0) continue;
+                            s += exp(-(double)(ox * ox + oy * oy + oz * oz) / l2) * c->n[id];
+                        }
+                c->phi[z * plane + (int64_t)y * c->p.nx + x] = -c->p.att_eps * s;
+            }
+        }
+    }
+}
+
 /* Equation (12) with the isothermal restriction, plus the external field:
  *   C1(r) = -v_T^2 sigma^2 4pi n(r) sum_q W_q s_q sum_k alpha_qk G_qk
  *           [ n(r+d) - chi(r) kappa s_q . (j(r+d) - n(r+d) u(r)) ],
@@ -440,7 +485,18 @@ static void phase_force(hsref_ctx *c)
                             for (int a = 0; a < 3; ++a) S[a] += Sp[a];
                         }
                     }
-                    for (int a = 0; a < 3; ++a) Fv[a] = pref * nr * S[a] + nr * c->p.accel[a];
+                    double Fa[3] = {0.0, 0.0, 0.0};
+                    if (c->att_R > 0) {
+                        /* central differences of Phi; r +- e_a lies inside the array at a fluid node */
+                        for (int a = 0; a < 3; ++a) {
+                            int e[3] = {0, 0, 0};
+                            e[a] = 1;
+                            int64_t ip = node_at(c, x + e[0], y + e[1], z + e[2]);
+                            int64_t im = node_at(c, x - e[0], y - e[1], z - e[2]);
+                            Fa[a] = -nr * (c->phi[ip] - c->phi[im]) / 2.0;
+                        }
+                    }
+                    for (int a = 0; a < 3; ++a) Fv[a] = pref * nr * S[a] + Fa[a] + nr * c->p.accel[a];
                 }
                 for (int a = 0; a < 3; ++a) c->F[a * N + id] = Fv[a];
             }
@@ -531,6 +587,7 @@ int hsref_step(hsref_ctx *c, int64_t nsteps)
     for (int64_t s = 0; s < nsteps; ++s) {
         phase_moments(c);
         if (c->p.force_mode != 2) phase_eta_bar(c);
+        if (c->att_R > 0) phase_attraction(c);
         phase_force(c);
         phase_collide_stream(c);
     }
@@ -591,8 +648,20 @@ int hsref_force(hsref_ctx *c, double *F)
     if (!c || !F) return -1;
     phase_moments(c);
     if (c->p.force_mode != 2) phase_eta_bar(c);
+    if (c->att_R > 0) phase_attraction(c);
     phase_force(c);
     memcpy(F, c->F, sizeof(double) * 3 * (size_t)c->N);
+    return 0;
+}
+
+/* Mean-field attraction potential Phi[N] at the current state (0 when the
+ * attraction is off). */
+int hsref_attraction_potential(hsref_ctx *c, double *phi)
+{
+    if (!c || !phi) return -1;
+    phase_moments(c);
+    if (c->att_R > 0) phase_attraction(c);
+    memcpy(phi, c->phi, sizeof(double) * (size_t)c->N);
     return 0;
 }
 

@@ -17,6 +17,11 @@ a(t+1) = A(k) a(t).  With dn = sum a_i, dj = sum c_i a_i (u0 = 0):
     of e^{ik.m} over the lattice nodes nearest the midpoint d/2, and G0, g2'
     the closure and its derivative at eta0 (the current term's velocity at the
     receiving node enters as n0 du = dj);
+  - optional mean-field attraction (its real-space form is in the header of
+    hsref.c): Phi = -eps (g * n) with the separable Gaussian weights g, so
+    dPhi = -eps g_hat(k) dn and the central difference of Phi gives
+    dC1_att = -n0 i sin(k) dPhi = i eps n0 g_hat(k) sin(k) dn, where
+    g_hat(k) = prod_a sum_{|m| <= R} exp(-m^2/lambda^2) cos(k_a m);
   - collision with the first-order source (eq. 10):
     a*_i = a_i - (a_i - df_eq,i)/tau + 3 w_i c_i . dC1;
   - push propagation: a_i(t+1) = exp(-i k.c_i) a*_i.
@@ -97,8 +102,20 @@ def midpoint_nodes(d: np.ndarray) -> np.ndarray:
     return np.array(np.meshgrid(*choices, indexing="ij")).reshape(3, -1).T
 
 
+def att_cutoff(att_range: float) -> int:
+    return int(math.ceil(3.0 * att_range))
+
+
+def att_ghat(k, att_range: float) -> float:
+    """Lattice Fourier transform of the truncated Gaussian weights at k."""
+    R = att_cutoff(att_range)
+    m = np.arange(-R, R + 1, dtype=np.float64)
+    g1 = np.exp(-m * m / att_range ** 2)
+    return float(np.prod([np.sum(g1 * np.cos(ka * m)) for ka in np.asarray(k, dtype=np.float64)]))
+
+
 def amplification(k, sigma: int, eta: float, tau: float, model: int = G2_PAPER,
-                  hs_on: bool = True) -> np.ndarray:
+                  hs_on: bool = True, att_eps: float = 0.0, att_range: float = 0.0) -> np.ndarray:
     """A(k), 19 x 19 complex."""
     k = np.asarray(k, dtype=np.float64)
     n0 = 6 * eta / (math.pi * sigma ** 3)
@@ -127,12 +144,15 @@ def amplification(k, sigma: int, eta: float, tau: float, model: int = G2_PAPER,
         # dC1 = pref (sn dn - kappa G0 T dj); dn = 1.a, dj = c^T a
         MF = pref * (np.outer(sn, np.ones(19)) - KAPPA * G0 * T @ c.T)   # 3 x 19
         M = M + 3.0 * (W[:, None] * c) @ MF
+    if att_eps != 0.0:
+        att = 1j * att_eps * n0 * att_ghat(k, att_range) * np.sin(k)
+        M = M + 3.0 * (W[:, None] * c) @ np.outer(att, np.ones(19))
     E = np.exp(-1j * (c @ k))
     return E[:, None] * M
 
 
-def eigen(k, sigma, eta, tau, model=G2_PAPER, hs_on=True):
-    lam, vec = np.linalg.eig(amplification(k, sigma, eta, tau, model, hs_on))
+def eigen(k, sigma, eta, tau, model=G2_PAPER, hs_on=True, att_eps=0.0, att_range=0.0):
+    lam, vec = np.linalg.eig(amplification(k, sigma, eta, tau, model, hs_on, att_eps, att_range))
     return lam, vec
 
 
@@ -153,17 +173,19 @@ def shear_lambda(L: int, sigma: int, eta: float, tau: float, model=G2_PAPER, hs_
     return complex(lam[int(np.argmax(jx))])
 
 
-def sound(L: int, sigma: int, eta: float, tau: float, model=G2_PAPER, hs_on=True):
+def sound(L: int, sigma: int, eta: float, tau: float, model=G2_PAPER, hs_on=True, att_eps=0.0,
+          att_range=0.0):
     """(speed, amplitude damping rate per step) of the sound pair at k = 2 pi / L
     along z: the two eigenvalues with the largest density share."""
     k = np.array([0.0, 0.0, 2 * math.pi / L])
-    lam, vec = eigen(k, sigma, eta, tau, model, hs_on)
+    lam, vec = eigen(k, sigma, eta, tau, model, hs_on, att_eps, att_range)
     nshare = np.abs(vec.sum(axis=0)) / np.linalg.norm(vec, axis=0)
     m = int(np.argmax(nshare))
     return abs(np.angle(lam[m])) / k[2], -math.log(abs(lam[m]))
 
 
-def max_growth(L: int, sigma: int, eta: float, tau: float, model=G2_PAPER, axes: str = "xyz") -> float:
+def max_growth(L: int, sigma: int, eta: float, tau: float, model=G2_PAPER, axes: str = "xyz",
+               att_eps: float = 0.0, att_range: float = 0.0) -> float:
     """Largest |lambda| over the wavevectors 2 pi m / L of an L^3 periodic box,
     m1 >= m2 >= m3 >= 0 (cubic symmetry; axes='z' for k along z only)."""
     best = 0.0
@@ -174,6 +196,6 @@ def max_growth(L: int, sigma: int, eta: float, tau: float, model=G2_PAPER, axes:
         ms = [(a, b, c) for a in range(h + 1) for b in range(a + 1) for c in range(b + 1)]
     for m in ms:
         k = 2 * math.pi * np.array(m, dtype=np.float64) / L
-        lam = np.linalg.eigvals(amplification(k, sigma, eta, tau, model))
+        lam = np.linalg.eigvals(amplification(k, sigma, eta, tau, model, True, att_eps, att_range))
         best = max(best, float(np.abs(lam).max()))
     return best
