@@ -79,6 +79,19 @@ typedef struct {
     int32_t force_mode;       /* HSLB_FORCE_* */
     int32_t surr_check_every; /* surrogate mode: exact judge every K steps */
     double surr_tol;          /* surrogate mode: residual threshold */
+    /* Optional mean-field attraction, the generalisation to attractive forces
+     * named in the paper's conclusions (0: off).  In equilibrium the paper ties
+     * C^(1) to density functional theory (C^(1) = -n grad dF_exc/dn, section
+     * "Theory"); a mean-field attractive functional adds to the force
+     *   Phi(r)    = -att_eps sum_o exp(-|o|^2 / att_range^2) n(r + o),
+     *   C1_att(r) = -n(r) [Phi(r + e_a) - Phi(r - e_a)] / 2  (each axis a),
+     * o over the cube |o_x|, |o_y|, |o_z| <= ceil(3 att_range), n = 0 on solid
+     * layers and beyond the walls, periodic images along periodic axes.  The
+     * bulk pressure gains -(att_eps/2) (sum_o exp(-|o|^2/att_range^2)) n^2.
+     * att_range in (0, 10] when att_eps != 0.  Not with the learned force or
+     * the batch. */
+    double att_eps;
+    double att_range;
 } hslb_params;
 
 typedef struct hslb_ctx hslb_ctx;
@@ -106,7 +119,8 @@ int hslb_set_stream(hslb_ctx *ctx, void *hip_stream);
 int hslb_init(hslb_ctx *ctx, const double *n, const double *u);
 
 /* Advance nsteps time steps of equation (10): moments, coarse-grained density,
- * midpoint contact values, hard-sphere force (12) plus n g, BGK collision with
+ * midpoint contact values, hard-sphere force (12) (plus the mean-field
+ * attraction when att_eps != 0) plus n g, BGK collision with
  * the first-order source, streaming with halfway bounce-back.  Asynchronous;
  * launch errors are returned here, a failing watchdog (see
  * hslb_set_watchdog) returns HSLB_EUNSTABLE.  Errors: HSLB_ESTATE before init,
@@ -136,6 +150,10 @@ int hslb_force(hslb_ctx *ctx, double *F);
  * density over the lattice nodes of the closed ball of radius sigma/2, at the
  * current state. */
 int hslb_eta_bar(hslb_ctx *ctx, double *eta_bar);
+
+/* Mean-field attraction potential Phi[N] (see hslb_params.att_eps) at the
+ * current state, solid layers included; all zero when the attraction is off. */
+int hslb_attraction_potential(hslb_ctx *ctx, double *phi);
 
 /* Populations f[19][N] of the current state, and their replacement.
  * set_populations zeroes solid nodes, resets the step counter and rebuilds the

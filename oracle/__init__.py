@@ -130,6 +130,30 @@ def lattice():
     return c, w
 
 
+def attraction_potential_at(n, nodes, att_eps: float, att_range: float, zperiodic: bool):
+    """Mean-field attraction potential (its definition is in the header of
+    hsref.c) at the listed nodes (z, y, x) of the density field n [nz, ny, nx],
+    each as its own direct sum over the cube of offsets: for spot checks of
+    grids too large for the full oracle."""
+    nz, ny, nx = n.shape
+    R = int(np.ceil(3.0 * att_range))
+    o = np.arange(-R, R + 1)
+    OZ, OY, OX = np.meshgrid(o, o, o, indexing="ij")
+    g = np.exp(-(OX * OX + OY * OY + OZ * OZ).astype(np.float64) / att_range ** 2)
+    out = []
+    for z, y, x in nodes:
+        zz = z + OZ
+        inside = np.ones(zz.shape, dtype=bool)
+        if zperiodic:
+            zz = zz % nz
+        else:
+            inside = (zz >= 0) & (zz < nz)
+            zz = np.clip(zz, 0, nz - 1)
+        vals = n[zz, (y + OY) % ny, (x + OX) % nx]
+        out.append(-att_eps * float(np.sum(np.where(inside, g * vals, 0.0))))
+    return np.array(out)
+
+
 class Oracle:
     """One lattice on the CPU.  Fields use the node order x fastest, then y, then
     z: arrays are shaped (nz, ny, nx) and vectors (3, nz, ny, nx)."""

@@ -55,6 +55,7 @@ public:
     virtual int profiles(double *nz, double *uz) = 0;
     virtual int force(double *F) = 0;
     virtual int eta_bar(double *eb) = 0;
+    virtual int attraction_potential(double *phi) = 0;
     virtual int get_pop(double *f) = 0;
     virtual int set_pop(const double *f) = 0;
     virtual int sync() = 0;
@@ -175,6 +176,7 @@ public:
         (void)hipFree(f_[1]);
         (void)hipFree(fld_mem_);
         (void)hipFree(chi_d_);
+        (void)hipFree(att_d_);
         (void)hipFree(prof_d_);
         (void)hipFree(nref_d_);
         (void)hipHostFree(prof_h_);
@@ -242,6 +244,16 @@ public:
                 const double dw = std::fmin((double)z - za, zb - (double)z);
                 chi[z] = 1.0 - std::exp(-dw / (double)sig);
             }
+        }
+        if (p_.att_eps != 0.0) {
+            aw_.R = (int)std::ceil(3.0 * p_.att_range);
+            aw_.eps = p_.att_eps;
+            for (int m = -aw_.R; m <= aw_.R; ++m)
+                aw_.w[m + aw_.R] = std::exp(-(double)(m * m) / (p_.att_range * p_.att_range));
+            if (hipMalloc(&att_d_, sizeof(double) * 3 * (size_t)L_.N) != hipSuccess)
+                return fail(err, HSLB_ENOMEM, "attraction fields do not fit");
+            HIP_TRY(hipMemset(att_d_, 0, sizeof(double) * 3 * (size_t)L_.N));
+            sc_.phi = att_d_ + 2 * (size_t)L_.N;
         }
         HIP_TRY(hipMalloc(&chi_d_, sizeof(double) * p_.nz));
         HIP_TRY(hipMemcpy(chi_d_, chi.data(), sizeof(double) * p_.nz, hipMemcpyHostToDevice));
@@ -380,12 +392,22 @@ public:
             if (rc) return rc;
             if (sc_.hs_on && (rc = fields_hs())) return rc;
         }
+        if (sc_.phi && (rc = attraction())) return rc;
         rc = launch("collide", [&] {
             return launch_collide<TF, TM>(st(), L_, sigma_, sc_, chi_d_, f_[cur_], f_[1 - cur_], fld_);
         });
         if (rc) return rc;
         cur_ = 1 - cur_;
         return HSLB_OK;
+    }
+
+    // Mean-field attraction potential of the current moments (into sc_.phi).
+    int attraction()
+    {
+        return launch("attract", [&] {
+            return launch_attraction<TM>(st(), L_, aw_, fld_.n, att_d_, att_d_ + (size_t)L_.N,
+                                         att_d_ + 2 * (size_t)L_.N);
+        });
     }
 
     int capture(int parity)
@@ -568,8 +590,24 @@ public:
         if (rc) return rc;
         HIP_TRY(launch_moments<TF, TM>(st(), L_, nref_d_, f_[cur_], fld_));
         if (sc_.hs_on && (rc = fields_hs())) return rc;
+        if (sc_.phi && (rc = attraction())) return rc;
         HIP_TRY(launch_force<TF, TM>(st(), L_, sigma_, sc_, chi_d_, f_[cur_], fld_, d));
         HIP_TRY(hipMemcpyAsync(F, d, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, st()));
+        HIP_TRY(hipStreamSynchronize(st()));
+        return HSLB_OK;
+    }
+
+    int attraction_potential(double *phi) override
+    {
+        if (!inited) return fail(err, HSLB_ESTATE, "attraction_potential before init");
+        if (!sc_.phi) {
+            std::memset(phi, 0, sizeof(double) * (size_t)L_.N);
+            return HSLB_OK;
+        }
+        HIP_TRY(launch_moments<TF, TM>(st(), L_, nref_d_, f_[cur_], fld_));
+        int rc = attraction();
+        if (rc) return rc;
+        HIP_TRY(hipMemcpyAsync(phi, sc_.phi, sizeof(double) * L_.N, hipMemcpyDeviceToHost, st()));
         HIP_TRY(hipStreamSynchronize(st()));
         return HSLB_OK;
     }
@@ -956,6 +994,8 @@ private:
     hslb_params p_;
     LatticeDev L_{};
     StepConst sc_{};
+    AttWeights aw_{};
+    double *att_d_ = nullptr;  // attraction: x-pass, y-pass, potential [N] each
     int sigma_ = 2;
     hipStream_t stream_ = nullptr, ext_stream_ = nullptr;
     bool own_stream_ = false;
@@ -1005,6 +1045,7 @@ void slit_consts(const hslb_params &p, LatticeDev &L, StepConst &sc, std::vector
     sc.alpha[3] = th * th;
     sc.g2_model = p.g2_model;
     sc.hs_on = (p.force_mode == HSLB_FORCE_OFF) ? 0 : 1;
+    sc.phi = nullptr;
     chi.assign(p.nz, 1.0);
     if (!L.zper && p.wall_reg) {
         const double za = p.wall_lo - 0.5, zb = p.nz - p.wall_hi - 0.5;
@@ -1465,6 +1506,7 @@ public:
     int profiles(double *, double *) override { return fail_state("use hslb_batch_profiles on a batch"); }
     int force(double *) override { return fail_state("not available on a batch"); }
     int eta_bar(double *) override { return fail_state("not available on a batch"); }
+    int attraction_potential(double *) override { return fail_state("not available on a batch"); }
     int get_pop(double *) override { return fail_state("not available on a batch"); }
     int set_pop(const double *) override { return fail_state("not available on a batch"); }
 
@@ -1534,6 +1576,13 @@ static int validate(const hslb_params *p, std::string &err)
             return fail(err, HSLB_EINVAL, "the learned force needs nx %% 32 == 0 and ny %% 4 == 0");
         if (p->surr_check_every < 1) return fail(err, HSLB_EINVAL, "surr_check_every must be >= 1");
         if (!(p->surr_tol > 0.0)) return fail(err, HSLB_EINVAL, "surr_tol must be > 0");
+    }
+    if (!std::isfinite(p->att_eps)) return fail(err, HSLB_EINVAL, "att_eps must be finite");
+    if (p->att_eps != 0.0) {
+        if (!(p->att_range > 0.0 && p->att_range <= 10.0))
+            return fail(err, HSLB_EINVAL, "att_range must be in (0, 10] with the attraction on");
+        if (p->force_mode == HSLB_FORCE_SURROGATE)
+            return fail(err, HSLB_EINVAL, "the attraction is not available with the learned force");
     }
     const int sig = p->sigma >= 2 ? p->sigma : 2;
     const double fld = (double)p->nx * p->ny * (p->nz + 2.0 * sig);
@@ -1647,6 +1696,13 @@ int hslb_eta_bar(hslb_ctx *ctx, double *eb)
     if (!eb) return fail(ctx->eng->err, HSLB_EINVAL, "null output");
     if (ctx->p.force_mode == HSLB_FORCE_OFF) return fail(ctx->eng->err, HSLB_ESTATE, "hard-sphere term is off");
     return ctx->eng->eta_bar(eb);
+}
+
+int hslb_attraction_potential(hslb_ctx *ctx, double *phi)
+{
+    CTX_CHECK(ctx);
+    if (!phi) return fail(ctx->eng->err, HSLB_EINVAL, "null output");
+    return ctx->eng->attraction_potential(phi);
 }
 
 int hslb_get_populations(hslb_ctx *ctx, double *f)
@@ -1791,6 +1847,7 @@ int hslb_batch_create(const hslb_params *slits, int32_t nslits, hslb_ctx **out)
         }
         if (slits[k].precision != slits[0].precision) return fail(err, HSLB_EINVAL, "mixed precisions in a batch");
         if (slits[k].force_mode == HSLB_FORCE_SURROGATE) return fail(err, HSLB_EINVAL, "surrogate in a batch");
+        if (slits[k].att_eps != 0.0) return fail(err, HSLB_EINVAL, "attraction in a batch");
     }
     std::unique_ptr<hslb_ctx> c(new (std::nothrow) hslb_ctx());
     if (!c) return fail(err, HSLB_ENOMEM, "context allocation");

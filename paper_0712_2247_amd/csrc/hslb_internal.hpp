@@ -56,6 +56,18 @@ struct StepConst {
     const float *fext;
     const float *fdelta;
     double fscale;
+    // Mean-field attraction potential [N] (node order, no padding), or null:
+    // the force gains -n (phi(r + e_a) - phi(r - e_a)) / 2.
+    const double *phi;
+};
+
+// Separable weights of the mean-field attraction: w[m + R] = exp(-m^2 /
+// range^2) for |m| <= R, and the depth eps.
+constexpr int ATT_MAX_R = 30;
+struct AttWeights {
+    int R;
+    double eps;
+    double w[2 * ATT_MAX_R + 1];
 };
 
 template <typename TM>
@@ -132,6 +144,13 @@ hipError_t launch_set_pop(hipStream_t s, const LatticeDev &L, const double *nref
                           TF *f);
 
 hipError_t launch_copy(hipStream_t s, const void *src, void *dst, size_t bytes);
+
+// Mean-field attraction potential of the padded density field n over all nz
+// layers, as three passes along x, y and z (a and b hold the partial sums,
+// [N] each): phi = -eps sum_o w(o_x) w(o_y) w(o_z) n(r + o).
+template <typename TM>
+hipError_t launch_attraction(hipStream_t s, const LatticeDev &L, const AttWeights &aw, const TM *n, double *a,
+                             double *b, double *phi);
 
 // Batched ensemble: one persistent launch per phase over a work list.
 // phase 0 moments, 1 row sums, 2 ball sums, 3 contact values, 4 collide.

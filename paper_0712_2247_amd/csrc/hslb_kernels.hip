@@ -596,10 +596,25 @@ __device__ __forceinline__ void node_force(const Fields<TM> &F, const LatticeDev
         const TC alpha[4] = {(TC)sc.alpha[0], (TC)sc.alpha[1], (TC)sc.alpha[2], (TC)sc.alpha[3]};
         shell_sum<SIG, LZ>(F, L, c, alpha, S);
     }
+    double Fa[3] = {0.0, 0.0, 0.0};
+    if (sc.phi) {
+        // mean-field attraction: -n times the central difference of phi; the
+        // neighbours of a fluid node lie inside the array (walls are >= 1 layer)
+        int zu = z + 1, zd = z - 1;
+        if (L.zper) {
+            zu = (zu == L.nz) ? 0 : zu;
+            zd = (zd < 0) ? L.nz - 1 : zd;
+        }
+        const double *P = sc.phi;
+        const int row = L.nx * (y + L.ny * z);
+        Fa[0] = -n * (P[wrapc<1>(x, L.nx) + row] - P[wrapc<-1>(x, L.nx) + row]) / 2.0;
+        Fa[1] = -n * (P[x + L.nx * (wrapc<1>(y, L.ny) + L.ny * z)] - P[x + L.nx * (wrapc<-1>(y, L.ny) + L.ny * z)]) / 2.0;
+        Fa[2] = -n * (P[x + L.nx * (y + L.ny * zu)] - P[x + L.nx * (y + L.ny * zd)]) / 2.0;
+    }
     const double pn = sc.pref * n;
-    Fo[0] = pn * (double)S[0] + n * sc.g[0];
-    Fo[1] = pn * (double)S[1] + n * sc.g[1];
-    Fo[2] = pn * (double)S[2] + n * sc.g[2];
+    Fo[0] = pn * (double)S[0] + Fa[0] + n * sc.g[0];
+    Fo[1] = pn * (double)S[1] + Fa[1] + n * sc.g[1];
+    Fo[2] = pn * (double)S[2] + Fa[2] + n * sc.g[2];
     }
 }
 
@@ -736,6 +751,75 @@ __global__ __launch_bounds__(256) void k_force(LatticeDev L, StepConst sc, const
     Fout[id] = Fv[0];
     Fout[L.N + id] = Fv[1];
     Fout[2 * (size_t)L.N + id] = Fv[2];
+}
+
+// ------------------------------------------------- mean-field attraction
+
+// Pass along x of the padded density field: a = sum_m w[m] n(x + m - R).
+// grid (ceil(plane / 256), nz); R may exceed nx (the offsets wrap again).
+template <typename TM>
+__global__ __launch_bounds__(256) void k_att_x(LatticeDev L, AttWeights aw, const TM *__restrict__ n,
+                                               double *__restrict__ out)
+{
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    const int z = (int)blockIdx.y;
+    if (r >= L.plane) return;
+    const int y = r / L.nx;
+    const int x = r - y * L.nx;
+    const TM *row = n + (size_t)L.plane * (z + L.hz) + (size_t)L.nx * y;
+    int xm = (x - aw.R) % L.nx;
+    xm = xm < 0 ? xm + L.nx : xm;
+    double s = 0.0;
+    for (int m = 0; m <= 2 * aw.R; ++m) {
+        s += aw.w[m] * (double)row[xm];
+        xm = (xm + 1 == L.nx) ? 0 : xm + 1;
+    }
+    out[(size_t)L.plane * z + r] = s;
+}
+
+// Pass along y: b = sum_m w[m] a(y + m - R).
+__global__ __launch_bounds__(256) void k_att_y(LatticeDev L, AttWeights aw, const double *__restrict__ a,
+                                               double *__restrict__ out)
+{
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    const int z = (int)blockIdx.y;
+    if (r >= L.plane) return;
+    const int y = r / L.nx;
+    const int x = r - y * L.nx;
+    const double *col = a + (size_t)L.plane * z + x;
+    int ym = (y - aw.R) % L.ny;
+    ym = ym < 0 ? ym + L.ny : ym;
+    double s = 0.0;
+    for (int m = 0; m <= 2 * aw.R; ++m) {
+        s += aw.w[m] * col[(size_t)L.nx * ym];
+        ym = (ym + 1 == L.ny) ? 0 : ym + 1;
+    }
+    out[(size_t)L.plane * z + r] = s;
+}
+
+// Pass along z: phi = -eps sum_m w[m] b(z + m - R), wrapping for a periodic z
+// axis and with nothing beyond the array otherwise.
+__global__ __launch_bounds__(256) void k_att_z(LatticeDev L, AttWeights aw, const double *__restrict__ b,
+                                               double *__restrict__ out)
+{
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    const int z = (int)blockIdx.y;
+    if (r >= L.plane) return;
+    double s = 0.0;
+    if (L.zper) {
+        int zm = (z - aw.R) % L.nz;
+        zm = zm < 0 ? zm + L.nz : zm;
+        for (int m = 0; m <= 2 * aw.R; ++m) {
+            s += aw.w[m] * b[(size_t)L.plane * zm + r];
+            zm = (zm + 1 == L.nz) ? 0 : zm + 1;
+        }
+    } else {
+        for (int m = 0; m <= 2 * aw.R; ++m) {
+            const int zm = z + m - aw.R;
+            if (zm >= 0 && zm < L.nz) s += aw.w[m] * b[(size_t)L.plane * zm + r];
+        }
+    }
+    out[(size_t)L.plane * z + r] = -aw.eps * s;
 }
 
 // -------------------------------------------------------------- reductions
@@ -1006,6 +1090,18 @@ inline unsigned blocks_for(int n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
+template <typename TM>
+hipError_t launch_attraction(hipStream_t s, const LatticeDev &L, const AttWeights &aw, const TM *n, double *a,
+                             double *b, double *phi)
+{
+    if (aw.R < 0 || aw.R > ATT_MAX_R) return hipErrorInvalidValue;
+    const dim3 g(blocks_for(L.plane), L.nz), blk(256);
+    hipLaunchKernelGGL((k_att_x<TM>), g, blk, 0, s, L, aw, n, a);
+    hipLaunchKernelGGL(k_att_y, g, blk, 0, s, L, aw, a, b);
+    hipLaunchKernelGGL(k_att_z, g, blk, 0, s, L, aw, b, phi);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy(hipStream_t s, const void *src, void *dst, size_t bytes)
 {
     const size_t n = bytes / 16;
@@ -1226,6 +1322,8 @@ hipError_t launch_batch_profiles(hipStream_t s, const SlitDesc *desc, const Work
                                                   const int *, const TF *, double *);
 #define HSLB_INST_TM(TM)                                                                              \
     template hipError_t launch_gfield<TM>(hipStream_t, const LatticeDev &, int, Fields<TM>);         \
+    template hipError_t launch_attraction<TM>(hipStream_t, const LatticeDev &, const AttWeights &,   \
+                                              const TM *, double *, double *, double *);             \
     template hipError_t launch_smooth2<TM>(hipStream_t, const LatticeDev &, int, double, Fields<TM>, TM *); \
     template hipError_t launch_ballsum<TM>(hipStream_t, const LatticeDev &, int, double, Fields<TM>, const TM *); \
     template hipError_t launch_unpad<TM>(hipStream_t, const LatticeDev &, const TM *, double *);

@@ -43,7 +43,7 @@ HSLB_CNN_NWEIGHTS = 144067
 EXPORTS = (
     "hslb_create", "hslb_destroy", "hslb_last_error", "hslb_set_stream", "hslb_init",
     "hslb_step", "hslb_sync", "hslb_step_count", "hslb_moments", "hslb_profiles",
-    "hslb_force", "hslb_eta_bar", "hslb_get_populations", "hslb_set_populations",
+    "hslb_force", "hslb_eta_bar", "hslb_attraction_potential", "hslb_get_populations", "hslb_set_populations",
     "hslb_set_watchdog", "hslb_set_shift_period", "hslb_set_graph",
     "hslb_checkpoint_size", "hslb_checkpoint_save", "hslb_checkpoint_load", "hslb_set_kernel_timing", "hslb_kernel_times",
     "hslb_get_timings", "hslb_copy_bandwidth",
@@ -69,6 +69,7 @@ class hslb_params(ctypes.Structure):
         ("precision", ctypes.c_int32), ("force_mode", ctypes.c_int32),
         ("surr_check_every", ctypes.c_int32),
         ("surr_tol", ctypes.c_double),
+        ("att_eps", ctypes.c_double), ("att_range", ctypes.c_double),
     ]
 
 
@@ -108,6 +109,7 @@ def load(path: Optional[str] = None):
         "hslb_profiles": (ctypes.c_int, [_vp, _dp, _dp]),
         "hslb_force": (ctypes.c_int, [_vp, _dp]),
         "hslb_eta_bar": (ctypes.c_int, [_vp, _dp]),
+        "hslb_attraction_potential": (ctypes.c_int, [_vp, _dp]),
         "hslb_get_populations": (ctypes.c_int, [_vp, _dp]),
         "hslb_set_populations": (ctypes.c_int, [_vp, _dp]),
         "hslb_set_watchdog": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_double]),
@@ -229,6 +231,10 @@ def hslb_force(ctx, F: np.ndarray):
 
 def hslb_eta_bar(ctx, eb: np.ndarray):
     _chk(ctx, load().hslb_eta_bar(ctx, _d(eb)))
+
+
+def hslb_attraction_potential(ctx, phi: np.ndarray):
+    _chk(ctx, load().hslb_attraction_potential(ctx, _d(phi)))
 
 
 def hslb_get_populations(ctx, f: np.ndarray):
@@ -461,7 +467,8 @@ def hslb_cnn_op(op: int, nx: int, ny: int, nz: int, zper: bool, w, inp, aux=None
 
 def make_params(nx, ny, nz, sigma, tau, accel=(0.0, 0.0, 0.0), wall_lo=0, wall_hi=0,
                 g2_model=HSLB_G2_PAPER, wall_reg=1, precision=HSLB_FP64,
-                force_mode=HSLB_FORCE_EXACT, surr_check_every=50, surr_tol=1e-3) -> hslb_params:
+                force_mode=HSLB_FORCE_EXACT, surr_check_every=50, surr_tol=1e-3, att_eps=0.0,
+                att_range=0.0) -> hslb_params:
     p = hslb_params()
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     p.wall_lo, p.wall_hi = int(wall_lo), int(wall_hi)
@@ -471,6 +478,7 @@ def make_params(nx, ny, nz, sigma, tau, accel=(0.0, 0.0, 0.0), wall_lo=0, wall_h
     p.g2_model, p.wall_reg = int(g2_model), int(wall_reg)
     p.precision, p.force_mode = int(precision), int(force_mode)
     p.surr_check_every, p.surr_tol = int(surr_check_every), float(surr_tol)
+    p.att_eps, p.att_range = float(att_eps), float(att_range)
     return p
 
 
@@ -480,11 +488,13 @@ class Sim:
 
     def __init__(self, nx, ny, nz, sigma, tau, accel=(0.0, 0.0, 0.0), wall_lo=0, wall_hi=0,
                  precision="f64", g2_model=HSLB_G2_PAPER, wall_reg=1,
-                 force_mode=HSLB_FORCE_EXACT, surr_check_every=50, surr_tol=1e-3):
+                 force_mode=HSLB_FORCE_EXACT, surr_check_every=50, surr_tol=1e-3, att_eps=0.0,
+                 att_range=0.0):
         prec = {"f64": HSLB_FP64, "f32": HSLB_FP32}[precision] if isinstance(precision, str) \
             else int(precision)
         self.params = make_params(nx, ny, nz, sigma, tau, accel, wall_lo, wall_hi, g2_model,
-                                  wall_reg, prec, force_mode, surr_check_every, surr_tol)
+                                  wall_reg, prec, force_mode, surr_check_every, surr_tol, att_eps,
+                                  att_range)
         self.shape = (int(nz), int(ny), int(nx))
         self.N = int(nx) * int(ny) * int(nz)
         self.ctx = hslb_create(self.params)
@@ -531,6 +541,11 @@ class Sim:
         e = np.zeros(self.N)
         hslb_eta_bar(self.ctx, e)
         return e.reshape(self.shape)
+
+    def attraction_potential(self):
+        phi = np.zeros(self.N)
+        hslb_attraction_potential(self.ctx, phi)
+        return phi.reshape(self.shape)
 
     def get_populations(self):
         f = np.zeros(19 * self.N)

@@ -43,6 +43,8 @@ def test_library_exports_every_declared_symbol(lib):
     dict(tau=0.5), dict(tau=0.4), dict(sigma=1), dict(sigma=9), dict(nx=5),
     dict(wall_lo=1, wall_hi=0), dict(wall_lo=10, wall_hi=10), dict(precision=7),
     dict(g2_model=3), dict(force_mode=5), dict(accel=(float("nan"), 0.0, 0.0)),
+    dict(att_eps=1e-3, att_range=0.0), dict(att_eps=1e-3, att_range=10.5),
+    dict(att_eps=float("inf"), att_range=2.0),
 ])
 def test_create_rejects_bad_parameters(lib, bad):
     kw = dict(nx=12, ny=12, nz=20, sigma=4, tau=1.0, wall_lo=2, wall_hi=2)
@@ -63,6 +65,19 @@ def test_surrogate_geometry_and_judge_settings_are_validated(lib, nx, ny, K, tol
                         surr_check_every=K, surr_tol=tol)
     with pytest.raises(lib.HslbError) as ei:
         lib.hslb_create(p)
+    assert ei.value.code == lib.HSLB_EINVAL
+
+
+def test_attraction_is_rejected_with_the_learned_force_and_in_a_batch(lib):
+    p = lib.make_params(32, 32, 20, 4, 1.0, wall_lo=2, wall_hi=2, force_mode=lib.HSLB_FORCE_SURROGATE,
+                        att_eps=1e-3, att_range=2.0)
+    with pytest.raises(lib.HslbError) as ei:
+        lib.hslb_create(p)
+    assert ei.value.code == lib.HSLB_EINVAL
+    slits = [lib.make_params(16, 16, 24, 4, 1.0, wall_lo=2, wall_hi=2, precision=lib.HSLB_FP32,
+                             att_eps=1e-3 * k, att_range=2.0) for k in range(2)]
+    with pytest.raises(lib.HslbError) as ei:
+        lib.hslb_batch_create(slits)
     assert ei.value.code == lib.HSLB_EINVAL
 
 
