@@ -22,6 +22,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -137,6 +138,30 @@ def surrogate_leg(hslb, workloads, wl, steps: int, epochs: int):
     return out
 
 
+def attraction_leg(hslb, wl, n, u, steps: int):
+    """The benchmark slit with the mean-field attraction on (range sigma / 2,
+    a 25-point cube side, depth 1e-3): throughput over `steps` graph-replayed
+    steps, then the three potential passes and the collide timed per kernel."""
+    lam = wl.sigma / 2.0
+    s = hslb.Sim.from_workload(wl, att_eps=1e-3, att_range=lam)
+    s.init(n, u)
+    s.step(20)
+    s.sync()
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.sync()
+    dt = time.perf_counter() - t0
+    hslb.hslb_set_kernel_timing(s.ctx, True)
+    s.step(min(steps, 200))
+    s.sync()
+    kt = hslb.hslb_kernel_times(s.ctx)
+    s.close()
+    return {"workload": f"{wl.name} + attraction (range {lam:g}, cube side {2 * math.ceil(3 * lam) + 1})",
+            "steps": steps, "value": round(wl.fluid_nodes * steps / dt / 1e6, 1), "unit": "MLUPS",
+            "ms_per_step": round(dt / steps * 1e3, 5),
+            "kernels_us": {k: round(v[0] / v[1] * 1e3, 2) for k, v in kt.items()}}
+
+
 def cpu_baseline(wl, n, u, budget_s: float):
     import oracle
     o = oracle.Oracle(**wl.params())
@@ -166,6 +191,7 @@ def main():
     ap.add_argument("--no-kernel-pass", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-attraction", action="store_true")
     ap.add_argument("--surrogate-epochs", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -255,6 +281,11 @@ def main():
         print("bench: surrogate", file=sys.stderr, flush=True)
         surr = surrogate_leg(hslb, workloads, wl, args.steps, args.surrogate_epochs)
 
+    att = None
+    if not args.no_attraction:
+        print("bench: attraction", file=sys.stderr, flush=True)
+        att = attraction_leg(hslb, wl, n, u, args.steps)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
@@ -284,6 +315,7 @@ def main():
         "as_specified": as_specified,
         "ensemble": ens,
         "surrogate": surr,
+        "attraction": att,
         "roofline": roof,
         "kernels_us": kernels,
         "cpu_baseline": cpu,

@@ -239,6 +239,125 @@ def poiseuille_width(widths: Sequence[int], n_star: float = 0.512, sigma: int = 
     return {"sigma": sigma, "tau": tau, "g": g, "n_star": n_star, "rows": rows}
 
 
+# ------------------------------------------------- attraction: coexistence
+
+def att_lattice_sum(att_range: float) -> float:
+    """sum_o exp(-|o|^2 / range^2) over the cube |o_a| <= ceil(3 range)."""
+    R = math.ceil(3.0 * att_range)
+    m = np.arange(-R, R + 1, dtype=np.float64)
+    return float(np.sum(np.exp(-m * m / att_range ** 2))) ** 3
+
+
+def compressibility_Z(eta: float) -> float:
+    """Compressibility factor of the printed closure: Z = 1 + 4 eta g2(eta) =
+    (1 + eta + eta^2) / (1 - eta)^3."""
+    return (1.0 + eta + eta * eta) / (1.0 - eta) ** 3
+
+
+def mean_field_A(att_eps: float, att_range: float, sigma: int) -> float:
+    """The attraction's pressure -(eps G0 / 2) n^2 (G0 the lattice sum) in the
+    reduced form p pi sigma^3 / (6 k_B T) = eta Z(eta) - A eta^2."""
+    return att_eps * att_lattice_sum(att_range) / 2.0 * 6.0 / (math.pi * sigma ** 3) / VT2
+
+
+def mean_field_pressure(eta: float, A: float) -> float:
+    return eta * compressibility_Z(eta) - A * eta * eta
+
+
+def mean_field_betamu(eta: float, A: float) -> float:
+    """beta mu up to a constant: ln eta + beta mu_ex + Z - 1 - 2 A eta, with
+    beta mu_ex = int_0^eta (Z - 1)/e de = 3 / (2 (1 - eta)^2) - 3/2 - ln(1 - eta)
+    for this Z."""
+    return (math.log(eta) + 1.5 / (1.0 - eta) ** 2 - 1.5 - math.log(1.0 - eta)
+            + compressibility_Z(eta) - 1.0 - 2.0 * A * eta)
+
+
+def mean_field_critical():
+    """(eta_c, A_c) where dP/d eta and d2P/d eta2 vanish."""
+    from scipy.optimize import brentq
+    d1 = lambda e, h=1e-6: (e + h) * compressibility_Z(e + h) - (e - h) * compressibility_Z(e - h)  # noqa: E731
+    d2 = lambda e, h=1e-4: ((e + h) * compressibility_Z(e + h) - 2 * e * compressibility_Z(e)  # noqa: E731
+                           + (e - h) * compressibility_Z(e - h)) / (h * h)
+    eta_c = brentq(lambda e: d1(e) / (2e-6) / e - d2(e), 0.05, 0.3)
+    return eta_c, d2(eta_c) / 2.0
+
+
+def mean_field_binodal(A: float):
+    """Coexisting packing fractions (vapour, liquid): equal pressure and
+    chemical potential (the Maxwell construction of the mean-field EOS), by
+    nested bisection between the spinodal points; None at or above the
+    critical point."""
+    from scipy.optimize import brentq
+    eta_c, A_c = mean_field_critical()
+    if A <= A_c * (1 + 1e-9):
+        return None
+    dP = lambda e, h=1e-7: (mean_field_pressure(e + h, A) - mean_field_pressure(e - h, A)) / (2 * h)  # noqa: E731
+    s1 = brentq(dP, 1e-6, eta_c)        # spinodal, vapour side
+    s2 = brentq(dP, eta_c, 0.6)         # spinodal, liquid side
+
+    def vapour_at(eta_l):
+        p = mean_field_pressure(eta_l, A)
+        return brentq(lambda e: mean_field_pressure(e, A) - p, 1e-12, s1)
+
+    def mismatch(eta_l):
+        return mean_field_betamu(vapour_at(eta_l), A) - mean_field_betamu(eta_l, A)
+
+    # liquid packings whose pressure lies within the vapour branch's range
+    p_lo, p_hi = mean_field_pressure(1e-12, A), mean_field_pressure(s1, A)
+    lo = brentq(lambda e: mean_field_pressure(e, A) - p_lo, s2, 0.7) if mean_field_pressure(s2, A) < p_lo else s2
+    hi = brentq(lambda e: mean_field_pressure(e, A) - p_hi, s2, 0.7)
+    span = hi - lo
+    eta_l = brentq(mismatch, lo + 1e-9 * span, hi - 1e-9 * span)
+    return float(vapour_at(eta_l)), float(eta_l)
+
+
+def coexistence(quenches: Sequence[float], sigma: int = 4, tau: float = 1.0, att_range: float = 4.0,
+                L: int = 128, precision: str = "f64", max_steps: int = 30000, log=None) -> Dict:
+    """Liquid-vapour separation with the mean-field attraction: a periodic
+    16 x 16 x L box at the critical packing of the mean-field EOS, attraction
+    depth `quench` times its critical value, density n_c (1 + 0.02 cos(2 pi z/L)),
+    run until the profile is steady.  Reports the plateau packings against
+    the Maxwell construction of the same EOS."""
+    eta_c, A_c = mean_field_critical()
+    G0 = att_lattice_sum(att_range)
+    eps_c = A_c * 2.0 * VT2 * math.pi * sigma ** 3 / 6.0 / G0
+    n_c = workloads.number_density(eta_c, sigma)
+    z = np.arange(L)
+    rows = []
+    for q in quenches:
+        eps = q * eps_c
+        s = hslb.Sim(LATERAL, LATERAL, L, sigma, tau, precision=precision, att_eps=eps, att_range=att_range)
+        n0 = np.broadcast_to((n_c * (1.0 + 0.02 * np.cos(2.0 * math.pi * z / L)))[:, None, None],
+                             (L, LATERAL, LATERAL)).copy()
+        s.init(n0)
+        prev, done, change = None, 0, math.inf
+        while done < max_steps:
+            s.step(1000)
+            done += 1000
+            pn, _ = s.profiles()
+            if not np.isfinite(pn).all():
+                raise RuntimeError(f"coexistence run at quench {q} diverged by step {done}")
+            if prev is not None:
+                change = float(np.abs(pn - prev).max() / pn.max())
+                if change < 1e-10:
+                    break
+            prev = pn.copy()
+        pn, pu = s.profiles()
+        s.close()
+        eta = pn * math.pi * sigma ** 3 / 6.0
+        bi = mean_field_binodal(mean_field_A(eps, att_range, sigma))
+        row = {"quench": q, "eps": eps, "steps": done, "last_change": change, "eta_profile": eta.tolist(),
+               "eta_vapour": float(eta.min()), "eta_liquid": float(eta.max()),
+               "binodal": bi, "max_u": float(np.abs(pu).max())}
+        rows.append(row)
+        if log:
+            log(f"coexistence quench {q}: {done} steps, vapour {row['eta_vapour']:.4f} liquid "
+                f"{row['eta_liquid']:.4f} (mean-field binodal {bi[0]:.4f} / {bi[1]:.4f})" if bi else
+                f"coexistence quench {q}: {done} steps, packing {row['eta_vapour']:.4f}..{row['eta_liquid']:.4f}")
+    return {"sigma": sigma, "tau": tau, "att_range": att_range, "L": L, "eta_c": eta_c, "eps_c": eps_c,
+            "rows": rows}
+
+
 FIG1_NSTARS = (0.064, 0.128, 0.192, 0.256, 0.32, 0.384, 0.448, 0.512, 0.576, 0.609)
 FIG2_NSTARS = (0.256, 0.512, 0.609)
 FIG3_NSTARS = (0.064, 0.128, 0.256, 0.384, 0.512)
@@ -250,7 +369,8 @@ def run_all(sigma: int = 8, log=print) -> Dict:
     out = {"fig1": viscosity_sweep(FIG1_NSTARS, sigma=sigma, log=log),
            "fig2": statics(FIG2_NSTARS, sigma=sigma, log=log),
            "fig3": poiseuille_density(FIG3_NSTARS, sigma=sigma, log=log),
-           "fig4": poiseuille_width(FIG4_WIDTHS, sigma=sigma, log=log)}
+           "fig4": poiseuille_width(FIG4_WIDTHS, sigma=sigma, log=log),
+           "coexistence": coexistence((0.9, 1.05, 1.1), log=log)}
     out["seconds"] = time.perf_counter() - t0
     return out
 

@@ -35,3 +35,29 @@ def test_near_wall_drop():
     assert ex.near_wall_drop(bump) == pytest.approx((par[10] - par[4]) / par.max())
     # the same bump at the other wall counts the same
     assert ex.near_wall_drop(bump[::-1]) == pytest.approx(ex.near_wall_drop(bump))
+
+
+def test_mean_field_eos_and_binodal():
+    """The closed-form excess chemical potential of the printed closure's EOS
+    against quadrature of (Z - 1)/eta, the critical point (dP = d2P = 0), and
+    the binodal's equal pressure and chemical potential."""
+    from scipy.integrate import quad
+    for eta in (0.05, 0.2, 0.35):
+        ex_mu = quad(lambda e: (ex.compressibility_Z(e) - 1.0) / e, 0.0, eta)[0]
+        closed = ex.mean_field_betamu(eta, 0.0) - math.log(eta) - ex.compressibility_Z(eta) + 1.0
+        assert closed == pytest.approx(ex_mu, rel=1e-10)
+    ec, Ac = ex.mean_field_critical()
+    h = 1e-4
+    P = lambda e: ex.mean_field_pressure(e, Ac)  # noqa: E731
+    assert abs((P(ec + h) - P(ec - h)) / (2 * h)) < 1e-6
+    assert abs((P(ec + h) - 2 * P(ec) + P(ec - h)) / h ** 2) < 1e-3
+    assert ex.mean_field_binodal(0.95 * Ac) is None
+    for q in (1.02, 1.1, 1.5):
+        v, l = ex.mean_field_binodal(q * Ac)
+        assert v < ec < l
+        A = q * Ac
+        assert ex.mean_field_pressure(v, A) == pytest.approx(ex.mean_field_pressure(l, A), rel=1e-8, abs=1e-12)
+        assert ex.mean_field_betamu(v, A) == pytest.approx(ex.mean_field_betamu(l, A), rel=1e-8, abs=1e-10)
+    # the attraction's A from its depth and lattice sum
+    assert ex.mean_field_A(2.0, 1.5, 4) == pytest.approx(
+        2.0 * ex.att_lattice_sum(1.5) / 2 * 6 / (math.pi * 64) * 3, rel=1e-14)

@@ -109,3 +109,47 @@ def test_full_size_potential_at_sampled_nodes():
     got = np.array([phi[z, y, x] for z, y, x in nodes])
     assert np.abs(got - ref).max() <= 1e-9 * np.abs(ref).max()
     assert math.isfinite(float(np.abs(phi).max()))
+
+
+def test_quench_against_oracle_column():
+    """The coexistence run's box (16 x 16 x 128 periodic, sigma 4, tau 1,
+    attraction range 4 at 1.05 times the critical depth), 300 steps into the
+    separation, against a 1 x 1 x 128 oracle column (laterally uniform)."""
+    from paper_0712_2247_amd import experiments as ex
+    sigma, L, lam = 4, 128, 4.0
+    eta_c, A_c = ex.mean_field_critical()
+    eps = 1.05 * A_c * 2.0 * ex.VT2 * math.pi * sigma ** 3 / 6.0 / ex.att_lattice_sum(lam)
+    n_c = workloads.number_density(eta_c, sigma)
+    z = np.arange(L)
+    col = n_c * (1.0 + 0.02 * np.cos(2.0 * math.pi * z / L))
+    g = hslb.Sim(16, 16, L, sigma, 1.0, att_eps=eps, att_range=lam)
+    g.init(np.broadcast_to(col[:, None, None], (L, 16, 16)).copy())
+    o = oracle.Oracle(1, 1, L, sigma, 1.0, att_eps=eps, att_range=lam)
+    o.init(col[:, None, None])
+    g.step(300)
+    o.step(300)
+    gn, gu = g.profiles()
+    on, ou = o.profiles()
+    print(f"density contrast after 300 steps: {gn.max() / gn.min():.3f}", flush=True)
+    assert gn.max() / gn.min() > 1.1      # well into the separation
+    assert np.abs(gn - on).max() <= 1e-11 * on.max()
+    assert np.abs(gu - ou).max() <= 1e-9 * np.abs(ou).max()
+
+
+def test_phase_separation_reaches_mean_field_binodal():
+    """Below the critical attraction the perturbed uniform state relaxes; above
+    it the box separates into liquid and vapour slabs whose packings match the
+    Maxwell construction of the mean-field EOS (hard-sphere Z of the printed
+    closure minus the attraction's A eta^2) within 2 %."""
+    from paper_0712_2247_amd import experiments as ex
+    res = ex.coexistence((0.9, 1.05, 1.1))
+    for r in res["rows"]:
+        print(f"quench {r['quench']}: {r['steps']} steps, vapour {r['eta_vapour']:.4f}, liquid "
+              f"{r['eta_liquid']:.4f}, binodal {r['binodal']}", flush=True)
+    sub = res["rows"][0]
+    assert sub["binodal"] is None and sub["eta_liquid"] - sub["eta_vapour"] < 1e-6
+    for r in res["rows"][1:]:
+        assert r["last_change"] < 1e-10
+        v, l = r["binodal"]
+        assert r["eta_vapour"] == pytest.approx(v, rel=0.02)
+        assert r["eta_liquid"] == pytest.approx(l, rel=0.02)
