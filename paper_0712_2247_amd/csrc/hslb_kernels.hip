@@ -770,6 +770,7 @@ __global__ __launch_bounds__(256) void k_att_x(LatticeDev L, AttWeights aw, cons
     int xm = (x - aw.R) % L.nx;
     xm = xm < 0 ? xm + L.nx : xm;
     double s = 0.0;
+#pragma unroll 8
     for (int m = 0; m <= 2 * aw.R; ++m) {
         s += aw.w[m] * (double)row[xm];
         xm = (xm + 1 == L.nx) ? 0 : xm + 1;
@@ -790,6 +791,7 @@ __global__ __launch_bounds__(256) void k_att_y(LatticeDev L, AttWeights aw, cons
     int ym = (y - aw.R) % L.ny;
     ym = ym < 0 ? ym + L.ny : ym;
     double s = 0.0;
+#pragma unroll 8
     for (int m = 0; m <= 2 * aw.R; ++m) {
         s += aw.w[m] * col[(size_t)L.nx * ym];
         ym = (ym + 1 == L.ny) ? 0 : ym + 1;
@@ -809,15 +811,16 @@ __global__ __launch_bounds__(256) void k_att_z(LatticeDev L, AttWeights aw, cons
     if (L.zper) {
         int zm = (z - aw.R) % L.nz;
         zm = zm < 0 ? zm + L.nz : zm;
+#pragma unroll 8
         for (int m = 0; m <= 2 * aw.R; ++m) {
             s += aw.w[m] * b[(size_t)L.plane * zm + r];
             zm = (zm + 1 == L.nz) ? 0 : zm + 1;
         }
     } else {
-        for (int m = 0; m <= 2 * aw.R; ++m) {
-            const int zm = z + m - aw.R;
-            if (zm >= 0 && zm < L.nz) s += aw.w[m] * b[(size_t)L.plane * zm + r];
-        }
+        // only the offsets that stay inside the array contribute
+        const int m0 = max(0, aw.R - z), m1 = min(2 * aw.R, L.nz - 1 - z + aw.R);
+#pragma unroll 8
+        for (int m = m0; m <= m1; ++m) s += aw.w[m] * b[(size_t)L.plane * (z + m - aw.R) + r];
     }
     out[(size_t)L.plane * z + r] = -aw.eps * s;
 }
