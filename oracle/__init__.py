@@ -74,6 +74,8 @@ def _load():
                  "hsref_step_with_force", "hsref_attraction_potential"):
         getattr(lib, name).argtypes = [ctypes.c_void_p, d]
         getattr(lib, name).restype = ctypes.c_int
+    lib.hsref_set_solid.argtypes = [ctypes.c_void_p, P(ctypes.c_uint8)]
+    lib.hsref_set_solid.restype = ctypes.c_int
     lib.hsref_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
     lib.hsref_step.restype = ctypes.c_int
     lib.hsref_g2.argtypes = [ctypes.c_int, ctypes.c_double]
@@ -185,6 +187,12 @@ class Oracle:
     def _chk(self, rc, what):
         if rc != 0:
             raise ValueError(f"oracle {what} failed ({rc})")
+
+    def set_solid(self, solid):
+        """Solid mask [nz, ny, nx] (nonzero: solid), before init."""
+        m = np.ascontiguousarray(np.asarray(solid) != 0, dtype=np.uint8).reshape(self.N)
+        self._chk(self._lib.hsref_set_solid(self._ctx, m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))),
+                  "set_solid")
 
     def init(self, n, u=None):
         n = np.ascontiguousarray(n, dtype=np.float64).reshape(self.N)

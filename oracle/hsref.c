@@ -55,6 +55,15 @@
  * with R = ceil(3 att_range), the same n = 0 on solid nodes and beyond the
  * array, and periodic images along periodic axes.  Written here as the plain
  * triple sum.
+ *
+ * Optional solid mask (hsref_set_solid): any node may be solid, beyond the wall
+ * layers.  Solid nodes carry n = j = 0 and take part in nothing; a population
+ * heading into a solid node returns reversed (halfway bounce-back), as at the
+ * walls; the wall factor of a fluid node uses the distance to the nearest
+ * solid surface, read as the distance to the nearest solid node centre (wall
+ * layers included, periodic images along periodic axes) minus half a lattice
+ * spacing, which is the halfway-plane distance of the flat walls.  Found here
+ * by brute force over all solid nodes.
  */
 #include <math.h>
 #include <stdint.h>
@@ -134,6 +143,8 @@ struct hsref_ctx {
     double *F;       /* [3][N] total force */
     double *phi;     /* [N] mean-field attraction potential (att_eps != 0) */
     int att_R;       /* its cube half-width, ceil(3 att_range) */
+    uint8_t *solid;  /* [N] solid mask (NULL: only the wall layers are solid) */
+    double *chi_n;   /* [N] per-node wall factor when a mask is set */
 };
 
 typedef struct hsref_ctx hsref_ctx;
@@ -249,7 +260,14 @@ static int fluid_node(const hsref_ctx *c, int64_t id)
 {
     if (id < 0) return 0;
     int z = (int)(id / ((int64_t)c->p.nx * c->p.ny));
-    return !is_solid_z(c, z);
+    if (is_solid_z(c, z)) return 0;
+    return !(c->solid && c->solid[id]);
+}
+
+/* Wall factor of the receiving node. */
+static double chi_at(const hsref_ctx *c, int64_t id, int z)
+{
+    return c->chi_n ? c->chi_n[id] : c->chi[z];
 }
 
 /* ---------------------------------------------------------------- create */
@@ -329,7 +347,7 @@ void hsref_destroy(hsref_ctx *c)
 {
     if (!c) return;
     free(c->ball); free(c->chi); free(c->f); free(c->fs); free(c->n); free(c->j);
-    free(c->u); free(c->eb); free(c->F); free(c->phi);
+    free(c->u); free(c->eb); free(c->F); free(c->phi); free(c->solid); free(c->chi_n);
     free(c);
 }
 
@@ -344,7 +362,7 @@ static void phase_moments(hsref_ctx *c)
     for (int z = 0; z < c->p.nz; ++z) {
         for (int64_t id = z * plane; id < (z + 1) * plane; ++id) {
             double n = 0.0, j[3] = {0.0, 0.0, 0.0};
-            if (!is_solid_z(c, z)) {
+            if (fluid_node(c, id)) {
                 for (int i = 0; i < NQ; ++i) {
                     double fi = c->f[(int64_t)i * N + id];
                     n += fi;
@@ -458,7 +476,7 @@ static void phase_force(hsref_ctx *c)
             for (int x = 0; x < c->p.nx; ++x) {
                 int64_t id = z * plane + (int64_t)y * c->p.nx + x;
                 double Fv[3] = {0.0, 0.0, 0.0};
-                if (!is_solid_z(c, z)) {
+                if (fluid_node(c, id)) {
                     double nr = c->n[id];
                     double ur[3] = {c->u[id], c->u[N + id], c->u[2 * N + id]};
                     double S[3] = {0.0, 0.0, 0.0};
@@ -478,7 +496,7 @@ static void phase_force(hsref_ctx *c)
                                     double cur = 0.0;
                                     for (int a = 0; a < 3; ++a)
                                         cur += e->s[a] * (c->j[a * N + id2] - n2 * ur[a]);
-                                    acc += e->alpha[k] * G * (n2 - c->chi[z] * kappa * cur);
+                                    acc += e->alpha[k] * G * (n2 - chi_at(c, id, z) * kappa * cur);
                                 }
                                 for (int a = 0; a < 3; ++a) Sp[a] += e->W * e->s[a] * acc;
                             }
@@ -520,6 +538,7 @@ static void phase_collide_stream(hsref_ctx *c)
         for (int y = 0; y < c->p.ny; ++y) {
             for (int x = 0; x < c->p.nx; ++x) {
                 int64_t id = z * plane + (int64_t)y * c->p.nx + x;
+                if (!fluid_node(c, id)) continue;
                 double n = c->n[id];
                 double u[3] = {c->u[id], c->u[N + id], c->u[2 * N + id]};
                 double F[3] = {c->F[id], c->F[N + id], c->F[2 * N + id]};
@@ -651,6 +670,56 @@ int hsref_force(hsref_ctx *c, double *F)
     if (c->att_R > 0) phase_attraction(c);
     phase_force(c);
     memcpy(F, c->F, sizeof(double) * 3 * (size_t)c->N);
+    return 0;
+}
+
+/* Solid mask solid[N] (nonzero: solid), before hsref_init.  Rebuilds the
+ * per-node wall factor by brute force over the solid nodes. */
+int hsref_set_solid(hsref_ctx *c, const uint8_t *solid)
+{
+    if (!c || !solid) return -1;
+    const int64_t N = c->N, plane = (int64_t)c->p.nx * c->p.ny;
+    if (!c->solid) c->solid = malloc((size_t)N);
+    if (!c->chi_n) c->chi_n = malloc(sizeof(double) * (size_t)N);
+    if (!c->solid || !c->chi_n) return -1;
+    for (int64_t id = 0; id < N; ++id) c->solid[id] = solid[id] ? 1 : 0;
+    /* solid node centres: mask and wall layers */
+    int64_t ns = 0;
+    for (int64_t id = 0; id < N; ++id)
+        if (!fluid_node(c, id)) ++ns;
+    int (*sp)[3] = malloc(sizeof(int[3]) * (size_t)(ns ? ns : 1));
+    if (!sp) return -1;
+    ns = 0;
+    for (int64_t id = 0; id < N; ++id)
+        if (!fluid_node(c, id)) {
+            sp[ns][2] = (int)(id / plane);
+            sp[ns][1] = (int)((id % plane) / c->p.nx);
+            sp[ns][0] = (int)(id % c->p.nx);
+            ++ns;
+        }
+    const int sig = c->p.sigma >= 2 ? c->p.sigma : 2;
+    const int dims[3] = {c->p.nx, c->p.ny, c->p.nz};
+    const int per[3] = {1, 1, c->zperiodic};
+#pragma omp parallel for schedule(static) if (N >= PAR_MIN_NODES)
+    for (int64_t id = 0; id < N; ++id) {
+        double chi = 1.0;
+        if (c->p.wall_reg && ns > 0 && fluid_node(c, id)) {
+            const int r[3] = {(int)(id % c->p.nx), (int)((id % plane) / c->p.nx), (int)(id / plane)};
+            int64_t best = -1;
+            for (int64_t k = 0; k < ns; ++k) {
+                int64_t d2 = 0;
+                for (int a = 0; a < 3; ++a) {
+                    int d = abs(r[a] - sp[k][a]);
+                    if (per[a] && dims[a] - d < d) d = dims[a] - d;   /* nearest periodic image */
+                    d2 += (int64_t)d * d;
+                }
+                if (best < 0 || d2 < best) best = d2;
+            }
+            chi = 1.0 - exp(-(sqrt((double)best) - 0.5) / (double)sig);
+        }
+        c->chi_n[id] = chi;
+    }
+    free(sp);
     return 0;
 }
 
