@@ -151,6 +151,18 @@ int hslb_force(hslb_ctx *ctx, double *F);
  * current state. */
 int hslb_eta_bar(hslb_ctx *ctx, double *eta_bar);
 
+/* Solid mask solid[N] (host, nonzero: solid node), beyond the wall layers;
+ * call before hslb_init.  Solid nodes carry n = j = 0; a population heading
+ * into one returns reversed to its node (halfway bounce-back, as at the walls
+ * of section "Numerical validation"); the wall factor of a fluid node uses
+ * d_w = (distance to the nearest solid node centre, wall layers included,
+ * periodic images along periodic axes) - 1/2, which is the halfway-plane
+ * distance of flat walls.  With FP32 storage the reference tables are then
+ * kept FP32-representable, so solid nodes hold exact zeros.  Errors:
+ * HSLB_ESTATE after hslb_init or on a batch, HSLB_EINVAL with the learned
+ * force or a NULL mask. */
+int hslb_set_solid(hslb_ctx *ctx, const uint8_t *solid);
+
 /* Mean-field attraction potential Phi[N] (see hslb_params.att_eps) at the
  * current state, solid layers included; all zero when the attraction is off. */
 int hslb_attraction_potential(hslb_ctx *ctx, double *phi);

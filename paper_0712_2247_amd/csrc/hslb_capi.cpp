@@ -22,6 +22,82 @@ using namespace hslb;
 
 namespace {
 
+// ------------------------------------------------ distance to solid nodes
+
+constexpr double kEdtInf = 1e30;
+
+// Lower envelope of parabolas (Felzenszwalb and Huttenlocher's distance
+// transform) along one line of m samples: out[q] = min_p f[p] + (q - p)^2
+// over the p with f[p] < kEdtInf (kEdtInf everywhere when there is none).
+void edt_line(const double *f, int m, double *out, std::vector<int> &v, std::vector<double> &zb)
+{
+    v.resize(m);
+    zb.resize(m + 1);
+    int k = -1;
+    for (int q = 0; q < m; ++q) {
+        if (f[q] >= kEdtInf) continue;
+        if (k < 0) {
+            k = 0;
+            v[0] = q;
+            zb[0] = -kEdtInf;
+            zb[1] = kEdtInf;
+            continue;
+        }
+        double s;
+        while (true) {
+            const int p = v[k];
+            s = ((f[q] + (double)q * q) - (f[p] + (double)p * p)) / (2.0 * (q - p));
+            if (s > zb[k] || k == 0) break;
+            --k;
+        }
+        if (s <= zb[k]) {  // only for k == 0: the new parabola is lower everywhere
+            v[0] = q;
+            zb[1] = kEdtInf;
+            continue;
+        }
+        ++k;
+        v[k] = q;
+        zb[k] = s;
+        zb[k + 1] = kEdtInf;
+    }
+    if (k < 0) {
+        for (int q = 0; q < m; ++q) out[q] = kEdtInf;
+        return;
+    }
+    int j = 0;
+    for (int q = 0; q < m; ++q) {
+        while (zb[j + 1] < q) ++j;
+        const double d = (double)(q - v[j]);
+        out[q] = d * d + f[v[j]];
+    }
+}
+
+// Squared Euclidean distance from every node to the nearest solid node centre
+// (periodic images along x, y and, if zper, z), by one line transform per
+// axis; a periodic line is transformed as three copies and read in the middle.
+void solid_distance2(const std::vector<uint8_t> &sol, int nx, int ny, int nz, bool zper, std::vector<double> &d2)
+{
+    const int N = nx * ny * nz;
+    d2.assign(N, kEdtInf);
+    for (int id = 0; id < N; ++id)
+        if (sol[id]) d2[id] = 0.0;
+    std::vector<int> v;
+    std::vector<double> zb, in, out;
+    auto axis = [&](int n, bool per, int count, auto index) {
+        const int m = per ? 3 * n : n;
+        in.resize(m);
+        out.resize(m);
+        for (int l = 0; l < count; ++l) {
+            for (int q = 0; q < m; ++q) in[q] = d2[index(l, q % n)];
+            edt_line(in.data(), m, out.data(), v, zb);
+            for (int q = 0; q < n; ++q) d2[index(l, q)] = out[per ? q + n : q];
+        }
+    };
+    axis(nx, true, ny * nz, [&](int l, int q) { return q + nx * l; });
+    axis(ny, true, nx * nz, [&](int l, int q) { return (l % nx) + nx * (q + ny * (l / nx)); });
+    axis(nz, zper, nx * ny, [&](int l, int q) { return l + nx * ny * q; });
+}
+
 struct KernelTimer {
     bool enabled = false;
     std::vector<hipEvent_t> pool;
@@ -56,6 +132,11 @@ public:
     virtual int force(double *F) = 0;
     virtual int eta_bar(double *eb) = 0;
     virtual int attraction_potential(double *phi) = 0;
+    virtual int set_solid(const uint8_t *solid)
+    {
+        (void)solid;
+        return fail_state("not available on a batch");
+    }
     virtual int get_pop(double *f) = 0;
     virtual int set_pop(const double *f) = 0;
     virtual int sync() = 0;
@@ -177,6 +258,8 @@ public:
         (void)hipFree(fld_mem_);
         (void)hipFree(chi_d_);
         (void)hipFree(att_d_);
+        (void)hipFree(links_d_);
+        (void)hipFree(chi_n_d_);
         (void)hipFree(prof_d_);
         (void)hipFree(nref_d_);
         (void)hipHostFree(prof_h_);
@@ -297,9 +380,19 @@ public:
 
     // Store full FP64 populations [19][N] (device): the reference tables
     // become their layer means, then the populations are stored relative to them.
+    // With a solid mask and FP32 storage, reference tables are rounded to
+    // FP32 so that a solid node's zero populations are stored exactly (-ref).
+    int round_refs(double *table)
+    {
+        if (sc_.links && sizeof(TF) == 4) HIP_TRY(launch_round_f32(st(), table, NQ * L_.nz));
+        return HSLB_OK;
+    }
+
     int store_populations(const double *stage)
     {
         HIP_TRY(launch_layer_means<double>(st(), L_, stage, L_.N, nullptr, nref_d_));
+        int rc = round_refs(nref_d_);
+        if (rc) return rc;
         HIP_TRY(hipMemcpyAsync(nref_d_ + NQ * L_.nz, nref_d_, sizeof(double) * NQ * L_.nz, hipMemcpyDeviceToDevice,
                                st()));
         HIP_TRY(launch_set_pop<TF>(st(), L_, nref_d_, stage, f_[cur_]));
@@ -309,6 +402,20 @@ public:
     int init(const double *n, const double *u) override
     {
         const int N = L_.N;
+        std::vector<double> nm, um;
+        if (!solid_h_.empty()) {
+            // solid nodes carry nothing
+            nm.assign(n, n + N);
+            if (u) um.assign(u, u + 3 * (size_t)N);
+            for (int id = 0; id < N; ++id)
+                if (solid_h_[id]) {
+                    nm[id] = 0.0;
+                    if (u)
+                        for (int a = 0; a < 3; ++a) um[(size_t)a * N + id] = 0.0;
+                }
+            n = nm.data();
+            if (u) u = um.data();
+        }
         double msum = 0.0;
         int64_t nfl = 0;
         for (int id = 0; id < N; ++id) {
@@ -440,7 +547,9 @@ public:
     int refresh_step()
     {
         HIP_TRY(launch_layer_means<TF>(st(), L_, f_[cur_], L_.pop_stride, nref_d_, nref_d_ + NQ * L_.nz));
-        int rc = one_step();
+        int rc = round_refs(nref_d_ + NQ * L_.nz);
+        if (rc) return rc;
+        rc = one_step();
         if (rc) return rc;
         HIP_TRY(hipMemcpyAsync(nref_d_, nref_d_ + NQ * L_.nz, sizeof(double) * NQ * L_.nz, hipMemcpyDeviceToDevice,
                                st()));
@@ -597,6 +706,52 @@ public:
         return HSLB_OK;
     }
 
+    int set_solid(const uint8_t *solid) override
+    {
+        if (inited) return fail(err, HSLB_ESTATE, "set_solid after init");
+        if (p_.force_mode == HSLB_FORCE_SURROGATE)
+            return fail(err, HSLB_EINVAL, "solid masks are not available with the learned force");
+        const int N = L_.N, nx = L_.nx, ny = L_.ny, nz = L_.nz;
+        solid_h_.assign(N, 0);
+        std::vector<uint8_t> sol(N);
+        for (int id = 0; id < N; ++id) {
+            solid_h_[id] = (solid[id] != 0 && fluid_z(id / L_.plane)) ? 1 : 0;
+            sol[id] = (solid[id] != 0 || !fluid_z(id / L_.plane)) ? 1 : 0;
+        }
+        std::vector<uint32_t> links(N, 0u);
+        for (int id = 0; id < N; ++id) {
+            const int z = id / L_.plane, y = (id / nx) % ny, x = id % nx;
+            if (sol[id]) {
+                links[id] = LINK_SOLID;
+                continue;
+            }
+            for (int i = 0; i < NQ; ++i) {
+                const int xt = (x + CX[i] + nx) % nx, yt = (y + CY[i] + ny) % ny;
+                int zt = z + CZ[i];
+                if (L_.zper) zt = (zt + nz) % nz;
+                if (zt < 0 || zt >= nz || sol[xt + nx * (yt + ny * zt)]) links[id] |= 1u << i;
+            }
+        }
+        std::vector<double> chi(N, 1.0);
+        if (p_.wall_reg) {
+            std::vector<double> d2;
+            solid_distance2(sol, nx, ny, nz, L_.zper != 0, d2);
+            for (int id = 0; id < N; ++id)
+                if (!sol[id] && d2[id] < kEdtInf)
+                    chi[id] = 1.0 - std::exp(-(std::sqrt(d2[id]) - 0.5) / (double)sigma_);
+        }
+        if (!links_d_ && hipMalloc(&links_d_, sizeof(uint32_t) * N) != hipSuccess)
+            return fail(err, HSLB_ENOMEM, "solid links do not fit");
+        if (!chi_n_d_ && hipMalloc(&chi_n_d_, sizeof(double) * N) != hipSuccess)
+            return fail(err, HSLB_ENOMEM, "wall factors do not fit");
+        HIP_TRY(hipMemcpy(links_d_, links.data(), sizeof(uint32_t) * N, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(chi_n_d_, chi.data(), sizeof(double) * N, hipMemcpyHostToDevice));
+        sc_.links = links_d_;
+        sc_.chi_n = chi_n_d_;
+        drop_graphs();
+        return HSLB_OK;
+    }
+
     int attraction_potential(double *phi) override
     {
         if (!inited) return fail(err, HSLB_ESTATE, "attraction_potential before init");
@@ -646,10 +801,19 @@ public:
         for (size_t k = 0; k < tot; ++k)
             if (!std::isfinite(f[k]))
                 return fail(err, HSLB_EINVAL, "population %zu is not finite", k);
+        std::vector<double> fm;
+        if (!solid_h_.empty()) {
+            fm.assign(f, f + tot);
+            for (int id = 0; id < L_.N; ++id)
+                if (solid_h_[id])
+                    for (int i = 0; i < NQ; ++i) fm[(size_t)i * L_.N + id] = 0.0;
+            f = fm.data();
+        }
         double *d;
         int rc = io(sizeof(double) * tot, &d);
         if (rc) return rc;
         HIP_TRY(hipMemcpyAsync(d, f, sizeof(double) * tot, hipMemcpyHostToDevice, st()));
+        HIP_TRY(hipStreamSynchronize(st()));
         rc = store_populations(d);
         if (rc) return rc;
         HIP_TRY(hipStreamSynchronize(st()));
@@ -996,6 +1160,9 @@ private:
     StepConst sc_{};
     AttWeights aw_{};
     double *att_d_ = nullptr;  // attraction: x-pass, y-pass, potential [N] each
+    std::vector<uint8_t> solid_h_;  // solid mask (empty: walls only)
+    uint32_t *links_d_ = nullptr;   // [N] solid-neighbour bits (mask set)
+    double *chi_n_d_ = nullptr;     // [N] per-node wall factor (mask set)
     int sigma_ = 2;
     hipStream_t stream_ = nullptr, ext_stream_ = nullptr;
     bool own_stream_ = false;
@@ -1046,6 +1213,8 @@ void slit_consts(const hslb_params &p, LatticeDev &L, StepConst &sc, std::vector
     sc.g2_model = p.g2_model;
     sc.hs_on = (p.force_mode == HSLB_FORCE_OFF) ? 0 : 1;
     sc.phi = nullptr;
+    sc.links = nullptr;
+    sc.chi_n = nullptr;
     chi.assign(p.nz, 1.0);
     if (!L.zper && p.wall_reg) {
         const double za = p.wall_lo - 0.5, zb = p.nz - p.wall_hi - 0.5;
@@ -1696,6 +1865,13 @@ int hslb_eta_bar(hslb_ctx *ctx, double *eb)
     if (!eb) return fail(ctx->eng->err, HSLB_EINVAL, "null output");
     if (ctx->p.force_mode == HSLB_FORCE_OFF) return fail(ctx->eng->err, HSLB_ESTATE, "hard-sphere term is off");
     return ctx->eng->eta_bar(eb);
+}
+
+int hslb_set_solid(hslb_ctx *ctx, const uint8_t *solid)
+{
+    CTX_CHECK(ctx);
+    if (!solid) return fail(ctx->eng->err, HSLB_EINVAL, "null mask");
+    return ctx->eng->set_solid(solid);
 }
 
 int hslb_attraction_potential(hslb_ctx *ctx, double *phi)

@@ -8,6 +8,11 @@
 namespace hslb {
 
 constexpr int NQ = 19;
+// D3Q19 velocities and opposite directions (host and device)
+constexpr int CX[NQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int CY[NQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int CZ[NQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+constexpr int OPP[NQ] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
 constexpr int NGSLOT = 7;  // contact-value sub-lattices: bits x=1, y=2, z=4 (0..6)
 
 // Workgroups are handed to the 8 XCDs round-robin by linear block index.  This
@@ -59,7 +64,14 @@ struct StepConst {
     // Mean-field attraction potential [N] (node order, no padding), or null:
     // the force gains -n (phi(r + e_a) - phi(r - e_a)) / 2.
     const double *phi;
+    // Solid mask, or null: links[N] has bit i set when the node's neighbour
+    // along c_i is solid, and LINK_SOLID when the node itself is; chi_n[N] is
+    // then the per-node wall factor.
+    const uint32_t *links;
+    const double *chi_n;
 };
+
+constexpr uint32_t LINK_SOLID = 1u << 31;
 
 // Separable weights of the mean-field attraction: w[m + R] = exp(-m^2 /
 // range^2) for |m| <= R, and the depth eps.
@@ -144,6 +156,10 @@ hipError_t launch_set_pop(hipStream_t s, const LatticeDev &L, const double *nref
                           TF *f);
 
 hipError_t launch_copy(hipStream_t s, const void *src, void *dst, size_t bytes);
+
+// a[k] = (double)(float)a[k]: FP32-representable reference tables, so that a
+// solid node (all populations 0) is stored exactly as -ref in FP32.
+hipError_t launch_round_f32(hipStream_t s, double *a, int count);
 
 // Mean-field attraction potential of the padded density field n over all nz
 // layers, as three passes along x, y and z (a and b hold the partial sums,

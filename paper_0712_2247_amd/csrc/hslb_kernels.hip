@@ -31,10 +31,6 @@ namespace hslb {
 
 namespace {
 
-constexpr int CX[NQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
-constexpr int CY[NQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
-constexpr int CZ[NQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
-constexpr int OPP[NQ] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
 
 __device__ __forceinline__ constexpr double wq(int i)
 {
@@ -592,7 +588,7 @@ __device__ __forceinline__ void node_force(const Fields<TM> &F, const LatticeDev
         c.u[0] = (TC)u[0];
         c.u[1] = (TC)u[1];
         c.u[2] = (TC)u[2];
-        c.ckap = (TC)(chi[z] * sc.kappa);
+        c.ckap = (TC)((sc.chi_n ? sc.chi_n[x + L.nx * (y + L.ny * z)] : chi[z]) * sc.kappa);
         const TC alpha[4] = {(TC)sc.alpha[0], (TC)sc.alpha[1], (TC)sc.alpha[2], (TC)sc.alpha[3]};
         shell_sum<SIG, LZ>(F, L, c, alpha, S);
     }
@@ -637,6 +633,18 @@ __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &
     const size_t lstride = EB * (size_t)L.plane;
     const uint32_t rb = (uint32_t)r * EB;
     const int id = z * L.plane + r;
+    // solid mask: a solid node only restates its (zero) populations against
+    // the write reference; its neighbours bounce off it
+    uint32_t lk = 0;
+    if (sc.links) {
+        lk = sc.links[id];
+        if (lk & LINK_SOLID) {
+            const double *rw = layer_ref(sc.nref_w, z);
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) fout[(size_t)i * L.pop_stride + id] = (TF)(0.0 - rw[i]);
+            return;
+        }
+    }
     double f[NQ];
     const double *rr = layer_ref(sc.nref_r, z);
     if constexpr (LZ) {
@@ -674,11 +682,11 @@ __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &
         const int xt = wrapr(x + CX[i], L.nx);
         const int yt = wrapr(y + CY[i], L.ny);
         int zt = z + CZ[i];
-        bool bounce = false;
+        bool bounce = (lk >> i) & 1u;
         if (L.zper) {
             zt = (zt < 0) ? zt + L.nz : ((zt >= L.nz) ? zt - L.nz : zt);
         } else {
-            bounce = (zt < L.wall_lo) || (zt >= L.nz - L.wall_hi);
+            bounce = bounce || (zt < L.wall_lo) || (zt >= L.nz - L.wall_hi);
         }
         // stored relative to the reference of the layer it lands in
         if constexpr (LZ) {
@@ -1084,6 +1092,12 @@ __global__ __launch_bounds__(256) void kb_layer_means(const SlitDesc *__restrict
 
 // Plain device-to-device copy (16-byte lanes, grid-stride): the achievable
 // HBM bandwidth reference and the calibration kernel of the traffic counters.
+__global__ __launch_bounds__(256) void k_round_f32(double *__restrict__ a, int count)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k < count) a[k] = (double)(float)a[k];
+}
+
 __global__ __launch_bounds__(256) void k_copy(const float4 *__restrict__ a, float4 *__restrict__ b, size_t n)
 {
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) b[i] = a[i];
@@ -1102,6 +1116,12 @@ hipError_t launch_attraction(hipStream_t s, const LatticeDev &L, const AttWeight
     hipLaunchKernelGGL((k_att_x<TM>), g, blk, 0, s, L, aw, n, a);
     hipLaunchKernelGGL(k_att_y, g, blk, 0, s, L, aw, a, b);
     hipLaunchKernelGGL(k_att_z, g, blk, 0, s, L, aw, b, phi);
+    return hipGetLastError();
+}
+
+hipError_t launch_round_f32(hipStream_t s, double *a, int count)
+{
+    hipLaunchKernelGGL(k_round_f32, dim3(blocks_for(count)), dim3(256), 0, s, a, count);
     return hipGetLastError();
 }
 

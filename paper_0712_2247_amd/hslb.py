@@ -43,7 +43,8 @@ HSLB_CNN_NWEIGHTS = 144067
 EXPORTS = (
     "hslb_create", "hslb_destroy", "hslb_last_error", "hslb_set_stream", "hslb_init",
     "hslb_step", "hslb_sync", "hslb_step_count", "hslb_moments", "hslb_profiles",
-    "hslb_force", "hslb_eta_bar", "hslb_attraction_potential", "hslb_get_populations", "hslb_set_populations",
+    "hslb_force", "hslb_eta_bar", "hslb_attraction_potential", "hslb_set_solid", "hslb_get_populations",
+    "hslb_set_populations",
     "hslb_set_watchdog", "hslb_set_shift_period", "hslb_set_graph",
     "hslb_checkpoint_size", "hslb_checkpoint_save", "hslb_checkpoint_load", "hslb_set_kernel_timing", "hslb_kernel_times",
     "hslb_get_timings", "hslb_copy_bandwidth",
@@ -110,6 +111,7 @@ def load(path: Optional[str] = None):
         "hslb_force": (ctypes.c_int, [_vp, _dp]),
         "hslb_eta_bar": (ctypes.c_int, [_vp, _dp]),
         "hslb_attraction_potential": (ctypes.c_int, [_vp, _dp]),
+        "hslb_set_solid": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint8)]),
         "hslb_get_populations": (ctypes.c_int, [_vp, _dp]),
         "hslb_set_populations": (ctypes.c_int, [_vp, _dp]),
         "hslb_set_watchdog": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_double]),
@@ -235,6 +237,11 @@ def hslb_eta_bar(ctx, eb: np.ndarray):
 
 def hslb_attraction_potential(ctx, phi: np.ndarray):
     _chk(ctx, load().hslb_attraction_potential(ctx, _d(phi)))
+
+
+def hslb_set_solid(ctx, solid: np.ndarray):
+    m = np.ascontiguousarray(np.asarray(solid) != 0, dtype=np.uint8)
+    _chk(ctx, load().hslb_set_solid(ctx, m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
 
 
 def hslb_get_populations(ctx, f: np.ndarray):
@@ -541,6 +548,10 @@ class Sim:
         e = np.zeros(self.N)
         hslb_eta_bar(self.ctx, e)
         return e.reshape(self.shape)
+
+    def set_solid(self, solid):
+        """Solid mask shaped (nz, ny, nx), nonzero = solid; before init."""
+        hslb_set_solid(self.ctx, np.asarray(solid).reshape(self.N))
 
     def attraction_potential(self):
         phi = np.zeros(self.N)
