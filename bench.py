@@ -162,6 +162,30 @@ def attraction_leg(hslb, wl, n, u, steps: int):
             "kernels_us": {k: round(v[0] / v[1] * 1e3, 2) for k, v in kt.items()}}
 
 
+def obstacle_leg(hslb, np, wl, n, u, steps: int):
+    """The benchmark slit with a solid cylinder of radius sigma across y at its
+    centre (solid mask, per-node wall factor): throughput over the fluid nodes
+    that remain, graph-replayed steps."""
+    z, x = np.meshgrid(np.arange(wl.nz), np.arange(wl.nx), indexing="ij")
+    cyl = (z - wl.nz / 2) ** 2 + (x - wl.nx / 2) ** 2 <= wl.sigma ** 2
+    m = np.broadcast_to(cyl[:, None, :], (wl.nz, wl.ny, wl.nx)).astype(np.uint8)
+    fluid = wl.fluid_nodes - int(m.sum())
+    s = hslb.Sim.from_workload(wl)
+    s.set_solid(m)
+    s.init(n, u)
+    s.step(20)
+    s.sync()
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.sync()
+    dt = time.perf_counter() - t0
+    finite = bool(np.isfinite(s.moments()[0]).all())
+    s.close()
+    return {"workload": f"{wl.name} + solid cylinder (radius {wl.sigma}, axis along y)",
+            "fluid_nodes": fluid, "steps": steps, "value": round(fluid * steps / dt / 1e6, 1), "unit": "MLUPS",
+            "ms_per_step": round(dt / steps * 1e3, 5), "state_finite_after": finite}
+
+
 def cpu_baseline(wl, n, u, budget_s: float):
     import oracle
     o = oracle.Oracle(**wl.params())
@@ -192,6 +216,7 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-attraction", action="store_true")
+    ap.add_argument("--no-obstacle", action="store_true")
     ap.add_argument("--surrogate-epochs", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -286,6 +311,11 @@ def main():
         print("bench: attraction", file=sys.stderr, flush=True)
         att = attraction_leg(hslb, wl, n, u, args.steps)
 
+    obst = None
+    if not args.no_obstacle:
+        print("bench: obstacle", file=sys.stderr, flush=True)
+        obst = obstacle_leg(hslb, np, wl, n, u, args.steps)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
@@ -316,6 +346,7 @@ def main():
         "ensemble": ens,
         "surrogate": surr,
         "attraction": att,
+        "obstacle": obst,
         "roofline": roof,
         "kernels_us": kernels,
         "cpu_baseline": cpu,

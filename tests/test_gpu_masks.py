@@ -154,3 +154,15 @@ def test_full_size_obstacle_one_step():
     assert _rel(fg, fo) <= 1e-6
     gn, _ = g2.moments()
     assert np.all(gn[m == 1] == 0.0)
+
+
+def test_set_solid_errors():
+    g = hslb.Sim(12, 12, 16, 4, 1.0, wall_lo=2, wall_hi=2)
+    g.init(np.full((16, 12, 12), 0.005))
+    with pytest.raises(hslb.HslbError) as ei:
+        g.set_solid(np.zeros((16, 12, 12)))
+    assert ei.value.code == hslb.HSLB_ESTATE
+    s = hslb.Sim(32, 32, 16, 4, 1.0, wall_lo=2, wall_hi=2, force_mode=hslb.HSLB_FORCE_SURROGATE)
+    with pytest.raises(hslb.HslbError) as ei:
+        s.set_solid(np.zeros((16, 32, 32)))
+    assert ei.value.code == hslb.HSLB_EINVAL
