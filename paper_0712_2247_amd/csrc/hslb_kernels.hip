@@ -557,7 +557,7 @@ __device__ __forceinline__ void shell_sum(const Fields<TM> &F, const LatticeDev 
 }
 
 // Total force C^(1) + n g at a fluid node with local moments (n, u).
-template <int SIG, bool LZ, typename TM>
+template <int SIG, bool LZ, typename TM, bool MASK = true>
 __device__ __forceinline__ void node_force(const Fields<TM> &F, const LatticeDev &L, const StepConst &sc,
                                            const double *__restrict__ chi, int x, int y, int z, double n,
                                            const double u[3], double Fo[3])
@@ -588,7 +588,10 @@ __device__ __forceinline__ void node_force(const Fields<TM> &F, const LatticeDev
         c.u[0] = (TC)u[0];
         c.u[1] = (TC)u[1];
         c.u[2] = (TC)u[2];
-        c.ckap = (TC)((sc.chi_n ? sc.chi_n[x + L.nx * (y + L.ny * z)] : chi[z]) * sc.kappa);
+        if constexpr (MASK)
+            c.ckap = (TC)((sc.chi_n ? sc.chi_n[x + L.nx * (y + L.ny * z)] : chi[z]) * sc.kappa);
+        else
+            c.ckap = (TC)(chi[z] * sc.kappa);
         const TC alpha[4] = {(TC)sc.alpha[0], (TC)sc.alpha[1], (TC)sc.alpha[2], (TC)sc.alpha[3]};
         shell_sum<SIG, LZ>(F, L, c, alpha, S);
     }
@@ -617,7 +620,7 @@ __device__ __forceinline__ void node_force(const Fields<TM> &F, const LatticeDev
 // ------------------------------------------------- collide and stream
 
 // Node r (0 <= r < plane) of fluid layer z.
-template <int SIG, bool LZ, typename TF, typename TM>
+template <int SIG, bool LZ, typename TF, typename TM, bool MASK = false>
 __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &sc, const double *__restrict__ chi,
                                           const TF *__restrict__ fin, TF *__restrict__ fout, const Fields<TM> &fld,
                                           int z, int r)
@@ -636,7 +639,7 @@ __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &
     // solid mask: a solid node only restates its (zero) populations against
     // the write reference; its neighbours bounce off it
     uint32_t lk = 0;
-    if (sc.links) {
+    if (MASK && sc.links) {
         lk = sc.links[id];
         if (lk & LINK_SOLID) {
             const double *rw = layer_ref(sc.nref_w, z);
@@ -669,7 +672,7 @@ __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &
     const double inv_n = (n != 0.0) ? 1.0 / n : 0.0;
     const double u[3] = {jx * inv_n, jy * inv_n, jz * inv_n};
     double Fv[3];
-    node_force<SIG, LZ>(fld, L, sc, chi, x, y, z, n, u, Fv);
+    node_force<SIG, LZ, TM, MASK>(fld, L, sc, chi, x, y, z, n, u, Fv);
 
     const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     const double omega = 1.0 / sc.tau;
@@ -706,10 +709,6 @@ __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &
     }
 }
 
-// 1-D grid over (layer, chunk of 256 nodes of the layer): z is uniform over a
-// block, so the rows of the storage reference tables come in through scalar
-// loads.
-template <int SIG, typename TF, typename TM>
 // Waves per SIMD the collide kernel is compiled for (register budget
 // 512 / waves).  3 leaves the compiler its natural ~130 VGPRs; 4 and 5
 // (104 and 96 VGPRs, no spills) measured 25 % slower: the shell reads of more
@@ -718,6 +717,11 @@ template <int SIG, typename TF, typename TM>
 #define HSLB_COLLIDE_WAVES 3
 #endif
 
+// 1-D grid over (layer, chunk of 256 nodes of the layer): z is uniform over a
+// block, so the rows of the storage reference tables come in through scalar
+// loads.  MASK: the solid-mask code is compiled in (a separate instance, so
+// that the plain path keeps its registers).
+template <int SIG, typename TF, typename TM, bool MASK>
 __global__ __launch_bounds__(256, HSLB_COLLIDE_WAVES) void k_collide(LatticeDev L, StepConst sc, const double *__restrict__ chi,
                                                  const TF *__restrict__ fin, TF *__restrict__ fout,
                                                  Fields<TM> fld, int cpp)
@@ -727,7 +731,7 @@ __global__ __launch_bounds__(256, HSLB_COLLIDE_WAVES) void k_collide(LatticeDev 
     const int c = lb - zl * cpp;
     const int r = c * 256 + threadIdx.x;
     const int z = (L.zper ? 0 : L.wall_lo) + zl;
-    if (r < L.plane) d_collide<SIG, true>(L, sc, chi, fin, fout, fld, z, r);
+    if (r < L.plane) d_collide<SIG, true, TF, TM, MASK>(L, sc, chi, fin, fout, fld, z, r);
 }
 
 template <int SIG, typename TF, typename TM>
@@ -1225,6 +1229,10 @@ hipError_t launch_gfield(hipStream_t s, const LatticeDev &L, int g2_model, Field
     return hipGetLastError();
 }
 
+template <typename TF, typename TM, bool M>
+hipError_t launch_collide_t(hipStream_t s, int sigma, dim3 g, dim3 b, const LatticeDev &L, const StepConst &c,
+                            const double *chi, const TF *fin, TF *fout, Fields<TM> fld, int cpp);
+
 template <typename TF, typename TM>
 hipError_t launch_collide(hipStream_t s, const LatticeDev &L, int sigma, const StepConst &c, const double *chi,
                           const TF *fin, TF *fout, Fields<TM> fld)
@@ -1232,15 +1240,23 @@ hipError_t launch_collide(hipStream_t s, const LatticeDev &L, int sigma, const S
     const int layers = L.zper ? L.nz : L.nz - L.wall_lo - L.wall_hi;
     const int cpp = (int)blocks_for(L.plane);
     const dim3 g(cpp * layers), b(256);
+    if (c.links) return launch_collide_t<TF, TM, true>(s, sigma, g, b, L, c, chi, fin, fout, fld, cpp);
+    return launch_collide_t<TF, TM, false>(s, sigma, g, b, L, c, chi, fin, fout, fld, cpp);
+}
+
+template <typename TF, typename TM, bool M>
+hipError_t launch_collide_t(hipStream_t s, int sigma, dim3 g, dim3 b, const LatticeDev &L, const StepConst &c,
+                            const double *chi, const TF *fin, TF *fout, Fields<TM> fld, int cpp)
+{
     switch (sigma) {
-    case 0: hipLaunchKernelGGL((k_collide<0, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
-    case 2: hipLaunchKernelGGL((k_collide<2, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
-    case 3: hipLaunchKernelGGL((k_collide<3, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
-    case 4: hipLaunchKernelGGL((k_collide<4, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
-    case 5: hipLaunchKernelGGL((k_collide<5, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
-    case 6: hipLaunchKernelGGL((k_collide<6, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
-    case 7: hipLaunchKernelGGL((k_collide<7, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
-    case 8: hipLaunchKernelGGL((k_collide<8, TF, TM>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
+    case 0: hipLaunchKernelGGL((k_collide<0, TF, TM, M>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
+    case 2: hipLaunchKernelGGL((k_collide<2, TF, TM, M>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
+    case 3: hipLaunchKernelGGL((k_collide<3, TF, TM, M>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
+    case 4: hipLaunchKernelGGL((k_collide<4, TF, TM, M>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
+    case 5: hipLaunchKernelGGL((k_collide<5, TF, TM, M>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
+    case 6: hipLaunchKernelGGL((k_collide<6, TF, TM, M>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
+    case 7: hipLaunchKernelGGL((k_collide<7, TF, TM, M>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
+    case 8: hipLaunchKernelGGL((k_collide<8, TF, TM, M>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
