@@ -158,9 +158,10 @@ int hslb_eta_bar(hslb_ctx *ctx, double *eta_bar);
  * d_w = (distance to the nearest solid node centre, wall layers included,
  * periodic images along periodic axes) - 1/2, which is the halfway-plane
  * distance of flat walls.  With FP32 storage the reference tables are then
- * kept FP32-representable, so solid nodes hold exact zeros.  Errors:
- * HSLB_ESTATE after hslb_init or on a batch, HSLB_EINVAL with the learned
- * force or a NULL mask. */
+ * kept FP32-representable, so solid nodes hold exact zeros.  Checkpoints do
+ * not hold the mask: set it on the new context before hslb_init, then load.
+ * Errors: HSLB_ESTATE after hslb_init or on a batch, HSLB_EINVAL with the
+ * learned force or a NULL mask. */
 int hslb_set_solid(hslb_ctx *ctx, const uint8_t *solid);
 
 /* Mean-field attraction potential Phi[N] (see hslb_params.att_eps) at the

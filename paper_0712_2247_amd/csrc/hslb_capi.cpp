@@ -1447,6 +1447,23 @@ public:
         return HSLB_OK;
     }
 
+    int collide(const WorkItem *wf, int nw)
+    {
+        hipEvent_t a = nullptr, b = nullptr;
+        if (kt.enabled && !capturing_) {
+            HIP_TRY(kt.ev(&a));
+            HIP_TRY(kt.ev(&b));
+            HIP_TRY(hipEventRecord(a, st()));
+        }
+        const unsigned grid = (unsigned)std::max(1, std::min(nw, ncu_ * grid_per_cu_));
+        HIP_TRY(launch_batch_collide<TF, TM>(st(), grid, desc_d_, wf, nw, f_[cur_], f_[1 - cur_], fld_, chi_d_));
+        if (a) {
+            HIP_TRY(hipEventRecord(b, st()));
+            kt.pending.push_back({"b_collide", {(int)kt.used - 2, (int)kt.used - 1}});
+        }
+        return HSLB_OK;
+    }
+
     int one_step()
     {
         const WorkItem *wn = work_d_, *wr = wn + wl_nodes_.size(), *wf = wr + wl_rows_.size();
@@ -1455,7 +1472,7 @@ public:
         if ((rc = phase("b_rowsum", 1, wr, (int)wl_rows_.size()))) return rc;
         if ((rc = phase("b_ballsum", 2, wn, (int)wl_nodes_.size()))) return rc;
         if ((rc = phase("b_gfield", 3, wn, (int)wl_nodes_.size()))) return rc;
-        if ((rc = phase("b_collide", 4, wf, (int)wl_fluid_.size()))) return rc;
+        if ((rc = collide(wf, (int)wl_fluid_.size()))) return rc;
         cur_ = 1 - cur_;
         return HSLB_OK;
     }

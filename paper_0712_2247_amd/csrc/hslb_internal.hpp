@@ -169,11 +169,16 @@ hipError_t launch_attraction(hipStream_t s, const LatticeDev &L, const AttWeight
                              double *b, double *phi);
 
 // Batched ensemble: one persistent launch per phase over a work list.
-// phase 0 moments, 1 row sums, 2 ball sums, 3 contact values, 4 collide.
+// phase 0 moments, 1 row sums, 2 ball sums, 3 contact values (the collide
+// phase is launch_batch_collide).
 template <typename TF, typename TM>
 hipError_t launch_batch_phase(hipStream_t s, int phase, unsigned grid, const SlitDesc *desc,
                               const WorkItem *work, int nwork, const TF *fin, TF *fout, Fields<TM> fld,
                               TM *rs, const double *chi);
+// Collide phase of every slit: work holds the fluid items.
+template <typename TF, typename TM>
+hipError_t launch_batch_collide(hipStream_t s, unsigned grid, const SlitDesc *desc, const WorkItem *work, int nwork,
+                                const TF *fin, TF *fout, Fields<TM> fld, const double *chi);
 // Layer profiles of every slit: items (slit, z); out holds 5 rows per slit
 // layer at prof_off[slit] (n_z, u_z[3], sum n).
 template <typename TF>

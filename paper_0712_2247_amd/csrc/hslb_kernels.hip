@@ -980,6 +980,37 @@ __device__ __forceinline__ void batch_collide(const LatticeDev &L, const StepCon
     d_collide<SIG, false>(L, sc, chi, fin, fout, fld, z, id - z * L.plane);
 }
 
+// Collide phase of every slit in one persistent launch: the grid walks the
+// fluid work items; each item's descriptor (and sigma, hence the shell
+// stencil) is uniform over the block.  A kernel of its own, so that the
+// lighter phases of kb_phase keep a small register budget.
+template <typename TF, typename TM>
+__global__ __launch_bounds__(256, 3) void kb_collide(const SlitDesc *__restrict__ desc,
+                                                     const WorkItem *__restrict__ work, int nwork,
+                                                     const TF *__restrict__ fin, TF *__restrict__ fout,
+                                                     Fields<TM> fld, const double *__restrict__ chi)
+{
+    for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+        const WorkItem it = work[w];
+        const SlitDesc &d = desc[it.slit];
+        const Fields<TM> F = shift_fields(fld, d.fld_off);
+        const TF *fi = fin + d.pop_off;
+        TF *fo = fout + d.pop_off;
+        const double *ch = chi + d.chi_off;
+        const int idx = it.block * 256 + (int)threadIdx.x;
+        switch (d.sigma) {
+        case 2: batch_collide<2>(d.L, d.sc, ch, fi, fo, F, idx); break;
+        case 3: batch_collide<3>(d.L, d.sc, ch, fi, fo, F, idx); break;
+        case 4: batch_collide<4>(d.L, d.sc, ch, fi, fo, F, idx); break;
+        case 5: batch_collide<5>(d.L, d.sc, ch, fi, fo, F, idx); break;
+        case 6: batch_collide<6>(d.L, d.sc, ch, fi, fo, F, idx); break;
+        case 7: batch_collide<7>(d.L, d.sc, ch, fi, fo, F, idx); break;
+        case 8: batch_collide<8>(d.L, d.sc, ch, fi, fo, F, idx); break;
+        default: break;
+        }
+    }
+}
+
 // Persistent kernel of one phase of the step for every slit: the grid walks
 // the work list; each item is one block of 256 indices of one slit, whose
 // descriptor (and sigma, hence the shell stencil) is uniform over the block.
@@ -1016,7 +1047,6 @@ __global__ __launch_bounds__(256) void kb_phase(int phase, const SlitDesc *__res
         } else if (phase == 2) {                                                         \
             if (idx < d.L.N) d_ballsum<SG>(d.L, d.sc.eta_pref, F, rsl, idx / d.L.plane, idx % d.L.plane); \
         }                                                                                \
-        else batch_collide<SG>(d.L, d.sc, ch, fi, fo, F, idx);                           \
         break;
             switch (d.sigma) {
                 HSLB_BPH(2)
@@ -1335,6 +1365,15 @@ hipError_t launch_batch_phase(hipStream_t s, int phase, unsigned grid, const Sli
     return hipGetLastError();
 }
 
+template <typename TF, typename TM>
+hipError_t launch_batch_collide(hipStream_t s, unsigned grid, const SlitDesc *desc, const WorkItem *work, int nwork,
+                                const TF *fin, TF *fout, Fields<TM> fld, const double *chi)
+{
+    if (nwork <= 0) return hipSuccess;
+    hipLaunchKernelGGL((kb_collide<TF, TM>), dim3(grid), dim3(256), 0, s, desc, work, nwork, fin, fout, fld, chi);
+    return hipGetLastError();
+}
+
 template <typename TF>
 hipError_t launch_batch_profiles(hipStream_t s, const SlitDesc *desc, const WorkItem *items, int nitems,
                                  const int *prof_off, const TF *f, double *out)
@@ -1377,7 +1416,10 @@ hipError_t launch_batch_profiles(hipStream_t s, const SlitDesc *desc, const Work
                                              const double *, const TF *, Fields<TM>, double *);              \
     template hipError_t launch_batch_phase<TF, TM>(hipStream_t, int, unsigned, const SlitDesc *,            \
                                                    const WorkItem *, int, const TF *, TF *, Fields<TM>, TM *, \
-                                                   const double *);
+                                                   const double *);                                          \
+    template hipError_t launch_batch_collide<TF, TM>(hipStream_t, unsigned, const SlitDesc *,               \
+                                                     const WorkItem *, int, const TF *, TF *, Fields<TM>,     \
+                                                     const double *);
 
 HSLB_INST_TF(float)
 HSLB_INST_TF(double)

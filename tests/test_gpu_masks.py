@@ -166,3 +166,21 @@ def test_set_solid_errors():
     with pytest.raises(hslb.HslbError) as ei:
         s.set_solid(np.zeros((16, 32, 32)))
     assert ei.value.code == hslb.HSLB_EINVAL
+
+
+def test_obstacles_with_attraction_fp64():
+    """Obstacles and the mean-field attraction together (12 x 13 x 18 slit,
+    sigma 3, 10 % solid, attraction range 1.5): 30 FP64 steps against the
+    oracle."""
+    case = CASES[2]
+    m, n, u = _obstacles(case)
+    g, o = _pair(case, "f64", att_eps=0.05, att_range=1.5)
+    g.set_solid(m)
+    o.set_solid(m)
+    g.init(n, u)
+    o.init(n, u)
+    g.step(30)
+    o.step(30)
+    assert _rel(g.get_populations(), o.get_populations()) <= 1e-13
+    gn, _ = g.moments()
+    assert np.all(gn[m == 1] == 0.0)
