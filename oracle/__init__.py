@@ -49,6 +49,7 @@ class _Params(ctypes.Structure):
         ("g2_model", ctypes.c_int32), ("wall_reg", ctypes.c_int32),
         ("force_mode", ctypes.c_int32),
         ("att_eps", ctypes.c_double), ("att_range", ctypes.c_double),
+        ("lattice", ctypes.c_int32),
     ]
 
 
@@ -83,6 +84,10 @@ def _load():
     lib.hsref_shell_table.argtypes = [ctypes.c_int, d, d, P(ctypes.c_int), P(ctypes.c_int), d]
     lib.hsref_ball_count.argtypes = [ctypes.c_int]
     lib.hsref_lattice.argtypes = [P(ctypes.c_int), d]
+    lib.hsref_lattice_q.argtypes = [ctypes.c_int, P(ctypes.c_int), d]
+    lib.hsref_lattice_q.restype = ctypes.c_int
+    lib.hsref_q.argtypes = [ctypes.c_void_p]
+    lib.hsref_q.restype = ctypes.c_int
     lib.hsref_set_threads.argtypes = [ctypes.c_int]
     lib.hsref_max_threads.restype = ctypes.c_int
     _lib = lib
@@ -132,6 +137,16 @@ def lattice():
     return c, w
 
 
+def lattice_q(q: int):
+    """Return (c[q,3], w[q]) of the lattice with q = 19 or 39 velocities."""
+    c = np.zeros((q, 3), dtype=np.int32)
+    w = np.zeros(q)
+    rc = _load().hsref_lattice_q(int(q), c.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dptr(w))
+    if rc != q:
+        raise ValueError(f"no lattice with {q} velocities")
+    return c, w
+
+
 def attraction_potential_at(n, nodes, att_eps: float, att_range: float, zperiodic: bool):
     """Mean-field attraction potential (its definition is in the header of
     hsref.c) at the listed nodes (z, y, x) of the density field n [nz, ny, nx],
@@ -161,7 +176,8 @@ class Oracle:
     z: arrays are shaped (nz, ny, nx) and vectors (3, nz, ny, nx)."""
 
     def __init__(self, nx, ny, nz, sigma, tau, accel=(0.0, 0.0, 0.0), wall_lo=0, wall_hi=0,
-                 g2_model=G2_PAPER, wall_reg=1, force_mode=FORCE_EXACT, att_eps=0.0, att_range=0.0):
+                 g2_model=G2_PAPER, wall_reg=1, force_mode=FORCE_EXACT, att_eps=0.0, att_range=0.0,
+                 lattice=19):
         self._lib = _load()
         p = _Params()
         p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
@@ -171,12 +187,14 @@ class Oracle:
         p.accel = (ctypes.c_double * 3)(*[float(a) for a in accel])
         p.g2_model, p.wall_reg, p.force_mode = int(g2_model), int(wall_reg), int(force_mode)
         p.att_eps, p.att_range = float(att_eps), float(att_range)
+        p.lattice = int(lattice)
         self.params = p
         self.shape = (int(nz), int(ny), int(nx))
         self.N = int(nx) * int(ny) * int(nz)
         self._ctx = self._lib.hsref_create(ctypes.byref(p))
         if not self._ctx:
             raise ValueError("oracle rejected the parameters")
+        self.q = int(self._lib.hsref_q(self._ctx))
 
     def __del__(self):
         ctx = getattr(self, "_ctx", None)
@@ -240,10 +258,10 @@ class Oracle:
         return e.reshape(self.shape)
 
     def get_populations(self):
-        f = np.zeros(19 * self.N)
+        f = np.zeros(self.q * self.N)
         self._chk(self._lib.hsref_get_populations(self._ctx, _dptr(f)), "get_populations")
-        return f.reshape((19,) + self.shape)
+        return f.reshape((self.q,) + self.shape)
 
     def set_populations(self, f):
-        f = np.ascontiguousarray(f, dtype=np.float64).reshape(19 * self.N)
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(self.q * self.N)
         self._chk(self._lib.hsref_set_populations(self._ctx, _dptr(f)), "set_populations")

@@ -56,6 +56,30 @@
  * array, and periodic images along periodic axes.  Written here as the plain
  * triple sum.
  *
+ * Optional third-order lattice (lattice = 39; the higher-order Hermite basis the
+ * paper names in its discussion of the wall regulariser and in its conclusions,
+ * as the way to high Knudsen numbers).  Readings, all in the design notes:
+ *   - the 39-velocity quadrature of degree 7 with integer velocities: the rest
+ *     vector (weight 1/12), the 6 axis vectors of length 1 (1/12), the 8 cube
+ *     diagonals (1, 1, 1) (1/27), the 6 axis vectors of length 2 (2/135), the 12
+ *     vectors (2, 2, 0) (1/432) and the 6 axis vectors of length 3 (1/1620); its
+ *     second moment fixes v_T^2 = k_B T = 2/3 in lattice units, which also enters
+ *     the force's k_B T and its current-term coefficient;
+ *   - the local equilibrium (11) carried to third order in u, the Hermite
+ *     expansion of the Maxwellian through h^(3);
+ *   - "removing the off-basis contributions": before relaxation the
+ *     non-equilibrium part f - f_eq is replaced by its projection on h^(2) and
+ *     h^(3), f_neq -> w_i [h2(c_i) : a2 / (2 v_T^4) + h3(c_i) : a3 / (6 v_T^6)],
+ *     a_l = sum_i h_l(c_i) (f_i - f_eq,i); post-collision
+ *     f = f_eq + (1 - 1/tau) f_neq + w_i c_i . F / v_T^2 (the same first-order
+ *     source as on the 19-velocity lattice);
+ *   - halfway bounce-back for the longer links: a population that would cross
+ *     a wall plane is reversed where it meets the plane and travels the rest of
+ *     the step back, landing on a lattice node (every link of this set that
+ *     crosses a z plane has |c_x|, |c_y| equal to 0 or |c_z|); the slit needs at
+ *     least 3 fluid layers so that no link crosses both walls; solid masks are
+ *     not available on this lattice.
+ *
  * Optional solid mask (hsref_set_solid): any node may be solid, beyond the wall
  * layers.  Solid nodes carry n = j = 0 and take part in nothing; a population
  * heading into a solid node returns reversed (halfway bounce-back), as at the
@@ -74,6 +98,7 @@
 #endif
 
 #define NQ 19
+#define QMAX 39
 /* grids below this size run on one thread: the fork/join of four phases per
  * step would cost more than the work */
 #define PAR_MIN_NODES 32768
@@ -90,6 +115,7 @@ typedef struct {
     int32_t force_mode;       /* 0: hard-sphere term on, 2: off */
     double att_eps;           /* depth of the Gaussian attraction (0: off) */
     double att_range;         /* its range in lattice units */
+    int32_t lattice;          /* 19 (or 0): D3Q19; 39: the third-order lattice */
 } hsref_params;
 
 /* D3Q19 velocities, the discrete set of section "Methods and Results". */
@@ -100,19 +126,37 @@ static const int CV[NQ][3] = {
     {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
     {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
 
+/* The 39-velocity third-order lattice; each velocity is followed by its
+ * opposite.  Weights by shell: |c|^2 = 0, 1: 1/12; 3: 1/27; 4: 2/135; 8: 1/432;
+ * 9: 1/1620. */
+static const int CV39[QMAX][3] = {
+    {0, 0, 0},
+    {1, 0, 0},   {-1, 0, 0},  {0, 1, 0},   {0, -1, 0},  {0, 0, 1},   {0, 0, -1},
+    {1, 1, 1},   {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1}, {1, -1, 1},  {-1, 1, -1},
+    {-1, 1, 1},  {1, -1, -1},
+    {2, 0, 0},   {-2, 0, 0},  {0, 2, 0},   {0, -2, 0},  {0, 0, 2},   {0, 0, -2},
+    {2, 2, 0},   {-2, -2, 0}, {2, -2, 0},  {-2, 2, 0},  {2, 0, 2},   {-2, 0, -2},
+    {2, 0, -2},  {-2, 0, 2},  {0, 2, 2},   {0, -2, -2}, {0, 2, -2},  {0, -2, 2},
+    {3, 0, 0},   {-3, 0, 0},  {0, 3, 0},   {0, -3, 0},  {0, 0, 3},   {0, 0, -3}};
+
+static double weight39_of(const int *v)
+{
+    switch (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) {
+    case 0:
+    case 1: return 1.0 / 12.0;
+    case 3: return 1.0 / 27.0;
+    case 4: return 2.0 / 135.0;
+    case 8: return 1.0 / 432.0;
+    default: return 1.0 / 1620.0;
+    }
+}
+
 static double weight_of(int i)
 {
     int s = abs(CV[i][0]) + abs(CV[i][1]) + abs(CV[i][2]);
     if (s == 0) return 1.0 / 3.0;
     if (s == 1) return 1.0 / 18.0;
     return 1.0 / 36.0;
-}
-
-static int opposite_of(int i)
-{
-    for (int k = 0; k < NQ; ++k)
-        if (CV[k][0] == -CV[i][0] && CV[k][1] == -CV[i][1] && CV[k][2] == -CV[i][2]) return k;
-    return -1;
 }
 
 /* One of the 18 quadrature directions on the sphere of radius sigma. */
@@ -128,14 +172,17 @@ struct hsref_ctx {
     hsref_params p;
     int64_t N;
     int zperiodic;
-    double w[NQ];
-    int opp[NQ];
+    int q;                /* number of velocities, 19 or 39 */
+    int cv[QMAX][3];
+    double cs2;           /* v_T^2 of the lattice: 1/3 or 2/3 */
+    double w[QMAX];
+    int opp[QMAX];
     shell_dir shell[NSHELL];
     int nball;
     int (*ball)[3];
     double *chi;     /* [nz] wall factor of the receiving layer */
-    double *f;       /* [19][N] populations after streaming */
-    double *fs;      /* [19][N] scratch for the streamed populations */
+    double *f;       /* [q][N] populations after streaming */
+    double *fs;      /* [q][N] scratch for the streamed populations */
     double *n;       /* [N] */
     double *j;       /* [3][N] */
     double *u;       /* [3][N] */
@@ -301,15 +348,24 @@ hsref_ctx *hsref_create(const hsref_params *p)
     if (!(p->tau > 0.5)) return NULL;
     if (!isfinite(p->att_eps) || (p->att_eps != 0.0 && !(p->att_range > 0.0 && p->att_range <= 10.0)))
         return NULL;
+    if (p->lattice != 0 && p->lattice != 19 && p->lattice != 39) return NULL;
+    /* no link of the third-order lattice may cross both walls */
+    if (p->lattice == 39 && p->wall_lo > 0 && p->nz - p->wall_lo - p->wall_hi < 3) return NULL;
     hsref_ctx *c = (hsref_ctx *)calloc(1, sizeof(hsref_ctx));
     if (!c) return NULL;
     c->p = *p;
     c->N = (int64_t)p->nx * p->ny * p->nz;
     c->zperiodic = (p->wall_lo == 0 && p->wall_hi == 0);
-    for (int i = 0; i < NQ; ++i) {
-        c->w[i] = weight_of(i);
-        c->opp[i] = opposite_of(i);
+    c->q = p->lattice == 39 ? 39 : NQ;
+    c->cs2 = p->lattice == 39 ? 2.0 / 3.0 : 1.0 / 3.0;
+    for (int i = 0; i < c->q; ++i) {
+        for (int a = 0; a < 3; ++a) c->cv[i][a] = c->q == 39 ? CV39[i][a] : CV[i][a];
+        c->w[i] = c->q == 39 ? weight39_of(CV39[i]) : weight_of(i);
     }
+    for (int i = 0; i < c->q; ++i)
+        for (int k = 0; k < c->q; ++k)
+            if (c->cv[k][0] == -c->cv[i][0] && c->cv[k][1] == -c->cv[i][1] && c->cv[k][2] == -c->cv[i][2])
+                c->opp[i] = k;
     int sig = p->sigma >= 2 ? p->sigma : 2;
     build_shell(sig, c->shell);
     c->nball = build_ball(sig, NULL);
@@ -326,8 +382,8 @@ hsref_ctx *hsref_create(const hsref_params *p)
         c->chi[z] = chi;
     }
     size_t N = (size_t)c->N;
-    c->f = calloc((size_t)NQ * N, sizeof(double));
-    c->fs = calloc((size_t)NQ * N, sizeof(double));
+    c->f = calloc((size_t)c->q * N, sizeof(double));
+    c->fs = calloc((size_t)c->q * N, sizeof(double));
     c->n = calloc(N, sizeof(double));
     c->j = calloc(3 * N, sizeof(double));
     c->u = calloc(3 * N, sizeof(double));
@@ -363,12 +419,12 @@ static void phase_moments(hsref_ctx *c)
         for (int64_t id = z * plane; id < (z + 1) * plane; ++id) {
             double n = 0.0, j[3] = {0.0, 0.0, 0.0};
             if (fluid_node(c, id)) {
-                for (int i = 0; i < NQ; ++i) {
+                for (int i = 0; i < c->q; ++i) {
                     double fi = c->f[(int64_t)i * N + id];
                     n += fi;
-                    j[0] += CV[i][0] * fi;
-                    j[1] += CV[i][1] * fi;
-                    j[2] += CV[i][2] * fi;
+                    j[0] += c->cv[i][0] * fi;
+                    j[1] += c->cv[i][1] * fi;
+                    j[2] += c->cv[i][2] * fi;
                 }
             }
             c->n[id] = n;
@@ -465,7 +521,7 @@ static void phase_force(hsref_ctx *c)
 {
     const int64_t N = c->N;
     const int64_t plane = (int64_t)c->p.nx * c->p.ny;
-    const double vt2 = 1.0 / 3.0;
+    const double vt2 = c->cs2;
     const double kappa = 2.0 / (sqrt(vt2) * sqrt(M_PI));
     const double sig = (double)c->p.sigma;
     const double pref = -vt2 * sig * sig * 4.0 * M_PI;
@@ -522,12 +578,111 @@ static void phase_force(hsref_ctx *c)
     }
 }
 
+/* Third-order lattice: the local equilibrium (11) carried through h^(3),
+ * w n [1 + h1.u/v_T^2 + h2:uu/(2 v_T^4) + h3:uuu/(6 v_T^6)], written out as
+ * w n [1 + xi + xi^2/2 - u^2/(2 v_T^2) + xi^3/6 - xi u^2/(2 v_T^2)], xi = c.u / v_T^2. */
+static double feq39(const hsref_ctx *c, int i, double n, const double u[3])
+{
+    const double cs2 = c->cs2;
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double xi = (c->cv[i][0] * u[0] + c->cv[i][1] * u[1] + c->cv[i][2] * u[2]) / cs2;
+    return c->w[i] * n * (1.0 + xi + 0.5 * xi * xi - uu / (2.0 * cs2) + xi * xi * xi / 6.0 - xi * uu / (2.0 * cs2));
+}
+
+/* Hermite tensors of velocity i: h2_ab = c_a c_b - v_T^2 d_ab and
+ * h3_abc = c_a c_b c_c - v_T^2 (c_a d_bc + c_b d_ac + c_c d_ab). */
+static double herm2(const hsref_ctx *c, int i, int a, int b)
+{
+    return c->cv[i][a] * c->cv[i][b] - (a == b ? c->cs2 : 0.0);
+}
+
+static double herm3(const hsref_ctx *c, int i, int a, int b, int g)
+{
+    const int *v = c->cv[i];
+    return (double)(v[a] * v[b] * v[g]) -
+           c->cs2 * ((b == g ? v[a] : 0) + (a == g ? v[b] : 0) + (a == b ? v[g] : 0));
+}
+
+/* Collision on the third-order lattice (readings in the header): the
+ * non-equilibrium part is projected on h^(2) and h^(3), relaxed, and the
+ * first-order source added; then propagation, with the longer links reversed
+ * at the wall planes. */
+static void phase_collide_stream39(hsref_ctx *c)
+{
+    const int64_t N = c->N;
+    const int64_t plane = (int64_t)c->p.nx * c->p.ny;
+    const double tau = c->p.tau, cs2 = c->cs2;
+    const int q = c->q;
+    memset(c->fs, 0, sizeof(double) * (size_t)q * (size_t)N);
+#pragma omp parallel for schedule(static) if (c->N >= PAR_MIN_NODES)
+    for (int z = 0; z < c->p.nz; ++z) {
+        if (is_solid_z(c, z)) continue;
+        for (int y = 0; y < c->p.ny; ++y) {
+            for (int x = 0; x < c->p.nx; ++x) {
+                int64_t id = z * plane + (int64_t)y * c->p.nx + x;
+                double n = c->n[id];
+                double u[3] = {c->u[id], c->u[N + id], c->u[2 * N + id]};
+                double F[3] = {c->F[id], c->F[N + id], c->F[2 * N + id]};
+                double feq[QMAX], a2[3][3] = {{0.0}}, a3[3][3][3] = {{{0.0}}};
+                for (int i = 0; i < q; ++i) {
+                    feq[i] = feq39(c, i, n, u);
+                    double fneq = c->f[(int64_t)i * N + id] - feq[i];
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b) {
+                            a2[a][b] += herm2(c, i, a, b) * fneq;
+                            for (int g = 0; g < 3; ++g) a3[a][b][g] += herm3(c, i, a, b, g) * fneq;
+                        }
+                }
+                for (int i = 0; i < q; ++i) {
+                    double p2 = 0.0, p3 = 0.0;
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b) {
+                            p2 += herm2(c, i, a, b) * a2[a][b];
+                            for (int g = 0; g < 3; ++g) p3 += herm3(c, i, a, b, g) * a3[a][b][g];
+                        }
+                    double fneq_reg = c->w[i] * (p2 / (2.0 * cs2 * cs2) + p3 / (6.0 * cs2 * cs2 * cs2));
+                    double cF = c->cv[i][0] * F[0] + c->cv[i][1] * F[1] + c->cv[i][2] * F[2];
+                    double fpost = feq[i] + (1.0 - 1.0 / tau) * fneq_reg + c->w[i] * cF / cs2;
+                    const int *v = c->cv[i];
+                    int xt = x + v[0], yt = y + v[1], zt = z + v[2], k = i;
+                    if (!c->zperiodic) {
+                        const int lo = c->p.wall_lo, hi = c->p.nz - c->p.wall_hi;  /* fluid layers [lo, hi) */
+                        int run = 0;   /* signed lateral distance travelled in units of c_a / |c_z| */
+                        if (zt < lo) {
+                            run = 2 * (z - lo) + 1 + v[2];       /* 2 d - |c_z| with d = z - lo + 1/2 */
+                            zt = 2 * lo - 1 - zt;
+                        } else if (zt >= hi) {
+                            run = 2 * (hi - 1 - z) + 1 - v[2];
+                            zt = 2 * hi - 1 - zt;
+                        }
+                        if (zt != z + v[2]) {
+                            const int az = abs(v[2]);
+                            xt = x + v[0] / az * run;
+                            yt = y + v[1] / az * run;
+                            k = c->opp[i];
+                        }
+                    }
+                    int64_t id2 = node_at(c, xt, yt, zt);
+                    c->fs[(int64_t)k * N + id2] = fpost;
+                }
+            }
+        }
+    }
+    double *t = c->f;
+    c->f = c->fs;
+    c->fs = t;
+}
+
 /* Equations (10) and (11): BGK relaxation toward the second-order equilibrium
  * with the first-order source 3 w_i c_i . F, then propagation to r + c_i, with
  * halfway bounce-back (the population returns reversed to r) when r + c_i is
  * solid. */
 static void phase_collide_stream(hsref_ctx *c)
 {
+    if (c->q == 39) {
+        phase_collide_stream39(c);
+        return;
+    }
     const int64_t N = c->N;
     const int64_t plane = (int64_t)c->p.nx * c->p.ny;
     const double tau = c->p.tau;
@@ -584,12 +739,16 @@ int hsref_init(hsref_ctx *c, const double *n, const double *u)
     if (!c || !n) return -1;
     if (check_fields(c, n, u)) return -1;
     const int64_t N = c->N;
-    memset(c->f, 0, sizeof(double) * (size_t)NQ * (size_t)N);
+    memset(c->f, 0, sizeof(double) * (size_t)c->q * (size_t)N);
     for (int64_t id = 0; id < N; ++id) {
         if (!fluid_node(c, id)) continue;
         double uu[3] = {0.0, 0.0, 0.0};
         if (u)
             for (int a = 0; a < 3; ++a) uu[a] = u[a * N + id];
+        if (c->q == 39) {
+            for (int i = 0; i < c->q; ++i) c->f[(int64_t)i * N + id] = feq39(c, i, n[id], uu);
+            continue;
+        }
         double u2 = uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2];
         for (int i = 0; i < NQ; ++i) {
             double cu = CV[i][0] * uu[0] + CV[i][1] * uu[1] + CV[i][2] * uu[2];
@@ -677,7 +836,7 @@ int hsref_force(hsref_ctx *c, double *F)
  * per-node wall factor by brute force over the solid nodes. */
 int hsref_set_solid(hsref_ctx *c, const uint8_t *solid)
 {
-    if (!c || !solid) return -1;
+    if (!c || !solid || c->q != NQ) return -1;
     const int64_t N = c->N, plane = (int64_t)c->p.nx * c->p.ny;
     if (!c->solid) c->solid = malloc((size_t)N);
     if (!c->chi_n) c->chi_n = malloc(sizeof(double) * (size_t)N);
@@ -746,17 +905,17 @@ int hsref_eta_bar(hsref_ctx *c, double *eb)
 int hsref_get_populations(hsref_ctx *c, double *f)
 {
     if (!c || !f) return -1;
-    memcpy(f, c->f, sizeof(double) * NQ * (size_t)c->N);
+    memcpy(f, c->f, sizeof(double) * c->q * (size_t)c->N);
     return 0;
 }
 
 int hsref_set_populations(hsref_ctx *c, const double *f)
 {
     if (!c || !f) return -1;
-    memcpy(c->f, f, sizeof(double) * NQ * (size_t)c->N);
+    memcpy(c->f, f, sizeof(double) * c->q * (size_t)c->N);
     for (int64_t id = 0; id < c->N; ++id)
         if (!fluid_node(c, id))
-            for (int i = 0; i < NQ; ++i) c->f[(int64_t)i * c->N + id] = 0.0;
+            for (int i = 0; i < c->q; ++i) c->f[(int64_t)i * c->N + id] = 0.0;
     phase_moments(c);
     return 0;
 }
@@ -794,3 +953,20 @@ int hsref_lattice(int *c, double *w)
     }
     return 0;
 }
+
+/* Velocities [q][3] and weights [q] of the lattice with q = 19 or 39; returns
+ * q, or -1 for another count. */
+int hsref_lattice_q(int q, int *c, double *w)
+{
+    if (q != 19 && q != 39) return -1;
+    for (int i = 0; i < q; ++i) {
+        const int *v = q == 39 ? CV39[i] : CV[i];
+        if (w) w[i] = q == 39 ? weight39_of(v) : weight_of(i);
+        for (int a = 0; a < 3; ++a)
+            if (c) c[3 * i + a] = v[a];
+    }
+    return q;
+}
+
+/* Number of velocities of the context's lattice. */
+int hsref_q(const hsref_ctx *c) { return c ? c->q : -1; }
