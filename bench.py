@@ -37,6 +37,11 @@ PEAK_HBM_GBPS = 8000.0
 #   populations + n, j read once (16 B) = 168 B.
 STEP_BYTES = 184.0
 COLLIDE_BYTES = 168.0
+# The same counts on the 39-velocity lattice (FP64 populations, FP64 moments):
+#   step 39 x 8 x 2 = 624 B + n, j written and read (64 B) = 688 B; its collide
+#   kernel 624 B + n, j read once (32 B) = 656 B.
+STEP39_BYTES = 688.0
+COLLIDE39_BYTES = 656.0
 DOMINANT = "collide"
 
 
@@ -186,6 +191,37 @@ def obstacle_leg(hslb, np, wl, n, u, steps: int):
             "ms_per_step": round(dt / steps * 1e3, 5), "state_finite_after": finite}
 
 
+def d3q39_leg(hslb, np, wl, n, u, steps: int):
+    """The benchmark slit on the third-order 39-velocity lattice (FP64
+    populations and moments, regularised collision): throughput over `steps`
+    graph-replayed steps, then the kernels timed one by one, with the collide
+    kernel's achieved bandwidth on its algorithmic bytes."""
+    s = hslb.Sim.from_workload(wl, precision="f64", lattice=hslb.HSLB_D3Q39)
+    s.init(n, u)
+    s.step(20)
+    s.sync()
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.sync()
+    dt = time.perf_counter() - t0
+    hslb.hslb_set_kernel_timing(s.ctx, True)
+    s.step(min(steps, 200))
+    s.sync()
+    kt = hslb.hslb_kernel_times(s.ctx)
+    finite = bool(np.isfinite(s.moments()[0]).all())
+    s.close()
+    mlups = wl.fluid_nodes * steps / dt / 1e6
+    col_s = kt["collide"][0] / kt["collide"][1] * 1e-3
+    col_gbps = COLLIDE39_BYTES * wl.fluid_nodes / col_s / 1e9
+    return {"workload": f"{wl.name} on the 39-velocity lattice, FP64", "steps": steps,
+            "value": round(mlups, 1), "unit": "MLUPS", "ms_per_step": round(dt / steps * 1e3, 5),
+            "step_algorithmic_GBps": round(mlups * 1e6 * STEP39_BYTES / 1e9, 1),
+            "collide_us": round(col_s * 1e6, 2), "collide_GBps": round(col_gbps, 1),
+            "collide_hbm_frac": round(col_gbps / PEAK_HBM_GBPS, 4),
+            "kernels_us": {k: round(v[0] / v[1] * 1e3, 2) for k, v in kt.items()},
+            "state_finite_after": finite}
+
+
 def cpu_baseline(wl, n, u, budget_s: float):
     import oracle
     o = oracle.Oracle(**wl.params())
@@ -217,6 +253,7 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-attraction", action="store_true")
     ap.add_argument("--no-obstacle", action="store_true")
+    ap.add_argument("--no-d3q39", action="store_true")
     ap.add_argument("--surrogate-epochs", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -316,6 +353,11 @@ def main():
         print("bench: obstacle", file=sys.stderr, flush=True)
         obst = obstacle_leg(hslb, np, wl, n, u, args.steps)
 
+    q39 = None
+    if not args.no_d3q39:
+        print("bench: 39-velocity lattice", file=sys.stderr, flush=True)
+        q39 = d3q39_leg(hslb, np, wl, n, u, min(args.steps, 1000))
+
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
@@ -347,6 +389,7 @@ def main():
         "surrogate": surr,
         "attraction": att,
         "obstacle": obst,
+        "d3q39": q39,
         "roofline": roof,
         "kernels_us": kernels,
         "cpu_baseline": cpu,

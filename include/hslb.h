@@ -14,11 +14,13 @@
  *
  * Conventions shared by every call:
  *  - Node order: node = x + nx*(y + ny*z).  Scalar fields are [N] arrays,
- *    vector fields [3][N] (component-major), populations [19][N], where
+ *    vector fields [3][N] (component-major), populations [Q][N] (Q = 19, or 39
+ *    with HSLB_D3Q39), where
  *    N = nx*ny*nz counts solid wall layers too.
  *  - Host arrays are caller-owned, FP64, and copied during the call; the
  *    library never keeps a host pointer.  The library owns all device memory.
- *  - Units: lattice units, particle mass m = 1, k_B T = v_T^2 = 1/3.
+ *  - Units: lattice units, particle mass m = 1, k_B T = v_T^2 = 1/3 (2/3 on
+ *    the 39-velocity lattice).
  *  - Every call returns int: HSLB_OK (0) or a negative HSLB_E* code; no call
  *    aborts or throws.  hslb_last_error() gives a message for the last failure.
  *  - A context is used by one host thread at a time.  Work is queued on the
@@ -61,6 +63,28 @@ enum { HSLB_G2_PAPER = 0, HSLB_G2_CS = 1 };
  * surrogate (with the exact sum as periodic judge), or none. */
 enum { HSLB_FORCE_EXACT = 0, HSLB_FORCE_SURROGATE = 1, HSLB_FORCE_OFF = 2 };
 
+/* Velocity set.  HSLB_D3Q19 (0) is the paper's 19-velocity lattice with the
+ * second-order equilibrium (11) and k_B T = v_T^2 = 1/3.  HSLB_D3Q39 is the
+ * higher-order Hermite basis the paper names as the alternative to the wall
+ * regulariser and as the route to high Knudsen numbers (discussion of the
+ * validation, and conclusions): the 39-velocity quadrature of degree 7 with
+ * integer velocities, k_B T = v_T^2 = 2/3 (also in the force's k_B T and its
+ * current coefficient), the equilibrium (11) carried to third order in u, and
+ * a collision that keeps only the h^(2) and h^(3) projections of the
+ * non-equilibrium part (off-basis contributions removed):
+ *   f_i <- f_eq,i + (1 - 1/tau) w_i [h2_i : a2 / (2 v_T^4) + h3_i : a3 / (6 v_T^6)]
+ *          + w_i c_i . F / v_T^2,   a_l = sum_i h_l(c_i) (f_i - f_eq,i).
+ * Its population order is: 0 rest; 1-6 +-x, +-y, +-z; 7-14 (1,1,1), (-1,-1,-1),
+ * (1,1,-1), (-1,-1,1), (1,-1,1), (-1,1,-1), (-1,1,1), (1,-1,-1); 15-20 +-2x,
+ * +-2y, +-2z; 21-32 (2,2,0), (-2,-2,0), (2,-2,0), (-2,2,0), (2,0,2), (-2,0,-2),
+ * (2,0,-2), (-2,0,2), (0,2,2), (0,-2,-2), (0,2,-2), (0,-2,2); 33-38 +-3x, +-3y,
+ * +-3z.  A link that would cross a wall plane is reversed where it meets the
+ * plane and lands on a node (halfway bounce-back for links up to length 3).
+ * D3Q39 contexts are FP64 only, need nx, ny >= 3, nz >= 3 when z is periodic
+ * and at least 3 fluid layers in a slit, and take no solid mask, learned force
+ * or batch. */
+enum { HSLB_D3Q19 = 0, HSLB_D3Q39 = 39 };
+
 typedef struct {
     int32_t nx, ny, nz;       /* full grid, solid wall layers included */
     int32_t wall_lo, wall_hi; /* solid layers at the z ends; both 0: z periodic.
@@ -92,6 +116,7 @@ typedef struct {
      * the batch. */
     double att_eps;
     double att_range;
+    int32_t lattice;          /* HSLB_D3Q19 (0) or HSLB_D3Q39 */
 } hslb_params;
 
 typedef struct hslb_ctx hslb_ctx;
@@ -168,7 +193,8 @@ int hslb_set_solid(hslb_ctx *ctx, const uint8_t *solid);
  * current state, solid layers included; all zero when the attraction is off. */
 int hslb_attraction_potential(hslb_ctx *ctx, double *phi);
 
-/* Populations f[19][N] of the current state, and their replacement.
+/* Populations f[Q][N] (Q = 19 or 39, see hslb_params.lattice) of the current
+ * state, and their replacement.
  * set_populations zeroes solid nodes, resets the step counter and rebuilds the
  * storage reference from the given populations; in HSLB_FP32 contexts the
  * values pass through FP32 storage (for a bitwise resume use the raw
@@ -180,7 +206,7 @@ int hslb_set_populations(hslb_ctx *ctx, const double *f);
  * the per-layer reference table and the step counters, so that a run resumed
  * from it continues bit for bit.  hslb_checkpoint_size gives the byte count of
  * the caller-owned buffer; hslb_checkpoint_load needs an initialised context
- * of the same grid and precision (HSLB_EINVAL otherwise). */
+ * of the same grid, precision and lattice (HSLB_EINVAL otherwise). */
 int hslb_checkpoint_size(hslb_ctx *ctx, int64_t *bytes);
 int hslb_checkpoint_save(hslb_ctx *ctx, void *buf);
 int hslb_checkpoint_load(hslb_ctx *ctx, const void *buf);

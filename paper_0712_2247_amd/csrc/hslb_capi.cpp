@@ -16,6 +16,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 using namespace hslb;
@@ -284,10 +285,11 @@ public:
         L_.pop_stride = (L_.N + 63) / 64 * 64;
         L_.fld_stride = (L_.plane * (p_.nz + 2 * L_.hz) + 63) / 64 * 64;
         sigma_ = sig;
+        q_ = (p_.lattice == HSLB_D3Q39) ? Q39 : NQ;
 
         sc_.tau = p_.tau;
         for (int a = 0; a < 3; ++a) sc_.g[a] = p_.accel[a];
-        const double vt2 = 1.0 / 3.0;
+        const double vt2 = l39() ? CS2_39 : 1.0 / 3.0;
         sc_.pref = -vt2 * (double)sig * (double)sig * 4.0 * M_PI;
         sc_.kappa = 2.0 / (std::sqrt(vt2) * std::sqrt(M_PI));
         sc_.eta_pref = M_PI * (double)sig * sig * sig / 6.0 / (double)ball_count(sig);
@@ -304,7 +306,7 @@ public:
         own_stream_ = true;
         HIP_TRY(hipEventCreate(&ev0_));
         HIP_TRY(hipEventCreate(&ev1_));
-        const size_t popb = sizeof(TF) * (size_t)NQ * L_.pop_stride;
+        const size_t popb = sizeof(TF) * (size_t)q_ * L_.pop_stride;
         if (hipMalloc(&f_[0], popb) != hipSuccess || hipMalloc(&f_[1], popb) != hipSuccess)
             return fail(err, HSLB_ENOMEM, "population buffers (%zu bytes each) do not fit", popb);
         // n, j, eta_bar, the 7 contact-value slots and sigma/2 + 1 row-sum fields
@@ -390,6 +392,13 @@ public:
 
     int store_populations(const double *stage)
     {
+        if (l39()) {
+            // FP64 storage as given: [39][N] into the padded [39][pop_stride]
+            if constexpr (!std::is_same<TF, double>::value) return fail(err, HSLB_EINVAL, "D3Q39 is FP64 only");
+            HIP_TRY(hipMemcpy2DAsync(f_[cur_], sizeof(double) * L_.pop_stride, stage, sizeof(double) * L_.N,
+                                     sizeof(double) * L_.N, Q39, hipMemcpyDeviceToDevice, st()));
+            return HSLB_OK;
+        }
         HIP_TRY(launch_layer_means<double>(st(), L_, stage, L_.N, nullptr, nref_d_));
         int rc = round_refs(nref_d_);
         if (rc) return rc;
@@ -431,7 +440,7 @@ public:
         }
         mass0_ = msum;
         double *d;
-        int rc = io(sizeof(double) * (4 + NQ) * (size_t)N, &d);
+        int rc = io(sizeof(double) * (4 + q_) * (size_t)N, &d);
         if (rc) return rc;
         double *stage = d + 4 * (size_t)N;
         HIP_TRY(hipMemcpyAsync(d, n, sizeof(double) * N, hipMemcpyHostToDevice, st()));
@@ -440,7 +449,10 @@ public:
         else
             HIP_TRY(hipMemsetAsync(d + N, 0, sizeof(double) * 3 * (size_t)N, st()));
         cur_ = 0;
-        HIP_TRY(launch_feq(st(), L_, d, d + N, stage));
+        if (l39())
+            HIP_TRY(launch_feq39(st(), L_, d, d + N, stage));
+        else
+            HIP_TRY(launch_feq(st(), L_, d, d + N, stage));
         rc = store_populations(stage);
         if (rc) return rc;
         HIP_TRY(hipStreamSynchronize(st()));
@@ -482,9 +494,43 @@ public:
     // whole x-rows per 256-thread block: moments and row sums in one launch
     bool fused_rows() const { return 256 % L_.nx == 0 && L_.plane % 256 == 0; }
 
+    // Moments into the padded fields, for the readouts.
+    hipError_t moments_fields()
+    {
+        if (l39()) return launch_moments39(st(), L_, (const double *)f_[cur_], fld39());
+        return launch_moments<TF, TM>(st(), L_, nref_d_, f_[cur_], fld_);
+    }
+
+    // The fields as the 39-velocity kernels take them (FP64 contexts only).
+    Fields<double> fld39() const
+    {
+        Fields<double> f{};
+        if constexpr (std::is_same<TM, double>::value) f = fld_;
+        return f;
+    }
+
+    int one_step39()
+    {
+        if constexpr (!std::is_same<TF, double>::value) {
+            return fail(err, HSLB_EINVAL, "D3Q39 is FP64 only");
+        } else {
+            int rc = launch("moments", [&] { return launch_moments39(st(), L_, f_[cur_], fld39()); });
+            if (rc) return rc;
+            if (sc_.hs_on && (rc = fields_hs())) return rc;
+            if (sc_.phi && (rc = attraction())) return rc;
+            rc = launch("collide", [&] {
+                return launch_collide39(st(), L_, sigma_, sc_, chi_d_, f_[cur_], f_[1 - cur_], fld39());
+            });
+            if (rc) return rc;
+            cur_ = 1 - cur_;
+            return HSLB_OK;
+        }
+    }
+
     int one_step()
     {
         int rc;
+        if (l39()) return one_step39();
         if (sc_.hs_on && fused_rows()) {
             rc = launch("moments", [&] {
                 return launch_moments_rs<TF, TM>(st(), L_, sigma_, nref_d_, f_[cur_], fld_, rs_);
@@ -604,9 +650,15 @@ public:
         return HSLB_OK;
     }
 
+    hipError_t launch_profiles()
+    {
+        if (l39()) return launch_profiles39(st(), L_, (const double *)f_[cur_], prof_d_);
+        return launch_profiles_pop<TF>(st(), L_, nref_d_, f_[cur_], prof_d_);
+    }
+
     int watchdog_check()
     {
-        HIP_TRY(launch_profiles_pop<TF>(st(), L_, nref_d_, f_[cur_], prof_d_));
+        HIP_TRY(launch_profiles());
         HIP_TRY(hipMemcpyAsync(prof_h_, prof_d_, sizeof(double) * 5 * L_.nz, hipMemcpyDeviceToHost, st()));
         HIP_TRY(hipStreamSynchronize(st()));
         double m = 0.0;
@@ -672,7 +724,10 @@ public:
         const size_t N = L_.N;
         int rc = io(sizeof(double) * 4 * N, &d);
         if (rc) return rc;
-        HIP_TRY(launch_export_moments<TF>(st(), L_, nref_d_, f_[cur_], d, d + N));
+        if (l39())
+            HIP_TRY(launch_export39(st(), L_, (const double *)f_[cur_], d, d + N));
+        else
+            HIP_TRY(launch_export_moments<TF>(st(), L_, nref_d_, f_[cur_], d, d + N));
         if (n) HIP_TRY(hipMemcpyAsync(n, d, sizeof(double) * N, hipMemcpyDeviceToHost, st()));
         if (u) HIP_TRY(hipMemcpyAsync(u, d + N, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, st()));
         HIP_TRY(hipStreamSynchronize(st()));
@@ -682,7 +737,7 @@ public:
     int profiles(double *nz, double *uz) override
     {
         if (!inited) return fail(err, HSLB_ESTATE, "profiles before init");
-        HIP_TRY(launch_profiles_pop<TF>(st(), L_, nref_d_, f_[cur_], prof_d_));
+        HIP_TRY(launch_profiles());
         HIP_TRY(hipMemcpyAsync(prof_h_, prof_d_, sizeof(double) * 5 * L_.nz, hipMemcpyDeviceToHost, st()));
         HIP_TRY(hipStreamSynchronize(st()));
         if (nz) std::memcpy(nz, prof_h_, sizeof(double) * L_.nz);
@@ -697,10 +752,13 @@ public:
         const size_t N = L_.N;
         int rc = io(sizeof(double) * 3 * N, &d);
         if (rc) return rc;
-        HIP_TRY(launch_moments<TF, TM>(st(), L_, nref_d_, f_[cur_], fld_));
+        HIP_TRY(moments_fields());
         if (sc_.hs_on && (rc = fields_hs())) return rc;
         if (sc_.phi && (rc = attraction())) return rc;
-        HIP_TRY(launch_force<TF, TM>(st(), L_, sigma_, sc_, chi_d_, f_[cur_], fld_, d));
+        if (l39())
+            HIP_TRY(launch_force39(st(), L_, sigma_, sc_, chi_d_, (const double *)f_[cur_], fld39(), d));
+        else
+            HIP_TRY(launch_force<TF, TM>(st(), L_, sigma_, sc_, chi_d_, f_[cur_], fld_, d));
         HIP_TRY(hipMemcpyAsync(F, d, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, st()));
         HIP_TRY(hipStreamSynchronize(st()));
         return HSLB_OK;
@@ -709,6 +767,7 @@ public:
     int set_solid(const uint8_t *solid) override
     {
         if (inited) return fail(err, HSLB_ESTATE, "set_solid after init");
+        if (l39()) return fail(err, HSLB_EINVAL, "solid masks are not available on the 39-velocity lattice");
         if (p_.force_mode == HSLB_FORCE_SURROGATE)
             return fail(err, HSLB_EINVAL, "solid masks are not available with the learned force");
         const int N = L_.N, nx = L_.nx, ny = L_.ny, nz = L_.nz;
@@ -759,7 +818,7 @@ public:
             std::memset(phi, 0, sizeof(double) * (size_t)L_.N);
             return HSLB_OK;
         }
-        HIP_TRY(launch_moments<TF, TM>(st(), L_, nref_d_, f_[cur_], fld_));
+        HIP_TRY(moments_fields());
         int rc = attraction();
         if (rc) return rc;
         HIP_TRY(hipMemcpyAsync(phi, sc_.phi, sizeof(double) * L_.N, hipMemcpyDeviceToHost, st()));
@@ -773,7 +832,7 @@ public:
         double *d;
         int rc = io(sizeof(double) * (size_t)L_.N, &d);
         if (rc) return rc;
-        HIP_TRY(launch_moments<TF, TM>(st(), L_, nref_d_, f_[cur_], fld_));
+        HIP_TRY(moments_fields());
         HIP_TRY(launch_smooth2<TM>(st(), L_, sigma_, sc_.eta_pref, fld_, rs_));
         HIP_TRY(launch_unpad<TM>(st(), L_, fld_.eb, d));
         HIP_TRY(hipMemcpyAsync(eb, d, sizeof(double) * L_.N, hipMemcpyDeviceToHost, st()));
@@ -784,6 +843,12 @@ public:
     int get_pop(double *f) override
     {
         if (!inited) return fail(err, HSLB_ESTATE, "get_populations before init");
+        if (l39()) {
+            HIP_TRY(hipMemcpy2DAsync(f, sizeof(double) * L_.N, f_[cur_], sizeof(TF) * L_.pop_stride,
+                                     sizeof(double) * L_.N, Q39, hipMemcpyDeviceToHost, st()));
+            HIP_TRY(hipStreamSynchronize(st()));
+            return HSLB_OK;
+        }
         double *d;
         const size_t tot = (size_t)NQ * L_.N;
         int rc = io(sizeof(double) * tot, &d);
@@ -797,11 +862,19 @@ public:
     int set_pop(const double *f) override
     {
         if (!inited) return fail(err, HSLB_ESTATE, "set_populations before init");
-        const size_t tot = (size_t)NQ * L_.N;
+        const size_t tot = (size_t)q_ * L_.N;
         for (size_t k = 0; k < tot; ++k)
             if (!std::isfinite(f[k]))
                 return fail(err, HSLB_EINVAL, "population %zu is not finite", k);
         std::vector<double> fm;
+        if (l39()) {
+            // solid layers carry nothing
+            fm.assign(f, f + tot);
+            for (int id = 0; id < L_.N; ++id)
+                if (!fluid_z(id / L_.plane))
+                    for (int i = 0; i < Q39; ++i) fm[(size_t)i * L_.N + id] = 0.0;
+            f = fm.data();
+        }
         if (!solid_h_.empty()) {
             fm.assign(f, f + tot);
             for (int id = 0; id < L_.N; ++id)
@@ -827,24 +900,24 @@ public:
     // Raw checkpoint: header, populations in storage precision [19][N], the
     // reference table [nz][19].
     struct CkHeader {
-        int64_t magic, tf_bytes, nx, ny, nz, steps, refreshed_at;
+        int64_t magic, tf_bytes, nx, ny, nz, steps, refreshed_at, q;
     };
     static constexpr int64_t kMagic = 0x48534c4243503031;  // "HSLBCP01"
 
     int checkpoint_bytes(int64_t *bytes) override
     {
-        *bytes = (int64_t)sizeof(CkHeader) + (int64_t)sizeof(TF) * NQ * L_.N + (int64_t)sizeof(double) * NQ * L_.nz;
+        *bytes = (int64_t)sizeof(CkHeader) + (int64_t)sizeof(TF) * q_ * L_.N + (int64_t)sizeof(double) * NQ * L_.nz;
         return HSLB_OK;
     }
 
     int checkpoint_save(void *buf) override
     {
         if (!inited) return fail(err, HSLB_ESTATE, "checkpoint before init");
-        CkHeader h{kMagic, (int64_t)sizeof(TF), L_.nx, L_.ny, L_.nz, steps, refreshed_at_};
+        CkHeader h{kMagic, (int64_t)sizeof(TF), L_.nx, L_.ny, L_.nz, steps, refreshed_at_, q_};
         char *p = (char *)buf;
         std::memcpy(p, &h, sizeof(h));
         p += sizeof(h);
-        for (int i = 0; i < NQ; ++i) {
+        for (int i = 0; i < q_; ++i) {
             HIP_TRY(hipMemcpyAsync(p, f_[cur_] + (size_t)i * L_.pop_stride, sizeof(TF) * L_.N, hipMemcpyDeviceToHost,
                                    st()));
             p += sizeof(TF) * L_.N;
@@ -860,10 +933,10 @@ public:
         CkHeader h;
         std::memcpy(&h, buf, sizeof(h));
         if (h.magic != kMagic || h.tf_bytes != (int64_t)sizeof(TF) || h.nx != L_.nx || h.ny != L_.ny ||
-            h.nz != L_.nz)
+            h.nz != L_.nz || h.q != q_)
             return fail(err, HSLB_EINVAL, "checkpoint does not match this context");
         const char *p = (const char *)buf + sizeof(h);
-        for (int i = 0; i < NQ; ++i) {
+        for (int i = 0; i < q_; ++i) {
             HIP_TRY(hipMemcpyAsync(f_[cur_] + (size_t)i * L_.pop_stride, p, sizeof(TF) * L_.N, hipMemcpyHostToDevice,
                                    st()));
             p += sizeof(TF) * L_.N;
@@ -1113,6 +1186,7 @@ public:
     {
         if (!inited) return fail(err, HSLB_ESTATE, "snapshot before init");
         if (p_.force_mode == HSLB_FORCE_OFF) return fail(err, HSLB_ESTATE, "hard-sphere term is off");
+        if (l39()) return fail(err, HSLB_EINVAL, "training snapshots come from 19-velocity lattices");
         if (L_.nx % 32 || L_.ny % 4) return fail(err, HSLB_EINVAL, "training snapshots need nx %% 32 == 0 and ny %% 4 == 0");
         if (!x || !target) {  // geometry only
             *g = cnn_geo();
@@ -1164,6 +1238,8 @@ private:
     uint32_t *links_d_ = nullptr;   // [N] solid-neighbour bits (mask set)
     double *chi_n_d_ = nullptr;     // [N] per-node wall factor (mask set)
     int sigma_ = 2;
+    int q_ = NQ;  // velocities: 19, or 39 for the third-order lattice (FP64)
+    bool l39() const { return q_ == Q39; }
     hipStream_t stream_ = nullptr, ext_stream_ = nullptr;
     bool own_stream_ = false;
     hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
@@ -1770,6 +1846,16 @@ static int validate(const hslb_params *p, std::string &err)
         if (p->force_mode == HSLB_FORCE_SURROGATE)
             return fail(err, HSLB_EINVAL, "the attraction is not available with the learned force");
     }
+    if (p->lattice != HSLB_D3Q19 && p->lattice != HSLB_D3Q39) return fail(err, HSLB_EINVAL, "lattice");
+    if (p->lattice == HSLB_D3Q39) {
+        if (p->precision != HSLB_FP64) return fail(err, HSLB_EINVAL, "the 39-velocity lattice is FP64 only");
+        if (p->force_mode == HSLB_FORCE_SURROGATE)
+            return fail(err, HSLB_EINVAL, "the learned force needs the 19-velocity lattice");
+        if (p->nx < 3 || p->ny < 3) return fail(err, HSLB_EINVAL, "the 39-velocity lattice needs nx, ny >= 3");
+        if (p->wall_lo == 0 && p->nz < 3) return fail(err, HSLB_EINVAL, "the 39-velocity lattice needs nz >= 3");
+        if (p->wall_lo > 0 && p->nz - p->wall_lo - p->wall_hi < 3)
+            return fail(err, HSLB_EINVAL, "the 39-velocity lattice needs at least 3 fluid layers");
+    }
     const int sig = p->sigma >= 2 ? p->sigma : 2;
     const double fld = (double)p->nx * p->ny * (p->nz + 2.0 * sig);
     if (fld + 64 >= 2147483647.0) return fail(err, HSLB_EINVAL, "grid too large for 32-bit node indices");
@@ -2040,6 +2126,7 @@ int hslb_batch_create(const hslb_params *slits, int32_t nslits, hslb_ctx **out)
         }
         if (slits[k].precision != slits[0].precision) return fail(err, HSLB_EINVAL, "mixed precisions in a batch");
         if (slits[k].force_mode == HSLB_FORCE_SURROGATE) return fail(err, HSLB_EINVAL, "surrogate in a batch");
+        if (slits[k].lattice != HSLB_D3Q19) return fail(err, HSLB_EINVAL, "a batch holds 19-velocity slits");
         if (slits[k].att_eps != 0.0) return fail(err, HSLB_EINVAL, "attraction in a batch");
     }
     std::unique_ptr<hslb_ctx> c(new (std::nothrow) hslb_ctx());

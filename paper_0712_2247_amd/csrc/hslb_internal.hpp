@@ -13,6 +13,25 @@ constexpr int CX[NQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 
 constexpr int CY[NQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 constexpr int CZ[NQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
 constexpr int OPP[NQ] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+// The 39-velocity third-order lattice in the public population order: rest,
+// axis length 1, cube diagonals, axis length 2, (2, 2, 0) family, axis
+// length 3; every odd index is followed by its opposite.
+constexpr int Q39 = 39;
+constexpr int C39X[Q39] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, -1, 1, 2, -2, 0, 0, 0,
+                           0, 2, -2, 2, -2, 2, -2, 2, -2, 0, 0, 0, 0, 3, -3, 0, 0, 0, 0};
+constexpr int C39Y[Q39] = {0, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, -1, 1, 1, -1, 0, 0, 2, -2, 0,
+                           0, 2, -2, -2, 2, 0, 0, 0, 0, 2, -2, 2, -2, 0, 0, 3, -3, 0, 0};
+constexpr int C39Z[Q39] = {0, 0, 0, 0, 0, 1, -1, 1, -1, -1, 1, 1, -1, 1, -1, 0, 0, 0, 0, 2,
+                           -2, 0, 0, 0, 0, 2, -2, -2, 2, 2, -2, -2, 2, 0, 0, 0, 0, 3, -3};
+__host__ __device__ constexpr int opp39(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+// Weight by |c|^2: 0 and 1 -> 1/12, 3 -> 1/27, 4 -> 2/135, 8 -> 1/432, 9 -> 1/1620.
+__host__ __device__ constexpr double w39(int i)
+{
+    const int c2 = C39X[i] * C39X[i] + C39Y[i] * C39Y[i] + C39Z[i] * C39Z[i];
+    return c2 <= 1 ? 1.0 / 12.0 : c2 == 3 ? 1.0 / 27.0 : c2 == 4 ? 2.0 / 135.0 : c2 == 8 ? 1.0 / 432.0 : 1.0 / 1620.0;
+}
+constexpr double CS2_39 = 2.0 / 3.0;  // v_T^2 of the 39-velocity lattice
+
 constexpr int NGSLOT = 7;  // contact-value sub-lattices: bits x=1, y=2, z=4 (0..6)
 
 // Workgroups are handed to the 8 XCDs round-robin by linear block index.  This
@@ -156,6 +175,21 @@ hipError_t launch_set_pop(hipStream_t s, const LatticeDev &L, const double *nref
                           TF *f);
 
 hipError_t launch_copy(hipStream_t s, const void *src, void *dst, size_t bytes);
+
+// The 39-velocity lattice (FP64 populations [39][pop_stride], stored as they
+// are, without a reference table).  feq: third-order equilibrium of (n, u) as
+// [39][N] (0 on solid layers); moments: n and (n, j) into the padded fields;
+// collide: force, regularised collision and streaming, one launch over the
+// fluid layers; force: F[3][N] of the current fields; export: n[N], u[3][N].
+hipError_t launch_feq39(hipStream_t s, const LatticeDev &L, const double *n, const double *u, double *out);
+hipError_t launch_moments39(hipStream_t s, const LatticeDev &L, const double *f, Fields<double> fld);
+hipError_t launch_collide39(hipStream_t s, const LatticeDev &L, int sigma, const StepConst &c, const double *chi,
+                            const double *fin, double *fout, Fields<double> fld);
+hipError_t launch_force39(hipStream_t s, const LatticeDev &L, int sigma, const StepConst &c, const double *chi,
+                          const double *f, Fields<double> fld, double *F);
+hipError_t launch_export39(hipStream_t s, const LatticeDev &L, const double *f, double *n, double *u);
+// Layer profiles [5][nz] as launch_profiles_pop.
+hipError_t launch_profiles39(hipStream_t s, const LatticeDev &L, const double *f, double *out);
 
 // a[k] = (double)(float)a[k]: FP32-representable reference tables, so that a
 // solid node (all populations 0) is stored exactly as -ref in FP32.

@@ -19,6 +19,7 @@
 #include "hslb_internal.hpp"
 
 #include <algorithm>
+#include <utility>
 #include <cmath>
 
 // Tuning switch (compile-time): 1 evaluates the shell sum in FP64 whatever the
@@ -1137,6 +1138,286 @@ __global__ __launch_bounds__(256) void k_copy(const float4 *__restrict__ a, floa
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) b[i] = a[i];
 }
 
+// ------------------------------------------------- 39-velocity lattice
+
+// Third-order equilibrium of velocity I: w n [1 + xi + xi^2/2 - u^2/(2 s) +
+// xi^3/6 - xi u^2/(2 s)], xi = c.u / s, s = v_T^2 = 2/3.
+template <int I>
+__device__ __forceinline__ double feq39_of(double n, const double u[3], double uu_s)
+{
+    constexpr double is = 1.0 / CS2_39;
+    const double xi = (C39X[I] * u[0] + C39Y[I] * u[1] + C39Z[I] * u[2]) * is;
+    return w39(I) * n * (1.0 + xi + 0.5 * xi * xi - 0.5 * uu_s + xi * xi * xi * (1.0 / 6.0) - 0.5 * xi * uu_s);
+}
+
+template <int... I>
+__device__ __forceinline__ void feq39_all(double n, const double u[3], double *out, std::integer_sequence<int, I...>)
+{
+    const double uu_s = (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / CS2_39;
+    ((out[I] = feq39_of<I>(n, u, uu_s)), ...);
+}
+
+__global__ __launch_bounds__(256) void k_feq39(LatticeDev L, const double *__restrict__ n,
+                                               const double *__restrict__ u, double *__restrict__ out)
+{
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= L.N) return;
+    double f[Q39];
+    if (is_fluid_z(L, id / L.plane)) {
+        const double uv[3] = {u[id], u[L.N + id], u[2 * (size_t)L.N + id]};
+        feq39_all(n[id], uv, f, std::make_integer_sequence<int, Q39>{});
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q39; ++i) f[i] = 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < Q39; ++i) out[(size_t)i * L.N + id] = f[i];
+}
+
+// n and j of a node from its 39 populations (0 on solid layers).
+__device__ __forceinline__ void moments39(const LatticeDev &L, const double *__restrict__ f, size_t id, int z,
+                                          double &n, double &jx, double &jy, double &jz)
+{
+    n = jx = jy = jz = 0.0;
+    if (!is_fluid_z(L, z)) return;
+#pragma unroll
+    for (int i = 0; i < Q39; ++i) {
+        const double fi = f[(size_t)i * L.pop_stride + id];
+        n += fi;
+        jx += C39X[i] * fi;
+        jy += C39Y[i] * fi;
+        jz += C39Z[i] * fi;
+    }
+}
+
+// grid (ceil(plane / 256), nz)
+__global__ __launch_bounds__(256) void k_moments39(LatticeDev L, const double *__restrict__ f, Fields<double> fld)
+{
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    const int z = (int)blockIdx.y;
+    if (r >= L.plane) return;
+    double n, jx, jy, jz;
+    moments39(L, f, (size_t)z * L.plane + r, z, n, jx, jy, jz);
+    store_padded(L, fld.n, r, z, n);
+    store_padded4(L, fld.nj, r, z, n, jx, jy, jz);
+}
+
+__global__ __launch_bounds__(256) void k_export39(LatticeDev L, const double *__restrict__ f, double *__restrict__ n,
+                                                  double *__restrict__ u)
+{
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= L.N) return;
+    double m, jx, jy, jz;
+    moments39(L, f, id, id / L.plane, m, jx, jy, jz);
+    const double inv = (m != 0.0) ? 1.0 / m : 0.0;
+    n[id] = m;
+    u[id] = jx * inv;
+    u[L.N + id] = jy * inv;
+    u[2 * (size_t)L.N + id] = jz * inv;
+}
+
+// Layer profiles as k_profiles: out[z] = mean n, out[(1 + a) nz + z] = u_a,
+// out[4 nz + z] = sum n.  grid (nz)
+__global__ __launch_bounds__(256) void k_profiles39(LatticeDev L, const double *__restrict__ f, double *__restrict__ out)
+{
+    const int z = blockIdx.x;
+    __shared__ double red[4][4];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r = threadIdx.x; r < L.plane; r += 256) {
+        double n, jx, jy, jz;
+        moments39(L, f, (size_t)z * L.plane + r, z, n, jx, jy, jz);
+        s[0] += n;
+        s[1] += jx;
+        s[2] += jy;
+        s[3] += jz;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double t = wave_sum(s[k]);
+        if (lane == 0) red[wv][k] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) t[k] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+        out[z] = t[0] / (double)L.plane;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) out[(1 + a) * L.nz + z] = (t[0] != 0.0) ? t[1 + a] / t[0] : 0.0;
+        out[4 * L.nz + z] = t[0];
+    }
+}
+
+// Hermite coefficients of the non-equilibrium part d = f - f_eq:
+// a2 = sum h2 d over (xx, yy, zz, xy, xz, yz), a3 = sum h3 d over
+// (xxx, yyy, zzz, xxy, xxz, xyy, yyz, xzz, yzz, xyz), with
+// h2_ab = c_a c_b - s d_ab and h3_abg = c_a c_b c_g - s (c_a d_bg + c_b d_ag + c_g d_ab).
+template <int I>
+__device__ __forceinline__ void herm_acc(double d, double a2[6], double a3[10])
+{
+    constexpr double s = CS2_39;
+    constexpr double x = C39X[I], y = C39Y[I], z = C39Z[I];
+    a2[0] += (x * x - s) * d;
+    a2[1] += (y * y - s) * d;
+    a2[2] += (z * z - s) * d;
+    if constexpr (C39X[I] * C39Y[I] != 0) a2[3] += (x * y) * d;
+    if constexpr (C39X[I] * C39Z[I] != 0) a2[4] += (x * z) * d;
+    if constexpr (C39Y[I] * C39Z[I] != 0) a2[5] += (y * z) * d;
+    if constexpr (C39X[I] != 0) a3[0] += (x * x * x - 3.0 * s * x) * d;
+    if constexpr (C39Y[I] != 0) a3[1] += (y * y * y - 3.0 * s * y) * d;
+    if constexpr (C39Z[I] != 0) a3[2] += (z * z * z - 3.0 * s * z) * d;
+    if constexpr (C39Y[I] != 0) a3[3] += (x * x * y - s * y) * d;
+    if constexpr (C39Z[I] != 0) a3[4] += (x * x * z - s * z) * d;
+    if constexpr (C39X[I] != 0) a3[5] += (x * y * y - s * x) * d;
+    if constexpr (C39Z[I] != 0) a3[6] += (y * y * z - s * z) * d;
+    if constexpr (C39X[I] != 0) a3[7] += (x * z * z - s * x) * d;
+    if constexpr (C39Y[I] != 0) a3[8] += (y * z * z - s * y) * d;
+    if constexpr (C39X[I] * C39Y[I] * C39Z[I] != 0) a3[9] += (x * y * z) * d;
+}
+
+// The projection of velocity I: h2 : a2 / (2 s^2) + h3 : a3 / (6 s^3), the
+// full contractions written over the distinct components with their
+// multiplicities (2 for xy-type in h2; 3 for xxy-type, 6 for xyz in h3).
+template <int I>
+__device__ __forceinline__ double herm_proj(const double a2[6], const double a3[10])
+{
+    constexpr double s = CS2_39;
+    constexpr double x = C39X[I], y = C39Y[I], z = C39Z[I];
+    const double p2 = (x * x - s) * a2[0] + (y * y - s) * a2[1] + (z * z - s) * a2[2] +
+                      2.0 * ((x * y) * a2[3] + (x * z) * a2[4] + (y * z) * a2[5]);
+    const double p3 = (x * x * x - 3.0 * s * x) * a3[0] + (y * y * y - 3.0 * s * y) * a3[1] +
+                      (z * z * z - 3.0 * s * z) * a3[2] +
+                      3.0 * ((x * x * y - s * y) * a3[3] + (x * x * z - s * z) * a3[4] + (x * y * y - s * x) * a3[5] +
+                             (y * y * z - s * z) * a3[6] + (x * z * z - s * x) * a3[7] + (y * z * z - s * y) * a3[8]) +
+                      6.0 * (x * y * z) * a3[9];
+    return p2 * (1.0 / (2.0 * s * s)) + p3 * (1.0 / (6.0 * s * s * s));
+}
+
+// Collide and stream of velocity I from node (x, y, z): post-collision value
+// from the equilibrium, the relaxed projection and the first-order source,
+// then the landing node.  A link that would leave the fluid layers is
+// reversed at the wall plane: lateral run (2 d - |c_z|) c_a / |c_z| with d the
+// node's distance to the plane, mirrored z.
+template <int I>
+__device__ __forceinline__ void out39(const LatticeDev &L, double *__restrict__ fout, int x, int y, int z, double fe,
+                                      double om, const double a2[6], const double a3[10], const double F[3])
+{
+    constexpr int cx = C39X[I], cy = C39Y[I], cz = C39Z[I];
+    const double src = w39(I) * (cx * F[0] + cy * F[1] + cz * F[2]) * (1.0 / CS2_39);
+    const double fp = fe + om * (w39(I) * herm_proj<I>(a2, a3)) + src;
+    int xt = x + cx, yt = y + cy, zt = z + cz, k = I;
+    if constexpr (cz != 0) {
+        if (L.zper) {
+            zt = (zt < 0) ? zt + L.nz : ((zt >= L.nz) ? zt - L.nz : zt);
+        } else {
+            constexpr int az = cz < 0 ? -cz : cz;
+            const int lo = L.wall_lo, hi = L.nz - L.wall_hi;
+            int run = 0;
+            bool hit = false;
+            if constexpr (cz < 0) {
+                if (zt < lo) {
+                    run = 2 * (z - lo) + 1 + cz;
+                    zt = 2 * lo - 1 - zt;
+                    hit = true;
+                }
+            } else {
+                if (zt >= hi) {
+                    run = 2 * (hi - 1 - z) + 1 - cz;
+                    zt = 2 * hi - 1 - zt;
+                    hit = true;
+                }
+            }
+            if (hit) {
+                xt = x + (cx / az) * run;
+                yt = y + (cy / az) * run;
+                k = opp39(I);
+            }
+        }
+    }
+    xt = (xt < 0) ? xt + L.nx : ((xt >= L.nx) ? xt - L.nx : xt);
+    yt = (yt < 0) ? yt + L.ny : ((yt >= L.ny) ? yt - L.ny : yt);
+    fout[(size_t)k * L.pop_stride + (size_t)xt + (size_t)L.nx * ((size_t)yt + (size_t)L.ny * zt)] = fp;
+}
+
+// The projections first (the populations are dead before the force's shell
+// sum), the post-collision values and their streaming after it.
+template <int... I>
+__device__ __forceinline__ void project39(double n, const double u[3], const double *__restrict__ f, double a2[6],
+                                          double a3[10], std::integer_sequence<int, I...>)
+{
+    const double uu_s = (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / CS2_39;
+    (herm_acc<I>(f[I] - feq39_of<I>(n, u, uu_s), a2, a3), ...);
+}
+
+template <int... I>
+__device__ __forceinline__ void emit39(const LatticeDev &L, double *__restrict__ fout, int x, int y, int z, double n,
+                                      const double u[3], double om, const double F[3], const double a2[6],
+                                      const double a3[10], std::integer_sequence<int, I...>)
+{
+    const double uu_s = (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / CS2_39;
+    (out39<I>(L, fout, x, y, z, feq39_of<I>(n, u, uu_s), om, a2, a3, F), ...);
+}
+
+// 1-D grid over (fluid layer, chunk of 256 nodes of the layer), as k_collide.
+template <int SIG>
+__global__ __launch_bounds__(256) void k_collide39(LatticeDev L, StepConst sc, const double *__restrict__ chi,
+                                                   const double *__restrict__ fin, double *__restrict__ fout,
+                                                   Fields<double> fld, int cpp)
+{
+    const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int zl = lb / cpp;
+    const int r = (lb - zl * cpp) * 256 + threadIdx.x;
+    const int z = (L.zper ? 0 : L.wall_lo) + zl;
+    if (r >= L.plane) return;
+    const int y = r / L.nx;
+    const int x = r - y * L.nx;
+    const size_t id = (size_t)z * L.plane + r;
+    double f[Q39];
+#pragma unroll
+    for (int i = 0; i < Q39; ++i) f[i] = fin[(size_t)i * L.pop_stride + id];
+    double n = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q39; ++i) {
+        n += f[i];
+        jx += C39X[i] * f[i];
+        jy += C39Y[i] * f[i];
+        jz += C39Z[i] * f[i];
+    }
+    const double inv_n = (n != 0.0) ? 1.0 / n : 0.0;
+    const double u[3] = {jx * inv_n, jy * inv_n, jz * inv_n};
+    double a2[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double a3[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    project39(n, u, f, a2, a3, std::make_integer_sequence<int, Q39>{});
+    double Fv[3];
+    node_force<SIG, true, double, false>(fld, L, sc, chi, x, y, z, n, u, Fv);
+    emit39(L, fout, x, y, z, n, u, 1.0 - 1.0 / sc.tau, Fv, a2, a3, std::make_integer_sequence<int, Q39>{});
+}
+
+template <int SIG>
+__global__ __launch_bounds__(256) void k_force39(LatticeDev L, StepConst sc, const double *__restrict__ chi,
+                                                 const double *__restrict__ f, Fields<double> fld,
+                                                 double *__restrict__ Fout)
+{
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= L.N) return;
+    const int z = id / L.plane;
+    const int rem = id - z * L.plane;
+    const int y = rem / L.nx;
+    const int x = rem - y * L.nx;
+    double Fv[3] = {0.0, 0.0, 0.0};
+    if (is_fluid_z(L, z)) {
+        double n, jx, jy, jz;
+        moments39(L, f, id, z, n, jx, jy, jz);
+        const double inv_n = (n != 0.0) ? 1.0 / n : 0.0;
+        const double u[3] = {jx * inv_n, jy * inv_n, jz * inv_n};
+        node_force<SIG, false, double, false>(fld, L, sc, chi, x, y, z, n, u, Fv);
+    }
+    Fout[id] = Fv[0];
+    Fout[L.N + id] = Fv[1];
+    Fout[2 * (size_t)L.N + id] = Fv[2];
+}
+
 inline unsigned blocks_for(int n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
@@ -1156,6 +1437,72 @@ hipError_t launch_attraction(hipStream_t s, const LatticeDev &L, const AttWeight
 hipError_t launch_round_f32(hipStream_t s, double *a, int count)
 {
     hipLaunchKernelGGL(k_round_f32, dim3(blocks_for(count)), dim3(256), 0, s, a, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_feq39(hipStream_t s, const LatticeDev &L, const double *n, const double *u, double *out)
+{
+    hipLaunchKernelGGL(k_feq39, dim3(blocks_for(L.N)), dim3(256), 0, s, L, n, u, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments39(hipStream_t s, const LatticeDev &L, const double *f, Fields<double> fld)
+{
+    hipLaunchKernelGGL(k_moments39, dim3(blocks_for(L.plane), L.nz), dim3(256), 0, s, L, f, fld);
+    return hipGetLastError();
+}
+
+hipError_t launch_profiles39(hipStream_t s, const LatticeDev &L, const double *f, double *out)
+{
+    hipLaunchKernelGGL(k_profiles39, dim3(L.nz), dim3(256), 0, s, L, f, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_export39(hipStream_t s, const LatticeDev &L, const double *f, double *n, double *u)
+{
+    hipLaunchKernelGGL(k_export39, dim3(blocks_for(L.N)), dim3(256), 0, s, L, f, n, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_collide39(hipStream_t s, const LatticeDev &L, int sigma, const StepConst &c, const double *chi,
+                            const double *fin, double *fout, Fields<double> fld)
+{
+    const int layers = L.zper ? L.nz : L.nz - L.wall_lo - L.wall_hi;
+    const int cpp = (int)blocks_for(L.plane);
+    const dim3 g(cpp * layers), b(256);
+#define HSLB_C39(SG)                                                                               \
+    case SG: hipLaunchKernelGGL((k_collide39<SG>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
+    switch (sigma) {
+        HSLB_C39(2)
+        HSLB_C39(3)
+        HSLB_C39(4)
+        HSLB_C39(5)
+        HSLB_C39(6)
+        HSLB_C39(7)
+        HSLB_C39(8)
+    default: return hipErrorInvalidValue;
+    }
+#undef HSLB_C39
+    return hipGetLastError();
+}
+
+hipError_t launch_force39(hipStream_t s, const LatticeDev &L, int sigma, const StepConst &c, const double *chi,
+                          const double *f, Fields<double> fld, double *F)
+{
+    const dim3 g(blocks_for(L.N)), b(256);
+#define HSLB_F39(SG)                                                                               \
+    case SG: hipLaunchKernelGGL((k_force39<SG>), g, b, 0, s, L, c, chi, f, fld, F); break;
+    switch (sigma) {
+        HSLB_F39(2)
+        HSLB_F39(3)
+        HSLB_F39(4)
+        HSLB_F39(5)
+        HSLB_F39(6)
+        HSLB_F39(7)
+        HSLB_F39(8)
+    default: return hipErrorInvalidValue;
+    }
+#undef HSLB_F39
     return hipGetLastError();
 }
 

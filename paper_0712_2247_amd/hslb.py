@@ -32,6 +32,8 @@ HSLB_G2_CS = 1
 HSLB_FORCE_EXACT = 0
 HSLB_FORCE_SURROGATE = 1
 HSLB_FORCE_OFF = 2
+HSLB_D3Q19 = 0
+HSLB_D3Q39 = 39
 HSLB_SURR_CORRECTED = 0
 HSLB_SURR_PLAIN = 1
 HSLB_SURR_FROZEN = 2
@@ -71,6 +73,7 @@ class hslb_params(ctypes.Structure):
         ("surr_check_every", ctypes.c_int32),
         ("surr_tol", ctypes.c_double),
         ("att_eps", ctypes.c_double), ("att_range", ctypes.c_double),
+        ("lattice", ctypes.c_int32),
     ]
 
 
@@ -475,7 +478,7 @@ def hslb_cnn_op(op: int, nx: int, ny: int, nz: int, zper: bool, w, inp, aux=None
 def make_params(nx, ny, nz, sigma, tau, accel=(0.0, 0.0, 0.0), wall_lo=0, wall_hi=0,
                 g2_model=HSLB_G2_PAPER, wall_reg=1, precision=HSLB_FP64,
                 force_mode=HSLB_FORCE_EXACT, surr_check_every=50, surr_tol=1e-3, att_eps=0.0,
-                att_range=0.0) -> hslb_params:
+                att_range=0.0, lattice=HSLB_D3Q19) -> hslb_params:
     p = hslb_params()
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     p.wall_lo, p.wall_hi = int(wall_lo), int(wall_hi)
@@ -486,22 +489,25 @@ def make_params(nx, ny, nz, sigma, tau, accel=(0.0, 0.0, 0.0), wall_lo=0, wall_h
     p.precision, p.force_mode = int(precision), int(force_mode)
     p.surr_check_every, p.surr_tol = int(surr_check_every), float(surr_tol)
     p.att_eps, p.att_range = float(att_eps), float(att_range)
+    p.lattice = int(lattice)
     return p
 
 
 class Sim:
     """One lattice on the GPU.  Fields are float64 arrays shaped (nz, ny, nx),
-    vectors (3, nz, ny, nx), populations (19, nz, ny, nx)."""
+    vectors (3, nz, ny, nx), populations (Q, nz, ny, nx) with Q = 19, or 39 for
+    lattice=39 (the third-order lattice, FP64 only)."""
 
     def __init__(self, nx, ny, nz, sigma, tau, accel=(0.0, 0.0, 0.0), wall_lo=0, wall_hi=0,
                  precision="f64", g2_model=HSLB_G2_PAPER, wall_reg=1,
                  force_mode=HSLB_FORCE_EXACT, surr_check_every=50, surr_tol=1e-3, att_eps=0.0,
-                 att_range=0.0):
+                 att_range=0.0, lattice=HSLB_D3Q19):
         prec = {"f64": HSLB_FP64, "f32": HSLB_FP32}[precision] if isinstance(precision, str) \
             else int(precision)
         self.params = make_params(nx, ny, nz, sigma, tau, accel, wall_lo, wall_hi, g2_model,
                                   wall_reg, prec, force_mode, surr_check_every, surr_tol, att_eps,
-                                  att_range)
+                                  att_range, lattice)
+        self.q = 39 if int(lattice) == 39 else 19
         self.shape = (int(nz), int(ny), int(nx))
         self.N = int(nx) * int(ny) * int(nz)
         self.ctx = hslb_create(self.params)
@@ -559,12 +565,12 @@ class Sim:
         return phi.reshape(self.shape)
 
     def get_populations(self):
-        f = np.zeros(19 * self.N)
+        f = np.zeros(self.q * self.N)
         hslb_get_populations(self.ctx, f)
-        return f.reshape((19,) + self.shape)
+        return f.reshape((self.q,) + self.shape)
 
     def set_populations(self, f):
-        f = np.ascontiguousarray(f, dtype=np.float64).reshape(19 * self.N)
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(self.q * self.N)
         hslb_set_populations(self.ctx, f)
 
     def timings(self):

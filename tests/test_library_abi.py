@@ -81,6 +81,26 @@ def test_attraction_is_rejected_with_the_learned_force_and_in_a_batch(lib):
     assert ei.value.code == lib.HSLB_EINVAL
 
 
+@pytest.mark.parametrize("bad", [
+    dict(lattice=27),                                   # no such lattice
+    dict(lattice=39, precision=1),                      # FP64 only
+    dict(lattice=39, nz=6, wall_lo=2, wall_hi=2),       # 2 fluid layers: a link could cross both walls
+    dict(lattice=39, nz=2, wall_lo=0, wall_hi=0, force_mode=2, nx=4, ny=4),
+    dict(lattice=39, nx=32, ny=32, force_mode=1),       # no learned force
+])
+def test_lattice_choice_is_validated(lib, bad):
+    kw = dict(nx=12, ny=12, nz=20, sigma=4, tau=1.0, wall_lo=2, wall_hi=2)
+    kw.update(bad)
+    p = lib.make_params(**kw)
+    with pytest.raises(lib.HslbError) as ei:
+        lib.hslb_create(p)
+    assert ei.value.code == lib.HSLB_EINVAL
+    slits = [lib.make_params(16, 16, 24, 4, 1.0, wall_lo=2, wall_hi=2, lattice=39) for _ in range(2)]
+    with pytest.raises(lib.HslbError) as ei:
+        lib.hslb_batch_create(slits)
+    assert ei.value.code == lib.HSLB_EINVAL
+
+
 def test_trainer_and_network_op_arguments_are_validated(lib):
     with pytest.raises(lib.HslbError) as ei:
         lib.hslb_trainer_create(100, 1000)          # per-snapshot maximum above the capacity
