@@ -54,15 +54,16 @@ def _kernel_source_hash() -> str:
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_collide_slit64x64x136_s8.txt")
+TRAFFIC39_FILE = os.path.join(ROOT, "profiles", "traffic_collide39_slit64x64x136_s8.txt")
 
 
-def _traffic(workload: str):
-    """HBM bytes per launch of the dominant kernel, from the committed
+def _traffic(workload: str, path: str = TRAFFIC_FILE):
+    """HBM bytes per launch of a collide kernel, from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE summary (key = value lines), if it was
     taken on the current kernel source and workload; else None."""
     try:
         rec = {}
-        for line in open(TRAFFIC_FILE):
+        for line in open(path):
             if "=" in line and not line.startswith("#"):
                 k, v = line.split("=", 1)
                 rec[k.strip()] = v.strip()
@@ -218,6 +219,8 @@ def d3q39_leg(hslb, np, wl, n, u, steps: int):
             "step_algorithmic_GBps": round(mlups * 1e6 * STEP39_BYTES / 1e9, 1),
             "collide_us": round(col_s * 1e6, 2), "collide_GBps": round(col_gbps, 1),
             "collide_hbm_frac": round(col_gbps / PEAK_HBM_GBPS, 4),
+            "collide_algorithmic_bytes": COLLIDE39_BYTES * wl.fluid_nodes,
+            "collide_traffic": _traffic(wl.name, TRAFFIC39_FILE),
             "kernels_us": {k: round(v[0] / v[1] * 1e3, 2) for k, v in kt.items()},
             "state_finite_after": finite}
 

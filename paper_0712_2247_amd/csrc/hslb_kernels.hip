@@ -1276,22 +1276,47 @@ __device__ __forceinline__ void herm_acc(double d, double a2[6], double a3[10])
     if constexpr (C39X[I] * C39Y[I] * C39Z[I] != 0) a3[9] += (x * y * z) * d;
 }
 
-// The projection of velocity I: h2 : a2 / (2 s^2) + h3 : a3 / (6 s^3), the
-// full contractions written over the distinct components with their
-// multiplicities (2 for xy-type in h2; 3 for xxy-type, 6 for xyz in h3).
-template <int I>
-__device__ __forceinline__ double herm_proj(const double a2[6], const double a3[10])
+// The projection h2(c) : a2 / (2 s^2) + h3(c) : a3 / (6 s^3) as a cubic
+// polynomial in c, P(c) = K0 + K1.c + c.K2.c + K3 : ccc, with
+//   K0 = -tr a2 / (2 s),  K1_a = -(sum_b a3_abb) / (2 s^2),
+//   K2_aa = a2_aa / (2 s^2), K2_ab = a2_ab / s^2 (a < b, both orders),
+//   K3_aaa = a3_aaa / (6 s^3), K3_aab = a3_aab / (2 s^3) (three orders),
+//   K3_xyz = a3_xyz / s^3 (six orders);
+// k[] holds (K0, K1 x y z, K2 xx yy zz xy xz yz, K3 xxx yyy zzz xxy xxz xyy yyz xzz yzz xyz).
+__device__ __forceinline__ void proj_coeffs(const double a2[6], const double a3[10], double k[20])
 {
     constexpr double s = CS2_39;
-    constexpr double x = C39X[I], y = C39Y[I], z = C39Z[I];
-    const double p2 = (x * x - s) * a2[0] + (y * y - s) * a2[1] + (z * z - s) * a2[2] +
-                      2.0 * ((x * y) * a2[3] + (x * z) * a2[4] + (y * z) * a2[5]);
-    const double p3 = (x * x * x - 3.0 * s * x) * a3[0] + (y * y * y - 3.0 * s * y) * a3[1] +
-                      (z * z * z - 3.0 * s * z) * a3[2] +
-                      3.0 * ((x * x * y - s * y) * a3[3] + (x * x * z - s * z) * a3[4] + (x * y * y - s * x) * a3[5] +
-                             (y * y * z - s * z) * a3[6] + (x * z * z - s * x) * a3[7] + (y * z * z - s * y) * a3[8]) +
-                      6.0 * (x * y * z) * a3[9];
-    return p2 * (1.0 / (2.0 * s * s)) + p3 * (1.0 / (6.0 * s * s * s));
+    constexpr double i2 = 1.0 / (2.0 * s * s), i3 = 1.0 / (s * s * s);
+    k[0] = -(a2[0] + a2[1] + a2[2]) * (1.0 / (2.0 * s));
+    k[1] = -(a3[0] + a3[5] + a3[7]) * i2;
+    k[2] = -(a3[3] + a3[1] + a3[8]) * i2;
+    k[3] = -(a3[4] + a3[6] + a3[2]) * i2;
+    k[4] = a2[0] * i2;
+    k[5] = a2[1] * i2;
+    k[6] = a2[2] * i2;
+    k[7] = a2[3] * (2.0 * i2);
+    k[8] = a2[4] * (2.0 * i2);
+    k[9] = a2[5] * (2.0 * i2);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) k[10 + m] = a3[m] * (i3 / 6.0);
+#pragma unroll
+    for (int m = 3; m < 9; ++m) k[10 + m] = a3[m] * (i3 / 2.0);
+    k[19] = a3[9] * i3;
+}
+
+template <int I>
+__device__ __forceinline__ double proj_of(const double k[20])
+{
+    constexpr int x = C39X[I], y = C39Y[I], z = C39Z[I];
+    double p = k[0];
+    if constexpr (x != 0) p += x * k[1] + (x * x) * k[4] + (x * x * x) * k[10];
+    if constexpr (y != 0) p += y * k[2] + (y * y) * k[5] + (y * y * y) * k[11];
+    if constexpr (z != 0) p += z * k[3] + (z * z) * k[6] + (z * z * z) * k[12];
+    if constexpr (x * y != 0) p += (x * y) * k[7] + (x * x * y) * k[13] + (x * y * y) * k[15];
+    if constexpr (x * z != 0) p += (x * z) * k[8] + (x * x * z) * k[14] + (x * z * z) * k[17];
+    if constexpr (y * z != 0) p += (y * z) * k[9] + (y * y * z) * k[16] + (y * z * z) * k[18];
+    if constexpr (x * y * z != 0) p += (x * y * z) * k[19];
+    return p;
 }
 
 // Collide and stream of velocity I from node (x, y, z): post-collision value
@@ -1301,11 +1326,11 @@ __device__ __forceinline__ double herm_proj(const double a2[6], const double a3[
 // node's distance to the plane, mirrored z.
 template <int I>
 __device__ __forceinline__ void out39(const LatticeDev &L, double *__restrict__ fout, int x, int y, int z, double fe,
-                                      double om, const double a2[6], const double a3[10], const double F[3])
+                                      double om, const double K[20], const double F[3])
 {
     constexpr int cx = C39X[I], cy = C39Y[I], cz = C39Z[I];
     const double src = w39(I) * (cx * F[0] + cy * F[1] + cz * F[2]) * (1.0 / CS2_39);
-    const double fp = fe + om * (w39(I) * herm_proj<I>(a2, a3)) + src;
+    const double fp = fe + om * (w39(I) * proj_of<I>(K)) + src;
     int xt = x + cx, yt = y + cy, zt = z + cz, k = I;
     if constexpr (cz != 0) {
         if (L.zper) {
@@ -1356,12 +1381,21 @@ __device__ __forceinline__ void emit39(const LatticeDev &L, double *__restrict__
                                       const double a3[10], std::integer_sequence<int, I...>)
 {
     const double uu_s = (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / CS2_39;
-    (out39<I>(L, fout, x, y, z, feq39_of<I>(n, u, uu_s), om, a2, a3, F), ...);
+    double k[20];
+    proj_coeffs(a2, a3, k);
+    (out39<I>(L, fout, x, y, z, feq39_of<I>(n, u, uu_s), om, k, F), ...);
 }
+
+// Waves per SIMD the 39-velocity collide kernel is compiled for: the
+// compiler's ~246 VGPRs allow 2; capping at 3 or 4 spills and measured 30 %
+// and 100 % slower.
+#ifndef HSLB_COLLIDE39_WAVES
+#define HSLB_COLLIDE39_WAVES 2
+#endif
 
 // 1-D grid over (fluid layer, chunk of 256 nodes of the layer), as k_collide.
 template <int SIG>
-__global__ __launch_bounds__(256) void k_collide39(LatticeDev L, StepConst sc, const double *__restrict__ chi,
+__global__ __launch_bounds__(256, HSLB_COLLIDE39_WAVES) void k_collide39(LatticeDev L, StepConst sc, const double *__restrict__ chi,
                                                    const double *__restrict__ fin, double *__restrict__ fout,
                                                    Fields<double> fld, int cpp)
 {
