@@ -49,7 +49,7 @@ class _Params(ctypes.Structure):
         ("g2_model", ctypes.c_int32), ("wall_reg", ctypes.c_int32),
         ("force_mode", ctypes.c_int32),
         ("att_eps", ctypes.c_double), ("att_range", ctypes.c_double),
-        ("lattice", ctypes.c_int32),
+        ("lattice", ctypes.c_int32), ("thermal", ctypes.c_int32),
     ]
 
 
@@ -75,6 +75,10 @@ def _load():
                  "hsref_step_with_force", "hsref_attraction_potential"):
         getattr(lib, name).argtypes = [ctypes.c_void_p, d]
         getattr(lib, name).restype = ctypes.c_int
+    lib.hsref_init_thermal.argtypes = [ctypes.c_void_p, d, d, d]
+    lib.hsref_init_thermal.restype = ctypes.c_int
+    lib.hsref_thermal_fields.argtypes = [ctypes.c_void_p, d, d]
+    lib.hsref_thermal_fields.restype = ctypes.c_int
     lib.hsref_set_solid.argtypes = [ctypes.c_void_p, P(ctypes.c_uint8)]
     lib.hsref_set_solid.restype = ctypes.c_int
     lib.hsref_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
@@ -177,7 +181,7 @@ class Oracle:
 
     def __init__(self, nx, ny, nz, sigma, tau, accel=(0.0, 0.0, 0.0), wall_lo=0, wall_hi=0,
                  g2_model=G2_PAPER, wall_reg=1, force_mode=FORCE_EXACT, att_eps=0.0, att_range=0.0,
-                 lattice=19):
+                 lattice=19, thermal=0):
         self._lib = _load()
         p = _Params()
         p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
@@ -188,6 +192,7 @@ class Oracle:
         p.g2_model, p.wall_reg, p.force_mode = int(g2_model), int(wall_reg), int(force_mode)
         p.att_eps, p.att_range = float(att_eps), float(att_range)
         p.lattice = int(lattice)
+        p.thermal = int(thermal)
         self.params = p
         self.shape = (int(nz), int(ny), int(nx))
         self.N = int(nx) * int(ny) * int(nz)
@@ -212,12 +217,27 @@ class Oracle:
         self._chk(self._lib.hsref_set_solid(self._ctx, m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))),
                   "set_solid")
 
-    def init(self, n, u=None):
+    def init(self, n, u=None, T=None):
+        """Equilibrium populations of (n, u), and of T in a thermal context
+        (T None: the lattice temperature 2/3 everywhere)."""
         n = np.ascontiguousarray(n, dtype=np.float64).reshape(self.N)
         if u is None:
             u = np.zeros(3 * self.N)
         u = np.ascontiguousarray(u, dtype=np.float64).reshape(3 * self.N)
-        self._chk(self._lib.hsref_init(self._ctx, _dptr(n), _dptr(u)), "init")
+        if self.params.thermal:
+            Tp = None if T is None else _dptr(np.ascontiguousarray(T, dtype=np.float64).reshape(self.N))
+            self._chk(self._lib.hsref_init_thermal(self._ctx, _dptr(n), _dptr(u), Tp), "init_thermal")
+        else:
+            if T is not None:
+                raise ValueError("a temperature field needs thermal=1")
+            self._chk(self._lib.hsref_init(self._ctx, _dptr(n), _dptr(u)), "init")
+
+    def thermal_fields(self):
+        """Temperature T and energy source C^(2) [nz, ny, nx] of the current state."""
+        T = np.zeros(self.N)
+        Q = np.zeros(self.N)
+        self._chk(self._lib.hsref_thermal_fields(self._ctx, _dptr(T), _dptr(Q)), "thermal_fields")
+        return T.reshape(self.shape), Q.reshape(self.shape)
 
     def step(self, nsteps=1):
         self._chk(self._lib.hsref_step(self._ctx, int(nsteps)), "step")

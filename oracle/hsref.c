@@ -80,6 +80,31 @@
  *     least 3 fluid layers so that no link crosses both walls; solid masks are
  *     not available on this lattice.
  *
+ * Optional non-isothermal terms (thermal = 1, on the third-order lattice only):
+ * the temperature term of C^(1) and the energy source C^(2) that the paper
+ * derives next to equation (12) and then drops by taking T constant.  Readings,
+ * all in the design notes:
+ *   - k_B = m = 1; n T = (1/3) sum_i f_i |c_i - u|^2; solid nodes carry T = 0;
+ *   - v_T^2 = T(r), the receiving node's temperature, in C^(1)'s prefactor, in
+ *     kappa = 2/(v_T sqrt(pi)), and in both temperature terms; the garbled
+ *     T(r + s_hat) is T(r + sigma s_hat), the partner of the pair;
+ *   - C^(1) = -v_T^2 sigma^2 4 pi n sum_q W_q s_q sum_k alpha_k G_k
+ *             [n' - chi kappa s.(j' - n' u) + n' (T' - T) / (2 v_T^2)],
+ *     C^(2) = v_T^2 sigma^2 4 pi n sum_q W_q sum_k alpha_k G_k
+ *             [-s.(j' - n' u) / 2 + n' (T' - T) / (sqrt(pi) v_T)],
+ *     with the same quadrature, interpolation and midpoint closure as C^(1)
+ *     (the wall factor only on C^(1)'s current term, as before); C^(2) is the
+ *     energy gained per unit volume and step;
+ *   - the equilibrium is the third-order Hermite expansion of the Maxwellian at
+ *     (n, u, T) about the lattice temperature T0 = 2/3 (xi = c/sqrt(T0),
+ *     theta = T/T0): w n [1 + xi.u~ + ((xi.u~)^2 - u~^2 + (theta - 1)(xi^2 - 3))/2
+ *     + (xi.u~)((xi.u~)^2 - 3 u~^2 + 3 (theta - 1)(xi^2 - 5))/6], u~ = u/sqrt(T0);
+ *   - the sources are the force's Hermite terms through second order and the
+ *     energy source on the trace of h^(2):
+ *     w_i [c.F/T0 + ((c.F)(c.u) - T0 F.u)/T0^2 + C2 (c^2 - 3 T0)/(3 T0^2)],
+ *     so that momentum gains F and energy gains F.u + C2;
+ *   - the same regularised collision; bounce-back walls are adiabatic.
+ *
  * Optional solid mask (hsref_set_solid): any node may be solid, beyond the wall
  * layers.  Solid nodes carry n = j = 0 and take part in nothing; a population
  * heading into a solid node returns reversed (halfway bounce-back), as at the
@@ -116,6 +141,7 @@ typedef struct {
     double att_eps;           /* depth of the Gaussian attraction (0: off) */
     double att_range;         /* its range in lattice units */
     int32_t lattice;          /* 19 (or 0): D3Q19; 39: the third-order lattice */
+    int32_t thermal;          /* 1: temperature field and energy source (lattice 39) */
 } hsref_params;
 
 /* D3Q19 velocities, the discrete set of section "Methods and Results". */
@@ -189,6 +215,8 @@ struct hsref_ctx {
     double *eb;      /* [N] coarse-grained packing fraction */
     double *F;       /* [3][N] total force */
     double *phi;     /* [N] mean-field attraction potential (att_eps != 0) */
+    double *T;       /* [N] temperature (thermal) */
+    double *Q;       /* [N] energy source C^(2) (thermal) */
     int att_R;       /* its cube half-width, ceil(3 att_range) */
     uint8_t *solid;  /* [N] solid mask (NULL: only the wall layers are solid) */
     double *chi_n;   /* [N] per-node wall factor when a mask is set */
@@ -351,6 +379,7 @@ hsref_ctx *hsref_create(const hsref_params *p)
     if (p->lattice != 0 && p->lattice != 19 && p->lattice != 39) return NULL;
     /* no link of the third-order lattice may cross both walls */
     if (p->lattice == 39 && p->wall_lo > 0 && p->nz - p->wall_lo - p->wall_hi < 3) return NULL;
+    if (p->thermal != 0 && (p->thermal != 1 || p->lattice != 39)) return NULL;
     hsref_ctx *c = (hsref_ctx *)calloc(1, sizeof(hsref_ctx));
     if (!c) return NULL;
     c->p = *p;
@@ -390,10 +419,13 @@ hsref_ctx *hsref_create(const hsref_params *p)
     c->eb = calloc(N, sizeof(double));
     c->F = calloc(3 * N, sizeof(double));
     c->phi = calloc(N, sizeof(double));
+    c->T = calloc(N, sizeof(double));
+    c->Q = calloc(N, sizeof(double));
     c->att_R = p->att_eps != 0.0 ? (int)ceil(3.0 * p->att_range) : 0;
-    if (!c->ball || !c->chi || !c->f || !c->fs || !c->n || !c->j || !c->u || !c->eb || !c->F || !c->phi) {
+    if (!c->ball || !c->chi || !c->f || !c->fs || !c->n || !c->j || !c->u || !c->eb || !c->F || !c->phi ||
+        !c->T || !c->Q) {
         free(c->ball); free(c->chi); free(c->f); free(c->fs); free(c->n); free(c->j);
-        free(c->u); free(c->eb); free(c->F); free(c->phi); free(c);
+        free(c->u); free(c->eb); free(c->F); free(c->phi); free(c->T); free(c->Q); free(c);
         return NULL;
     }
     return c;
@@ -404,6 +436,7 @@ void hsref_destroy(hsref_ctx *c)
     if (!c) return;
     free(c->ball); free(c->chi); free(c->f); free(c->fs); free(c->n); free(c->j);
     free(c->u); free(c->eb); free(c->F); free(c->phi); free(c->solid); free(c->chi_n);
+    free(c->T); free(c->Q);
     free(c);
 }
 
@@ -417,7 +450,7 @@ static void phase_moments(hsref_ctx *c)
 #pragma omp parallel for schedule(static) if (c->N >= PAR_MIN_NODES)
     for (int z = 0; z < c->p.nz; ++z) {
         for (int64_t id = z * plane; id < (z + 1) * plane; ++id) {
-            double n = 0.0, j[3] = {0.0, 0.0, 0.0};
+            double n = 0.0, j[3] = {0.0, 0.0, 0.0}, e = 0.0;
             if (fluid_node(c, id)) {
                 for (int i = 0; i < c->q; ++i) {
                     double fi = c->f[(int64_t)i * N + id];
@@ -425,13 +458,18 @@ static void phase_moments(hsref_ctx *c)
                     j[0] += c->cv[i][0] * fi;
                     j[1] += c->cv[i][1] * fi;
                     j[2] += c->cv[i][2] * fi;
+                    e += (c->cv[i][0] * c->cv[i][0] + c->cv[i][1] * c->cv[i][1] + c->cv[i][2] * c->cv[i][2]) * fi;
                 }
             }
             c->n[id] = n;
+            double uu = 0.0;
             for (int a = 0; a < 3; ++a) {
                 c->j[a * N + id] = j[a];
                 c->u[a * N + id] = n != 0.0 ? j[a] / n : 0.0;
+                uu += c->u[a * N + id] * c->u[a * N + id];
             }
+            /* n T = (1/3) sum f |c - u|^2 = (sum f c^2 - n u^2) / 3 */
+            if (c->p.thermal) c->T[id] = n != 0.0 ? (e / n - uu) / 3.0 : 0.0;
         }
     }
 }
@@ -526,22 +564,28 @@ static void phase_force(hsref_ctx *c)
     const double sig = (double)c->p.sigma;
     const double pref = -vt2 * sig * sig * 4.0 * M_PI;
     const int hs_on = (c->p.force_mode != 2);
+    const int th = c->p.thermal;
 #pragma omp parallel for schedule(static) if (c->N >= PAR_MIN_NODES)
     for (int z = 0; z < c->p.nz; ++z) {
         for (int y = 0; y < c->p.ny; ++y) {
             for (int x = 0; x < c->p.nx; ++x) {
                 int64_t id = z * plane + (int64_t)y * c->p.nx + x;
                 double Fv[3] = {0.0, 0.0, 0.0};
+                double Qv = 0.0;
                 if (fluid_node(c, id)) {
                     double nr = c->n[id];
                     double ur[3] = {c->u[id], c->u[N + id], c->u[2 * N + id]};
-                    double S[3] = {0.0, 0.0, 0.0};
+                    double S[3] = {0.0, 0.0, 0.0}, Qs = 0.0;
+                    /* thermal: v_T^2 = T(r) in the prefactor, kappa and the temperature terms */
+                    const double Tr = th ? c->T[id] : 0.0;
+                    const double kap = th ? 2.0 / (sqrt(Tr) * sqrt(M_PI)) : kappa;
+                    const double prf = th ? -Tr * sig * sig * 4.0 * M_PI : pref;
                     if (hs_on) {
                         for (int pr = 0; pr < NSHELL / 2; ++pr) {
-                            double Sp[3] = {0.0, 0.0, 0.0};
+                            double Sp[3] = {0.0, 0.0, 0.0}, Qp = 0.0;
                             for (int m = 0; m < 2; ++m) {
                                 const shell_dir *e = &c->shell[2 * pr + m];
-                                double acc = 0.0;
+                                double acc = 0.0, accq = 0.0;
                                 for (int k = 0; k < e->ncorner; ++k) {
                                     int64_t id2 = node_at(c, x + e->d[k][0], y + e->d[k][1], z + e->d[k][2]);
                                     if (!fluid_node(c, id2)) continue; /* n = j = 0 there */
@@ -552,13 +596,23 @@ static void phase_force(hsref_ctx *c)
                                     double cur = 0.0;
                                     for (int a = 0; a < 3; ++a)
                                         cur += e->s[a] * (c->j[a * N + id2] - n2 * ur[a]);
-                                    acc += e->alpha[k] * G * (n2 - chi_at(c, id, z) * kappa * cur);
+                                    if (!th) {
+                                        acc += e->alpha[k] * G * (n2 - chi_at(c, id, z) * kappa * cur);
+                                    } else {
+                                        const double dT = c->T[id2] - Tr;
+                                        acc += e->alpha[k] * G *
+                                               (n2 - chi_at(c, id, z) * kap * cur + n2 * dT / (2.0 * Tr));
+                                        accq += e->alpha[k] * G * (-0.5 * cur + n2 * dT / (sqrt(M_PI) * sqrt(Tr)));
+                                    }
                                 }
                                 for (int a = 0; a < 3; ++a) Sp[a] += e->W * e->s[a] * acc;
+                                Qp += e->W * accq;
                             }
                             for (int a = 0; a < 3; ++a) S[a] += Sp[a];
+                            Qs += Qp;
                         }
                     }
+                    Qv = -prf * nr * Qs;  /* C^(2) = v_T^2 sigma^2 4 pi n sum ... */
                     double Fa[3] = {0.0, 0.0, 0.0};
                     if (c->att_R > 0) {
                         /* central differences of Phi; r +- e_a lies inside the array at a fluid node */
@@ -570,9 +624,10 @@ static void phase_force(hsref_ctx *c)
                             Fa[a] = -nr * (c->phi[ip] - c->phi[im]) / 2.0;
                         }
                     }
-                    for (int a = 0; a < 3; ++a) Fv[a] = pref * nr * S[a] + Fa[a] + nr * c->p.accel[a];
+                    for (int a = 0; a < 3; ++a) Fv[a] = prf * nr * S[a] + Fa[a] + nr * c->p.accel[a];
                 }
                 for (int a = 0; a < 3; ++a) c->F[a * N + id] = Fv[a];
+                c->Q[id] = th ? Qv : 0.0;
             }
         }
     }
@@ -587,6 +642,23 @@ static double feq39(const hsref_ctx *c, int i, double n, const double u[3])
     const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     const double xi = (c->cv[i][0] * u[0] + c->cv[i][1] * u[1] + c->cv[i][2] * u[2]) / cs2;
     return c->w[i] * n * (1.0 + xi + 0.5 * xi * xi - uu / (2.0 * cs2) + xi * xi * xi / 6.0 - xi * uu / (2.0 * cs2));
+}
+
+/* Thermal: the Maxwellian at (n, u, T) expanded through h^(3) about T0 = v_T^2
+ * of the lattice (xi = c/sqrt(T0), u~ = u/sqrt(T0), theta = T/T0):
+ * w n [1 + xi.u~ + ((xi.u~)^2 - u~^2 + (theta - 1)(xi^2 - 3))/2
+ *      + (xi.u~)((xi.u~)^2 - 3 u~^2 + 3 (theta - 1)(xi^2 - 5))/6]. */
+static double feq39_thermal(const hsref_ctx *c, int i, double n, const double u[3], double T)
+{
+    const double T0 = c->cs2;
+    const int *v = c->cv[i];
+    const double xu = (v[0] * u[0] + v[1] * u[1] + v[2] * u[2]) / T0;          /* xi.u~ */
+    const double uu = (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / T0;          /* u~^2 */
+    const double xx = (double)(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) / T0;  /* xi^2 */
+    const double th1 = T / T0 - 1.0;
+    return c->w[i] * n *
+           (1.0 + xu + 0.5 * (xu * xu - uu + th1 * (xx - 3.0)) +
+            xu * (xu * xu - 3.0 * uu + 3.0 * th1 * (xx - 5.0)) / 6.0);
 }
 
 /* Hermite tensors of velocity i: h2_ab = c_a c_b - v_T^2 d_ab and
@@ -624,8 +696,11 @@ static void phase_collide_stream39(hsref_ctx *c)
                 double u[3] = {c->u[id], c->u[N + id], c->u[2 * N + id]};
                 double F[3] = {c->F[id], c->F[N + id], c->F[2 * N + id]};
                 double feq[QMAX], a2[3][3] = {{0.0}}, a3[3][3][3] = {{{0.0}}};
+                const int th = c->p.thermal;
+                const double Tn = th ? c->T[id] : 0.0, Qn = th ? c->Q[id] : 0.0;
+                const double Fu = F[0] * u[0] + F[1] * u[1] + F[2] * u[2];
                 for (int i = 0; i < q; ++i) {
-                    feq[i] = feq39(c, i, n, u);
+                    feq[i] = th ? feq39_thermal(c, i, n, u, Tn) : feq39(c, i, n, u);
                     double fneq = c->f[(int64_t)i * N + id] - feq[i];
                     for (int a = 0; a < 3; ++a)
                         for (int b = 0; b < 3; ++b) {
@@ -642,7 +717,15 @@ static void phase_collide_stream39(hsref_ctx *c)
                         }
                     double fneq_reg = c->w[i] * (p2 / (2.0 * cs2 * cs2) + p3 / (6.0 * cs2 * cs2 * cs2));
                     double cF = c->cv[i][0] * F[0] + c->cv[i][1] * F[1] + c->cv[i][2] * F[2];
-                    double fpost = feq[i] + (1.0 - 1.0 / tau) * fneq_reg + c->w[i] * cF / cs2;
+                    double src = cF / cs2;
+                    if (th) {
+                        /* the force's second Hermite order and the energy source on the trace of h^(2) */
+                        const int *v = c->cv[i];
+                        const double cu = v[0] * u[0] + v[1] * u[1] + v[2] * u[2];
+                        const double c2 = (double)(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                        src += (cF * cu - cs2 * Fu) / (cs2 * cs2) + Qn * (c2 - 3.0 * cs2) / (3.0 * cs2 * cs2);
+                    }
+                    double fpost = feq[i] + (1.0 - 1.0 / tau) * fneq_reg + c->w[i] * src;
                     const int *v = c->cv[i];
                     int xt = x + v[0], yt = y + v[1], zt = z + v[2], k = i;
                     if (!c->zperiodic) {
@@ -733,11 +816,28 @@ static int check_fields(const hsref_ctx *c, const double *n, const double *u)
     return 0;
 }
 
+static int init_fields(hsref_ctx *c, const double *n, const double *u, const double *T);
+
 /* Initial populations: the local equilibrium (11) of the given fields. */
 int hsref_init(hsref_ctx *c, const double *n, const double *u)
 {
+    return init_fields(c, n, u, NULL);
+}
+
+/* Thermal contexts: the equilibrium at (n, u, T); T NULL means T0 everywhere. */
+int hsref_init_thermal(hsref_ctx *c, const double *n, const double *u, const double *T)
+{
+    if (!c || !c->p.thermal) return -1;
+    return init_fields(c, n, u, T);
+}
+
+static int init_fields(hsref_ctx *c, const double *n, const double *u, const double *T)
+{
     if (!c || !n) return -1;
     if (check_fields(c, n, u)) return -1;
+    if (T)
+        for (int64_t id = 0; id < c->N; ++id)
+            if (fluid_node(c, id) && !(isfinite(T[id]) && T[id] > 0.0)) return -1;
     const int64_t N = c->N;
     memset(c->f, 0, sizeof(double) * (size_t)c->q * (size_t)N);
     for (int64_t id = 0; id < N; ++id) {
@@ -746,7 +846,9 @@ int hsref_init(hsref_ctx *c, const double *n, const double *u)
         if (u)
             for (int a = 0; a < 3; ++a) uu[a] = u[a * N + id];
         if (c->q == 39) {
-            for (int i = 0; i < c->q; ++i) c->f[(int64_t)i * N + id] = feq39(c, i, n[id], uu);
+            for (int i = 0; i < c->q; ++i)
+                c->f[(int64_t)i * N + id] = c->p.thermal ? feq39_thermal(c, i, n[id], uu, T ? T[id] : c->cs2)
+                                                         : feq39(c, i, n[id], uu);
             continue;
         }
         double u2 = uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2];
@@ -970,3 +1072,17 @@ int hsref_lattice_q(int q, int *c, double *w)
 
 /* Number of velocities of the context's lattice. */
 int hsref_q(const hsref_ctx *c) { return c ? c->q : -1; }
+
+/* Temperature T[N] and energy source C^(2) Q[N] at the current state (thermal
+ * contexts; Q needs the force phase, run here). */
+int hsref_thermal_fields(hsref_ctx *c, double *T, double *Q)
+{
+    if (!c || !c->p.thermal) return -1;
+    phase_moments(c);
+    if (c->p.force_mode != 2) phase_eta_bar(c);
+    if (c->att_R > 0) phase_attraction(c);
+    phase_force(c);
+    if (T) memcpy(T, c->T, sizeof(double) * (size_t)c->N);
+    if (Q) memcpy(Q, c->Q, sizeof(double) * (size_t)c->N);
+    return 0;
+}

@@ -150,3 +150,61 @@ class Grid:
                         F[a, z, y, x] = -VT2 * self.sigma ** 2 * 4.0 * math.pi * nr * S[a] \
                             + nr * accel[a]
         return F
+
+
+def thermal_force(grid: Grid, T, accel=(0.0, 0.0, 0.0)):
+    """The non-isothermal C^(1) and the energy source C^(2) (readings in the
+    oracle's header: v_T^2 = T(r) at the receiving node, the partner's T at
+    r + sigma s_hat), by the same geometry as Grid.force: returns (F, Q)."""
+    T = np.asarray(T, dtype=np.float64)
+    F = np.zeros((3, grid.nz, grid.ny, grid.nx))
+    Q = np.zeros((grid.nz, grid.ny, grid.nx))
+    eb = {}
+
+    def ebar(x, y, z):
+        key = grid.wrap(x, y, z)
+        if key not in eb:
+            eb[key] = grid.eta_bar(*key)
+        return eb[key]
+
+    def temp(x, y, z):
+        x, y, z = grid.wrap(x, y, z)
+        return T[z, y, x]
+
+    for z in range(grid.nz):
+        if grid.solid(z):
+            continue
+        for y in range(grid.ny):
+            for x in range(grid.nx):
+                nr, jr = grid.dens(x, y, z)
+                ur = [jr[a] / nr if nr != 0 else 0.0 for a in range(3)]
+                Tr = T[z, y, x]
+                vt = math.sqrt(Tr)
+                kap = 2.0 / (vt * math.sqrt(math.pi))
+                S = [0.0, 0.0, 0.0]
+                Qs = 0.0
+                for W, s in quadrature_points():
+                    acc = accq = 0.0
+                    for d, al in corners(grid.sigma, s):
+                        cx, cy, cz = x + d[0], y + d[1], z + d[2]
+                        nc, jc = grid.dens(cx, cy, cz)
+                        if nc == 0.0 and jc == (0.0, 0.0, 0.0):
+                            continue
+                        mids = []
+                        for r0, c0 in ((x, cx), (y, cy), (z, cz)):
+                            h = (r0 + c0) / 2.0
+                            mids.append(sorted({math.floor(h), math.ceil(h)}))
+                        vals = [ebar(mx, my, mz) for mz in mids[2] for my in mids[1] for mx in mids[0]]
+                        G = g2(sum(vals) / len(vals), grid.g2_model)
+                        cur = sum(s[a] * (jc[a] - nc * ur[a]) for a in range(3))
+                        dT = temp(cx, cy, cz) - Tr
+                        acc += al * G * (nc - grid.chi(z) * kap * cur + nc * dT / (2.0 * Tr))
+                        accq += al * G * (-0.5 * cur + nc * dT / (math.sqrt(math.pi) * vt))
+                    for a in range(3):
+                        S[a] += W * s[a] * acc
+                    Qs += W * accq
+                pre = Tr * grid.sigma ** 2 * 4.0 * math.pi * nr
+                for a in range(3):
+                    F[a, z, y, x] = -pre * S[a] + nr * accel[a]
+                Q[z, y, x] = pre * Qs
+    return F, Q
