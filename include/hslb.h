@@ -117,6 +117,21 @@ typedef struct {
     double att_eps;
     double att_range;
     int32_t lattice;          /* HSLB_D3Q19 (0) or HSLB_D3Q39 */
+    /* 1: the non-isothermal terms the paper derives beside equation (12) and
+     * then drops by taking T constant (section "Methods and Results"), on the
+     * 39-velocity lattice only.  k_B = m = 1; the temperature is
+     * n T = (1/3) sum_i f_i |c_i - u|^2 and v_T^2 = T(r) at the receiving node.
+     *   C^(1) = -v_T^2 sigma^2 4 pi n sum_q W_q s_q sum_k alpha_k G_k
+     *           [n' - chi kappa s.(j' - n' u) + n' (T' - T) / (2 v_T^2)],
+     *   C^(2) = v_T^2 sigma^2 4 pi n sum_q W_q sum_k alpha_k G_k
+     *           [-s.(j' - n' u) / 2 + n' (T' - T) / (sqrt(pi) v_T)],
+     * with the quadrature, interpolation and midpoint closure of the isothermal
+     * term; C^(2) is the energy gained per unit volume and step.  The
+     * equilibrium is the Maxwellian at (n, u, T) expanded through h^(3) about
+     * T0 = 2/3; the sources are w_i [c.F/T0 + ((c.F)(c.u) - T0 F.u)/T0^2 +
+     * C2 (c^2 - 3 T0)/(3 T0^2)], so that momentum gains F and energy
+     * F.u + C2.  Walls are adiabatic (bounce-back). */
+    int32_t thermal;
 } hslb_params;
 
 typedef struct hslb_ctx hslb_ctx;
@@ -142,6 +157,16 @@ int hslb_set_stream(hslb_ctx *ctx, void *hip_stream);
  * are ignored and treated as 0.  Errors: HSLB_EINVAL if a fluid n is negative
  * or non-finite or a fluid u non-finite. */
 int hslb_init(hslb_ctx *ctx, const double *n, const double *u);
+
+/* Thermal contexts (hslb_params.thermal = 1): the initial state at the
+ * equilibrium of (n, u, T), T[N] positive on fluid nodes (NULL: T0 = 2/3
+ * everywhere; hslb_init does the same).  Errors: HSLB_ESTATE on a context
+ * that is not thermal, HSLB_EINVAL as hslb_init or for a non-positive T. */
+int hslb_init_thermal(hslb_ctx *ctx, const double *n, const double *u, const double *T);
+
+/* Thermal contexts: temperature T[N] and energy source C^(2) Q[N] of the
+ * current state (0 on solid layers); either pointer may be NULL, not both. */
+int hslb_thermal_fields(hslb_ctx *ctx, double *T, double *Q);
 
 /* Advance nsteps time steps of equation (10): moments, coarse-grained density,
  * midpoint contact values, hard-sphere force (12) (plus the mean-field

@@ -140,6 +140,17 @@ public:
     }
     virtual int get_pop(double *f) = 0;
     virtual int set_pop(const double *f) = 0;
+    // thermal 39-velocity contexts only
+    virtual int init_thermal(const double *n, const double *u, const double *T)
+    {
+        (void)n, (void)u, (void)T;
+        return fail_state("not a thermal context");
+    }
+    virtual int thermal_fields(double *T, double *Q)
+    {
+        (void)T, (void)Q;
+        return fail_state("not a thermal context");
+    }
     virtual int sync() = 0;
     virtual int timings(double *ms, double *mlups) = 0;
     virtual void set_stream(hipStream_t s) = 0;
@@ -286,6 +297,7 @@ public:
         L_.fld_stride = (L_.plane * (p_.nz + 2 * L_.hz) + 63) / 64 * 64;
         sigma_ = sig;
         q_ = (p_.lattice == HSLB_D3Q39) ? Q39 : NQ;
+        thermal_ = (p_.thermal == 1);
 
         sc_.tau = p_.tau;
         for (int a = 0; a < 3; ++a) sc_.g[a] = p_.accel[a];
@@ -310,7 +322,8 @@ public:
         if (hipMalloc(&f_[0], popb) != hipSuccess || hipMalloc(&f_[1], popb) != hipSuccess)
             return fail(err, HSLB_ENOMEM, "population buffers (%zu bytes each) do not fit", popb);
         // n, j, eta_bar, the 7 contact-value slots and sigma/2 + 1 row-sum fields
-        const size_t nfld = (size_t)(1 + 4 + 1 + NGSLOT + sig / 2 + 1) * L_.fld_stride;
+        // (plus the temperature in thermal contexts)
+        const size_t nfld = (size_t)(1 + 4 + 1 + NGSLOT + sig / 2 + 1 + (thermal_ ? 1 : 0)) * L_.fld_stride;
         if (hipMalloc(&fld_mem_, sizeof(TM) * nfld) != hipSuccess)
             return fail(err, HSLB_ENOMEM, "moment fields do not fit");
         HIP_TRY(hipMemset(fld_mem_, 0, sizeof(TM) * nfld));
@@ -321,6 +334,7 @@ public:
         fld_.eb = fld_mem_ + 5 * (size_t)L_.fld_stride;
         fld_.G = fld_mem_ + 6 * (size_t)L_.fld_stride;
         rs_ = fld_mem_ + (size_t)(6 + NGSLOT) * L_.fld_stride;
+        fld_.T = thermal_ ? rs_ + (size_t)(sig / 2 + 1) * L_.fld_stride : nullptr;
 
         std::vector<double> chi(p_.nz, 1.0);
         if (!L_.zper && p_.wall_reg) {
@@ -408,7 +422,15 @@ public:
         return HSLB_OK;
     }
 
-    int init(const double *n, const double *u) override
+    int init(const double *n, const double *u) override { return init_fields(n, u, nullptr); }
+
+    int init_thermal(const double *n, const double *u, const double *T) override
+    {
+        if (!thermal_) return fail(err, HSLB_ESTATE, "not a thermal context");
+        return init_fields(n, u, T);
+    }
+
+    int init_fields(const double *n, const double *u, const double *T)
     {
         const int N = L_.N;
         std::vector<double> nm, um;
@@ -435,14 +457,17 @@ public:
                 for (int a = 0; a < 3; ++a)
                     if (!std::isfinite(u[(size_t)a * N + id]))
                         return fail(err, HSLB_EINVAL, "velocity at node %d is not finite", id);
+            if (T && !(std::isfinite(T[id]) && T[id] > 0.0))
+                return fail(err, HSLB_EINVAL, "temperature at node %d is not positive and finite", id);
             msum += n[id];
             ++nfl;
         }
         mass0_ = msum;
         double *d;
-        int rc = io(sizeof(double) * (4 + q_) * (size_t)N, &d);
+        int rc = io(sizeof(double) * (5 + q_) * (size_t)N, &d);
         if (rc) return rc;
-        double *stage = d + 4 * (size_t)N;
+        double *stage = d + 5 * (size_t)N;
+        if (T) HIP_TRY(hipMemcpyAsync(d + 4 * (size_t)N, T, sizeof(double) * N, hipMemcpyHostToDevice, st()));
         HIP_TRY(hipMemcpyAsync(d, n, sizeof(double) * N, hipMemcpyHostToDevice, st()));
         if (u)
             HIP_TRY(hipMemcpyAsync(d + N, u, sizeof(double) * 3 * (size_t)N, hipMemcpyHostToDevice, st()));
@@ -450,7 +475,7 @@ public:
             HIP_TRY(hipMemsetAsync(d + N, 0, sizeof(double) * 3 * (size_t)N, st()));
         cur_ = 0;
         if (l39())
-            HIP_TRY(launch_feq39(st(), L_, d, d + N, stage));
+            HIP_TRY(launch_feq39(st(), L_, d, d + N, T ? d + 4 * (size_t)N : nullptr, stage));
         else
             HIP_TRY(launch_feq(st(), L_, d, d + N, stage));
         rc = store_populations(stage);
@@ -497,7 +522,7 @@ public:
     // Moments into the padded fields, for the readouts.
     hipError_t moments_fields()
     {
-        if (l39()) return launch_moments39(st(), L_, (const double *)f_[cur_], fld39());
+        if (l39()) return launch_moments39(st(), L_, (const double *)f_[cur_], fld39(), thermal_);
         return launch_moments<TF, TM>(st(), L_, nref_d_, f_[cur_], fld_);
     }
 
@@ -514,12 +539,12 @@ public:
         if constexpr (!std::is_same<TF, double>::value) {
             return fail(err, HSLB_EINVAL, "D3Q39 is FP64 only");
         } else {
-            int rc = launch("moments", [&] { return launch_moments39(st(), L_, f_[cur_], fld39()); });
+            int rc = launch("moments", [&] { return launch_moments39(st(), L_, f_[cur_], fld39(), thermal_); });
             if (rc) return rc;
             if (sc_.hs_on && (rc = fields_hs())) return rc;
             if (sc_.phi && (rc = attraction())) return rc;
             rc = launch("collide", [&] {
-                return launch_collide39(st(), L_, sigma_, sc_, chi_d_, f_[cur_], f_[1 - cur_], fld39());
+                return launch_collide39(st(), L_, sigma_, sc_, chi_d_, f_[cur_], f_[1 - cur_], fld39(), thermal_);
             });
             if (rc) return rc;
             cur_ = 1 - cur_;
@@ -756,10 +781,31 @@ public:
         if (sc_.hs_on && (rc = fields_hs())) return rc;
         if (sc_.phi && (rc = attraction())) return rc;
         if (l39())
-            HIP_TRY(launch_force39(st(), L_, sigma_, sc_, chi_d_, (const double *)f_[cur_], fld39(), d));
+            HIP_TRY(launch_force39(st(), L_, sigma_, sc_, chi_d_, (const double *)f_[cur_], fld39(), thermal_, d,
+                                   nullptr));
         else
             HIP_TRY(launch_force<TF, TM>(st(), L_, sigma_, sc_, chi_d_, f_[cur_], fld_, d));
         HIP_TRY(hipMemcpyAsync(F, d, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, st()));
+        HIP_TRY(hipStreamSynchronize(st()));
+        return HSLB_OK;
+    }
+
+    int thermal_fields(double *T, double *Q) override
+    {
+        if (!thermal_) return fail(err, HSLB_ESTATE, "not a thermal context");
+        if (!inited) return fail(err, HSLB_ESTATE, "thermal_fields before init");
+        double *d;
+        const size_t N = L_.N;
+        int rc = io(sizeof(double) * 5 * N, &d);
+        if (rc) return rc;
+        HIP_TRY(moments_fields());
+        if (sc_.hs_on && (rc = fields_hs())) return rc;
+        if (sc_.phi && (rc = attraction())) return rc;
+        HIP_TRY(launch_force39(st(), L_, sigma_, sc_, chi_d_, (const double *)f_[cur_], fld39(), true, d,
+                               d + 3 * N));
+        HIP_TRY(launch_unpad<TM>(st(), L_, fld_.T, d + 4 * N));
+        if (T) HIP_TRY(hipMemcpyAsync(T, d + 4 * N, sizeof(double) * N, hipMemcpyDeviceToHost, st()));
+        if (Q) HIP_TRY(hipMemcpyAsync(Q, d + 3 * N, sizeof(double) * N, hipMemcpyDeviceToHost, st()));
         HIP_TRY(hipStreamSynchronize(st()));
         return HSLB_OK;
     }
@@ -1239,6 +1285,7 @@ private:
     double *chi_n_d_ = nullptr;     // [N] per-node wall factor (mask set)
     int sigma_ = 2;
     int q_ = NQ;  // velocities: 19, or 39 for the third-order lattice (FP64)
+    bool thermal_ = false;  // non-isothermal terms (39 velocities)
     bool l39() const { return q_ == Q39; }
     hipStream_t stream_ = nullptr, ext_stream_ = nullptr;
     bool own_stream_ = false;
@@ -1847,6 +1894,9 @@ static int validate(const hslb_params *p, std::string &err)
             return fail(err, HSLB_EINVAL, "the attraction is not available with the learned force");
     }
     if (p->lattice != HSLB_D3Q19 && p->lattice != HSLB_D3Q39) return fail(err, HSLB_EINVAL, "lattice");
+    if (p->thermal != 0 && p->thermal != 1) return fail(err, HSLB_EINVAL, "thermal");
+    if (p->thermal && p->lattice != HSLB_D3Q39)
+        return fail(err, HSLB_EINVAL, "the non-isothermal terms need the 39-velocity lattice");
     if (p->lattice == HSLB_D3Q39) {
         if (p->precision != HSLB_FP64) return fail(err, HSLB_EINVAL, "the 39-velocity lattice is FP64 only");
         if (p->force_mode == HSLB_FORCE_SURROGATE)
@@ -1922,6 +1972,20 @@ int hslb_init(hslb_ctx *ctx, const double *n, const double *u)
     CTX_CHECK(ctx);
     if (!n) return fail(ctx->eng->err, HSLB_EINVAL, "null density");
     return ctx->eng->init(n, u);
+}
+
+int hslb_init_thermal(hslb_ctx *ctx, const double *n, const double *u, const double *T)
+{
+    CTX_CHECK(ctx);
+    if (!n) return fail(ctx->eng->err, HSLB_EINVAL, "null density");
+    return ctx->eng->init_thermal(n, u, T);
+}
+
+int hslb_thermal_fields(hslb_ctx *ctx, double *T, double *Q)
+{
+    CTX_CHECK(ctx);
+    if (!T && !Q) return fail(ctx->eng->err, HSLB_EINVAL, "null outputs");
+    return ctx->eng->thermal_fields(T, Q);
 }
 
 int hslb_step(hslb_ctx *ctx, int64_t nsteps)

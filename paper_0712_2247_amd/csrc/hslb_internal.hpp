@@ -107,6 +107,7 @@ struct Fields {
     TM *nj;         // [fld_stride][4]: (n, jx, jy, jz) interleaved, one load per shell read
     TM *eb;         // [fld_stride]
     TM *G;          // [7][fld_stride]
+    TM *T;          // [fld_stride] temperature (thermal 39-velocity contexts), else null
 };
 
 // One slit of a batched ensemble.  Its populations start at pop_off in arrays
@@ -181,12 +182,17 @@ hipError_t launch_copy(hipStream_t s, const void *src, void *dst, size_t bytes);
 // [39][N] (0 on solid layers); moments: n and (n, j) into the padded fields;
 // collide: force, regularised collision and streaming, one launch over the
 // fluid layers; force: F[3][N] of the current fields; export: n[N], u[3][N].
-hipError_t launch_feq39(hipStream_t s, const LatticeDev &L, const double *n, const double *u, double *out);
-hipError_t launch_moments39(hipStream_t s, const LatticeDev &L, const double *f, Fields<double> fld);
+// thermal: the non-isothermal terms (temperature field in fld.T, the
+// temperature term of C^(1), the energy source C^(2), the thermal equilibrium
+// and the second-order sources).  feq39 takes T[N] (null: the lattice
+// temperature); force39 also writes C^(2) to Q[N] when Q is not null.
+hipError_t launch_feq39(hipStream_t s, const LatticeDev &L, const double *n, const double *u, const double *T,
+                        double *out);
+hipError_t launch_moments39(hipStream_t s, const LatticeDev &L, const double *f, Fields<double> fld, bool thermal);
 hipError_t launch_collide39(hipStream_t s, const LatticeDev &L, int sigma, const StepConst &c, const double *chi,
-                            const double *fin, double *fout, Fields<double> fld);
+                            const double *fin, double *fout, Fields<double> fld, bool thermal);
 hipError_t launch_force39(hipStream_t s, const LatticeDev &L, int sigma, const StepConst &c, const double *chi,
-                          const double *f, Fields<double> fld, double *F);
+                          const double *f, Fields<double> fld, bool thermal, double *F, double *Q);
 hipError_t launch_export39(hipStream_t s, const LatticeDev &L, const double *f, double *n, double *u);
 // Layer profiles [5][nz] as launch_profiles_pop.
 hipError_t launch_profiles39(hipStream_t s, const LatticeDev &L, const double *f, double *out);

@@ -557,6 +557,23 @@ __device__ __forceinline__ void shell_sum(const Fields<TM> &F, const LatticeDev 
     diag_pair<2, 1, -1, LL, LZ>(F, L, c, alpha, S);
 }
 
+// Mean-field attraction at a fluid node: -n times the central difference of
+// phi; the neighbours of a fluid node lie inside the array (walls are >= 1 layer).
+__device__ __forceinline__ void att_force(const LatticeDev &L, const StepConst &sc, int x, int y, int z, double n,
+                                          double Fa[3])
+{
+    int zu = z + 1, zd = z - 1;
+    if (L.zper) {
+        zu = (zu == L.nz) ? 0 : zu;
+        zd = (zd < 0) ? L.nz - 1 : zd;
+    }
+    const double *P = sc.phi;
+    const int row = L.nx * (y + L.ny * z);
+    Fa[0] = -n * (P[wrapc<1>(x, L.nx) + row] - P[wrapc<-1>(x, L.nx) + row]) / 2.0;
+    Fa[1] = -n * (P[x + L.nx * (wrapc<1>(y, L.ny) + L.ny * z)] - P[x + L.nx * (wrapc<-1>(y, L.ny) + L.ny * z)]) / 2.0;
+    Fa[2] = -n * (P[x + L.nx * (y + L.ny * zu)] - P[x + L.nx * (y + L.ny * zd)]) / 2.0;
+}
+
 // Total force C^(1) + n g at a fluid node with local moments (n, u).
 template <int SIG, bool LZ, typename TM, bool MASK = true>
 __device__ __forceinline__ void node_force(const Fields<TM> &F, const LatticeDev &L, const StepConst &sc,
@@ -597,20 +614,7 @@ __device__ __forceinline__ void node_force(const Fields<TM> &F, const LatticeDev
         shell_sum<SIG, LZ>(F, L, c, alpha, S);
     }
     double Fa[3] = {0.0, 0.0, 0.0};
-    if (sc.phi) {
-        // mean-field attraction: -n times the central difference of phi; the
-        // neighbours of a fluid node lie inside the array (walls are >= 1 layer)
-        int zu = z + 1, zd = z - 1;
-        if (L.zper) {
-            zu = (zu == L.nz) ? 0 : zu;
-            zd = (zd < 0) ? L.nz - 1 : zd;
-        }
-        const double *P = sc.phi;
-        const int row = L.nx * (y + L.ny * z);
-        Fa[0] = -n * (P[wrapc<1>(x, L.nx) + row] - P[wrapc<-1>(x, L.nx) + row]) / 2.0;
-        Fa[1] = -n * (P[x + L.nx * (wrapc<1>(y, L.ny) + L.ny * z)] - P[x + L.nx * (wrapc<-1>(y, L.ny) + L.ny * z)]) / 2.0;
-        Fa[2] = -n * (P[x + L.nx * (y + L.ny * zu)] - P[x + L.nx * (y + L.ny * zd)]) / 2.0;
-    }
+    if (sc.phi) att_force(L, sc, x, y, z, n, Fa);
     const double pn = sc.pref * n;
     Fo[0] = pn * (double)S[0] + Fa[0] + n * sc.g[0];
     Fo[1] = pn * (double)S[1] + Fa[1] + n * sc.g[1];
@@ -1150,22 +1154,52 @@ __device__ __forceinline__ double feq39_of(double n, const double u[3], double u
     return w39(I) * n * (1.0 + xi + 0.5 * xi * xi - 0.5 * uu_s + xi * xi * xi * (1.0 / 6.0) - 0.5 * xi * uu_s);
 }
 
-template <int... I>
-__device__ __forceinline__ void feq39_all(double n, const double u[3], double *out, std::integer_sequence<int, I...>)
+// Thermal: the Maxwellian at (n, u, T) through h^(3) about the lattice
+// temperature s (xi = c/sqrt(s), u~ = u/sqrt(s), th1 = T/s - 1):
+// w n [1 + xi.u~ + ((xi.u~)^2 - u~^2 + th1 (xi^2 - 3))/2
+//      + (xi.u~)((xi.u~)^2 - 3 u~^2 + 3 th1 (xi^2 - 5))/6].  uu_s = u~^2.
+template <int I>
+__device__ __forceinline__ double feq39t_of(double n, const double u[3], double uu_s, double th1)
 {
-    const double uu_s = (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / CS2_39;
-    ((out[I] = feq39_of<I>(n, u, uu_s)), ...);
+    constexpr double is = 1.0 / CS2_39;
+    constexpr double xx = (C39X[I] * C39X[I] + C39Y[I] * C39Y[I] + C39Z[I] * C39Z[I]) * is;
+    const double xu = (C39X[I] * u[0] + C39Y[I] * u[1] + C39Z[I] * u[2]) * is;
+    return w39(I) * n *
+           (1.0 + xu + 0.5 * (xu * xu - uu_s + th1 * (xx - 3.0)) +
+            xu * (xu * xu - 3.0 * uu_s + 3.0 * th1 * (xx - 5.0)) * (1.0 / 6.0));
 }
 
+template <bool TH, int I>
+__device__ __forceinline__ double feq39x(double n, const double u[3], double uu_s, double th1)
+{
+    if constexpr (TH)
+        return feq39t_of<I>(n, u, uu_s, th1);
+    else
+        return feq39_of<I>(n, u, uu_s);
+}
+
+template <bool TH, int... I>
+__device__ __forceinline__ void feq39_all(double n, const double u[3], double th1, double *out,
+                                          std::integer_sequence<int, I...>)
+{
+    const double uu_s = (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / CS2_39;
+    ((out[I] = feq39x<TH, I>(n, u, uu_s, th1)), ...);
+}
+
+// T null: the lattice temperature (the isothermal equilibrium).
 __global__ __launch_bounds__(256) void k_feq39(LatticeDev L, const double *__restrict__ n,
-                                               const double *__restrict__ u, double *__restrict__ out)
+                                               const double *__restrict__ u, const double *__restrict__ T,
+                                               double *__restrict__ out)
 {
     const int id = blockIdx.x * 256 + threadIdx.x;
     if (id >= L.N) return;
     double f[Q39];
     if (is_fluid_z(L, id / L.plane)) {
         const double uv[3] = {u[id], u[L.N + id], u[2 * (size_t)L.N + id]};
-        feq39_all(n[id], uv, f, std::make_integer_sequence<int, Q39>{});
+        if (T)
+            feq39_all<true>(n[id], uv, T[id] / CS2_39 - 1.0, f, std::make_integer_sequence<int, Q39>{});
+        else
+            feq39_all<false>(n[id], uv, 0.0, f, std::make_integer_sequence<int, Q39>{});
     } else {
 #pragma unroll
         for (int i = 0; i < Q39; ++i) f[i] = 0.0;
@@ -1190,16 +1224,33 @@ __device__ __forceinline__ void moments39(const LatticeDev &L, const double *__r
     }
 }
 
+// Temperature of a node from its populations: n T = (sum f c^2 - n u^2) / 3
+// (0 on solid layers and where n = 0).
+__device__ __forceinline__ double temp39(const LatticeDev &L, const double *__restrict__ f, size_t id, int z, double n,
+                                         double jx, double jy, double jz)
+{
+    if (!is_fluid_z(L, z) || n == 0.0) return 0.0;
+    double e = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q39; ++i)
+        e += (double)(C39X[i] * C39X[i] + C39Y[i] * C39Y[i] + C39Z[i] * C39Z[i]) * f[(size_t)i * L.pop_stride + id];
+    const double inv = 1.0 / n;
+    return (e * inv - (jx * jx + jy * jy + jz * jz) * inv * inv) / 3.0;
+}
+
 // grid (ceil(plane / 256), nz)
+template <bool TH>
 __global__ __launch_bounds__(256) void k_moments39(LatticeDev L, const double *__restrict__ f, Fields<double> fld)
 {
     const int r = blockIdx.x * 256 + threadIdx.x;
     const int z = (int)blockIdx.y;
     if (r >= L.plane) return;
     double n, jx, jy, jz;
-    moments39(L, f, (size_t)z * L.plane + r, z, n, jx, jy, jz);
+    const size_t id = (size_t)z * L.plane + r;
+    moments39(L, f, id, z, n, jx, jy, jz);
     store_padded(L, fld.n, r, z, n);
     store_padded4(L, fld.nj, r, z, n, jx, jy, jz);
+    if constexpr (TH) store_padded(L, fld.T, r, z, temp39(L, f, id, z, n, jx, jy, jz));
 }
 
 __global__ __launch_bounds__(256) void k_export39(LatticeDev L, const double *__restrict__ f, double *__restrict__ n,
@@ -1324,12 +1375,22 @@ __device__ __forceinline__ double proj_of(const double k[20])
 // then the landing node.  A link that would leave the fluid layers is
 // reversed at the wall plane: lateral run (2 d - |c_z|) c_a / |c_z| with d the
 // node's distance to the plane, mirrored z.
-template <int I>
+// Thermal: the source adds the force's second Hermite order and the energy
+// source on the trace of h^(2): w [((c.F)(c.u) - s F.u)/s^2 + Q (c^2 - 3 s)/(3 s^2)].
+template <int I, bool TH>
 __device__ __forceinline__ void out39(const LatticeDev &L, double *__restrict__ fout, int x, int y, int z, double fe,
-                                      double om, const double K[20], const double F[3])
+                                      double om, const double K[20], const double F[3], const double u[3], double Fu,
+                                      double Q)
 {
     constexpr int cx = C39X[I], cy = C39Y[I], cz = C39Z[I];
-    const double src = w39(I) * (cx * F[0] + cy * F[1] + cz * F[2]) * (1.0 / CS2_39);
+    constexpr double s = CS2_39;
+    const double cF = cx * F[0] + cy * F[1] + cz * F[2];
+    double src = w39(I) * cF * (1.0 / s);
+    if constexpr (TH) {
+        constexpr double c2 = cx * cx + cy * cy + cz * cz;
+        const double cu = cx * u[0] + cy * u[1] + cz * u[2];
+        src += w39(I) * ((cF * cu - s * Fu) * (1.0 / (s * s)) + Q * ((c2 - 3.0 * s) * (1.0 / (3.0 * s * s))));
+    }
     const double fp = fe + om * (w39(I) * proj_of<I>(K)) + src;
     int xt = x + cx, yt = y + cy, zt = z + cz, k = I;
     if constexpr (cz != 0) {
@@ -1367,23 +1428,150 @@ __device__ __forceinline__ void out39(const LatticeDev &L, double *__restrict__ 
 
 // The projections first (the populations are dead before the force's shell
 // sum), the post-collision values and their streaming after it.
-template <int... I>
-__device__ __forceinline__ void project39(double n, const double u[3], const double *__restrict__ f, double a2[6],
-                                          double a3[10], std::integer_sequence<int, I...>)
+template <bool TH, int... I>
+__device__ __forceinline__ void project39(double n, const double u[3], double th1, const double *__restrict__ f,
+                                          double a2[6], double a3[10], std::integer_sequence<int, I...>)
 {
     const double uu_s = (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / CS2_39;
-    (herm_acc<I>(f[I] - feq39_of<I>(n, u, uu_s), a2, a3), ...);
+    (herm_acc<I>(f[I] - feq39x<TH, I>(n, u, uu_s, th1), a2, a3), ...);
 }
 
-template <int... I>
+template <bool TH, int... I>
 __device__ __forceinline__ void emit39(const LatticeDev &L, double *__restrict__ fout, int x, int y, int z, double n,
-                                      const double u[3], double om, const double F[3], const double a2[6],
-                                      const double a3[10], std::integer_sequence<int, I...>)
+                                      const double u[3], double th1, double om, const double F[3], double Q,
+                                      const double a2[6], const double a3[10], std::integer_sequence<int, I...>)
 {
     const double uu_s = (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / CS2_39;
+    const double Fu = F[0] * u[0] + F[1] * u[1] + F[2] * u[2];
     double k[20];
     proj_coeffs(a2, a3, k);
-    (out39<I>(L, fout, x, y, z, feq39_of<I>(n, u, uu_s), om, k, F), ...);
+    (out39<I, TH>(L, fout, x, y, z, feq39x<TH, I>(n, u, uu_s, th1), om, k, F, u, Fu, Q), ...);
+}
+
+// ------------------------------------------------- non-isothermal shell terms
+
+// One element of the thermal shell sum, the lattice corner d of direction s
+// (s scaled by 1/sqrt(2) on the face diagonals): with cur = s.(j' - n' u),
+//   e1 = G [n' - chi kappa cur + n' (T' - T) / (2 T)]   (C^(1), along s)
+//   e2 = G [-cur / 2 + n' (T' - T) / (sqrt(pi) v_T)]     (C^(2))
+// Solid partners hold n' = j' = 0 and add nothing.
+struct ThCtx {
+    int x, y, zp;
+    double u[3];
+    double ckap;   // chi(z) * 2 / (v_T sqrt(pi))
+    double T;      // T(r)
+    double i2T;    // 1 / (2 T)
+    double ipv;    // 1 / (sqrt(pi) v_T)
+};
+
+template <int DX, int DY, int DZ, int SX, int SY, int SZ, bool DIAG>
+__device__ __forceinline__ void th_element(const Fields<double> &F, const LatticeDev &L, const ThCtx &c, double su,
+                                           double &e1, double &e2)
+{
+    constexpr int SLOT = (DX & 1) | ((DY & 1) << 1) | ((DZ & 1) << 2);
+    constexpr int BX = floordiv2(DX), BY = floordiv2(DY), BZ = floordiv2(DZ);
+    const int ip = wrapc<DX>(c.x, L.nx) + L.nx * (wrapc<DY>(c.y, L.ny) + L.ny * (c.zp + DZ));
+    const int gp = wrapc<BX>(c.x, L.nx) + L.nx * (wrapc<BY>(c.y, L.ny) + L.ny * (c.zp + BZ));
+    const double G = F.G[SLOT * (size_t)L.fld_stride + gp];
+    double q[4];
+    load4(F.nj + 4 * (size_t)ip, q);
+    double sj = s_dot_j<SX, SY, SZ, double, double>(q);
+    if constexpr (DIAG) sj *= 0.70710678118654752440;
+    const double cur = sj - q[0] * su;
+    const double ndT = q[0] * (F.T[ip] - c.T);
+    e1 = G * (q[0] - c.ckap * cur + ndT * c.i2T);
+    e2 = G * (-0.5 * cur + ndT * c.ipv);
+}
+
+template <int AX, int SG, int SIG>
+__device__ __forceinline__ void th_axis(const Fields<double> &F, const LatticeDev &L, const ThCtx &c, double S[3],
+                                        double &Qs)
+{
+    double e1, e2;
+    th_element<AX == 0 ? SG * SIG : 0, AX == 1 ? SG * SIG : 0, AX == 2 ? SG * SIG : 0, AX == 0 ? SG : 0,
+               AX == 1 ? SG : 0, AX == 2 ? SG : 0, false>(F, L, c, SG * c.u[AX], e1, e2);
+    S[AX] += (1.0 / 30.0) * SG * e1;
+    Qs += (1.0 / 30.0) * e2;
+}
+
+template <int PL, int SA, int SB, int LA, int LB>
+__device__ __forceinline__ void th_corner(const Fields<double> &F, const LatticeDev &L, const ThCtx &c, double su,
+                                          double al, double &d1, double &d2)
+{
+    using D = Diag<PL, SA, SB, LA, LB>;
+    double e1, e2;
+    th_element<D::DX, D::DY, D::DZ, D::SX, D::SY, D::SZ, true>(F, L, c, su, e1, e2);
+    d1 += al * e1;
+    d2 += al * e2;
+}
+
+template <int PL, int SA, int SB, int LL>
+__device__ __forceinline__ void th_diag(const Fields<double> &F, const LatticeDev &L, const ThCtx &c,
+                                        const double *alpha, double S[3], double &Qs)
+{
+    constexpr int A = (PL == 2) ? 1 : 0;
+    constexpr int B = (PL == 0) ? 1 : 2;
+    const double su = 0.70710678118654752440 * (SA * c.u[A] + SB * c.u[B]);
+    double d1 = 0.0, d2 = 0.0;
+    th_corner<PL, SA, SB, LL, LL>(F, L, c, su, alpha[0], d1, d2);
+    th_corner<PL, SA, SB, LL, LL + 1>(F, L, c, su, alpha[1], d1, d2);
+    th_corner<PL, SA, SB, LL + 1, LL>(F, L, c, su, alpha[2], d1, d2);
+    th_corner<PL, SA, SB, LL + 1, LL + 1>(F, L, c, su, alpha[3], d1, d2);
+    const double w = (1.0 / 15.0) * 0.70710678118654752440 * d1;
+    S[A] += SA * w;
+    S[B] += SB * w;
+    Qs += (1.0 / 15.0) * d2;
+}
+
+template <int PL, int LL>
+__device__ __forceinline__ void th_plane(const Fields<double> &F, const LatticeDev &L, const ThCtx &c,
+                                         const double *alpha, double S[3], double &Qs)
+{
+    th_diag<PL, 1, 1, LL>(F, L, c, alpha, S, Qs);
+    th_diag<PL, -1, -1, LL>(F, L, c, alpha, S, Qs);
+    th_diag<PL, 1, -1, LL>(F, L, c, alpha, S, Qs);
+    th_diag<PL, -1, 1, LL>(F, L, c, alpha, S, Qs);
+}
+
+// C^(1) with its temperature term, plus attraction and n g, and C^(2), at a
+// fluid node with moments (n, u) and temperature T; v_T^2 = T.
+template <int SIG>
+__device__ __forceinline__ void th_node_force(const Fields<double> &F, const LatticeDev &L, const StepConst &sc,
+                                              const double *__restrict__ chi, int x, int y, int z, double n,
+                                              const double u[3], double T, double Fo[3], double &Qo)
+{
+    double S[3] = {0.0, 0.0, 0.0}, Qs = 0.0;
+    const double vt = sqrt(T);
+    if (sc.hs_on) {
+        ThCtx c;
+        c.x = x;
+        c.y = y;
+        c.zp = z + L.hz;
+        c.u[0] = u[0];
+        c.u[1] = u[1];
+        c.u[2] = u[2];
+        c.T = T;
+        c.ckap = chi[z] * (2.0 / (vt * 1.7724538509055160273));
+        c.i2T = 0.5 / T;
+        c.ipv = 1.0 / (1.7724538509055160273 * vt);
+        constexpr int LL = ell_of(SIG);
+        th_axis<0, 1, SIG>(F, L, c, S, Qs);
+        th_axis<0, -1, SIG>(F, L, c, S, Qs);
+        th_axis<1, 1, SIG>(F, L, c, S, Qs);
+        th_axis<1, -1, SIG>(F, L, c, S, Qs);
+        th_axis<2, 1, SIG>(F, L, c, S, Qs);
+        th_axis<2, -1, SIG>(F, L, c, S, Qs);
+        th_plane<0, LL>(F, L, c, sc.alpha, S, Qs);
+        th_plane<1, LL>(F, L, c, sc.alpha, S, Qs);
+        th_plane<2, LL>(F, L, c, sc.alpha, S, Qs);
+    }
+    double Fa[3] = {0.0, 0.0, 0.0};
+    if (sc.phi) att_force(L, sc, x, y, z, n, Fa);
+    const double pn = -T * (double)(SIG * SIG) * 4.0 * M_PI * n;
+    Fo[0] = pn * S[0] + Fa[0] + n * sc.g[0];
+    Fo[1] = pn * S[1] + Fa[1] + n * sc.g[1];
+    Fo[2] = pn * S[2] + Fa[2] + n * sc.g[2];
+    Qo = -pn * Qs;
 }
 
 // Waves per SIMD the 39-velocity collide kernel is compiled for: the
@@ -1394,7 +1582,7 @@ __device__ __forceinline__ void emit39(const LatticeDev &L, double *__restrict__
 #endif
 
 // 1-D grid over (fluid layer, chunk of 256 nodes of the layer), as k_collide.
-template <int SIG>
+template <int SIG, bool TH>
 __global__ __launch_bounds__(256, HSLB_COLLIDE39_WAVES) void k_collide39(LatticeDev L, StepConst sc, const double *__restrict__ chi,
                                                    const double *__restrict__ fin, double *__restrict__ fout,
                                                    Fields<double> fld, int cpp)
@@ -1420,18 +1608,29 @@ __global__ __launch_bounds__(256, HSLB_COLLIDE39_WAVES) void k_collide39(Lattice
     }
     const double inv_n = (n != 0.0) ? 1.0 / n : 0.0;
     const double u[3] = {jx * inv_n, jy * inv_n, jz * inv_n};
+    double T = 0.0;
+    if constexpr (TH) {
+        double e = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q39; ++i) e += (double)(C39X[i] * C39X[i] + C39Y[i] * C39Y[i] + C39Z[i] * C39Z[i]) * f[i];
+        T = (n != 0.0) ? (e * inv_n - (jx * jx + jy * jy + jz * jz) * inv_n * inv_n) / 3.0 : 0.0;
+    }
+    const double th1 = T / CS2_39 - 1.0;
     double a2[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double a3[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    project39(n, u, f, a2, a3, std::make_integer_sequence<int, Q39>{});
-    double Fv[3];
-    node_force<SIG, true, double, false>(fld, L, sc, chi, x, y, z, n, u, Fv);
-    emit39(L, fout, x, y, z, n, u, 1.0 - 1.0 / sc.tau, Fv, a2, a3, std::make_integer_sequence<int, Q39>{});
+    project39<TH>(n, u, th1, f, a2, a3, std::make_integer_sequence<int, Q39>{});
+    double Fv[3], Q = 0.0;
+    if constexpr (TH)
+        th_node_force<SIG>(fld, L, sc, chi, x, y, z, n, u, T, Fv, Q);
+    else
+        node_force<SIG, true, double, false>(fld, L, sc, chi, x, y, z, n, u, Fv);
+    emit39<TH>(L, fout, x, y, z, n, u, th1, 1.0 - 1.0 / sc.tau, Fv, Q, a2, a3, std::make_integer_sequence<int, Q39>{});
 }
 
-template <int SIG>
+template <int SIG, bool TH>
 __global__ __launch_bounds__(256) void k_force39(LatticeDev L, StepConst sc, const double *__restrict__ chi,
                                                  const double *__restrict__ f, Fields<double> fld,
-                                                 double *__restrict__ Fout)
+                                                 double *__restrict__ Fout, double *__restrict__ Qout)
 {
     const int id = blockIdx.x * 256 + threadIdx.x;
     if (id >= L.N) return;
@@ -1439,17 +1638,21 @@ __global__ __launch_bounds__(256) void k_force39(LatticeDev L, StepConst sc, con
     const int rem = id - z * L.plane;
     const int y = rem / L.nx;
     const int x = rem - y * L.nx;
-    double Fv[3] = {0.0, 0.0, 0.0};
+    double Fv[3] = {0.0, 0.0, 0.0}, Q = 0.0;
     if (is_fluid_z(L, z)) {
         double n, jx, jy, jz;
         moments39(L, f, id, z, n, jx, jy, jz);
         const double inv_n = (n != 0.0) ? 1.0 / n : 0.0;
         const double u[3] = {jx * inv_n, jy * inv_n, jz * inv_n};
-        node_force<SIG, false, double, false>(fld, L, sc, chi, x, y, z, n, u, Fv);
+        if constexpr (TH)
+            th_node_force<SIG>(fld, L, sc, chi, x, y, z, n, u, temp39(L, f, id, z, n, jx, jy, jz), Fv, Q);
+        else
+            node_force<SIG, false, double, false>(fld, L, sc, chi, x, y, z, n, u, Fv);
     }
     Fout[id] = Fv[0];
     Fout[L.N + id] = Fv[1];
     Fout[2 * (size_t)L.N + id] = Fv[2];
+    if (Qout) Qout[id] = Q;
 }
 
 inline unsigned blocks_for(int n) { return (unsigned)((n + 255) / 256); }
@@ -1474,15 +1677,21 @@ hipError_t launch_round_f32(hipStream_t s, double *a, int count)
     return hipGetLastError();
 }
 
-hipError_t launch_feq39(hipStream_t s, const LatticeDev &L, const double *n, const double *u, double *out)
+hipError_t launch_feq39(hipStream_t s, const LatticeDev &L, const double *n, const double *u, const double *T,
+                        double *out)
 {
-    hipLaunchKernelGGL(k_feq39, dim3(blocks_for(L.N)), dim3(256), 0, s, L, n, u, out);
+    hipLaunchKernelGGL(k_feq39, dim3(blocks_for(L.N)), dim3(256), 0, s, L, n, u, T, out);
     return hipGetLastError();
 }
 
-hipError_t launch_moments39(hipStream_t s, const LatticeDev &L, const double *f, Fields<double> fld)
+hipError_t launch_moments39(hipStream_t s, const LatticeDev &L, const double *f, Fields<double> fld, bool thermal)
 {
-    hipLaunchKernelGGL(k_moments39, dim3(blocks_for(L.plane), L.nz), dim3(256), 0, s, L, f, fld);
+    if (thermal && !fld.T) return hipErrorInvalidValue;
+    const dim3 g(blocks_for(L.plane), L.nz), b(256);
+    if (thermal)
+        hipLaunchKernelGGL(k_moments39<true>, g, b, 0, s, L, f, fld);
+    else
+        hipLaunchKernelGGL(k_moments39<false>, g, b, 0, s, L, f, fld);
     return hipGetLastError();
 }
 
@@ -1499,13 +1708,19 @@ hipError_t launch_export39(hipStream_t s, const LatticeDev &L, const double *f, 
 }
 
 hipError_t launch_collide39(hipStream_t s, const LatticeDev &L, int sigma, const StepConst &c, const double *chi,
-                            const double *fin, double *fout, Fields<double> fld)
+                            const double *fin, double *fout, Fields<double> fld, bool thermal)
 {
+    if (thermal && !fld.T) return hipErrorInvalidValue;
     const int layers = L.zper ? L.nz : L.nz - L.wall_lo - L.wall_hi;
     const int cpp = (int)blocks_for(L.plane);
     const dim3 g(cpp * layers), b(256);
 #define HSLB_C39(SG)                                                                               \
-    case SG: hipLaunchKernelGGL((k_collide39<SG>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
+    case SG:                                                                                       \
+        if (thermal)                                                                               \
+            hipLaunchKernelGGL((k_collide39<SG, true>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_collide39<SG, false>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); \
+        break;
     switch (sigma) {
         HSLB_C39(2)
         HSLB_C39(3)
@@ -1521,11 +1736,17 @@ hipError_t launch_collide39(hipStream_t s, const LatticeDev &L, int sigma, const
 }
 
 hipError_t launch_force39(hipStream_t s, const LatticeDev &L, int sigma, const StepConst &c, const double *chi,
-                          const double *f, Fields<double> fld, double *F)
+                          const double *f, Fields<double> fld, bool thermal, double *F, double *Q)
 {
+    if (thermal && !fld.T) return hipErrorInvalidValue;
     const dim3 g(blocks_for(L.N)), b(256);
 #define HSLB_F39(SG)                                                                               \
-    case SG: hipLaunchKernelGGL((k_force39<SG>), g, b, 0, s, L, c, chi, f, fld, F); break;
+    case SG:                                                                                       \
+        if (thermal)                                                                               \
+            hipLaunchKernelGGL((k_force39<SG, true>), g, b, 0, s, L, c, chi, f, fld, F, Q);          \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_force39<SG, false>), g, b, 0, s, L, c, chi, f, fld, F, Q);         \
+        break;
     switch (sigma) {
         HSLB_F39(2)
         HSLB_F39(3)

@@ -44,6 +44,7 @@ HSLB_CNN_NWEIGHTS = 144067
 # Every exported entry point of include/hslb.h.
 EXPORTS = (
     "hslb_create", "hslb_destroy", "hslb_last_error", "hslb_set_stream", "hslb_init",
+    "hslb_init_thermal", "hslb_thermal_fields",
     "hslb_step", "hslb_sync", "hslb_step_count", "hslb_moments", "hslb_profiles",
     "hslb_force", "hslb_eta_bar", "hslb_attraction_potential", "hslb_set_solid", "hslb_get_populations",
     "hslb_set_populations",
@@ -73,7 +74,7 @@ class hslb_params(ctypes.Structure):
         ("surr_check_every", ctypes.c_int32),
         ("surr_tol", ctypes.c_double),
         ("att_eps", ctypes.c_double), ("att_range", ctypes.c_double),
-        ("lattice", ctypes.c_int32),
+        ("lattice", ctypes.c_int32), ("thermal", ctypes.c_int32),
     ]
 
 
@@ -106,6 +107,8 @@ def load(path: Optional[str] = None):
         "hslb_last_error": (ctypes.c_char_p, [_vp]),
         "hslb_set_stream": (ctypes.c_int, [_vp, _vp]),
         "hslb_init": (ctypes.c_int, [_vp, _dp, _dp]),
+        "hslb_init_thermal": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
+        "hslb_thermal_fields": (ctypes.c_int, [_vp, _dp, _dp]),
         "hslb_step": (ctypes.c_int, [_vp, ctypes.c_int64]),
         "hslb_sync": (ctypes.c_int, [_vp]),
         "hslb_step_count": (ctypes.c_int, [_vp, _P(ctypes.c_int64)]),
@@ -206,6 +209,14 @@ def hslb_set_stream(ctx, stream_handle: int):
 
 def hslb_init(ctx, n: np.ndarray, u: Optional[np.ndarray]):
     _chk(ctx, load().hslb_init(ctx, _d(n), _d(u)))
+
+
+def hslb_init_thermal(ctx, n: np.ndarray, u: Optional[np.ndarray], T: Optional[np.ndarray]):
+    _chk(ctx, load().hslb_init_thermal(ctx, _d(n), _d(u), _d(T)))
+
+
+def hslb_thermal_fields(ctx, T: Optional[np.ndarray], Q: Optional[np.ndarray]):
+    _chk(ctx, load().hslb_thermal_fields(ctx, _d(T), _d(Q)))
 
 
 def hslb_step(ctx, nsteps: int):
@@ -478,7 +489,7 @@ def hslb_cnn_op(op: int, nx: int, ny: int, nz: int, zper: bool, w, inp, aux=None
 def make_params(nx, ny, nz, sigma, tau, accel=(0.0, 0.0, 0.0), wall_lo=0, wall_hi=0,
                 g2_model=HSLB_G2_PAPER, wall_reg=1, precision=HSLB_FP64,
                 force_mode=HSLB_FORCE_EXACT, surr_check_every=50, surr_tol=1e-3, att_eps=0.0,
-                att_range=0.0, lattice=HSLB_D3Q19) -> hslb_params:
+                att_range=0.0, lattice=HSLB_D3Q19, thermal=0) -> hslb_params:
     p = hslb_params()
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     p.wall_lo, p.wall_hi = int(wall_lo), int(wall_hi)
@@ -490,6 +501,7 @@ def make_params(nx, ny, nz, sigma, tau, accel=(0.0, 0.0, 0.0), wall_lo=0, wall_h
     p.surr_check_every, p.surr_tol = int(surr_check_every), float(surr_tol)
     p.att_eps, p.att_range = float(att_eps), float(att_range)
     p.lattice = int(lattice)
+    p.thermal = int(thermal)
     return p
 
 
@@ -501,12 +513,12 @@ class Sim:
     def __init__(self, nx, ny, nz, sigma, tau, accel=(0.0, 0.0, 0.0), wall_lo=0, wall_hi=0,
                  precision="f64", g2_model=HSLB_G2_PAPER, wall_reg=1,
                  force_mode=HSLB_FORCE_EXACT, surr_check_every=50, surr_tol=1e-3, att_eps=0.0,
-                 att_range=0.0, lattice=HSLB_D3Q19):
+                 att_range=0.0, lattice=HSLB_D3Q19, thermal=0):
         prec = {"f64": HSLB_FP64, "f32": HSLB_FP32}[precision] if isinstance(precision, str) \
             else int(precision)
         self.params = make_params(nx, ny, nz, sigma, tau, accel, wall_lo, wall_hi, g2_model,
                                   wall_reg, prec, force_mode, surr_check_every, surr_tol, att_eps,
-                                  att_range, lattice)
+                                  att_range, lattice, thermal)
         self.q = 39 if int(lattice) == 39 else 19
         self.shape = (int(nz), int(ny), int(nx))
         self.N = int(nx) * int(ny) * int(nz)
@@ -520,11 +532,22 @@ class Sim:
     def __del__(self):
         self.close()
 
-    def init(self, n, u=None):
+    def init(self, n, u=None, T=None):
+        """Equilibrium of (n, u), and of the temperature T in a thermal context."""
         n = np.ascontiguousarray(n, dtype=np.float64).reshape(self.N)
         if u is not None:
             u = np.ascontiguousarray(u, dtype=np.float64).reshape(3 * self.N)
-        hslb_init(self.ctx, n, u)
+        if T is None:
+            hslb_init(self.ctx, n, u)
+        else:
+            hslb_init_thermal(self.ctx, n, u, np.ascontiguousarray(T, dtype=np.float64).reshape(self.N))
+
+    def thermal_fields(self):
+        """Temperature and energy source C^(2), each (nz, ny, nx)."""
+        T = np.zeros(self.N)
+        Q = np.zeros(self.N)
+        hslb_thermal_fields(self.ctx, T, Q)
+        return T.reshape(self.shape), Q.reshape(self.shape)
 
     def step(self, nsteps=1):
         hslb_step(self.ctx, nsteps)

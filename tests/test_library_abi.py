@@ -87,6 +87,8 @@ def test_attraction_is_rejected_with_the_learned_force_and_in_a_batch(lib):
     dict(lattice=39, nz=6, wall_lo=2, wall_hi=2),       # 2 fluid layers: a link could cross both walls
     dict(lattice=39, nz=2, wall_lo=0, wall_hi=0, force_mode=2, nx=4, ny=4),
     dict(lattice=39, nx=32, ny=32, force_mode=1),       # no learned force
+    dict(thermal=1),                                    # the thermal terms need 39 velocities
+    dict(lattice=39, thermal=2),
 ])
 def test_lattice_choice_is_validated(lib, bad):
     kw = dict(nx=12, ny=12, nz=20, sigma=4, tau=1.0, wall_lo=2, wall_hi=2)
