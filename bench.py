@@ -42,6 +42,10 @@ COLLIDE_BYTES = 168.0
 #   kernel 624 B + n, j read once (32 B) = 656 B.
 STEP39_BYTES = 688.0
 COLLIDE39_BYTES = 656.0
+# With the non-isothermal terms the temperature field adds 8 B written and read
+# once to the step and 8 B read to the collide kernel.
+STEP39T_BYTES = 704.0
+COLLIDE39T_BYTES = 664.0
 DOMINANT = "collide"
 
 
@@ -55,6 +59,7 @@ def _kernel_source_hash() -> str:
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_collide_slit64x64x136_s8.txt")
 TRAFFIC39_FILE = os.path.join(ROOT, "profiles", "traffic_collide39_slit64x64x136_s8.txt")
+TRAFFIC39T_FILE = os.path.join(ROOT, "profiles", "traffic_collide39_thermal_slit64x64x136_s8.txt")
 
 
 def _traffic(workload: str, path: str = TRAFFIC_FILE):
@@ -192,13 +197,22 @@ def obstacle_leg(hslb, np, wl, n, u, steps: int):
             "ms_per_step": round(dt / steps * 1e3, 5), "state_finite_after": finite}
 
 
-def d3q39_leg(hslb, np, wl, n, u, steps: int):
+def d3q39_leg(hslb, np, wl, n, u, steps: int, thermal: bool = False):
     """The benchmark slit on the third-order 39-velocity lattice (FP64
     populations and moments, regularised collision): throughput over `steps`
     graph-replayed steps, then the kernels timed one by one, with the collide
-    kernel's achieved bandwidth on its algorithmic bytes."""
-    s = hslb.Sim.from_workload(wl, precision="f64", lattice=hslb.HSLB_D3Q39)
-    s.init(n, u)
+    kernel's achieved bandwidth on its algorithmic bytes.  thermal: with the
+    non-isothermal terms, from a temperature 2 % above and below the lattice
+    temperature across the slit."""
+    s = hslb.Sim.from_workload(wl, precision="f64", lattice=hslb.HSLB_D3Q39, thermal=int(thermal))
+    if thermal:
+        T0 = 2.0 / 3.0
+        zz = np.arange(wl.nz)
+        T = np.broadcast_to((T0 * (1.0 + 0.02 * np.sin(2.0 * np.pi * zz / wl.nz)))[:, None, None],
+                            (wl.nz, wl.ny, wl.nx)).copy()
+        s.init(n, u, T)
+    else:
+        s.init(n, u)
     s.step(20)
     s.sync()
     t0 = time.perf_counter()
@@ -213,14 +227,16 @@ def d3q39_leg(hslb, np, wl, n, u, steps: int):
     s.close()
     mlups = wl.fluid_nodes * steps / dt / 1e6
     col_s = kt["collide"][0] / kt["collide"][1] * 1e-3
-    col_gbps = COLLIDE39_BYTES * wl.fluid_nodes / col_s / 1e9
-    return {"workload": f"{wl.name} on the 39-velocity lattice, FP64", "steps": steps,
+    cb = COLLIDE39T_BYTES if thermal else COLLIDE39_BYTES
+    col_gbps = cb * wl.fluid_nodes / col_s / 1e9
+    return {"workload": f"{wl.name} on the 39-velocity lattice, FP64" + (", non-isothermal" if thermal else ""),
+            "steps": steps,
             "value": round(mlups, 1), "unit": "MLUPS", "ms_per_step": round(dt / steps * 1e3, 5),
-            "step_algorithmic_GBps": round(mlups * 1e6 * STEP39_BYTES / 1e9, 1),
+            "step_algorithmic_GBps": round(mlups * 1e6 * (STEP39T_BYTES if thermal else STEP39_BYTES) / 1e9, 1),
             "collide_us": round(col_s * 1e6, 2), "collide_GBps": round(col_gbps, 1),
             "collide_hbm_frac": round(col_gbps / PEAK_HBM_GBPS, 4),
-            "collide_algorithmic_bytes": COLLIDE39_BYTES * wl.fluid_nodes,
-            "collide_traffic": _traffic(wl.name, TRAFFIC39_FILE),
+            "collide_algorithmic_bytes": cb * wl.fluid_nodes,
+            "collide_traffic": _traffic(wl.name, TRAFFIC39T_FILE if thermal else TRAFFIC39_FILE),
             "kernels_us": {k: round(v[0] / v[1] * 1e3, 2) for k, v in kt.items()},
             "state_finite_after": finite}
 
@@ -257,6 +273,7 @@ def main():
     ap.add_argument("--no-attraction", action="store_true")
     ap.add_argument("--no-obstacle", action="store_true")
     ap.add_argument("--no-d3q39", action="store_true")
+    ap.add_argument("--no-thermal", action="store_true")
     ap.add_argument("--surrogate-epochs", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -361,6 +378,11 @@ def main():
         print("bench: 39-velocity lattice", file=sys.stderr, flush=True)
         q39 = d3q39_leg(hslb, np, wl, n, u, min(args.steps, 1000))
 
+    q39t = None
+    if not args.no_thermal:
+        print("bench: 39-velocity lattice, non-isothermal", file=sys.stderr, flush=True)
+        q39t = d3q39_leg(hslb, np, wl, n, u, min(args.steps, 500), thermal=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
@@ -393,6 +415,7 @@ def main():
         "attraction": att,
         "obstacle": obst,
         "d3q39": q39,
+        "d3q39_thermal": q39t,
         "roofline": roof,
         "kernels_us": kernels,
         "cpu_baseline": cpu,

@@ -1224,16 +1224,27 @@ __device__ __forceinline__ void moments39(const LatticeDev &L, const double *__r
     }
 }
 
-// Temperature of a node from its populations: n T = (sum f c^2 - n u^2) / 3
-// (0 on solid layers and where n = 0).
-__device__ __forceinline__ double temp39(const LatticeDev &L, const double *__restrict__ f, size_t id, int z, double n,
-                                         double jx, double jy, double jz)
+// n, j and sum f c^2 of a node in one pass (0 on solid layers).
+__device__ __forceinline__ void moments39e(const LatticeDev &L, const double *__restrict__ f, size_t id, int z,
+                                           double &n, double &jx, double &jy, double &jz, double &e)
 {
-    if (!is_fluid_z(L, z) || n == 0.0) return 0.0;
-    double e = 0.0;
+    n = jx = jy = jz = e = 0.0;
+    if (!is_fluid_z(L, z)) return;
 #pragma unroll
-    for (int i = 0; i < Q39; ++i)
-        e += (double)(C39X[i] * C39X[i] + C39Y[i] * C39Y[i] + C39Z[i] * C39Z[i]) * f[(size_t)i * L.pop_stride + id];
+    for (int i = 0; i < Q39; ++i) {
+        const double fi = f[(size_t)i * L.pop_stride + id];
+        n += fi;
+        jx += C39X[i] * fi;
+        jy += C39Y[i] * fi;
+        jz += C39Z[i] * fi;
+        e += (double)(C39X[i] * C39X[i] + C39Y[i] * C39Y[i] + C39Z[i] * C39Z[i]) * fi;
+    }
+}
+
+// Temperature from the moments: n T = (sum f c^2 - n u^2) / 3 (0 where n = 0).
+__device__ __forceinline__ double temp_of(double n, double jx, double jy, double jz, double e)
+{
+    if (n == 0.0) return 0.0;
     const double inv = 1.0 / n;
     return (e * inv - (jx * jx + jy * jy + jz * jz) * inv * inv) / 3.0;
 }
@@ -1245,12 +1256,15 @@ __global__ __launch_bounds__(256) void k_moments39(LatticeDev L, const double *_
     const int r = blockIdx.x * 256 + threadIdx.x;
     const int z = (int)blockIdx.y;
     if (r >= L.plane) return;
-    double n, jx, jy, jz;
+    double n, jx, jy, jz, e = 0.0;
     const size_t id = (size_t)z * L.plane + r;
-    moments39(L, f, id, z, n, jx, jy, jz);
+    if constexpr (TH)
+        moments39e(L, f, id, z, n, jx, jy, jz, e);
+    else
+        moments39(L, f, id, z, n, jx, jy, jz);
     store_padded(L, fld.n, r, z, n);
     store_padded4(L, fld.nj, r, z, n, jx, jy, jz);
-    if constexpr (TH) store_padded(L, fld.T, r, z, temp39(L, f, id, z, n, jx, jy, jz));
+    if constexpr (TH) store_padded(L, fld.T, r, z, temp_of(n, jx, jy, jz, e));
 }
 
 __global__ __launch_bounds__(256) void k_export39(LatticeDev L, const double *__restrict__ f, double *__restrict__ n,
@@ -1580,10 +1594,16 @@ __device__ __forceinline__ void th_node_force(const Fields<double> &F, const Lat
 #ifndef HSLB_COLLIDE39_WAVES
 #define HSLB_COLLIDE39_WAVES 2
 #endif
+// With the non-isothermal terms the kernel needs ~320 registers: at 1 wave per
+// SIMD they fit in VGPRs plus AGPRs without scratch (180 us against 187 us at 2
+// waves with scratch spills).
+#ifndef HSLB_COLLIDE39T_WAVES
+#define HSLB_COLLIDE39T_WAVES 1
+#endif
 
 // 1-D grid over (fluid layer, chunk of 256 nodes of the layer), as k_collide.
 template <int SIG, bool TH>
-__global__ __launch_bounds__(256, HSLB_COLLIDE39_WAVES) void k_collide39(LatticeDev L, StepConst sc, const double *__restrict__ chi,
+__global__ __launch_bounds__(256, TH ? HSLB_COLLIDE39T_WAVES : HSLB_COLLIDE39_WAVES) void k_collide39(LatticeDev L, StepConst sc, const double *__restrict__ chi,
                                                    const double *__restrict__ fin, double *__restrict__ fout,
                                                    Fields<double> fld, int cpp)
 {
@@ -1640,12 +1660,12 @@ __global__ __launch_bounds__(256) void k_force39(LatticeDev L, StepConst sc, con
     const int x = rem - y * L.nx;
     double Fv[3] = {0.0, 0.0, 0.0}, Q = 0.0;
     if (is_fluid_z(L, z)) {
-        double n, jx, jy, jz;
-        moments39(L, f, id, z, n, jx, jy, jz);
+        double n, jx, jy, jz, e;
+        moments39e(L, f, id, z, n, jx, jy, jz, e);
         const double inv_n = (n != 0.0) ? 1.0 / n : 0.0;
         const double u[3] = {jx * inv_n, jy * inv_n, jz * inv_n};
         if constexpr (TH)
-            th_node_force<SIG>(fld, L, sc, chi, x, y, z, n, u, temp39(L, f, id, z, n, jx, jy, jz), Fv, Q);
+            th_node_force<SIG>(fld, L, sc, chi, x, y, z, n, u, temp_of(n, jx, jy, jz, e), Fv, Q);
         else
             node_force<SIG, false, double, false>(fld, L, sc, chi, x, y, z, n, u, Fv);
     }
