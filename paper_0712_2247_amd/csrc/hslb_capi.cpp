@@ -539,9 +539,23 @@ public:
         if constexpr (!std::is_same<TF, double>::value) {
             return fail(err, HSLB_EINVAL, "D3Q39 is FP64 only");
         } else {
-            int rc = launch("moments", [&] { return launch_moments39(st(), L_, f_[cur_], fld39(), thermal_); });
-            if (rc) return rc;
-            if (sc_.hs_on && (rc = fields_hs())) return rc;
+            int rc;
+            if (sc_.hs_on && fused_rows()) {
+                double *rs = nullptr;
+                if constexpr (std::is_same<TM, double>::value) rs = rs_;
+                rc = launch("moments", [&] {
+                    return launch_moments39_rs(st(), L_, sigma_, f_[cur_], fld39(), thermal_, rs);
+                });
+                if (rc) return rc;
+                rc = launch("smooth", [&] { return launch_ballsum<TM>(st(), L_, sigma_, sc_.eta_pref, fld_, rs_); });
+                if (rc) return rc;
+                rc = launch("gfield", [&] { return launch_gfield<TM>(st(), L_, sc_.g2_model, fld_); });
+                if (rc) return rc;
+            } else {
+                rc = launch("moments", [&] { return launch_moments39(st(), L_, f_[cur_], fld39(), thermal_); });
+                if (rc) return rc;
+                if (sc_.hs_on && (rc = fields_hs())) return rc;
+            }
             if (sc_.phi && (rc = attraction())) return rc;
             rc = launch("collide", [&] {
                 return launch_collide39(st(), L_, sigma_, sc_, chi_d_, f_[cur_], f_[1 - cur_], fld39(), thermal_);

@@ -189,6 +189,10 @@ hipError_t launch_copy(hipStream_t s, const void *src, void *dst, size_t bytes);
 hipError_t launch_feq39(hipStream_t s, const LatticeDev &L, const double *n, const double *u, const double *T,
                         double *out);
 hipError_t launch_moments39(hipStream_t s, const LatticeDev &L, const double *f, Fields<double> fld, bool thermal);
+// The same fused with the ball sum's row sums (as launch_moments_rs: nx divides
+// 256 and the plane is a multiple of 256, else hipErrorInvalidValue).
+hipError_t launch_moments39_rs(hipStream_t s, const LatticeDev &L, int sigma, const double *f, Fields<double> fld,
+                               bool thermal, double *rs);
 hipError_t launch_collide39(hipStream_t s, const LatticeDev &L, int sigma, const StepConst &c, const double *chi,
                             const double *fin, double *fout, Fields<double> fld, bool thermal);
 hipError_t launch_force39(hipStream_t s, const LatticeDev &L, int sigma, const StepConst &c, const double *chi,

@@ -240,16 +240,29 @@ __global__ __launch_bounds__(256) void k_moments(LatticeDev L, const double *__r
 // node's row sums rs[w], w = 0..R, come from the block's densities in LDS.
 // They are written at the padded layer of z and, for a periodic z axis, at
 // its images within the padded range the ball sum reads, [hz - R, nz + hz + R).
+template <int SIG, typename TM>
+__device__ __forceinline__ void block_rowsums(const LatticeDev &L, const TM *sn, TM *__restrict__ rs, int z, int r);
+
 template <int SIG, typename TF, typename TM>
 __global__ __launch_bounds__(256) void k_moments_rs(LatticeDev L, const double *__restrict__ nref,
                                                     const TF *__restrict__ f, Fields<TM> fld, TM *__restrict__ rs)
 {
-    constexpr int R = SIG / 2;
     __shared__ TM sn[256];
     const int r = blockIdx.x * 256 + threadIdx.x;
     const int z = (int)blockIdx.y;
     sn[threadIdx.x] = d_moments(L, nref, f, fld, z, r);
     __syncthreads();
+    block_rowsums<SIG>(L, sn, rs, z, r);
+}
+
+// Row sums rs[w], w = 0..R, of node r of layer z from the block's densities in
+// LDS (the block holds whole x-rows of the layer), written at the padded layer
+// of z and, for a periodic z axis, at its images within the padded range the
+// ball sum reads, [hz - R, nz + hz + R).
+template <int SIG, typename TM>
+__device__ __forceinline__ void block_rowsums(const LatticeDev &L, const TM *sn, TM *__restrict__ rs, int z, int r)
+{
+    constexpr int R = SIG / 2;
     const int x = (int)threadIdx.x % L.nx;
     const int row = (int)threadIdx.x - x;
     TM acc[R + 1];
@@ -1267,6 +1280,29 @@ __global__ __launch_bounds__(256) void k_moments39(LatticeDev L, const double *_
     if constexpr (TH) store_padded(L, fld.T, r, z, temp_of(n, jx, jy, jz, e));
 }
 
+// Moments (and temperature) fused with the row sums of the two-pass ball sum,
+// as k_moments_rs: the block holds whole x-rows of layer z.
+template <int SIG, bool TH>
+__global__ __launch_bounds__(256) void k_moments39_rs(LatticeDev L, const double *__restrict__ f, Fields<double> fld,
+                                                      double *__restrict__ rs)
+{
+    __shared__ double sn[256];
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    const int z = (int)blockIdx.y;
+    double n, jx, jy, jz, e = 0.0;
+    const size_t id = (size_t)z * L.plane + r;
+    if constexpr (TH)
+        moments39e(L, f, id, z, n, jx, jy, jz, e);
+    else
+        moments39(L, f, id, z, n, jx, jy, jz);
+    store_padded(L, fld.n, r, z, n);
+    store_padded4(L, fld.nj, r, z, n, jx, jy, jz);
+    if constexpr (TH) store_padded(L, fld.T, r, z, temp_of(n, jx, jy, jz, e));
+    sn[threadIdx.x] = n;
+    __syncthreads();
+    block_rowsums<SIG>(L, sn, rs, z, r);
+}
+
 __global__ __launch_bounds__(256) void k_export39(LatticeDev L, const double *__restrict__ f, double *__restrict__ n,
                                                   double *__restrict__ u)
 {
@@ -1717,6 +1753,33 @@ hipError_t launch_moments39(hipStream_t s, const LatticeDev &L, const double *f,
         hipLaunchKernelGGL(k_moments39<true>, g, b, 0, s, L, f, fld);
     else
         hipLaunchKernelGGL(k_moments39<false>, g, b, 0, s, L, f, fld);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments39_rs(hipStream_t s, const LatticeDev &L, int sigma, const double *f, Fields<double> fld,
+                               bool thermal, double *rs)
+{
+    if (256 % L.nx != 0 || L.plane % 256 != 0) return hipErrorInvalidValue;
+    if (thermal && !fld.T) return hipErrorInvalidValue;
+    const dim3 g(L.plane / 256, L.nz), b(256);
+#define HSLB_M39(SG)                                                                               \
+    case SG:                                                                                       \
+        if (thermal)                                                                               \
+            hipLaunchKernelGGL((k_moments39_rs<SG, true>), g, b, 0, s, L, f, fld, rs);             \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_moments39_rs<SG, false>), g, b, 0, s, L, f, fld, rs);            \
+        break;
+    switch (sigma) {
+        HSLB_M39(2)
+        HSLB_M39(3)
+        HSLB_M39(4)
+        HSLB_M39(5)
+        HSLB_M39(6)
+        HSLB_M39(7)
+        HSLB_M39(8)
+    default: return hipErrorInvalidValue;
+    }
+#undef HSLB_M39
     return hipGetLastError();
 }
 
