@@ -2,7 +2,8 @@
 steps (periodic boxes and slits, the hard-sphere force, the attraction, force
 off with a driving field, the narrowest slit and the smallest periodic box),
 the force and moment readouts, population and checkpoint round trips, and at
-the benchmarked 64x64x136 slit's size two steps against two oracle steps."""
+the benchmarked 64x64x136 slit's size two steps against two oracle steps, and
+the graph-replayed and eager steps (isothermal and thermal) bit for bit."""
 import numpy as np
 import pytest
 
@@ -133,3 +134,28 @@ def test_full_size_two_steps():
     err = _rel(fg, fo)
     print(f"64x64x136, 2 steps: relative difference {err:.3e}", flush=True)
     assert err <= TOL
+
+
+@pytest.mark.parametrize("thermal", [0, 1])
+def test_graph_and_eager_steps_agree_and_watchdog_passes(thermal):
+    """The captured two-step graphs and the eager launches run the same kernels
+    in the same order: 11 steps (5 graph replays and one eager step, against 11
+    eager steps) give identical populations; the watchdog (mass and finiteness
+    every 4 steps, through the 39-velocity profile kernel) stays quiet."""
+    case = CASES[6]
+    nx, ny, nz, sigma, walls, fm, lam = case
+    n, u = _state(case, seed=34)
+    kw = dict(accel=(2e-5, 0.0, 0.0), wall_lo=walls, wall_hi=walls, precision="f64",
+              lattice=hslb.HSLB_D3Q39, thermal=thermal)
+    T = None
+    if thermal:
+        T = (2.0 / 3.0) * (1.0 + 0.03 * np.random.default_rng(35).uniform(-1, 1, size=(nz, ny, nx)))
+    a = hslb.Sim(nx, ny, nz, sigma, 0.9, **kw)
+    b = hslb.Sim(nx, ny, nz, sigma, 0.9, **kw)
+    hslb.hslb_set_graph(b.ctx, False)
+    hslb.hslb_set_watchdog(a.ctx, 4, 1e-10)
+    for s in (a, b):
+        s.init(n, u, T)
+        s.step(11)
+    assert hslb.hslb_step_count(a.ctx) == 11
+    assert np.array_equal(a.get_populations(), b.get_populations())
