@@ -1420,6 +1420,80 @@ __device__ __forceinline__ double proj_of(const double k[20])
     return p;
 }
 
+// Hermite coefficients of f - f_eq from the raw ones of f (herm_acc on f):
+// the equilibrium's are n (u u + (T - s) I) and n (u u u + (T - s)(u d)_sym),
+// which the degree-7 quadrature integrates exactly.  dT = T - s (0 isothermal).
+__device__ __forceinline__ void sub_eq_moments(double n, const double u[3], double dT, double a2[6], double a3[10])
+{
+    const double x = u[0], y = u[1], z = u[2];
+    a2[0] -= n * (x * x + dT);
+    a2[1] -= n * (y * y + dT);
+    a2[2] -= n * (z * z + dT);
+    a2[3] -= n * (x * y);
+    a2[4] -= n * (x * z);
+    a2[5] -= n * (y * z);
+    a3[0] -= n * (x * x * x + 3.0 * dT * x);
+    a3[1] -= n * (y * y * y + 3.0 * dT * y);
+    a3[2] -= n * (z * z * z + 3.0 * dT * z);
+    a3[3] -= n * (x * x * y + dT * y);
+    a3[4] -= n * (x * x * z + dT * z);
+    a3[5] -= n * (x * y * y + dT * x);
+    a3[6] -= n * (y * y * z + dT * z);
+    a3[7] -= n * (x * z * z + dT * x);
+    a3[8] -= n * (y * z * z + dT * y);
+    a3[9] -= n * (x * y * z);
+}
+
+// The post-collision value divided by w_i is a cubic polynomial in c_i:
+//   n E(c) + (1 - 1/tau) P(c) + S(c),
+// E the equilibrium (through h^(3); th1 = T/s - 1, 0 isothermal), P the
+// projection (proj_coeffs), S the source (c.F/s; thermal: plus
+// ((c.F)(c.u) - s F.u)/s^2 + Q (c^2 - 3 s)/(3 s^2)).  A[] holds its 20
+// coefficients in the layout of proj_coeffs, evaluated per velocity by proj_of.
+template <bool TH>
+__device__ __forceinline__ void post_coeffs(double n, const double u[3], double th1, double om, const double F[3],
+                                            double Q, const double a2[6], const double a3[10], double A[20])
+{
+    constexpr double is = 1.0 / CS2_39, is2 = is * is, is3 = is2 * is;
+    const double x = u[0], y = u[1], z = u[2];
+    proj_coeffs(a2, a3, A);
+#pragma unroll
+    for (int m = 0; m < 20; ++m) A[m] *= om;
+    const double uu = (x * x + y * y + z * z) * is;
+    const double g1 = (1.0 - 0.5 * uu - 2.5 * th1) * is;
+    const double h2 = 0.5 * th1 * is, h3 = 0.5 * th1 * is2;
+    A[0] += n * (1.0 - 0.5 * uu - 1.5 * th1);
+    A[1] += n * (x * g1) + F[0] * is;
+    A[2] += n * (y * g1) + F[1] * is;
+    A[3] += n * (z * g1) + F[2] * is;
+    A[4] += n * (0.5 * x * x * is2 + h2);
+    A[5] += n * (0.5 * y * y * is2 + h2);
+    A[6] += n * (0.5 * z * z * is2 + h2);
+    A[7] += n * (x * y * is2);
+    A[8] += n * (x * z * is2);
+    A[9] += n * (y * z * is2);
+    A[10] += n * (x * x * x * (is3 / 6.0) + h3 * x);
+    A[11] += n * (y * y * y * (is3 / 6.0) + h3 * y);
+    A[12] += n * (z * z * z * (is3 / 6.0) + h3 * z);
+    A[13] += n * (0.5 * x * x * y * is3 + h3 * y);
+    A[14] += n * (0.5 * x * x * z * is3 + h3 * z);
+    A[15] += n * (0.5 * x * y * y * is3 + h3 * x);
+    A[16] += n * (0.5 * y * y * z * is3 + h3 * z);
+    A[17] += n * (0.5 * x * z * z * is3 + h3 * x);
+    A[18] += n * (0.5 * y * z * z * is3 + h3 * y);
+    A[19] += n * (x * y * z * is3);
+    if constexpr (TH) {
+        const double Fu = F[0] * x + F[1] * y + F[2] * z;
+        A[0] -= (Fu + Q) * is;
+        A[4] += (F[0] * x + Q * (1.0 / 3.0)) * is2;
+        A[5] += (F[1] * y + Q * (1.0 / 3.0)) * is2;
+        A[6] += (F[2] * z + Q * (1.0 / 3.0)) * is2;
+        A[7] += (F[0] * y + F[1] * x) * is2;
+        A[8] += (F[0] * z + F[2] * x) * is2;
+        A[9] += (F[1] * z + F[2] * y) * is2;
+    }
+}
+
 // Collide and stream of velocity I from node (x, y, z): post-collision value
 // from the equilibrium, the relaxed projection and the first-order source,
 // then the landing node.  A link that would leave the fluid layers is
@@ -1427,21 +1501,10 @@ __device__ __forceinline__ double proj_of(const double k[20])
 // node's distance to the plane, mirrored z.
 // Thermal: the source adds the force's second Hermite order and the energy
 // source on the trace of h^(2): w [((c.F)(c.u) - s F.u)/s^2 + Q (c^2 - 3 s)/(3 s^2)].
-template <int I, bool TH>
-__device__ __forceinline__ void out39(const LatticeDev &L, double *__restrict__ fout, int x, int y, int z, double fe,
-                                      double om, const double K[20], const double F[3], const double u[3], double Fu,
-                                      double Q)
+template <int I>
+__device__ __forceinline__ void out39(const LatticeDev &L, double *__restrict__ fout, int x, int y, int z, double fp)
 {
     constexpr int cx = C39X[I], cy = C39Y[I], cz = C39Z[I];
-    constexpr double s = CS2_39;
-    const double cF = cx * F[0] + cy * F[1] + cz * F[2];
-    double src = w39(I) * cF * (1.0 / s);
-    if constexpr (TH) {
-        constexpr double c2 = cx * cx + cy * cy + cz * cz;
-        const double cu = cx * u[0] + cy * u[1] + cz * u[2];
-        src += w39(I) * ((cF * cu - s * Fu) * (1.0 / (s * s)) + Q * ((c2 - 3.0 * s) * (1.0 / (3.0 * s * s))));
-    }
-    const double fp = fe + om * (w39(I) * proj_of<I>(K)) + src;
     int xt = x + cx, yt = y + cy, zt = z + cz, k = I;
     if constexpr (cz != 0) {
         if (L.zper) {
@@ -1479,24 +1542,50 @@ __device__ __forceinline__ void out39(const LatticeDev &L, double *__restrict__ 
 
 // The projections first (the populations are dead before the force's shell
 // sum), the post-collision values and their streaming after it.
-template <bool TH, int... I>
-__device__ __forceinline__ void project39(double n, const double u[3], double th1, const double *__restrict__ f,
-                                          double a2[6], double a3[10], std::integer_sequence<int, I...>)
+// Two forms of the same collision, chosen by measurement on the 64x64x136
+// slit.  Isothermal: f - f_eq per velocity for the projection, and per velocity
+// f_eq + (1 - 1/tau) w P(c) + w c.F/s (96 us; the polynomial form below took
+// 100 us).  Thermal: the raw Hermite moments of f less the equilibrium's, and
+// the whole post-collision value as one cubic polynomial per node (116 us
+// against 159 us, at 228 VGPRs instead of ~320).
+template <int... I>
+__device__ __forceinline__ void project39(double n, const double u[3], const double *__restrict__ f, double a2[6],
+                                          double a3[10], std::integer_sequence<int, I...>)
 {
     const double uu_s = (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / CS2_39;
-    (herm_acc<I>(f[I] - feq39x<TH, I>(n, u, uu_s, th1), a2, a3), ...);
+    (herm_acc<I>(f[I] - feq39_of<I>(n, u, uu_s), a2, a3), ...);
 }
 
-template <bool TH, int... I>
+template <int I>
+__device__ __forceinline__ double post39(double fe, double om, const double K[20], const double F[3])
+{
+    const double cF = C39X[I] * F[0] + C39Y[I] * F[1] + C39Z[I] * F[2];
+    return fe + om * (w39(I) * proj_of<I>(K)) + w39(I) * cF * (1.0 / CS2_39);
+}
+
+template <int... I>
 __device__ __forceinline__ void emit39(const LatticeDev &L, double *__restrict__ fout, int x, int y, int z, double n,
-                                      const double u[3], double th1, double om, const double F[3], double Q,
-                                      const double a2[6], const double a3[10], std::integer_sequence<int, I...>)
+                                      const double u[3], double om, const double F[3], const double a2[6],
+                                      const double a3[10], std::integer_sequence<int, I...>)
 {
     const double uu_s = (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / CS2_39;
-    const double Fu = F[0] * u[0] + F[1] * u[1] + F[2] * u[2];
     double k[20];
     proj_coeffs(a2, a3, k);
-    (out39<I, TH>(L, fout, x, y, z, feq39x<TH, I>(n, u, uu_s, th1), om, k, F, u, Fu, Q), ...);
+    (out39<I>(L, fout, x, y, z, post39<I>(feq39_of<I>(n, u, uu_s), om, k, F)), ...);
+}
+
+template <int... I>
+__device__ __forceinline__ void raw_herm39(const double *__restrict__ f, double a2[6], double a3[10],
+                                           std::integer_sequence<int, I...>)
+{
+    (herm_acc<I>(f[I], a2, a3), ...);
+}
+
+template <int... I>
+__device__ __forceinline__ void emit39_poly(const LatticeDev &L, double *__restrict__ fout, int x, int y, int z,
+                                           const double A[20], std::integer_sequence<int, I...>)
+{
+    (out39<I>(L, fout, x, y, z, w39(I) * proj_of<I>(A)), ...);
 }
 
 // ------------------------------------------------- non-isothermal shell terms
@@ -1631,11 +1720,8 @@ __device__ __forceinline__ void th_node_force(const Fields<double> &F, const Lat
 #ifndef HSLB_COLLIDE39_WAVES
 #define HSLB_COLLIDE39_WAVES 2
 #endif
-// With the non-isothermal terms the kernel needs ~320 registers: at 1 wave per
-// SIMD they fit in VGPRs plus AGPRs without scratch (180 us against 187 us at 2
-// waves with scratch spills).
 #ifndef HSLB_COLLIDE39T_WAVES
-#define HSLB_COLLIDE39T_WAVES 1
+#define HSLB_COLLIDE39T_WAVES 2
 #endif
 
 // 1-D grid over (fluid layer, chunk of 256 nodes of the layer), as k_collide.
@@ -1679,13 +1765,21 @@ __global__ __launch_bounds__(256, TH ? HSLB_COLLIDE39T_WAVES : HSLB_COLLIDE39_WA
     const double th1 = T / CS2_39 - 1.0;
     double a2[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double a3[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    project39<TH>(n, u, th1, f, a2, a3, std::make_integer_sequence<int, Q39>{});
-    double Fv[3], Q = 0.0;
-    if constexpr (TH)
+    const double om = 1.0 - 1.0 / sc.tau;
+    double Fv[3];
+    if constexpr (TH) {
+        raw_herm39(f, a2, a3, std::make_integer_sequence<int, Q39>{});
+        sub_eq_moments(n, u, T - CS2_39, a2, a3);
+        double Q;
         th_node_force<SIG>(fld, L, sc, chi, x, y, z, n, u, T, Fv, Q);
-    else
+        double A[20];
+        post_coeffs<true>(n, u, th1, om, Fv, Q, a2, a3, A);
+        emit39_poly(L, fout, x, y, z, A, std::make_integer_sequence<int, Q39>{});
+    } else {
+        project39(n, u, f, a2, a3, std::make_integer_sequence<int, Q39>{});
         node_force<SIG, true, double, false>(fld, L, sc, chi, x, y, z, n, u, Fv);
-    emit39<TH>(L, fout, x, y, z, n, u, th1, 1.0 - 1.0 / sc.tau, Fv, Q, a2, a3, std::make_integer_sequence<int, Q39>{});
+        emit39(L, fout, x, y, z, n, u, om, Fv, a2, a3, std::make_integer_sequence<int, Q39>{});
+    }
 }
 
 template <int SIG, bool TH>
