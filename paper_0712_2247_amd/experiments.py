@@ -364,13 +364,54 @@ FIG3_NSTARS = (0.064, 0.128, 0.256, 0.384, 0.512)
 FIG4_WIDTHS = (5, 10, 15, 20)
 
 
+def basis_comparison(sigma: int = 4, eta: float = 0.25, H: int = 40, tau: float = 0.8, steps: int = 3000,
+                     lateral: int = 8, log=print) -> Dict:
+    """The question the paper attaches to the higher-order basis: does it make
+    the wall factor unnecessary?  A static slit (no driving field, uniform
+    start) on the 19- and 39-velocity lattices, with and without the wall
+    factor, run to rest (`steps` steps, FP64).  Reported per run: the static
+    current max |u_z| (the current the wall factor damps in the coupling term),
+    its departure from the half-step current -F_z/(2n) of the first-order
+    source, and the contact, maximum and minimum density of the profile
+    relative to the bulk."""
+    w = 2
+    nz = H + 2 * w
+    nb = workloads.number_density(eta, sigma)
+    n = np.full((nz, lateral, lateral), nb)
+    n[:w] = n[-w:] = 0.0
+    rows = []
+    for lat in (hslb.HSLB_D3Q19, hslb.HSLB_D3Q39):
+        for reg in (1, 0):
+            s = hslb.Sim(lateral, lateral, nz, sigma, tau, wall_lo=w, wall_hi=w, precision="f64", lattice=lat,
+                         wall_reg=reg)
+            s.init(n)
+            s.step(steps)
+            nn, uu = s.moments()
+            F = s.force()
+            s.close()
+            fl = slice(w, nz - w)
+            uz = uu[2, fl, 0, 0]
+            half = -F[2, fl, 0, 0] / (2.0 * nn[fl, 0, 0])
+            prof = nn[fl, 0, 0] / nb
+            row = {"lattice": 39 if lat == hslb.HSLB_D3Q39 else 19, "wall_reg": reg,
+                   "max_uz": float(np.abs(uz).max()), "halfstep_residual": float(np.abs(uz - half).max()),
+                   "contact": float(prof[0]), "max": float(prof.max()), "min": float(prof.min()),
+                   "profile": prof.tolist()}
+            log(f"basis: {row['lattice']} velocities, wall factor {reg}: max|u_z| {row['max_uz']:.4g}, "
+                f"|u_z + F_z/2n| {row['halfstep_residual']:.2e}, contact {row['contact']:.4f}, "
+                f"min {row['min']:.4f}")
+            rows.append(row)
+    return {"sigma": sigma, "eta": eta, "H": H, "tau": tau, "steps": steps, "rows": rows}
+
+
 def run_all(sigma: int = 8, log=print) -> Dict:
     t0 = time.perf_counter()
     out = {"fig1": viscosity_sweep(FIG1_NSTARS, sigma=sigma, log=log),
            "fig2": statics(FIG2_NSTARS, sigma=sigma, log=log),
            "fig3": poiseuille_density(FIG3_NSTARS, sigma=sigma, log=log),
            "fig4": poiseuille_width(FIG4_WIDTHS, sigma=sigma, log=log),
-           "coexistence": coexistence((0.9, 1.05, 1.1), log=log)}
+           "coexistence": coexistence((0.9, 1.05, 1.1), log=log),
+           "basis": basis_comparison(log=log)}
     out["seconds"] = time.perf_counter() - t0
     return out
 
