@@ -173,3 +173,26 @@ def test_rejections():
     o = oracle.Oracle(6, 6, 8, 2, 0.9, wall_lo=1, wall_hi=1, lattice=39, thermal=1)
     with pytest.raises(ValueError):
         o.init(np.full((8, 6, 6), 0.01), None, np.full((8, 6, 6), -1.0))
+
+
+@pytest.mark.parametrize("thermal,gamma", [(0, 1.0), (1, 5.0 / 3.0)])
+def test_sound_speed_isothermal_and_adiabatic(thermal, gamma):
+    """A density wave (force off, uniform T0 start) on the 39-velocity lattice:
+    its velocity mode oscillates at c k with c^2 = T0 on the isothermal lattice
+    and c^2 = 5 T0 / 3, the adiabatic value of a monatomic gas, once the energy
+    equation is coupled.  (The density mode of the thermal lattice also carries
+    the non-propagating entropy mode; the velocity mode does not.)"""
+    L, eps = 64, 1e-4
+    k = 2 * math.pi / L
+    z = np.arange(L)
+    o = oracle.Oracle(1, 1, L, 4, 0.8, lattice=39, thermal=thermal, force_mode=oracle.FORCE_OFF)
+    o.init((1 + eps * np.cos(k * z))[:, None, None])
+    v = []
+    for _ in range(400):
+        v.append(float(o.moments()[1][2, :, 0, 0] @ np.sin(k * z)))
+        o.step(1)
+    a = np.array(v)
+    zc = [i + a[i] / (a[i] - a[i + 1]) for i in range(1, len(a) - 1) if a[i] * a[i + 1] < 0]
+    assert len(zc) >= 8
+    c = math.pi / ((zc[-1] - zc[0]) / (len(zc) - 1)) / k
+    assert c == pytest.approx(math.sqrt(gamma * T0), rel=3e-3)
