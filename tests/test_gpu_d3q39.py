@@ -21,6 +21,8 @@ CASES = [
     (6, 5, 12, 4, 1, hslb.HSLB_FORCE_OFF, 0.0),        # force off, driven
     (3, 3, 5, 2, 0, hslb.HSLB_FORCE_OFF, 0.0),         # smallest periodic box
     (16, 16, 24, 6, 3, hslb.HSLB_FORCE_EXACT, 0.0),    # 256 nodes per layer
+    (14, 13, 20, 5, 3, hslb.HSLB_FORCE_EXACT, 0.0),    # odd sigma: half-integer axis midpoints
+    (16, 16, 22, 7, 0, hslb.HSLB_FORCE_EXACT, 0.0),    # sigma 7, periodic, fused row sums
 ]
 TOL = 1e-12   # FP64 against the FP64 oracle
 

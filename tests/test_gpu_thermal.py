@@ -22,6 +22,8 @@ CASES = [
     (12, 12, 18, 4, 3, hslb.HSLB_FORCE_EXACT, 1.5),
     (6, 5, 12, 4, 1, hslb.HSLB_FORCE_OFF, 0.0),
     (16, 16, 24, 6, 3, hslb.HSLB_FORCE_EXACT, 0.0),
+    (14, 13, 20, 5, 3, hslb.HSLB_FORCE_EXACT, 0.0),
+    (16, 16, 22, 7, 0, hslb.HSLB_FORCE_EXACT, 0.0),
 ]
 
 
