@@ -1604,48 +1604,61 @@ struct ThCtx {
     double ipv;    // 1 / (sqrt(pi) v_T)
 };
 
-template <int DX, int DY, int DZ, int SX, int SY, int SZ, bool DIAG>
+// LZ: z uniform over the block, the layer parts of the addresses scalar (as
+// pair_element); otherwise one node index per read.
+template <int DX, int DY, int DZ, int SX, int SY, int SZ, bool DIAG, bool LZ>
 __device__ __forceinline__ void th_element(const Fields<double> &F, const LatticeDev &L, const ThCtx &c, double su,
                                            double &e1, double &e2)
 {
     constexpr int SLOT = (DX & 1) | ((DY & 1) << 1) | ((DZ & 1) << 2);
     constexpr int BX = floordiv2(DX), BY = floordiv2(DY), BZ = floordiv2(DZ);
-    const int ip = wrapc<DX>(c.x, L.nx) + L.nx * (wrapc<DY>(c.y, L.ny) + L.ny * (c.zp + DZ));
-    const int gp = wrapc<BX>(c.x, L.nx) + L.nx * (wrapc<BY>(c.y, L.ny) + L.ny * (c.zp + BZ));
-    const double G = F.G[SLOT * (size_t)L.fld_stride + gp];
-    double q[4];
-    load4(F.nj + 4 * (size_t)ip, q);
+    double G, Tp, q[4];
+    if constexpr (LZ) {
+        const size_t lay = (size_t)L.plane;
+        const char *njp = (const char *)F.nj + 32 * lay * (size_t)(c.zp + DZ);
+        const char *tp = (const char *)F.T + 8 * lay * (size_t)(c.zp + DZ);
+        const char *gz = (const char *)F.G + 8 * ((size_t)SLOT * L.fld_stride + lay * (size_t)(c.zp + BZ));
+        G = *(const double *)(gz + (xb<BX, 8>(c.x, L.nx) + yb<BY, 8>(c.y, L.ny, L.nx)));
+        Tp = *(const double *)(tp + (xb<DX, 8>(c.x, L.nx) + yb<DY, 8>(c.y, L.ny, L.nx)));
+        load4((const double *)(njp + (xb<DX, 32>(c.x, L.nx) + yb<DY, 32>(c.y, L.ny, L.nx))), q);
+    } else {
+        const int ip = wrapc<DX>(c.x, L.nx) + L.nx * (wrapc<DY>(c.y, L.ny) + L.ny * (c.zp + DZ));
+        const int gp = wrapc<BX>(c.x, L.nx) + L.nx * (wrapc<BY>(c.y, L.ny) + L.ny * (c.zp + BZ));
+        G = F.G[SLOT * (size_t)L.fld_stride + gp];
+        Tp = F.T[ip];
+        load4(F.nj + 4 * (size_t)ip, q);
+    }
     double sj = s_dot_j<SX, SY, SZ, double, double>(q);
     if constexpr (DIAG) sj *= 0.70710678118654752440;
     const double cur = sj - q[0] * su;
-    const double ndT = q[0] * (F.T[ip] - c.T);
+    const double ndT = q[0] * (Tp - c.T);
     e1 = G * (q[0] - c.ckap * cur + ndT * c.i2T);
     e2 = G * (-0.5 * cur + ndT * c.ipv);
 }
 
-template <int AX, int SG, int SIG>
+template <int AX, int SG, int SIG, bool LZ>
 __device__ __forceinline__ void th_axis(const Fields<double> &F, const LatticeDev &L, const ThCtx &c, double S[3],
                                         double &Qs)
 {
     double e1, e2;
     th_element<AX == 0 ? SG * SIG : 0, AX == 1 ? SG * SIG : 0, AX == 2 ? SG * SIG : 0, AX == 0 ? SG : 0,
-               AX == 1 ? SG : 0, AX == 2 ? SG : 0, false>(F, L, c, SG * c.u[AX], e1, e2);
+               AX == 1 ? SG : 0, AX == 2 ? SG : 0, false, LZ>(F, L, c, SG * c.u[AX], e1, e2);
     S[AX] += (1.0 / 30.0) * SG * e1;
     Qs += (1.0 / 30.0) * e2;
 }
 
-template <int PL, int SA, int SB, int LA, int LB>
+template <int PL, int SA, int SB, int LA, int LB, bool LZ>
 __device__ __forceinline__ void th_corner(const Fields<double> &F, const LatticeDev &L, const ThCtx &c, double su,
                                           double al, double &d1, double &d2)
 {
     using D = Diag<PL, SA, SB, LA, LB>;
     double e1, e2;
-    th_element<D::DX, D::DY, D::DZ, D::SX, D::SY, D::SZ, true>(F, L, c, su, e1, e2);
+    th_element<D::DX, D::DY, D::DZ, D::SX, D::SY, D::SZ, true, LZ>(F, L, c, su, e1, e2);
     d1 += al * e1;
     d2 += al * e2;
 }
 
-template <int PL, int SA, int SB, int LL>
+template <int PL, int SA, int SB, int LL, bool LZ>
 __device__ __forceinline__ void th_diag(const Fields<double> &F, const LatticeDev &L, const ThCtx &c,
                                         const double *alpha, double S[3], double &Qs)
 {
@@ -1653,29 +1666,29 @@ __device__ __forceinline__ void th_diag(const Fields<double> &F, const LatticeDe
     constexpr int B = (PL == 0) ? 1 : 2;
     const double su = 0.70710678118654752440 * (SA * c.u[A] + SB * c.u[B]);
     double d1 = 0.0, d2 = 0.0;
-    th_corner<PL, SA, SB, LL, LL>(F, L, c, su, alpha[0], d1, d2);
-    th_corner<PL, SA, SB, LL, LL + 1>(F, L, c, su, alpha[1], d1, d2);
-    th_corner<PL, SA, SB, LL + 1, LL>(F, L, c, su, alpha[2], d1, d2);
-    th_corner<PL, SA, SB, LL + 1, LL + 1>(F, L, c, su, alpha[3], d1, d2);
+    th_corner<PL, SA, SB, LL, LL, LZ>(F, L, c, su, alpha[0], d1, d2);
+    th_corner<PL, SA, SB, LL, LL + 1, LZ>(F, L, c, su, alpha[1], d1, d2);
+    th_corner<PL, SA, SB, LL + 1, LL, LZ>(F, L, c, su, alpha[2], d1, d2);
+    th_corner<PL, SA, SB, LL + 1, LL + 1, LZ>(F, L, c, su, alpha[3], d1, d2);
     const double w = (1.0 / 15.0) * 0.70710678118654752440 * d1;
     S[A] += SA * w;
     S[B] += SB * w;
     Qs += (1.0 / 15.0) * d2;
 }
 
-template <int PL, int LL>
+template <int PL, int LL, bool LZ>
 __device__ __forceinline__ void th_plane(const Fields<double> &F, const LatticeDev &L, const ThCtx &c,
                                          const double *alpha, double S[3], double &Qs)
 {
-    th_diag<PL, 1, 1, LL>(F, L, c, alpha, S, Qs);
-    th_diag<PL, -1, -1, LL>(F, L, c, alpha, S, Qs);
-    th_diag<PL, 1, -1, LL>(F, L, c, alpha, S, Qs);
-    th_diag<PL, -1, 1, LL>(F, L, c, alpha, S, Qs);
+    th_diag<PL, 1, 1, LL, LZ>(F, L, c, alpha, S, Qs);
+    th_diag<PL, -1, -1, LL, LZ>(F, L, c, alpha, S, Qs);
+    th_diag<PL, 1, -1, LL, LZ>(F, L, c, alpha, S, Qs);
+    th_diag<PL, -1, 1, LL, LZ>(F, L, c, alpha, S, Qs);
 }
 
 // C^(1) with its temperature term, plus attraction and n g, and C^(2), at a
 // fluid node with moments (n, u) and temperature T; v_T^2 = T.
-template <int SIG>
+template <int SIG, bool LZ>
 __device__ __forceinline__ void th_node_force(const Fields<double> &F, const LatticeDev &L, const StepConst &sc,
                                               const double *__restrict__ chi, int x, int y, int z, double n,
                                               const double u[3], double T, double Fo[3], double &Qo)
@@ -1695,15 +1708,15 @@ __device__ __forceinline__ void th_node_force(const Fields<double> &F, const Lat
         c.i2T = 0.5 / T;
         c.ipv = 1.0 / (1.7724538509055160273 * vt);
         constexpr int LL = ell_of(SIG);
-        th_axis<0, 1, SIG>(F, L, c, S, Qs);
-        th_axis<0, -1, SIG>(F, L, c, S, Qs);
-        th_axis<1, 1, SIG>(F, L, c, S, Qs);
-        th_axis<1, -1, SIG>(F, L, c, S, Qs);
-        th_axis<2, 1, SIG>(F, L, c, S, Qs);
-        th_axis<2, -1, SIG>(F, L, c, S, Qs);
-        th_plane<0, LL>(F, L, c, sc.alpha, S, Qs);
-        th_plane<1, LL>(F, L, c, sc.alpha, S, Qs);
-        th_plane<2, LL>(F, L, c, sc.alpha, S, Qs);
+        th_axis<0, 1, SIG, LZ>(F, L, c, S, Qs);
+        th_axis<0, -1, SIG, LZ>(F, L, c, S, Qs);
+        th_axis<1, 1, SIG, LZ>(F, L, c, S, Qs);
+        th_axis<1, -1, SIG, LZ>(F, L, c, S, Qs);
+        th_axis<2, 1, SIG, LZ>(F, L, c, S, Qs);
+        th_axis<2, -1, SIG, LZ>(F, L, c, S, Qs);
+        th_plane<0, LL, LZ>(F, L, c, sc.alpha, S, Qs);
+        th_plane<1, LL, LZ>(F, L, c, sc.alpha, S, Qs);
+        th_plane<2, LL, LZ>(F, L, c, sc.alpha, S, Qs);
     }
     double Fa[3] = {0.0, 0.0, 0.0};
     if (sc.phi) att_force(L, sc, x, y, z, n, Fa);
@@ -1771,7 +1784,7 @@ __global__ __launch_bounds__(256, TH ? HSLB_COLLIDE39T_WAVES : HSLB_COLLIDE39_WA
         raw_herm39(f, a2, a3, std::make_integer_sequence<int, Q39>{});
         sub_eq_moments(n, u, T - CS2_39, a2, a3);
         double Q;
-        th_node_force<SIG>(fld, L, sc, chi, x, y, z, n, u, T, Fv, Q);
+        th_node_force<SIG, true>(fld, L, sc, chi, x, y, z, n, u, T, Fv, Q);
         double A[20];
         post_coeffs<true>(n, u, th1, om, Fv, Q, a2, a3, A);
         emit39_poly(L, fout, x, y, z, A, std::make_integer_sequence<int, Q39>{});
@@ -1800,7 +1813,7 @@ __global__ __launch_bounds__(256) void k_force39(LatticeDev L, StepConst sc, con
         const double inv_n = (n != 0.0) ? 1.0 / n : 0.0;
         const double u[3] = {jx * inv_n, jy * inv_n, jz * inv_n};
         if constexpr (TH)
-            th_node_force<SIG>(fld, L, sc, chi, x, y, z, n, u, temp_of(n, jx, jy, jz, e), Fv, Q);
+            th_node_force<SIG, false>(fld, L, sc, chi, x, y, z, n, u, temp_of(n, jx, jy, jz, e), Fv, Q);
         else
             node_force<SIG, false, double, false>(fld, L, sc, chi, x, y, z, n, u, Fv);
     }
