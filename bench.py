@@ -277,7 +277,7 @@ def main():
     ap.add_argument("--surrogate-epochs", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the library has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
