@@ -140,10 +140,10 @@ def test_full_size_two_steps():
 
 @pytest.mark.parametrize("thermal", [0, 1])
 def test_graph_and_eager_steps_agree_and_watchdog_passes(thermal):
-    """The captured two-step graphs and the eager launches run the same kernels
-    in the same order: 11 steps (5 graph replays and one eager step, against 11
-    eager steps) give identical populations; the watchdog (mass and finiteness
-    every 4 steps, through the 39-velocity profile kernel) stays quiet."""
+    """The captured graphs (16-step and 2-step) and the eager launches run the
+    same kernels in the same order: 11 steps with the watchdog on (mass and
+    finiteness every 4 steps, through the 39-velocity profile kernel), then 35
+    without it, give populations identical to eager stepping."""
     case = CASES[6]
     nx, ny, nz, sigma, walls, fm, lam = case
     n, u = _state(case, seed=34)
@@ -160,4 +160,10 @@ def test_graph_and_eager_steps_agree_and_watchdog_passes(thermal):
         s.init(n, u, T)
         s.step(11)
     assert hslb.hslb_step_count(a.ctx) == 11
+    assert np.array_equal(a.get_populations(), b.get_populations())
+    # without the watchdog's 4-step chunks: 16-step graphs, a 2-step graph and
+    # an eager step (35 = 2 x 16 + 2 + 1)
+    hslb.hslb_set_watchdog(a.ctx, 0, 1e-10)
+    a.step(35)
+    b.step(35)
     assert np.array_equal(a.get_populations(), b.get_populations())
