@@ -241,6 +241,30 @@ def d3q39_leg(hslb, np, wl, n, u, steps: int, thermal: bool = False):
             "state_finite_after": finite}
 
 
+def fp64_leg(hslb, wl, n, u, steps: int):
+    """The benchmark slit with FP64 population storage (all else equal):
+    throughput over `steps` graph-replayed steps and the collide kernel's time.
+    Two FP64 population copies (2 x 85 MB) exceed the 128 MiB threshold of the
+    non-temporal collide instance."""
+    s = hslb.Sim.from_workload(wl, precision="f64")
+    s.init(n, u)
+    s.step(20)
+    s.sync()
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.sync()
+    dt = time.perf_counter() - t0
+    hslb.hslb_set_kernel_timing(s.ctx, True)
+    s.step(min(steps, 200))
+    s.sync()
+    kt = hslb.hslb_kernel_times(s.ctx)
+    s.close()
+    return {"workload": f"{wl.name} with FP64 storage", "steps": steps,
+            "value": round(wl.fluid_nodes * steps / dt / 1e6, 1), "unit": "MLUPS",
+            "ms_per_step": round(dt / steps * 1e3, 5),
+            "kernels_us": {k: round(v[0] / v[1] * 1e3, 2) for k, v in kt.items()}}
+
+
 def cpu_baseline(wl, n, u, budget_s: float):
     import oracle
     o = oracle.Oracle(**wl.params())
@@ -274,6 +298,7 @@ def main():
     ap.add_argument("--no-obstacle", action="store_true")
     ap.add_argument("--no-d3q39", action="store_true")
     ap.add_argument("--no-thermal", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--surrogate-epochs", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -373,6 +398,11 @@ def main():
         print("bench: obstacle", file=sys.stderr, flush=True)
         obst = obstacle_leg(hslb, np, wl, n, u, args.steps)
 
+    f64 = None
+    if not args.no_fp64:
+        print("bench: FP64 storage", file=sys.stderr, flush=True)
+        f64 = fp64_leg(hslb, wl, n, u, min(args.steps, 1000))
+
     q39 = None
     if not args.no_d3q39:
         print("bench: 39-velocity lattice", file=sys.stderr, flush=True)
@@ -414,6 +444,7 @@ def main():
         "surrogate": surr,
         "attraction": att,
         "obstacle": obst,
+        "fp64_storage": f64,
         "d3q39": q39,
         "d3q39_thermal": q39t,
         "roofline": roof,
