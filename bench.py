@@ -265,6 +265,34 @@ def fp64_leg(hslb, wl, n, u, steps: int):
             "kernels_us": {k: round(v[0] / v[1] * 1e3, 2) for k, v in kt.items()}}
 
 
+def bulk_leg(hslb, workloads, steps: int):
+    """The 256^3 periodic bulk (sigma 6, packing 0.25, FP32 storage, shear wave
+    and density noise as its recipe states): throughput over `steps`
+    graph-replayed steps and the per-kernel times.  Its two population copies
+    (2 x 1.27 GB) overflow the last-level cache, so the collide runs the
+    non-temporal instance."""
+    wl = workloads.bulk_256_f32()
+    n, u = wl.fields()
+    s = hslb.Sim.from_workload(wl)
+    s.init(n, u)
+    del n, u
+    s.step(20)
+    s.sync()
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.sync()
+    dt = time.perf_counter() - t0
+    hslb.hslb_set_kernel_timing(s.ctx, True)
+    s.step(min(steps, 100))
+    s.sync()
+    kt = hslb.hslb_kernel_times(s.ctx)
+    s.close()
+    return {"workload": wl.name, "steps": steps,
+            "value": round(wl.fluid_nodes * steps / dt / 1e6, 1), "unit": "MLUPS",
+            "ms_per_step": round(dt / steps * 1e3, 5),
+            "kernels_us": {k: round(v[0] / v[1] * 1e3, 2) for k, v in kt.items()}}
+
+
 def cpu_baseline(wl, n, u, budget_s: float):
     import oracle
     o = oracle.Oracle(**wl.params())
@@ -299,6 +327,7 @@ def main():
     ap.add_argument("--no-d3q39", action="store_true")
     ap.add_argument("--no-thermal", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-bulk", action="store_true")
     ap.add_argument("--surrogate-epochs", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -403,6 +432,11 @@ def main():
         print("bench: FP64 storage", file=sys.stderr, flush=True)
         f64 = fp64_leg(hslb, wl, n, u, min(args.steps, 1000))
 
+    bulk = None
+    if not args.no_bulk:
+        print("bench: 256^3 bulk", file=sys.stderr, flush=True)
+        bulk = bulk_leg(hslb, workloads, min(args.steps, 300))
+
     q39 = None
     if not args.no_d3q39:
         print("bench: 39-velocity lattice", file=sys.stderr, flush=True)
@@ -445,6 +479,7 @@ def main():
         "attraction": att,
         "obstacle": obst,
         "fp64_storage": f64,
+        "bulk": bulk,
         "d3q39": q39,
         "d3q39_thermal": q39t,
         "roofline": roof,
