@@ -60,6 +60,7 @@ def _kernel_source_hash() -> str:
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_collide_slit64x64x136_s8.txt")
 TRAFFIC39_FILE = os.path.join(ROOT, "profiles", "traffic_collide39_slit64x64x136_s8.txt")
 TRAFFIC39T_FILE = os.path.join(ROOT, "profiles", "traffic_collide39_thermal_slit64x64x136_s8.txt")
+TRAFFIC_BULK_FILE = os.path.join(ROOT, "profiles", "traffic_collide_bulk256_s6.txt")
 
 
 def _traffic(workload: str, path: str = TRAFFIC_FILE):
@@ -287,9 +288,15 @@ def bulk_leg(hslb, workloads, steps: int):
     s.sync()
     kt = hslb.hslb_kernel_times(s.ctx)
     s.close()
+    col_s = kt["collide"][0] / kt["collide"][1] * 1e-3
+    col_gbps = COLLIDE_BYTES * wl.fluid_nodes / col_s / 1e9
     return {"workload": wl.name, "steps": steps,
             "value": round(wl.fluid_nodes * steps / dt / 1e6, 1), "unit": "MLUPS",
             "ms_per_step": round(dt / steps * 1e3, 5),
+            "collide_us": round(col_s * 1e6, 2), "collide_GBps": round(col_gbps, 1),
+            "collide_hbm_frac": round(col_gbps / PEAK_HBM_GBPS, 4),
+            "collide_algorithmic_bytes": int(COLLIDE_BYTES * wl.fluid_nodes),
+            "collide_traffic": _traffic(wl.name, TRAFFIC_BULK_FILE),
             "kernels_us": {k: round(v[0] / v[1] * 1e3, 2) for k, v in kt.items()}}
 
 
