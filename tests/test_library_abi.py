@@ -45,6 +45,9 @@ def test_library_exports_every_declared_symbol(lib):
     dict(g2_model=3), dict(force_mode=5), dict(accel=(float("nan"), 0.0, 0.0)),
     dict(att_eps=1e-3, att_range=0.0), dict(att_eps=1e-3, att_range=10.5),
     dict(att_eps=float("inf"), att_range=2.0),
+    # empty and degenerate grids, and grids beyond 32-bit node indices
+    dict(nx=0), dict(ny=0), dict(nz=0), dict(nx=-4), dict(nz=3, wall_lo=2, wall_hi=2),
+    dict(nx=1 << 20, ny=1 << 20), dict(tau=float("nan")), dict(tau=float("inf")),
 ])
 def test_create_rejects_bad_parameters(lib, bad):
     kw = dict(nx=12, ny=12, nz=20, sigma=4, tau=1.0, wall_lo=2, wall_hi=2)
