@@ -117,3 +117,19 @@ def test_trainer_and_network_op_arguments_are_validated(lib):
     with pytest.raises(lib.HslbError) as ei:
         lib.hslb_cnn_op(lib.HSLB_CNN_DW2, 32, 4, 4, True, w, np.zeros(32 * 512))  # aux missing
     assert ei.value.code == lib.HSLB_EINVAL
+
+
+def test_batch_arguments_are_validated(lib):
+    """An empty batch, mixed storage precisions and an invalid slit among valid
+    ones are rejected before any device work; the error names the slit."""
+    with pytest.raises(lib.HslbError) as ei:
+        lib.hslb_batch_create([])
+    assert ei.value.code == lib.HSLB_EINVAL
+    ok = lambda prec: lib.make_params(16, 16, 24, 4, 1.0, wall_lo=2, wall_hi=2, precision=prec)  # noqa: E731
+    with pytest.raises(lib.HslbError) as ei:
+        lib.hslb_batch_create([ok(lib.HSLB_FP32), ok(lib.HSLB_FP64)])
+    assert ei.value.code == lib.HSLB_EINVAL and "mixed precisions" in str(ei.value)
+    bad = lib.make_params(16, 16, 24, 4, 0.5, wall_lo=2, wall_hi=2, precision=lib.HSLB_FP32)
+    with pytest.raises(lib.HslbError) as ei:
+        lib.hslb_batch_create([ok(lib.HSLB_FP32), ok(lib.HSLB_FP32), bad])
+    assert ei.value.code == lib.HSLB_EINVAL and "slit 2" in str(ei.value)
