@@ -154,6 +154,26 @@ def test_fp32_slit_against_oracle(lateral):
     assert rel(gn, on) <= 1e-5 and rel(gu, ou) <= 1e-5
 
 
+def test_slit_64_fp64_storage_full_size():
+    """The benchmarked slit (64x64x136, sigma 8, packing 0.25) with FP64
+    population storage, as the FP64-storage benchmark runs it: its two copies
+    (2 x 19 x 8 B x 557056 nodes, 169 MB) exceed 128 MiB, so the collide runs the
+    instance with non-temporal population loads and stores. Two GPU steps from
+    the workload's initial state against two oracle steps, every population."""
+    wl = workloads.slit_64_f32_stable()
+    n, u = wl.fields()
+    assert 2 * 19 * 8 * wl.nx * wl.ny * wl.nz > 128 * 2 ** 20
+    g = hslb.Sim.from_workload(wl, precision="f64")
+    g.init(n, u)
+    g.step(2)
+    o = oracle.Oracle(**wl.params())
+    o.init(n, u)
+    o.step(2)
+    err = rel(g.get_populations(), o.get_populations())
+    print(f"64x64x136 FP64 storage, 2 steps: relative difference {err:.3e}", flush=True)
+    assert err <= 1e-12
+
+
 @pytest.mark.parametrize("maker,before", [(workloads.slit_64_f32, 3),
                                           (workloads.slit_64_f32_stable, 300)],
                          ids=["eta0.35", "eta0.25"])
