@@ -1,19 +1,21 @@
 """Throughput of the hard-sphere lattice Boltzmann step on one MI355X.
 
-Workload: the 64x64x136 slit (128 fluid layers), sigma 8, tau 0.8, g 2e-6
-along x, FP32 populations with FP64 arithmetic, exact shell-sum force: the
-plain path of the benchmark metric.  The slit is specified at packing fraction
-0.35, where the scheme diverges a few hundred steps after the uniform start;
-the timed run uses packing fraction 0.25 (same grid, stencil and cost per
-step; 0.30 and above diverge on this grid), and the 0.35 slit is timed
-separately over 250 steps.  Inputs are seeded and synthetic (paper_0712_2247_amd.workloads).
+Headline workload: the 256^3 periodic bulk (sigma 6, packing fraction 0.25,
+tau 1, a shear wave u_x = 1e-3 sin(2 pi z / 256) and Gaussian density noise of
+relative amplitude 1e-3), FP32 populations, exact shell-sum force: the largest
+single-GPU configuration of the benchmark metric.  Inputs are seeded and
+synthetic (paper_0712_2247_amd.workloads).
 
 A step is one pass of the whole hot path: moments, coarse-grained density,
 midpoint contact values, hard-sphere force plus external field, BGK collision,
-streaming with bounce-back.  The state stays resident in HBM; the timed region
-is K steps replayed from the library's HIP graphs, bracketed by stream
-synchronisation.  A second pass of K steps launches kernel by kernel with HIP
-events on the library's stream to time each kernel (roofline).
+streaming with bounce-back.  The state stays resident in HBM.  After the
+warmup every HIP graph the timed steps replay is captured (hslb_prepare), then
+K steps run from those graphs, bracketed by stream synchronisation.  A second
+pass launches kernel by kernel with HIP events on the library's stream to time
+each kernel (roofline).  Further legs time the 64x64x136 slit (sigma 8, at
+packing 0.25, and as specified at 0.35 where it diverges), the 512-slit
+ensemble, the learned force, the attraction, a solid obstacle, FP64 storage and
+the 39-velocity lattices; the FP64 CPU oracle is timed on the host.
 
 Prints one JSON line.
 """
@@ -47,6 +49,47 @@ COLLIDE39_BYTES = 656.0
 STEP39T_BYTES = 704.0
 COLLIDE39T_BYTES = 664.0
 DOMINANT = "collide"
+GOLDEN_SLIT = os.path.join(ROOT, "tests", "golden", "slit_64x64x136_eta0.25_profiles.json")
+
+
+def _timed(sim, warmup: int, steps: int):
+    """`warmup` steps, capture of every graph the timed steps replay, then
+    `steps` steps between stream synchronisations: seconds."""
+    sim.step(warmup)
+    sim.prepare()
+    sim.sync()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    return time.perf_counter() - t0
+
+
+def _kernel_pass(hslb, sim, steps: int):
+    """`steps` steps launched kernel by kernel, each bracketed by HIP events on
+    the library's stream: {name: (total ms, launches)}."""
+    hslb.hslb_set_kernel_timing(sim.ctx, True)
+    sim.step(steps)
+    sim.sync()
+    kt = hslb.hslb_kernel_times(sim.ctx)
+    hslb.hslb_set_kernel_timing(sim.ctx, False)
+    return kt
+
+
+def _roofline(kt, fluid_nodes: int, workload: str, traffic_file: str):
+    """Roofline of the collide kernel: the step's algorithmic 184 B per
+    fluid-node update (and the kernel's own 168 B share) over its average
+    launch time."""
+    avg_s = kt[DOMINANT][0] / kt[DOMINANT][1] * 1e-3
+    per_launch = STEP_BYTES * fluid_nodes
+    achieved = per_launch / avg_s / 1e9
+    own = COLLIDE_BYTES * fluid_nodes / avg_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
+            "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
+            "traffic": _traffic(workload, traffic_file), "kernel": "k_collide",
+            "algorithmic_bytes_per_launch": per_launch, "bytes_per_node": STEP_BYTES,
+            "kernel_share_bytes_per_node": COLLIDE_BYTES,
+            "kernel_share_frac": round(own / PEAK_HBM_GBPS, 4),
+            "avg_launch_us": round(avg_s * 1e6, 2)}
 
 
 def _kernel_source_hash() -> str:
@@ -87,12 +130,7 @@ def ensemble_throughput(hslb, workloads, steps: int):
     b = hslb.Batch(wls)
     b.init_all()
     choice, us = b.autotune(steps=10)
-    b.step(20)
-    b.sync()
-    t0 = time.perf_counter()
-    b.step(steps)
-    b.sync()
-    dt = time.perf_counter() - t0
+    dt = _timed(b, 20, steps)
     fin = int(b.finite().sum())
     out = {"workload": f"{len(wls)} slits 16x16x(H+walls), H 10..60, sigma 3..8, packing 0.10..0.40",
            "fluid_nodes": b.fluid_nodes, "steps": steps,
@@ -106,12 +144,25 @@ def ensemble_throughput(hslb, workloads, steps: int):
 PEAK_BF16_TFLOPS = 2500.0
 
 
-def surrogate_leg(hslb, workloads, wl, steps: int, epochs: int):
-    """The learned force on the benchmark slit: snapshots of the 40 training
-    slits (64x64xnz, sigma 4..8, stable runs only), Adam on the GPU, then the
-    surrogate path (exact judge every 50 steps, residual threshold 1e-3) with
-    the network plus frozen correction and without the network (frozen exact
-    force: the ablation), each against the exact path's profiles."""
+def _golden_profiles(step: int):
+    """n(z), u(z) of the FP64 oracle's run of the 64x64x136 slit at packing
+    0.25 after `step` steps (tests/golden, written by make_golden.py)."""
+    import numpy as np
+    with open(GOLDEN_SLIT) as fh:
+        snap = json.load(fh)["snapshots"][str(step)]
+    return np.array(snap["n_z"]), np.array(snap["u_z"])
+
+
+def surrogate_leg(hslb, np, workloads, wl, steps: int, epochs: int):
+    """The learned force on the 64x64x136 slit at packing 0.25: snapshots of
+    the 40 training slits (64x64xnz, sigma 4..8, stable runs only), Adam on
+    the GPU, then `steps` steps of the surrogate path (exact judge every 50
+    steps, residual threshold 1e-3) with the network plus frozen correction,
+    and without the network (frozen exact force: the ablation), against the
+    FP64 oracle's profiles of the same slit after the same number of steps.
+    `network_steps` counts the steps that applied the network's force; a mode
+    whose every step fell back to the exact force has measured only the exact
+    path."""
     from paper_0712_2247_amd import surrogate
     runs = workloads.surrogate_training_runs()
     tr = hslb.Trainer(sum(w.nodes for w in runs) * 100 + 1, max(w.nodes for w in runs))
@@ -122,16 +173,28 @@ def surrogate_leg(hslb, workloads, wl, steps: int, epochs: int):
     res = surrogate.train(tr, workloads.cnn_init_weights(), snaps, epochs, 1e-3)
     w = res["weights"]
     tr.close()
-    ref = surrogate.exact_profiles(wl, steps)
-    out = {"training": {"runs": len(runs), "stable_runs": sum(r["stable"] for r in recs),
+    ref = _golden_profiles(steps)
+    exact = surrogate.exact_profiles(wl, steps)
+    fl = slice(wl.wall_lo, wl.nz - wl.wall_hi)
+    out = {"workload": wl.name, "steps": steps, "reference": f"FP64 oracle, step {steps}",
+           "training": {"runs": len(runs), "stable_runs": sum(r["stable"] for r in recs),
                         "snapshots": len(snaps), "epochs": epochs, "adam_steps": res["steps"],
                         "mean_loss_per_epoch": [float(v) for v in res["losses"]],
-                        "collect_s": round(t_collect, 1), "train_s": round(res["seconds"], 1)}}
+                        "collect_s": round(t_collect, 1), "train_s": round(res["seconds"], 1)},
+           "exact_path_err_n": float(np.linalg.norm(exact[0][fl] - ref[0][fl]) / np.linalg.norm(ref[0][fl])),
+           "exact_path_err_ux": float(np.linalg.norm(exact[1][0][fl] - ref[1][0][fl]) /
+                                      np.linalg.norm(ref[1][0][fl]))}
     for mode in (hslb.HSLB_SURR_CORRECTED, hslb.HSLB_SURR_FROZEN):
         r = surrogate.evaluate(wl, w, steps, 50, 1e-3, mode, reference=ref)
+        done = r["steps"] if r["diverged_at_step"] is None else r["diverged_at_step"]
+        # steps that used the surrogate force (network or frozen correction)
+        # rather than an exact check or an exact fallback step
+        r["surrogate_steps"] = int(done - r["checks"] - r["fallback_steps"])
+        r["network_steps"] = r["surrogate_steps"] if mode != hslb.HSLB_SURR_FROZEN else 0
+        r["measured"] = r["surrogate_steps"] > 0 and r["diverged_at_step"] is None
         out[r["mode"]] = r
         print(f"bench: surrogate {r['mode']}: {r}", file=sys.stderr, flush=True)
-    # network kernel times on the benchmark slit (eager, HIP events)
+    # network kernel times on the slit (eager, HIP events)
     s = hslb.Sim.from_workload(wl, force_mode=hslb.HSLB_FORCE_SURROGATE, surr_check_every=50, surr_tol=1e-3)
     hslb.hslb_surrogate_set_weights(s.ctx, w)
     n, u = wl.fields()
@@ -157,12 +220,7 @@ def attraction_leg(hslb, wl, n, u, steps: int):
     lam = wl.sigma / 2.0
     s = hslb.Sim.from_workload(wl, att_eps=1e-3, att_range=lam)
     s.init(n, u)
-    s.step(20)
-    s.sync()
-    t0 = time.perf_counter()
-    s.step(steps)
-    s.sync()
-    dt = time.perf_counter() - t0
+    dt = _timed(s, 20, steps)
     hslb.hslb_set_kernel_timing(s.ctx, True)
     s.step(min(steps, 200))
     s.sync()
@@ -185,12 +243,7 @@ def obstacle_leg(hslb, np, wl, n, u, steps: int):
     s = hslb.Sim.from_workload(wl)
     s.set_solid(m)
     s.init(n, u)
-    s.step(20)
-    s.sync()
-    t0 = time.perf_counter()
-    s.step(steps)
-    s.sync()
-    dt = time.perf_counter() - t0
+    dt = _timed(s, 20, steps)
     finite = bool(np.isfinite(s.moments()[0]).all())
     s.close()
     return {"workload": f"{wl.name} + solid cylinder (radius {wl.sigma}, axis along y)",
@@ -214,12 +267,7 @@ def d3q39_leg(hslb, np, wl, n, u, steps: int, thermal: bool = False):
         s.init(n, u, T)
     else:
         s.init(n, u)
-    s.step(20)
-    s.sync()
-    t0 = time.perf_counter()
-    s.step(steps)
-    s.sync()
-    dt = time.perf_counter() - t0
+    dt = _timed(s, 20, steps)
     hslb.hslb_set_kernel_timing(s.ctx, True)
     s.step(min(steps, 200))
     s.sync()
@@ -249,12 +297,7 @@ def fp64_leg(hslb, wl, n, u, steps: int):
     non-temporal collide instance."""
     s = hslb.Sim.from_workload(wl, precision="f64")
     s.init(n, u)
-    s.step(20)
-    s.sync()
-    t0 = time.perf_counter()
-    s.step(steps)
-    s.sync()
-    dt = time.perf_counter() - t0
+    dt = _timed(s, 20, steps)
     hslb.hslb_set_kernel_timing(s.ctx, True)
     s.step(min(steps, 200))
     s.sync()
@@ -266,67 +309,97 @@ def fp64_leg(hslb, wl, n, u, steps: int):
             "kernels_us": {k: round(v[0] / v[1] * 1e3, 2) for k, v in kt.items()}}
 
 
-def bulk_leg(hslb, workloads, steps: int):
-    """The 256^3 periodic bulk (sigma 6, packing 0.25, FP32 storage, shear wave
-    and density noise as its recipe states): throughput over `steps`
-    graph-replayed steps and the per-kernel times.  Its two population copies
-    (2 x 1.27 GB) overflow the last-level cache, so the collide runs the
-    non-temporal instance."""
-    wl = workloads.bulk_256_f32()
-    n, u = wl.fields()
+def slit_leg(hslb, np, wl, n, u, warmup: int, steps: int):
+    """The 64x64x136 slit (sigma 8, tau 0.8, g 2e-6) at packing 0.25: graph
+    throughput, per-kernel times and the collide kernel's roofline.  Its
+    working set (2 x 42 MB of populations and the moment fields) fits the
+    last-level cache."""
     s = hslb.Sim.from_workload(wl)
     s.init(n, u)
-    del n, u
-    s.step(20)
-    s.sync()
-    t0 = time.perf_counter()
-    s.step(steps)
-    s.sync()
-    dt = time.perf_counter() - t0
-    hslb.hslb_set_kernel_timing(s.ctx, True)
-    s.step(min(steps, 100))
-    s.sync()
-    kt = hslb.hslb_kernel_times(s.ctx)
+    dt = _timed(s, warmup, steps)
+    kt = _kernel_pass(hslb, s, steps)
+    finite = bool(np.isfinite(s.moments()[0]).all())
     s.close()
-    col_s = kt["collide"][0] / kt["collide"][1] * 1e-3
-    col_gbps = COLLIDE_BYTES * wl.fluid_nodes / col_s / 1e9
-    return {"workload": wl.name, "steps": steps,
-            "value": round(wl.fluid_nodes * steps / dt / 1e6, 1), "unit": "MLUPS",
+    mlups = wl.fluid_nodes * steps / dt / 1e6
+    return {"workload": wl.name, "steps": steps, "value": round(mlups, 1), "unit": "MLUPS",
             "ms_per_step": round(dt / steps * 1e3, 5),
-            "collide_us": round(col_s * 1e6, 2), "collide_GBps": round(col_gbps, 1),
-            "collide_hbm_frac": round(col_gbps / PEAK_HBM_GBPS, 4),
-            "collide_algorithmic_bytes": int(COLLIDE_BYTES * wl.fluid_nodes),
-            "collide_traffic": _traffic(wl.name, TRAFFIC_BULK_FILE),
-            "kernels_us": {k: round(v[0] / v[1] * 1e3, 2) for k, v in kt.items()}}
+            "step_hbm_frac": round(mlups * 1e6 * STEP_BYTES / 1e9 / PEAK_HBM_GBPS, 4),
+            "roofline": _roofline(kt, wl.fluid_nodes, wl.name, TRAFFIC_FILE),
+            "kernels_us": {k: round(v[0] / v[1] * 1e3, 2) for k, v in kt.items()},
+            "state_finite_after": finite}
 
 
-def cpu_baseline(wl, n, u, budget_s: float):
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(wl, n, u, budget_s: float, min_steps: int = 2):
+    """Fluid-node updates per second of the oracle stepping `wl` from (n, u):
+    whole steps until `budget_s` seconds have passed (after one untimed
+    step); (MLUPS, steps, seconds)."""
     import oracle
     o = oracle.Oracle(**wl.params())
     o.init(n, u)
-    o.step(1)  # first-touch
+    o.step(1)  # first touch
     steps = 0
     t0 = time.perf_counter()
     while True:
         o.step(1)
         steps += 1
         dt = time.perf_counter() - t0
-        if dt >= budget_s and steps >= 2:
+        if dt >= budget_s and steps >= min_steps:
             break
-    return {"value": wl.fluid_nodes * steps / dt / 1e6, "unit": "MLUPS",
-            "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"{steps} full steps of the {wl.nx}x{wl.ny}x{wl.nz} slit, FP64 C oracle, "
-                      f"OpenMP, {dt:.1f} s"}
+    del o
+    return wl.fluid_nodes * steps / dt / 1e6, steps, dt
+
+
+def cpu_baseline(workloads, wl, n, u, budget_s: float):
+    """The FP64 CPU oracle (C, OpenMP over z layers) on the host cores: on the
+    headline workload with every core it may use, and at one thread on the
+    64x64x136 slit (a few steps) and the 8x8x24 slit."""
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    oracle.set_threads(cores)
+    v, k, dt = _oracle_rate(wl, n, u, budget_s)
+    out = {"value": v, "unit": "MLUPS", "cores": oracle.max_threads(), "kind": "oracle",
+           "sample": f"{k} full steps of the {wl.nx}x{wl.ny}x{wl.nz} {wl.name}, FP64 C oracle "
+                     f"(gcc {' '.join(oracle.CFLAGS)}), OpenMP, {dt:.1f} s",
+           "cpu_model": _cpu_model()}
+    others = {}
+    slit = workloads.slit_64_f32_stable()
+    sn, su = slit.fields()
+    v2, k2, dt2 = _oracle_rate(slit, sn, su, budget_s / 4)
+    others[slit.name] = {"value": round(v2, 3), "threads": oracle.max_threads(), "steps": k2,
+                         "seconds": round(dt2, 2)}
+    oracle.set_threads(1)
+    v1, k1, dt1 = _oracle_rate(slit, sn, su, budget_s / 4)
+    others[slit.name + " one thread"] = {"value": round(v1, 3), "threads": 1, "steps": k1,
+                                         "seconds": round(dt1, 2)}
+    small = workloads.slit_small_f64()
+    mn, mu = small.fields()
+    v3, k3, dt3 = _oracle_rate(small, mn, mu, 1.0)
+    others[small.name + " one thread"] = {"value": round(v3, 3), "threads": 1, "steps": k3,
+                                          "seconds": round(dt3, 2)}
+    oracle.set_threads(cores)
+    out["others"] = others
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-pass", action="store_true")
+    ap.add_argument("--no-slit", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-attraction", action="store_true")
@@ -334,8 +407,11 @@ def main():
     ap.add_argument("--no-d3q39", action="store_true")
     ap.add_argument("--no-thermal", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--no-bulk", action="store_true")
+    ap.add_argument("--no-bulk", action="store_true",
+                    help="no effect: the bulk is the headline workload (accepted for older profile commands)")
     ap.add_argument("--surrogate-epochs", type=int, default=2)
+    ap.add_argument("--surrogate-steps", type=int, default=5000,
+                    help="steps of each surrogate-path run (a step count of the oracle's stored run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the library has no "
@@ -347,12 +423,13 @@ def main():
 
     from paper_0712_2247_amd import hslb, workloads
 
-    wl = workloads.slit_64_f32_stable()
+    wl = workloads.bulk_256_f32()
     n, u = wl.fields()
     sim = hslb.Sim.from_workload(wl)
     sim.init(n, u)
     print(f"bench: {wl.name} warmup {args.warmup}", file=sys.stderr, flush=True)
     sim.step(args.warmup)
+    sim.prepare()
     sim.sync()
     torch.cuda.synchronize()
 
@@ -365,18 +442,37 @@ def main():
     mlups = wl.fluid_nodes * args.steps / dt / 1e6
     print(f"bench: timed {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
 
+    roof = None
+    kernels = {}
+    if not args.no_kernel_pass:
+        kt = _kernel_pass(hslb, sim, min(args.steps, 100))
+        kernels = {k: {"avg_us": v[0] / v[1] * 1e3, "launches": v[1]} for k, v in kt.items()}
+        roof = _roofline(kt, wl.fluid_nodes, wl.name, TRAFFIC_BULK_FILE)
+        print(f"bench: kernel pass {kernels}", file=sys.stderr, flush=True)
+
+    gn, _ = sim.moments()
+    assert np.isfinite(gn).all(), "non-finite state"
+    del gn
+    sim.close()
+
+    copy_gbps = hslb.hslb_copy_bandwidth(1 << 30, 20)
+    print(f"bench: device copy {copy_gbps:.0f} GB/s", file=sys.stderr, flush=True)
+
+    swl = workloads.slit_64_f32_stable()
+    sn, su = swl.fields()
+    slit = None
+    if not args.no_slit:
+        print("bench: slit", file=sys.stderr, flush=True)
+        slit = slit_leg(hslb, np, swl, sn, su, args.warmup, max(args.steps, 200))
+
     # the slit as specified (eta 0.35), timed before it diverges
     spec = workloads.slit_64_f32()
-    sn, su = spec.fields()
+    pn, pu = spec.fields()
     ssim = hslb.Sim.from_workload(spec)
-    ssim.init(sn, su)
-    ssim.step(20)
-    ssim.sync()
-    k_spec = min(args.steps, 250)
-    t1 = time.perf_counter()
-    ssim.step(k_spec)
-    ssim.sync()
-    dt_spec = time.perf_counter() - t1
+    hslb.hslb_set_watchdog(ssim.ctx, 0, 0.0)   # timed on its diverged state on purpose
+    ssim.init(pn, pu)
+    k_spec = 250
+    dt_spec = _timed(ssim, 20, k_spec)
     spec_finite = bool(np.isfinite(ssim.moments()[0]).all())
     ssim.close()
     as_specified = {"workload": spec.name, "steps": k_spec,
@@ -388,77 +484,47 @@ def main():
                             "steps 20-270 on the diverged state: work and traffic per step do "
                             "not depend on the values"}
 
-    roof = None
-    kernels = {}
-    if not args.no_kernel_pass:
-        hslb.hslb_set_kernel_timing(sim.ctx, True)
-        sim.step(args.steps)
-        sim.sync()
-        kt = hslb.hslb_kernel_times(sim.ctx)
-        hslb.hslb_set_kernel_timing(sim.ctx, False)
-        kernels = {k: {"avg_us": v[0] / v[1] * 1e3, "launches": v[1]} for k, v in kt.items()}
-        avg_s = kt[DOMINANT][0] / kt[DOMINANT][1] * 1e-3
-        per_launch = COLLIDE_BYTES * wl.fluid_nodes
-        achieved = per_launch / avg_s / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
-                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
-                "traffic": _traffic(wl.name), "kernel": "k_collide",
-                "algorithmic_bytes_per_launch": per_launch,
-                "avg_launch_us": round(avg_s * 1e6, 2)}
-        print(f"bench: kernel pass {kernels}", file=sys.stderr, flush=True)
-
-    gn, gu = sim.moments()
-    assert np.isfinite(gn).all(), "non-finite state"
-    sim.close()
-
-    copy_gbps = hslb.hslb_copy_bandwidth(1 << 30, 20)
-    print(f"bench: device copy {copy_gbps:.0f} GB/s", file=sys.stderr, flush=True)
-
     ens = None
     if not args.no_ensemble:
         print("bench: ensemble", file=sys.stderr, flush=True)
-        ens = ensemble_throughput(hslb, workloads, min(args.steps, 500))
+        ens = ensemble_throughput(hslb, workloads, max(min(args.steps, 500), 100))
 
     surr = None
     if not args.no_surrogate:
         print("bench: surrogate", file=sys.stderr, flush=True)
-        surr = surrogate_leg(hslb, workloads, wl, args.steps, args.surrogate_epochs)
+        surr = surrogate_leg(hslb, np, workloads, swl, args.surrogate_steps, args.surrogate_epochs)
 
     att = None
     if not args.no_attraction:
         print("bench: attraction", file=sys.stderr, flush=True)
-        att = attraction_leg(hslb, wl, n, u, args.steps)
+        att = attraction_leg(hslb, swl, sn, su, max(args.steps, 200))
 
     obst = None
     if not args.no_obstacle:
         print("bench: obstacle", file=sys.stderr, flush=True)
-        obst = obstacle_leg(hslb, np, wl, n, u, args.steps)
+        obst = obstacle_leg(hslb, np, swl, sn, su, max(args.steps, 200))
 
     f64 = None
     if not args.no_fp64:
         print("bench: FP64 storage", file=sys.stderr, flush=True)
-        f64 = fp64_leg(hslb, wl, n, u, min(args.steps, 1000))
-
-    bulk = None
-    if not args.no_bulk:
-        print("bench: 256^3 bulk", file=sys.stderr, flush=True)
-        bulk = bulk_leg(hslb, workloads, min(args.steps, 300))
+        f64 = fp64_leg(hslb, swl, sn, su, max(min(args.steps, 1000), 200))
 
     q39 = None
     if not args.no_d3q39:
         print("bench: 39-velocity lattice", file=sys.stderr, flush=True)
-        q39 = d3q39_leg(hslb, np, wl, n, u, min(args.steps, 1000))
+        q39 = d3q39_leg(hslb, np, swl, sn, su, max(min(args.steps, 1000), 200))
 
     q39t = None
     if not args.no_thermal:
         print("bench: 39-velocity lattice, non-isothermal", file=sys.stderr, flush=True)
-        q39t = d3q39_leg(hslb, np, wl, n, u, min(args.steps, 500), thermal=True)
+        q39t = d3q39_leg(hslb, np, swl, sn, su, max(min(args.steps, 500), 200), thermal=True)
 
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(wl, n, u, args.cpu_seconds)
+        cpu = cpu_baseline(workloads, wl, n, u, args.cpu_seconds)
 
+    summed = sum(v["avg_us"] for v in kernels.values()) / 1e3 if kernels else None
     out = {
         "metric": "MLUPS incl. HS force: plain FP32 vs surrogate at <=1e-3 profile err; % HBM BW",
         "value": round(mlups, 1),
@@ -470,23 +536,25 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "grid": [wl.nx, wl.ny, wl.nz],
                    "fluid_nodes": wl.fluid_nodes, "sigma": wl.sigma, "eta": wl.eta,
-                   "tau": wl.tau, "storage": "f32 populations, f32 moments",
+                   "tau": wl.tau, "storage": "f32 populations, f32 moment fields",
+                   "arithmetic": "f64 in registers (moments, shell sum, equilibrium subtraction, profiles)",
                    "force": "exact shell sum", "parallelism": "single GPU"},
+        "summed_kernel_ms_per_step": round(summed, 5) if summed else None,
         "step_algorithmic_GBps": round(mlups * 1e6 * STEP_BYTES / 1e9, 1),
         "step_hbm_frac": round(mlups * 1e6 * STEP_BYTES / 1e9 / PEAK_HBM_GBPS, 4),
         "copy_GBps": round(copy_gbps, 1),
         "step_copy_frac": round(mlups * 1e6 * STEP_BYTES / 1e9 / copy_gbps, 4),
+        "slit": slit,
         "as_specified": as_specified,
         "ensemble": ens,
         "surrogate": surr,
         "attraction": att,
         "obstacle": obst,
         "fp64_storage": f64,
-        "bulk": bulk,
         "d3q39": q39,
         "d3q39_thermal": q39t,
         "roofline": roof,

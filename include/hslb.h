@@ -180,6 +180,14 @@ int hslb_step(hslb_ctx *ctx, int64_t nsteps);
 /* Wait for all queued work of the context. */
 int hslb_sync(hslb_ctx *ctx);
 
+/* Capture, without running them, every HIP graph that later hslb_step calls
+ * replay (both population buffers as the starting one, every replay length),
+ * so that a timed or latency-critical hslb_step does no graph capture or
+ * instantiation.  Contexts that step eagerly (learned force, kernel timing on,
+ * graphs off) have nothing to capture.  The state does not change.
+ * Errors: HSLB_ESTATE before init, HSLB_EDEVICE. */
+int hslb_prepare(hslb_ctx *ctx);
+
 /* Number of steps taken since init (or since the last set_populations). */
 int hslb_step_count(const hslb_ctx *ctx, int64_t *steps);
 
@@ -239,7 +247,10 @@ int hslb_checkpoint_load(hslb_ctx *ctx, const void *buf);
 /* Watchdog: every `every` steps (0: off) check that the state is finite and
  * that the total mass drifts by at most tol (relative) from its value at init;
  * hslb_step returns HSLB_EUNSTABLE at the first failing check, with the step
- * count at that check available from hslb_step_count. */
+ * count at that check available from hslb_step_count.  A single lattice starts
+ * with every = 1000 and tol = 1e-3, so that a diverging run (the scheme is
+ * unstable above a packing fraction that depends on sigma and tau) stops
+ * instead of stepping on in non-finite values; a batch starts with it off. */
 int hslb_set_watchdog(hslb_ctx *ctx, int64_t every, double tol);
 
 /* Storage of the populations: f_i is kept as f_i - w_i nref(z), with nref the
@@ -337,6 +348,31 @@ int hslb_surrogate_set_mode(hslb_ctx *ctx, int32_t mode);
 int hslb_surrogate_stats(hslb_ctx *ctx, int64_t *checks, int64_t *fallback_steps, double *last_residual,
                          double *max_residual);
 int hslb_surrogate_force(hslb_ctx *ctx, double *F);
+
+/* Training of the learned force from snapshot files.
+ * hslb_surrogate_save_snapshot writes the current state of a context (FP32 or
+ *   FP64, exact or surrogate force mode, nx % 32 == 0, ny % 4 == 0, hard-sphere
+ *   term on) to the file `path`: its network input bf16(pi sigma^3 n / 6) and
+ *   its exact C1 / fs without the external field, the training pair of
+ *   hslb_trainer_add_snapshot.  Format: the 8 bytes "HSLBSNP1", int32 nx, ny,
+ *   nz, wall_lo, wall_hi, sigma, then uint16 x[N] and float target[3][N]
+ *   (little endian).
+ * hslb_surrogate_train trains the network of a surrogate-mode context on every
+ *   file named *.hsnap in snapshot_dir (taken in byte order of their names):
+ *   `epochs` passes of one Adam step per snapshot (as hslb_trainer_train), the
+ *   learning rate lr halved after each pass, each pass over a permutation of
+ *   the snapshots drawn by Fisher-Yates from splitmix64 seeded with
+ *   0x48534c42 + pass, swapping entry i with entry (splitmix64 output mod
+ *   (i + 1)) for i = count - 1 down to 1.  Training starts from the context's
+ *   weights (hslb_surrogate_set_weights; HSLB_ENOSURR without) and leaves the
+ *   trained weights loaded, as hslb_surrogate_set_weights would;
+ *   *final_loss (nullable) is the mean loss of the last pass.  Errors:
+ *   HSLB_ESTATE (not a surrogate context), HSLB_EINVAL (no snapshot files, a
+ *   malformed file, epochs < 1, lr <= 0), HSLB_ENOMEM, HSLB_EUNSTABLE (a loss
+ *   is not finite; the context's weights are then left unchanged). */
+int hslb_surrogate_save_snapshot(hslb_ctx *ctx, const char *path);
+int hslb_surrogate_train(hslb_ctx *ctx, const char *snapshot_dir, int32_t epochs, double lr,
+                         double *final_loss);
 
 /* Training of the learned force on the GPU.  A trainer holds up to
  * capacity_nodes nodes of snapshots (14 bytes per node of device memory), each

@@ -18,6 +18,8 @@
 #include <string>
 #include <type_traits>
 
+#include <vector>
+
 // Steps per replay of the long graphs of a single lattice (even; 0 or 2: the
 // two-step graphs only).  16 steps per replay took the benchmark slit's step
 // from 68.7 to 67.2 us; the two-step graphs cover what remains before a
@@ -25,7 +27,11 @@
 #ifndef HSLB_GRAPH_LONG
 #define HSLB_GRAPH_LONG 16
 #endif
-#include <vector>
+
+// Default watchdog of a single lattice: finite state and total mass within
+// 1e-3 of its initial value, checked every 1000 steps.
+constexpr int64_t kWatchEvery = 1000;
+constexpr double kWatchTol = 1e-3;
 
 using namespace hslb;
 
@@ -160,6 +166,8 @@ public:
         return fail_state("not a thermal context");
     }
     virtual int sync() = 0;
+    // Capture every HIP graph a later step replays, without running it.
+    virtual int prepare() { return HSLB_OK; }
     virtual int timings(double *ms, double *mlups) = 0;
     virtual void set_stream(hipStream_t s) = 0;
     // batched ensembles only
@@ -639,6 +647,19 @@ public:
         e = hipGraphInstantiate(len == 2 ? &gexec_[parity] : &gexecL_[parity], g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) return fail(err, HSLB_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+        return HSLB_OK;
+    }
+
+    int prepare() override
+    {
+        if (!inited) return fail(err, HSLB_ESTATE, "prepare before init");
+        if (!use_graph || kt.enabled || p_.force_mode == HSLB_FORCE_SURROGATE) return HSLB_OK;
+        for (int par = 0; par < 2; ++par) {
+            int rc = HSLB_OK;
+            if (HSLB_GRAPH_LONG > 2 && !gexecL_[par]) rc = capture(par, HSLB_GRAPH_LONG);
+            if (!rc && !gexec_[par]) rc = capture(par);
+            if (rc) return rc;
+        }
         return HSLB_OK;
     }
 
@@ -1661,6 +1682,19 @@ public:
         return HSLB_OK;
     }
 
+    int prepare() override
+    {
+        if (!inited) return fail(err, HSLB_ESTATE, "prepare before every slit is initialised");
+        if (!use_graph || kt.enabled) return HSLB_OK;
+        for (int par = 0; par < 2; ++par) {
+            if (!gexec_[par]) {
+                int rc = capture(par);
+                if (rc) return rc;
+            }
+        }
+        return HSLB_OK;
+    }
+
     int refresh_step()
     {
         const WorkItem *wp = work_d_ + wl_nodes_.size() + wl_rows_.size() + wl_fluid_.size();
@@ -1980,6 +2014,9 @@ int hslb_create(const hslb_params *p, hslb_ctx **out)
         err = c->eng->err;
         return rc;
     }
+    // a diverging run stops with HSLB_EUNSTABLE instead of stepping on in NaNs
+    c->eng->watch_every = kWatchEvery;
+    c->eng->watch_tol = kWatchTol;
     *out = c.release();
     return HSLB_OK;
 }
@@ -2036,6 +2073,12 @@ int hslb_sync(hslb_ctx *ctx)
 {
     CTX_CHECK(ctx);
     return ctx->eng->sync();
+}
+
+int hslb_prepare(hslb_ctx *ctx)
+{
+    CTX_CHECK(ctx);
+    return ctx->eng->prepare();
 }
 
 int hslb_step_count(const hslb_ctx *ctx, int64_t *s)
@@ -2328,5 +2371,12 @@ int context_training_pair(hslb_ctx *ctx, uint16_t *x, float *target, cnn::Geo *g
     const int rc = ctx->eng->training_pair(x, target, g, wall_lo, wall_hi, sigma);
     if (rc && msg) *msg = ctx->eng->err;
     return rc;
+}
+
+// Records a failure of a call made on ctx from another translation unit.
+int context_fail(hslb_ctx *ctx, int code, const std::string &msg)
+{
+    if (ctx && ctx->eng) ctx->eng->err = msg;
+    return code;
 }
 }  // namespace hslb

@@ -18,6 +18,8 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstring>
+#include <dirent.h>
 #include <new>
 #include <string>
 #include <vector>
@@ -29,6 +31,7 @@ namespace hslb {
 // hslb_capi.cpp: network input and target of a context's current state.
 int context_training_pair(hslb_ctx *ctx, uint16_t *x, float *target, Geo *g, int *wall_lo, int *wall_hi, int *sigma,
                           std::string *msg);
+int context_fail(hslb_ctx *ctx, int code, const std::string &msg);
 }
 
 namespace {
@@ -587,6 +590,165 @@ int hslb_cnn_op(int32_t op, int32_t nx, int32_t ny, int32_t nz, int32_t zper, co
     }
     T_TRY(hipMemcpyAsync(out, res, sizeof(float) * nout, hipMemcpyDeviceToHost, s));
     T_TRY(hipStreamSynchronize(s));
+    return HSLB_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ training from snapshot files
+
+namespace {
+
+constexpr char kSnapMagic[8] = {'H', 'S', 'L', 'B', 'S', 'N', 'P', '1'};
+
+struct SnapHeader {
+    int32_t nx, ny, nz, wall_lo, wall_hi, sigma;
+};
+
+// splitmix64 (Steele, Lea and Flood, 2014): the generator of the training
+// order.
+uint64_t splitmix64(uint64_t &s)
+{
+    uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+struct FileCloser {
+    FILE *f;
+    ~FileCloser()
+    {
+        if (f) std::fclose(f);
+    }
+};
+
+int read_snap_header(const std::string &path, SnapHeader &h, std::string &err)
+{
+    FileCloser fc{std::fopen(path.c_str(), "rb")};
+    if (!fc.f) return tfail(err, HSLB_EINVAL, "cannot open %s", path.c_str());
+    char m[8];
+    if (std::fread(m, 1, 8, fc.f) != 8 || std::memcmp(m, kSnapMagic, 8) != 0 || std::fread(&h, sizeof(h), 1, fc.f) != 1)
+        return tfail(err, HSLB_EINVAL, "%s is not a snapshot file", path.c_str());
+    if (!geo_ok(h.nx, h.ny, h.nz) || h.wall_lo < 0 || h.wall_hi < 0 || h.wall_lo + h.wall_hi >= h.nz ||
+        ((h.wall_lo == 0) != (h.wall_hi == 0)) || (int64_t)h.nx * h.ny * h.nz >= ((int64_t)1 << 26))
+        return tfail(err, HSLB_EINVAL, "%s: bad geometry", path.c_str());
+    std::fseek(fc.f, 0, SEEK_END);
+    const long want = 8 + (long)sizeof(h) + 14L * h.nx * h.ny * h.nz;
+    if (std::ftell(fc.f) != want) return tfail(err, HSLB_EINVAL, "%s: wrong size", path.c_str());
+    return HSLB_OK;
+}
+
+}  // namespace
+
+// Adds the snapshot of file `path` (header already checked) to the store.
+static int trainer_add_file(hslb_trainer *tr, const std::string &path, const SnapHeader &h)
+{
+    std::string &err = tr->err;
+    Snapshot sn{};
+    sn.g = Geo{h.nx, h.ny, h.nz, h.wall_lo == 0 ? 1 : 0, h.nx * h.ny * h.nz};
+    sn.wall_lo = h.wall_lo;
+    sn.wall_hi = h.wall_hi;
+    const size_t N = (size_t)sn.g.N;
+    int rc = tr->reserve(N, sn);
+    if (rc) return rc;
+    std::vector<char> buf(14 * N);
+    FileCloser fc{std::fopen(path.c_str(), "rb")};
+    if (!fc.f || std::fseek(fc.f, 8 + (long)sizeof(SnapHeader), SEEK_SET) != 0 ||
+        std::fread(buf.data(), 1, buf.size(), fc.f) != buf.size())
+        return tfail(err, HSLB_EINVAL, "cannot read %s", path.c_str());
+    T_TRY(hipMemcpy(tr->arena + sn.x_off, buf.data(), 2 * N, hipMemcpyHostToDevice));
+    T_TRY(hipMemcpy(tr->arena + sn.t_off, buf.data() + 2 * N, 12 * N, hipMemcpyHostToDevice));
+    tr->snaps.push_back(sn);
+    return HSLB_OK;
+}
+
+extern "C" {
+
+int hslb_surrogate_save_snapshot(hslb_ctx *ctx, const char *path)
+{
+    if (!ctx) return HSLB_EINVAL;
+    std::string err;
+    if (!path) return context_fail(ctx, HSLB_EINVAL, "null path");
+    Geo g{};
+    int wl = 0, wh = 0, sig = 0;
+    int rc = context_training_pair(ctx, nullptr, nullptr, &g, &wl, &wh, &sig, &err);  // geometry only
+    if (rc) return context_fail(ctx, rc, err);
+    const size_t N = (size_t)g.N;
+    void *d = nullptr;
+    if (hipMalloc(&d, 14 * N) != hipSuccess) return context_fail(ctx, HSLB_ENOMEM, "snapshot staging buffer");
+    std::vector<char> host(14 * N);
+    rc = context_training_pair(ctx, (uint16_t *)d, (float *)((char *)d + 2 * N), &g, &wl, &wh, &sig, &err);
+    if (!rc && hipMemcpy(host.data(), d, 14 * N, hipMemcpyDeviceToHost) != hipSuccess) {
+        rc = HSLB_EDEVICE;
+        err = "snapshot copy to the host";
+    }
+    (void)hipFree(d);
+    if (rc) return context_fail(ctx, rc, err);
+    const SnapHeader h{g.nx, g.ny, g.nz, wl, wh, sig};
+    FileCloser fc{std::fopen(path, "wb")};
+    if (!fc.f || std::fwrite(kSnapMagic, 1, 8, fc.f) != 8 || std::fwrite(&h, sizeof(h), 1, fc.f) != 1 ||
+        std::fwrite(host.data(), 1, host.size(), fc.f) != host.size())
+        return context_fail(ctx, HSLB_EINVAL, std::string("cannot write ") + path);
+    return HSLB_OK;
+}
+
+int hslb_surrogate_train(hslb_ctx *ctx, const char *snapshot_dir, int32_t epochs, double lr, double *final_loss)
+{
+    if (!ctx) return HSLB_EINVAL;
+    std::string err;
+    if (!snapshot_dir) return context_fail(ctx, HSLB_EINVAL, "null directory");
+    if (epochs < 1) return context_fail(ctx, HSLB_EINVAL, "epochs must be >= 1");
+    if (!(lr > 0.0) || !std::isfinite(lr)) return context_fail(ctx, HSLB_EINVAL, "learning rate must be > 0");
+    std::vector<float> w(NW);
+    int rc = hslb_surrogate_get_weights(ctx, w.data(), NW);  // also rejects a context without weights
+    if (rc) return rc;
+    std::vector<std::string> files;
+    if (DIR *dd = opendir(snapshot_dir)) {
+        while (dirent *e = readdir(dd)) {
+            const std::string nm = e->d_name;
+            if (nm.size() > 6 && nm.compare(nm.size() - 6, 6, ".hsnap") == 0)
+                files.push_back(std::string(snapshot_dir) + "/" + nm);
+        }
+        closedir(dd);
+    } else {
+        return context_fail(ctx, HSLB_EINVAL, std::string("cannot open directory ") + snapshot_dir);
+    }
+    if (files.empty()) return context_fail(ctx, HSLB_EINVAL, std::string("no *.hsnap files in ") + snapshot_dir);
+    std::sort(files.begin(), files.end());
+    std::vector<SnapHeader> hd(files.size());
+    int64_t total = 0, largest = 0;
+    for (size_t k = 0; k < files.size(); ++k) {
+        if ((rc = read_snap_header(files[k], hd[k], err))) return context_fail(ctx, rc, err);
+        const int64_t N = (int64_t)hd[k].nx * hd[k].ny * hd[k].nz;
+        total += N;
+        largest = std::max(largest, N);
+    }
+    hslb_trainer *tr = nullptr;
+    if ((rc = hslb_trainer_create(total, largest, &tr))) return context_fail(ctx, rc, hslb_trainer_last_error(nullptr));
+    struct Owner {
+        hslb_trainer *t;
+        ~Owner() { hslb_trainer_destroy(t); }
+    } own{tr};
+    for (size_t k = 0; k < files.size(); ++k)
+        if ((rc = trainer_add_file(tr, files[k], hd[k]))) return context_fail(ctx, rc, tr->err);
+    if ((rc = hslb_trainer_set_weights(tr, w.data(), NW))) return context_fail(ctx, rc, tr->err);
+    const int32_t cnt = (int32_t)files.size();
+    std::vector<int32_t> order(cnt);
+    double L = 0.0;
+    for (int32_t ep = 0; ep < epochs; ++ep) {
+        for (int32_t i = 0; i < cnt; ++i) order[i] = i;
+        uint64_t st = 0x48534c42ull + (uint64_t)ep;
+        for (int32_t i = cnt - 1; i >= 1; --i) {
+            const int32_t j = (int32_t)(splitmix64(st) % (uint64_t)(i + 1));
+            std::swap(order[i], order[j]);
+        }
+        if ((rc = hslb_trainer_train(tr, order.data(), cnt, lr * std::ldexp(1.0, -ep), &L)))
+            return context_fail(ctx, rc, tr->err);
+    }
+    if ((rc = hslb_trainer_get_weights(tr, w.data(), NW))) return context_fail(ctx, rc, tr->err);
+    if ((rc = hslb_surrogate_set_weights(ctx, w.data(), NW))) return rc;
+    if (final_loss) *final_loss = L;
     return HSLB_OK;
 }
 

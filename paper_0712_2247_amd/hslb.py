@@ -45,7 +45,7 @@ HSLB_CNN_NWEIGHTS = 144067
 EXPORTS = (
     "hslb_create", "hslb_destroy", "hslb_last_error", "hslb_set_stream", "hslb_init",
     "hslb_init_thermal", "hslb_thermal_fields",
-    "hslb_step", "hslb_sync", "hslb_step_count", "hslb_moments", "hslb_profiles",
+    "hslb_step", "hslb_sync", "hslb_prepare", "hslb_step_count", "hslb_moments", "hslb_profiles",
     "hslb_force", "hslb_eta_bar", "hslb_attraction_potential", "hslb_set_solid", "hslb_get_populations",
     "hslb_set_populations",
     "hslb_set_watchdog", "hslb_set_shift_period", "hslb_set_graph",
@@ -54,7 +54,7 @@ EXPORTS = (
     "hslb_batch_create", "hslb_batch_init", "hslb_batch_profiles", "hslb_batch_finite",
     "hslb_batch_set_config", "hslb_batch_autotune",
     "hslb_surrogate_set_weights", "hslb_surrogate_get_weights", "hslb_surrogate_set_mode",
-    "hslb_surrogate_stats", "hslb_surrogate_force",
+    "hslb_surrogate_stats", "hslb_surrogate_force", "hslb_surrogate_save_snapshot", "hslb_surrogate_train",
     "hslb_trainer_create", "hslb_trainer_destroy", "hslb_trainer_last_error",
     "hslb_trainer_add_snapshot", "hslb_trainer_add_snapshot_host", "hslb_trainer_count",
     "hslb_trainer_set_weights", "hslb_trainer_get_weights", "hslb_trainer_eval",
@@ -111,6 +111,7 @@ def load(path: Optional[str] = None):
         "hslb_thermal_fields": (ctypes.c_int, [_vp, _dp, _dp]),
         "hslb_step": (ctypes.c_int, [_vp, ctypes.c_int64]),
         "hslb_sync": (ctypes.c_int, [_vp]),
+        "hslb_prepare": (ctypes.c_int, [_vp]),
         "hslb_step_count": (ctypes.c_int, [_vp, _P(ctypes.c_int64)]),
         "hslb_moments": (ctypes.c_int, [_vp, _dp, _dp]),
         "hslb_profiles": (ctypes.c_int, [_vp, _dp, _dp]),
@@ -143,6 +144,8 @@ def load(path: Optional[str] = None):
         "hslb_surrogate_set_mode": (ctypes.c_int, [_vp, ctypes.c_int32]),
         "hslb_surrogate_stats": (ctypes.c_int, [_vp, _P(ctypes.c_int64), _P(ctypes.c_int64), _dp, _dp]),
         "hslb_surrogate_force": (ctypes.c_int, [_vp, _dp]),
+        "hslb_surrogate_save_snapshot": (ctypes.c_int, [_vp, ctypes.c_char_p]),
+        "hslb_surrogate_train": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_int32, ctypes.c_double, _dp]),
         "hslb_trainer_create": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, _P(_vp)]),
         "hslb_trainer_destroy": (None, [_vp]),
         "hslb_trainer_last_error": (ctypes.c_char_p, [_vp]),
@@ -225,6 +228,10 @@ def hslb_step(ctx, nsteps: int):
 
 def hslb_sync(ctx):
     _chk(ctx, load().hslb_sync(ctx))
+
+
+def hslb_prepare(ctx):
+    _chk(ctx, load().hslb_prepare(ctx))
 
 
 def hslb_step_count(ctx) -> int:
@@ -388,6 +395,17 @@ def hslb_surrogate_stats(ctx):
 
 def hslb_surrogate_force(ctx, F: np.ndarray):
     _chk(ctx, load().hslb_surrogate_force(ctx, _d(F)))
+
+
+def hslb_surrogate_save_snapshot(ctx, path: str):
+    _chk(ctx, load().hslb_surrogate_save_snapshot(ctx, os.fsencode(path)))
+
+
+def hslb_surrogate_train(ctx, snapshot_dir: str, epochs: int, lr: float) -> float:
+    L = ctypes.c_double()
+    _chk(ctx, load().hslb_surrogate_train(ctx, os.fsencode(snapshot_dir), int(epochs), float(lr),
+                                          ctypes.byref(L)))
+    return L.value
 
 
 def _tchk(tr, rc: int):
@@ -555,6 +573,10 @@ class Sim:
     def sync(self):
         hslb_sync(self.ctx)
 
+    def prepare(self):
+        """Capture every graph later steps replay (see hslb_prepare)."""
+        hslb_prepare(self.ctx)
+
     def moments(self):
         n = np.zeros(self.N)
         u = np.zeros(3 * self.N)
@@ -647,6 +669,9 @@ class Batch:
 
     def sync(self):
         hslb_sync(self.ctx)
+
+    def prepare(self):
+        hslb_prepare(self.ctx)
 
     def profiles(self, slit):
         nz = self.wls[slit].nz

@@ -4,12 +4,20 @@ Every number written here comes from the FP64 CPU oracle (``oracle/``) run on
 the seeded inputs of ``paper_0712_2247_amd.workloads``; nothing comes from the
 GPU library.  Usage:
 
-    python tests/golden/make_golden.py slit_64   # 64x64x136 slit, 20000 steps
-    python tests/golden/make_golden.py columns   # laterally uniform reductions
+    python tests/golden/make_golden.py slit_64    # 64x64x136 slit, 20000 steps
+    python tests/golden/make_golden.py ensemble   # the 512-slit ensemble as columns
 
 ``slit_64`` runs the full three-dimensional 64x64x136 slit (sigma 8, eta 0.25,
 tau 0.8, g 2e-6, +-0.5% noise; at eta 0.30 and above the scheme diverges) and stores the
 layer profiles n(z), u(z) at several step counts, plus the total mass.
+
+``ensemble`` runs every slit of the seeded 512-slit ensemble as a laterally
+uniform 1 x 1 x nz column (its start is uniform in x and y, so the periodic
+lateral offsets make the column's profiles those of the 16 x 16 x nz slit):
+10000 steps from the uniform density times 1 + eps sin(z) for eps = 1e-9 and
+2e-9, and 1000 steps of a dozen slits from the plain start.  It stores n(z),
+u_x(z) and the step by which a run turned non-finite (checked every 500 steps;
+-1: finite) in ``ensemble_columns.npz``.
 """
 from __future__ import annotations
 
@@ -56,9 +64,66 @@ def slit_64(snapshots=(1000, 5000, 10000, 20000)):
         print(f"step {s}: {time.time() - t0:.0f} s", flush=True)
 
 
+# slits of the ensemble run from the plain start for 1000 steps
+ENSEMBLE_SMALL = [0, 1, 2, 3, 5, 8, 13, 21, 34, 55, 89, 144]
+
+
+def _column(args):
+    """Oracle profiles of one ensemble slit run as a laterally uniform column,
+    from its uniform density times 1 + eps sin(z); and the step by which the
+    run turned non-finite (-1 if it stayed finite)."""
+    k, steps, eps = args
+    w = workloads.ensemble()[k]
+    o = oracle.Oracle(1, 1, w.nz, sigma=w.sigma, tau=w.tau, accel=w.accel, wall_lo=w.wall_lo,
+                      wall_hi=w.wall_hi)
+    n, u = w.fields()
+    n = n[:, :1, :1] * (1.0 + eps * np.sin(np.arange(w.nz)))[:, None, None]
+    o.init(n, u[:, :, :1, :1])
+    div = -1
+    chunk = 500
+    for done in range(0, steps, chunk):
+        o.step(min(chunk, steps - done))
+        if not np.isfinite(o.moments()[0]).all():
+            div = done + chunk
+            break
+    pn, pu = o.profiles()
+    return k, pn, pu[0], div
+
+
+def ensemble(procs=None):
+    import multiprocessing as mp
+    oracle.set_threads(1)
+    wls = workloads.ensemble()
+    nzmax = max(w.nz for w in wls)
+    runs = {"eps1": (range(len(wls)), 10000, 1e-9), "eps2": (range(len(wls)), 10000, 2e-9),
+            "small": (ENSEMBLE_SMALL, 1000, 0.0)}
+    out = {"small_index": np.array(ENSEMBLE_SMALL, dtype=np.int32),
+           "nz": np.array([w.nz for w in wls], dtype=np.int32)}
+    t0 = time.time()
+    with mp.get_context("spawn").Pool(procs or os.cpu_count()) as pool:
+        for name, (idx, steps, eps) in runs.items():
+            idx = list(idx)
+            res = pool.map(_column, [(k, steps, eps) for k in idx])
+            N = np.full((len(idx), nzmax), np.nan)
+            U = np.full((len(idx), nzmax), np.nan)
+            D = np.full(len(idx), -1, dtype=np.int64)
+            for i, (k, pn, pu, div) in enumerate(res):
+                assert k == idx[i]
+                N[i, :len(pn)] = pn
+                U[i, :len(pu)] = pu
+                D[i] = div
+            out[f"{name}_n"], out[f"{name}_ux"], out[f"{name}_div"] = N, U, D
+            print(f"{name}: {time.time() - t0:.0f} s", flush=True)
+    path = os.path.join(HERE, "ensemble_columns.npz")
+    np.savez_compressed(path + ".tmp.npz", **out)
+    os.replace(path + ".tmp.npz", path)
+
+
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "slit_64"
     if what == "slit_64":
         slit_64()
+    elif what == "ensemble":
+        ensemble()
     else:
         raise SystemExit(f"unknown target {what}")

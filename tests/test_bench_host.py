@@ -67,7 +67,7 @@ def test_traffic_is_read_only_for_its_source_and_workload(path, monkeypatch):
 def test_profile_commands_use_options_the_script_accepts():
     src = open(os.path.join(ROOT, "bench.py")).read()
     accepted = set(re.findall(r'add_argument\("(--[a-z0-9-]+)"', src))
-    assert {"--gpus", "--steps", "--warmup", "--no-bulk"} <= accepted
+    assert {"--gpus", "--steps", "--warmup", "--no-slit", "--surrogate-steps"} <= accepted
     files = glob.glob(os.path.join(ROOT, "profiles", "*"))
     assert files
     seen = 0

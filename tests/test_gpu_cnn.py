@@ -216,6 +216,99 @@ def test_trainer_adam_steps_reduce_the_loss():
     assert all(b < 0.5 * a for a, b in zip(L0, L1)), (L0, L1)
 
 
+def test_adam_matches_oracle_element_by_element():
+    """Three Adam steps of the trainer against oracle/cnn.py adam() fed the
+    same gradients (the trainer's own, read before each step): every weight
+    agrees with the FP64 update to 1e-6 of its step, plus the FP32 rounding
+    of the stored weight."""
+    tr = hslb.Trainer(40000, 5000)
+    ks = [tr.add_host(*snapshot_fields(60 + i), 2, 2) for i in range(3)]
+    w = weights(31)
+    tr.set_weights(w)
+    lr = 1e-3
+    m = np.zeros(hslb.HSLB_CNN_NWEIGHTS)
+    v = np.zeros(hslb.HSLB_CNN_NWEIGHTS)
+    w_gpu = w.astype(np.float64)
+    for t in range(1, 4):
+        k = ks[(t - 1) % 3]
+        _, g = tr.grad(k)                      # deterministic: the step recomputes it
+        tr.step(k, lr)
+        w_new = tr.weights().astype(np.float64)
+        w_or, m, v = cnn.adam(w_gpu, m, v, g.astype(np.float64), t, lr)
+        step = np.abs(w_or - w_gpu)
+        ulp = np.spacing(np.abs(w_or).astype(np.float32)).astype(np.float64)
+        err = np.abs(w_new - w_or)
+        print(f"adam step {t}: max |dw| {step.max():.3e}, max err {err.max():.3e}, "
+              f"max err / (1e-6 |dw| + ulp) {(err / (1e-6 * step + ulp)).max():.3f}", flush=True)
+        assert np.all(err <= 1e-6 * step + ulp), t
+        assert np.count_nonzero(step) > 0.9 * step.size
+        w_gpu = w_new
+
+
+def test_surrogate_train_through_the_c_abi(tmp_path):
+    """hslb_surrogate_train on snapshot files written by
+    hslb_surrogate_save_snapshot equals the trainer object run on the same
+    snapshots in the documented order (splitmix64 Fisher-Yates per pass,
+    learning rate halved per pass): bitwise the same weights and final loss.
+    The file holds the trainer's own snapshot of the state."""
+    wl = workloads.slit("snapf-32x8x20", 32, 8, 16, 4, 0.2, 1.0, 1e-5, 10, "f64", 1031, 0.02)
+    s = hslb.Sim.from_workload(wl)
+    n, u = wl.fields()
+    s.init(n, u)
+    tr = hslb.Trainer(10 * wl.nodes, wl.nodes)
+    for j in range(5):
+        s.step(3)
+        hslb.hslb_surrogate_save_snapshot(s.ctx, str(tmp_path / f"snap{j:02d}.hsnap"))
+        tr.add(s)
+    (tmp_path / "notes.txt").write_text("not a snapshot")
+    raw = (tmp_path / "snap04.hsnap").read_bytes()
+    assert raw[:8] == b"HSLBSNP1"
+    hdr = np.frombuffer(raw[8:32], dtype=np.int32)
+    assert hdr.tolist() == [wl.nx, wl.ny, wl.nz, wl.wall_lo, wl.wall_hi, wl.sigma]
+    assert len(raw) == 32 + 14 * wl.nodes
+    target = np.frombuffer(raw[32 + 2 * wl.nodes:], dtype=np.float32)
+    w0 = weights(32, out_scale=1e-2)
+    tr.set_weights(np.zeros(hslb.HSLB_CNN_NWEIGHTS, dtype=np.float32))
+    L_zero = tr.eval(4)
+    mask = cnn.fluid_mask(wl.nz, wl.ny, wl.nx, wl.wall_lo, wl.wall_hi)
+    t3 = target.astype(np.float64).reshape(3, wl.nz, wl.ny, wl.nx)
+    assert L_zero == pytest.approx(float(((t3 * mask[None]) ** 2).sum() / (3 * mask.sum())), rel=1e-6)
+
+    def splitmix64(state):
+        mask64 = (1 << 64) - 1
+        state = (state + 0x9E3779B97F4A7C15) & mask64
+        z = state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & mask64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & mask64
+        return state, z ^ (z >> 31)
+
+    epochs, lr = 3, 1e-3
+    tr.set_weights(w0)
+    L_tr = None
+    for ep in range(epochs):
+        order = list(range(5))
+        st = 0x48534C42 + ep
+        for i in range(4, 0, -1):
+            st, r = splitmix64(st)
+            j = r % (i + 1)
+            order[i], order[j] = order[j], order[i]
+        L_tr = tr.train(np.array(order, dtype=np.int32), lr * 0.5 ** ep)
+    s2 = hslb.Sim.from_workload(wl, force_mode=hslb.HSLB_FORCE_SURROGATE, surr_check_every=10, surr_tol=1e-3)
+    with pytest.raises(hslb.HslbError) as ei:
+        hslb.hslb_surrogate_train(s2.ctx, str(tmp_path), epochs, lr)
+    assert ei.value.code == hslb.HSLB_ENOSURR
+    hslb.hslb_surrogate_set_weights(s2.ctx, w0)
+    L_abi = hslb.hslb_surrogate_train(s2.ctx, str(tmp_path), epochs, lr)
+    assert L_abi == L_tr
+    assert np.array_equal(hslb.hslb_surrogate_get_weights(s2.ctx), tr.weights())
+    with pytest.raises(hslb.HslbError) as ei:
+        hslb.hslb_surrogate_train(s2.ctx, str(tmp_path / "missing"), 1, lr)
+    assert ei.value.code == hslb.HSLB_EINVAL
+    with pytest.raises(hslb.HslbError) as ei:
+        hslb.hslb_surrogate_train(s.ctx, str(tmp_path), 1, lr)
+    assert ei.value.code == hslb.HSLB_ENOSURR
+
+
 # ------------------------------------------------- the learned force in the step
 
 def small_slit(precision="f64"):
