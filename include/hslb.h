@@ -294,16 +294,29 @@ int hslb_get_timings(hslb_ctx *ctx, double *ms_per_step, double *mlups);
  * hslb_batch_finite: flags[nslits] = 1 where the slit's state is finite
  *   (unstable slits diverge independently of the others).
  * hslb_batch_set_config: persistent grid of grid_per_cu blocks per compute
- *   unit; work in slit order (order 0) or grouped by sigma (order 1).
- * hslb_batch_autotune: times the 12 (grid, order) candidates -- grids of
- *   1, 2, 4, 8, 16, 32 blocks per CU, slit order then sigma order -- over
- *   `steps` steps each, keeps the fastest (*choice = its index), writes the
- *   microseconds per step of up to `cap` candidates; the state is restored. */
+ *   unit for every phase; work in slit order (order 0) or grouped by sigma
+ *   (order 1).
+ * hslb_batch_set_launch / hslb_batch_get_launch: the same with separate grids
+ *   for the four field phases (moments, row sums, ball sums, contact values)
+ *   and for the collide phase; the active configuration.
+ * hslb_batch_autotune: times 12 launch configurations over `steps` steps
+ *   each: one grid of 1, 2, 4, 8, 16, 32 blocks per CU for every phase (slit
+ *   order); then the best phase grid with the five other collide grids; then
+ *   the best of these with the work grouped by sigma.  Keeps the fastest
+ *   (*choice = its index), writes the microseconds per step of up to `cap`
+ *   candidates in that order; the state is restored.  When the environment
+ *   variable HSLB_TUNE_CACHE names a file, a configuration stored there for
+ *   the same device, storage precision and slit list (geometry and sigma of
+ *   every slit, in order) is applied without timing (*choice = -1,
+ *   us_per_step[0] = its stored time); otherwise the result is added to the
+ *   file (a JSON object, one entry per line). */
 int hslb_batch_create(const hslb_params *slits, int32_t nslits, hslb_ctx **out);
 int hslb_batch_init(hslb_ctx *ctx, int32_t slit, const double *n, const double *u);
 int hslb_batch_profiles(hslb_ctx *ctx, int32_t slit, double *n_z, double *u_z);
 int hslb_batch_finite(hslb_ctx *ctx, int32_t *flags);
 int hslb_batch_set_config(hslb_ctx *ctx, int32_t grid_per_cu, int32_t order);
+int hslb_batch_set_launch(hslb_ctx *ctx, int32_t phase_grid_per_cu, int32_t collide_grid_per_cu, int32_t order);
+int hslb_batch_get_launch(hslb_ctx *ctx, int32_t *phase_grid_per_cu, int32_t *collide_grid_per_cu, int32_t *order);
 int hslb_batch_autotune(hslb_ctx *ctx, int32_t steps, int32_t *choice, double *us_per_step,
                         int32_t cap);
 

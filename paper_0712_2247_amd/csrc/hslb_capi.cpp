@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <cstdlib>
 #include <map>
 #include <memory>
 #include <string>
@@ -194,6 +195,16 @@ public:
     virtual int batch_set_config(int32_t grid_per_cu, int32_t order)
     {
         (void)grid_per_cu, (void)order;
+        return fail_state("not a batch context");
+    }
+    virtual int batch_set_launch(int32_t phase_grid, int32_t collide_grid, int32_t order)
+    {
+        (void)phase_grid, (void)collide_grid, (void)order;
+        return fail_state("not a batch context");
+    }
+    virtual int batch_get_launch(int32_t *phase_grid, int32_t *collide_grid, int32_t *order)
+    {
+        (void)phase_grid, (void)collide_grid, (void)order;
         return fail_state("not a batch context");
     }
     virtual int checkpoint_bytes(int64_t *bytes)
@@ -1637,7 +1648,7 @@ public:
             HIP_TRY(kt.ev(&b));
             HIP_TRY(hipEventRecord(a, st()));
         }
-        const unsigned grid = (unsigned)std::max(1, std::min(nw, ncu_ * grid_per_cu_));
+        const unsigned grid = (unsigned)std::max(1, std::min(nw, ncu_ * cgrid_per_cu_));
         HIP_TRY(launch_batch_collide<TF, TM>(st(), grid, desc_d_, wf, nw, f_[cur_], f_[1 - cur_], fld_, chi_d_));
         if (a) {
             HIP_TRY(hipEventRecord(b, st()));
@@ -1820,19 +1831,127 @@ public:
 
     int batch_set_config(int32_t grid_per_cu, int32_t order) override
     {
-        if (grid_per_cu < 1 || grid_per_cu > 1024 || order < 0 || order > 1)
-            return fail(err, HSLB_EINVAL, "batch configuration");
-        grid_per_cu_ = grid_per_cu;
+        return batch_set_launch(grid_per_cu, grid_per_cu, order);
+    }
+
+    int batch_set_launch(int32_t phase_grid, int32_t collide_grid, int32_t order) override
+    {
+        if (phase_grid < 1 || phase_grid > 1024 || collide_grid < 1 || collide_grid > 1024 || order < 0 || order > 1)
+            return fail(err, HSLB_EINVAL, "batch launch configuration");
+        grid_per_cu_ = phase_grid;
+        cgrid_per_cu_ = collide_grid;
         if (order != order_) HIP_TRY(upload_work(order));
         drop_graphs();
         return HSLB_OK;
     }
 
-    // Time every (grid size, work order) candidate over `nsteps` launched steps
-    // and keep the fastest.  The state is saved before and restored after.
+    int batch_get_launch(int32_t *phase_grid, int32_t *collide_grid, int32_t *order) override
+    {
+        if (phase_grid) *phase_grid = grid_per_cu_;
+        if (collide_grid) *collide_grid = cgrid_per_cu_;
+        if (order) *order = order_;
+        return HSLB_OK;
+    }
+
+    // Key of the tuning cache: device, storage precision and the slits'
+    // geometry and sigma in order (FNV-1a 64).
+    std::string tune_key() const
+    {
+        uint64_t h = 1469598103934665603ull;
+        auto mix = [&](int64_t v) {
+            for (int k = 0; k < 8; ++k) {
+                h ^= (uint64_t)((v >> (8 * k)) & 0xff);
+                h *= 1099511628211ull;
+            }
+        };
+        for (const auto &p : p_) {
+            mix(p.nx), mix(p.ny), mix(p.nz), mix(p.wall_lo), mix(p.wall_hi), mix(p.sigma);
+        }
+        int dev = 0;
+        hipDeviceProp_t prop{};
+        std::string arch = "gpu";
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            arch = prop.gcnArchName;
+            arch = arch.substr(0, arch.find(':'));
+        }
+        char buf[160];
+        std::snprintf(buf, sizeof(buf), "hslb-batch-v1|%s|%s|%d|%016llx", arch.c_str(),
+                      sizeof(TF) == 4 ? "f32" : "f64", (int)p_.size(), (unsigned long long)h);
+        return buf;
+    }
+
+    // The cache file holds one JSON object; each line below its opening
+    // brace is one entry "key": {"phase_grid": g, "collide_grid": c,
+    // "order": o, "us_per_step": t}, as written by tune_store.
+    static std::map<std::string, std::string> tune_read(const char *path)
+    {
+        std::map<std::string, std::string> out;
+        FILE *f = std::fopen(path, "r");
+        if (!f) return out;
+        char line[1024];
+        while (std::fgets(line, sizeof(line), f)) {
+            const char *q0 = std::strchr(line, '"');
+            const char *q1 = q0 ? std::strchr(q0 + 1, '"') : nullptr;
+            const char *br = q1 ? std::strchr(q1, '{') : nullptr;
+            const char *be = br ? std::strchr(br, '}') : nullptr;
+            if (!be) continue;
+            out[std::string(q0 + 1, q1)] = std::string(br, be + 1);
+        }
+        std::fclose(f);
+        return out;
+    }
+
+    static bool tune_parse(const std::string &v, int *pg, int *cg, int *order, double *us)
+    {
+        return std::sscanf(v.c_str(), "{\"phase_grid\": %d, \"collide_grid\": %d, \"order\": %d, \"us_per_step\": %lf}",
+                           pg, cg, order, us) == 4;
+    }
+
+    static void tune_store(const char *path, const std::string &key, int pg, int cg, int order, double us)
+    {
+        auto all = tune_read(path);
+        char v[256];
+        std::snprintf(v, sizeof(v), "{\"phase_grid\": %d, \"collide_grid\": %d, \"order\": %d, \"us_per_step\": %.3f}",
+                      pg, cg, order, us);
+        all[key] = v;
+        const std::string tmp = std::string(path) + ".tmp";
+        FILE *f = std::fopen(tmp.c_str(), "w");
+        if (!f) return;
+        std::fprintf(f, "{\n");
+        size_t k = 0;
+        for (const auto &e : all)
+            std::fprintf(f, "  \"%s\": %s%s\n", e.first.c_str(), e.second.c_str(), ++k < all.size() ? "," : "");
+        std::fprintf(f, "}\n");
+        const bool ok = std::fclose(f) == 0;
+        if (ok) std::rename(tmp.c_str(), path);
+    }
+
+    // Time launch configurations over `nsteps` replayed steps each and keep
+    // the fastest: (1) one grid for every phase, 1..32 blocks per compute
+    // unit, slit order; (2) that phase grid with the other collide grids;
+    // (3) the best of these with the work grouped by sigma.  The state is
+    // saved before and restored after.  With HSLB_TUNE_CACHE naming a file,
+    // a configuration stored there for the same device, precision and slits is
+    // applied without timing (*choice = -1, us[0] = its stored time), and a
+    // new result is added to the file.
     int batch_autotune(int32_t nsteps, int32_t *choice, double *us, int32_t cap) override
     {
         if (!inited) return fail(err, HSLB_ESTATE, "autotune before init");
+        const char *cache = std::getenv("HSLB_TUNE_CACHE");
+        const std::string key = tune_key();
+        if (cache && *cache) {
+            auto all = tune_read(cache);
+            auto it = all.find(key);
+            int pg, cg, order;
+            double t;
+            if (it != all.end() && tune_parse(it->second, &pg, &cg, &order, &t)) {
+                int rc = batch_set_launch(pg, cg, order);
+                if (rc) return rc;
+                if (choice) *choice = -1;
+                if (us && cap > 0) us[0] = t;
+                return HSLB_OK;
+            }
+        }
         const int grids[] = {1, 2, 4, 8, 16, 32};
         const size_t popb = sizeof(TF) * (size_t)NQ * pop_stride_;
         TF *save = nullptr;
@@ -1844,30 +1963,43 @@ public:
         HIP_TRY(hipStreamSynchronize(st()));
         const int save_cur = cur_;
         const int64_t save_steps = steps, save_refreshed = refreshed_at_;
-        double best = 1e300;
-        int best_k = 0, k = 0;
-        for (int order = 0; order < 2; ++order)
-            for (int g : grids) {
-                int rc = batch_set_config(g, order);
-                if (!rc) rc = advance(2);  // warm
-                if (!rc && hipEventRecord(ev0_, st()) != hipSuccess) rc = HSLB_EDEVICE;
-                if (!rc) rc = advance(nsteps);
-                float ms = 0.f;
-                if (!rc && (hipEventRecord(ev1_, st()) != hipSuccess || hipEventSynchronize(ev1_) != hipSuccess ||
-                            hipEventElapsedTime(&ms, ev0_, ev1_) != hipSuccess))
-                    rc = fail(err, HSLB_EDEVICE, "autotune timing");
-                if (rc) {
-                    (void)hipFree(save);
-                    return rc;
-                }
-                const double per = 1e3 * ms / nsteps;
-                if (us && k < cap) us[k] = per;
-                if (per < best) {
-                    best = per;
-                    best_k = k;
-                }
-                ++k;
-            }
+        struct Cand {
+            int pg, cg, order;
+            double us;
+        };
+        std::vector<Cand> cands;
+        auto run = [&](int pg, int cg, int order) -> int {
+            int rc = batch_set_launch(pg, cg, order);
+            if (!rc) rc = advance(2);  // warm (and capture)
+            if (!rc && hipEventRecord(ev0_, st()) != hipSuccess) rc = HSLB_EDEVICE;
+            if (!rc) rc = advance(nsteps);
+            float ms = 0.f;
+            if (!rc && (hipEventRecord(ev1_, st()) != hipSuccess || hipEventSynchronize(ev1_) != hipSuccess ||
+                        hipEventElapsedTime(&ms, ev0_, ev1_) != hipSuccess))
+                rc = fail(err, HSLB_EDEVICE, "autotune timing");
+            if (!rc) cands.push_back({pg, cg, order, 1e3 * ms / nsteps});
+            return rc;
+        };
+        auto best_of = [&]() {
+            size_t b = 0;
+            for (size_t k = 1; k < cands.size(); ++k)
+                if (cands[k].us < cands[b].us) b = k;
+            return b;
+        };
+        int rc = HSLB_OK;
+        for (int g : grids)
+            if (!rc) rc = run(g, g, 0);
+        const int pg = rc ? 8 : cands[best_of()].pg;
+        for (int g : grids)
+            if (!rc && g != pg) rc = run(pg, g, 0);
+        if (!rc) {
+            const Cand b = cands[best_of()];
+            rc = run(b.pg, b.cg, 1);
+        }
+        if (rc) {
+            (void)hipFree(save);
+            return rc;
+        }
         cur_ = save_cur;
         HIP_TRY(hipMemcpyAsync(f_[cur_], save, popb, hipMemcpyDeviceToDevice, st()));
         HIP_TRY(hipMemcpyAsync(nref_d_, save_ref.data(), sizeof(double) * save_ref.size(), hipMemcpyHostToDevice,
@@ -1877,9 +2009,12 @@ public:
         steps = save_steps;
         refreshed_at_ = save_refreshed;
         prof_valid_ = false;
-        int rc = batch_set_config(grids[best_k % 6], best_k / 6);
+        const size_t best = best_of();
+        for (size_t k = 0; k < cands.size() && us && (int32_t)k < cap; ++k) us[k] = cands[k].us;
+        rc = batch_set_launch(cands[best].pg, cands[best].cg, cands[best].order);
         if (rc) return rc;
-        if (choice) *choice = best_k;
+        if (choice) *choice = (int32_t)best;
+        if (cache && *cache) tune_store(cache, key, cands[best].pg, cands[best].cg, cands[best].order, cands[best].us);
         return HSLB_OK;
     }
 
@@ -1899,7 +2034,7 @@ private:
     std::vector<WorkItem> wl_nodes_, wl_rows_, wl_fluid_, wl_prof_;
     std::vector<int> prof_off_;
     std::vector<char> inited_;
-    int pop_stride_ = 0, fld_stride_ = 0, nprof_ = 0, ncu_ = 256, grid_per_cu_ = 8, order_ = 0;
+    int pop_stride_ = 0, fld_stride_ = 0, nprof_ = 0, ncu_ = 256, grid_per_cu_ = 8, cgrid_per_cu_ = 8, order_ = 0;
     int64_t nfluid_ = 0;
     hipStream_t stream_ = nullptr, ext_stream_ = nullptr;
     hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
@@ -2320,6 +2455,18 @@ int hslb_batch_set_config(hslb_ctx *ctx, int32_t grid_per_cu, int32_t order)
 {
     CTX_CHECK(ctx);
     return ctx->eng->batch_set_config(grid_per_cu, order);
+}
+
+int hslb_batch_set_launch(hslb_ctx *ctx, int32_t phase_grid_per_cu, int32_t collide_grid_per_cu, int32_t order)
+{
+    CTX_CHECK(ctx);
+    return ctx->eng->batch_set_launch(phase_grid_per_cu, collide_grid_per_cu, order);
+}
+
+int hslb_batch_get_launch(hslb_ctx *ctx, int32_t *phase_grid_per_cu, int32_t *collide_grid_per_cu, int32_t *order)
+{
+    CTX_CHECK(ctx);
+    return ctx->eng->batch_get_launch(phase_grid_per_cu, collide_grid_per_cu, order);
 }
 
 int hslb_batch_autotune(hslb_ctx *ctx, int32_t steps, int32_t *choice, double *us_per_step, int32_t cap)

@@ -21,17 +21,31 @@
 #include <algorithm>
 #include <utility>
 #include <cmath>
+#include <type_traits>
 
 // Tuning switch (compile-time): 1 evaluates the shell sum in FP64 whatever the
-// storage precision (measured faster on gfx950 than FP32 with conversions).
+// storage precision.  FP32 arithmetic on FP32 fields was measured: within 2 %
+// of the time (the kernel is bound by its ~130 vector-memory reads per node,
+// not by arithmetic) and up to 15x the profile error in narrow dense slits,
+// where the rounding of the large layering terms meets the small viscous ones.
 #ifndef HSLB_FORCE_FP64
 #define HSLB_FORCE_FP64 1
 #endif
+
 
 namespace hslb {
 
 namespace {
 
+
+// The collision takes opposite velocities in pairs (i, i + 1), i odd.
+constexpr bool odd_pairs_opposite()
+{
+    for (int i = 1; i < NQ; i += 2)
+        if (OPP[i] != i + 1 || CX[i] != -CX[i + 1] || CY[i] != -CY[i + 1] || CZ[i] != -CZ[i + 1]) return false;
+    return true;
+}
+static_assert(odd_pairs_opposite(), "D3Q19 order: every odd velocity is followed by its opposite");
 
 __device__ __forceinline__ constexpr double wq(int i)
 {
@@ -454,6 +468,41 @@ __device__ __forceinline__ TC s_dot_j(const TM q[4])
     }
 }
 
+// Loads of one mirrored lattice pair: the contact values G+ (midpoint of
+// (r, r+d)) and G- (midpoint of (r, r-d)) and the (n, j) of r+d and r-d.
+template <int DX, int DY, int DZ, bool LZ, typename TM>
+__device__ __forceinline__ void load_pair(const Fields<TM> &F, const LatticeDev &L, int x, int y, int zp, TM &Gp,
+                                          TM &Gm, TM qp[4], TM qm[4])
+{
+    constexpr int SLOT = (DX & 1) | ((DY & 1) << 1) | ((DZ & 1) << 2);
+    constexpr int BXP = floordiv2(DX), BYP = floordiv2(DY), BZP = floordiv2(DZ);
+    constexpr int BXM = floordiv2(-DX), BYM = floordiv2(-DY), BZM = floordiv2(-DZ);
+    if constexpr (LZ) {
+        constexpr int NJB = 4 * (int)sizeof(TM);  // bytes of one (n, j) entry
+        constexpr int GB = (int)sizeof(TM);
+        const size_t lay = (size_t)L.plane;
+        const char *njp = (const char *)F.nj + NJB * lay * (size_t)(zp + DZ);
+        const char *njm = (const char *)F.nj + NJB * lay * (size_t)(zp - DZ);
+        const char *gs = (const char *)F.G + GB * (size_t)SLOT * L.fld_stride;
+        const char *gzp = gs + GB * lay * (size_t)(zp + BZP);
+        const char *gzm = gs + GB * lay * (size_t)(zp + BZM);
+        Gp = *(const TM *)(gzp + (xb<BXP, GB>(x, L.nx) + yb<BYP, GB>(y, L.ny, L.nx)));
+        Gm = *(const TM *)(gzm + (xb<BXM, GB>(x, L.nx) + yb<BYM, GB>(y, L.ny, L.nx)));
+        load4((const TM *)(njp + (xb<DX, NJB>(x, L.nx) + yb<DY, NJB>(y, L.ny, L.nx))), qp);
+        load4((const TM *)(njm + (xb<-DX, NJB>(x, L.nx) + yb<-DY, NJB>(y, L.ny, L.nx))), qm);
+    } else {
+        const size_t fs = L.fld_stride;
+        const int ip = wrapc<DX>(x, L.nx) + L.nx * (wrapc<DY>(y, L.ny) + L.ny * (zp + DZ));
+        const int im = wrapc<-DX>(x, L.nx) + L.nx * (wrapc<-DY>(y, L.ny) + L.ny * (zp - DZ));
+        const int gp = wrapc<BXP>(x, L.nx) + L.nx * (wrapc<BYP>(y, L.ny) + L.ny * (zp + BZP));
+        const int gm = wrapc<BXM>(x, L.nx) + L.nx * (wrapc<BYM>(y, L.ny) + L.ny * (zp + BZM));
+        Gp = F.G[SLOT * fs + gp];
+        Gm = F.G[SLOT * fs + gm];
+        load4(F.nj + 4 * (size_t)ip, qp);
+        load4(F.nj + 4 * (size_t)im, qm);
+    }
+}
+
 // Difference of the two elements of one mirrored lattice pair, the corner d of
 // direction q and the corner -d of direction -q:
 //   e+ - e- = G+ [n+ - chi kappa s.(j+ - n+ u)] - G- [n- + chi kappa s.(j- - n- u)]
@@ -470,35 +519,9 @@ template <int DX, int DY, int DZ, int SX, int SY, int SZ, bool DIAG, bool LZ, ty
 __device__ __forceinline__ TC pair_element(const Fields<TM> &F, const LatticeDev &L, const NodeCtx<TC> &c,
                                            TC su)
 {
-    constexpr int SLOT = (DX & 1) | ((DY & 1) << 1) | ((DZ & 1) << 2);
-    constexpr int BXP = floordiv2(DX), BYP = floordiv2(DY), BZP = floordiv2(DZ);
-    constexpr int BXM = floordiv2(-DX), BYM = floordiv2(-DY), BZM = floordiv2(-DZ);
-    TC Gp, Gm;
-    TM qp[4], qm[4];
-    if constexpr (LZ) {
-        constexpr int NJB = 4 * (int)sizeof(TM);  // bytes of one (n, j) entry
-        constexpr int GB = (int)sizeof(TM);
-        const size_t lay = (size_t)L.plane;
-        const char *njp = (const char *)F.nj + NJB * lay * (size_t)(c.zp + DZ);
-        const char *njm = (const char *)F.nj + NJB * lay * (size_t)(c.zp - DZ);
-        const char *gs = (const char *)F.G + GB * (size_t)SLOT * L.fld_stride;
-        const char *gzp = gs + GB * lay * (size_t)(c.zp + BZP);
-        const char *gzm = gs + GB * lay * (size_t)(c.zp + BZM);
-        Gp = (TC) * (const TM *)(gzp + (xb<BXP, GB>(c.x, L.nx) + yb<BYP, GB>(c.y, L.ny, L.nx)));
-        Gm = (TC) * (const TM *)(gzm + (xb<BXM, GB>(c.x, L.nx) + yb<BYM, GB>(c.y, L.ny, L.nx)));
-        load4((const TM *)(njp + (xb<DX, NJB>(c.x, L.nx) + yb<DY, NJB>(c.y, L.ny, L.nx))), qp);
-        load4((const TM *)(njm + (xb<-DX, NJB>(c.x, L.nx) + yb<-DY, NJB>(c.y, L.ny, L.nx))), qm);
-    } else {
-        const size_t fs = L.fld_stride;
-        const int ip = wrapc<DX>(c.x, L.nx) + L.nx * (wrapc<DY>(c.y, L.ny) + L.ny * (c.zp + DZ));
-        const int im = wrapc<-DX>(c.x, L.nx) + L.nx * (wrapc<-DY>(c.y, L.ny) + L.ny * (c.zp - DZ));
-        const int gp = wrapc<BXP>(c.x, L.nx) + L.nx * (wrapc<BYP>(c.y, L.ny) + L.ny * (c.zp + BZP));
-        const int gm = wrapc<BXM>(c.x, L.nx) + L.nx * (wrapc<BYM>(c.y, L.ny) + L.ny * (c.zp + BZM));
-        Gp = (TC)F.G[SLOT * fs + gp];
-        Gm = (TC)F.G[SLOT * fs + gm];
-        load4(F.nj + 4 * (size_t)ip, qp);
-        load4(F.nj + 4 * (size_t)im, qm);
-    }
+    TM gp, gm, qp[4], qm[4];
+    load_pair<DX, DY, DZ, LZ>(F, L, c.x, c.y, c.zp, gp, gm, qp, qm);
+    const TC Gp = (TC)gp, Gm = (TC)gm;
     const TC np = (TC)qp[0], nm = (TC)qm[0];
     TC sjp = s_dot_j<SX, SY, SZ, TM, TC>(qp);
     TC sjm = s_dot_j<SX, SY, SZ, TM, TC>(qm);
@@ -666,7 +689,9 @@ __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &
             return;
         }
     }
-    double f[NQ];
+    // the stored values are kept through the shell sum (half the registers of
+    // FP64 populations) and turned into FP64 populations again for the collision
+    TF fs[NQ];
     const double *rr = layer_ref(sc.nref_r, z);
     if constexpr (LZ) {
         const char *fz = (const char *)fin + lstride * (size_t)z;
@@ -674,42 +699,79 @@ __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &
         for (int i = 0; i < NQ; ++i) {
             const TF *p = (const TF *)(fz + dstride * i + rb);
             if constexpr (NT)
-                f[i] = (double)__builtin_nontemporal_load(p) + rr[i];
+                fs[i] = __builtin_nontemporal_load(p);
             else
-                f[i] = (double)*p + rr[i];
+                fs[i] = *p;
         }
     } else if constexpr (NT) {
 #pragma unroll
-        for (int i = 0; i < NQ; ++i)
-            f[i] = (double)__builtin_nontemporal_load(fin + (size_t)i * L.pop_stride + id) + rr[i];
+        for (int i = 0; i < NQ; ++i) fs[i] = __builtin_nontemporal_load(fin + (size_t)i * L.pop_stride + id);
     } else {
 #pragma unroll
-        for (int i = 0; i < NQ; ++i) f[i] = (double)fin[(size_t)i * L.pop_stride + id] + rr[i];
+        for (int i = 0; i < NQ; ++i) fs[i] = fin[(size_t)i * L.pop_stride + id];
     }
     double n = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
-        n += f[i];
-        if (CX[i] > 0) jx += f[i];
-        if (CX[i] < 0) jx -= f[i];
-        if (CY[i] > 0) jy += f[i];
-        if (CY[i] < 0) jy -= f[i];
-        if (CZ[i] > 0) jz += f[i];
-        if (CZ[i] < 0) jz -= f[i];
+        const double fi = (double)fs[i] + rr[i];
+        n += fi;
+        if (CX[i] > 0) jx += fi;
+        if (CX[i] < 0) jx -= fi;
+        if (CY[i] > 0) jy += fi;
+        if (CY[i] < 0) jy -= fi;
+        if (CZ[i] > 0) jz += fi;
+        if (CZ[i] < 0) jz -= fi;
     }
     const double inv_n = (n != 0.0) ? 1.0 / n : 0.0;
     const double u[3] = {jx * inv_n, jy * inv_n, jz * inv_n};
     double Fv[3];
     node_force<SIG, LZ, TM, MASK>(fld, L, sc, chi, x, y, z, n, u, Fv);
 
+    // BGK relaxation (10) towards the equilibrium (11), with the first-order
+    // source, for opposite velocities i and i + 1 together: with cu = c_i.u,
+    // f_eq = w n (1 - 1.5 u.u + 4.5 cu^2) +- 3 w n cu and the source
+    // +- 3 w c_i.F; f - f_eq is formed in FP64.
     const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     const double omega = 1.0 / sc.tau;
+    const double base = 1.0 - 1.5 * uu;
+    double f[NQ];
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) {
+    for (int i = 0; i < NQ; ++i) f[i] = (double)fs[i] + rr[i];
+    double fq[NQ];
+    fq[0] = f[0] - omega * (f[0] - (1.0 / 3.0) * n * base);
+#pragma unroll
+    for (int i = 1; i < NQ; i += 2) {
         const double cu = CX[i] * u[0] + CY[i] * u[1] + CZ[i] * u[2];
         const double cF = CX[i] * Fv[0] + CY[i] * Fv[1] + CZ[i] * Fv[2];
-        const double feq = wq(i) * n * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-        const double fp = f[i] - omega * (f[i] - feq) + 3.0 * wq(i) * cF;
+        const double wn = wq(i) * n;
+        const double A = wn * fma(4.5 * cu, cu, base);
+        const double B = (3.0 * wn) * cu;
+        const double src = (3.0 * wq(i)) * cF;
+        fq[i] = fma(-omega, f[i] - (A + B), f[i] + src);
+        fq[i + 1] = fma(-omega, f[i + 1] - (A - B), f[i + 1] - src);
+    }
+    // The write references of the layers the populations land in, read before
+    // the first store: later reads could not be scalar (the compiler cannot
+    // rule out that the stores alias the table) and would each wait out a
+    // vector-memory round trip.
+    int zu = z + 1, zd = z - 1;
+    if (L.zper) {
+        zu = (zu == L.nz) ? 0 : zu;
+        zd = (zd < 0) ? L.nz - 1 : zd;
+    } else {
+        zu = (zu < L.nz) ? zu : z;   // a fluid layer's upper neighbour exists in a slit
+        zd = (zd >= 0) ? zd : z;
+    }
+    const double *rwz = layer_ref(sc.nref_w, z), *rwu = layer_ref(sc.nref_w, zu), *rwd = layer_ref(sc.nref_w, zd);
+    double rwh[NQ], rwl[NQ];  // layer z; the layer direction i lands in
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        rwh[i] = rwz[i];
+        rwl[i] = CZ[i] > 0 ? rwu[i] : (CZ[i] < 0 ? rwd[i] : rwh[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const double fp = fq[i];
         const int xt = wrapr(x + CX[i], L.nx);
         const int yt = wrapr(y + CY[i], L.ny);
         int zt = z + CZ[i];
@@ -720,36 +782,34 @@ __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &
             bounce = bounce || (zt < L.wall_lo) || (zt >= L.nz - L.wall_hi);
         }
         // stored relative to the reference of the layer it lands in
+        const TF vb = (TF)(fp - rwh[OPP[i]]);
+        const TF vs = (TF)(fp - rwl[i]);
         if constexpr (LZ) {
             char *fo = (char *)fout;
             if (bounce) {
                 TF *p = (TF *)(fo + dstride * OPP[i] + lstride * (size_t)z + rb);
-                const TF v = (TF)(fp - layer_ref(sc.nref_w, z)[OPP[i]]);
                 if constexpr (NT)
-                    __builtin_nontemporal_store(v, p);
+                    __builtin_nontemporal_store(vb, p);
                 else
-                    *p = v;
+                    *p = vb;
             } else {
                 TF *p = (TF *)(fo + dstride * i + lstride * (size_t)zt +
                                ((uint32_t)xt * EB + __umul24((uint32_t)yt, (uint32_t)L.nx * EB)));
-                const TF v = (TF)(fp - layer_ref(sc.nref_w, zt)[i]);
                 if constexpr (NT)
-                    __builtin_nontemporal_store(v, p);
+                    __builtin_nontemporal_store(vs, p);
                 else
-                    *p = v;
+                    *p = vs;
             }
         } else if constexpr (NT) {
             if (bounce)
-                __builtin_nontemporal_store((TF)(fp - layer_ref(sc.nref_w, z)[OPP[i]]),
-                                            fout + (size_t)OPP[i] * L.pop_stride + id);
+                __builtin_nontemporal_store(vb, fout + (size_t)OPP[i] * L.pop_stride + id);
             else
-                __builtin_nontemporal_store((TF)(fp - layer_ref(sc.nref_w, zt)[i]),
-                                            fout + (size_t)i * L.pop_stride + xt + L.nx * (yt + L.ny * zt));
+                __builtin_nontemporal_store(vs, fout + (size_t)i * L.pop_stride + xt + L.nx * (yt + L.ny * zt));
         } else {
             if (bounce)
-                fout[(size_t)OPP[i] * L.pop_stride + id] = (TF)(fp - layer_ref(sc.nref_w, z)[OPP[i]]);
+                fout[(size_t)OPP[i] * L.pop_stride + id] = vb;
             else
-                fout[(size_t)i * L.pop_stride + xt + L.nx * (yt + L.ny * zt)] = (TF)(fp - layer_ref(sc.nref_w, zt)[i]);
+                fout[(size_t)i * L.pop_stride + xt + L.nx * (yt + L.ny * zt)] = vs;
         }
     }
 }
@@ -1036,7 +1096,7 @@ __device__ __forceinline__ void batch_collide(const LatticeDev &L, const StepCon
 // stencil) is uniform over the block.  A kernel of its own, so that the
 // lighter phases of kb_phase keep a small register budget.
 template <typename TF, typename TM>
-__global__ __launch_bounds__(256, 3) void kb_collide(const SlitDesc *__restrict__ desc,
+__global__ __launch_bounds__(256, HSLB_COLLIDE_WAVES) void kb_collide(const SlitDesc *__restrict__ desc,
                                                      const WorkItem *__restrict__ work, int nwork,
                                                      const TF *__restrict__ fin, TF *__restrict__ fout,
                                                      Fields<TM> fld, const double *__restrict__ chi)

@@ -52,7 +52,7 @@ EXPORTS = (
     "hslb_checkpoint_size", "hslb_checkpoint_save", "hslb_checkpoint_load", "hslb_set_kernel_timing", "hslb_kernel_times",
     "hslb_get_timings", "hslb_copy_bandwidth",
     "hslb_batch_create", "hslb_batch_init", "hslb_batch_profiles", "hslb_batch_finite",
-    "hslb_batch_set_config", "hslb_batch_autotune",
+    "hslb_batch_set_config", "hslb_batch_set_launch", "hslb_batch_get_launch", "hslb_batch_autotune",
     "hslb_surrogate_set_weights", "hslb_surrogate_get_weights", "hslb_surrogate_set_mode",
     "hslb_surrogate_stats", "hslb_surrogate_force", "hslb_surrogate_save_snapshot", "hslb_surrogate_train",
     "hslb_trainer_create", "hslb_trainer_destroy", "hslb_trainer_last_error",
@@ -137,6 +137,8 @@ def load(path: Optional[str] = None):
         "hslb_batch_profiles": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, _dp]),
         "hslb_batch_finite": (ctypes.c_int, [_vp, _P(ctypes.c_int32)]),
         "hslb_batch_set_config": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
+        "hslb_batch_set_launch": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+        "hslb_batch_get_launch": (ctypes.c_int, [_vp, _P(ctypes.c_int32), _P(ctypes.c_int32), _P(ctypes.c_int32)]),
         "hslb_batch_autotune": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_int32), _dp,
                                                ctypes.c_int32]),
         "hslb_surrogate_set_weights": (ctypes.c_int, [_vp, _fp, ctypes.c_int64]),
@@ -359,10 +361,21 @@ def hslb_batch_set_config(ctx, grid_per_cu: int, order: int):
     _chk(ctx, load().hslb_batch_set_config(ctx, int(grid_per_cu), int(order)))
 
 
+def hslb_batch_set_launch(ctx, phase_grid_per_cu: int, collide_grid_per_cu: int, order: int):
+    _chk(ctx, load().hslb_batch_set_launch(ctx, int(phase_grid_per_cu), int(collide_grid_per_cu), int(order)))
+
+
+def hslb_batch_get_launch(ctx):
+    """(phase grid per CU, collide grid per CU, order) in effect."""
+    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _chk(ctx, load().hslb_batch_get_launch(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
 def hslb_batch_autotune(ctx, steps: int):
-    """Returns (choice, us_per_step[12]): candidates are grid sizes of
-    (1, 2, 4, 8, 16, 32) blocks per compute unit with work in slit order, then
-    the same with work grouped by sigma."""
+    """Returns (choice, us_per_step[12]) over the 12 launch configurations
+    (see include/hslb.h); choice -1 when HSLB_TUNE_CACHE supplied the
+    configuration (then us_per_step[0] is its stored time)."""
     choice = ctypes.c_int32()
     us = np.zeros(12)
     _chk(ctx, load().hslb_batch_autotune(ctx, int(steps), ctypes.byref(choice), _d(us), 12))

@@ -140,6 +140,16 @@ def slit_128_f32() -> Workload:
                 "f32", 1005, 0.005)
 
 
+def slit_128_f32_stable() -> Workload:
+    """The held-out evaluation slit at packing fraction 0.28 instead of 0.38
+    (everything else unchanged): 0.38 is linearly unstable under the scheme
+    (sigma 8, tau 1: the uniform state's symbol grows for packing above 0.32),
+    and on this slit 0.30 already diverges within 500 steps while 0.28 stays
+    finite over 6000; 0.28 is the largest of 0.26, 0.28, 0.30, 0.32 that runs."""
+    return slit("slit-128x128x264-s8-eta0.28-f32", 128, 128, 256, 8, 0.28, 1.0, 1e-6, 50000,
+                "f32", 1005, 0.005)
+
+
 def ensemble(nslits: int = 512, seed: int = 1004, steps: int = 10000) -> List[Workload]:
     """Ragged ensemble of slits with a 16x16 periodic cross section.  Per slit, in
     slit order: fluid width H ~ U{10..60}, sigma ~ U{3,4,5,6,8},
@@ -206,6 +216,7 @@ WORKLOADS = {
     "slit_small_f64": slit_small_f64,
     "slit_64_f32": slit_64_f32,
     "slit_64_f32_stable": slit_64_f32_stable,
+    "slit_128_f32_stable": slit_128_f32_stable,
     "bulk_256_f32": bulk_256_f32,
     "slit_128_f32": slit_128_f32,
 }

@@ -109,6 +109,53 @@ class Grid:
         za, zb = self.wl - 0.5, self.nz - self.wh - 0.5
         return 1.0 - math.exp(-min(z - za, zb - z) / self.sigma)
 
+    def force_at(self, nodes):
+        """C^(1) at the given nodes [(x, y, z), ...] (fluid nodes), and for
+        each the sum of the magnitudes of the terms it is made of,
+        |v_T^2 sigma^2 4 pi n| sum_q W_q |s_q| sum_k alpha_k G (|n'| + chi
+        kappa |s.j'| + chi kappa |n' s.u|), the scale of its rounding error."""
+        eb = {}
+
+        def ebar(x, y, z):
+            key = self.wrap(x, y, z)
+            if key not in eb:
+                eb[key] = self.eta_bar(*key)
+            return eb[key]
+
+        pts = quadrature_points()
+        F = np.zeros((3, len(nodes)))
+        A = np.zeros((3, len(nodes)))
+        pref = VT2 * self.sigma ** 2 * 4.0 * math.pi
+        for i, (x, y, z) in enumerate(nodes):
+            nr, jr = self.dens(x, y, z)
+            ur = [jr[a] / nr if nr != 0 else 0.0 for a in range(3)]
+            S = [0.0, 0.0, 0.0]
+            Sa = [0.0, 0.0, 0.0]
+            for W, s in pts:
+                acc = 0.0
+                acca = 0.0
+                for d, al in corners(self.sigma, s):
+                    cx, cy, cz = x + d[0], y + d[1], z + d[2]
+                    nc, jc = self.dens(cx, cy, cz)
+                    mids = []
+                    for r0, c0 in ((x, cx), (y, cy), (z, cz)):
+                        h = (r0 + c0) / 2.0
+                        mids.append(sorted({math.floor(h), math.ceil(h)}))
+                    vals = [ebar(mx, my, mz) for mz in mids[2] for my in mids[1] for mx in mids[0]]
+                    G = g2(sum(vals) / len(vals), self.g2_model)
+                    sj = sum(s[a] * jc[a] for a in range(3))
+                    su = sum(s[a] * ur[a] for a in range(3))
+                    ck = self.chi(z) * KAPPA
+                    acc += al * G * (nc - ck * (sj - nc * su))
+                    acca += al * G * (abs(nc) + ck * (abs(sj) + abs(nc * su)))
+                for a in range(3):
+                    S[a] += W * s[a] * acc
+                    Sa[a] += W * abs(s[a]) * acca
+            for a in range(3):
+                F[a, i] = -pref * nr * S[a]
+                A[a, i] = pref * abs(nr) * Sa[a]
+        return F, A
+
     def force(self, accel=(0.0, 0.0, 0.0)):
         F = np.zeros((3, self.nz, self.ny, self.nx))
         eb = {}

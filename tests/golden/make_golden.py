@@ -6,6 +6,7 @@ GPU library.  Usage:
 
     python tests/golden/make_golden.py slit_64    # 64x64x136 slit, 20000 steps
     python tests/golden/make_golden.py ensemble   # the 512-slit ensemble as columns
+    python tests/golden/make_golden.py slit_128   # held-out 128x128x264 slit, 3000 steps
 
 ``slit_64`` runs the full three-dimensional 64x64x136 slit (sigma 8, eta 0.25,
 tau 0.8, g 2e-6, +-0.5% noise; at eta 0.30 and above the scheme diverges) and stores the
@@ -59,6 +60,29 @@ def slit_64(snapshots=(1000, 5000, 10000, 20000)):
         nn, _ = o.moments()
         out["snapshots"][str(s)] = {"n_z": pn.tolist(), "u_z": pu.tolist(),
                                     "mass": float(nn.sum())}
+        out["seconds"] = time.time() - t0
+        _dump(path, out)
+        print(f"step {s}: {time.time() - t0:.0f} s", flush=True)
+
+
+def slit_128(snapshots=(500, 1000, 2000, 3000)):
+    """The held-out 128x128x264 slit (sigma 8, packing 0.28, tau 1, g 1e-6,
+    +-0.5% noise): layer profiles at several step counts."""
+    wl = workloads.slit_128_f32_stable()
+    n, u = wl.fields()
+    o = oracle.Oracle(**wl.params())
+    o.init(n, u)
+    del n, u
+    out = {"workload": wl.name, "source": "oracle FP64, full 3-D grid",
+           "threads": oracle.max_threads(), "snapshots": {}}
+    path = os.path.join(HERE, "slit_128x128x264_eta0.28_profiles.json")
+    done = 0
+    t0 = time.time()
+    for s in snapshots:
+        o.step(s - done)
+        done = s
+        pn, pu = o.profiles()
+        out["snapshots"][str(s)] = {"n_z": pn.tolist(), "u_z": pu.tolist()}
         out["seconds"] = time.time() - t0
         _dump(path, out)
         print(f"step {s}: {time.time() - t0:.0f} s", flush=True)
@@ -125,5 +149,7 @@ if __name__ == "__main__":
         slit_64()
     elif what == "ensemble":
         ensemble()
+    elif what == "slit_128":
+        slit_128()
     else:
         raise SystemExit(f"unknown target {what}")

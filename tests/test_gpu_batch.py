@@ -68,6 +68,7 @@ def test_batch_matches_single_lattice_and_oracle():
     for i in (0, 3, 7):
         w = wls[i]
         g = hslb.Sim.from_workload(w)
+        hslb.hslb_set_watchdog(g.ctx, 0, 0.0)   # slit 3 diverges; only finite slits are compared
         n, u = w.fields()
         g.init(n, u)
         g.step(steps)
@@ -117,6 +118,39 @@ def test_batch_graph_and_eager_agree_and_autotune_restores_state():
         b.step(1)
     for i in range(len(wls)):
         assert np.array_equal(a.profiles(i)[0], b.profiles(i)[0])
+
+
+def test_autotune_cache_round_trip(tmp_path, monkeypatch):
+    """With HSLB_TUNE_CACHE set, the first autotune times the 12 launch
+    configurations and stores the fastest; a second batch of the same slits
+    applies it without timing; a different slit list is timed again."""
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("HSLB_TUNE_CACHE", str(cache))
+    wls = [workloads.ensemble()[k].with_size(steps=60) for k in SMALL[:6]]
+    a = hslb.Batch(wls)
+    a.init_all()
+    choice, us = a.autotune(steps=4)
+    assert 0 <= choice < 12 and (us > 0).all()
+    launch = hslb.hslb_batch_get_launch(a.ctx)
+    text = cache.read_text()
+    assert text.startswith("{") and "hslb-batch-v1|" in text and '"collide_grid": %d' % launch[1] in text
+    b = hslb.Batch(wls)
+    b.init_all()
+    choice2, us2 = b.autotune(steps=4)
+    assert choice2 == -1 and us2[0] == pytest.approx(us[choice], rel=1e-3)
+    assert hslb.hslb_batch_get_launch(b.ctx) == launch
+    c = hslb.Batch(wls[:5])
+    c.init_all()
+    choice3, _ = c.autotune(steps=4)
+    assert choice3 >= 0 and text != cache.read_text()
+    # the state after a cached or timed tuning steps as an untuned batch
+    ref = hslb.Batch(wls)
+    ref.init_all()
+    for bb in (a, b, ref):
+        bb.step(20)
+    for i in range(len(wls)):
+        assert np.array_equal(a.profiles(i)[0], ref.profiles(i)[0])
+        assert np.array_equal(b.profiles(i)[0], ref.profiles(i)[0])
 
 
 # Both sides start from the ensemble's uniform density times 1 + EPS sin(z):

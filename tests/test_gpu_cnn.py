@@ -218,30 +218,38 @@ def test_trainer_adam_steps_reduce_the_loss():
 
 def test_adam_matches_oracle_element_by_element():
     """Three Adam steps of the trainer against oracle/cnn.py adam() fed the
-    same gradients (the trainer's own, read before each step): every weight
-    agrees with the FP64 update to 1e-6 of its step, plus the FP32 rounding
-    of the stored weight."""
+    same gradients (the trainer's own, read before each step; the step
+    recomputes them bitwise).  The GPU evaluates in FP32: every weight agrees
+    with the FP64 update within a few FP32 roundings of the terms it is built
+    from -- the first moment beta1 |m| + (1 - beta1) |g| (which may cancel),
+    the update m_hat / (sqrt(v_hat) + eps) itself -- plus the rounding of the
+    stored weight."""
     tr = hslb.Trainer(40000, 5000)
     ks = [tr.add_host(*snapshot_fields(60 + i), 2, 2) for i in range(3)]
     w = weights(31)
     tr.set_weights(w)
-    lr = 1e-3
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
     m = np.zeros(hslb.HSLB_CNN_NWEIGHTS)
     v = np.zeros(hslb.HSLB_CNN_NWEIGHTS)
     w_gpu = w.astype(np.float64)
+    u32 = 2.0 ** -24
     for t in range(1, 4):
         k = ks[(t - 1) % 3]
-        _, g = tr.grad(k)                      # deterministic: the step recomputes it
+        _, g = tr.grad(k)
         tr.step(k, lr)
         w_new = tr.weights().astype(np.float64)
-        w_or, m, v = cnn.adam(w_gpu, m, v, g.astype(np.float64), t, lr)
-        step = np.abs(w_or - w_gpu)
-        ulp = np.spacing(np.abs(w_or).astype(np.float32)).astype(np.float64)
+        g = g.astype(np.float64)
+        mabs = b1 * np.abs(m) + (1 - b1) * np.abs(g)
+        w_or, m, v = cnn.adam(w_gpu, m, v, g, t, lr)
+        den = np.sqrt(v / (1 - b2 ** t)) + eps
+        mh = m / (1 - b1 ** t)
+        bound = 8 * u32 * lr * (mabs / (1 - b1 ** t) / den + np.abs(mh) / den) \
+            + np.spacing(np.abs(w_or).astype(np.float32)).astype(np.float64)
         err = np.abs(w_new - w_or)
-        print(f"adam step {t}: max |dw| {step.max():.3e}, max err {err.max():.3e}, "
-              f"max err / (1e-6 |dw| + ulp) {(err / (1e-6 * step + ulp)).max():.3f}", flush=True)
-        assert np.all(err <= 1e-6 * step + ulp), t
-        assert np.count_nonzero(step) > 0.9 * step.size
+        print(f"adam step {t}: max |dw| {np.abs(w_or - w_gpu).max():.3e}, max err {err.max():.3e}, "
+              f"max err / bound {(err / bound).max():.3f}", flush=True)
+        assert np.all(err <= bound), t
+        assert np.count_nonzero(w_or != w_gpu) > 0.9 * w_or.size
         w_gpu = w_new
 
 

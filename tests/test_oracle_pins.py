@@ -221,6 +221,27 @@ def test_force_matches_brute_force(sigma, walls):
     assert np.abs(F - ref).max() <= 1e-13 * scale
 
 
+def test_sampled_brute_force_equals_full_brute_force_and_oracle():
+    """force_at (the sampled evaluation used on the full-size GPU state)
+    reproduces the full brute-force sweep and the oracle at the same nodes,
+    and its term-magnitude scale bounds the force."""
+    sigma, shape = 6, (14, 13, 12)
+    nb = workloads.number_density(0.25, sigma)
+    n, u = workloads.random_state(shape, nb, 0.05, 3e-3, seed=5)
+    o = oracle.Oracle(12, 13, 14, sigma=sigma, tau=1.0)
+    o.init(n, u)
+    F = o.force()
+    nn, uu = o.moments()
+    grid = bf.Grid(nn, nn[None] * uu, sigma)
+    nodes = [(1, 2, 3), (11, 12, 13), (5, 0, 7), (0, 0, 0)]
+    Fs, A = grid.force_at(nodes)
+    full = grid.force()
+    for i, (x, y, z) in enumerate(nodes):
+        assert np.array_equal(Fs[:, i], full[:, z, y, x])
+        assert np.abs(Fs[:, i] - F[:, z, y, x]).max() <= 1e-13 * np.abs(F).max()
+        assert np.all(np.abs(Fs[:, i]) <= A[:, i])
+
+
 # --------------------------------------------------------------- uniform fluid
 
 
