@@ -439,6 +439,27 @@ enum { HSLB_CNN_FWD1 = 0, HSLB_CNN_FWD2, HSLB_CNN_FWD3, HSLB_CNN_DX3, HSLB_CNN_D
 int hslb_cnn_op(int32_t op, int32_t nx, int32_t ny, int32_t nz, int32_t zper, const float *w, const float *in,
                 const float *aux, float *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the total
+ * force F[3][N] = C^(1) + n g of the density n[N] and velocity u[3][N] (u may
+ * be NULL: rest) on the lattice *p, as hslb_force returns it for an FP64
+ * context initialised with hslb_init(n, u) (the same kernels, on the local
+ * equilibrium of (n, u)).  n, u and F are caller-owned DEVICE arrays of FP64
+ * in the node order of this header; the work is queued on hip_stream (NULL:
+ * the null stream) and the call returns without synchronising.  *p must be
+ * an FP64 19-velocity lattice with the exact force or none and no attraction.
+ * Every intermediate (populations, moment fields, contact values, tables)
+ * lives in one fixed device-resident array of HSLB_FORCE_NOALLOC_BYTES per GPU
+ * (64 MiB, held from the first call on that GPU until the process ends),
+ * enough for about 200 000 nodes at sigma 8: a lattice that needs more is
+ * rejected with HSLB_EINVAL.  The call allocates nothing.  All calls on one
+ * GPU share the array and it keeps the last call's contents (each call
+ * clears what it reads), so calls that overlap on one GPU race.  Errors:
+ * HSLB_EINVAL (parameters, size, null n or F), HSLB_EDEVICE; the message is in
+ * hslb_last_error(NULL). */
+#define HSLB_FORCE_NOALLOC_BYTES (64ll << 20)
+int hslb_force_noalloc(const hslb_params *p, const double *n, const double *u, double *F, void *hip_stream);
+
 /* Device-to-device copy of `bytes` bytes, repeated `iters` times on a private
  * stream: *gbps = 2 * bytes * iters / elapsed (read + write).  The reference
  * for the achievable HBM bandwidth and the calibration kernel ("k_copy") of the

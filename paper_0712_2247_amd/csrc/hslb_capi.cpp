@@ -2476,6 +2476,76 @@ int hslb_batch_autotune(hslb_ctx *ctx, int32_t steps, int32_t *choice, double *u
     return ctx->eng->batch_autotune(steps, choice, us_per_step, cap);
 }
 
+static_assert(kScratchBytes == (size_t)HSLB_FORCE_NOALLOC_BYTES, "scratch size of the header");
+
+int hslb_force_noalloc(const hslb_params *p, const double *n, const double *u, double *F, void *hip_stream)
+{
+    std::string &err = g_create_err;
+    err.clear();
+    int rc = validate(p, err);
+    if (rc) return rc;
+    if (p->precision != HSLB_FP64 || p->lattice != HSLB_D3Q19 || p->force_mode == HSLB_FORCE_SURROGATE ||
+        p->att_eps != 0.0)
+        return fail(err, HSLB_EINVAL, "hslb_force_noalloc takes FP64 19-velocity lattices, exact or no force, "
+                                      "no attraction");
+    if (!n || !F) return fail(err, HSLB_EINVAL, "null device pointer");
+    LatticeDev L{};
+    StepConst sc{};
+    std::vector<double> chi_h;
+    slit_consts(*p, L, sc, chi_h);
+    const int sig = p->sigma >= 2 ? p->sigma : 2;
+    L.pop_stride = L.N;  // the equilibrium kernel writes [19][N]
+    L.fld_stride = (L.plane * (p->nz + 2 * L.hz) + 63) / 64 * 64;
+    // scratch layout (doubles, each part 256-byte aligned): populations
+    // [19][N], reference table [nz][19] (zeros), chi[nz], then n, (n, j) [4],
+    // eta_bar, the 7 contact-value slots and sigma/2 + 1 row-sum fields
+    auto al = [](size_t d) { return (d + 31) / 32 * 32; };
+    const size_t o_ref = al((size_t)NQ * L.N), o_chi = o_ref + al((size_t)NQ * p->nz);
+    const size_t o_fld = o_chi + al((size_t)p->nz);
+    const size_t nfld = (size_t)(1 + 4 + 1 + NGSLOT + sig / 2 + 1) * L.fld_stride;
+    const size_t need = sizeof(double) * (o_fld + nfld);
+    if (need > kScratchBytes)
+        return fail(err, HSLB_EINVAL, "lattice needs %zu bytes of scratch, more than the %zu the allocation-free "
+                                      "entry point holds", need, kScratchBytes);
+    void *base = nullptr;
+    hipError_t e = scratch_address(&base);
+    if (e != hipSuccess) return fail(err, HSLB_EDEVICE, "scratch address: %s", hipGetErrorString(e));
+    double *d = (double *)base;
+    hipStream_t s = (hipStream_t)hip_stream;
+    Fields<double> fld{};
+    fld.n = d + o_fld;
+    fld.nj = fld.n + L.fld_stride;
+    fld.eb = fld.n + 5 * (size_t)L.fld_stride;
+    fld.G = fld.n + 6 * (size_t)L.fld_stride;
+    double *rs = fld.n + (size_t)(6 + NGSLOT) * L.fld_stride;
+    // the scratch keeps the previous call's contents: clear the reference
+    // table and every field (their padding layers must read zero)
+#define NA_TRY(...)                                                                                        \
+    do {                                                                                                   \
+        hipError_t e_ = (__VA_ARGS__);                                                                     \
+        if (e_ != hipSuccess) return fail(err, HSLB_EDEVICE, "%s: %s", #__VA_ARGS__, hipGetErrorString(e_)); \
+    } while (0)
+    NA_TRY(launch_fill(s, d + o_ref, (size_t)NQ * p->nz, 0.0));
+    NA_TRY(launch_fill(s, fld.n, nfld, 0.0));
+    NA_TRY(launch_chi(s, L, sig, p->wall_reg, d + o_chi));
+    if (u) {
+        NA_TRY(launch_feq(s, L, n, u, d));
+    } else {
+        // rest: the equilibrium of (n, 0) from a zero velocity field held in F
+        NA_TRY(launch_fill(s, F, 3 * (size_t)L.N, 0.0));
+        NA_TRY(launch_feq(s, L, n, F, d));
+    }
+    NA_TRY(launch_moments<double, double>(s, L, d + o_ref, d, fld));
+    if (sc.hs_on) {
+        NA_TRY(launch_smooth2<double>(s, L, sig, sc.eta_pref, fld, rs));
+        NA_TRY(launch_gfield<double>(s, L, sc.g2_model, fld));
+    }
+    sc.nref_r = sc.nref_w = d + o_ref;
+    NA_TRY(launch_force<double, double>(s, L, sig, sc, d + o_chi, d, fld, F));
+#undef NA_TRY
+    return HSLB_OK;
+}
+
 int hslb_copy_bandwidth(int64_t bytes, int32_t iters, double *gbps)
 {
     std::string &err = g_create_err;

@@ -212,6 +212,17 @@ template <typename TM>
 hipError_t launch_attraction(hipStream_t s, const LatticeDev &L, const AttWeights &aw, const TM *n, double *a,
                              double *b, double *phi);
 
+// Device-resident scratch of the allocation-free force entry point: a
+// file-scope array of kScratchBytes on every GPU the library runs on.
+// scratch_address sets *ptr to its device address on the current device
+// (looked up with hipGetSymbolAddress once per device).  launch_fill sets
+// count doubles to v; launch_chi writes the wall factor table chi[nz] of a
+// lattice (1 on periodic z or with wall_reg 0).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+hipError_t scratch_address(void **ptr);
+hipError_t launch_fill(hipStream_t s, double *a, size_t count, double v);
+hipError_t launch_chi(hipStream_t s, const LatticeDev &L, int sigma, int wall_reg, double *chi);
+
 // Batched ensemble: one persistent launch per phase over a work list.
 // phase 0 moments, 1 row sums, 2 ball sums, 3 contact values (the collide
 // phase is launch_batch_collide).

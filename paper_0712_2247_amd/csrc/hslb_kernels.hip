@@ -19,6 +19,7 @@
 #include "hslb_internal.hpp"
 
 #include <algorithm>
+#include <mutex>
 #include <utility>
 #include <cmath>
 #include <type_traits>
@@ -2315,6 +2316,67 @@ hipError_t launch_batch_profiles(hipStream_t s, const SlitDesc *desc, const Work
     template hipError_t launch_batch_collide<TF, TM>(hipStream_t, unsigned, const SlitDesc *,               \
                                                      const WorkItem *, int, const TF *, TF *, Fields<TM>,     \
                                                      const double *);
+
+// ------------------------------------------------ allocation-free scratch
+
+namespace {
+
+// The scratch of hslb_force_noalloc.  Host code reaches it only through the
+// address scratch_address looked up for the current device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+__global__ __launch_bounds__(256) void k_fill(double *__restrict__ a, size_t count, double v)
+{
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256) a[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_chi(LatticeDev L, int sigma, int wall_reg, double *__restrict__ chi)
+{
+    const int z = blockIdx.x * 256 + threadIdx.x;
+    if (z >= L.nz) return;
+    double c = 1.0;
+    if (!L.zper && wall_reg) {
+        const double za = L.wall_lo - 0.5, zb = L.nz - L.wall_hi - 0.5;
+        c = 1.0 - exp(-fmin((double)z - za, zb - (double)z) / (double)sigma);
+    }
+    chi[z] = c;
+}
+
+}  // namespace
+
+hipError_t scratch_address(void **ptr)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_fill(hipStream_t s, double *a, size_t count, double v)
+{
+    if (count == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, s, a, count, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_chi(hipStream_t s, const LatticeDev &L, int sigma, int wall_reg, double *chi)
+{
+    hipLaunchKernelGGL(k_chi, dim3((L.nz + 255) / 256), dim3(256), 0, s, L, sigma, wall_reg, chi);
+    return hipGetLastError();
+}
 
 HSLB_INST_TF(float)
 HSLB_INST_TF(double)

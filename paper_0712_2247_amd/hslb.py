@@ -58,7 +58,7 @@ EXPORTS = (
     "hslb_trainer_create", "hslb_trainer_destroy", "hslb_trainer_last_error",
     "hslb_trainer_add_snapshot", "hslb_trainer_add_snapshot_host", "hslb_trainer_count",
     "hslb_trainer_set_weights", "hslb_trainer_get_weights", "hslb_trainer_eval",
-    "hslb_trainer_grad", "hslb_trainer_step", "hslb_trainer_train", "hslb_cnn_op",
+    "hslb_trainer_grad", "hslb_trainer_step", "hslb_trainer_train", "hslb_cnn_op", "hslb_force_noalloc",
 )
 
 
@@ -132,6 +132,7 @@ def load(path: Optional[str] = None):
                                              _P(ctypes.c_int64), _P(ctypes.c_int32)]),
         "hslb_get_timings": (ctypes.c_int, [_vp, _dp, _dp]),
         "hslb_copy_bandwidth": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, _dp]),
+        "hslb_force_noalloc": (ctypes.c_int, [_P(hslb_params), _vp, _vp, _vp, _vp]),
         "hslb_batch_create": (ctypes.c_int, [_P(hslb_params), ctypes.c_int32, _P(_vp)]),
         "hslb_batch_init": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, _dp]),
         "hslb_batch_profiles": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, _dp]),
@@ -331,6 +332,18 @@ def hslb_copy_bandwidth(nbytes: int, iters: int) -> float:
     if rc != HSLB_OK:
         raise HslbError(rc, load().hslb_last_error(None).decode())
     return v.value
+
+
+HSLB_FORCE_NOALLOC_BYTES = 64 << 20
+
+
+def hslb_force_noalloc(params: hslb_params, n_dev: int, u_dev: Optional[int], F_dev: int, stream: int = 0):
+    """The allocation-free force on device arrays given by address (FP64:
+    n[N], u[3][N] or None, F[3][N]); queued on `stream` without a wait."""
+    rc = load().hslb_force_noalloc(ctypes.byref(params), _vp(n_dev), _vp(u_dev) if u_dev else None, _vp(F_dev),
+                                   _vp(stream) if stream else None)
+    if rc != HSLB_OK:
+        raise HslbError(rc, load().hslb_last_error(None).decode())
 
 
 def hslb_batch_create(slits) -> ctypes.c_void_p:
