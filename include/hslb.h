@@ -265,6 +265,17 @@ int hslb_set_shift_period(hslb_ctx *ctx, int64_t every);
  * one (0).  Both give bitwise identical results. */
 int hslb_set_graph(hslb_ctx *ctx, int32_t enable);
 
+/* Collide kernel of the step (the shell sum of eq. (12) with the BGK update):
+ * 0 (default) reads the shell fields from global memory; 1 stages the (n, j)
+ * entries and contact values of the layer, and the (n, j) entries of the xz
+ * face diagonals, of each 64 x 4 tile of a layer through LDS wherever the
+ * lattice allows it (FP32 storage, nx a multiple of 64 and ny of 4, no solid
+ * mask, hard-sphere force on; else the default kernel runs).  Both give
+ * bitwise identical results; on the 256^3 bulk at sigma 6 the staged kernel
+ * takes about as long as the default one, on the sigma-8 slit longer.
+ * Errors: HSLB_EINVAL (null context). */
+int hslb_set_collide_tiles(hslb_ctx *ctx, int32_t enable);
+
 /* Per-kernel timing with HIP events on the context's stream.  When enabled
  * (and graphs off), hslb_step brackets every kernel launch with events;
  * hslb_kernel_times fills names/total milliseconds/launch counts for up to

@@ -249,6 +249,14 @@ public:
     int64_t watch_every = 0;
     double watch_tol = 0.0;
     bool use_graph = true;
+    // collide with shell fields staged through LDS where the lattice allows
+    // (off by default: it measured no faster than the direct reads)
+    virtual int set_collide_tiles(bool on)
+    {
+        collide_tiles = on;
+        return HSLB_OK;
+    }
+    bool collide_tiles = false;
     int64_t shift_every = 0;  // refresh period of the layer reference densities (0: never)
     KernelTimer kt;
 };
@@ -411,6 +419,13 @@ public:
             io_bytes_ = bytes;
         }
         *out = io_d_;
+        return HSLB_OK;
+    }
+
+    int set_collide_tiles(bool on) override
+    {
+        if (on != collide_tiles) drop_graphs();  // the captured steps hold the other kernel
+        collide_tiles = on;
         return HSLB_OK;
     }
 
@@ -620,7 +635,7 @@ public:
         }
         if (sc_.phi && (rc = attraction())) return rc;
         rc = launch("collide", [&] {
-            return launch_collide<TF, TM>(st(), L_, sigma_, sc_, chi_d_, f_[cur_], f_[1 - cur_], fld_);
+            return launch_collide<TF, TM>(st(), L_, sigma_, sc_, chi_d_, f_[cur_], f_[1 - cur_], fld_, collide_tiles);
         });
         if (rc) return rc;
         cur_ = 1 - cur_;
@@ -1226,7 +1241,7 @@ public:
             return rc;
         HIP_TRY(hipMemcpyAsync(jpart_h_, jpart_, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, st()));
         rc = launch("collide", [&] {
-            return launch_collide<TF, TM>(st(), L_, sigma_, sc_, chi_d_, f_[cur_], f_[1 - cur_], fld_);
+            return launch_collide<TF, TM>(st(), L_, sigma_, sc_, chi_d_, f_[cur_], f_[1 - cur_], fld_, collide_tiles);
         });
         if (rc) return rc;
         cur_ = 1 - cur_;
@@ -2357,6 +2372,12 @@ int hslb_set_graph(hslb_ctx *ctx, int32_t enable)
     CTX_CHECK(ctx);
     ctx->eng->use_graph = enable != 0;
     return HSLB_OK;
+}
+
+int hslb_set_collide_tiles(hslb_ctx *ctx, int32_t enable)
+{
+    CTX_CHECK(ctx);
+    return ctx->eng->set_collide_tiles(enable != 0);
 }
 
 int hslb_set_kernel_timing(hslb_ctx *ctx, int32_t enable)

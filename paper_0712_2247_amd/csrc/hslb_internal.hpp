@@ -154,9 +154,14 @@ template <typename TM>
 hipError_t launch_smooth2(hipStream_t s, const LatticeDev &L, int sigma, double eta_pref, Fields<TM> fld,
                           TM *rs);
 
+// tiles: with FP32 storage and fields, nx a multiple of 64 and ny of 4, no
+// solid mask, the hard-sphere force on and sigma in 2..8, the collide stages
+// shell fields of each 64 x 4 tile through LDS (bit for bit the same result).
 template <typename TF, typename TM>
 hipError_t launch_collide(hipStream_t s, const LatticeDev &L, int sigma, const StepConst &c,
-                          const double *chi, const TF *fin, TF *fout, Fields<TM> fld);
+                          const double *chi, const TF *fin, TF *fout, Fields<TM> fld, bool tiles = false);
+// Whether launch_collide with tiles = true takes the LDS-staged kernel.
+bool collide_tiles_apply(const LatticeDev &L, int sigma, const StepConst &c, bool fp32);
 template <typename TF, typename TM>
 hipError_t launch_force(hipStream_t s, const LatticeDev &L, int sigma, const StepConst &c,
                         const double *chi, const TF *f, Fields<TM> fld, double *F);

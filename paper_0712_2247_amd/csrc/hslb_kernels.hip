@@ -504,6 +504,22 @@ __device__ __forceinline__ void load_pair(const Fields<TM> &F, const LatticeDev 
     }
 }
 
+// The contact values G+ and G- of the pair with offset (DX, DY, DZ) from global
+// memory, addressed as load_pair does for a block of uniform z.
+template <int DX, int DY, int DZ>
+__device__ __forceinline__ void load_g(const Fields<float> &F, const LatticeDev &L, int x, int y, int zp, float &Gp,
+                                       float &Gm)
+{
+    constexpr int SLOT = (DX & 1) | ((DY & 1) << 1) | ((DZ & 1) << 2);
+    constexpr int GB = (int)sizeof(float);
+    const size_t lay = (size_t)L.plane;
+    const char *gs = (const char *)F.G + GB * (size_t)SLOT * L.fld_stride;
+    const char *gzp = gs + GB * lay * (size_t)(zp + floordiv2(DZ));
+    const char *gzm = gs + GB * lay * (size_t)(zp + floordiv2(-DZ));
+    Gp = *(const float *)(gzp + (xb<floordiv2(DX), GB>(x, L.nx) + yb<floordiv2(DY), GB>(y, L.ny, L.nx)));
+    Gm = *(const float *)(gzm + (xb<floordiv2(-DX), GB>(x, L.nx) + yb<floordiv2(-DY), GB>(y, L.ny, L.nx)));
+}
+
 // Difference of the two elements of one mirrored lattice pair, the corner d of
 // direction q and the corner -d of direction -q:
 //   e+ - e- = G+ [n+ - chi kappa s.(j+ - n+ u)] - G- [n- + chi kappa s.(j- - n- u)]
@@ -516,12 +532,9 @@ __device__ __forceinline__ void load_pair(const Fields<TM> &F, const LatticeDev 
 // LZ: z is uniform over the block (layer-indexed grids); the layer parts of
 // the addresses then stay scalar.  Grids with a per-lane z (batch, k_force)
 // form one 32-bit node index per read instead, which needs fewer registers.
-template <int DX, int DY, int DZ, int SX, int SY, int SZ, bool DIAG, bool LZ, typename TM, typename TC>
-__device__ __forceinline__ TC pair_element(const Fields<TM> &F, const LatticeDev &L, const NodeCtx<TC> &c,
-                                           TC su)
+template <int SX, int SY, int SZ, bool DIAG, typename TM, typename TC>
+__device__ __forceinline__ TC pair_math(TM gp, TM gm, const TM qp[4], const TM qm[4], const NodeCtx<TC> &c, TC su)
 {
-    TM gp, gm, qp[4], qm[4];
-    load_pair<DX, DY, DZ, LZ>(F, L, c.x, c.y, c.zp, gp, gm, qp, qm);
     const TC Gp = (TC)gp, Gm = (TC)gm;
     const TC np = (TC)qp[0], nm = (TC)qm[0];
     TC sjp = s_dot_j<SX, SY, SZ, TM, TC>(qp);
@@ -534,6 +547,15 @@ __device__ __forceinline__ TC pair_element(const Fields<TM> &F, const LatticeDev
     const TC cm = sjm - nm * su;
     const TC dens = TC(0.5) * ((Gp + Gm) * (np - nm) + (Gp - Gm) * (np + nm));
     return dens - c.ckap * (Gp * cp + Gm * cm);
+}
+
+template <int DX, int DY, int DZ, int SX, int SY, int SZ, bool DIAG, bool LZ, typename TM, typename TC>
+__device__ __forceinline__ TC pair_element(const Fields<TM> &F, const LatticeDev &L, const NodeCtx<TC> &c,
+                                           TC su)
+{
+    TM gp, gm, qp[4], qm[4];
+    load_pair<DX, DY, DZ, LZ>(F, L, c.x, c.y, c.zp, gp, gm, qp, qm);
+    return pair_math<SX, SY, SZ, DIAG>(gp, gm, qp, qm, c, su);
 }
 
 // Offsets of corner (LA, LB) of the face diagonal with signs (SA, SB) in plane
@@ -549,27 +571,34 @@ struct Diag {
     static constexpr int SZ = (PL == 0) ? 0 : SB;
 };
 
-template <int PL, int SA, int SB, int LA, int LB, bool LZ, typename TM, typename TC>
-__device__ __forceinline__ TC diag_pair_element(const Fields<TM> &F, const LatticeDev &L, const NodeCtx<TC> &c,
-                                                TC su)
-{
-    using D = Diag<PL, SA, SB, LA, LB>;
-    return pair_element<D::DX, D::DY, D::DZ, D::SX, D::SY, D::SZ, true, LZ>(F, L, c, su);
-}
+// Pair elements read from global memory (the padded fields, any field type).
+template <bool LZ, typename TM>
+struct GlobalShell {
+    const Fields<TM> &F;
+    const LatticeDev &L;
+    template <int DX, int DY, int DZ, int SX, int SY, int SZ, bool DIAG, typename TC>
+    __device__ __forceinline__ TC elem(const NodeCtx<TC> &c, TC su) const
+    {
+        return pair_element<DX, DY, DZ, SX, SY, SZ, DIAG, LZ>(F, L, c, su);
+    }
+};
 
 // The interpolated quadrature point q = (SA, SB) in plane PL and its mirror -q:
 // W s_q sum_k alpha_k (e+_k - e-_k), k over the four bilinear corners.
-template <int PL, int SA, int SB, int LL, bool LZ, typename TM, typename TC>
-__device__ __forceinline__ void diag_pair(const Fields<TM> &F, const LatticeDev &L, const NodeCtx<TC> &c,
-                                          const TC *alpha, TC S[3])
+template <int PL, int SA, int SB, int LL, typename SRC, typename TC>
+__device__ __forceinline__ void diag_pair(const SRC &src, const NodeCtx<TC> &c, const TC *alpha, TC S[3])
 {
     constexpr int A = (PL == 2) ? 1 : 0;
     constexpr int B = (PL == 0) ? 1 : 2;
+    using D00 = Diag<PL, SA, SB, LL, LL>;
+    using D01 = Diag<PL, SA, SB, LL, LL + 1>;
+    using D10 = Diag<PL, SA, SB, LL + 1, LL>;
+    using D11 = Diag<PL, SA, SB, LL + 1, LL + 1>;
     const TC su = TC(0.70710678118654752440) * (TC(SA) * c.u[A] + TC(SB) * c.u[B]);
-    TC d = alpha[0] * diag_pair_element<PL, SA, SB, LL, LL, LZ>(F, L, c, su);
-    d += alpha[1] * diag_pair_element<PL, SA, SB, LL, LL + 1, LZ>(F, L, c, su);
-    d += alpha[2] * diag_pair_element<PL, SA, SB, LL + 1, LL, LZ>(F, L, c, su);
-    d += alpha[3] * diag_pair_element<PL, SA, SB, LL + 1, LL + 1, LZ>(F, L, c, su);
+    TC d = alpha[0] * src.template elem<D00::DX, D00::DY, D00::DZ, D00::SX, D00::SY, D00::SZ, true>(c, su);
+    d += alpha[1] * src.template elem<D01::DX, D01::DY, D01::DZ, D01::SX, D01::SY, D01::SZ, true>(c, su);
+    d += alpha[2] * src.template elem<D10::DX, D10::DY, D10::DZ, D10::SX, D10::SY, D10::SZ, true>(c, su);
+    d += alpha[3] * src.template elem<D11::DX, D11::DY, D11::DZ, D11::SX, D11::SY, D11::SZ, true>(c, su);
     const TC w = TC((1.0 / 15.0) * 0.70710678118654752440) * d;
     S[A] += TC(SA) * w;
     S[B] += TC(SB) * w;
@@ -582,16 +611,220 @@ __device__ __forceinline__ void shell_sum(const Fields<TM> &F, const LatticeDev 
                                           const TC *alpha, TC S[3])
 {
     constexpr int LL = ell_of(SIG);
+    const GlobalShell<LZ, TM> src{F, L};
     const TC w30 = TC(1.0 / 30.0);
     S[0] = w30 * pair_element<SIG, 0, 0, 1, 0, 0, false, LZ>(F, L, c, c.u[0]);
     S[1] = w30 * pair_element<0, SIG, 0, 0, 1, 0, false, LZ>(F, L, c, c.u[1]);
     S[2] = w30 * pair_element<0, 0, SIG, 0, 0, 1, false, LZ>(F, L, c, c.u[2]);
-    diag_pair<0, 1, 1, LL, LZ>(F, L, c, alpha, S);
-    diag_pair<0, 1, -1, LL, LZ>(F, L, c, alpha, S);
-    diag_pair<1, 1, 1, LL, LZ>(F, L, c, alpha, S);
-    diag_pair<1, 1, -1, LL, LZ>(F, L, c, alpha, S);
-    diag_pair<2, 1, 1, LL, LZ>(F, L, c, alpha, S);
-    diag_pair<2, 1, -1, LL, LZ>(F, L, c, alpha, S);
+    diag_pair<0, 1, 1, LL>(src, c, alpha, S);
+    diag_pair<0, 1, -1, LL>(src, c, alpha, S);
+    diag_pair<1, 1, 1, LL>(src, c, alpha, S);
+    diag_pair<1, 1, -1, LL>(src, c, alpha, S);
+    diag_pair<2, 1, 1, LL>(src, c, alpha, S);
+    diag_pair<2, 1, -1, LL>(src, c, alpha, S);
+}
+
+// ------------------------------------- shell sum staged through LDS (FP32 fields)
+//
+// A block of 256 threads owns a 64 x 4 tile of one layer (a wave per row, so
+// the population accesses stay whole rows).  The shell reads of neighbouring
+// nodes overlap: an (n, j) entry of the layer is read by up to 20 nodes of the
+// tile, one of the layers z -+ l, z -+ (l + 1) by up to 4 through the face
+// diagonals of the xz plane.  The block copies those regions of the shell
+// fields into LDS once, with global-to-LDS loads issued together with the
+// population loads (their latency overlaps the moment sums):
+//   A   layer z: (n, j) over the tile widened by sigma in x and y (the pairs
+//       along x and y, the face diagonals of the xy plane) and contact-value
+//       slots 0..3 widened by GH;
+//   B   layers z -+ (l + 1), z -+ l: (n, j) widened by l + 1 in x (face
+//       diagonals of the xz plane), optionally the 8 contact-value planes
+//       they read (STAGE_BG).
+// The pair along z and the face diagonals of the yz plane, whose reads a
+// 4-row tile hardly shares, read global memory.  The elements are summed in
+// the order of shell_sum with the same arithmetic, so the force is bit for bit
+// that of the direct reads.  The halo of a 64 x 4 tile is large (phase A copies
+// 4.75 entries per node of the tile), and the copies cost about what the
+// gathers they replace cost: the kernel is an option, not the default.
+namespace stage {
+constexpr int TX = 64, TY = 4;  // tile
+constexpr int GH = 4;           // contact-value halo: |floor(d / 2)| <= 4 for sigma <= 8
+constexpr int GWX = TX + 2 * GH;
+static_assert(GWX % 4 == 0 && GH % 4 == 0, "contact-value rows are copied as float4");
+static_assert(TX * TY == 256, "a block of 256 threads per tile");
+
+// Which contact values go through LDS (phase A, phase B); the others are read
+// from global memory like the pair along z.  Measured on the 256^3 bulk
+// (sigma 6): staging both needs 61 KB of LDS per block (two blocks per compute
+// unit) and takes 1764 us per collide; staging neither, 2035 us; phase A's
+// only (52 KB, three blocks), 1554 us, the best of the three.
+constexpr bool STAGE_AG = true, STAGE_BG = false;
+
+template <int SIG>
+struct Geo {
+    static_assert(SIG >= 2 && SIG <= 8, "staged shell sum covers sigma 2..8");
+    static constexpr int LL = ell_of(SIG);
+    static constexpr int H1 = LL + 1;
+    static constexpr int AWX = TX + 2 * SIG, AWY = TY + 2 * SIG;  // phase A (n, j) region
+    static constexpr int AGY = TY + 2 * GH;                         // phase A contact-value rows
+    static constexpr int BWX = TX + 2 * H1;                         // phase B (n, j) rows
+    static constexpr int A_NJ = AWX * AWY;                          // float4 entries
+    static constexpr int B_NJ = 4 * BWX * TY;
+    static constexpr int A_G4 = STAGE_AG ? 4 * AGY * (GWX / 4) : 0;  // float4 entries
+    static constexpr int B_G4 = STAGE_BG ? 8 * TY * (GWX / 4) : 0;
+    // one LDS array of float4: A (n, j), B (n, j), A contact values, B contact values
+    static constexpr int O_BNJ = A_NJ, O_AG = A_NJ + B_NJ, O_BG = O_AG + A_G4;
+    static constexpr int SIZE = O_BG + B_G4;
+    // layer offsets of phase B, indexed -(l+1), -l, l, l+1
+    __host__ __device__ static constexpr int zi(int dz)
+    {
+        return dz == -H1 ? 0 : (dz == -LL ? 1 : (dz == LL ? 2 : 3));
+    }
+    __host__ __device__ static constexpr int dz_of(int i)
+    {
+        return i == 0 ? -H1 : (i == 1 ? -LL : (i == 2 ? LL : H1));
+    }
+};
+// the largest contact-value offset, floor(-sigma / 2), stays inside the halo
+static_assert(floordiv2(-8) >= -GH && floordiv2(8) <= GH, "contact-value halo");
+
+struct Tile {
+    float4 *lds;  // Geo<SIG>::SIZE entries
+    int x0, y0;   // tile origin
+    int lx, ly;   // this node inside the tile
+};
+
+// Global-to-LDS load of 16 bytes per lane: lane l of the wave writes LDS
+// entry `wave_base` + l (wave_base is uniform over the wave).
+__device__ __forceinline__ void to_lds(const float4 *src, float4 *wave_base)
+{
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                     (__attribute__((address_space(3))) void *)wave_base, 16, 0, 0);
+}
+
+// Entries [0, CNT) of a region, entry i from src_of(i): the wave issuing
+// entries [256 k + 64 w, 256 k + 64 w + 64) writes them to dst + that range.
+template <int CNT, typename F>
+__device__ __forceinline__ void copy_region(float4 *dst, F src_of)
+{
+    const int w64 = __builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~63;
+#pragma unroll
+    for (int k = 0; k < (CNT + 255) / 256; ++k) {
+        const int i = (int)threadIdx.x + 256 * k;
+        if (i < CNT) to_lds(src_of(i), dst + 256 * k + w64);
+    }
+}
+
+// Issues the copies of phases A and B for the tile of layer zp (padded index).
+template <int SIG>
+__device__ __forceinline__ void copy_tile(const Fields<float> &F, const LatticeDev &L, const Tile &t, int zp)
+{
+    using G = Geo<SIG>;
+    const float4 *nj = (const float4 *)F.nj;
+    const size_t pl = (size_t)L.plane;
+    // A (n, j): [x0 - SIG, x0 + TX + SIG) x [y0 - SIG, y0 + TY + SIG) of layer zp
+    copy_region<G::A_NJ>(t.lds, [&](int i) {
+        const int ry = i / G::AWX, rx = i - ry * G::AWX;
+        const int gx = wrapr(t.x0 + rx - SIG, L.nx), gy = wrapr(t.y0 + ry - SIG, L.ny);
+        return nj + pl * (size_t)zp + (gx + L.nx * gy);
+    });
+    // B (n, j): layers zp + dz_of(p), [x0 - H1, x0 + TX + H1) x [y0, y0 + TY)
+    copy_region<G::B_NJ>(t.lds + G::O_BNJ, [&](int i) {
+        const int p = i / (G::BWX * TY), rem = i - p * (G::BWX * TY);
+        const int ry = rem / G::BWX, rx = rem - ry * G::BWX;
+        const int gx = wrapr(t.x0 + rx - G::H1, L.nx);
+        return nj + pl * (size_t)(zp + G::dz_of(p)) + (gx + L.nx * (t.y0 + ry));
+    });
+    // A contact values: slots 0..3 of layer zp, [x0 - GH, x0 + TX + GH) x [y0 - GH, y0 + TY + GH)
+    constexpr int R4 = GWX / 4;
+    if constexpr (STAGE_AG) copy_region<G::A_G4>(t.lds + G::O_AG, [&](int i) {
+        const int slot = i / (G::AGY * R4), rem = i - slot * (G::AGY * R4);
+        const int ry = rem / R4, c4 = rem - ry * R4;
+        const int gx = wrapr(t.x0 - GH + 4 * c4, L.nx), gy = wrapr(t.y0 + ry - GH, L.ny);
+        return (const float4 *)(F.G + (size_t)slot * L.fld_stride + pl * (size_t)zp + (gx + L.nx * gy));
+    });
+    // B contact values: plane c = (layer offset p, x parity b) = 2 p + b holds slot
+    // b | (dz & 1) << 2 of layer zp + floor(dz / 2), [x0 - GH, x0 + TX + GH) x [y0, y0 + TY)
+    if constexpr (STAGE_BG) copy_region<G::B_G4>(t.lds + G::O_BG, [&](int i) {
+        const int c = i / (TY * R4), rem = i - c * (TY * R4);
+        const int ry = rem / R4, c4 = rem - ry * R4;
+        const int dz = G::dz_of(c >> 1);
+        const int slot = (c & 1) | ((dz & 1) << 2);
+        const int gx = wrapr(t.x0 - GH + 4 * c4, L.nx);
+        return (const float4 *)(F.G + (size_t)slot * L.fld_stride + pl * (size_t)(zp + floordiv2(dz)) +
+                                (gx + L.nx * (t.y0 + ry)));
+    });
+}
+
+// Pair elements read from the staged regions of phase PH (0: A, 1: B).
+template <int SIG, int PH>
+struct StagedShell {
+    const Tile &t;
+    const Fields<float> &F;
+    const LatticeDev &L;
+    template <int DX, int DY, int DZ, int SX, int SY, int SZ, bool DIAG, typename TC>
+    __device__ __forceinline__ TC elem(const NodeCtx<TC> &c, TC su) const
+    {
+        using G = Geo<SIG>;
+        const float *g = (const float *)t.lds;
+        float4 a, b;
+        float gp, gm;
+        if constexpr (PH == 0) {
+            static_assert(DZ == 0, "phase A holds layer z");
+            constexpr int slot = (DX & 1) | ((DY & 1) << 1);
+            const int o = t.ly * G::AWX + t.lx;
+            a = t.lds[o + (DY + SIG) * G::AWX + DX + SIG];
+            b = t.lds[o + (SIG - DY) * G::AWX + SIG - DX];
+            if constexpr (STAGE_AG) {
+                const int og = 4 * G::O_AG + slot * G::AGY * GWX + t.ly * GWX + t.lx;
+                gp = g[og + (floordiv2(DY) + GH) * GWX + floordiv2(DX) + GH];
+                gm = g[og + (floordiv2(-DY) + GH) * GWX + floordiv2(-DX) + GH];
+            } else {
+                load_g<DX, DY, DZ>(F, L, c.x, c.y, c.zp, gp, gm);
+            }
+        } else {
+            static_assert(DY == 0, "phase B holds the xz diagonals");
+            constexpr int cp = 2 * G::zi(DZ) + (DX & 1), cm = 2 * G::zi(-DZ) + (DX & 1);
+            const int o = G::O_BNJ + t.ly * G::BWX + t.lx + G::H1;
+            a = t.lds[o + G::zi(DZ) * G::BWX * TY + DX];
+            b = t.lds[o + G::zi(-DZ) * G::BWX * TY - DX];
+            if constexpr (STAGE_BG) {
+                const int og = 4 * G::O_BG + t.ly * GWX + t.lx + GH;
+                gp = g[og + cp * TY * GWX + floordiv2(DX)];
+                gm = g[og + cm * TY * GWX + floordiv2(-DX)];
+            } else {
+                load_g<DX, DY, DZ>(F, L, c.x, c.y, c.zp, gp, gm);
+            }
+        }
+        const float qp[4] = {a.x, a.y, a.z, a.w}, qm[4] = {b.x, b.y, b.z, b.w};
+        return pair_math<SX, SY, SZ, DIAG>(gp, gm, qp, qm, c, su);
+    }
+};
+
+}  // namespace stage
+
+// shell_sum with the pairs of layer z and the face diagonals of the xz plane
+// read from the LDS regions that copy_tile filled; every thread of the block
+// calls it (it waits for the copies and synchronises the block).
+template <int SIG, typename TC>
+__device__ __forceinline__ void shell_sum_staged(const Fields<float> &F, const LatticeDev &L, const NodeCtx<TC> &c,
+                                                 const TC *alpha, TC S[3], const stage::Tile &t)
+{
+    constexpr int LL = ell_of(SIG);
+    const TC w30 = TC(1.0 / 30.0);
+    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's global-to-LDS loads
+    __syncthreads();
+    const stage::StagedShell<SIG, 0> a{t, F, L};
+    const stage::StagedShell<SIG, 1> b{t, F, L};
+    const GlobalShell<true, float> direct{F, L};
+    S[0] = w30 * a.template elem<SIG, 0, 0, 1, 0, 0, false>(c, c.u[0]);
+    S[1] = w30 * a.template elem<0, SIG, 0, 0, 1, 0, false>(c, c.u[1]);
+    S[2] = w30 * pair_element<0, 0, SIG, 0, 0, 1, false, true>(F, L, c, c.u[2]);
+    diag_pair<0, 1, 1, LL>(a, c, alpha, S);
+    diag_pair<0, 1, -1, LL>(a, c, alpha, S);
+    diag_pair<1, 1, 1, LL>(b, c, alpha, S);
+    diag_pair<1, 1, -1, LL>(b, c, alpha, S);
+    diag_pair<2, 1, 1, LL>(direct, c, alpha, S);
+    diag_pair<2, 1, -1, LL>(direct, c, alpha, S);
 }
 
 // Mean-field attraction at a fluid node: -n times the central difference of
@@ -612,10 +845,12 @@ __device__ __forceinline__ void att_force(const LatticeDev &L, const StepConst &
 }
 
 // Total force C^(1) + n g at a fluid node with local moments (n, u).
-template <int SIG, bool LZ, typename TM, bool MASK = true>
+// STAGED: the shell sum reads LDS through the block's tile *tile (FP32 fields;
+// every thread of the block must call).
+template <int SIG, bool LZ, typename TM, bool MASK = true, bool STAGED = false>
 __device__ __forceinline__ void node_force(const Fields<TM> &F, const LatticeDev &L, const StepConst &sc,
                                            const double *__restrict__ chi, int x, int y, int z, double n,
-                                           const double u[3], double Fo[3])
+                                           const double u[3], double Fo[3], const stage::Tile *tile = nullptr)
 {
 #if HSLB_FORCE_FP64
     using TC = double;
@@ -648,7 +883,10 @@ __device__ __forceinline__ void node_force(const Fields<TM> &F, const LatticeDev
         else
             c.ckap = (TC)(chi[z] * sc.kappa);
         const TC alpha[4] = {(TC)sc.alpha[0], (TC)sc.alpha[1], (TC)sc.alpha[2], (TC)sc.alpha[3]};
-        shell_sum<SIG, LZ>(F, L, c, alpha, S);
+        if constexpr (STAGED)
+            shell_sum_staged<SIG>(F, L, c, alpha, S, *tile);
+        else
+            shell_sum<SIG, LZ>(F, L, c, alpha, S);
     }
     double Fa[3] = {0.0, 0.0, 0.0};
     if (sc.phi) att_force(L, sc, x, y, z, n, Fa);
@@ -661,11 +899,12 @@ __device__ __forceinline__ void node_force(const Fields<TM> &F, const LatticeDev
 
 // ------------------------------------------------- collide and stream
 
-// Node r (0 <= r < plane) of fluid layer z.
-template <int SIG, bool LZ, typename TF, typename TM, bool MASK = false, bool NT = false>
+// Node r (0 <= r < plane) of fluid layer z.  STAGED: the shell sum goes
+// through the LDS tile *tile (see shell_sum_staged).
+template <int SIG, bool LZ, typename TF, typename TM, bool MASK = false, bool NT = false, bool STAGED = false>
 __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &sc, const double *__restrict__ chi,
                                           const TF *__restrict__ fin, TF *__restrict__ fout, const Fields<TM> &fld,
-                                          int z, int r)
+                                          int z, int r, const stage::Tile *tile = nullptr)
 {
     const int y = r / L.nx;
     const int x = r - y * L.nx;
@@ -711,6 +950,8 @@ __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &
 #pragma unroll
         for (int i = 0; i < NQ; ++i) fs[i] = fin[(size_t)i * L.pop_stride + id];
     }
+    // the staged shell fields load into LDS while the moments are summed
+    if constexpr (STAGED) stage::copy_tile<SIG>(fld, L, *tile, z + L.hz);
     double n = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
@@ -726,7 +967,7 @@ __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &
     const double inv_n = (n != 0.0) ? 1.0 / n : 0.0;
     const double u[3] = {jx * inv_n, jy * inv_n, jz * inv_n};
     double Fv[3];
-    node_force<SIG, LZ, TM, MASK>(fld, L, sc, chi, x, y, z, n, u, Fv);
+    node_force<SIG, LZ, TM, MASK, STAGED>(fld, L, sc, chi, x, y, z, n, u, Fv, tile);
 
     // BGK relaxation (10) towards the equilibrium (11), with the first-order
     // source, for opposite velocities i and i + 1 together: with cu = c_i.u,
@@ -841,6 +1082,34 @@ __global__ __launch_bounds__(256, HSLB_COLLIDE_WAVES) void k_collide(LatticeDev 
     const int r = c * 256 + threadIdx.x;
     const int z = (L.zper ? 0 : L.wall_lo) + zl;
     if (r < L.plane) d_collide<SIG, true, TF, TM, MASK, NT>(L, sc, chi, fin, fout, fld, z, r);
+}
+
+// k_collide for FP32 storage and fields with the shell sum staged through LDS:
+// one block per 64 x 4 tile of a fluid layer (nx a multiple of 64, ny of 4, no
+// solid mask, hard-sphere force on, sigma 2..8); blocks in (layer, tile row,
+// tile) order, spread over the XCDs as k_collide's.  Up to 59 KB of LDS per
+// block: three blocks per compute unit for sigma <= 6, two above.
+template <int SIG, bool NT>
+__global__ __launch_bounds__(256, 3) void k_collide_tiles(LatticeDev L, StepConst sc, const double *__restrict__ chi,
+                                                          const float *__restrict__ fin, float *__restrict__ fout,
+                                                          Fields<float> fld)
+{
+    __shared__ float4 s_lds[stage::Geo<SIG>::SIZE];
+    const int tnx = L.nx / stage::TX;
+    const int tpl = tnx * (L.ny / stage::TY);
+    const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int zl = lb / tpl;
+    const int tl = lb - zl * tpl;
+    const int ty = tl / tnx;
+    stage::Tile tile;
+    tile.lds = s_lds;
+    tile.x0 = (tl - ty * tnx) * stage::TX;
+    tile.y0 = ty * stage::TY;
+    tile.lx = (int)threadIdx.x % stage::TX;
+    tile.ly = (int)threadIdx.x / stage::TX;
+    const int r = (tile.y0 + tile.ly) * L.nx + tile.x0 + tile.lx;
+    const int z = (L.zper ? 0 : L.wall_lo) + zl;
+    d_collide<SIG, true, float, float, false, NT, true>(L, sc, chi, fin, fout, fld, z, r, &tile);
 }
 
 template <int SIG, typename TF, typename TM>
@@ -2154,9 +2423,42 @@ template <typename TF, typename TM, bool M, bool NT>
 hipError_t launch_collide_t(hipStream_t s, int sigma, dim3 g, dim3 b, const LatticeDev &L, const StepConst &c,
                             const double *chi, const TF *fin, TF *fout, Fields<TM> fld, int cpp);
 
+bool collide_tiles_apply(const LatticeDev &L, int sigma, const StepConst &c, bool fp32)
+{
+    return fp32 && !c.links && c.hs_on && sigma >= 2 && sigma <= 8 && L.nx % stage::TX == 0 &&
+           L.ny % stage::TY == 0;
+}
+
+template <bool NT>
+hipError_t launch_collide_tiles_t(hipStream_t s, int sigma, int layers, const LatticeDev &L, const StepConst &c,
+                                  const double *chi, const float *fin, float *fout, Fields<float> fld)
+{
+    const dim3 g((unsigned)(layers * (L.nx / stage::TX) * (L.ny / stage::TY))), b(256);
+    switch (sigma) {
+    case 2: hipLaunchKernelGGL((k_collide_tiles<2, NT>), g, b, 0, s, L, c, chi, fin, fout, fld); break;
+    case 3: hipLaunchKernelGGL((k_collide_tiles<3, NT>), g, b, 0, s, L, c, chi, fin, fout, fld); break;
+    case 4: hipLaunchKernelGGL((k_collide_tiles<4, NT>), g, b, 0, s, L, c, chi, fin, fout, fld); break;
+    case 5: hipLaunchKernelGGL((k_collide_tiles<5, NT>), g, b, 0, s, L, c, chi, fin, fout, fld); break;
+    case 6: hipLaunchKernelGGL((k_collide_tiles<6, NT>), g, b, 0, s, L, c, chi, fin, fout, fld); break;
+    case 7: hipLaunchKernelGGL((k_collide_tiles<7, NT>), g, b, 0, s, L, c, chi, fin, fout, fld); break;
+    case 8: hipLaunchKernelGGL((k_collide_tiles<8, NT>), g, b, 0, s, L, c, chi, fin, fout, fld); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_collide_tiles(hipStream_t s, int sigma, int layers, bool nt, const LatticeDev &L,
+                                const StepConst &c, const double *chi, const float *fin, float *fout,
+                                Fields<float> fld)
+{
+    return nt ? launch_collide_tiles_t<true>(s, sigma, layers, L, c, chi, fin, fout, fld)
+              : launch_collide_tiles_t<false>(s, sigma, layers, L, c, chi, fin, fout, fld);
+}
+
+
 template <typename TF, typename TM>
 hipError_t launch_collide(hipStream_t s, const LatticeDev &L, int sigma, const StepConst &c, const double *chi,
-                          const TF *fin, TF *fout, Fields<TM> fld)
+                          const TF *fin, TF *fout, Fields<TM> fld, bool tiles)
 {
     const int layers = L.zper ? L.nz : L.nz - L.wall_lo - L.wall_hi;
     const int cpp = (int)blocks_for(L.plane);
@@ -2165,6 +2467,10 @@ hipError_t launch_collide(hipStream_t s, const LatticeDev &L, int sigma, const S
     // populations beyond the last-level cache (two copies over 128 MiB) stream
     // non-temporally
     const double pop_bytes = 2.0 * NQ * (double)L.pop_stride * sizeof(TF);
+    if constexpr (std::is_same<TF, float>::value && std::is_same<TM, float>::value) {
+        if (tiles && collide_tiles_apply(L, sigma, c, true))
+            return launch_collide_tiles(s, sigma, layers, pop_bytes > 128.0 * 1024 * 1024, L, c, chi, fin, fout, fld);
+    }
     if (pop_bytes > 128.0 * 1024 * 1024)
         return launch_collide_t<TF, TM, false, true>(s, sigma, g, b, L, c, chi, fin, fout, fld, cpp);
     return launch_collide_t<TF, TM, false, false>(s, sigma, g, b, L, c, chi, fin, fout, fld, cpp);
@@ -2307,7 +2613,7 @@ hipError_t launch_batch_profiles(hipStream_t s, const SlitDesc *desc, const Work
     template hipError_t launch_moments_rs<TF, TM>(hipStream_t, const LatticeDev &, int, const double *,      \
                                                   const TF *, Fields<TM>, TM *);                            \
     template hipError_t launch_collide<TF, TM>(hipStream_t, const LatticeDev &, int, const StepConst &,    \
-                                               const double *, const TF *, TF *, Fields<TM>);               \
+                                               const double *, const TF *, TF *, Fields<TM>, bool);         \
     template hipError_t launch_force<TF, TM>(hipStream_t, const LatticeDev &, int, const StepConst &,      \
                                              const double *, const TF *, Fields<TM>, double *);              \
     template hipError_t launch_batch_phase<TF, TM>(hipStream_t, int, unsigned, const SlitDesc *,            \

@@ -50,7 +50,7 @@ EXPORTS = (
     "hslb_set_populations",
     "hslb_set_watchdog", "hslb_set_shift_period", "hslb_set_graph",
     "hslb_checkpoint_size", "hslb_checkpoint_save", "hslb_checkpoint_load", "hslb_set_kernel_timing", "hslb_kernel_times",
-    "hslb_get_timings", "hslb_copy_bandwidth",
+    "hslb_get_timings", "hslb_copy_bandwidth", "hslb_set_collide_tiles",
     "hslb_batch_create", "hslb_batch_init", "hslb_batch_profiles", "hslb_batch_finite",
     "hslb_batch_set_config", "hslb_batch_set_launch", "hslb_batch_get_launch", "hslb_batch_autotune",
     "hslb_surrogate_set_weights", "hslb_surrogate_get_weights", "hslb_surrogate_set_mode",
@@ -127,6 +127,7 @@ def load(path: Optional[str] = None):
         "hslb_checkpoint_save": (ctypes.c_int, [_vp, ctypes.c_void_p]),
         "hslb_checkpoint_load": (ctypes.c_int, [_vp, ctypes.c_void_p]),
         "hslb_set_graph": (ctypes.c_int, [_vp, ctypes.c_int32]),
+        "hslb_set_collide_tiles": (ctypes.c_int, [_vp, ctypes.c_int32]),
         "hslb_set_kernel_timing": (ctypes.c_int, [_vp, ctypes.c_int32]),
         "hslb_kernel_times": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_void_p, _dp,
                                              _P(ctypes.c_int64), _P(ctypes.c_int32)]),
@@ -299,6 +300,10 @@ def hslb_set_shift_period(ctx, every: int):
 
 def hslb_set_graph(ctx, enable: bool):
     _chk(ctx, load().hslb_set_graph(ctx, int(bool(enable))))
+
+
+def hslb_set_collide_tiles(ctx, enable: bool):
+    _chk(ctx, load().hslb_set_collide_tiles(ctx, int(bool(enable))))
 
 
 def hslb_set_kernel_timing(ctx, enable: bool):
