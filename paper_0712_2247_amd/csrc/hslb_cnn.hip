@@ -167,17 +167,55 @@ __global__ __launch_bounds__(256) void k_conv_fwd(FwdArgs a)
 #pragma unroll
         for (int h = 0; h < NH; ++h) acc[r][h] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-    for (int s = 0; s < KS; ++s) {
-        bf16x8 bw[NH];
+    if constexpr (NH == 2) {
+        // The B operands (the same for every block, so cache hits) are loaded
+        // PD K-steps ahead into a register ring; rows past the end of a partial
+        // z tile are computed on the staged zeros or wrapped layers and not
+        // stored, which keeps the loop free of branches.  Layer 2 (32 -> 32)
+        // on the 64x64x136 slit: 285 -> 247 us.  The 3-channel layer gains
+        // nothing from it (fewer products per step) and keeps the plain loop.
+        constexpr int PD = 8;
+        auto load_b = [&](int s, int h) { return *(const u32x4 *)(a.wp + ((size_t)(s * NH + h) * 64 + lane) * 8); };
+        u32x4 bq[PD][NH];
 #pragma unroll
-        for (int h = 0; h < NH; ++h) bw[h] = as_bf(*(const u32x4 *)(a.wp + ((size_t)(s * NH + h) * 64 + lane) * 8));
+        for (int q = 0; q < PD; ++q)
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
-            if (r < rows) {
-                const bf16x8 av = as_bf(lds_a<CIN>(tile, s, li, w, r, lg));
+            for (int h = 0; h < NH; ++h) bq[q][h] = q < KS ? load_b(q, h) : (u32x4){0u, 0u, 0u, 0u};
+        for (int s0 = 0; s0 < KS; s0 += PD) {
 #pragma unroll
-                for (int h = 0; h < NH; ++h)
-                    acc[r][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[h], acc[r][h], 0, 0, 0);
+            for (int q = 0; q < PD; ++q) {
+                const int s = s0 + q;
+                if (s < KS) {
+                    bf16x8 av[ROWS], bw[NH];
+#pragma unroll
+                    for (int r = 0; r < ROWS; ++r) av[r] = as_bf(lds_a<CIN>(tile, s, li, w, r, lg));
+#pragma unroll
+                    for (int h = 0; h < NH; ++h) {
+                        bw[h] = as_bf(bq[q][h]);
+                        if (s + PD < KS) bq[q][h] = load_b(s + PD, h);
+                    }
+#pragma unroll
+                    for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                        for (int h = 0; h < NH; ++h)
+                            acc[r][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[r], bw[h], acc[r][h], 0, 0, 0);
+                }
+            }
+        }
+    } else {
+        for (int s = 0; s < KS; ++s) {
+            bf16x8 bw[NH];
+#pragma unroll
+            for (int h = 0; h < NH; ++h)
+                bw[h] = as_bf(*(const u32x4 *)(a.wp + ((size_t)(s * NH + h) * 64 + lane) * 8));
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                if (r < rows) {
+                    const bf16x8 av = as_bf(lds_a<CIN>(tile, s, li, w, r, lg));
+#pragma unroll
+                    for (int h = 0; h < NH; ++h)
+                        acc[r][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[h], acc[r][h], 0, 0, 0);
+                }
             }
         }
     }
