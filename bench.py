@@ -153,9 +153,10 @@ def _golden_profiles(step: int):
     return np.array(snap["n_z"]), np.array(snap["u_z"])
 
 
-def surrogate_leg(hslb, np, workloads, wl, steps: int, epochs: int):
+def surrogate_leg(hslb, np, workloads, wl, steps: int, epochs: int, nruns: int = 40):
     """The learned force on the 64x64x136 slit at packing 0.25: snapshots of
-    the 40 training slits (64x64xnz, sigma 4..8, stable runs only), Adam on
+    the first `nruns` of the 40 training slits (64x64xnz, sigma 4..8, stable
+    runs only), Adam on
     the GPU, then `steps` steps of the surrogate path (exact judge every 50
     steps, residual threshold 1e-3) with the network plus frozen correction,
     and without the network (frozen exact force: the ablation), against the
@@ -164,7 +165,7 @@ def surrogate_leg(hslb, np, workloads, wl, steps: int, epochs: int):
     whose every step fell back to the exact force has measured only the exact
     path."""
     from paper_0712_2247_amd import surrogate
-    runs = workloads.surrogate_training_runs()
+    runs = workloads.surrogate_training_runs()[:nruns]
     tr = hslb.Trainer(sum(w.nodes for w in runs) * 100 + 1, max(w.nodes for w in runs))
     t0 = time.perf_counter()
     recs = surrogate.collect(tr, runs, 20, 2000)
@@ -412,6 +413,8 @@ def main():
     ap.add_argument("--surrogate-epochs", type=int, default=2)
     ap.add_argument("--surrogate-steps", type=int, default=5000,
                     help="steps of each surrogate-path run (a step count of the oracle's stored run)")
+    ap.add_argument("--surrogate-runs", type=int, default=40,
+                    help="training slits the learned force collects snapshots from (the first N of 40)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the library has no "
@@ -492,7 +495,8 @@ def main():
     surr = None
     if not args.no_surrogate:
         print("bench: surrogate", file=sys.stderr, flush=True)
-        surr = surrogate_leg(hslb, np, workloads, swl, args.surrogate_steps, args.surrogate_epochs)
+        surr = surrogate_leg(hslb, np, workloads, swl, args.surrogate_steps, args.surrogate_epochs,
+                            args.surrogate_runs)
 
     att = None
     if not args.no_attraction:
