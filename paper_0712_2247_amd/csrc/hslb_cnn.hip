@@ -9,7 +9,9 @@
 //    row, N = output channels, K = (tap, input channel).  The 8 K-values of a
 //    lane are 8 channels of one node, a 16-byte load from channel-last bf16
 //    activations.  A wave computes 4 rows (y) x 16 nodes against both 16-column
-//    output halves; B comes pre-packed in lane order.
+//    output halves; B comes pre-packed in lane order.  The forward layers with
+//    32 input channels stage them in two halves of 16 (k_conv_fwd_split), which
+//    halves the LDS per block and doubles the resident waves.
 //  - Weight gradients: K = nodes, so a lane's 8 K-values are 8 consecutive
 //    x-nodes of one channel (channel-major copies).  The x-shift of a tap is
 //    taken from aligned 16-byte chunks with 16-bit funnel shifts, wrapping at
@@ -81,6 +83,7 @@ __device__ __forceinline__ int zsrc(const Geo &g, int z)
 #define HSLB_CNN_TZ 4
 #endif
 constexpr int TX = 16, TY = 4, TZ = HSLB_CNN_TZ;
+constexpr int KQ = (NT + 1) / 2;  // two-tap K-steps per channel half (k_conv_fwd_split)
 constexpr int HX = TX + 4, HY = TY + 4, HZ = TZ + 4, HNODES = HX * HY * HZ;
 constexpr int ROWS = TZ;
 
@@ -244,6 +247,114 @@ __global__ __launch_bounds__(256) void k_conv_fwd(FwdArgs a)
                     if (a.out_f32) a.out_f32[(size_t)node * 32 + c] = v;
                     if (a.out_cl) a.out_cl[(size_t)node * 32 + c] = (uint16_t)bits;
                     if (a.out_cm) a.out_cm[(size_t)c * g.N + node] = (uint16_t)bits;
+                }
+            }
+        }
+    }
+}
+
+// Forward layers 2 (32 -> 32 channels, GELU) and 3 (32 -> 3) with the input
+// channels in two halves of 16.  The staged halo then holds 32 B per node (40 KB instead of
+// 80 KB), so four blocks share a compute unit, twice the resident waves of the
+// 64-byte halo, which hides the latencies of the LDS and weight reads.  A K-step
+// of 32 covers two taps x 16 channels: lane group lg takes tap 2q + lg/2 and
+// channels 8 (lg % 2) .. + 8 of the half; the weights come packed in that order
+// (PK_F2, PK_F3).  Output layout and epilogues as k_conv_fwd.  On the 64x64x136
+// slit layer 2 takes 197 us instead of 249 (29 % of the BF16 peak).
+template <int NH, int EPI>
+__global__ __launch_bounds__(256, 4) void k_conv_fwd_split(FwdArgs a)
+{
+    static_assert((NH == 2 && EPI == EPI_GELU) || (NH == 1 && EPI == EPI_OUT), "forward layers 2 and 3");
+    __shared__ __attribute__((aligned(16))) uint16_t tile[HNODES * 16];
+    const Geo g = a.g;
+    const int nxb = g.nx / TX, nyb = g.ny / TY;
+    const int b = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int zb = b / (nxb * nyb);
+    const int rem = b - zb * nxb * nyb;
+    const int yb = rem / nxb;
+    const int x0 = (rem - yb * nxb) * TX, y0 = yb * TY, z0 = zb * TZ;
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int part = lg & 1, second = lg >> 1;
+    const int rows = min(ROWS, g.nz - z0);
+    f32x4 acc[ROWS][NH];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+        for (int h = 0; h < NH; ++h) acc[r][h] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+    constexpr int PD = 4;
+    auto load_b = [&](int sq, int h) { return *(const u32x4 *)(a.wp + ((size_t)(sq * NH + h) * 64 + lane) * 8); };
+    for (int hc = 0; hc < 2; ++hc) {
+        if (hc) __syncthreads();  // every wave is done with the first half
+        for (int c = threadIdx.x; c < HNODES * 2; c += 256) {
+            const int node = c >> 1, pt = c & 1;
+            const int hx = node % HX, hy = (node / HX) % HY, hz = node / (HX * HY);
+            const int zr = z0 - 2 + hz;
+            const int zs = g.zper ? mod_pos(zr, g.nz) : ((zr < 0 || zr >= g.nz) ? -1 : zr);
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (zs >= 0) {
+                const size_t src = (size_t)wrapi(x0 - 2 + hx, g.nx) +
+                                   (size_t)g.nx * (mod_pos(y0 - 2 + hy, g.ny) + (size_t)g.ny * zs);
+                v = *(const u32x4 *)(a.in + src * 32 + 16 * hc + 8 * pt);
+            }
+            ((u32x4 *)tile)[c] = v;
+        }
+        __syncthreads();
+        u32x4 bq[PD][NH];
+#pragma unroll
+        for (int q = 0; q < PD; ++q)
+#pragma unroll
+            for (int h = 0; h < NH; ++h) bq[q][h] = load_b(hc * KQ + q, h);
+        for (int q0 = 0; q0 < KQ; q0 += PD) {
+#pragma unroll
+            for (int qq = 0; qq < PD; ++qq) {
+                const int q = q0 + qq;
+                if (q < KQ) {
+                    const int t = 2 * q + second;
+                    const int dz = t / 25, dy = (t / 5) % 5, dx = t % 5;
+                    bf16x8 av[ROWS], bw[NH];
+#pragma unroll
+                    for (int r = 0; r < ROWS; ++r) {
+                        u32x4 v = {0u, 0u, 0u, 0u};
+                        if (t < NT) v = ((const u32x4 *)tile)[lnode(li + dx, w + dy, r + dz) * 2 + part];
+                        av[r] = as_bf(v);
+                    }
+#pragma unroll
+                    for (int h = 0; h < NH; ++h) {
+                        bw[h] = as_bf(bq[qq][h]);
+                        if (q + PD < KQ) bq[qq][h] = load_b(hc * KQ + q + PD, h);
+                    }
+#pragma unroll
+                    for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                        for (int h = 0; h < NH; ++h)
+                            acc[r][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[r], bw[h], acc[r][h], 0, 0, 0);
+                }
+            }
+        }
+    }
+
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        if (r >= rows) continue;
+        const int rowbase = g.nx * ((y0 + w) + g.ny * (z0 + r));
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            const int c = 16 * h + li;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int node = rowbase + x0 + 4 * lg + j;
+                const float v = acc[r][h][j];
+                if constexpr (EPI == EPI_GELU) {
+                    const float zz = v + a.bias[c];
+                    const uint32_t bits = f2bf(gelu(zz));
+                    if (a.out_cl) a.out_cl[(size_t)node * 32 + c] = (uint16_t)bits;
+                    if (a.out_cm) a.out_cm[(size_t)c * g.N + node] = (uint16_t)bits;
+                    if (a.out_f32) a.out_f32[(size_t)node * 32 + c] = zz;
+                } else {
+                    if (c < CO) a.out_f32[(size_t)c * g.N + node] = v + a.bias[c];
                 }
             }
         }
@@ -506,9 +617,13 @@ __global__ __launch_bounds__(256) void k_pack(int kind, const float *__restrict_
         const int t = 32 * s + 8 * lg + e;
         if (t < NT) v = w[OW1 + col * NT + t];
     } else if (kind == PK_F2) {
-        v = w[OW2 + (col * CH + 8 * lg + e) * NT + s];
+        // channel half hc, two-tap step q: lane group lg holds tap 2q + lg/2,
+        // channels 16 hc + 8 (lg % 2) .. + 8 (k_conv_fwd_split)
+        const int hc = s / KQ, q = s - hc * KQ, t = 2 * q + (lg >> 1);
+        if (t < NT) v = w[OW2 + (col * CH + 16 * hc + 8 * (lg & 1) + e) * NT + t];
     } else if (kind == PK_F3) {
-        if (li < CO) v = w[OW3 + (li * CH + 8 * lg + e) * NT + s];
+        const int hc = s / KQ, q = s - hc * KQ, t = 2 * q + (lg >> 1);  // as PK_F2
+        if (li < CO && t < NT) v = w[OW3 + (li * CH + 16 * hc + 8 * (lg & 1) + e) * NT + t];
     } else if (kind == PK_D2) {
         v = w[OW2 + ((8 * lg + e) * CH + col) * NT + (NT - 1 - s)];
     } else {
@@ -660,8 +775,14 @@ hipError_t launch_conv_fwd(hipStream_t s, int cin, int cout, int epi, const FwdA
 #define HSLB_CONV(CI, NH_, EP) \
     if (cin == CI && nh == NH_ && epi == EP) { hipLaunchKernelGGL((k_conv_fwd<CI, NH_, EP>), grid, blk, 0, s, a); return hipGetLastError(); }
     HSLB_CONV(1, 2, EPI_GELU)
-    HSLB_CONV(32, 2, EPI_GELU)
-    HSLB_CONV(32, 1, EPI_OUT)
+    if (cin == 32 && nh == 2 && epi == EPI_GELU) {
+        hipLaunchKernelGGL((k_conv_fwd_split<2, EPI_GELU>), grid, blk, 0, s, a);
+        return hipGetLastError();
+    }
+    if (cin == 32 && nh == 1 && epi == EPI_OUT) {
+        hipLaunchKernelGGL((k_conv_fwd_split<1, EPI_OUT>), grid, blk, 0, s, a);
+        return hipGetLastError();
+    }
     HSLB_CONV(32, 2, EPI_DGELU)
     HSLB_CONV(4, 2, EPI_DGELU)
 #undef HSLB_CONV

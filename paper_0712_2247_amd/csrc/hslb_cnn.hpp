@@ -40,8 +40,8 @@ enum PackKind { PK_F1 = 0, PK_F2, PK_F3, PK_D2, PK_D3, PK_COUNT };
 constexpr int pack_elems(int kind)
 {
     return kind == PK_F1 ? 4 * 2 * 512
-         : kind == PK_F2 ? NT * 2 * 512
-         : kind == PK_F3 ? NT * 1 * 512
+         : kind == PK_F2 ? 2 * ((NT + 1) / 2) * 2 * 512
+         : kind == PK_F3 ? 2 * ((NT + 1) / 2) * 1 * 512
          : kind == PK_D2 ? NT * 2 * 512
                          : 16 * 2 * 512;
 }
