@@ -260,7 +260,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(FwdArgs a)
 // of 32 covers two taps x 16 channels: lane group lg takes tap 2q + lg/2 and
 // channels 8 (lg % 2) .. + 8 of the half; the weights come packed in that order
 // (PK_F2, PK_F3).  Output layout and epilogues as k_conv_fwd.  On the 64x64x136
-// slit layer 2 takes 197 us instead of 249 (29 % of the BF16 peak).
+// slit layer 2 takes 193 us instead of 249 (30 % of the BF16 peak).
 template <int NH, int EPI>
 __global__ __launch_bounds__(256, 4) void k_conv_fwd_split(FwdArgs a)
 {
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(256, 4) void k_conv_fwd_split(FwdArgs a)
                                    (size_t)g.nx * (mod_pos(y0 - 2 + hy, g.ny) + (size_t)g.ny * zs);
                 v = *(const u32x4 *)(a.in + src * 32 + 16 * hc + 8 * pt);
             }
-            ((u32x4 *)tile)[c] = v;
+            ((u32x4 *)tile)[pt * HNODES + node] = v;  // planar by 16-byte part: no bank conflicts
         }
         __syncthreads();
         u32x4 bq[PD][NH];
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(256, 4) void k_conv_fwd_split(FwdArgs a)
 #pragma unroll
                     for (int r = 0; r < ROWS; ++r) {
                         u32x4 v = {0u, 0u, 0u, 0u};
-                        if (t < NT) v = ((const u32x4 *)tile)[lnode(li + dx, w + dy, r + dz) * 2 + part];
+                        if (t < NT) v = ((const u32x4 *)tile)[part * HNODES + lnode(li + dx, w + dy, r + dz)];
                         av[r] = as_bf(v);
                     }
 #pragma unroll
