@@ -492,3 +492,46 @@ def test_snapshot_from_a_lattice_against_oracle(precision):
     _, out = tr.eval(k, want_out=True)
     ref = cnn.forward(w.astype(np.float64), cnn.eta_field(m, wl.sigma), zper=False)["out"]
     assert rel(out, ref) <= 1e-3   # bf16 near-tie flips, as in the trainer test
+
+
+def test_surrogate_train_error_paths(tmp_path):
+    """hslb_surrogate_train rejects, with HSLB_EINVAL and a message naming the
+    cause, a missing directory, a directory without snapshot files, a file
+    that is not a snapshot or is cut short, and bad epochs or learning rates;
+    a context without network weights gives HSLB_ENOSURR.  A rejected call
+    leaves the context's weights as they were."""
+    wl = workloads.slit("snaperr-32x8x20", 32, 8, 16, 4, 0.2, 1.0, 1e-5, 10, "f64", 1032, 0.02)
+    plain = hslb.Sim.from_workload(wl)
+    n, u = wl.fields()
+    plain.init(n, u)
+    good = tmp_path / "good"
+    good.mkdir()
+    hslb.hslb_surrogate_save_snapshot(plain.ctx, str(good / "a.hsnap"))
+    s = hslb.Sim(wl.nx, wl.ny, wl.nz, wl.sigma, wl.tau, accel=wl.accel, wall_lo=wl.wall_lo, wall_hi=wl.wall_hi,
+                 precision="f64", force_mode=hslb.HSLB_FORCE_SURROGATE)
+    with pytest.raises(hslb.HslbError) as ei:
+        hslb.hslb_surrogate_train(s.ctx, str(good), 1, 1e-3)
+    assert ei.value.code == hslb.HSLB_ENOSURR
+    w0 = weights(33, out_scale=1e-2)
+    hslb.hslb_surrogate_set_weights(s.ctx, w0)
+    empty = tmp_path / "empty"
+    empty.mkdir()
+    (empty / "notes.txt").write_text("no snapshots here")
+    bad = tmp_path / "bad"
+    bad.mkdir()
+    (bad / "x.hsnap").write_bytes(b"NOTASNAP" + bytes(64))
+    short = tmp_path / "short"
+    short.mkdir()
+    raw = (good / "a.hsnap").read_bytes()
+    (short / "a.hsnap").write_bytes(raw[: len(raw) // 2])
+    cases = [(str(tmp_path / "missing"), 1, 1e-3, "cannot open directory"), (str(empty), 1, 1e-3, "no *.hsnap"),
+             (str(bad), 1, 1e-3, ""), (str(short), 1, 1e-3, ""), (str(good), 0, 1e-3, "epochs"),
+             (str(good), 1, 0.0, "learning rate"), (str(good), 1, float("nan"), "learning rate")]
+    for d, ep, lr, msg in cases:
+        with pytest.raises(hslb.HslbError) as ei:
+            hslb.hslb_surrogate_train(s.ctx, d, ep, lr)
+        assert ei.value.code == hslb.HSLB_EINVAL, (d, ep, lr)
+        assert msg in str(ei.value), (d, str(ei.value))
+        assert np.array_equal(hslb.hslb_surrogate_get_weights(s.ctx), np.asarray(w0, dtype=np.float32))
+    L = hslb.hslb_surrogate_train(s.ctx, str(good), 1, 1e-3)
+    assert np.isfinite(L)
