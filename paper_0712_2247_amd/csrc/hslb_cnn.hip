@@ -146,6 +146,55 @@ __device__ __forceinline__ u32x4 lds_a(const uint16_t *tile, int s, int li, int 
     return v;
 }
 
+// GELU epilogue of a forward layer with 32 output channels: lane (li, lg)
+// holds acc[r][h][j] of node (x0 + 4 lg + j, y0 + w, z0 + r), channel 16 h + li.
+// The activations go through LDS, so that the channel-last copy leaves as
+// whole 16-byte node parts and the channel-major copy as runs of consecutive
+// nodes, instead of one scattered 2-byte store per value.  `ot` holds
+// TX * TY * TZ * 32 bf16 (16 KB) of LDS that no wave reads any more; tile-local
+// node l = (r TY + y) TX + x.
+__device__ __forceinline__ void gelu_epilogue(const FwdArgs &a, const Geo &g, uint16_t *ot, const f32x4 (&acc)[ROWS][2],
+                                              int x0, int y0, int z0, int rows, int w, int li, int lg)
+{
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int rowbase = g.nx * ((y0 + w) + g.ny * (z0 + r));
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int c = 16 * h + li;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float zz = acc[r][h][j] + a.bias[c];
+                ot[((r * TY + w) * TX + 4 * lg + j) * 32 + c] = (uint16_t)f2bf(gelu(zz));
+                if (a.out_f32 && r < rows) a.out_f32[(size_t)(rowbase + x0 + 4 * lg + j) * 32 + c] = zz;
+            }
+        }
+    }
+    __syncthreads();
+    constexpr int TN = TX * TY * TZ;
+    if (a.out_cl) {
+        for (int q = threadIdx.x; q < TN * 4; q += 256) {
+            const int l = q >> 2, pt = q & 3;
+            const int x = l % TX, y = (l / TX) % TY, r = l / (TX * TY);
+            if (r < rows) {
+                const size_t node = (size_t)(x0 + x) + (size_t)g.nx * ((y0 + y) + (size_t)g.ny * (z0 + r));
+                *(u32x4 *)(a.out_cl + node * 32 + 8 * pt) = *(const u32x4 *)(ot + l * 32 + 8 * pt);
+            }
+        }
+    }
+    if (a.out_cm) {
+        for (int q = threadIdx.x; q < TN * 32; q += 256) {
+            const int c = q / TN, l = q - c * TN;
+            const int x = l % TX, y = (l / TX) % TY, r = l / (TX * TY);
+            if (r < rows) {
+                const size_t node = (size_t)(x0 + x) + (size_t)g.nx * ((y0 + y) + (size_t)g.ny * (z0 + r));
+                a.out_cm[(size_t)c * g.N + node] = ot[l * 32 + c];
+            }
+        }
+    }
+}
+
 template <int CIN, int NH, int EPI>
 __global__ __launch_bounds__(256) void k_conv_fwd(FwdArgs a)
 {
@@ -223,6 +272,12 @@ __global__ __launch_bounds__(256) void k_conv_fwd(FwdArgs a)
         }
     }
 
+    if constexpr (EPI == EPI_GELU) {
+        static_assert(NH == 2, "GELU layers have 32 outputs");
+        __shared__ __attribute__((aligned(16))) uint16_t ot[TX * TY * TZ * 32];
+        gelu_epilogue(a, g, ot, acc, x0, y0, z0, rows, w, li, lg);
+        return;
+    }
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
         if (r >= rows) continue;
@@ -234,13 +289,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(FwdArgs a)
             for (int j = 0; j < 4; ++j) {
                 const int node = rowbase + x0 + 4 * lg + j;
                 const float v = acc[r][h][j];
-                if constexpr (EPI == EPI_GELU) {
-                    const float zz = v + a.bias[c];
-                    const uint32_t bits = f2bf(gelu(zz));
-                    if (a.out_cl) a.out_cl[(size_t)node * 32 + c] = (uint16_t)bits;
-                    if (a.out_cm) a.out_cm[(size_t)c * g.N + node] = (uint16_t)bits;
-                    if (a.out_f32) a.out_f32[(size_t)node * 32 + c] = zz;
-                } else if constexpr (EPI == EPI_OUT) {
+                if constexpr (EPI == EPI_OUT) {
                     if (c < CO) a.out_f32[(size_t)c * g.N + node] = v + a.bias[c];
                 } else {
                     const uint32_t bits = f2bf(v * gelu_grad(a.zsave[(size_t)node * 32 + c]));
@@ -337,49 +386,8 @@ __global__ __launch_bounds__(256, 4) void k_conv_fwd_split(FwdArgs a)
     }
 
     if constexpr (EPI == EPI_GELU) {
-        // The activations go through LDS (the halo is no longer needed), so that
-        // the channel-last copy leaves as whole 16-byte node parts and the
-        // channel-major copy as runs of consecutive nodes, instead of one scattered
-        // 2-byte store per value.  Tile-local node l = (r TY + y) TX + x.
-        __syncthreads();
         static_assert(TX * TY * TZ * 32 <= HNODES * 16, "the block's activations fit the halo buffer");
-        uint16_t *ot = tile;  // [TX * TY * TZ][32] bf16, 16 KB of the 40 KB halo
-#pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
-            const int rowbase = g.nx * ((y0 + w) + g.ny * (z0 + r));
-#pragma unroll
-            for (int h = 0; h < NH; ++h) {
-                const int c = 16 * h + li;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float zz = acc[r][h][j] + a.bias[c];
-                    ot[((r * TY + w) * TX + 4 * lg + j) * 32 + c] = (uint16_t)f2bf(gelu(zz));
-                    if (a.out_f32 && r < rows) a.out_f32[(size_t)(rowbase + x0 + 4 * lg + j) * 32 + c] = zz;
-                }
-            }
-        }
-        __syncthreads();
-        constexpr int TN = TX * TY * TZ;
-        if (a.out_cl) {
-            for (int q = threadIdx.x; q < TN * 4; q += 256) {
-                const int l = q >> 2, pt = q & 3;
-                const int x = l % TX, y = (l / TX) % TY, r = l / (TX * TY);
-                if (r < rows) {
-                    const size_t node = (size_t)(x0 + x) + (size_t)g.nx * ((y0 + y) + (size_t)g.ny * (z0 + r));
-                    *(u32x4 *)(a.out_cl + node * 32 + 8 * pt) = *(const u32x4 *)(ot + l * 32 + 8 * pt);
-                }
-            }
-        }
-        if (a.out_cm) {
-            for (int q = threadIdx.x; q < TN * 32; q += 256) {
-                const int c = q / TN, l = q - c * TN;
-                const int x = l % TX, y = (l / TX) % TY, r = l / (TX * TY);
-                if (r < rows) {
-                    const size_t node = (size_t)(x0 + x) + (size_t)g.nx * ((y0 + y) + (size_t)g.ny * (z0 + r));
-                    a.out_cm[(size_t)c * g.N + node] = ot[l * 32 + c];
-                }
-            }
-        }
+        gelu_epilogue(a, g, tile, acc, x0, y0, z0, rows, w, li, lg);
     } else {
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
