@@ -302,18 +302,20 @@ __global__ __launch_bounds__(256) void k_conv_fwd(FwdArgs a)
     }
 }
 
-// Forward layers 2 (32 -> 32 channels, GELU) and 3 (32 -> 3) with the input
+// Forward layers 2 (32 -> 32 channels, GELU) and 3 (32 -> 3), and the input
+// gradient of layer 2 (transposed weights, GELU' epilogue), with the input
 // channels in two halves of 16.  The staged halo then holds 32 B per node (40 KB instead of
 // 80 KB), so four blocks share a compute unit, twice the resident waves of the
 // 64-byte halo, which hides the latencies of the LDS and weight reads.  A K-step
 // of 32 covers two taps x 16 channels: lane group lg takes tap 2q + lg/2 and
 // channels 8 (lg % 2) .. + 8 of the half; the weights come packed in that order
-// (PK_F2, PK_F3).  Output layout and epilogues as k_conv_fwd.  On the 64x64x136
+// (PK_F2, PK_F3, PK_D2).  Output layout and epilogues as k_conv_fwd.  On the 64x64x136
 // slit layer 2 takes 193 us instead of 249 (30 % of the BF16 peak).
 template <int NH, int EPI>
 __global__ __launch_bounds__(256, 4) void k_conv_fwd_split(FwdArgs a)
 {
-    static_assert((NH == 2 && EPI == EPI_GELU) || (NH == 1 && EPI == EPI_OUT), "forward layers 2 and 3");
+    static_assert((NH == 2 && (EPI == EPI_GELU || EPI == EPI_DGELU)) || (NH == 1 && EPI == EPI_OUT),
+                  "layers 2 and 3 forward, layer 2 input gradient");
     __shared__ __attribute__((aligned(16))) uint16_t tile[HNODES * 16];
     const Geo g = a.g;
     const int nxb = g.nx / TX, nyb = g.ny / TY;
@@ -397,8 +399,18 @@ __global__ __launch_bounds__(256, 4) void k_conv_fwd_split(FwdArgs a)
             for (int h = 0; h < NH; ++h) {
                 const int c = 16 * h + li;
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (c < CO) a.out_f32[(size_t)c * g.N + rowbase + x0 + 4 * lg + j] = acc[r][h][j] + a.bias[c];
+                for (int j = 0; j < 4; ++j) {
+                    const int node = rowbase + x0 + 4 * lg + j;
+                    const float v = acc[r][h][j];
+                    if constexpr (EPI == EPI_OUT) {
+                        if (c < CO) a.out_f32[(size_t)c * g.N + node] = v + a.bias[c];
+                    } else {
+                        const uint32_t bits = f2bf(v * gelu_grad(a.zsave[(size_t)node * 32 + c]));
+                        if (a.out_f32) a.out_f32[(size_t)node * 32 + c] = v;
+                        if (a.out_cl) a.out_cl[(size_t)node * 32 + c] = (uint16_t)bits;
+                        if (a.out_cm) a.out_cm[(size_t)c * g.N + node] = (uint16_t)bits;
+                    }
+                }
             }
         }
     }
@@ -668,7 +680,9 @@ __global__ __launch_bounds__(256) void k_pack(int kind, const float *__restrict_
         const int hc = s / KQ, q = s - hc * KQ, t = 2 * q + (lg >> 1);  // as PK_F2
         if (li < CO && t < NT) v = w[OW3 + (li * CH + 16 * hc + 8 * (lg & 1) + e) * NT + t];
     } else if (kind == PK_D2) {
-        v = w[OW2 + ((8 * lg + e) * CH + col) * NT + (NT - 1 - s)];
+        // transposed, tap-flipped layer-2 weights in the split order of PK_F2
+        const int hc = s / KQ, q = s - hc * KQ, t = 2 * q + (lg >> 1);
+        if (t < NT) v = w[OW2 + ((16 * hc + 8 * (lg & 1) + e) * CH + col) * NT + (NT - 1 - t)];
     } else {
         const int t = 8 * s + 2 * lg + (e >> 2), cf = e & 3;
         if (t < NT && cf < CO) v = w[OW3 + (cf * CH + col) * NT + (NT - 1 - t)];
@@ -822,11 +836,14 @@ hipError_t launch_conv_fwd(hipStream_t s, int cin, int cout, int epi, const FwdA
         hipLaunchKernelGGL((k_conv_fwd_split<2, EPI_GELU>), grid, blk, 0, s, a);
         return hipGetLastError();
     }
+    if (cin == 32 && nh == 2 && epi == EPI_DGELU) {
+        hipLaunchKernelGGL((k_conv_fwd_split<2, EPI_DGELU>), grid, blk, 0, s, a);
+        return hipGetLastError();
+    }
     if (cin == 32 && nh == 1 && epi == EPI_OUT) {
         hipLaunchKernelGGL((k_conv_fwd_split<1, EPI_OUT>), grid, blk, 0, s, a);
         return hipGetLastError();
     }
-    HSLB_CONV(32, 2, EPI_DGELU)
     HSLB_CONV(4, 2, EPI_DGELU)
 #undef HSLB_CONV
     return hipErrorInvalidValue;

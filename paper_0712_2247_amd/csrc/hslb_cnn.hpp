@@ -42,7 +42,7 @@ constexpr int pack_elems(int kind)
     return kind == PK_F1 ? 4 * 2 * 512
          : kind == PK_F2 ? 2 * ((NT + 1) / 2) * 2 * 512
          : kind == PK_F3 ? 2 * ((NT + 1) / 2) * 1 * 512
-         : kind == PK_D2 ? NT * 2 * 512
+         : kind == PK_D2 ? 2 * ((NT + 1) / 2) * 2 * 512
                          : 16 * 2 * 512;
 }
 
