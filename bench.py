@@ -132,11 +132,18 @@ def ensemble_throughput(hslb, workloads, steps: int):
     choice, us = b.autotune(steps=10)
     dt = _timed(b, 20, steps)
     fin = int(b.finite().sum())
+    kt = _kernel_pass(hslb, b, 20)   # eager, HIP events per launch
+    kus = {k: round(v[0] / v[1] * 1e3, 2) for k, v in kt.items()}
+    avg_s = kt["b_collide"][0] / kt["b_collide"][1] * 1e-3
+    ach = STEP_BYTES * b.fluid_nodes / avg_s / 1e9
     out = {"workload": f"{len(wls)} slits 16x16x(H+walls), H 10..60, sigma 3..8, packing 0.10..0.40",
            "fluid_nodes": b.fluid_nodes, "steps": steps,
            "value": round(b.fluid_nodes * steps / dt / 1e6, 1), "unit": "MLUPS",
            "ms_per_step": round(dt / steps * 1e3, 5),
-           "autotune_choice": int(choice), "finite_slits": fin}
+           "autotune_choice": int(choice), "finite_slits": fin, "kernels_us": kus,
+           "roofline_kb_collide": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                                   "frac": round(ach / PEAK_HBM_GBPS, 4), "bytes_per_node": STEP_BYTES,
+                                   "avg_launch_us": round(avg_s * 1e6, 2)}}
     b.close()
     return out
 
