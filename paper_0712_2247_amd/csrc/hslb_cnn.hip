@@ -87,9 +87,30 @@ constexpr int KQ = (NT + 1) / 2;  // two-tap K-steps per channel half (k_conv_fw
 constexpr int HX = TX + 4, HY = TY + 4, HZ = TZ + 4, HNODES = HX * HY * HZ;
 constexpr int ROWS = TZ;
 
-__device__ __forceinline__ int lnode(int hx, int hy, int hz) { return (hz * HY + hy) * HX + hx; }
+__host__ __device__ __forceinline__ constexpr int lnode(int hx, int hy, int hz) { return (hz * HY + hy) * HX + hx; }
 
-__device__ __forceinline__ int mod_pos(int v, int n) { return ((v % n) + n) % n; }
+// LDS byte offsets (16-byte parts) of the taps t = 0 .. 2 KQ - 1 of the
+// split-channel convolution relative to the output node, read by a block as
+// scalar loads; the pad tap t = NT reads the node itself (its weights are 0).
+struct TapOffsets {
+    uint32_t v[2 * KQ];
+};
+constexpr TapOffsets make_tap_offsets()
+{
+    TapOffsets o{};
+    for (int t = 0; t < 2 * KQ; ++t) o.v[t] = t < NT ? (uint32_t)lnode(t % 5, (t / 5) % 5, t / 25) * 16u : 0u;
+    return o;
+}
+__constant__ TapOffsets c_tap_offsets = make_tap_offsets();
+
+// v mod n in [0, n) for v within a few periods of the range (halo indices of
+// small lattices): adds and subtracts instead of two integer divisions.
+__device__ __forceinline__ int mod_pos(int v, int n)
+{
+    while (v < 0) v += n;
+    while (v >= n) v -= n;
+    return v;
+}
 
 template <int CIN>
 __device__ __forceinline__ void stage_tile(const Geo &g, const uint16_t *__restrict__ in, uint16_t *tile, int x0,
@@ -309,8 +330,12 @@ __global__ __launch_bounds__(256) void k_conv_fwd(FwdArgs a)
 // 64-byte halo, which hides the latencies of the LDS and weight reads.  A K-step
 // of 32 covers two taps x 16 channels: lane group lg takes tap 2q + lg/2 and
 // channels 8 (lg % 2) .. + 8 of the half; the weights come packed in that order
-// (PK_F2, PK_F3, PK_D2).  Output layout and epilogues as k_conv_fwd.  On the 64x64x136
-// slit layer 2 takes 193 us instead of 249 (30 % of the BF16 peak).
+// (PK_F2, PK_F3, PK_D2).  Output layout and epilogues as k_conv_fwd.  The K-loop
+// carries no branch and no per-lane index arithmetic: the tap offsets come
+// from a constant table and the B ring runs on over the zero-padded end of the
+// pack.  On the 64x64x136 slit layer 2 takes 155 us (37 % of the BF16 peak;
+// 188 us with per-lane tap division and guarded loads, 249 us with the 64-byte
+// halo).
 template <int NH, int EPI>
 __global__ __launch_bounds__(256, 4) void k_conv_fwd_split(FwdArgs a)
 {
@@ -335,8 +360,20 @@ __global__ __launch_bounds__(256, 4) void k_conv_fwd_split(FwdArgs a)
 #pragma unroll
         for (int h = 0; h < NH; ++h) acc[r][h] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-    constexpr int PD = 4;
+    // B operands: a ring of PD K-steps loaded ahead, over the steps of both
+    // channel halves in a row (the packs end in PACK_PAD zero steps).
+    constexpr int PD = 3;
+    static_assert(KQ % PD == 0 && PD <= PACK_PAD, "the prefetch ring runs on across the halves");
     auto load_b = [&](int sq, int h) { return *(const u32x4 *)(a.wp + ((size_t)(sq * NH + h) * 64 + lane) * 8); };
+    u32x4 bq[PD][NH];
+#pragma unroll
+    for (int q = 0; q < PD; ++q)
+#pragma unroll
+        for (int h = 0; h < NH; ++h) bq[q][h] = load_b(q, h);
+    // A operands: the LDS byte offset of a lane's node (x0 + li, y0 + w, z0)
+    // of its 16-byte part, plus the offset of its tap of the pair.
+    const uint32_t lane_base = (uint32_t)(part * HNODES + lnode(li, w, 0)) * 16u;
+    constexpr uint32_t ROW_BYTES = HX * HY * 16;
     for (int hc = 0; hc < 2; ++hc) {
         if (hc) __syncthreads();  // every wave is done with the first half
         for (int c = threadIdx.x; c < HNODES * 2; c += 256) {
@@ -353,36 +390,26 @@ __global__ __launch_bounds__(256, 4) void k_conv_fwd_split(FwdArgs a)
             ((u32x4 *)tile)[pt * HNODES + node] = v;  // planar by 16-byte part: no bank conflicts
         }
         __syncthreads();
-        u32x4 bq[PD][NH];
-#pragma unroll
-        for (int q = 0; q < PD; ++q)
-#pragma unroll
-            for (int h = 0; h < NH; ++h) bq[q][h] = load_b(hc * KQ + q, h);
+#pragma unroll 1
         for (int q0 = 0; q0 < KQ; q0 += PD) {
 #pragma unroll
             for (int qq = 0; qq < PD; ++qq) {
                 const int q = q0 + qq;
-                if (q < KQ) {
-                    const int t = 2 * q + second;
-                    const int dz = t / 25, dy = (t / 5) % 5, dx = t % 5;
-                    bf16x8 av[ROWS], bw[NH];
+                const uint32_t off = lane_base + (second ? c_tap_offsets.v[2 * q + 1] : c_tap_offsets.v[2 * q]);
+                bf16x8 av[ROWS], bw[NH];
 #pragma unroll
-                    for (int r = 0; r < ROWS; ++r) {
-                        u32x4 v = {0u, 0u, 0u, 0u};
-                        if (t < NT) v = ((const u32x4 *)tile)[part * HNODES + lnode(li + dx, w + dy, r + dz)];
-                        av[r] = as_bf(v);
-                    }
+                for (int r = 0; r < ROWS; ++r)
+                    av[r] = as_bf(*(const u32x4 *)((const char *)tile + off + r * ROW_BYTES));
 #pragma unroll
-                    for (int h = 0; h < NH; ++h) {
-                        bw[h] = as_bf(bq[qq][h]);
-                        if (q + PD < KQ) bq[qq][h] = load_b(hc * KQ + q + PD, h);
-                    }
-#pragma unroll
-                    for (int r = 0; r < ROWS; ++r)
-#pragma unroll
-                        for (int h = 0; h < NH; ++h)
-                            acc[r][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[r], bw[h], acc[r][h], 0, 0, 0);
+                for (int h = 0; h < NH; ++h) {
+                    bw[h] = as_bf(bq[qq][h]);
+                    bq[qq][h] = load_b(hc * KQ + q + PD, h);
                 }
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                    for (int h = 0; h < NH; ++h)
+                        acc[r][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[r], bw[h], acc[r][h], 0, 0, 0);
             }
         }
     }
@@ -673,16 +700,17 @@ __global__ __launch_bounds__(256) void k_pack(int kind, const float *__restrict_
         if (t < NT) v = w[OW1 + col * NT + t];
     } else if (kind == PK_F2) {
         // channel half hc, two-tap step q: lane group lg holds tap 2q + lg/2,
-        // channels 16 hc + 8 (lg % 2) .. + 8 (k_conv_fwd_split)
+        // channels 16 hc + 8 (lg % 2) .. + 8 (k_conv_fwd_split); zero padding
+        // steps after the second half
         const int hc = s / KQ, q = s - hc * KQ, t = 2 * q + (lg >> 1);
-        if (t < NT) v = w[OW2 + (col * CH + 16 * hc + 8 * (lg & 1) + e) * NT + t];
+        if (hc < 2 && t < NT) v = w[OW2 + (col * CH + 16 * hc + 8 * (lg & 1) + e) * NT + t];
     } else if (kind == PK_F3) {
         const int hc = s / KQ, q = s - hc * KQ, t = 2 * q + (lg >> 1);  // as PK_F2
-        if (li < CO && t < NT) v = w[OW3 + (li * CH + 16 * hc + 8 * (lg & 1) + e) * NT + t];
+        if (hc < 2 && li < CO && t < NT) v = w[OW3 + (li * CH + 16 * hc + 8 * (lg & 1) + e) * NT + t];
     } else if (kind == PK_D2) {
         // transposed, tap-flipped layer-2 weights in the split order of PK_F2
         const int hc = s / KQ, q = s - hc * KQ, t = 2 * q + (lg >> 1);
-        if (t < NT) v = w[OW2 + ((16 * hc + 8 * (lg & 1) + e) * CH + col) * NT + (NT - 1 - t)];
+        if (hc < 2 && t < NT) v = w[OW2 + ((16 * hc + 8 * (lg & 1) + e) * CH + col) * NT + (NT - 1 - t)];
     } else {
         const int t = 8 * s + 2 * lg + (e >> 2), cf = e & 3;
         if (t < NT && cf < CO) v = w[OW3 + (cf * CH + col) * NT + (NT - 1 - t)];

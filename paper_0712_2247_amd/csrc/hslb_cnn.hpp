@@ -36,13 +36,16 @@ struct Geo {
 
 // Packed MFMA B operands (bf16 bits), [ksteps][halves][64 lanes][8]:
 // forward layers 1-3 and the input-gradient convolutions of layers 2 and 3.
+// The split-channel packs (PK_F2, PK_F3, PK_D2) end in PACK_PAD zero K-steps,
+// so that their kernel's prefetch runs past the last step without a branch.
 enum PackKind { PK_F1 = 0, PK_F2, PK_F3, PK_D2, PK_D3, PK_COUNT };
+constexpr int PACK_PAD = 4;
 constexpr int pack_elems(int kind)
 {
     return kind == PK_F1 ? 4 * 2 * 512
-         : kind == PK_F2 ? 2 * ((NT + 1) / 2) * 2 * 512
-         : kind == PK_F3 ? 2 * ((NT + 1) / 2) * 1 * 512
-         : kind == PK_D2 ? 2 * ((NT + 1) / 2) * 2 * 512
+         : kind == PK_F2 ? (2 * ((NT + 1) / 2) + PACK_PAD) * 2 * 512
+         : kind == PK_F3 ? (2 * ((NT + 1) / 2) + PACK_PAD) * 1 * 512
+         : kind == PK_D2 ? (2 * ((NT + 1) / 2) + PACK_PAD) * 2 * 512
                          : 16 * 2 * 512;
 }
 
