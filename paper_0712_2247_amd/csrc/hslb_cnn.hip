@@ -87,22 +87,6 @@ constexpr int KQ = (NT + 1) / 2;  // two-tap K-steps per channel half (k_conv_fw
 constexpr int HX = TX + 4, HY = TY + 4, HZ = TZ + 4, HNODES = HX * HY * HZ;
 constexpr int ROWS = TZ;
 
-__host__ __device__ __forceinline__ constexpr int lnode(int hx, int hy, int hz) { return (hz * HY + hy) * HX + hx; }
-
-// LDS byte offsets (16-byte parts) of the taps t = 0 .. 2 KQ - 1 of the
-// split-channel convolution relative to the output node, read by a block as
-// scalar loads; the pad tap t = NT reads the node itself (its weights are 0).
-struct TapOffsets {
-    uint32_t v[2 * KQ];
-};
-constexpr TapOffsets make_tap_offsets()
-{
-    TapOffsets o{};
-    for (int t = 0; t < 2 * KQ; ++t) o.v[t] = t < NT ? (uint32_t)lnode(t % 5, (t / 5) % 5, t / 25) * 16u : 0u;
-    return o;
-}
-__constant__ TapOffsets c_tap_offsets = make_tap_offsets();
-
 // v mod n in [0, n) for v within a few periods of the range (halo indices of
 // small lattices): adds and subtracts instead of two integer divisions.
 __device__ __forceinline__ int mod_pos(int v, int n)
@@ -111,6 +95,52 @@ __device__ __forceinline__ int mod_pos(int v, int n)
     while (v >= n) v -= n;
     return v;
 }
+
+__host__ __device__ __forceinline__ constexpr int lnode(int hx, int hy, int hz) { return (hz * HY + hy) * HX + hx; }
+
+// LDS byte offsets of the tap pairs of the split-channel convolution relative
+// to the output node (16-byte parts): v[2q] is the offset of tap 2q, v[2q + 1]
+// that of tap 2q + 1 minus it.  A block reads them as scalar loads; the pad
+// tap t = NT reads the node itself (its weights are 0).
+struct TapOffsets {
+    uint32_t v[2 * KQ];
+};
+constexpr uint32_t tap_lds_offset(int t) { return t < NT ? (uint32_t)lnode(t % 5, (t / 5) % 5, t / 25) * 16u : 0u; }
+constexpr TapOffsets make_tap_offsets()
+{
+    TapOffsets o{};
+    for (int q = 0; q < KQ; ++q) {
+        o.v[2 * q] = tap_lds_offset(2 * q);
+        o.v[2 * q + 1] = tap_lds_offset(2 * q + 1) - tap_lds_offset(2 * q);
+    }
+    return o;
+}
+__constant__ TapOffsets c_tap_offsets = make_tap_offsets();
+
+// Stages channel half hc (16 channels, two 16-byte parts per node, stored
+// planar by part) of the block's input halo.  Wave w copies the halo rows
+// (hz, hy) = w, w + 4, ...: their source y and z are uniform, and lanes
+// 0 .. 2 HX - 1 take the row's HX nodes x 2 parts.
+__device__ __forceinline__ void stage_half(const Geo &g, const uint16_t *__restrict__ in, uint16_t *tile, int x0,
+                                           int y0, int z0, int hc, int lane)
+{
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int hx = lane >> 1, pt = lane & 1;
+    const bool act = lane < 2 * HX;
+    const size_t col = (size_t)(act ? wrapi(x0 - 2 + hx, g.nx) : 0) * 32 + 16 * hc + 8 * pt;
+    for (int row = w; row < HY * HZ; row += 4) {
+        const int hy = row % HY, hz = row / HY;
+        const int zr = z0 - 2 + hz;
+        const int zs = g.zper ? mod_pos(zr, g.nz) : ((zr < 0 || zr >= g.nz) ? -1 : zr);
+        const size_t rbase = (size_t)g.nx * (mod_pos(y0 - 2 + hy, g.ny) + (size_t)g.ny * (zs < 0 ? 0 : zs)) * 32;
+        if (act) {
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (zs >= 0) v = *(const u32x4 *)(in + rbase + col);
+            ((u32x4 *)tile)[pt * HNODES + row * HX + hx] = v;
+        }
+    }
+}
+
 
 template <int CIN>
 __device__ __forceinline__ void stage_tile(const Geo &g, const uint16_t *__restrict__ in, uint16_t *tile, int x0,
@@ -332,10 +362,11 @@ __global__ __launch_bounds__(256) void k_conv_fwd(FwdArgs a)
 // channels 8 (lg % 2) .. + 8 of the half; the weights come packed in that order
 // (PK_F2, PK_F3, PK_D2).  Output layout and epilogues as k_conv_fwd.  The K-loop
 // carries no branch and no per-lane index arithmetic: the tap offsets come
-// from a constant table and the B ring runs on over the zero-padded end of the
-// pack.  On the 64x64x136 slit layer 2 takes 155 us (37 % of the BF16 peak;
-// 188 us with per-lane tap division and guarded loads, 249 us with the 64-byte
-// halo).
+// from a constant table through scalar loads, the B ring runs on over the
+// zero-padded end of the pack, and a ring slot is refilled after its products
+// are issued (no register copies, no wait on a load just issued).  On the
+// 64x64x136 slit layer 2 takes 141 us (40 % of the BF16 peak; 188 us with
+// per-lane tap division and guarded loads, 249 us with the 64-byte halo).
 template <int NH, int EPI>
 __global__ __launch_bounds__(256, 4) void k_conv_fwd_split(FwdArgs a)
 {
@@ -373,43 +404,33 @@ __global__ __launch_bounds__(256, 4) void k_conv_fwd_split(FwdArgs a)
     // A operands: the LDS byte offset of a lane's node (x0 + li, y0 + w, z0)
     // of its 16-byte part, plus the offset of its tap of the pair.
     const uint32_t lane_base = (uint32_t)(part * HNODES + lnode(li, w, 0)) * 16u;
+    const uint32_t second_mask = second ? ~0u : 0u;
     constexpr uint32_t ROW_BYTES = HX * HY * 16;
     for (int hc = 0; hc < 2; ++hc) {
         if (hc) __syncthreads();  // every wave is done with the first half
-        for (int c = threadIdx.x; c < HNODES * 2; c += 256) {
-            const int node = c >> 1, pt = c & 1;
-            const int hx = node % HX, hy = (node / HX) % HY, hz = node / (HX * HY);
-            const int zr = z0 - 2 + hz;
-            const int zs = g.zper ? mod_pos(zr, g.nz) : ((zr < 0 || zr >= g.nz) ? -1 : zr);
-            u32x4 v = {0u, 0u, 0u, 0u};
-            if (zs >= 0) {
-                const size_t src = (size_t)wrapi(x0 - 2 + hx, g.nx) +
-                                   (size_t)g.nx * (mod_pos(y0 - 2 + hy, g.ny) + (size_t)g.ny * zs);
-                v = *(const u32x4 *)(a.in + src * 32 + 16 * hc + 8 * pt);
-            }
-            ((u32x4 *)tile)[pt * HNODES + node] = v;  // planar by 16-byte part: no bank conflicts
-        }
+        stage_half(g, a.in, tile, x0, y0, z0, hc, lane);
         __syncthreads();
 #pragma unroll 1
         for (int q0 = 0; q0 < KQ; q0 += PD) {
 #pragma unroll
             for (int qq = 0; qq < PD; ++qq) {
                 const int q = q0 + qq;
-                const uint32_t off = lane_base + (second ? c_tap_offsets.v[2 * q + 1] : c_tap_offsets.v[2 * q]);
-                bf16x8 av[ROWS], bw[NH];
+                const uint32_t t0 = __builtin_amdgcn_readfirstlane(c_tap_offsets.v[2 * q]);
+                const uint32_t dt = __builtin_amdgcn_readfirstlane(c_tap_offsets.v[2 * q + 1]);
+                const uint32_t off = lane_base + t0 + (dt & second_mask);
+                bf16x8 av[ROWS];
 #pragma unroll
                 for (int r = 0; r < ROWS; ++r)
                     av[r] = as_bf(*(const u32x4 *)((const char *)tile + off + r * ROW_BYTES));
 #pragma unroll
-                for (int h = 0; h < NH; ++h) {
-                    bw[h] = as_bf(bq[qq][h]);
-                    bq[qq][h] = load_b(hc * KQ + q + PD, h);
-                }
-#pragma unroll
                 for (int r = 0; r < ROWS; ++r)
 #pragma unroll
                     for (int h = 0; h < NH; ++h)
-                        acc[r][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[r], bw[h], acc[r][h], 0, 0, 0);
+                        acc[r][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[r], as_bf(bq[qq][h]), acc[r][h], 0, 0, 0);
+                // refill the ring slot once its products are issued, so that
+                // the load lands in the same registers
+#pragma unroll
+                for (int h = 0; h < NH; ++h) bq[qq][h] = load_b(hc * KQ + q + PD, h);
             }
         }
     }
