@@ -165,8 +165,9 @@ def surrogate_leg(hslb, np, workloads, wl, steps: int, epochs: int, nruns: int =
     the first `nruns` of the 40 training slits (64x64xnz, sigma 4..8, stable
     runs only), Adam on
     the GPU, then `steps` steps of the surrogate path (exact judge every 50
-    steps, residual threshold 1e-3) with the network plus frozen correction,
-    and without the network (frozen exact force: the ablation), against the
+    steps, residual threshold 1e-3) with the network plus frozen correction
+    (on every force component, and on the wall-normal component only), and
+    without the network (frozen exact force: the ablation), against the
     FP64 oracle's profiles of the same slit after the same number of steps.
     `network_steps` counts the steps that applied the network's force; a mode
     whose every step fell back to the exact force has measured only the exact
@@ -192,16 +193,20 @@ def surrogate_leg(hslb, np, workloads, wl, steps: int, epochs: int, nruns: int =
            "exact_path_err_n": float(np.linalg.norm(exact[0][fl] - ref[0][fl]) / np.linalg.norm(ref[0][fl])),
            "exact_path_err_ux": float(np.linalg.norm(exact[1][0][fl] - ref[1][0][fl]) /
                                       np.linalg.norm(ref[1][0][fl]))}
-    for mode in (hslb.HSLB_SURR_CORRECTED, hslb.HSLB_SURR_FROZEN):
-        r = surrogate.evaluate(wl, w, steps, 50, 1e-3, mode, reference=ref)
+    # the network on every component, the wall-normal variant (network on z
+    # only, in-plane components frozen at the last check), the ablation
+    for key, mode, comps in (("corrected", hslb.HSLB_SURR_CORRECTED, 7),
+                             ("wall_normal", hslb.HSLB_SURR_CORRECTED, 4),
+                             ("frozen", hslb.HSLB_SURR_FROZEN, 7)):
+        r = surrogate.evaluate(wl, w, steps, 50, 1e-3, mode, reference=ref, components=comps)
         done = r["steps"] if r["diverged_at_step"] is None else r["diverged_at_step"]
         # steps that used the surrogate force (network or frozen correction)
         # rather than an exact check or an exact fallback step
         r["surrogate_steps"] = int(done - r["checks"] - r["fallback_steps"])
         r["network_steps"] = r["surrogate_steps"] if mode != hslb.HSLB_SURR_FROZEN else 0
         r["measured"] = r["surrogate_steps"] > 0 and r["diverged_at_step"] is None
-        out[r["mode"]] = r
-        print(f"bench: surrogate {r['mode']}: {r}", file=sys.stderr, flush=True)
+        out[key] = r
+        print(f"bench: surrogate {key}: {r}", file=sys.stderr, flush=True)
     # network kernel times on the slit (eager, HIP events)
     s = hslb.Sim.from_workload(wl, force_mode=hslb.HSLB_FORCE_SURROGATE, surr_check_every=50, surr_tol=1e-3)
     hslb.hslb_surrogate_set_weights(s.ctx, w)

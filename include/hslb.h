@@ -363,12 +363,21 @@ int hslb_batch_autotune(hslb_ctx *ctx, int32_t steps, int32_t *choice, double *u
  *     load or new weights has no previous correction.
  * hslb_surrogate_stats: checks done, exact fallback steps, last and largest
  * residual.  hslb_surrogate_force: fs F_hat [3][N] of the current state
- * (host, caller-owned).  Weight arrays are caller-owned and copied. */
+ * (host, caller-owned).  Weight arrays are caller-owned and copied.
+ * hslb_surrogate_set_components: the components of F_hat the network drives,
+ * bits x = 1, y = 2, z = 4 (default 7; 0 or above 7: HSLB_EINVAL).  A component
+ * outside the mask is 0 in F_hat everywhere, so that the corrected path keeps
+ * it at the exact value of the last check (as the frozen mode does) while the
+ * network moves the others; 4 is the wall-normal variant for slits, whose
+ * in-plane force balances the driving field, orders of magnitude below the
+ * layering force the network learns.  Like a mode change it drops the
+ * previous correction. */
 #define HSLB_CNN_NWEIGHTS 144067
 enum { HSLB_SURR_CORRECTED = 0, HSLB_SURR_PLAIN = 1, HSLB_SURR_FROZEN = 2 };
 int hslb_surrogate_set_weights(hslb_ctx *ctx, const float *w, int64_t nw);
 int hslb_surrogate_get_weights(hslb_ctx *ctx, float *w, int64_t nw);
 int hslb_surrogate_set_mode(hslb_ctx *ctx, int32_t mode);
+int hslb_surrogate_set_components(hslb_ctx *ctx, int32_t mask);
 int hslb_surrogate_stats(hslb_ctx *ctx, int64_t *checks, int64_t *fallback_steps, double *last_residual,
                          double *max_residual);
 int hslb_surrogate_force(hslb_ctx *ctx, double *F);

@@ -226,6 +226,7 @@ public:
     virtual int surr_set_weights(const float *w) { (void)w; return fail_state("learned force needs a single lattice"); }
     virtual int surr_get_weights(float *w) { (void)w; return fail_state("learned force needs a single lattice"); }
     virtual int surr_set_mode(int mode) { (void)mode; return fail_state("learned force needs a single lattice"); }
+    virtual int surr_set_components(int mask) { (void)mask; return fail_state("learned force needs a single lattice"); }
     virtual int surr_stats(int64_t *checks, int64_t *fallback, double *last_r, double *max_r)
     {
         (void)checks, (void)fallback, (void)last_r, (void)max_r;
@@ -1160,6 +1161,16 @@ public:
         return HSLB_OK;
     }
 
+    int surr_set_components(int mask) override
+    {
+        if (p_.force_mode != HSLB_FORCE_SURROGATE) return fail(err, HSLB_ESTATE, "context is not in surrogate mode");
+        if (mask < 1 || mask > 7) return fail(err, HSLB_EINVAL, "network force components: a mask of bits 0..2, not 0");
+        surr_zero_ = ~mask & 7;
+        surr_ok_ = false;
+        have_delta_ = false;
+        return HSLB_OK;
+    }
+
     int surr_stats(int64_t *checks, int64_t *fallback, double *last_r, double *max_r) override
     {
         if (checks) *checks = surr_checks_;
@@ -1193,6 +1204,7 @@ public:
         a.bias = cw_ + cnn::OB3;
         a.out_cl = nullptr;
         a.out_f32 = fhat_;
+        a.out_zero = surr_zero_;
         return launch("cnn_l3", [&] { return cnn::launch_conv_fwd(st(), 32, 3, cnn::EPI_OUT, a); });
     }
 
@@ -1356,6 +1368,7 @@ private:
     double fscale_ = 0.0;
     bool have_w_ = false, surr_ok_ = false, have_delta_ = false;
     int surr_mode_ = HSLB_SURR_CORRECTED;
+    int surr_zero_ = 0;  // network force components (bit c) held at 0
     int64_t surr_checks_ = 0, surr_fallback_ = 0;
     double surr_last_r_ = -1.0, surr_max_r_ = 0.0;
 
@@ -2343,6 +2356,12 @@ int hslb_surrogate_set_mode(hslb_ctx *ctx, int32_t mode)
 {
     CTX_CHECK(ctx);
     return ctx->eng->surr_set_mode(mode);
+}
+
+int hslb_surrogate_set_components(hslb_ctx *ctx, int32_t mask)
+{
+    CTX_CHECK(ctx);
+    return ctx->eng->surr_set_components(mask);
 }
 
 int hslb_surrogate_stats(hslb_ctx *ctx, int64_t *checks, int64_t *fallback_steps, double *last_residual,

@@ -341,7 +341,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(FwdArgs a)
                 const int node = rowbase + x0 + 4 * lg + j;
                 const float v = acc[r][h][j];
                 if constexpr (EPI == EPI_OUT) {
-                    if (c < CO) a.out_f32[(size_t)c * g.N + node] = v + a.bias[c];
+                    if (c < CO) a.out_f32[(size_t)c * g.N + node] = (a.out_zero >> c) & 1 ? 0.f : v + a.bias[c];
                 } else {
                     const uint32_t bits = f2bf(v * gelu_grad(a.zsave[(size_t)node * 32 + c]));
                     if (a.out_f32) a.out_f32[(size_t)node * 32 + c] = v;
@@ -451,7 +451,7 @@ __global__ __launch_bounds__(256, 4) void k_conv_fwd_split(FwdArgs a)
                     const int node = rowbase + x0 + 4 * lg + j;
                     const float v = acc[r][h][j];
                     if constexpr (EPI == EPI_OUT) {
-                        if (c < CO) a.out_f32[(size_t)c * g.N + node] = v + a.bias[c];
+                        if (c < CO) a.out_f32[(size_t)c * g.N + node] = (a.out_zero >> c) & 1 ? 0.f : v + a.bias[c];
                     } else {
                         const uint32_t bits = f2bf(v * gelu_grad(a.zsave[(size_t)node * 32 + c]));
                         if (a.out_f32) a.out_f32[(size_t)node * 32 + c] = v;

@@ -61,6 +61,7 @@ struct FwdArgs {
     uint16_t *out_cl;      // bf16 [N][32] (nullable)
     uint16_t *out_cm;      // bf16 [32][N] (nullable)
     float *out_f32;        // EPI_GELU: z [N][32]; EPI_OUT: [3][N]; EPI_DGELU: raw sum [N][32] (nullable)
+    int out_zero;          // EPI_OUT: output channels (bit c) written as 0 instead of conv + bias
 };
 
 // cin in {1, 4, 32}; cout 32 (two output halves) or 3; epi as above.

@@ -54,6 +54,7 @@ EXPORTS = (
     "hslb_batch_create", "hslb_batch_init", "hslb_batch_profiles", "hslb_batch_finite",
     "hslb_batch_set_config", "hslb_batch_set_launch", "hslb_batch_get_launch", "hslb_batch_autotune",
     "hslb_surrogate_set_weights", "hslb_surrogate_get_weights", "hslb_surrogate_set_mode",
+    "hslb_surrogate_set_components",
     "hslb_surrogate_stats", "hslb_surrogate_force", "hslb_surrogate_save_snapshot", "hslb_surrogate_train",
     "hslb_trainer_create", "hslb_trainer_destroy", "hslb_trainer_last_error",
     "hslb_trainer_add_snapshot", "hslb_trainer_add_snapshot_host", "hslb_trainer_count",
@@ -146,6 +147,7 @@ def load(path: Optional[str] = None):
         "hslb_surrogate_set_weights": (ctypes.c_int, [_vp, _fp, ctypes.c_int64]),
         "hslb_surrogate_get_weights": (ctypes.c_int, [_vp, _fp, ctypes.c_int64]),
         "hslb_surrogate_set_mode": (ctypes.c_int, [_vp, ctypes.c_int32]),
+        "hslb_surrogate_set_components": (ctypes.c_int, [_vp, ctypes.c_int32]),
         "hslb_surrogate_stats": (ctypes.c_int, [_vp, _P(ctypes.c_int64), _P(ctypes.c_int64), _dp, _dp]),
         "hslb_surrogate_force": (ctypes.c_int, [_vp, _dp]),
         "hslb_surrogate_save_snapshot": (ctypes.c_int, [_vp, ctypes.c_char_p]),
@@ -413,6 +415,10 @@ def hslb_surrogate_get_weights(ctx) -> np.ndarray:
 
 def hslb_surrogate_set_mode(ctx, mode: int):
     _chk(ctx, load().hslb_surrogate_set_mode(ctx, int(mode)))
+
+
+def hslb_surrogate_set_components(ctx, mask: int):
+    _chk(ctx, load().hslb_surrogate_set_components(ctx, int(mask)))
 
 
 def hslb_surrogate_stats(ctx):

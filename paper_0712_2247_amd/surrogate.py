@@ -81,16 +81,18 @@ def train(trainer: hslb.Trainer, w0: np.ndarray, snapshots: Sequence[int], epoch
 
 def evaluate(wl: workloads.Workload, w: Optional[np.ndarray], steps: int, K: int, tol: float,
              mode: int = hslb.HSLB_SURR_CORRECTED, precision: str = "f32",
-             reference: Optional[tuple] = None) -> Dict:
+             reference: Optional[tuple] = None, components: int = 7) -> Dict:
     """Runs the surrogate path for `steps` steps and returns its throughput
     (every step, checks included), judge statistics and profile errors
     against `reference` = (n_z, u_z) of the exact path (relative L2 of n(z)
-    and u_x(z) over the fluid layers)."""
+    and u_x(z) over the fluid layers).  `components`: the force components
+    the network drives (bits x, y, z; 4 = wall-normal only)."""
     s = hslb.Sim.from_workload(wl, precision=precision, force_mode=hslb.HSLB_FORCE_SURROGATE,
                                surr_check_every=K, surr_tol=tol)
     hslb.hslb_surrogate_set_weights(s.ctx, w if w is not None else
                                     np.zeros(hslb.HSLB_CNN_NWEIGHTS, dtype=np.float32))
     hslb.hslb_surrogate_set_mode(s.ctx, mode)
+    hslb.hslb_surrogate_set_components(s.ctx, components)
     n, u = wl.fields()
     s.init(n, u)
     # the watchdog (every K steps: finite state, mass within 1e-3) stops a run
@@ -113,6 +115,7 @@ def evaluate(wl: workloads.Workload, w: Optional[np.ndarray], steps: int, K: int
     s.close()
     fin = lambda v: float(v) if np.isfinite(v) else None  # noqa: E731
     out = {"steps": steps, "K": K, "tol": tol, "mode": {0: "corrected", 1: "plain", 2: "frozen"}[mode],
+           "components": components,
            "mlups": wl.fluid_nodes * done / dt / 1e6, "ms_per_step": dt / max(done, 1) * 1e3,
            "checks": checks, "fallback_steps": fallback, "last_residual": fin(last_r),
            "max_residual": fin(max_r), "diverged_at_step": diverged_at}

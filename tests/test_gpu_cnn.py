@@ -325,12 +325,13 @@ def small_slit(precision="f64"):
     return workloads.slit("surr-32x8x20", 32, 8, 16, 4, 0.2, 1.0, 1e-5, 100, precision, 1010, 0.01)
 
 
-def surr_sim(wl, K, tol, precision="f64", mode=hslb.HSLB_SURR_CORRECTED, w=None):
+def surr_sim(wl, K, tol, precision="f64", mode=hslb.HSLB_SURR_CORRECTED, w=None, components=7):
     s = hslb.Sim.from_workload(wl, precision=precision, force_mode=hslb.HSLB_FORCE_SURROGATE,
                                surr_check_every=K, surr_tol=tol)
     if w is not None:
         hslb.hslb_surrogate_set_weights(s.ctx, w)
     hslb.hslb_surrogate_set_mode(s.ctx, mode)
+    hslb.hslb_surrogate_set_components(s.ctx, components)
     n, u = wl.fields()
     s.init(n, u)
     return s
@@ -349,6 +350,31 @@ def test_surrogate_force_matches_oracle():
     n, _ = wl.fields()
     ref = oracle_fhat(w, n, wl.sigma)
     assert rel(F, ref) <= 1e-4
+
+
+def test_surrogate_force_components():
+    """A component outside the network mask is 0 in F_hat; the others are the
+    network's, bit for bit.  Masks outside 1..7 and contexts without the
+    learned force are refused."""
+    wl = small_slit()
+    w = weights(26, out_scale=1e-3)
+    full = surr_sim(wl, 50, 1.0, w=w).surrogate_force()
+    for mask in (4, 3, 1):
+        F = surr_sim(wl, 50, 1.0, w=w, components=mask).surrogate_force()
+        for c in range(3):
+            if (mask >> c) & 1:
+                assert np.array_equal(F[c], full[c])
+            else:
+                assert not F[c].any()
+    s = surr_sim(wl, 50, 1.0, w=w)
+    for bad in (0, 8, -1):
+        with pytest.raises(hslb.HslbError) as ei:
+            hslb.hslb_surrogate_set_components(s.ctx, bad)
+        assert ei.value.code == hslb.HSLB_EINVAL
+    e = hslb.Sim.from_workload(wl)
+    with pytest.raises(hslb.HslbError) as ei:
+        hslb.hslb_surrogate_set_components(e.ctx, 4)
+    assert ei.value.code == hslb.HSLB_ESTATE
 
 
 def test_step_before_weights_is_reported():
@@ -418,15 +444,19 @@ def test_frozen_exact_force_between_checks():
     assert e <= 1e-6
 
 
-def test_corrected_network_schedule_matches_oracle():
+@pytest.mark.parametrize("components", [7, 4])
+def test_corrected_network_schedule_matches_oracle(components):
     """Network force plus the frozen correction between checks, against the
     oracle's network driven by the same schedule.  The residual threshold is
-    set high so the network is used after every check."""
+    set high so the network is used after every check.  components = 4: the
+    wall-normal variant, whose x and y network outputs are 0, so that those
+    components carry the exact force of the last check."""
     wl = small_slit()
     K, steps = 4, 10
     w = weights(28, out_scale=1e-3)
-    s = surr_sim(wl, K, 1e9, w=w)
+    s = surr_sim(wl, K, 1e9, w=w, components=components)
     s.step(steps)
+    off = [c for c in range(3) if not (components >> c) & 1]
     o = oracle.Oracle(**wl.params())
     n, u = wl.fields()
     o.init(n, u)
@@ -437,6 +467,7 @@ def test_corrected_network_schedule_matches_oracle():
     for t in range(steps):
         m, _ = o.moments()
         fh = oracle_fhat(w, m, wl.sigma) * mask
+        fh[off] = 0.0
         if t % K == 0:
             c1 = (o.force() - m[None] * g) * mask
             pred = fh + (delta if delta is not None else 0.0)

@@ -5,7 +5,8 @@ oracle's run of the same slit (tests/golden, written by make_golden.py from
 the oracle alone; 3000 steps of the oracle took 2.4 hours on 6 threads, so
 the comparison is made in the transient, where the force changes fastest,
 rather than at the steady state some 10^5 steps later), and what the trained
-network gains over the method without it.
+network gains over the method without it, on every force component and on
+the wall-normal one only.
 
 The network is trained here on the first 12 of the 40 seeded training slits
 (64x64xnz, sigma 4..8, packing 0.1..0.4; slits the watchdog flags as unstable
@@ -86,23 +87,36 @@ def test_exact_path_against_the_oracle_on_the_held_out_slit():
 
 def test_what_the_network_gains_over_the_ablation(trained):
     """The network plus the frozen correction against the no-network ablation
-    on the held-out slit.  Measured relation (asserted as it stands): the
-    density-only network cannot represent the current term of eq. (12) and
-    its receptive field (radius 6) is smaller than sigma = 8, so between checks
-    it moves the force away from the exact one.  Measured: the judge lets the
-    network act on 49 of 3000 steps and u_x ends 19 % off the oracle (n 6.9e-4),
-    while the ablation, on the frozen force for 147 steps, stays within 8.6e-4
-    (n) and 3.3e-4 (u_x).  The network therefore gains nothing on this slit."""
+    on the held-out slit, on every force component and on the wall-normal
+    component only (components = 4: the in-plane components keep the exact
+    force of the last check).  Measured relations, asserted as they stand:
+
+    - On every component the network fails the bar on u_x (measured: 66 %
+      off after acting on 49 of 3000 steps).  In the slit the in-plane force
+      balances the driving field, g n ~ 1e-9 per node, while the network's
+      output error is of the order of the layering force it learns (~1e-5):
+      between checks its in-plane outputs move the flow.
+    - Wall-normal only, it meets the bar (measured: n 2.8e-4, u_x 1.2e-4), as
+      does the ablation (8.6e-4, 3.3e-4), whose profiles it beats here.  It
+      takes the surrogate force on 49 steps against the ablation's 147 (the
+      judge rejects more of its checks in the transient) and so runs slower
+      (about 7200 against 8400 MLUPS): the gain is in accuracy at fewer
+      approximate steps, not in throughput."""
     wl = workloads.slit_128_f32_stable()
     ref = _golden(STEPS)
     net = surrogate.evaluate(wl, trained, STEPS, K, TOL, hslb.HSLB_SURR_CORRECTED, reference=ref)
+    wn = surrogate.evaluate(wl, trained, STEPS, K, TOL, hslb.HSLB_SURR_CORRECTED, reference=ref,
+                            components=4)
     abl = surrogate.evaluate(wl, trained, STEPS, K, TOL, hslb.HSLB_SURR_FROZEN, reference=ref)
     print(f"network + correction: {net}", flush=True)
+    print(f"wall-normal network + correction: {wn}", flush=True)
     print(f"ablation (frozen exact force): {abl}", flush=True)
     ea = max(_errors(abl))
     assert ea <= 1e-3
     if net["diverged_at_step"] is None:
-        en = max(_errors(net))
-        assert en > ea
-    # checks happen on schedule in both runs
-    assert abl["checks"] == STEPS // K
+        assert max(_errors(net)) > ea
+    assert wn["diverged_at_step"] is None
+    assert max(_errors(wn)) <= 1e-3
+    assert wn["steps"] - wn["checks"] - wn["fallback_steps"] > 0   # the network did act
+    # checks happen on schedule in every run
+    assert abl["checks"] == wn["checks"] == STEPS // K
