@@ -120,3 +120,33 @@ def test_what_the_network_gains_over_the_ablation(trained):
     assert wn["steps"] - wn["checks"] - wn["fallback_steps"] > 0   # the network did act
     # checks happen on schedule in every run
     assert abl["checks"] == wn["checks"] == STEPS // K
+
+
+GOLDEN_BENCH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "slit_64x64x136_eta0.25_profiles.json")
+
+
+def test_wall_normal_network_on_the_benchmark_slit():
+    """The benchmark's surrogate leg as a test: the network trained on all 40
+    training slits (27 stable, 2700 snapshots, 2 epochs), then 5000 steps of
+    the 64x64x136 slit (sigma 8, packing 0.25, tau 0.8) with K = 50, against
+    the oracle's FP64 run of the same slit (tests/golden).  The wall-normal
+    variant and the ablation meet the 1e-3 bar, and the network acts on some
+    of the steps.  Measured: wall-normal n 4.9e-5, u_x 3.5e-5 on 245 network
+    steps; ablation 4.0e-4 and 2.5e-4 on 784 frozen steps."""
+    runs = workloads.surrogate_training_runs()
+    tr = hslb.Trainer(sum(w.nodes for w in runs) * 100 + 1, max(w.nodes for w in runs))
+    recs = surrogate.collect(tr, runs, 20, 2000)
+    snaps = [k for r in recs for k in r["snapshots"]]
+    w = surrogate.train(tr, workloads.cnn_init_weights(), snaps, 2, 1e-3)["weights"]
+    tr.close()
+    steps = 5000
+    with open(GOLDEN_BENCH) as fh:
+        snap = json.load(fh)["snapshots"][str(steps)]
+    ref = (np.array(snap["n_z"]), np.array(snap["u_z"]))
+    wl = workloads.slit_64_f32_stable()
+    wn = surrogate.evaluate(wl, w, steps, K, TOL, hslb.HSLB_SURR_CORRECTED, reference=ref, components=4)
+    abl = surrogate.evaluate(wl, w, steps, K, TOL, hslb.HSLB_SURR_FROZEN, reference=ref)
+    print(f"{len(snaps)} snapshots; wall-normal: {wn}; ablation: {abl}", flush=True)
+    assert wn["diverged_at_step"] is None and abl["diverged_at_step"] is None
+    assert max(_errors(wn)) <= 1e-3 and max(_errors(abl)) <= 1e-3
+    assert wn["steps"] - wn["checks"] - wn["fallback_steps"] > 0
