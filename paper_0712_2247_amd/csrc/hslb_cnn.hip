@@ -8,7 +8,7 @@
 //  - Forward and input-gradient convolutions: M = 16 consecutive x-nodes of a
 //    row, N = output channels, K = (tap, input channel).  The 8 K-values of a
 //    lane are 8 channels of one node, a 16-byte load from channel-last bf16
-//    activations.  A wave computes 4 rows (y) x 16 nodes against both 16-column
+//    activations.  A wave computes 4 rows (z) x 16 nodes against both 16-column
 //    output halves; B comes pre-packed in lane order.  The forward layers with
 //    32 input channels stage them in two halves of 16 (k_conv_fwd_split), which
 //    halves the LDS per block and doubles the resident waves.
@@ -78,7 +78,8 @@ __device__ __forceinline__ int zsrc(const Geo &g, int z)
 // wave w takes y0 + w, its 4 rows the layers z0 .. z0 + 3.  The input nodes
 // the tile reads, 20 x 8 x 8 with the halo of 2, are staged in LDS once (x
 // and y wrapped, z wrapped or zero beyond walls); every tap's A operand then
-// comes from LDS.  cin = 32: 64 B per node (80 KB); cin = 4: 8 B; cin = 1: 2 B.
+// comes from LDS.  32 input channels are staged as two halves of 32 B per node
+// (40 KB each, k_conv_fwd_split); cin = 4: 8 B per node; cin = 1: 2 B.
 #ifndef HSLB_CNN_TZ
 #define HSLB_CNN_TZ 4
 #endif
@@ -146,19 +147,14 @@ template <int CIN>
 __device__ __forceinline__ void stage_tile(const Geo &g, const uint16_t *__restrict__ in, uint16_t *tile, int x0,
                                            int y0, int z0)
 {
-    constexpr int PARTS = CIN == 32 ? 4 : 1;  // 16-byte parts per node (cin 32)
-    for (int c = threadIdx.x; c < HNODES * PARTS; c += 256) {
-        const int node = c / PARTS, part = c % PARTS;
+    static_assert(CIN == 1 || CIN == 4, "32-channel inputs are staged by halves (stage_half)");
+    for (int node = threadIdx.x; node < HNODES; node += 256) {
         const int hx = node % HX, hy = (node / HX) % HY, hz = node / (HX * HY);
         const int zr = z0 - 2 + hz;
         const int zs = g.zper ? mod_pos(zr, g.nz) : ((zr < 0 || zr >= g.nz) ? -1 : zr);
         size_t src = 0;
         if (zs >= 0) src = (size_t)wrapi(x0 - 2 + hx, g.nx) + (size_t)g.nx * (mod_pos(y0 - 2 + hy, g.ny) + (size_t)g.ny * zs);
-        if constexpr (CIN == 32) {
-            u32x4 v = {0u, 0u, 0u, 0u};
-            if (zs >= 0) v = ((const u32x4 *)(in + src * 32))[part];
-            ((u32x4 *)tile)[c] = v;
-        } else if constexpr (CIN == 4) {
+        if constexpr (CIN == 4) {
             u32x2 v = {0u, 0u};
             if (zs >= 0) v = *(const u32x2 *)(in + src * 4);
             ((u32x2 *)tile)[node] = v;
@@ -173,10 +169,7 @@ template <int CIN>
 __device__ __forceinline__ u32x4 lds_a(const uint16_t *tile, int s, int li, int w, int r, int lg)
 {
     u32x4 v = {0u, 0u, 0u, 0u};
-    if constexpr (CIN == 32) {
-        const int dz = s / 25, dy = (s / 5) % 5, dx = s % 5;  // offsets + 2
-        v = ((const u32x4 *)tile)[lnode(li + dx, w + dy, r + dz) * 4 + lg];
-    } else if constexpr (CIN == 4) {
+    if constexpr (CIN == 4) {
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int t = 8 * s + 2 * lg + q;
@@ -246,10 +239,20 @@ __device__ __forceinline__ void gelu_epilogue(const FwdArgs &a, const Geo &g, ui
     }
 }
 
-template <int CIN, int NH, int EPI>
+// Layer 1 forward (1 -> 32 channels, GELU epilogue) and the input gradient of
+// layer 3 (its 3 output-gradient channels padded to 4 -> 32, GELU' epilogue):
+// the block's whole input halo fits LDS (2 or 8 bytes per node).  The B
+// operands (the same for every block, so cache hits) are loaded PD K-steps
+// ahead into a register ring; rows past the end of a partial z tile are
+// computed on the staged zeros or wrapped layers and not stored, which keeps
+// the loop free of branches.
+template <int CIN, int EPI>
 __global__ __launch_bounds__(256) void k_conv_fwd(FwdArgs a)
 {
-    constexpr int KS = CIN == 32 ? NT : (CIN == 4 ? 16 : 4);
+    static_assert((CIN == 1 && EPI == EPI_GELU) || (CIN == 4 && EPI == EPI_DGELU),
+                  "layer 1 forward, layer 3 input gradient");
+    constexpr int NH = 2;
+    constexpr int KS = CIN == 4 ? 16 : 4;
     __shared__ __attribute__((aligned(16))) uint16_t tile[HNODES * CIN];
     const Geo g = a.g;
     const int nxb = g.nx / TX, nyb = g.ny / TY;
@@ -270,79 +273,50 @@ __global__ __launch_bounds__(256) void k_conv_fwd(FwdArgs a)
 #pragma unroll
         for (int h = 0; h < NH; ++h) acc[r][h] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-    if constexpr (NH == 2) {
-        // The B operands (the same for every block, so cache hits) are loaded
-        // PD K-steps ahead into a register ring; rows past the end of a partial
-        // z tile are computed on the staged zeros or wrapped layers and not
-        // stored, which keeps the loop free of branches.  Layer 2 (32 -> 32)
-        // on the 64x64x136 slit: 285 -> 247 us.  The 3-channel layer gains
-        // nothing from it (fewer products per step) and keeps the plain loop.
-        constexpr int PD = 8;
-        auto load_b = [&](int s, int h) { return *(const u32x4 *)(a.wp + ((size_t)(s * NH + h) * 64 + lane) * 8); };
-        u32x4 bq[PD][NH];
+    constexpr int PD = 8;
+    auto load_b = [&](int s, int h) { return *(const u32x4 *)(a.wp + ((size_t)(s * NH + h) * 64 + lane) * 8); };
+    u32x4 bq[PD][NH];
 #pragma unroll
-        for (int q = 0; q < PD; ++q)
+    for (int q = 0; q < PD; ++q)
 #pragma unroll
-            for (int h = 0; h < NH; ++h) bq[q][h] = q < KS ? load_b(q, h) : (u32x4){0u, 0u, 0u, 0u};
-        for (int s0 = 0; s0 < KS; s0 += PD) {
+        for (int h = 0; h < NH; ++h) bq[q][h] = q < KS ? load_b(q, h) : (u32x4){0u, 0u, 0u, 0u};
+    for (int s0 = 0; s0 < KS; s0 += PD) {
 #pragma unroll
-            for (int q = 0; q < PD; ++q) {
-                const int s = s0 + q;
-                if (s < KS) {
-                    bf16x8 av[ROWS], bw[NH];
+        for (int q = 0; q < PD; ++q) {
+            const int s = s0 + q;
+            if (s < KS) {
+                bf16x8 av[ROWS], bw[NH];
 #pragma unroll
-                    for (int r = 0; r < ROWS; ++r) av[r] = as_bf(lds_a<CIN>(tile, s, li, w, r, lg));
+                for (int r = 0; r < ROWS; ++r) av[r] = as_bf(lds_a<CIN>(tile, s, li, w, r, lg));
 #pragma unroll
-                    for (int h = 0; h < NH; ++h) {
-                        bw[h] = as_bf(bq[q][h]);
-                        if (s + PD < KS) bq[q][h] = load_b(s + PD, h);
-                    }
-#pragma unroll
-                    for (int r = 0; r < ROWS; ++r)
-#pragma unroll
-                        for (int h = 0; h < NH; ++h)
-                            acc[r][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[r], bw[h], acc[r][h], 0, 0, 0);
+                for (int h = 0; h < NH; ++h) {
+                    bw[h] = as_bf(bq[q][h]);
+                    if (s + PD < KS) bq[q][h] = load_b(s + PD, h);
                 }
-            }
-        }
-    } else {
-        for (int s = 0; s < KS; ++s) {
-            bf16x8 bw[NH];
 #pragma unroll
-            for (int h = 0; h < NH; ++h)
-                bw[h] = as_bf(*(const u32x4 *)(a.wp + ((size_t)(s * NH + h) * 64 + lane) * 8));
-#pragma unroll
-            for (int r = 0; r < ROWS; ++r) {
-                if (r < rows) {
-                    const bf16x8 av = as_bf(lds_a<CIN>(tile, s, li, w, r, lg));
+                for (int r = 0; r < ROWS; ++r)
 #pragma unroll
                     for (int h = 0; h < NH; ++h)
-                        acc[r][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[h], acc[r][h], 0, 0, 0);
-                }
+                        acc[r][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[r], bw[h], acc[r][h], 0, 0, 0);
             }
         }
     }
 
     if constexpr (EPI == EPI_GELU) {
-        static_assert(NH == 2, "GELU layers have 32 outputs");
         __shared__ __attribute__((aligned(16))) uint16_t ot[TX * TY * TZ * 32];
         gelu_epilogue(a, g, ot, acc, x0, y0, z0, rows, w, li, lg);
-        return;
-    }
+    } else {
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-        if (r >= rows) continue;
-        const int rowbase = g.nx * ((y0 + w) + g.ny * (z0 + r));
+        for (int r = 0; r < ROWS; ++r) {
+            if (r >= rows) continue;
+            const int rowbase = g.nx * ((y0 + w) + g.ny * (z0 + r));
 #pragma unroll
-        for (int h = 0; h < NH; ++h) {
-            const int c = 16 * h + li;
+            for (int h = 0; h < NH; ++h) {
+                const int c = 16 * h + li;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int node = rowbase + x0 + 4 * lg + j;
-                const float v = acc[r][h][j];
-                if constexpr (EPI == EPI_OUT) {
-                    if (c < CO) a.out_f32[(size_t)c * g.N + node] = (a.out_zero >> c) & 1 ? 0.f : v + a.bias[c];
-                } else {
+                for (int j = 0; j < 4; ++j) {
+                    const int node = rowbase + x0 + 4 * lg + j;
+                    const float v = acc[r][h][j];
                     const uint32_t bits = f2bf(v * gelu_grad(a.zsave[(size_t)node * 32 + c]));
                     if (a.out_f32) a.out_f32[(size_t)node * 32 + c] = v;
                     if (a.out_cl) a.out_cl[(size_t)node * 32 + c] = (uint16_t)bits;
@@ -878,9 +852,10 @@ hipError_t launch_conv_fwd(hipStream_t s, int cin, int cout, int epi, const FwdA
     const int blocks = (a.g.nx / TX) * (a.g.ny / TY) * ((a.g.nz + TZ - 1) / TZ);
     const dim3 grid(blocks), blk(256);
     const int nh = cout == 32 ? 2 : 1;
-#define HSLB_CONV(CI, NH_, EP) \
-    if (cin == CI && nh == NH_ && epi == EP) { hipLaunchKernelGGL((k_conv_fwd<CI, NH_, EP>), grid, blk, 0, s, a); return hipGetLastError(); }
-    HSLB_CONV(1, 2, EPI_GELU)
+    if (cin == 1 && nh == 2 && epi == EPI_GELU) {
+        hipLaunchKernelGGL((k_conv_fwd<1, EPI_GELU>), grid, blk, 0, s, a);
+        return hipGetLastError();
+    }
     if (cin == 32 && nh == 2 && epi == EPI_GELU) {
         hipLaunchKernelGGL((k_conv_fwd_split<2, EPI_GELU>), grid, blk, 0, s, a);
         return hipGetLastError();
@@ -893,8 +868,10 @@ hipError_t launch_conv_fwd(hipStream_t s, int cin, int cout, int epi, const FwdA
         hipLaunchKernelGGL((k_conv_fwd_split<1, EPI_OUT>), grid, blk, 0, s, a);
         return hipGetLastError();
     }
-    HSLB_CONV(4, 2, EPI_DGELU)
-#undef HSLB_CONV
+    if (cin == 4 && nh == 2 && epi == EPI_DGELU) {
+        hipLaunchKernelGGL((k_conv_fwd<4, EPI_DGELU>), grid, blk, 0, s, a);
+        return hipGetLastError();
+    }
     return hipErrorInvalidValue;
 }
 
