@@ -1070,7 +1070,10 @@ __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &
 // that the plain path keeps its registers).
 // NT: populations loaded and stored non-temporally, for lattices whose two
 // population copies overflow the last-level cache (256^3 bulk: 1603 -> 1539 us);
-// the cache-resident benchmark slit gains nothing from it.
+// the cache-resident benchmark slit gains nothing from it.  That instance also
+// addresses its reads by 32-bit node indices (as the batch kernel does) rather
+// than by layer-uniform base offsets: 1513 against 1530 us on the bulk, while
+// the slit keeps the layer-uniform form (39.5 against 40.8 us).
 template <int SIG, typename TF, typename TM, bool MASK, bool NT>
 __global__ __launch_bounds__(256, HSLB_COLLIDE_WAVES) void k_collide(LatticeDev L, StepConst sc, const double *__restrict__ chi,
                                                  const TF *__restrict__ fin, TF *__restrict__ fout,
@@ -1081,7 +1084,7 @@ __global__ __launch_bounds__(256, HSLB_COLLIDE_WAVES) void k_collide(LatticeDev 
     const int c = lb - zl * cpp;
     const int r = c * 256 + threadIdx.x;
     const int z = (L.zper ? 0 : L.wall_lo) + zl;
-    if (r < L.plane) d_collide<SIG, true, TF, TM, MASK, NT>(L, sc, chi, fin, fout, fld, z, r);
+    if (r < L.plane) d_collide<SIG, !NT, TF, TM, MASK, NT>(L, sc, chi, fin, fout, fld, z, r);
 }
 
 // k_collide for FP32 storage and fields with the shell sum staged through LDS:
