@@ -381,14 +381,14 @@ __global__ __launch_bounds__(256) void k_conv_fwd(FwdArgs a)
     }
 }
 
-// Forward layers 2 (32 -> 32 channels, GELU) and 3 (32 -> 3), and the input
-// gradient of layer 2 (transposed weights, GELU' epilogue), with the input
-// channels in two halves of 16.  The staged halo then holds 32 B per node (40 KB instead of
+// Forward layer 2 (32 -> 32 channels, GELU) and its input gradient
+// (transposed weights, GELU' epilogue), with the input channels in two halves
+// of 16.  The staged halo then holds 32 B per node (40 KB instead of
 // 80 KB), so four blocks share a compute unit, twice the resident waves of the
 // 64-byte halo, which hides the latencies of the LDS and weight reads.  A K-step
 // of 32 covers two taps x 16 channels: lane group lg takes tap 2q + lg/2 and
 // channels 8 (lg % 2) .. + 8 of the half; the weights come packed in that order
-// (PK_F2, PK_F3, PK_D2).  Output layout and epilogues as k_conv_fwd.  The K-loop
+// (PK_F2, PK_D2).  Output layout and epilogues as k_conv_fwd.  The K-loop
 // carries no branch and no per-lane index arithmetic: the tap offsets come
 // from a constant table through scalar loads, the B ring runs on over the
 // zero-padded end of the pack, and a ring slot is refilled after its products
@@ -398,8 +398,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(FwdArgs a)
 template <int NH, int EPI>
 __global__ __launch_bounds__(256, 4) void k_conv_fwd_split(FwdArgs a)
 {
-    static_assert((NH == 2 && (EPI == EPI_GELU || EPI == EPI_DGELU)) || (NH == 1 && EPI == EPI_OUT),
-                  "layers 2 and 3 forward, layer 2 input gradient");
+    static_assert(NH == 2 && (EPI == EPI_GELU || EPI == EPI_DGELU), "layer 2 forward and input gradient");
     __shared__ __attribute__((aligned(16))) uint16_t tile[HNODES * 16];
     const Geo g = a.g;
     const int nxb = g.nx / TX, nyb = g.ny / TY;
@@ -478,17 +477,116 @@ __global__ __launch_bounds__(256, 4) void k_conv_fwd_split(FwdArgs a)
                 for (int j = 0; j < 4; ++j) {
                     const int node = rowbase + x0 + 4 * lg + j;
                     const float v = acc[r][h][j];
-                    if constexpr (EPI == EPI_OUT) {
-                        if (c < CO) a.out_f32[(size_t)c * g.N + node] = (a.out_zero >> c) & 1 ? 0.f : v + a.bias[c];
-                    } else {
-                        const uint32_t bits = dgelu_bf16(v, a.zsave[(size_t)node * 32 + c]);
-                        if (a.out_f32) a.out_f32[(size_t)node * 32 + c] = v;
-                        if (a.out_cl) a.out_cl[(size_t)node * 32 + c] = (uint16_t)bits;
-                        if (a.out_cm) a.out_cm[(size_t)c * g.N + node] = (uint16_t)bits;
-                    }
+                    const uint32_t bits = dgelu_bf16(v, a.zsave[(size_t)node * 32 + c]);
+                    if (a.out_f32) a.out_f32[(size_t)node * 32 + c] = v;
+                    if (a.out_cl) a.out_cl[(size_t)node * 32 + c] = (uint16_t)bits;
+                    if (a.out_cm) a.out_cm[(size_t)c * g.N + node] = (uint16_t)bits;
                 }
             }
         }
+    }
+}
+
+// Layer 3 forward (32 -> 3 channels) with (output channel, dx) on the M
+// dimension of the products instead of the 16 x-nodes: M = 15 used of 16
+// rows (c, dx), N = 16 input columns x', K = 16 channels x two (dy, dz) taps.
+// The partial sums P[(c, dx)][x'] of a row then give
+//   out[c][x] = b[c] + sum_dx P[(c, dx)][x + dx]
+// through LDS.  A wave covers the 20 input columns of its 16 output nodes with
+// two N-tiles (32 columns, 20 used) and 4 z-rows, so a K-step is 8 products
+// against 1 weight fragment, where the node-major form (3 of 16 output
+// columns used) needs 2.4 times the products and LDS reads.  Halo staging and
+// the block's tile as in k_conv_fwd_split.  Weights packed as PK_F3.  On the
+// 64x64x136 slit: 61 us, against 91 us for the node-major form in the
+// split-channel kernel (69 us with the K loop rolled).
+constexpr int KD = 13;  // (dy, dz) pair steps per channel half: 25 taps + 1 pad
+
+struct DyDzOffsets {
+    uint32_t v[2 * KD];
+};
+constexpr DyDzOffsets make_dydz_offsets()
+{
+    DyDzOffsets o{};
+    for (int q = 0; q < KD; ++q)
+        for (int p = 0; p < 2; ++p) {
+            const int i = 2 * q + p;
+            o.v[i] = i < 25 ? (uint32_t)lnode(0, i % 5, i / 5) * 16u : 0u;
+        }
+    return o;
+}
+__constant__ DyDzOffsets c_dydz_offsets = make_dydz_offsets();
+
+__global__ __launch_bounds__(256, 4) void k_conv_out(FwdArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t tile[HNODES * 16];
+    const Geo g = a.g;
+    const int nxb = g.nx / TX, nyb = g.ny / TY;
+    const int b = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int zb = b / (nxb * nyb);
+    const int rem = b - zb * nxb * nyb;
+    const int yb = rem / nxb;
+    const int x0 = (rem - yb * nxb) * TX, y0 = yb * TY, z0 = zb * TZ;
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int part = lg & 1, second = lg >> 1;
+    const int rows = min(ROWS, g.nz - z0);
+    f32x4 acc[ROWS][2];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) acc[r][nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+    // B operand: column x' = li + 16 nt of the halo (x0 - 2 + x'); the columns
+    // past the halo's 20 are not needed and read its last one.
+    uint32_t col_base[2];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+        col_base[nt] = (uint32_t)(part * HNODES + lnode(min(li + 16 * nt, HX - 1), w, 0)) * 16u;
+    const uint32_t second_mask = second ? ~0u : 0u;
+    constexpr uint32_t ROW_BYTES = HX * HY * 16;
+    auto load_a = [&](int sq) { return *(const u32x4 *)(a.wp + ((size_t)sq * 64 + lane) * 8); };
+    u32x4 wq = load_a(0);
+    for (int hc = 0; hc < 2; ++hc) {
+        if (hc) __syncthreads();
+        stage_half(g, a.in, tile, x0, y0, z0, hc, lane);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < KD; ++q) {  // unrolled: the next step's LDS reads start early
+            const uint32_t t0 = __builtin_amdgcn_readfirstlane(c_dydz_offsets.v[2 * q]);
+            const uint32_t t1 = __builtin_amdgcn_readfirstlane(c_dydz_offsets.v[2 * q + 1]);
+            const uint32_t off = t0 + ((t1 - t0) & second_mask);
+            const bf16x8 wa = as_bf(wq);
+            wq = load_a(hc * KD + q + 1);  // the pack ends in PACK_PAD zero steps
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) {
+                    const bf16x8 bv = as_bf(*(const u32x4 *)((const char *)tile + col_base[nt] + off + r * ROW_BYTES));
+                    acc[r][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa, bv, acc[r][nt], 0, 0, 0);
+                }
+        }
+    }
+
+    // P[r][m][x'] of the wave through LDS (the halo is no longer read), then
+    // out[c][x0 + i] = b[c] + sum_dx P[r][5 c + dx][i + dx].
+    __syncthreads();
+    float *P = (float *)tile + w * (ROWS * 16 * 32);
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) P[(r * 16 + 4 * lg + j) * 32 + li + 16 * nt] = acc[r][nt][j];
+    __syncthreads();
+    for (int k = lane; k < ROWS * CO * 16; k += 64) {
+        const int i = k & 15, c = (k >> 4) % CO, r = k / (16 * CO);
+        if (r >= rows) continue;
+        float v = a.bias[c];
+#pragma unroll
+        for (int dx = 0; dx < 5; ++dx) v += P[(r * 16 + 5 * c + dx) * 32 + i + dx];
+        const size_t node = (size_t)(x0 + i) + (size_t)g.nx * ((y0 + w) + (size_t)g.ny * (z0 + r));
+        a.out_f32[(size_t)c * g.N + node] = (a.out_zero >> c) & 1 ? 0.f : v;
     }
 }
 
@@ -754,8 +852,12 @@ __global__ __launch_bounds__(256) void k_pack(int kind, const float *__restrict_
         const int hc = s / KQ, q = s - hc * KQ, t = 2 * q + (lg >> 1);
         if (hc < 2 && t < NT) v = w[OW2 + (col * CH + 16 * hc + 8 * (lg & 1) + e) * NT + t];
     } else if (kind == PK_F3) {
-        const int hc = s / KQ, q = s - hc * KQ, t = 2 * q + (lg >> 1);  // as PK_F2
-        if (hc < 2 && li < CO && t < NT) v = w[OW3 + (li * CH + 16 * hc + 8 * (lg & 1) + e) * NT + t];
+        // A operand of k_conv_out: row li = (output channel li / 5, dx li % 5),
+        // channel half hc, (dy, dz) pair step q: lane group lg holds tap
+        // (dy, dz) number 2q + lg/2 (dz major), channels 16 hc + 8 (lg % 2) .. + 8
+        const int hc = s / KD, q = s - hc * KD, i = 2 * q + (lg >> 1);
+        const int c = li / 5, dx = li % 5;
+        if (hc < 2 && c < CO && i < 25) v = w[OW3 + (c * CH + 16 * hc + 8 * (lg & 1) + e) * NT + (i / 5) * 25 + (i % 5) * 5 + dx];
     } else if (kind == PK_D2) {
         // transposed, tap-flipped layer-2 weights in the split order of PK_F2
         const int hc = s / KQ, q = s - hc * KQ, t = 2 * q + (lg >> 1);
@@ -919,7 +1021,7 @@ hipError_t launch_conv_fwd(hipStream_t s, int cin, int cout, int epi, const FwdA
         return hipGetLastError();
     }
     if (cin == 32 && nh == 1 && epi == EPI_OUT) {
-        hipLaunchKernelGGL((k_conv_fwd_split<1, EPI_OUT>), grid, blk, 0, s, a);
+        hipLaunchKernelGGL(k_conv_out, grid, blk, 0, s, a);
         return hipGetLastError();
     }
     if (cin == 4 && nh == 2 && epi == EPI_DGELU) {

@@ -34,17 +34,19 @@ struct Geo {
     int nx, ny, nz, zper, N;
 };
 
-// Packed MFMA B operands (bf16 bits), [ksteps][halves][64 lanes][8]:
-// forward layers 1-3 and the input-gradient convolutions of layers 2 and 3.
-// The split-channel packs (PK_F2, PK_F3, PK_D2) end in PACK_PAD zero K-steps,
-// so that their kernel's prefetch runs past the last step without a branch.
+// Packed MFMA weight operands (bf16 bits), [ksteps][halves][64 lanes][8]:
+// forward layers 1-3 and the input-gradient convolutions of layers 2 and 3
+// (the B operand everywhere but layer 3's forward, PK_F3: there the A operand
+// with rows (output channel, dx), 13 (dy, dz) pair steps per channel half).
+// PK_F2, PK_F3 and PK_D2 end in PACK_PAD zero K-steps, so that their kernels'
+// prefetch runs past the last step without a branch.
 enum PackKind { PK_F1 = 0, PK_F2, PK_F3, PK_D2, PK_D3, PK_COUNT };
 constexpr int PACK_PAD = 4;
 constexpr int pack_elems(int kind)
 {
     return kind == PK_F1 ? 4 * 2 * 512
          : kind == PK_F2 ? (2 * ((NT + 1) / 2) + PACK_PAD) * 2 * 512
-         : kind == PK_F3 ? (2 * ((NT + 1) / 2) + PACK_PAD) * 1 * 512
+         : kind == PK_F3 ? (2 * 13 + PACK_PAD) * 512
          : kind == PK_D2 ? (2 * ((NT + 1) / 2) + PACK_PAD) * 2 * 512
                          : 16 * 2 * 512;
 }
