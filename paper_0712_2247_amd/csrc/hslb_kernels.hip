@@ -118,6 +118,20 @@ __device__ __forceinline__ void store_padded(const LatticeDev &L, TM *dst, int r
     for (; p < L.nz + 2 * L.hz; p += L.nz) dst[rem + L.plane * p] = v;
 }
 
+// store_padded with non-temporal stores (fields written once and read by a
+// later kernel of a lattice beyond the last-level cache).
+template <typename TM>
+__device__ __forceinline__ void store_padded_nt(const LatticeDev &L, TM *dst, int rem, int z, TM v)
+{
+    if (!L.zper) {
+        __builtin_nontemporal_store(v, dst + rem + L.plane * (z + L.hz));
+        return;
+    }
+    int p = z + L.hz;
+    while (p - L.nz >= 0) p -= L.nz;
+    for (; p < L.nz + 2 * L.hz; p += L.nz) __builtin_nontemporal_store(v, dst + rem + L.plane * p);
+}
+
 // The interleaved (n, j) of a node into the padded field [..][4], with the
 // periodic images in the ghost layers as store_padded.
 template <typename TM>
@@ -395,8 +409,15 @@ __device__ __forceinline__ T g2_t(double eta, int model)
     }
 }
 
-// Node r (0 <= r < plane) of layer z.
-template <typename TM>
+#ifndef HSLB_GFIELD_NT_MIB
+#define HSLB_GFIELD_NT_MIB 256
+#endif
+// Node r (0 <= r < plane) of layer z.  NT: non-temporal stores, for contact
+// values that overflow the 256 MiB last-level cache on their own (256^3 bulk,
+// 492 MB: this kernel 154 -> 139 us and the collide that reads them 1515 ->
+// 1489 us).  Below that the collide loses from it: 6 us of 39 on the 64x64x136
+// slit (17 MB), 15 us of 336 on the 128x128x264 slit (128 MB).
+template <typename TM, bool NT = false>
 __device__ __forceinline__ void d_gfield(const LatticeDev &L, int model, const Fields<TM> &fld, int z, int r)
 {
     const int y = r / L.nx;
@@ -408,21 +429,27 @@ __device__ __forceinline__ void d_gfield(const LatticeDev &L, int model, const F
     const double e110 = e(x1, y1, zp), e101 = e(x1, y, zp + 1), e011 = e(x, y1, zp + 1);
     const size_t fs = L.fld_stride;
     const double h = 0.5, q = 0.25;
-    store_padded(L, fld.G + 0 * fs, r, z, g2_t<TM>(e000, model));
-    store_padded(L, fld.G + 1 * fs, r, z, g2_t<TM>(h * (e000 + e100), model));
-    store_padded(L, fld.G + 2 * fs, r, z, g2_t<TM>(h * (e000 + e010), model));
-    store_padded(L, fld.G + 3 * fs, r, z, g2_t<TM>(q * ((e000 + e100) + (e010 + e110)), model));
-    store_padded(L, fld.G + 4 * fs, r, z, g2_t<TM>(h * (e000 + e001), model));
-    store_padded(L, fld.G + 5 * fs, r, z, g2_t<TM>(q * ((e000 + e100) + (e001 + e101)), model));
-    store_padded(L, fld.G + 6 * fs, r, z, g2_t<TM>(q * ((e000 + e010) + (e001 + e011)), model));
+    auto st = [&](TM *dst, TM v) {
+        if constexpr (NT)
+            store_padded_nt(L, dst, r, z, v);
+        else
+            store_padded(L, dst, r, z, v);
+    };
+    st(fld.G + 0 * fs, g2_t<TM>(e000, model));
+    st(fld.G + 1 * fs, g2_t<TM>(h * (e000 + e100), model));
+    st(fld.G + 2 * fs, g2_t<TM>(h * (e000 + e010), model));
+    st(fld.G + 3 * fs, g2_t<TM>(q * ((e000 + e100) + (e010 + e110)), model));
+    st(fld.G + 4 * fs, g2_t<TM>(h * (e000 + e001), model));
+    st(fld.G + 5 * fs, g2_t<TM>(q * ((e000 + e100) + (e001 + e101)), model));
+    st(fld.G + 6 * fs, g2_t<TM>(q * ((e000 + e010) + (e001 + e011)), model));
 }
 
 // grid (ceil(plane / 256), nz)
-template <typename TM>
+template <typename TM, bool NT>
 __global__ __launch_bounds__(256) void k_gfield(LatticeDev L, int model, Fields<TM> fld)
 {
     const int r = blockIdx.x * 256 + threadIdx.x;
-    if (r < L.plane) d_gfield(L, model, fld, (int)blockIdx.y, r);
+    if (r < L.plane) d_gfield<TM, NT>(L, model, fld, (int)blockIdx.y, r);
 }
 
 // ------------------------------------------------------------ shell force
@@ -2418,7 +2445,11 @@ hipError_t launch_ballsum(hipStream_t s, const LatticeDev &L, int sigma, double 
 template <typename TM>
 hipError_t launch_gfield(hipStream_t s, const LatticeDev &L, int g2_model, Fields<TM> fld)
 {
-    hipLaunchKernelGGL(k_gfield<TM>, dim3(blocks_for(L.plane), L.nz), dim3(256), 0, s, L, g2_model, fld);
+    const double g_bytes = 7.0 * (double)L.fld_stride * sizeof(TM);
+    if (g_bytes > HSLB_GFIELD_NT_MIB * 1024.0 * 1024.0)
+        hipLaunchKernelGGL((k_gfield<TM, true>), dim3(blocks_for(L.plane), L.nz), dim3(256), 0, s, L, g2_model, fld);
+    else
+        hipLaunchKernelGGL((k_gfield<TM, false>), dim3(blocks_for(L.plane), L.nz), dim3(256), 0, s, L, g2_model, fld);
     return hipGetLastError();
 }
 
