@@ -622,7 +622,7 @@ public:
         if (l39()) return one_step39();
         if (sc_.hs_on && fused_rows()) {
             rc = launch("moments", [&] {
-                return launch_moments_rs<TF, TM>(st(), L_, sigma_, nref_d_, f_[cur_], fld_, rs_);
+                return launch_moments_rs<TF, TM>(st(), L_, sigma_, nref_d_, f_[cur_], fld_, rs_, sc_.phi != nullptr);
             });
             if (rc) return rc;
             rc = launch("smooth", [&] { return launch_ballsum<TM>(st(), L_, sigma_, sc_.eta_pref, fld_, rs_); });

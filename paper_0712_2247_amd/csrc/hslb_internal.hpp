@@ -142,10 +142,12 @@ template <typename TM>
 hipError_t launch_gfield(hipStream_t s, const LatticeDev &L, int g2_model, Fields<TM> fld);
 // Moments plus the row sums of the two-pass ball sum in one launch; returns
 // hipErrorInvalidValue (launching nothing) unless nx divides 256 and the plane
-// is a multiple of 256.  Then launch_ballsum completes eta_bar.
+// is a multiple of 256.  Then launch_ballsum completes eta_bar.  write_n: also
+// the separate density field fld.n (the interleaved (n, j) is always written;
+// within a step only the attraction reads fld.n).
 template <typename TF, typename TM>
 hipError_t launch_moments_rs(hipStream_t s, const LatticeDev &L, int sigma, const double *nref, const TF *f,
-                             Fields<TM> fld, TM *rs);
+                             Fields<TM> fld, TM *rs, bool write_n);
 template <typename TM>
 hipError_t launch_ballsum(hipStream_t s, const LatticeDev &L, int sigma, double eta_pref, Fields<TM> fld,
                           const TM *rs);

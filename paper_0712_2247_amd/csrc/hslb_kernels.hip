@@ -232,7 +232,8 @@ __global__ __launch_bounds__(256) void k_layer_means(LatticeDev L, const TF *__r
 // layer-indexed grid, so the reference row is read through scalar loads.
 template <typename TF, typename TM>
 __device__ __forceinline__ TM d_moments(const LatticeDev &L, const double *__restrict__ nref,
-                                        const TF *__restrict__ f, const Fields<TM> &fld, int z, int r)
+                                        const TF *__restrict__ f, const Fields<TM> &fld, int z, int r,
+                                        bool write_n = true)
 {
     const int id = z * L.plane + r;
     double n = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
@@ -250,7 +251,7 @@ __device__ __forceinline__ TM d_moments(const LatticeDev &L, const double *__res
             if (CZ[i] < 0) jz -= fi;
         }
     }
-    store_padded(L, fld.n, r, z, (TM)n);
+    if (write_n) store_padded(L, fld.n, r, z, (TM)n);
     store_padded4(L, fld.nj, r, z, (TM)n, (TM)jx, (TM)jy, (TM)jz);
     return (TM)n;
 }
@@ -274,12 +275,13 @@ __device__ __forceinline__ void block_rowsums(const LatticeDev &L, const TM *sn,
 
 template <int SIG, typename TF, typename TM>
 __global__ __launch_bounds__(256) void k_moments_rs(LatticeDev L, const double *__restrict__ nref,
-                                                    const TF *__restrict__ f, Fields<TM> fld, TM *__restrict__ rs)
+                                                    const TF *__restrict__ f, Fields<TM> fld, TM *__restrict__ rs,
+                                                    int write_n)
 {
     __shared__ TM sn[256];
     const int r = blockIdx.x * 256 + threadIdx.x;
     const int z = (int)blockIdx.y;
-    sn[threadIdx.x] = d_moments(L, nref, f, fld, z, r);
+    sn[threadIdx.x] = d_moments(L, nref, f, fld, z, r, write_n != 0);
     __syncthreads();
     block_rowsums<SIG>(L, sn, rs, z, r);
 }
@@ -2408,18 +2410,18 @@ hipError_t launch_smooth2(hipStream_t s, const LatticeDev &L, int sigma, double 
 
 template <typename TF, typename TM>
 hipError_t launch_moments_rs(hipStream_t s, const LatticeDev &L, int sigma, const double *nref, const TF *f,
-                             Fields<TM> fld, TM *rs)
+                             Fields<TM> fld, TM *rs, bool write_n)
 {
     if (256 % L.nx != 0 || L.plane % 256 != 0) return hipErrorInvalidValue;
     const dim3 g(L.plane / 256, L.nz), b(256);
     switch (sigma) {
-    case 2: hipLaunchKernelGGL((k_moments_rs<2, TF, TM>), g, b, 0, s, L, nref, f, fld, rs); break;
-    case 3: hipLaunchKernelGGL((k_moments_rs<3, TF, TM>), g, b, 0, s, L, nref, f, fld, rs); break;
-    case 4: hipLaunchKernelGGL((k_moments_rs<4, TF, TM>), g, b, 0, s, L, nref, f, fld, rs); break;
-    case 5: hipLaunchKernelGGL((k_moments_rs<5, TF, TM>), g, b, 0, s, L, nref, f, fld, rs); break;
-    case 6: hipLaunchKernelGGL((k_moments_rs<6, TF, TM>), g, b, 0, s, L, nref, f, fld, rs); break;
-    case 7: hipLaunchKernelGGL((k_moments_rs<7, TF, TM>), g, b, 0, s, L, nref, f, fld, rs); break;
-    case 8: hipLaunchKernelGGL((k_moments_rs<8, TF, TM>), g, b, 0, s, L, nref, f, fld, rs); break;
+    case 2: hipLaunchKernelGGL((k_moments_rs<2, TF, TM>), g, b, 0, s, L, nref, f, fld, rs, (int)write_n); break;
+    case 3: hipLaunchKernelGGL((k_moments_rs<3, TF, TM>), g, b, 0, s, L, nref, f, fld, rs, (int)write_n); break;
+    case 4: hipLaunchKernelGGL((k_moments_rs<4, TF, TM>), g, b, 0, s, L, nref, f, fld, rs, (int)write_n); break;
+    case 5: hipLaunchKernelGGL((k_moments_rs<5, TF, TM>), g, b, 0, s, L, nref, f, fld, rs, (int)write_n); break;
+    case 6: hipLaunchKernelGGL((k_moments_rs<6, TF, TM>), g, b, 0, s, L, nref, f, fld, rs, (int)write_n); break;
+    case 7: hipLaunchKernelGGL((k_moments_rs<7, TF, TM>), g, b, 0, s, L, nref, f, fld, rs, (int)write_n); break;
+    case 8: hipLaunchKernelGGL((k_moments_rs<8, TF, TM>), g, b, 0, s, L, nref, f, fld, rs, (int)write_n); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -2645,7 +2647,7 @@ hipError_t launch_batch_profiles(hipStream_t s, const SlitDesc *desc, const Work
     template hipError_t launch_moments<TF, TM>(hipStream_t, const LatticeDev &, const double *, const TF *, \
                                                Fields<TM>);                                                 \
     template hipError_t launch_moments_rs<TF, TM>(hipStream_t, const LatticeDev &, int, const double *,      \
-                                                  const TF *, Fields<TM>, TM *);                            \
+                                                  const TF *, Fields<TM>, TM *, bool);                      \
     template hipError_t launch_collide<TF, TM>(hipStream_t, const LatticeDev &, int, const StepConst &,    \
                                                const double *, const TF *, TF *, Fields<TM>, bool);         \
     template hipError_t launch_force<TF, TM>(hipStream_t, const LatticeDev &, int, const StepConst &,      \
