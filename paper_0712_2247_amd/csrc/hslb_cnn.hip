@@ -218,28 +218,45 @@ __device__ __forceinline__ void stage_tile(const Geo &g, const uint16_t *__restr
     }
 }
 
-// A operand of K-step s for row r of wave w (node x0 + li of the tile).
+// Tap offsets of the A operands of k_conv_fwd, in tile nodes relative to the
+// lane's node, per K-step s and lane group lg: CIN 1, taps 32 s + 8 lg + e
+// (e = 0..7); CIN 4, taps 8 s + 2 lg + q (q = 0, 1).  Taps past the last read
+// the node itself against zero weights.  A lane reads its step's offsets with
+// one or two 16-byte loads instead of dividing each tap index by 5 and 25.
+struct FwdTapOffsets {
+    uint32_t c1[4][4][8];
+    uint32_t c4[16][4][4];  // q = 0, 1 used; padded to 16 bytes
+};
+constexpr uint32_t tap_node(int t) { return t < NT ? (uint32_t)lnode(t % 5, (t / 5) % 5, t / 25) : 0u; }
+constexpr FwdTapOffsets make_fwd_tap_offsets()
+{
+    FwdTapOffsets o{};
+    for (int s = 0; s < 4; ++s)
+        for (int lg = 0; lg < 4; ++lg)
+            for (int e = 0; e < 8; ++e) o.c1[s][lg][e] = tap_node(32 * s + 8 * lg + e);
+    for (int s = 0; s < 16; ++s)
+        for (int lg = 0; lg < 4; ++lg)
+            for (int q = 0; q < 2; ++q) o.c4[s][lg][q] = tap_node(8 * s + 2 * lg + q);
+    return o;
+}
+__constant__ FwdTapOffsets c_fwd_taps = make_fwd_tap_offsets();
+
+// A operand of K-step s for the lane's node `node` (tile index of row r) from
+// the step's tap offsets.
 template <int CIN>
-__device__ __forceinline__ u32x4 lds_a(const uint16_t *tile, int s, int li, int w, int r, int lg)
+__device__ __forceinline__ u32x4 lds_a(const uint16_t *tile, int node, const uint32_t (&off)[8])
 {
     u32x4 v = {0u, 0u, 0u, 0u};
     if constexpr (CIN == 4) {
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            const int t = 8 * s + 2 * lg + q;
-            if (t < NT) {
-                const u32x2 w2 = ((const u32x2 *)tile)[lnode(li + t % 5, w + (t / 5) % 5, r + t / 25)];
-                v[2 * q] = w2[0];
-                v[2 * q + 1] = w2[1];
-            }
+            const u32x2 w2 = ((const u32x2 *)tile)[node + off[q]];
+            v[2 * q] = w2[0];
+            v[2 * q + 1] = w2[1];
         }
     } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int t = 32 * s + 8 * lg + e;
-            const uint32_t h = t < NT ? tile[lnode(li + t % 5, w + (t / 5) % 5, r + t / 25)] : 0u;
-            v[e >> 1] |= h << (16 * (e & 1));
-        }
+        for (int e = 0; e < 8; ++e) v[e >> 1] |= (uint32_t)tile[node + off[e]] << (16 * (e & 1));
     }
     return v;
 }
@@ -339,9 +356,24 @@ __global__ __launch_bounds__(256) void k_conv_fwd(FwdArgs a)
         for (int q = 0; q < PD; ++q) {
             const int s = s0 + q;
             if (s < KS) {
+                uint32_t off[8];
+                if constexpr (CIN == 1) {
+                    const u32x4 o0 = *(const u32x4 *)&c_fwd_taps.c1[s][lg][0];
+                    const u32x4 o1 = *(const u32x4 *)&c_fwd_taps.c1[s][lg][4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        off[e] = o0[e];
+                        off[4 + e] = o1[e];
+                    }
+                } else {
+                    const u32x4 o0 = *(const u32x4 *)&c_fwd_taps.c4[s][lg][0];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) off[e] = o0[e];
+                    off[4] = off[5] = off[6] = off[7] = 0u;
+                }
                 bf16x8 av[ROWS], bw[NH];
 #pragma unroll
-                for (int r = 0; r < ROWS; ++r) av[r] = as_bf(lds_a<CIN>(tile, s, li, w, r, lg));
+                for (int r = 0; r < ROWS; ++r) av[r] = as_bf(lds_a<CIN>(tile, lnode(li, w, r), off));
 #pragma unroll
                 for (int h = 0; h < NH; ++h) {
                     bw[h] = as_bf(bq[q][h]);
