@@ -146,6 +146,27 @@ __device__ __forceinline__ void store_padded4(const LatticeDev &L, TM *dst, int 
     for (; p < L.nz + 2 * L.hz; p += L.nz) store4(dst + 4 * ((size_t)rem + (size_t)L.plane * p), a, b, c, d);
 }
 
+// store_padded4 with non-temporal stores.
+template <typename TM>
+__device__ __forceinline__ void store_padded4_nt(const LatticeDev &L, TM *dst, int rem, int z, TM a, TM b, TM c,
+                                                 TM d)
+{
+    auto st = [&](int p) {
+        TM *q = dst + 4 * ((size_t)rem + (size_t)L.plane * p);
+        __builtin_nontemporal_store(a, q);
+        __builtin_nontemporal_store(b, q + 1);
+        __builtin_nontemporal_store(c, q + 2);
+        __builtin_nontemporal_store(d, q + 3);
+    };
+    if (!L.zper) {
+        st(z + L.hz);
+        return;
+    }
+    int p = z + L.hz;
+    while (p - L.nz >= 0) p -= L.nz;
+    for (; p < L.nz + 2 * L.hz; p += L.nz) st(p);
+}
+
 __device__ __forceinline__ bool is_fluid_z(const LatticeDev &L, int z)
 {
     return L.zper || (z >= L.wall_lo && z < L.nz - L.wall_hi);
@@ -233,7 +254,7 @@ __global__ __launch_bounds__(256) void k_layer_means(LatticeDev L, const TF *__r
 template <typename TF, typename TM>
 __device__ __forceinline__ TM d_moments(const LatticeDev &L, const double *__restrict__ nref,
                                         const TF *__restrict__ f, const Fields<TM> &fld, int z, int r,
-                                        bool write_n = true)
+                                        bool write_n = true, bool nt = false)
 {
     const int id = z * L.plane + r;
     double n = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
@@ -252,7 +273,10 @@ __device__ __forceinline__ TM d_moments(const LatticeDev &L, const double *__res
         }
     }
     if (write_n) store_padded(L, fld.n, r, z, (TM)n);
-    store_padded4(L, fld.nj, r, z, (TM)n, (TM)jx, (TM)jy, (TM)jz);
+    if (nt)
+        store_padded4_nt(L, fld.nj, r, z, (TM)n, (TM)jx, (TM)jy, (TM)jz);
+    else
+        store_padded4(L, fld.nj, r, z, (TM)n, (TM)jx, (TM)jy, (TM)jz);
     return (TM)n;
 }
 
@@ -271,19 +295,20 @@ __global__ __launch_bounds__(256) void k_moments(LatticeDev L, const double *__r
 // They are written at the padded layer of z and, for a periodic z axis, at
 // its images within the padded range the ball sum reads, [hz - R, nz + hz + R).
 template <int SIG, typename TM>
-__device__ __forceinline__ void block_rowsums(const LatticeDev &L, const TM *sn, TM *__restrict__ rs, int z, int r);
+__device__ __forceinline__ void block_rowsums(const LatticeDev &L, const TM *sn, TM *__restrict__ rs, int z, int r,
+                                              bool nt = false);
 
 template <int SIG, typename TF, typename TM>
 __global__ __launch_bounds__(256) void k_moments_rs(LatticeDev L, const double *__restrict__ nref,
                                                     const TF *__restrict__ f, Fields<TM> fld, TM *__restrict__ rs,
-                                                    int write_n)
+                                                    int write_n, int nt)
 {
     __shared__ TM sn[256];
     const int r = blockIdx.x * 256 + threadIdx.x;
     const int z = (int)blockIdx.y;
-    sn[threadIdx.x] = d_moments(L, nref, f, fld, z, r, write_n != 0);
+    sn[threadIdx.x] = d_moments(L, nref, f, fld, z, r, write_n != 0, nt != 0);
     __syncthreads();
-    block_rowsums<SIG>(L, sn, rs, z, r);
+    block_rowsums<SIG>(L, sn, rs, z, r, nt != 0);
 }
 
 // Row sums rs[w], w = 0..R, of node r of layer z from the block's densities in
@@ -291,7 +316,8 @@ __global__ __launch_bounds__(256) void k_moments_rs(LatticeDev L, const double *
 // of z and, for a periodic z axis, at its images within the padded range the
 // ball sum reads, [hz - R, nz + hz + R).
 template <int SIG, typename TM>
-__device__ __forceinline__ void block_rowsums(const LatticeDev &L, const TM *sn, TM *__restrict__ rs, int z, int r)
+__device__ __forceinline__ void block_rowsums(const LatticeDev &L, const TM *sn, TM *__restrict__ rs, int z, int r,
+                                              bool nt)
 {
     constexpr int R = SIG / 2;
     const int x = (int)threadIdx.x % L.nx;
@@ -308,7 +334,12 @@ __device__ __forceinline__ void block_rowsums(const LatticeDev &L, const TM *sn,
     for (int p = p0; p <= p1; p += L.nz) {
         const size_t q = (size_t)r + (size_t)L.plane * p;
 #pragma unroll
-        for (int w = 0; w <= R; ++w) rs[(size_t)w * L.fld_stride + q] = acc[w];
+        for (int w = 0; w <= R; ++w) {
+            if (nt)
+                __builtin_nontemporal_store(acc[w], rs + (size_t)w * L.fld_stride + q);
+            else
+                rs[(size_t)w * L.fld_stride + q] = acc[w];
+        }
     }
 }
 
@@ -411,8 +442,8 @@ __device__ __forceinline__ T g2_t(double eta, int model)
     }
 }
 
-#ifndef HSLB_GFIELD_NT_MIB
-#define HSLB_GFIELD_NT_MIB 256
+#ifndef HSLB_NT_FIELD_MIB
+#define HSLB_NT_FIELD_MIB 256
 #endif
 // Node r (0 <= r < plane) of layer z.  NT: non-temporal stores, for contact
 // values that overflow the 256 MiB last-level cache on their own (256^3 bulk,
@@ -2414,14 +2445,17 @@ hipError_t launch_moments_rs(hipStream_t s, const LatticeDev &L, int sigma, cons
 {
     if (256 % L.nx != 0 || L.plane % 256 != 0) return hipErrorInvalidValue;
     const dim3 g(L.plane / 256, L.nz), b(256);
+    // (n, j) and the row sums beyond the 256 MiB last-level cache are stored
+    // non-temporally, as the contact values are (256^3 bulk: 282 MB each)
+    const int nt = 4.0 * sizeof(TM) * (double)L.fld_stride > HSLB_NT_FIELD_MIB * 1024.0 * 1024.0 ? 1 : 0;
     switch (sigma) {
-    case 2: hipLaunchKernelGGL((k_moments_rs<2, TF, TM>), g, b, 0, s, L, nref, f, fld, rs, (int)write_n); break;
-    case 3: hipLaunchKernelGGL((k_moments_rs<3, TF, TM>), g, b, 0, s, L, nref, f, fld, rs, (int)write_n); break;
-    case 4: hipLaunchKernelGGL((k_moments_rs<4, TF, TM>), g, b, 0, s, L, nref, f, fld, rs, (int)write_n); break;
-    case 5: hipLaunchKernelGGL((k_moments_rs<5, TF, TM>), g, b, 0, s, L, nref, f, fld, rs, (int)write_n); break;
-    case 6: hipLaunchKernelGGL((k_moments_rs<6, TF, TM>), g, b, 0, s, L, nref, f, fld, rs, (int)write_n); break;
-    case 7: hipLaunchKernelGGL((k_moments_rs<7, TF, TM>), g, b, 0, s, L, nref, f, fld, rs, (int)write_n); break;
-    case 8: hipLaunchKernelGGL((k_moments_rs<8, TF, TM>), g, b, 0, s, L, nref, f, fld, rs, (int)write_n); break;
+    case 2: hipLaunchKernelGGL((k_moments_rs<2, TF, TM>), g, b, 0, s, L, nref, f, fld, rs, (int)write_n, nt); break;
+    case 3: hipLaunchKernelGGL((k_moments_rs<3, TF, TM>), g, b, 0, s, L, nref, f, fld, rs, (int)write_n, nt); break;
+    case 4: hipLaunchKernelGGL((k_moments_rs<4, TF, TM>), g, b, 0, s, L, nref, f, fld, rs, (int)write_n, nt); break;
+    case 5: hipLaunchKernelGGL((k_moments_rs<5, TF, TM>), g, b, 0, s, L, nref, f, fld, rs, (int)write_n, nt); break;
+    case 6: hipLaunchKernelGGL((k_moments_rs<6, TF, TM>), g, b, 0, s, L, nref, f, fld, rs, (int)write_n, nt); break;
+    case 7: hipLaunchKernelGGL((k_moments_rs<7, TF, TM>), g, b, 0, s, L, nref, f, fld, rs, (int)write_n, nt); break;
+    case 8: hipLaunchKernelGGL((k_moments_rs<8, TF, TM>), g, b, 0, s, L, nref, f, fld, rs, (int)write_n, nt); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -2448,7 +2482,7 @@ template <typename TM>
 hipError_t launch_gfield(hipStream_t s, const LatticeDev &L, int g2_model, Fields<TM> fld)
 {
     const double g_bytes = 7.0 * (double)L.fld_stride * sizeof(TM);
-    if (g_bytes > HSLB_GFIELD_NT_MIB * 1024.0 * 1024.0)
+    if (g_bytes > HSLB_NT_FIELD_MIB * 1024.0 * 1024.0)
         hipLaunchKernelGGL((k_gfield<TM, true>), dim3(blocks_for(L.plane), L.nz), dim3(256), 0, s, L, g2_model, fld);
     else
         hipLaunchKernelGGL((k_gfield<TM, false>), dim3(blocks_for(L.plane), L.nz), dim3(256), 0, s, L, g2_model, fld);
