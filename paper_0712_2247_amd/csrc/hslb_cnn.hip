@@ -56,14 +56,23 @@ __device__ __forceinline__ float bf2f(uint32_t h) { return __uint_as_float(h << 
 // and E = u P(u) with u = 1/(1 + 0.3 t) and P the degree-9 polynomial of
 // gen_phi_poly.py (relative error of the fit 3.5e-9 on [0, 16]);
 // Phi(z) = 1 - Phi(-z) for z > 0.  z^2 is split exactly (FMA), so that g keeps
-// its relative accuracy far in the tail: the result is good to about 6e-7
-// relative also for z << 0 (where 1 + erf(z / sqrt 2) would cancel), with
-// half the instructions of erfcf.
+// its relative accuracy far in the tail, and the Gaussian is the hardware
+// base-2 exponential of c z^2 with the product's rounding carried to first
+// order: the result is good to about 6e-7 relative also for z << 0 (where
+// 1 + erf(z / sqrt 2) would cancel), with well under half the instructions of
+// erfcf.  For z < -13 the Gaussian leaves the normal range (the caller takes
+// the reference form there).
 __device__ __forceinline__ float phi_cdf_fast(float z, float &g)
 {
     const float t = fabsf(z);
     const float q = z * z;
-    g = expf(-0.5f * q) * fmaf(-0.5f, fmaf(z, z, -q), 1.0f);
+    // g = 2^(c z^2), c = -log2(e) / 2 = CH + CL, z^2 = q + ql: x = q CH rounded, the
+    // rest xl = c z^2 - x goes in to first order, g = 2^x (1 + ln2 xl)
+    constexpr float CH = -0.7213475108146667f, CL = -9.629815167500055e-09f;
+    const float ql = fmaf(z, z, -q);
+    const float x = q * CH;
+    const float xl = fmaf(q, CH, -x) + fmaf(q, CL, ql * CH);
+    g = __builtin_amdgcn_exp2f(x) * fmaf(xl, 0.69314718055994531f, 1.0f);
     const float u = __builtin_amdgcn_rcpf(fmaf(0.3f, t, 1.0f));
     float p = -0.04126075655221939f;
     p = fmaf(p, u, 0.22495317459106445f);
@@ -103,7 +112,7 @@ __device__ __forceinline__ uint32_t gelu_bf16(float z)
 {
     float g;
     float v = z * phi_cdf_fast(z, g);
-    if (near_bf16_tie(v)) v = gelu_ref(z);
+    if (near_bf16_tie(v) || z < -13.0f) v = gelu_ref(z);
     return f2bf(v);
 }
 
