@@ -45,6 +45,18 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
     return x * q + (x < rm ? x : rm) + slot;
 }
 
+// The other bijection for a grid of (layer, chunk) blocks, layers * cpp of
+// them with cpp (chunks per layer) a multiple of 8: XCD x takes chunks
+// [x cpp/8, (x+1) cpp/8) of every layer, layer by layer, so that all XCDs move
+// through z together and each keeps a narrow band of the layers in its L2.
+// Returns the block's layer zl and chunk c.
+__device__ __forceinline__ void xcd_band(int b, int cpp, int &zl, int &c)
+{
+    const int x = b & 7, slot = b >> 3, bw = cpp >> 3;
+    zl = slot / bw;
+    c = x * bw + (slot - zl * bw);
+}
+
 // Geometry of one lattice as the kernels see it.
 //  - populations: [19][pop_stride], node = x + nx*(y + ny*z), z in [0, nz)
 //  - padded fields (n, j, eta_bar, G): [.. ][fld_stride] with hz ghost/zero

@@ -1126,8 +1126,10 @@ __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &
 
 // 1-D grid over (layer, chunk of 256 nodes of the layer): z is uniform over a
 // block, so the rows of the storage reference tables come in through scalar
-// loads.  MASK: the solid-mask code is compiled in (a separate instance, so
-// that the plain path keeps its registers).
+// loads.  band: blocks go to the XCDs by xcd_band (each XCD sweeps one eighth
+// of every layer, all layers together) instead of xcd_block (each XCD sweeps
+// whole layers of its own z slab).  MASK: the solid-mask code is compiled in (a
+// separate instance, so that the plain path keeps its registers).
 // NT: populations loaded and stored non-temporally, for lattices whose two
 // population copies overflow the last-level cache (256^3 bulk: 1603 -> 1539 us);
 // the cache-resident benchmark slit gains nothing from it.  That instance also
@@ -1137,11 +1139,16 @@ __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &
 template <int SIG, typename TF, typename TM, bool MASK, bool NT>
 __global__ __launch_bounds__(256, HSLB_COLLIDE_WAVES) void k_collide(LatticeDev L, StepConst sc, const double *__restrict__ chi,
                                                  const TF *__restrict__ fin, TF *__restrict__ fout,
-                                                 Fields<TM> fld, int cpp)
+                                                 Fields<TM> fld, int cpp, int band)
 {
-    const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
-    const int zl = lb / cpp;
-    const int c = lb - zl * cpp;
+    int zl, c;
+    if (band) {
+        xcd_band((int)blockIdx.x, cpp, zl, c);
+    } else {
+        const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+        zl = lb / cpp;
+        c = lb - zl * cpp;
+    }
     const int r = c * 256 + threadIdx.x;
     const int z = (L.zper ? 0 : L.wall_lo) + zl;
     if (r < L.plane) d_collide<SIG, !NT, TF, TM, MASK, NT>(L, sc, chi, fin, fout, fld, z, r);
@@ -2491,7 +2498,7 @@ hipError_t launch_gfield(hipStream_t s, const LatticeDev &L, int g2_model, Field
 
 template <typename TF, typename TM, bool M, bool NT>
 hipError_t launch_collide_t(hipStream_t s, int sigma, dim3 g, dim3 b, const LatticeDev &L, const StepConst &c,
-                            const double *chi, const TF *fin, TF *fout, Fields<TM> fld, int cpp);
+                            const double *chi, const TF *fin, TF *fout, Fields<TM> fld, int cpp, int band);
 
 bool collide_tiles_apply(const LatticeDev &L, int sigma, const StepConst &c, bool fp32)
 {
@@ -2533,7 +2540,13 @@ hipError_t launch_collide(hipStream_t s, const LatticeDev &L, int sigma, const S
     const int layers = L.zper ? L.nz : L.nz - L.wall_lo - L.wall_hi;
     const int cpp = (int)blocks_for(L.plane);
     const dim3 g(cpp * layers), b(256);
-    if (c.links) return launch_collide_t<TF, TM, true, false>(s, sigma, g, b, L, c, chi, fin, fout, fld, cpp);
+    // Bands of the layer per XCD once a band spans at least two shell
+    // diameters in y: 256^3 bulk (sigma 6, 32-row bands) 1486 -> 1399 us,
+    // 128 x 128 slit (sigma 8, 16 rows) 338 -> 320 us; the 64 x 64 slit
+    // (sigma 8, 8-row bands) keeps z slabs, 39.6 against 41.9 us.  Splitting
+    // each band's layers over 2 or 4 XCDs (wider bands) measured in between.
+    const int band = (cpp % 8 == 0 && L.ny >= 16 * sigma) ? 1 : 0;
+    if (c.links) return launch_collide_t<TF, TM, true, false>(s, sigma, g, b, L, c, chi, fin, fout, fld, cpp, band);
     // populations beyond the last-level cache (two copies over 128 MiB) stream
     // non-temporally
     const double pop_bytes = 2.0 * NQ * (double)L.pop_stride * sizeof(TF);
@@ -2542,23 +2555,23 @@ hipError_t launch_collide(hipStream_t s, const LatticeDev &L, int sigma, const S
             return launch_collide_tiles(s, sigma, layers, pop_bytes > 128.0 * 1024 * 1024, L, c, chi, fin, fout, fld);
     }
     if (pop_bytes > 128.0 * 1024 * 1024)
-        return launch_collide_t<TF, TM, false, true>(s, sigma, g, b, L, c, chi, fin, fout, fld, cpp);
-    return launch_collide_t<TF, TM, false, false>(s, sigma, g, b, L, c, chi, fin, fout, fld, cpp);
+        return launch_collide_t<TF, TM, false, true>(s, sigma, g, b, L, c, chi, fin, fout, fld, cpp, band);
+    return launch_collide_t<TF, TM, false, false>(s, sigma, g, b, L, c, chi, fin, fout, fld, cpp, band);
 }
 
 template <typename TF, typename TM, bool M, bool NT>
 hipError_t launch_collide_t(hipStream_t s, int sigma, dim3 g, dim3 b, const LatticeDev &L, const StepConst &c,
-                            const double *chi, const TF *fin, TF *fout, Fields<TM> fld, int cpp)
+                            const double *chi, const TF *fin, TF *fout, Fields<TM> fld, int cpp, int band)
 {
     switch (sigma) {
-    case 0: hipLaunchKernelGGL((k_collide<0, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
-    case 2: hipLaunchKernelGGL((k_collide<2, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
-    case 3: hipLaunchKernelGGL((k_collide<3, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
-    case 4: hipLaunchKernelGGL((k_collide<4, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
-    case 5: hipLaunchKernelGGL((k_collide<5, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
-    case 6: hipLaunchKernelGGL((k_collide<6, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
-    case 7: hipLaunchKernelGGL((k_collide<7, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
-    case 8: hipLaunchKernelGGL((k_collide<8, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); break;
+    case 0: hipLaunchKernelGGL((k_collide<0, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
+    case 2: hipLaunchKernelGGL((k_collide<2, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
+    case 3: hipLaunchKernelGGL((k_collide<3, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
+    case 4: hipLaunchKernelGGL((k_collide<4, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
+    case 5: hipLaunchKernelGGL((k_collide<5, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
+    case 6: hipLaunchKernelGGL((k_collide<6, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
+    case 7: hipLaunchKernelGGL((k_collide<7, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
+    case 8: hipLaunchKernelGGL((k_collide<8, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -42,6 +42,10 @@ ROW_CASES = [
     (16, 16, 12, 2, 0), (32, 8, 14, 3, 2), (16, 32, 16, 4, 2), (32, 16, 12, 5, 0),
     (32, 16, 20, 6, 3), (16, 16, 22, 7, 4), (32, 32, 24, 8, 4), (64, 12, 14, 8, 0),
 ]
+# Grids whose collide blocks are dealt to the XCDs in y bands of every layer (a
+# multiple of 8 chunks per layer and ny >= 16 sigma); the second has a partial
+# last chunk in each layer.
+BAND_CASES = [(32, 64, 12, 3, 2), (30, 66, 10, 4, 2), (64, 32, 10, 2, 0)]
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c)))
@@ -74,7 +78,7 @@ def test_force_fp32_storage(case):
     assert np.abs(F_g - F_o).max() <= 2e-6 * np.abs(F_o).max()
 
 
-@pytest.mark.parametrize("case", CASES + ROW_CASES, ids=lambda c: "x".join(map(str, c)))
+@pytest.mark.parametrize("case", CASES + ROW_CASES + BAND_CASES, ids=lambda c: "x".join(map(str, c)))
 def test_steps_fp64(case):
     nx, ny, nz, sigma, walls = case
     nb = workloads.number_density(0.25, sigma)
