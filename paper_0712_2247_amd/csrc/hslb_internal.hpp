@@ -46,7 +46,8 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
 }
 
 // The other bijection for a grid of (layer, chunk) blocks, layers * cpp of
-// them with cpp (chunks per layer) a multiple of 8: XCD x takes chunks
+// them with cpp (chunks per layer) a multiple of 8, b the linear block index
+// (a 2-D grid (cpp, layers) passes blockIdx.x + cpp * blockIdx.y): XCD x takes chunks
 // [x cpp/8, (x+1) cpp/8) of every layer, layer by layer, so that all XCDs move
 // through z together and each keeps a narrow band of the layers in its L2.
 // Returns the block's layer zl and chunk c.

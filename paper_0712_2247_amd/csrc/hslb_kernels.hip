@@ -409,13 +409,19 @@ __device__ __forceinline__ void d_ballsum(const LatticeDev &L, double eta_pref, 
     store_padded(L, fld.eb, r, z, (TM)(eta_pref * s));
 }
 
-// grid (ceil(plane / 256), nz)
+// grid (ceil(plane / 256), nz).  With a multiple of 8 chunks per layer the
+// blocks go to the XCDs in y bands (xcd_band) rather than round-robin by row,
+// so that the +-R rows a block reads sit in its own XCD's L2: 256^3 bulk 135 ->
+// 130 us, and the contact values that read eta_bar next 141 -> 132 us.  The
+// same order for the contact-value kernel itself gained nothing further.
 template <int SIG, typename TM>
 __global__ __launch_bounds__(256) void k_ballsum(LatticeDev L, double eta_pref, Fields<TM> fld,
                                                  const TM *__restrict__ rs)
 {
-    const int r = blockIdx.x * 256 + threadIdx.x;
-    if (r < L.plane) d_ballsum<SIG>(L, eta_pref, fld, rs, (int)blockIdx.y, r);
+    int z = (int)blockIdx.y, c = (int)blockIdx.x;
+    if ((gridDim.x & 7) == 0) xcd_band((int)(blockIdx.x + gridDim.x * blockIdx.y), (int)gridDim.x, z, c);
+    const int r = c * 256 + threadIdx.x;
+    if (r < L.plane) d_ballsum<SIG>(L, eta_pref, fld, rs, z, r);
 }
 
 // ------------------------------------------ contact values at pair midpoints
