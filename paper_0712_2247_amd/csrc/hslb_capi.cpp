@@ -1472,10 +1472,12 @@ public:
         std::vector<double> chi_all;
         int64_t pop = 0, fld = 0, prof = 0;
         int maxR = 0;
+        rows16_ = ns > 0;
         for (int k = 0; k < ns; ++k) {
             SlitDesc &d = desc_[k];
             std::vector<double> chi;
             slit_consts(p_[k], d.L, d.sc, chi);
+            rows16_ = rows16_ && d.L.nx == 16;
             d.sigma = p_[k].sigma >= 2 ? p_[k].sigma : 2;
             maxR = std::max(maxR, d.sigma / 2);
             d.pop_off = (int)pop;
@@ -1677,7 +1679,8 @@ public:
             HIP_TRY(hipEventRecord(a, st()));
         }
         const unsigned grid = (unsigned)std::max(1, std::min(nw, ncu_ * cgrid_per_cu_));
-        HIP_TRY(launch_batch_collide<TF, TM>(st(), grid, desc_d_, wf, nw, f_[cur_], f_[1 - cur_], fld_, chi_d_));
+        HIP_TRY(launch_batch_collide<TF, TM>(st(), grid, desc_d_, wf, nw, f_[cur_], f_[1 - cur_], fld_, chi_d_,
+                                             rows16_));
         if (a) {
             HIP_TRY(hipEventRecord(b, st()));
             kt.pending.push_back({"b_collide", {(int)kt.used - 2, (int)kt.used - 1}});
@@ -2058,6 +2061,7 @@ public:
 
 private:
     std::vector<hslb_params> p_;
+    bool rows16_ = false;  // every slit 16 nodes wide in x (see launch_batch_collide)
     std::vector<SlitDesc> desc_;
     std::vector<WorkItem> wl_nodes_, wl_rows_, wl_fluid_, wl_prof_;
     std::vector<int> prof_off_;

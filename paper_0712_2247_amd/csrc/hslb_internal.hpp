@@ -250,10 +250,12 @@ template <typename TF, typename TM>
 hipError_t launch_batch_phase(hipStream_t s, int phase, unsigned grid, const SlitDesc *desc,
                               const WorkItem *work, int nwork, const TF *fin, TF *fout, Fields<TM> fld,
                               TM *rs, const double *chi);
-// Collide phase of every slit: work holds the fluid items.
+// Collide phase of every slit: work holds the fluid items.  rows16: every slit
+// is 16 nodes wide in x (the shell sum then shares x-neighbour reads between
+// the lanes of each 16-lane row).
 template <typename TF, typename TM>
 hipError_t launch_batch_collide(hipStream_t s, unsigned grid, const SlitDesc *desc, const WorkItem *work, int nwork,
-                                const TF *fin, TF *fout, Fields<TM> fld, const double *chi);
+                                const TF *fin, TF *fout, Fields<TM> fld, const double *chi, bool rows16);
 // Layer profiles of every slit: items (slit, z); out holds 5 rows per slit
 // layer at prof_off[slit] (n_z, u_z[3], sum n).
 template <typename TF>

@@ -535,36 +535,49 @@ __device__ __forceinline__ TC s_dot_j(const TM q[4])
     }
 }
 
+// The contact values G+ (midpoint of (r, r+d)) and G- (midpoint of (r, r-d))
+// of one mirrored lattice pair, addressed as load_pair does.
+template <int DX, int DY, int DZ, bool LZ, typename TM>
+__device__ __forceinline__ void load_gpair(const Fields<TM> &F, const LatticeDev &L, int x, int y, int zp, TM &Gp,
+                                           TM &Gm)
+{
+    constexpr int SLOT = (DX & 1) | ((DY & 1) << 1) | ((DZ & 1) << 2);
+    constexpr int BXP = floordiv2(DX), BYP = floordiv2(DY), BZP = floordiv2(DZ);
+    constexpr int BXM = floordiv2(-DX), BYM = floordiv2(-DY), BZM = floordiv2(-DZ);
+    if constexpr (LZ) {
+        constexpr int GB = (int)sizeof(TM);
+        const size_t lay = (size_t)L.plane;
+        const char *gs = (const char *)F.G + GB * (size_t)SLOT * L.fld_stride;
+        const char *gzp = gs + GB * lay * (size_t)(zp + BZP);
+        const char *gzm = gs + GB * lay * (size_t)(zp + BZM);
+        Gp = *(const TM *)(gzp + (xb<BXP, GB>(x, L.nx) + yb<BYP, GB>(y, L.ny, L.nx)));
+        Gm = *(const TM *)(gzm + (xb<BXM, GB>(x, L.nx) + yb<BYM, GB>(y, L.ny, L.nx)));
+    } else {
+        const size_t fs = L.fld_stride;
+        const int gp = wrapc<BXP>(x, L.nx) + L.nx * (wrapc<BYP>(y, L.ny) + L.ny * (zp + BZP));
+        const int gm = wrapc<BXM>(x, L.nx) + L.nx * (wrapc<BYM>(y, L.ny) + L.ny * (zp + BZM));
+        Gp = F.G[SLOT * fs + gp];
+        Gm = F.G[SLOT * fs + gm];
+    }
+}
+
 // Loads of one mirrored lattice pair: the contact values G+ (midpoint of
 // (r, r+d)) and G- (midpoint of (r, r-d)) and the (n, j) of r+d and r-d.
 template <int DX, int DY, int DZ, bool LZ, typename TM>
 __device__ __forceinline__ void load_pair(const Fields<TM> &F, const LatticeDev &L, int x, int y, int zp, TM &Gp,
                                           TM &Gm, TM qp[4], TM qm[4])
 {
-    constexpr int SLOT = (DX & 1) | ((DY & 1) << 1) | ((DZ & 1) << 2);
-    constexpr int BXP = floordiv2(DX), BYP = floordiv2(DY), BZP = floordiv2(DZ);
-    constexpr int BXM = floordiv2(-DX), BYM = floordiv2(-DY), BZM = floordiv2(-DZ);
+    load_gpair<DX, DY, DZ, LZ>(F, L, x, y, zp, Gp, Gm);
     if constexpr (LZ) {
         constexpr int NJB = 4 * (int)sizeof(TM);  // bytes of one (n, j) entry
-        constexpr int GB = (int)sizeof(TM);
         const size_t lay = (size_t)L.plane;
         const char *njp = (const char *)F.nj + NJB * lay * (size_t)(zp + DZ);
         const char *njm = (const char *)F.nj + NJB * lay * (size_t)(zp - DZ);
-        const char *gs = (const char *)F.G + GB * (size_t)SLOT * L.fld_stride;
-        const char *gzp = gs + GB * lay * (size_t)(zp + BZP);
-        const char *gzm = gs + GB * lay * (size_t)(zp + BZM);
-        Gp = *(const TM *)(gzp + (xb<BXP, GB>(x, L.nx) + yb<BYP, GB>(y, L.ny, L.nx)));
-        Gm = *(const TM *)(gzm + (xb<BXM, GB>(x, L.nx) + yb<BYM, GB>(y, L.ny, L.nx)));
         load4((const TM *)(njp + (xb<DX, NJB>(x, L.nx) + yb<DY, NJB>(y, L.ny, L.nx))), qp);
         load4((const TM *)(njm + (xb<-DX, NJB>(x, L.nx) + yb<-DY, NJB>(y, L.ny, L.nx))), qm);
     } else {
-        const size_t fs = L.fld_stride;
         const int ip = wrapc<DX>(x, L.nx) + L.nx * (wrapc<DY>(y, L.ny) + L.ny * (zp + DZ));
         const int im = wrapc<-DX>(x, L.nx) + L.nx * (wrapc<-DY>(y, L.ny) + L.ny * (zp - DZ));
-        const int gp = wrapc<BXP>(x, L.nx) + L.nx * (wrapc<BYP>(y, L.ny) + L.ny * (zp + BZP));
-        const int gm = wrapc<BXM>(x, L.nx) + L.nx * (wrapc<BYM>(y, L.ny) + L.ny * (zp + BZM));
-        Gp = F.G[SLOT * fs + gp];
-        Gm = F.G[SLOT * fs + gm];
         load4(F.nj + 4 * (size_t)ip, qp);
         load4(F.nj + 4 * (size_t)im, qm);
     }
@@ -584,6 +597,37 @@ __device__ __forceinline__ void load_g(const Fields<float> &F, const LatticeDev 
     const char *gzm = gs + GB * lay * (size_t)(zp + floordiv2(-DZ));
     Gp = *(const float *)(gzp + (xb<floordiv2(DX), GB>(x, L.nx) + yb<floordiv2(DY), GB>(y, L.ny, L.nx)));
     Gm = *(const float *)(gzm + (xb<floordiv2(-DX), GB>(x, L.nx) + yb<floordiv2(-DY), GB>(y, L.ny, L.nx)));
+}
+
+// x-neighbour exchange between the lanes of a wave (DPP moves between the
+// lanes' registers, no memory access), for lanes laid out along whole periodic
+// x-rows.  ROT 1: a wave is one x-row of 64 nodes (nx = 64); ROT 2: each
+// 16-lane DPP row of the wave is one x-row of 16 nodes (nx = 16).  DIR +1
+// returns the value held by the lane of node x+1, DIR -1 that of node x-1,
+// both periodic in x.  Every lane of a row must be active.
+template <int ROT, int DIR>
+__device__ __forceinline__ uint32_t lane_x(uint32_t v)
+{
+    static_assert((ROT == 1 || ROT == 2) && (DIR == 1 || DIR == -1), "lane_x");
+    // wave_rol:1 / wave_ror:1 (lane l reads lane l+1 / l-1 mod 64); row_ror:15 /
+    // row_ror:1 (lane l reads lane l+1 / l-1 mod 16 within its row)
+    constexpr int ctrl = ROT == 1 ? (DIR > 0 ? 0x134 : 0x13C) : (DIR > 0 ? 0x12F : 0x121);
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, ctrl, 0xF, 0xF, false);
+}
+template <int ROT, int DIR, typename TM>
+__device__ __forceinline__ void lane_x4(const TM src[4], TM dst[4])
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if constexpr (sizeof(TM) == 4) {
+            dst[k] = __builtin_bit_cast(TM, lane_x<ROT, DIR>(__builtin_bit_cast(uint32_t, src[k])));
+        } else {
+            const unsigned long long b = __builtin_bit_cast(unsigned long long, src[k]);
+            const unsigned long long lo = lane_x<ROT, DIR>((uint32_t)b);
+            const unsigned long long hi = lane_x<ROT, DIR>((uint32_t)(b >> 32));
+            dst[k] = __builtin_bit_cast(TM, lo | (hi << 32));
+        }
+    }
 }
 
 // Difference of the two elements of one mirrored lattice pair, the corner d of
@@ -638,14 +682,36 @@ struct Diag {
 };
 
 // Pair elements read from global memory (the padded fields, any field type).
-template <bool LZ, typename TM>
+// ROT (see lane_x): the (n, j) of a face-diagonal corner whose x offset is one
+// further than another corner's comes from the neighbouring lane's load of
+// that corner, the same values; 0: every element loads its own.
+template <bool LZ, typename TM, int ROT_ = 0>
 struct GlobalShell {
+    static constexpr int ROT = ROT_;
     const Fields<TM> &F;
     const LatticeDev &L;
     template <int DX, int DY, int DZ, int SX, int SY, int SZ, bool DIAG, typename TC>
     __device__ __forceinline__ TC elem(const NodeCtx<TC> &c, TC su) const
     {
         return pair_element<DX, DY, DZ, SX, SY, SZ, DIAG, LZ>(F, L, c, su);
+    }
+    // The element of corner d = (DX, DY, DZ) and, in *e_next, that of corner
+    // d + (SA, 0, 0): its (n, j) at r + d + SA e_x is the (n, j) at r' + d of
+    // the node r' = r + SA e_x, and its (n, j) at r - d - SA e_x that at r'' - d
+    // of r'' = r - SA e_x.
+    template <int DX, int DY, int DZ, int SX, int SY, int SZ, int SA, typename TC>
+    __device__ __forceinline__ TC elem_share(const NodeCtx<TC> &c, TC su, TC &e_next) const
+    {
+        static_assert(ROT != 0, "elem_share needs lanes along x-rows");
+        TM gp, gm, qp[4], qm[4];
+        load_pair<DX, DY, DZ, LZ>(F, L, c.x, c.y, c.zp, gp, gm, qp, qm);
+        const TC e = pair_math<SX, SY, SZ, true>(gp, gm, qp, qm, c, su);
+        TM hp, hm, rp[4], rm[4];
+        load_gpair<DX + SA, DY, DZ, LZ>(F, L, c.x, c.y, c.zp, hp, hm);
+        lane_x4<ROT, SA>(qp, rp);
+        lane_x4<ROT, -SA>(qm, rm);
+        e_next = pair_math<SX, SY, SZ, true>(hp, hm, rp, rm, c, su);
+        return e;
     }
 };
 
@@ -661,10 +727,23 @@ __device__ __forceinline__ void diag_pair(const SRC &src, const NodeCtx<TC> &c, 
     using D10 = Diag<PL, SA, SB, LL + 1, LL>;
     using D11 = Diag<PL, SA, SB, LL + 1, LL + 1>;
     const TC su = TC(0.70710678118654752440) * (TC(SA) * c.u[A] + TC(SB) * c.u[B]);
-    TC d = alpha[0] * src.template elem<D00::DX, D00::DY, D00::DZ, D00::SX, D00::SY, D00::SZ, true>(c, su);
-    d += alpha[1] * src.template elem<D01::DX, D01::DY, D01::DZ, D01::SX, D01::SY, D01::SZ, true>(c, su);
-    d += alpha[2] * src.template elem<D10::DX, D10::DY, D10::DZ, D10::SX, D10::SY, D10::SZ, true>(c, su);
-    d += alpha[3] * src.template elem<D11::DX, D11::DY, D11::DZ, D11::SX, D11::SY, D11::SZ, true>(c, su);
+    TC d;
+    if constexpr (SRC::ROT != 0 && PL != 2) {
+        // corners (l+1, .) are corners (l, .) moved by SA along x
+        static_assert(D10::DX == D00::DX + SA && D11::DX == D01::DX + SA, "x-neighbour corners");
+        TC e10, e11;
+        const TC e00 = src.template elem_share<D00::DX, D00::DY, D00::DZ, D00::SX, D00::SY, D00::SZ, SA>(c, su, e10);
+        const TC e01 = src.template elem_share<D01::DX, D01::DY, D01::DZ, D01::SX, D01::SY, D01::SZ, SA>(c, su, e11);
+        d = alpha[0] * e00;
+        d += alpha[1] * e01;
+        d += alpha[2] * e10;
+        d += alpha[3] * e11;
+    } else {
+        d = alpha[0] * src.template elem<D00::DX, D00::DY, D00::DZ, D00::SX, D00::SY, D00::SZ, true>(c, su);
+        d += alpha[1] * src.template elem<D01::DX, D01::DY, D01::DZ, D01::SX, D01::SY, D01::SZ, true>(c, su);
+        d += alpha[2] * src.template elem<D10::DX, D10::DY, D10::DZ, D10::SX, D10::SY, D10::SZ, true>(c, su);
+        d += alpha[3] * src.template elem<D11::DX, D11::DY, D11::DZ, D11::SX, D11::SY, D11::SZ, true>(c, su);
+    }
     const TC w = TC((1.0 / 15.0) * 0.70710678118654752440) * d;
     S[A] += TC(SA) * w;
     S[B] += TC(SB) * w;
@@ -672,12 +751,12 @@ __device__ __forceinline__ void diag_pair(const SRC &src, const NodeCtx<TC> &c, 
 
 // S = sum_q W_q s_q sum_k alpha_qk G_qk [ ... ] over the 18-point rule, with
 // directions taken in (q, -q) pairs (a uniform fluid at rest gives exactly 0).
-template <int SIG, bool LZ, typename TM, typename TC>
+template <int SIG, bool LZ, typename TM, typename TC, int ROT = 0>
 __device__ __forceinline__ void shell_sum(const Fields<TM> &F, const LatticeDev &L, const NodeCtx<TC> &c,
                                           const TC *alpha, TC S[3])
 {
     constexpr int LL = ell_of(SIG);
-    const GlobalShell<LZ, TM> src{F, L};
+    const GlobalShell<LZ, TM, ROT> src{F, L};
     const TC w30 = TC(1.0 / 30.0);
     S[0] = w30 * pair_element<SIG, 0, 0, 1, 0, 0, false, LZ>(F, L, c, c.u[0]);
     S[1] = w30 * pair_element<0, SIG, 0, 0, 1, 0, false, LZ>(F, L, c, c.u[1]);
@@ -824,6 +903,7 @@ __device__ __forceinline__ void copy_tile(const Fields<float> &F, const LatticeD
 // Pair elements read from the staged regions of phase PH (0: A, 1: B).
 template <int SIG, int PH>
 struct StagedShell {
+    static constexpr int ROT = 0;
     const Tile &t;
     const Fields<float> &F;
     const LatticeDev &L;
@@ -913,7 +993,7 @@ __device__ __forceinline__ void att_force(const LatticeDev &L, const StepConst &
 // Total force C^(1) + n g at a fluid node with local moments (n, u).
 // STAGED: the shell sum reads LDS through the block's tile *tile (FP32 fields;
 // every thread of the block must call).
-template <int SIG, bool LZ, typename TM, bool MASK = true, bool STAGED = false>
+template <int SIG, bool LZ, typename TM, bool MASK = true, bool STAGED = false, int ROT = 0>
 __device__ __forceinline__ void node_force(const Fields<TM> &F, const LatticeDev &L, const StepConst &sc,
                                            const double *__restrict__ chi, int x, int y, int z, double n,
                                            const double u[3], double Fo[3], const stage::Tile *tile = nullptr)
@@ -952,7 +1032,7 @@ __device__ __forceinline__ void node_force(const Fields<TM> &F, const LatticeDev
         if constexpr (STAGED)
             shell_sum_staged<SIG>(F, L, c, alpha, S, *tile);
         else
-            shell_sum<SIG, LZ>(F, L, c, alpha, S);
+            shell_sum<SIG, LZ, TM, TC, ROT>(F, L, c, alpha, S);
     }
     double Fa[3] = {0.0, 0.0, 0.0};
     if (sc.phi) att_force(L, sc, x, y, z, n, Fa);
@@ -966,8 +1046,10 @@ __device__ __forceinline__ void node_force(const Fields<TM> &F, const LatticeDev
 // ------------------------------------------------- collide and stream
 
 // Node r (0 <= r < plane) of fluid layer z.  STAGED: the shell sum goes
-// through the LDS tile *tile (see shell_sum_staged).
-template <int SIG, bool LZ, typename TF, typename TM, bool MASK = false, bool NT = false, bool STAGED = false>
+// through the LDS tile *tile (see shell_sum_staged).  ROT: lanes along whole
+// x-rows share x-neighbour (n, j) reads (see GlobalShell).
+template <int SIG, bool LZ, typename TF, typename TM, bool MASK = false, bool NT = false, bool STAGED = false,
+          int ROT = 0>
 __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &sc, const double *__restrict__ chi,
                                           const TF *__restrict__ fin, TF *__restrict__ fout, const Fields<TM> &fld,
                                           int z, int r, const stage::Tile *tile = nullptr)
@@ -1033,7 +1115,7 @@ __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &
     const double inv_n = (n != 0.0) ? 1.0 / n : 0.0;
     const double u[3] = {jx * inv_n, jy * inv_n, jz * inv_n};
     double Fv[3];
-    node_force<SIG, LZ, TM, MASK, STAGED>(fld, L, sc, chi, x, y, z, n, u, Fv, tile);
+    node_force<SIG, LZ, TM, MASK, STAGED, ROT>(fld, L, sc, chi, x, y, z, n, u, Fv, tile);
 
     // BGK relaxation (10) towards the equilibrium (11), with the first-order
     // source, for opposite velocities i and i + 1 together: with cu = c_i.u,
@@ -1142,7 +1224,7 @@ __device__ __forceinline__ void d_collide(const LatticeDev &L, const StepConst &
 // addresses its reads by 32-bit node indices (as the batch kernel does) rather
 // than by layer-uniform base offsets: 1513 against 1530 us on the bulk, while
 // the slit keeps the layer-uniform form (39.5 against 40.8 us).
-template <int SIG, typename TF, typename TM, bool MASK, bool NT>
+template <int SIG, typename TF, typename TM, bool MASK, bool NT, int ROT>
 __global__ __launch_bounds__(256, HSLB_COLLIDE_WAVES) void k_collide(LatticeDev L, StepConst sc, const double *__restrict__ chi,
                                                  const TF *__restrict__ fin, TF *__restrict__ fout,
                                                  Fields<TM> fld, int cpp, int band)
@@ -1157,7 +1239,7 @@ __global__ __launch_bounds__(256, HSLB_COLLIDE_WAVES) void k_collide(LatticeDev 
     }
     const int r = c * 256 + threadIdx.x;
     const int z = (L.zper ? 0 : L.wall_lo) + zl;
-    if (r < L.plane) d_collide<SIG, !NT, TF, TM, MASK, NT>(L, sc, chi, fin, fout, fld, z, r);
+    if (r < L.plane) d_collide<SIG, !NT, TF, TM, MASK, NT, false, ROT>(L, sc, chi, fin, fout, fld, z, r);
 }
 
 // k_collide for FP32 storage and fields with the shell sum staged through LDS:
@@ -1421,7 +1503,7 @@ __device__ __forceinline__ Fields<TM> shift_fields(const Fields<TM> &F, int off)
 
 // Collision at fluid index k of a slit (fluid nodes counted from the first
 // fluid layer); the layer is computed per lane (see kb_phase).
-template <int SIG, typename TF, typename TM>
+template <int SIG, int ROT, typename TF, typename TM>
 __device__ __forceinline__ void batch_collide(const LatticeDev &L, const StepConst &sc, const double *__restrict__ chi,
                                               const TF *__restrict__ fin, TF *__restrict__ fout,
                                               const Fields<TM> &fld, int k)
@@ -1434,14 +1516,16 @@ __device__ __forceinline__ void batch_collide(const LatticeDev &L, const StepCon
     // The ensemble's populations (about 700 MB for 512 slits) overflow the
     // last-level cache: they stream non-temporally so that the shell fields stay
     // cached (6366 -> 6597 MLUPS).
-    d_collide<SIG, false, TF, TM, false, true>(L, sc, chi, fin, fout, fld, z, id - z * L.plane);
+    d_collide<SIG, false, TF, TM, false, true, false, ROT>(L, sc, chi, fin, fout, fld, z, id - z * L.plane);
 }
 
 // Collide phase of every slit in one persistent launch: the grid walks the
 // fluid work items; each item's descriptor (and sigma, hence the shell
 // stencil) is uniform over the block.  A kernel of its own, so that the
-// lighter phases of kb_phase keep a small register budget.
-template <typename TF, typename TM>
+// lighter phases of kb_phase keep a small register budget.  ROT 2: every slit
+// is 16 nodes wide in x, so that each 16-lane row of a wave is one x-row and
+// the shell sum shares x-neighbour (n, j) reads between lanes.
+template <typename TF, typename TM, int ROT>
 __global__ __launch_bounds__(256, HSLB_COLLIDE_WAVES) void kb_collide(const SlitDesc *__restrict__ desc,
                                                      const WorkItem *__restrict__ work, int nwork,
                                                      const TF *__restrict__ fin, TF *__restrict__ fout,
@@ -1456,13 +1540,13 @@ __global__ __launch_bounds__(256, HSLB_COLLIDE_WAVES) void kb_collide(const Slit
         const double *ch = chi + d.chi_off;
         const int idx = it.block * 256 + (int)threadIdx.x;
         switch (d.sigma) {
-        case 2: batch_collide<2>(d.L, d.sc, ch, fi, fo, F, idx); break;
-        case 3: batch_collide<3>(d.L, d.sc, ch, fi, fo, F, idx); break;
-        case 4: batch_collide<4>(d.L, d.sc, ch, fi, fo, F, idx); break;
-        case 5: batch_collide<5>(d.L, d.sc, ch, fi, fo, F, idx); break;
-        case 6: batch_collide<6>(d.L, d.sc, ch, fi, fo, F, idx); break;
-        case 7: batch_collide<7>(d.L, d.sc, ch, fi, fo, F, idx); break;
-        case 8: batch_collide<8>(d.L, d.sc, ch, fi, fo, F, idx); break;
+        case 2: batch_collide<2, ROT>(d.L, d.sc, ch, fi, fo, F, idx); break;
+        case 3: batch_collide<3, ROT>(d.L, d.sc, ch, fi, fo, F, idx); break;
+        case 4: batch_collide<4, ROT>(d.L, d.sc, ch, fi, fo, F, idx); break;
+        case 5: batch_collide<5, ROT>(d.L, d.sc, ch, fi, fo, F, idx); break;
+        case 6: batch_collide<6, ROT>(d.L, d.sc, ch, fi, fo, F, idx); break;
+        case 7: batch_collide<7, ROT>(d.L, d.sc, ch, fi, fo, F, idx); break;
+        case 8: batch_collide<8, ROT>(d.L, d.sc, ch, fi, fo, F, idx); break;
         default: break;
         }
     }
@@ -2502,7 +2586,7 @@ hipError_t launch_gfield(hipStream_t s, const LatticeDev &L, int g2_model, Field
     return hipGetLastError();
 }
 
-template <typename TF, typename TM, bool M, bool NT>
+template <typename TF, typename TM, bool M, bool NT, int ROT = 0>
 hipError_t launch_collide_t(hipStream_t s, int sigma, dim3 g, dim3 b, const LatticeDev &L, const StepConst &c,
                             const double *chi, const TF *fin, TF *fout, Fields<TM> fld, int cpp, int band);
 
@@ -2562,22 +2646,28 @@ hipError_t launch_collide(hipStream_t s, const LatticeDev &L, int sigma, const S
     }
     if (pop_bytes > 128.0 * 1024 * 1024)
         return launch_collide_t<TF, TM, false, true>(s, sigma, g, b, L, c, chi, fin, fout, fld, cpp, band);
+    // a wave per x-row of 64 nodes: x-neighbour (n, j) reads shared between
+    // lanes (benchmark slit 39.9 -> 36.7 us)
+    if constexpr (std::is_same<TF, float>::value && std::is_same<TM, float>::value) {
+        if (L.nx == 64)
+            return launch_collide_t<TF, TM, false, false, 1>(s, sigma, g, b, L, c, chi, fin, fout, fld, cpp, band);
+    }
     return launch_collide_t<TF, TM, false, false>(s, sigma, g, b, L, c, chi, fin, fout, fld, cpp, band);
 }
 
-template <typename TF, typename TM, bool M, bool NT>
+template <typename TF, typename TM, bool M, bool NT, int ROT>
 hipError_t launch_collide_t(hipStream_t s, int sigma, dim3 g, dim3 b, const LatticeDev &L, const StepConst &c,
                             const double *chi, const TF *fin, TF *fout, Fields<TM> fld, int cpp, int band)
 {
     switch (sigma) {
-    case 0: hipLaunchKernelGGL((k_collide<0, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
-    case 2: hipLaunchKernelGGL((k_collide<2, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
-    case 3: hipLaunchKernelGGL((k_collide<3, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
-    case 4: hipLaunchKernelGGL((k_collide<4, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
-    case 5: hipLaunchKernelGGL((k_collide<5, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
-    case 6: hipLaunchKernelGGL((k_collide<6, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
-    case 7: hipLaunchKernelGGL((k_collide<7, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
-    case 8: hipLaunchKernelGGL((k_collide<8, TF, TM, M, NT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
+    case 0: hipLaunchKernelGGL((k_collide<0, TF, TM, M, NT, ROT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
+    case 2: hipLaunchKernelGGL((k_collide<2, TF, TM, M, NT, ROT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
+    case 3: hipLaunchKernelGGL((k_collide<3, TF, TM, M, NT, ROT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
+    case 4: hipLaunchKernelGGL((k_collide<4, TF, TM, M, NT, ROT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
+    case 5: hipLaunchKernelGGL((k_collide<5, TF, TM, M, NT, ROT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
+    case 6: hipLaunchKernelGGL((k_collide<6, TF, TM, M, NT, ROT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
+    case 7: hipLaunchKernelGGL((k_collide<7, TF, TM, M, NT, ROT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
+    case 8: hipLaunchKernelGGL((k_collide<8, TF, TM, M, NT, ROT>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp, band); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -2658,10 +2748,17 @@ hipError_t launch_batch_phase(hipStream_t s, int phase, unsigned grid, const Sli
 
 template <typename TF, typename TM>
 hipError_t launch_batch_collide(hipStream_t s, unsigned grid, const SlitDesc *desc, const WorkItem *work, int nwork,
-                                const TF *fin, TF *fout, Fields<TM> fld, const double *chi)
+                                const TF *fin, TF *fout, Fields<TM> fld, const double *chi, bool rows16)
 {
     if (nwork <= 0) return hipSuccess;
-    hipLaunchKernelGGL((kb_collide<TF, TM>), dim3(grid), dim3(256), 0, s, desc, work, nwork, fin, fout, fld, chi);
+    if constexpr (std::is_same<TF, float>::value && std::is_same<TM, float>::value) {
+        if (rows16) {
+            hipLaunchKernelGGL((kb_collide<TF, TM, 2>), dim3(grid), dim3(256), 0, s, desc, work, nwork, fin, fout,
+                               fld, chi);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((kb_collide<TF, TM, 0>), dim3(grid), dim3(256), 0, s, desc, work, nwork, fin, fout, fld, chi);
     return hipGetLastError();
 }
 
@@ -2710,7 +2807,7 @@ hipError_t launch_batch_profiles(hipStream_t s, const SlitDesc *desc, const Work
                                                    const double *);                                          \
     template hipError_t launch_batch_collide<TF, TM>(hipStream_t, unsigned, const SlitDesc *,               \
                                                      const WorkItem *, int, const TF *, TF *, Fields<TM>,     \
-                                                     const double *);
+                                                     const double *, bool);
 
 // ------------------------------------------------ allocation-free scratch
 
