@@ -602,16 +602,18 @@ __device__ __forceinline__ void load_g(const Fields<float> &F, const LatticeDev 
 // x-neighbour exchange between the lanes of a wave (DPP moves between the
 // lanes' registers, no memory access), for lanes laid out along whole periodic
 // x-rows.  ROT 1: a wave is one x-row of 64 nodes (nx = 64); ROT 2: each
-// 16-lane DPP row of the wave is one x-row of 16 nodes (nx = 16).  DIR +1
-// returns the value held by the lane of node x+1, DIR -1 that of node x-1,
-// both periodic in x.  Every lane of a row must be active.
+// 16-lane DPP row of the wave is one x-row of 16 nodes (nx = 16); ROT 3: an
+// x-row of 128 or 256 nodes spans 2 or 4 waves of the block (the wave rotation
+// of ROT 1, whose row-edge lanes then take the neighbouring wave's value, see
+// s_xedge).  DIR +1 returns the value held by the lane of node x+1, DIR -1 that
+// of node x-1, both periodic in x.  Every lane of a row must be active.
 template <int ROT, int DIR>
 __device__ __forceinline__ uint32_t lane_x(uint32_t v)
 {
-    static_assert((ROT == 1 || ROT == 2) && (DIR == 1 || DIR == -1), "lane_x");
+    static_assert((ROT >= 1 && ROT <= 3) && (DIR == 1 || DIR == -1), "lane_x");
     // wave_rol:1 / wave_ror:1 (lane l reads lane l+1 / l-1 mod 64); row_ror:15 /
     // row_ror:1 (lane l reads lane l+1 / l-1 mod 16 within its row)
-    constexpr int ctrl = ROT == 1 ? (DIR > 0 ? 0x134 : 0x13C) : (DIR > 0 ? 0x12F : 0x121);
+    constexpr int ctrl = ROT != 2 ? (DIR > 0 ? 0x134 : 0x13C) : (DIR > 0 ? 0x12F : 0x121);
     return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, ctrl, 0xF, 0xF, false);
 }
 template <int ROT, int DIR, typename TM>
@@ -681,6 +683,47 @@ struct Diag {
     static constexpr int SZ = (PL == 0) ? 0 : SB;
 };
 
+// ROT 3: before the shell sum, lane 0 of each wave stores the (n, j) at r + d of
+// the 8 shared corners d (those of the face diagonals of the xy and xz planes
+// whose x-neighbour corner takes its reads from the lanes) and lane 63 the (n, j)
+// at r - d; after the rotation, the row-edge lane takes the neighbouring wave's
+// entry.  Layout [corner][0: lane 0 at r + d, 1: lane 63 at r - d][wave].
+__shared__ float4 s_xedge[8 * 2 * 4];
+
+template <int DX, int DY, int DZ, int EI>
+__device__ __forceinline__ void xedge_one(const Fields<float> &F, const LatticeDev &L, int x, int y, int zp, int lane,
+                                          int w)
+{
+    if (lane == 0 || lane == 63) {
+        const int ip = wrapc<DX>(x, L.nx) + L.nx * (wrapc<DY>(y, L.ny) + L.ny * (zp + DZ));
+        const int im = wrapc<-DX>(x, L.nx) + L.nx * (wrapc<-DY>(y, L.ny) + L.ny * (zp - DZ));
+        const float4 q = *(const float4 *)(F.nj + 4 * (size_t)(lane == 0 ? ip : im));
+        s_xedge[(EI * 2 + (lane == 0 ? 0 : 1)) * 4 + w] = q;
+    }
+}
+
+// Fills s_xedge for the block; every thread of the block calls it, and a
+// barrier must follow before the shell sum reads the entries.
+template <int SIG>
+__device__ __forceinline__ void xedge_prepass(const Fields<float> &F, const LatticeDev &L, int x, int y, int zp)
+{
+    constexpr int LL = ell_of(SIG);
+    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+    // corner index as diag_pair numbers it: (plane * 2 + (SB < 0)) * 2 + (0: (l, l), 1: (l, l+1))
+#define HSLB_XE(PL, SB, K)                                                                                    \
+    xedge_one<Diag<PL, 1, SB, LL, LL + K>::DX, Diag<PL, 1, SB, LL, LL + K>::DY, Diag<PL, 1, SB, LL, LL + K>::DZ, \
+              (PL * 2 + (SB > 0 ? 0 : 1)) * 2 + K>(F, L, x, y, zp, lane, w)
+    HSLB_XE(0, 1, 0);
+    HSLB_XE(0, 1, 1);
+    HSLB_XE(0, -1, 0);
+    HSLB_XE(0, -1, 1);
+    HSLB_XE(1, 1, 0);
+    HSLB_XE(1, 1, 1);
+    HSLB_XE(1, -1, 0);
+    HSLB_XE(1, -1, 1);
+#undef HSLB_XE
+}
+
 // Pair elements read from global memory (the padded fields, any field type).
 // ROT (see lane_x): the (n, j) of a face-diagonal corner whose x offset is one
 // further than another corner's comes from the neighbouring lane's load of
@@ -698,8 +741,8 @@ struct GlobalShell {
     // The element of corner d = (DX, DY, DZ) and, in *e_next, that of corner
     // d + (SA, 0, 0): its (n, j) at r + d + SA e_x is the (n, j) at r' + d of
     // the node r' = r + SA e_x, and its (n, j) at r - d - SA e_x that at r'' - d
-    // of r'' = r - SA e_x.
-    template <int DX, int DY, int DZ, int SX, int SY, int SZ, int SA, typename TC>
+    // of r'' = r - SA e_x.  EI: the corner's index in s_xedge (ROT 3).
+    template <int DX, int DY, int DZ, int SX, int SY, int SZ, int SA, int EI, typename TC>
     __device__ __forceinline__ TC elem_share(const NodeCtx<TC> &c, TC su, TC &e_next) const
     {
         static_assert(ROT != 0, "elem_share needs lanes along x-rows");
@@ -710,6 +753,23 @@ struct GlobalShell {
         load_gpair<DX + SA, DY, DZ, LZ>(F, L, c.x, c.y, c.zp, hp, hm);
         lane_x4<ROT, SA>(qp, rp);
         lane_x4<ROT, -SA>(qm, rm);
+        if constexpr (ROT == 3) {
+            static_assert(SA == 1 && sizeof(TM) == 4, "row-edge exchange: FP32 fields, corners moved by +x");
+            const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+            const int wr = L.nx >> 6, wb = w - w % wr;  // waves per x-row, first wave of this row
+            const int wn = wb + (w - wb + 1) % wr, wp = wb + (w - wb + wr - 1) % wr;
+            const float4 ep = s_xedge[(EI * 2 + 0) * 4 + wn];
+            const float4 em = s_xedge[(EI * 2 + 1) * 4 + wp];
+            const bool hi = lane == 63, lo = lane == 0;
+            rp[0] = hi ? ep.x : rp[0];
+            rp[1] = hi ? ep.y : rp[1];
+            rp[2] = hi ? ep.z : rp[2];
+            rp[3] = hi ? ep.w : rp[3];
+            rm[0] = lo ? em.x : rm[0];
+            rm[1] = lo ? em.y : rm[1];
+            rm[2] = lo ? em.z : rm[2];
+            rm[3] = lo ? em.w : rm[3];
+        }
         e_next = pair_math<SX, SY, SZ, true>(hp, hm, rp, rm, c, su);
         return e;
     }
@@ -732,8 +792,10 @@ __device__ __forceinline__ void diag_pair(const SRC &src, const NodeCtx<TC> &c, 
         // corners (l+1, .) are corners (l, .) moved by SA along x
         static_assert(D10::DX == D00::DX + SA && D11::DX == D01::DX + SA, "x-neighbour corners");
         TC e10, e11;
-        const TC e00 = src.template elem_share<D00::DX, D00::DY, D00::DZ, D00::SX, D00::SY, D00::SZ, SA>(c, su, e10);
-        const TC e01 = src.template elem_share<D01::DX, D01::DY, D01::DZ, D01::SX, D01::SY, D01::SZ, SA>(c, su, e11);
+        constexpr int EI = (PL * 2 + (SB > 0 ? 0 : 1)) * 2;
+        const TC e00 = src.template elem_share<D00::DX, D00::DY, D00::DZ, D00::SX, D00::SY, D00::SZ, SA, EI>(c, su, e10);
+        const TC e01 =
+            src.template elem_share<D01::DX, D01::DY, D01::DZ, D01::SX, D01::SY, D01::SZ, SA, EI + 1>(c, su, e11);
         d = alpha[0] * e00;
         d += alpha[1] * e01;
         d += alpha[2] * e10;
@@ -1239,6 +1301,13 @@ __global__ __launch_bounds__(256, HSLB_COLLIDE_WAVES) void k_collide(LatticeDev 
     }
     const int r = c * 256 + threadIdx.x;
     const int z = (L.zper ? 0 : L.wall_lo) + zl;
+    if constexpr (ROT == 3 && SIG >= 2) {
+        // the host takes ROT 3 only for a plane that is a multiple of 256 nodes:
+        // every thread of the block is a node and reaches the barrier
+        const int y = r / L.nx;
+        xedge_prepass<SIG>(fld, L, r - y * L.nx, y, z + L.hz);
+        __syncthreads();
+    }
     if (r < L.plane) d_collide<SIG, !NT, TF, TM, MASK, NT, false, ROT>(L, sc, chi, fin, fout, fld, z, r);
 }
 
@@ -2644,8 +2713,17 @@ hipError_t launch_collide(hipStream_t s, const LatticeDev &L, int sigma, const S
         if (tiles && collide_tiles_apply(L, sigma, c, true))
             return launch_collide_tiles(s, sigma, layers, pop_bytes > 128.0 * 1024 * 1024, L, c, chi, fin, fout, fld);
     }
-    if (pop_bytes > 128.0 * 1024 * 1024)
+    if (pop_bytes > 128.0 * 1024 * 1024) {
+        // x-rows of 128 or 256 nodes over 2 or 4 waves: lanes share x-neighbour
+        // reads, the row-edge lanes through the block's LDS (256^3 bulk 1401 ->
+        // 1373 us; the cache-resident 128 x 128 slit lost, 315 -> 366 us, so
+        // only this instance takes it)
+        if constexpr (std::is_same<TF, float>::value && std::is_same<TM, float>::value) {
+            if ((L.nx == 128 || L.nx == 256) && L.plane % 256 == 0 && sigma >= 2)
+                return launch_collide_t<TF, TM, false, true, 3>(s, sigma, g, b, L, c, chi, fin, fout, fld, cpp, band);
+        }
         return launch_collide_t<TF, TM, false, true>(s, sigma, g, b, L, c, chi, fin, fout, fld, cpp, band);
+    }
     // a wave per x-row of 64 nodes: x-neighbour (n, j) reads shared between
     // lanes (benchmark slit 39.9 -> 36.7 us)
     if constexpr (std::is_same<TF, float>::value && std::is_same<TM, float>::value) {

@@ -3,8 +3,10 @@ against the default kernel with direct reads: both sum the same pair elements
 in the same order with the same arithmetic, so the populations after several
 steps must agree bit for bit.  Cases cover one tile row (ny = 4), odd and even
 sigma, walls and periodic z, the non-temporal instance of lattices whose
-populations exceed the last-level cache, and a lattice the staged kernel does
-not take (nx not a multiple of 64), where the switch must change nothing."""
+populations exceed the last-level cache (with x-rows of 128 and 256 nodes,
+whose direct kernel exchanges row-edge reads between waves), and a lattice the
+staged kernel does not take (nx not a multiple of 64), where the switch must
+change nothing."""
 import numpy as np
 import pytest
 
@@ -33,6 +35,7 @@ def _run(nx, ny, nz, sigma, walls, steps, tiles, seed, eta=0.25, att=0.0):
     (64, 4, 20, 2, 1, 20),       # one tile row, walls
     (64, 12, 18, 3, 2, 20),      # odd sigma, walls
     (128, 128, 136, 6, 0, 4),    # populations beyond the last-level cache
+    (256, 64, 60, 5, 3, 3),      # beyond the cache, x-rows over four waves
     (48, 16, 20, 4, 2, 10),      # not tiled: the switch changes nothing
 ])
 def test_staged_collide_is_bitwise_the_direct_one(nx, ny, nz, sigma, walls, steps):
