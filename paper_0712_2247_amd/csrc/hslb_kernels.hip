@@ -561,6 +561,19 @@ __device__ __forceinline__ void load_gpair(const Fields<TM> &F, const LatticeDev
     }
 }
 
+// The (n, j) of r + (DX, DY, DZ), addressed as load_pair does.
+template <int DX, int DY, int DZ, bool LZ, typename TM>
+__device__ __forceinline__ void load_nj(const Fields<TM> &F, const LatticeDev &L, int x, int y, int zp, TM q[4])
+{
+    if constexpr (LZ) {
+        constexpr int NJB = 4 * (int)sizeof(TM);
+        const char *nz = (const char *)F.nj + NJB * (size_t)L.plane * (size_t)(zp + DZ);
+        load4((const TM *)(nz + (xb<DX, NJB>(x, L.nx) + yb<DY, NJB>(y, L.ny, L.nx))), q);
+    } else {
+        load4(F.nj + 4 * (size_t)(wrapc<DX>(x, L.nx) + L.nx * (wrapc<DY>(y, L.ny) + L.ny * (zp + DZ))), q);
+    }
+}
+
 // Loads of one mirrored lattice pair: the contact values G+ (midpoint of
 // (r, r+d)) and G- (midpoint of (r, r-d)) and the (n, j) of r+d and r-d.
 template <int DX, int DY, int DZ, bool LZ, typename TM>
@@ -630,6 +643,28 @@ __device__ __forceinline__ void lane_x4(const TM src[4], TM dst[4])
             dst[k] = __builtin_bit_cast(TM, lo | (hi << 32));
         }
     }
+}
+
+// ROT 2 only: the value held by the lane of node x + K (periodic, |K| < 16) of
+// the same 16-lane row (row_ror:N makes lane l read lane l - N mod 16).
+template <int K, typename TM>
+__device__ __forceinline__ TM lane_xk(TM v)
+{
+    constexpr int N = ((-K) % 16 + 16) % 16;
+    if constexpr (N == 0) {
+        return v;
+    } else {
+        static_assert(sizeof(TM) == 4, "lane_xk: 32-bit values");
+        return __builtin_bit_cast(
+            TM, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, v), __builtin_bit_cast(int, v), 0x120 + N, 0xF, 0xF,
+                                            false));
+    }
+}
+template <int K, typename TM>
+__device__ __forceinline__ void lane_xk4(const TM src[4], TM dst[4])
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dst[k] = lane_xk<K>(src[k]);
 }
 
 // Difference of the two elements of one mirrored lattice pair, the corner d of
@@ -811,6 +846,65 @@ __device__ __forceinline__ void diag_pair(const SRC &src, const NodeCtx<TC> &c, 
     S[B] += TC(SB) * w;
 }
 
+// Both face-diagonal quadrature points (1, 1) and (1, -1) of plane PL (0: xy,
+// 1: xz) for lanes along 16-node x-rows (ROT 2): the same sums as
+// diag_pair<PL, 1, 1> followed by diag_pair<PL, 1, -1>, with every value that
+// another lane of the row loads taken from that lane.  With b the offset off
+// the x axis and LA, LB in {l, l+1}:
+//  - (n, j): per LB, P at r + (l, LB) and M at r - (l, LB) are loaded; the other
+//    corners' entries lie on the same two rows, 1, 2l or 2l+1 nodes away in x;
+//  - contact values: per corner d = (LA, LB) of the point (1, 1), G+ and G- are
+//    loaded; the corner (LA, -LB) of the point (1, -1) finds its G- at the
+//    same row as G+(d), LA nodes back in x, and its G+ with G-(d), LA ahead.
+template <int PL, int LL, bool LZ, typename TM, typename TC>
+__device__ __forceinline__ void diag_plane16(const Fields<TM> &F, const LatticeDev &L, const NodeCtx<TC> &c,
+                                             const TC *alpha, TC S[3])
+{
+    static_assert(PL == 0 || PL == 1, "x-planes only");
+    constexpr int B = (PL == 0) ? 1 : 2;
+    TC e[2][2][2];  // [0: point (1, 1), 1: point (1, -1)][LA - l][LB - l]
+    const TC sup = TC(0.70710678118654752440) * (c.u[0] + c.u[B]);
+    const TC sum = TC(0.70710678118654752440) * (c.u[0] - c.u[B]);
+#define HSLB_D16_LB(KB)                                                                                        \
+    {                                                                                                          \
+        using Q0 = Diag<PL, 1, 1, LL, LL + KB>;                                                                \
+        TM P[4], M[4];                                                                                         \
+        load_nj<Q0::DX, Q0::DY, Q0::DZ, LZ>(F, L, c.x, c.y, c.zp, P);                                          \
+        load_nj<-Q0::DX, -Q0::DY, -Q0::DZ, LZ>(F, L, c.x, c.y, c.zp, M);                                       \
+        HSLB_D16_LA(0, KB)                                                                                     \
+        HSLB_D16_LA(1, KB)                                                                                     \
+    }
+#define HSLB_D16_LA(KA, KB)                                                                                    \
+    {                                                                                                          \
+        using Q = Diag<PL, 1, 1, LL + KA, LL + KB>;                                                            \
+        using R = Diag<PL, 1, -1, LL + KA, LL + KB>;                                                           \
+        constexpr int LA = LL + KA;                                                                            \
+        TM gp, gm, qp[4], qm[4], rp[4], rm[4];                                                                 \
+        load_gpair<Q::DX, Q::DY, Q::DZ, LZ>(F, L, c.x, c.y, c.zp, gp, gm);                                     \
+        lane_xk4<KA>(P, qp);                                                                                   \
+        lane_xk4<-KA>(M, qm);                                                                                  \
+        e[0][KA][KB] = pair_math<Q::SX, Q::SY, Q::SZ, true>(gp, gm, qp, qm, c, sup);                          \
+        lane_xk4<LL + LA>(M, rp);                                                                              \
+        lane_xk4<-(LL + LA)>(P, rm);                                                                           \
+        e[1][KA][KB] = pair_math<R::SX, R::SY, R::SZ, true>(lane_xk<LA>(gm), lane_xk<-LA>(gp), rp, rm, c, sum); \
+    }
+    HSLB_D16_LB(0)
+    HSLB_D16_LB(1)
+#undef HSLB_D16_LA
+#undef HSLB_D16_LB
+    const TC wq = TC((1.0 / 15.0) * 0.70710678118654752440);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        TC d = alpha[0] * e[k][0][0];
+        d += alpha[1] * e[k][0][1];
+        d += alpha[2] * e[k][1][0];
+        d += alpha[3] * e[k][1][1];
+        const TC w = wq * d;
+        S[0] += w;
+        S[B] += k == 0 ? w : -w;
+    }
+}
+
 // S = sum_q W_q s_q sum_k alpha_qk G_qk [ ... ] over the 18-point rule, with
 // directions taken in (q, -q) pairs (a uniform fluid at rest gives exactly 0).
 template <int SIG, bool LZ, typename TM, typename TC, int ROT = 0>
@@ -823,10 +917,15 @@ __device__ __forceinline__ void shell_sum(const Fields<TM> &F, const LatticeDev 
     S[0] = w30 * pair_element<SIG, 0, 0, 1, 0, 0, false, LZ>(F, L, c, c.u[0]);
     S[1] = w30 * pair_element<0, SIG, 0, 0, 1, 0, false, LZ>(F, L, c, c.u[1]);
     S[2] = w30 * pair_element<0, 0, SIG, 0, 0, 1, false, LZ>(F, L, c, c.u[2]);
-    diag_pair<0, 1, 1, LL>(src, c, alpha, S);
-    diag_pair<0, 1, -1, LL>(src, c, alpha, S);
-    diag_pair<1, 1, 1, LL>(src, c, alpha, S);
-    diag_pair<1, 1, -1, LL>(src, c, alpha, S);
+    if constexpr (ROT == 2) {
+        diag_plane16<0, LL, LZ>(F, L, c, alpha, S);
+        diag_plane16<1, LL, LZ>(F, L, c, alpha, S);
+    } else {
+        diag_pair<0, 1, 1, LL>(src, c, alpha, S);
+        diag_pair<0, 1, -1, LL>(src, c, alpha, S);
+        diag_pair<1, 1, 1, LL>(src, c, alpha, S);
+        diag_pair<1, 1, -1, LL>(src, c, alpha, S);
+    }
     diag_pair<2, 1, 1, LL>(src, c, alpha, S);
     diag_pair<2, 1, -1, LL>(src, c, alpha, S);
 }
