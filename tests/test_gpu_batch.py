@@ -100,6 +100,47 @@ def test_batch_ragged_planes_match_single_lattice():
         assert rel(pn, sn) <= 1e-12 and rel(pu[0], su[0]) <= 1e-12, (i, rel(pn, sn), rel(pu[0], su[0]))
 
 
+def test_lane_shared_shell_reads_match_loaded_ones():
+    """Where x-rows are whole 16-lane rows (a batch whose slits are all 16 wide)
+    or whole waves (a 64-wide single lattice), lanes take shell reads that
+    another lane of the row loads from that lane; the other path loads every
+    read.  16-wide slits whose planes are not multiples of 64 nodes (waves
+    straddle layers) against the single-lattice path, and a 64 x 18 single
+    lattice (a partial last chunk of 128 nodes per layer) against the batch
+    path, which loads every read for a 64-wide slit."""
+    base = [workloads.ensemble()[k] for k in (1, 2, 5)]   # sigma 4, 3, 8
+    wls = [base[0].with_size(nx=16, ny=12, noise=0.01, steps=40),
+           base[1].with_size(nx=16, ny=20, noise=0.01, steps=40),
+           base[2].with_size(nx=16, ny=12, noise=0.01, steps=40)]
+    print("16-wide batch", [(w.ny, w.sigma) for w in wls], flush=True)
+    b = hslb.Batch(wls)
+    b.init_all()
+    b.step(40)
+    for i, w in enumerate(wls):
+        g = hslb.Sim.from_workload(w)
+        n, u = w.fields()
+        g.init(n, u)
+        g.step(40)
+        sn, su = g.profiles()
+        pn, pu = b.profiles(i)
+        assert np.isfinite(sn).all()
+        assert rel(pn, sn) <= 1e-12 and rel(pu[0], su[0]) <= 1e-12, (i, rel(pn, sn), rel(pu[0], su[0]))
+    for w in (base[0].with_size(nx=64, ny=18, noise=0.01, steps=40),
+              base[2].with_size(nx=64, ny=18, noise=0.01, steps=40)):
+        print("64-wide single lattice", w.ny, w.sigma, flush=True)
+        b = hslb.Batch([w])
+        b.init_all()
+        b.step(40)
+        g = hslb.Sim.from_workload(w)
+        n, u = w.fields()
+        g.init(n, u)
+        g.step(40)
+        sn, su = g.profiles()
+        pn, pu = b.profiles(0)
+        assert np.isfinite(sn).all()
+        assert rel(pn, sn) <= 1e-12 and rel(pu[0], su[0]) <= 1e-12, (rel(pn, sn), rel(pu[0], su[0]))
+
+
 def test_batch_graph_and_eager_agree_and_autotune_restores_state():
     wls = [workloads.ensemble()[k].with_size(steps=60) for k in SMALL[:6]]
     a = hslb.Batch(wls)
