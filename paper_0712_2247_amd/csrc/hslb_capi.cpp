@@ -1473,11 +1473,13 @@ public:
         int64_t pop = 0, fld = 0, prof = 0;
         int maxR = 0;
         rows16_ = ns > 0;
+        fused_rows_ = ns > 0;
         for (int k = 0; k < ns; ++k) {
             SlitDesc &d = desc_[k];
             std::vector<double> chi;
             slit_consts(p_[k], d.L, d.sc, chi);
             rows16_ = rows16_ && d.L.nx == 16;
+            fused_rows_ = fused_rows_ && 256 % d.L.nx == 0 && d.L.plane % 256 == 0;
             d.sigma = p_[k].sigma >= 2 ? p_[k].sigma : 2;
             maxR = std::max(maxR, d.sigma / 2);
             d.pop_off = (int)pop;
@@ -1692,8 +1694,13 @@ public:
     {
         const WorkItem *wn = work_d_, *wr = wn + wl_nodes_.size(), *wf = wr + wl_rows_.size();
         int rc;
-        if ((rc = phase("b_moments", 0, wn, (int)wl_nodes_.size()))) return rc;
-        if ((rc = phase("b_rowsum", 1, wr, (int)wl_rows_.size()))) return rc;
+        if (fused_rows_) {
+            // 512 16x16 slits: 90 + 41 -> 100 us (moments and row sums)
+            if ((rc = phase("b_moments", 4, wn, (int)wl_nodes_.size()))) return rc;
+        } else {
+            if ((rc = phase("b_moments", 0, wn, (int)wl_nodes_.size()))) return rc;
+            if ((rc = phase("b_rowsum", 1, wr, (int)wl_rows_.size()))) return rc;
+        }
         if ((rc = phase("b_ballsum", 2, wn, (int)wl_nodes_.size()))) return rc;
         if ((rc = phase("b_gfield", 3, wn, (int)wl_nodes_.size()))) return rc;
         if ((rc = collide(wf, (int)wl_fluid_.size()))) return rc;
@@ -2062,6 +2069,7 @@ public:
 private:
     std::vector<hslb_params> p_;
     bool rows16_ = false;  // every slit 16 nodes wide in x (see launch_batch_collide)
+    bool fused_rows_ = false;  // every slit's layer whole 256-node blocks of x-rows (phase 4)
     std::vector<SlitDesc> desc_;
     std::vector<WorkItem> wl_nodes_, wl_rows_, wl_fluid_, wl_prof_;
     std::vector<int> prof_off_;

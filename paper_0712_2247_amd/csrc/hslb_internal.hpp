@@ -244,8 +244,10 @@ hipError_t launch_fill(hipStream_t s, double *a, size_t count, double v);
 hipError_t launch_chi(hipStream_t s, const LatticeDev &L, int sigma, int wall_reg, double *chi);
 
 // Batched ensemble: one persistent launch per phase over a work list.
-// phase 0 moments, 1 row sums, 2 ball sums, 3 contact values (the collide
-// phase is launch_batch_collide).
+// phase 0 moments, 1 row sums, 2 ball sums, 3 contact values, 4 moments with
+// the row sums (phases 0 and 1 in one; only when every slit's layer is a whole
+// number of 256-node blocks of whole x-rows) (the collide phase is
+// launch_batch_collide).
 template <typename TF, typename TM>
 hipError_t launch_batch_phase(hipStream_t s, int phase, unsigned grid, const SlitDesc *desc,
                               const WorkItem *work, int nwork, const TF *fin, TF *fout, Fields<TM> fld,

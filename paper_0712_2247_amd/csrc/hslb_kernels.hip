@@ -1747,6 +1747,28 @@ __global__ __launch_bounds__(256) void kb_phase(int phase, const SlitDesc *__res
         case 3:
             if (idx < d.L.N) d_gfield(d.L, d.sc.g2_model, F, idx / d.L.plane, idx % d.L.plane);
             break;
+        case 4: {
+            // phases 0 and 1 in one: every slit's layer is a whole number of
+            // 256-node blocks of whole x-rows (the host checks), so the block
+            // forms the row sums of its own densities, as k_moments_rs does;
+            // the row sums of the padding stay the zeros they were set to
+            __shared__ TM sn[256];
+            const int z = idx / d.L.plane, r = idx - z * d.L.plane;
+            sn[threadIdx.x] = d_moments(d.L, d.sc.nref_r, fi, F, z, r);
+            __syncthreads();
+            switch (d.sigma) {
+            case 2: block_rowsums<2>(d.L, sn, rsl, z, r); break;
+            case 3: block_rowsums<3>(d.L, sn, rsl, z, r); break;
+            case 4: block_rowsums<4>(d.L, sn, rsl, z, r); break;
+            case 5: block_rowsums<5>(d.L, sn, rsl, z, r); break;
+            case 6: block_rowsums<6>(d.L, sn, rsl, z, r); break;
+            case 7: block_rowsums<7>(d.L, sn, rsl, z, r); break;
+            case 8: block_rowsums<8>(d.L, sn, rsl, z, r); break;
+            default: break;
+            }
+            __syncthreads();  // sn is refilled by the next work item
+            break;
+        }
         default:
 #define HSLB_BPH(SG)                                                                     \
     case SG:                                                                             \
