@@ -2451,7 +2451,7 @@ __device__ __forceinline__ void th_node_force(const Fields<double> &F, const Lat
 #endif
 
 // 1-D grid over (fluid layer, chunk of 256 nodes of the layer), as k_collide.
-template <int SIG, bool TH>
+template <int SIG, bool TH, int ROT = 0>
 __global__ __launch_bounds__(256, TH ? HSLB_COLLIDE39T_WAVES : HSLB_COLLIDE39_WAVES) void k_collide39(LatticeDev L, StepConst sc, const double *__restrict__ chi,
                                                    const double *__restrict__ fin, double *__restrict__ fout,
                                                    Fields<double> fld, int cpp)
@@ -2503,7 +2503,7 @@ __global__ __launch_bounds__(256, TH ? HSLB_COLLIDE39T_WAVES : HSLB_COLLIDE39_WA
         emit39_poly(L, fout, x, y, z, A, std::make_integer_sequence<int, Q39>{});
     } else {
         project39(n, u, f, a2, a3, std::make_integer_sequence<int, Q39>{});
-        node_force<SIG, true, double, false>(fld, L, sc, chi, x, y, z, n, u, Fv);
+        node_force<SIG, true, double, false, false, ROT>(fld, L, sc, chi, x, y, z, n, u, Fv);
         emit39(L, fout, x, y, z, n, u, om, Fv, a2, a3, std::make_integer_sequence<int, Q39>{});
     }
 }
@@ -2622,12 +2622,16 @@ hipError_t launch_collide39(hipStream_t s, const LatticeDev &L, int sigma, const
     const int layers = L.zper ? L.nz : L.nz - L.wall_lo - L.wall_hi;
     const int cpp = (int)blocks_for(L.plane);
     const dim3 g(cpp * layers), b(256);
-#define HSLB_C39(SG)                                                                               \
-    case SG:                                                                                       \
-        if (thermal)                                                                               \
-            hipLaunchKernelGGL((k_collide39<SG, true>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); \
-        else                                                                                       \
-            hipLaunchKernelGGL((k_collide39<SG, false>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); \
+    // a wave per x-row of 64 nodes: x-neighbour (n, j) reads shared between lanes
+    const bool rot = L.nx == 64;
+#define HSLB_C39(SG)                                                                                  \
+    case SG:                                                                                          \
+        if (thermal)                                                                                  \
+            hipLaunchKernelGGL((k_collide39<SG, true>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp);    \
+        else if (rot)                                                                                 \
+            hipLaunchKernelGGL((k_collide39<SG, false, 1>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp); \
+        else                                                                                          \
+            hipLaunchKernelGGL((k_collide39<SG, false>), g, b, 0, s, L, c, chi, fin, fout, fld, cpp);   \
         break;
     switch (sigma) {
         HSLB_C39(2)
