@@ -1664,7 +1664,8 @@ public:
             HIP_TRY(hipEventRecord(a, st()));
         }
         const unsigned grid = (unsigned)std::max(1, std::min(nw, ncu_ * grid_per_cu_));
-        HIP_TRY(launch_batch_phase<TF, TM>(st(), ph, grid, desc_d_, w, nw, f_[cur_], f_[1 - cur_], fld_, rs_, chi_d_));
+        HIP_TRY(launch_batch_phase<TF, TM>(st(), ph, grid, desc_d_, w, nw, f_[cur_], f_[1 - cur_], fld_, rs_, chi_d_,
+                                           rows16_));
         if (a) {
             HIP_TRY(hipEventRecord(b, st()));
             kt.pending.push_back({name, {(int)kt.used - 2, (int)kt.used - 1}});

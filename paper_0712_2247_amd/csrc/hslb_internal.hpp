@@ -247,11 +247,11 @@ hipError_t launch_chi(hipStream_t s, const LatticeDev &L, int sigma, int wall_re
 // phase 0 moments, 1 row sums, 2 ball sums, 3 contact values, 4 moments with
 // the row sums (phases 0 and 1 in one; only when every slit's layer is a whole
 // number of 256-node blocks of whole x-rows) (the collide phase is
-// launch_batch_collide).
+// launch_batch_collide).  rows16: every slit is 16 nodes wide in x.
 template <typename TF, typename TM>
 hipError_t launch_batch_phase(hipStream_t s, int phase, unsigned grid, const SlitDesc *desc,
                               const WorkItem *work, int nwork, const TF *fin, TF *fout, Fields<TM> fld,
-                              TM *rs, const double *chi);
+                              TM *rs, const double *chi, bool rows16);
 // Collide phase of every slit: work holds the fluid items.  rows16: every slit
 // is 16 nodes wide in x (the shell sum then shares x-neighbour reads between
 // the lanes of each 16-lane row).

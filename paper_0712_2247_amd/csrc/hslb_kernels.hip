@@ -456,7 +456,31 @@ __device__ __forceinline__ T g2_t(double eta, int model)
 // 492 MB: this kernel 154 -> 139 us and the collide that reads them 1515 ->
 // 1489 us).  Below that the collide loses from it: 6 us of 39 on the 64x64x136
 // slit (17 MB), 15 us of 336 on the 128x128x264 slit (128 MB).
-template <typename TM, bool NT = false>
+// The value of v held by the lane of node x + 1 (periodic), for lanes along
+// whole x-rows: ROT 1 a wave per row of 64 nodes (wave_rol:1), ROT 2 a 16-lane
+// row per row of 16 nodes (row_ror:15).  A DPP move, no memory access.
+template <int ROT, typename TM>
+__device__ __forceinline__ TM lane_xp1(TM v)
+{
+    static_assert(ROT == 1 || ROT == 2, "lane_xp1");
+    constexpr int ctrl = ROT == 1 ? 0x134 : 0x12F;
+    if constexpr (sizeof(TM) == 4) {
+        return __builtin_bit_cast(TM, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, v),
+                                                                  __builtin_bit_cast(int, v), ctrl, 0xF, 0xF, false));
+    } else {
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+        const unsigned long long lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)b, (int)(uint32_t)b, ctrl,
+                                                                            0xF, 0xF, false);
+        const unsigned long long hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(b >> 32),
+                                                                            (int)(uint32_t)(b >> 32), ctrl, 0xF, 0xF,
+                                                                            false);
+        return __builtin_bit_cast(TM, lo | (hi << 32));
+    }
+}
+
+// ROT (see lane_xp1): the three eta_bar values at x + 1 come from the
+// neighbouring lane's loads at x; every lane of a row must be active.
+template <typename TM, bool NT = false, int ROT = 0>
 __device__ __forceinline__ void d_gfield(const LatticeDev &L, int model, const Fields<TM> &fld, int z, int r)
 {
     const int y = r / L.nx;
@@ -464,8 +488,26 @@ __device__ __forceinline__ void d_gfield(const LatticeDev &L, int model, const F
     const int x1 = wrapc<1>(x, L.nx), y1 = wrapc<1>(y, L.ny);
     const int zp = z + L.hz;
     auto e = [&](int xx, int yy, int zz) -> double { return (double)fld.eb[xx + L.nx * (yy + L.ny * zz)]; };
-    const double e000 = e(x, y, zp), e100 = e(x1, y, zp), e010 = e(x, y1, zp), e001 = e(x, y, zp + 1);
-    const double e110 = e(x1, y1, zp), e101 = e(x1, y, zp + 1), e011 = e(x, y1, zp + 1);
+    double e000, e100, e010, e001, e110, e101, e011;
+    if constexpr (ROT != 0) {
+        auto t = [&](int xx, int yy, int zz) -> TM { return fld.eb[xx + L.nx * (yy + L.ny * zz)]; };
+        const TM t000 = t(x, y, zp), t010 = t(x, y1, zp), t001 = t(x, y, zp + 1);
+        e000 = (double)t000;
+        e010 = (double)t010;
+        e001 = (double)t001;
+        e011 = e(x, y1, zp + 1);
+        e100 = (double)lane_xp1<ROT>(t000);
+        e110 = (double)lane_xp1<ROT>(t010);
+        e101 = (double)lane_xp1<ROT>(t001);
+    } else {
+        e000 = e(x, y, zp);
+        e100 = e(x1, y, zp);
+        e010 = e(x, y1, zp);
+        e001 = e(x, y, zp + 1);
+        e110 = e(x1, y1, zp);
+        e101 = e(x1, y, zp + 1);
+        e011 = e(x, y1, zp + 1);
+    }
     const size_t fs = L.fld_stride;
     const double h = 0.5, q = 0.25;
     auto st = [&](TM *dst, TM v) {
@@ -484,11 +526,11 @@ __device__ __forceinline__ void d_gfield(const LatticeDev &L, int model, const F
 }
 
 // grid (ceil(plane / 256), nz)
-template <typename TM, bool NT>
+template <typename TM, bool NT, int ROT = 0>
 __global__ __launch_bounds__(256) void k_gfield(LatticeDev L, int model, Fields<TM> fld)
 {
     const int r = blockIdx.x * 256 + threadIdx.x;
-    if (r < L.plane) d_gfield<TM, NT>(L, model, fld, (int)blockIdx.y, r);
+    if (r < L.plane) d_gfield<TM, NT, ROT>(L, model, fld, (int)blockIdx.y, r);
 }
 
 // ------------------------------------------------------------ shell force
@@ -1723,7 +1765,9 @@ __global__ __launch_bounds__(256, HSLB_COLLIDE_WAVES) void kb_collide(const Slit
 // Persistent kernel of one phase of the step for every slit: the grid walks
 // the work list; each item is one block of 256 indices of one slit, whose
 // descriptor (and sigma, hence the shell stencil) is uniform over the block.
-template <typename TF, typename TM>
+// ROT 2: every slit is 16 nodes wide, and the contact values take their
+// x + 1 eta_bar values from the neighbouring lane of the 16-lane row.
+template <typename TF, typename TM, int ROT = 0>
 __global__ __launch_bounds__(256) void kb_phase(int phase, const SlitDesc *__restrict__ desc,
                                                 const WorkItem *__restrict__ work, int nwork,
                                                 const TF *__restrict__ fin, TF *__restrict__ fout, Fields<TM> fld,
@@ -1745,7 +1789,7 @@ __global__ __launch_bounds__(256) void kb_phase(int phase, const SlitDesc *__res
             if (idx < d.L.N) d_moments(d.L, d.sc.nref_r, fi, F, idx / d.L.plane, idx % d.L.plane);
             break;
         case 3:
-            if (idx < d.L.N) d_gfield(d.L, d.sc.g2_model, F, idx / d.L.plane, idx % d.L.plane);
+            if (idx < d.L.N) d_gfield<TM, false, ROT>(d.L, d.sc.g2_model, F, idx / d.L.plane, idx % d.L.plane);
             break;
         case 4: {
             // phases 0 and 1 in one: every slit's layer is a whole number of
@@ -2773,10 +2817,15 @@ template <typename TM>
 hipError_t launch_gfield(hipStream_t s, const LatticeDev &L, int g2_model, Fields<TM> fld)
 {
     const double g_bytes = 7.0 * (double)L.fld_stride * sizeof(TM);
+    const dim3 g(blocks_for(L.plane), L.nz);
     if (g_bytes > HSLB_NT_FIELD_MIB * 1024.0 * 1024.0)
-        hipLaunchKernelGGL((k_gfield<TM, true>), dim3(blocks_for(L.plane), L.nz), dim3(256), 0, s, L, g2_model, fld);
+        hipLaunchKernelGGL((k_gfield<TM, true>), g, dim3(256), 0, s, L, g2_model, fld);
+    else if (L.nx == 64)  // a wave per x-row: the x + 1 values from the neighbouring lane
+        hipLaunchKernelGGL((k_gfield<TM, false, 1>), g, dim3(256), 0, s, L, g2_model, fld);
+    else if (L.nx == 16)  // a 16-lane row per x-row
+        hipLaunchKernelGGL((k_gfield<TM, false, 2>), g, dim3(256), 0, s, L, g2_model, fld);
     else
-        hipLaunchKernelGGL((k_gfield<TM, false>), dim3(blocks_for(L.plane), L.nz), dim3(256), 0, s, L, g2_model, fld);
+        hipLaunchKernelGGL((k_gfield<TM, false>), g, dim3(256), 0, s, L, g2_model, fld);
     return hipGetLastError();
 }
 
@@ -2941,11 +2990,16 @@ hipError_t launch_batch_layer_means(hipStream_t s, const SlitDesc *desc, const W
 
 template <typename TF, typename TM>
 hipError_t launch_batch_phase(hipStream_t s, int phase, unsigned grid, const SlitDesc *desc, const WorkItem *work,
-                              int nwork, const TF *fin, TF *fout, Fields<TM> fld, TM *rs, const double *chi)
+                              int nwork, const TF *fin, TF *fout, Fields<TM> fld, TM *rs, const double *chi,
+                              bool rows16)
 {
     if (nwork <= 0) return hipSuccess;
-    hipLaunchKernelGGL((kb_phase<TF, TM>), dim3(grid), dim3(256), 0, s, phase, desc, work, nwork, fin, fout, fld,
-                       rs, chi);
+    if (rows16 && phase == 3)
+        hipLaunchKernelGGL((kb_phase<TF, TM, 2>), dim3(grid), dim3(256), 0, s, phase, desc, work, nwork, fin, fout,
+                           fld, rs, chi);
+    else
+        hipLaunchKernelGGL((kb_phase<TF, TM>), dim3(grid), dim3(256), 0, s, phase, desc, work, nwork, fin, fout, fld,
+                           rs, chi);
     return hipGetLastError();
 }
 
@@ -3007,7 +3061,7 @@ hipError_t launch_batch_profiles(hipStream_t s, const SlitDesc *desc, const Work
                                              const double *, const TF *, Fields<TM>, double *);              \
     template hipError_t launch_batch_phase<TF, TM>(hipStream_t, int, unsigned, const SlitDesc *,            \
                                                    const WorkItem *, int, const TF *, TF *, Fields<TM>, TM *, \
-                                                   const double *);                                          \
+                                                   const double *, bool);                                          \
     template hipError_t launch_batch_collide<TF, TM>(hipStream_t, unsigned, const SlitDesc *,               \
                                                      const WorkItem *, int, const TF *, TF *, Fields<TM>,     \
                                                      const double *, bool);
