@@ -1515,7 +1515,9 @@ __global__ __launch_bounds__(256) void k_force(LatticeDev L, StepConst sc, const
 
 // Pass along x of the padded density field: a = sum_m w[m] n(x + m - R).
 // grid (ceil(plane / 256), nz); R may exceed nx (the offsets wrap again).
-template <typename TM>
+// ROT (see lane_xp1): one load of n(x - R), each further tap from the
+// neighbouring lane, in the same order.
+template <typename TM, int ROT = 0>
 __global__ __launch_bounds__(256) void k_att_x(LatticeDev L, AttWeights aw, const TM *__restrict__ n,
                                                double *__restrict__ out)
 {
@@ -1528,10 +1530,19 @@ __global__ __launch_bounds__(256) void k_att_x(LatticeDev L, AttWeights aw, cons
     int xm = (x - aw.R) % L.nx;
     xm = xm < 0 ? xm + L.nx : xm;
     double s = 0.0;
+    if constexpr (ROT != 0) {
+        TM v = row[xm];
 #pragma unroll 8
-    for (int m = 0; m <= 2 * aw.R; ++m) {
-        s += aw.w[m] * (double)row[xm];
-        xm = (xm + 1 == L.nx) ? 0 : xm + 1;
+        for (int m = 0; m <= 2 * aw.R; ++m) {
+            s += aw.w[m] * (double)v;
+            v = lane_xp1<ROT>(v);
+        }
+    } else {
+#pragma unroll 8
+        for (int m = 0; m <= 2 * aw.R; ++m) {
+            s += aw.w[m] * (double)row[xm];
+            xm = (xm + 1 == L.nx) ? 0 : xm + 1;
+        }
     }
     out[(size_t)L.plane * z + r] = s;
 }
@@ -2590,7 +2601,12 @@ hipError_t launch_attraction(hipStream_t s, const LatticeDev &L, const AttWeight
 {
     if (aw.R < 0 || aw.R > ATT_MAX_R) return hipErrorInvalidValue;
     const dim3 g(blocks_for(L.plane), L.nz), blk(256);
-    hipLaunchKernelGGL((k_att_x<TM>), g, blk, 0, s, L, aw, n, a);
+    if (L.nx == 64)  // a wave per x-row: the taps from the neighbouring lanes
+        hipLaunchKernelGGL((k_att_x<TM, 1>), g, blk, 0, s, L, aw, n, a);
+    else if (L.nx == 16)
+        hipLaunchKernelGGL((k_att_x<TM, 2>), g, blk, 0, s, L, aw, n, a);
+    else
+        hipLaunchKernelGGL((k_att_x<TM>), g, blk, 0, s, L, aw, n, a);
     hipLaunchKernelGGL(k_att_y, g, blk, 0, s, L, aw, a, b);
     hipLaunchKernelGGL(k_att_z, g, blk, 0, s, L, aw, b, phi);
     return hipGetLastError();
